@@ -1,0 +1,88 @@
+"""Small hand-built inputs shared by the tests (no method arithmetic here)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import scenegen as sg
+
+
+def single_cluster_asset(pos, scale, rot, opacity, sh, sh_degree=0) -> sg.Asset:
+    """One leaf cluster that is also the root: always selected."""
+    pos = np.asarray(pos, np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    assert 1 <= n <= 64
+    nc = (sh_degree + 1) ** 2
+    return sg.Asset(
+        sh_degree=sh_degree,
+        pos=pos,
+        scale=np.asarray(scale, np.float32).reshape(n, 3),
+        rot=np.asarray(rot, np.float32).reshape(n, 4),
+        opacity=np.asarray(opacity, np.float32).reshape(n),
+        sh=np.asarray(sh, np.float32).reshape(n, nc, 3),
+        first_row=np.array([0], np.uint32), count=np.array([n], np.uint8), level=np.array([0], np.uint8),
+        parent=np.array([-1], np.int32), first_child=np.array([-1], np.int32), n_children=np.array([0], np.uint8),
+        self_sphere=np.array([[0, 0, 0, 0]], np.float32),
+        parent_sphere=np.array([[0, 0, 0, np.inf]], np.float32),
+        n_leaf_clusters=1,
+    )
+
+
+def two_level_asset(root_sphere, n_leaves=4) -> sg.Asset:
+    """A root (own sphere given) over n_leaves single-row leaf clusters."""
+    nl = n_leaves
+    rows = nl + 1
+    pos = np.zeros((rows, 3), np.float32)
+    pos[:, 2] = np.linspace(-0.1, 0.1, rows)
+    rs = np.asarray(root_sphere, np.float32)
+    self_sphere = np.zeros((nl + 1, 4), np.float32)
+    self_sphere[:nl, :3] = pos[:nl]
+    self_sphere[nl] = rs
+    parent_sphere = np.zeros_like(self_sphere)
+    parent_sphere[:nl] = rs
+    parent_sphere[nl, :3] = rs[:3]
+    parent_sphere[nl, 3] = np.inf
+    return sg.Asset(
+        sh_degree=0, pos=pos, scale=np.full((rows, 3), 0.01, np.float32),
+        rot=np.tile(np.array([1, 0, 0, 0], np.float32), (rows, 1)), opacity=np.full(rows, 0.5, np.float32),
+        sh=np.zeros((rows, 1, 3), np.float32),
+        first_row=np.arange(nl + 1, dtype=np.uint32), count=np.ones(nl + 1, np.uint8),
+        level=np.array([0] * nl + [1], np.uint8),
+        parent=np.array([nl] * nl + [-1], np.int32), first_child=np.array([-1] * nl + [0], np.int32),
+        n_children=np.array([0] * nl + [nl], np.uint8),
+        self_sphere=self_sphere, parent_sphere=parent_sphere, n_leaf_clusters=nl,
+    )
+
+
+def identity_camera(width=64, height=64, f=100.0, cx=None, cy=None, near=0.01, far=1e10, bg=(0.0, 0.0, 0.0)):
+    v = np.hstack([np.eye(3), np.zeros((3, 1))]).astype(np.float32)
+    return sg.Camera(width, height, float(f), float(f), float(width / 2 if cx is None else cx),
+                     float(height / 2 if cy is None else cy), v, near, far, bg)
+
+
+def leaf_mask(asset) -> np.ndarray:
+    m = np.zeros(asset.n_clusters, np.uint8)
+    m[: asset.n_leaf_clusters] = 1
+    return m
+
+
+def chains_ok(asset, mask_row) -> bool:
+    """Exactly one selected cluster on every leaf-to-root chain."""
+    for leaf in range(asset.n_leaf_clusters):
+        k, n = leaf, 0
+        while k >= 0:
+            n += int(mask_row[k])
+            k = int(asset.parent[k])
+        if n != 1:
+            return False
+    return True
+
+
+def random_camera_near(rng, width=64, height=48, dist=(0.05, 30.0)):
+    az = rng.uniform(0, 2 * math.pi)
+    el = rng.uniform(-1.2, 1.2)
+    d = math.exp(rng.uniform(math.log(dist[0]), math.log(dist[1])))
+    eye = d * np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+    tgt = rng.uniform(-0.3, 0.3, 3)
+    return sg.look_at(eye, tgt, width, height, rng.uniform(0.3, 1.5))

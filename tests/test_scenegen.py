@@ -1,0 +1,71 @@
+"""The seeded input generator: determinism and the structure the path relies on."""
+import numpy as np
+
+import scenegen as sg
+
+
+def test_deterministic_digest():
+    a = sg.make_asset(4096, 3, 12)
+    b = sg.make_asset(4096, 3, 12)
+    c = sg.make_asset(4096, 3, 13)
+    assert a.digest() == b.digest()
+    assert a.digest() != c.digest()
+
+
+def test_c1_shape():
+    a = sg.make_asset(16384, 0, 1)
+    assert a.n_clusters == 341 and a.n_rows == 21824
+    assert np.bincount(a.level).tolist() == [256, 64, 16, 4, 1]
+    assert int((a.parent < 0).sum()) == 1 and a.parent[-1] == -1
+    assert a.count.max() <= 64
+
+
+def test_tree_and_spheres_consistent():
+    a = sg.make_asset(5000, 1, 3, n_ellipsoids=3)  # ragged: last clusters are partial
+    nc = a.n_clusters
+    assert a.n_leaf_rows == 5000
+    for k in range(nc):
+        if a.first_child[k] >= 0:
+            for c in range(a.first_child[k], a.first_child[k] + a.n_children[k]):
+                assert a.parent[c] == k
+    # parent sphere is a bit-identical copy of the parent's own sphere
+    has = a.parent >= 0
+    assert np.array_equal(a.parent_sphere[has], a.self_sphere[a.parent[has]])
+    assert np.isinf(a.parent_sphere[~has, 3]).all()
+    assert (a.self_sphere[: a.n_leaf_clusters, 3] == 0).all()
+    # nested spheres with slack for every non-leaf child
+    m = has & (a.level > 0)
+    c = a.self_sphere[m].astype(np.float64)
+    p = a.self_sphere[a.parent[m]].astype(np.float64)
+    need = (np.linalg.norm(c[:, :3] - p[:, :3], axis=1) + c[:, 3]) * (1 + 2.0 ** -10) + 1e-4
+    assert (p[:, 3] >= need).all()
+    # every child's rows lie inside the parent's own sphere
+    for k in range(a.n_leaf_clusters, nc):
+        fc, n = a.first_child[k], a.n_children[k]
+        r0, r1 = a.first_row[fc], a.first_row[fc + n - 1] + a.count[fc + n - 1]
+        d = np.linalg.norm(a.pos[r0:r1].astype(np.float64) - a.self_sphere[k, :3], axis=1)
+        assert d.max() <= a.self_sphere[k, 3]
+
+
+def test_unit_quaternions_and_ranges():
+    a = sg.make_asset(4096, 3, 5)
+    n = np.linalg.norm(a.rot.astype(np.float64), axis=1)
+    assert np.abs(n - 1).max() < 1e-6
+    assert (a.rot[:, 0] >= 0).all()
+    assert (a.opacity > 0).all() and (a.opacity < 1).all()
+    assert (a.scale > 0).all()
+    assert np.isfinite(a.pos).all() and (np.abs(a.pos[: a.n_leaf_rows]) <= 0.5).all()
+
+
+def test_cameras():
+    cams = sg.orbit_cameras(8, 102)
+    for c in cams:
+        R = c.world_to_cam[:, :3].astype(np.float64)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-6)
+        # looking at the origin: it projects to the principal point
+        o = c.world_to_cam[:, 3].astype(np.float64)
+        assert o[2] > 0 and abs(o[0]) < 1e-5 and abs(o[1]) < 1e-5
+    fl = sg.flythrough_cameras(30)
+    assert len(fl) == 30
+    T = sg.grid_instances()
+    assert T.shape == (100, 3, 4)
