@@ -1,0 +1,208 @@
+/*
+ * v3dg — per-frame hot path of Virtualized 3D Gaussians on MI355X (gfx950).
+ *
+ * The library keeps one asset's cluster hierarchy and Gaussians resident in
+ * HBM together with a table of rigid instances, and per frame
+ *   (a) tests every (instance, cluster) footprint against a tolerance and
+ *       compacts the cut (paper Sec. 3.4, "Parallel Selection on Discrete
+ *       Clusters"; footprint of Sec. 3.3),
+ *   (b) compacts the chosen clusters' Gaussians into a slot stream,
+ *   (c) projects each Gaussian to a 2D conic and colour (3D Gaussian splat of
+ *       Sec. 2.1, no 2D dilation as in Sec. 5.1),
+ *   (d) bins the splats to 16x16 tiles and radix-sorts 64-bit (tile, depth) keys,
+ *   (e) alpha-composites every tile front to back (Sec. 2.1).
+ * All device work runs as HIP kernels on the stream given at load time.
+ *
+ * Conventions for every entry point:
+ *   - return 0 (V3DG_OK) or a negative V3DG_ERR_* code; the message of the last
+ *     failure on the calling thread is available from v3dg_last_error();
+ *   - nothing is written to caller memory when a call fails;
+ *   - calls are asynchronous on the scene's stream unless marked "synchronises";
+ *     v3dg_render also waits once, mid-frame, for the device-side key count;
+ *   - host arrays passed in are only read during the call; device pointers
+ *     (the image) stay owned by the caller.
+ */
+#ifndef V3DG_H
+#define V3DG_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define V3DG_OK 0
+#define V3DG_ERR_INVALID_ARG (-1)  /* bad pointer, size, non-finite value, malformed tree */
+#define V3DG_ERR_OOM (-2)          /* device or host allocation failed                    */
+#define V3DG_ERR_HIP (-3)          /* a HIP runtime call failed                            */
+#define V3DG_ERR_NOT_MONOTONE (-4) /* parent sphere does not nest its child (see load)     */
+#define V3DG_ERR_CAPACITY (-5)     /* a frame exceeds a 32-bit count                       */
+#define V3DG_ERR_DEVICE (-6)       /* a kernel raised its error flag (bounded wait expired)*/
+
+/* precision of the stored attributes */
+#define V3DG_FP32 0u
+/* load flags */
+#define V3DG_LOAD_REPAIR_NESTING 1u /* inflate parent radii bottom-up instead of failing */
+
+typedef struct v3dg_scene v3dg_scene;         /* opaque; library-owned */
+typedef struct v3dg_selection v3dg_selection; /* opaque; library-owned */
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  Pixel (x, y) has
+ * its centre at (x + 0.5, y + 0.5).  Requirements: 1 <= width, height <= 16384;
+ * fx, fy > 0; every value finite; 0 < near_plane < far_plane. */
+typedef struct {
+    uint32_t width, height;
+    float fx, fy, cx, cy;
+    float world_to_cam[12]; /* 3x4 row-major [R | t] */
+    float near_plane, far_plane;
+    float bg[3];            /* background added as T * bg */
+    float pad0;
+} v3dg_camera;
+
+/* One asset: clusters and Gaussian rows as structure-of-arrays host arrays.
+ * Cluster k owns rows first_row[k] .. first_row[k] + count[k] - 1 (1 <= count <= 64).
+ * Children of k are first_child[k] .. first_child[k] + n_children[k] - 1; leaves
+ * have n_children = 0; roots have parent = -1.
+ * self_sphere[k] = (cx, cy, cz, r) is the bounding sphere of the cluster group
+ * k was simplified from (paper Sec. 3.3: centre = mean Gaussian position,
+ * r = farthest Gaussian); leaves have r = 0.  parent_sphere[k] must equal
+ * self_sphere[parent[k]] bit for bit, and r = +inf for roots (Sec. 3.4).
+ * Gaussian rows: pos (x,y,z), scale (linear, > 0), rot unit quaternion
+ * (w,x,y,z) within 1e-6, opacity in (0, 1], sh row-major
+ * [(sh_degree+1)^2][3] real-SH coefficients (sh_degree 0..3). */
+typedef struct {
+    uint32_t n_clusters, n_rows, sh_degree, precision;
+    const float *self_sphere;   /* n_clusters x 4 */
+    const float *parent_sphere; /* n_clusters x 4 */
+    const uint32_t *first_row;  /* n_clusters */
+    const uint8_t *count;       /* n_clusters */
+    const int32_t *parent;      /* n_clusters */
+    const int32_t *first_child; /* n_clusters */
+    const uint8_t *n_children;  /* n_clusters */
+    const float *pos;           /* n_rows x 3 */
+    const float *scale;         /* n_rows x 3 */
+    const float *rot;           /* n_rows x 4 */
+    const float *opacity;       /* n_rows */
+    const float *sh;            /* n_rows x (sh_degree+1)^2 x 3 */
+} v3dg_hierarchy_desc;
+
+/* Counters of the last frame rendered on a scene. */
+typedef struct {
+    uint64_t n_slots;    /* Gaussians in the rendered selection            */
+    uint64_t n_keys;     /* (tile, splat) pairs sorted                     */
+    uint32_t n_tiles;    /* tiles in the image                             */
+    uint32_t key_bits;   /* significant bits of the sort key               */
+    uint32_t sort_passes;
+    uint32_t pad0;
+} v3dg_frame_stats;
+
+/* Kernel stages timed when profiling is on (v3dg_set_profiling). */
+#define V3DG_STAGE_SETUP 0
+#define V3DG_STAGE_SELECT 1
+#define V3DG_STAGE_EXPAND 2
+#define V3DG_STAGE_PROJECT 3
+#define V3DG_STAGE_SCAN 4
+#define V3DG_STAGE_EMIT 5
+#define V3DG_STAGE_SORT_HIST 6
+#define V3DG_STAGE_SORT_PASS 7
+#define V3DG_STAGE_RANGES 8
+#define V3DG_STAGE_BLEND 9
+#define V3DG_N_STAGES 10
+
+/* Upload an asset and its instances to HBM and validate it.
+ * Validation (paper Sec. 3.4 keeps r_p > r_c so that a cluster and its parent
+ * are never both selected; this library requires the stronger nesting that
+ * makes the per-cluster test exact for every camera): for every non-root
+ * cluster with r_c > 0, r_p >= (|c_p - c_c| + r_c) (1 + 2^-12).  A violation
+ * returns V3DG_ERR_NOT_MONOTONE unless V3DG_LOAD_REPAIR_NESTING is set, in
+ * which case parent radii are enlarged bottom-up (and the copies in
+ * parent_sphere updated) on the library's copy.
+ * instances_3x4: n_instances x 12 doubles, each [s R | t] with R a rotation
+ * and s > 0 a uniform scale (paper Sec. 4.2 / Appendix A.2); 1 <= n_instances.
+ * hip_stream: the hipStream_t every later call runs on (NULL = default).
+ * On success *out receives a new scene; free it with v3dg_scene_free. */
+int v3dg_load_hierarchy(const v3dg_hierarchy_desc *desc, const double *instances_3x4, uint32_t n_instances,
+                        void *hip_stream, uint32_t flags, v3dg_scene **out);
+
+/* Replace the instance transforms (same count), e.g. every frame of a dynamic
+ * scene of rigid objects (paper Appendix A.3). */
+int v3dg_set_instances(v3dg_scene *scene, const double *instances_3x4, uint32_t n_instances);
+
+/* Parallel selection (paper Sec. 3.4): cluster k of instance i is selected iff
+ * F(own sphere) <= tolerance < F(parent sphere), F = pi r^2 fx fy / z^2 the
+ * pixel area of the sphere (Sec. 3.3).  tolerance is in the unit of F (pixel
+ * area), finite and >= 0.  The exact FP32 predicate: z = ((a0 cx + a1 cy) +
+ * a2 cz) + a3 with row 2 of A = fl32(V T_i); r' = r s_i; "fits" is r' == 0, or
+ * |z| > r' and (r' r') K <= tolerance (z z) with K = fl32(pi fx fy).
+ * Also expands the chosen clusters into the slot stream (one slot per
+ * Gaussian, ascending gid = i * n_clusters + k, rows in stored order).
+ * *inout: NULL to get a new selection object, or an existing one of this
+ * scene to overwrite (its buffers are reused). */
+int v3dg_select(v3dg_scene *scene, const v3dg_camera *cam, float tolerance, v3dg_selection **inout);
+
+/* Render a selection: project, bin, sort, blend.  image_rgba_dev is a device
+ * buffer of height x width x 4 floats (RGB = sum + T bg, A = 1 - T), written
+ * completely.  Synchronises once mid-frame to size the key buffers. */
+int v3dg_render(v3dg_scene *scene, const v3dg_camera *cam, const v3dg_selection *sel, float *image_rgba_dev);
+
+/* Full-detail baseline: every leaf cluster of every instance (no selection). */
+int v3dg_render_full(v3dg_scene *scene, const v3dg_camera *cam, float *image_rgba_dev);
+
+/* Selected cluster and Gaussian counts (synchronises). */
+int v3dg_selection_info(const v3dg_selection *sel, uint64_t *n_clusters, uint64_t *n_gaussians);
+
+/* Copy the ascending gid list to host memory (synchronises).  Fails with
+ * V3DG_ERR_CAPACITY when cap is smaller than the count. */
+int v3dg_selection_copy_ids(const v3dg_selection *sel, uint32_t *host_gids, uint64_t cap, uint64_t *n_out);
+
+/* Copy the slot stream (row and instance of every selected Gaussian). */
+int v3dg_selection_copy_slots(const v3dg_selection *sel, uint32_t *host_rows, uint32_t *host_inst, uint64_t cap,
+                              uint64_t *n_out);
+
+void v3dg_selection_free(v3dg_selection *sel);
+void v3dg_scene_free(v3dg_scene *scene);
+
+/* Counters of the last frame rendered on this scene (synchronises). */
+int v3dg_get_frame_stats(v3dg_scene *scene, v3dg_frame_stats *out);
+
+/* Per-slot results of the last frame's projection (synchronises), for
+ * parity checks.  Arrays of cap entries: mean2 x2, conic x3, rgb x3; depth;
+ * opacity; tiles = tiles touched (0 = culled). */
+int v3dg_copy_projection(v3dg_scene *scene, float *mean2, float *conic, float *rgb, float *opacity, float *depth,
+                         uint32_t *tiles, uint64_t cap, uint64_t *n_out);
+
+/* The last frame's sorted keys (tile << 32 | depth bits) and values (slot)
+ * (synchronises). */
+int v3dg_copy_sorted_keys(v3dg_scene *scene, uint64_t *keys, uint32_t *vals, uint64_t cap, uint64_t *n_out);
+
+/* Work done and time spent since the previous v3dg_collect_profile. */
+typedef struct {
+    double ms[V3DG_N_STAGES];          /* summed kernel time per stage (profiling on) */
+    uint64_t launches[V3DG_N_STAGES];  /* timed launches per stage                    */
+    uint64_t frames;                   /* renders                                     */
+    uint64_t selects, tests;           /* selections, (instance, cluster) tests       */
+    uint64_t sel_clusters;             /* selected clusters of the rendered selections*/
+    uint64_t slots, visible;           /* Gaussians projected / with a tile           */
+    uint64_t keys, tiles, pixels;      /* sorted keys, image tiles, image pixels      */
+    uint64_t sort_passes;              /* digit passes run                            */
+    uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending  */
+} v3dg_profile;
+
+/* Stage timing with hipEvents on the scene's stream.  While on, every kernel
+ * launch is bracketed by events.  Work counters are kept either way.
+ * v3dg_collect_profile synchronises, fills *out with the totals since the
+ * previous collect, and clears them. */
+int v3dg_set_profiling(v3dg_scene *scene, int on);
+int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
+
+/* Stable LSD radix sort of n (key, value) pairs in device memory by the low
+ * key_bits bits of the keys (1..64), the primitive used by (d).  Synchronises;
+ * allocates its own temporary buffers. */
+int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, void *hip_stream);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *v3dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

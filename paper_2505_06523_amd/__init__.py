@@ -1,0 +1,380 @@
+"""Python binding of libv3dg (the V3DG per-frame path on MI355X).
+
+The functions ``v3dg_*`` mirror the C ABI in ``include/v3dg.h`` one to one and
+only marshal arguments; every step of the frame runs in the library's HIP
+kernels.  ``Scene`` and ``Selection`` wrap the handles for convenience.
+PyTorch supplies device memory (the image tensor) and the HIP stream.
+
+The library must be built first (``python -m paper_2505_06523_amd.build``);
+loading fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libv3dg.so")
+
+V3DG_OK = 0
+V3DG_ERR_INVALID_ARG = -1
+V3DG_ERR_OOM = -2
+V3DG_ERR_HIP = -3
+V3DG_ERR_NOT_MONOTONE = -4
+V3DG_ERR_CAPACITY = -5
+V3DG_ERR_DEVICE = -6
+V3DG_FP32 = 0
+V3DG_LOAD_REPAIR_NESTING = 1
+STAGES = ["setup", "select", "expand", "project", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend"]
+
+
+class V3DGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("v3dg error %d: %s" % (code, msg))
+        self.code = code
+
+
+class v3dg_camera(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("world_to_cam", C.c_float * 12),
+                ("near_plane", C.c_float), ("far_plane", C.c_float), ("bg", C.c_float * 3), ("pad0", C.c_float)]
+
+
+class v3dg_hierarchy_desc(C.Structure):
+    _fields_ = [("n_clusters", C.c_uint32), ("n_rows", C.c_uint32), ("sh_degree", C.c_uint32),
+                ("precision", C.c_uint32), ("self_sphere", C.c_void_p), ("parent_sphere", C.c_void_p),
+                ("first_row", C.c_void_p), ("count", C.c_void_p), ("parent", C.c_void_p),
+                ("first_child", C.c_void_p), ("n_children", C.c_void_p), ("pos", C.c_void_p),
+                ("scale", C.c_void_p), ("rot", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class v3dg_frame_stats(C.Structure):
+    _fields_ = [("n_slots", C.c_uint64), ("n_keys", C.c_uint64), ("n_tiles", C.c_uint32),
+                ("key_bits", C.c_uint32), ("sort_passes", C.c_uint32), ("pad0", C.c_uint32)]
+
+
+class v3dg_profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 10), ("launches", C.c_uint64 * 10), ("frames", C.c_uint64),
+                ("selects", C.c_uint64), ("tests", C.c_uint64), ("sel_clusters", C.c_uint64),
+                ("slots", C.c_uint64), ("visible", C.c_uint64), ("keys", C.c_uint64), ("tiles", C.c_uint64),
+                ("pixels", C.c_uint64), ("sort_passes", C.c_uint64), ("pairs", C.c_uint64)]
+
+
+EXPORTS = [
+    "v3dg_load_hierarchy", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
+    "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
+    "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_sorted_keys",
+    "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs", "v3dg_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libv3dg.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libv3dg.so is not built: run `python -m paper_2505_06523_amd.build` (needs hipcc)")
+    L = C.CDLL(LIB_PATH)
+    P, U32, U64, I = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+    sig = {
+        "v3dg_load_hierarchy": ([P, P, U32, P, U32, P], I),
+        "v3dg_set_instances": ([P, P, U32], I),
+        "v3dg_select": ([P, P, C.c_float, P], I),
+        "v3dg_render": ([P, P, P, P], I),
+        "v3dg_render_full": ([P, P, P], I),
+        "v3dg_selection_info": ([P, P, P], I),
+        "v3dg_selection_copy_ids": ([P, P, U64, P], I),
+        "v3dg_selection_copy_slots": ([P, P, P, U64, P], I),
+        "v3dg_selection_free": ([P], None),
+        "v3dg_scene_free": ([P], None),
+        "v3dg_get_frame_stats": ([P, P], I),
+        "v3dg_copy_projection": ([P, P, P, P, P, P, P, U64, P], I),
+        "v3dg_copy_sorted_keys": ([P, P, P, U64, P], I),
+        "v3dg_set_profiling": ([P, I], I),
+        "v3dg_collect_profile": ([P, P], I),
+        "v3dg_sort_pairs": ([P, P, U64, U32, P], I),
+        "v3dg_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().v3dg_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise V3DGError(rc, last_error())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---- one-to-one wrappers of the C ABI ------------------------------------------
+def v3dg_load_hierarchy(desc, instances_3x4, n_instances, hip_stream, flags):
+    out = C.c_void_p()
+    _check(lib().v3dg_load_hierarchy(C.byref(desc), instances_3x4, n_instances, hip_stream, flags, C.byref(out)))
+    return out
+
+
+def v3dg_set_instances(scene, instances_3x4, n_instances):
+    _check(lib().v3dg_set_instances(scene, instances_3x4, n_instances))
+
+
+def v3dg_select(scene, cam, tolerance, sel=None):
+    h = C.c_void_p(sel.value if isinstance(sel, C.c_void_p) else sel)
+    _check(lib().v3dg_select(scene, C.byref(cam), float(tolerance), C.byref(h)))
+    return h
+
+
+def v3dg_render(scene, cam, sel, image_ptr):
+    _check(lib().v3dg_render(scene, C.byref(cam), sel, image_ptr))
+
+
+def v3dg_render_full(scene, cam, image_ptr):
+    _check(lib().v3dg_render_full(scene, C.byref(cam), image_ptr))
+
+
+def v3dg_selection_info(sel):
+    nc, ng = C.c_uint64(), C.c_uint64()
+    _check(lib().v3dg_selection_info(sel, C.byref(nc), C.byref(ng)))
+    return nc.value, ng.value
+
+
+def v3dg_selection_copy_ids(sel):
+    nc, _ = v3dg_selection_info(sel)
+    out = np.zeros(max(nc, 1), np.uint32)
+    n = C.c_uint64()
+    _check(lib().v3dg_selection_copy_ids(sel, _p(out), out.size, C.byref(n)))
+    return out[: n.value]
+
+
+def v3dg_selection_copy_slots(sel):
+    _, ng = v3dg_selection_info(sel)
+    rows = np.zeros(max(ng, 1), np.uint32)
+    inst = np.zeros(max(ng, 1), np.uint32)
+    n = C.c_uint64()
+    _check(lib().v3dg_selection_copy_slots(sel, _p(rows), _p(inst), rows.size, C.byref(n)))
+    return rows[: n.value], inst[: n.value]
+
+
+def v3dg_selection_free(sel):
+    lib().v3dg_selection_free(sel)
+
+
+def v3dg_scene_free(scene):
+    lib().v3dg_scene_free(scene)
+
+
+def v3dg_get_frame_stats(scene) -> dict:
+    st = v3dg_frame_stats()
+    _check(lib().v3dg_get_frame_stats(scene, C.byref(st)))
+    return dict(n_slots=st.n_slots, n_keys=st.n_keys, n_tiles=st.n_tiles, key_bits=st.key_bits,
+                sort_passes=st.sort_passes)
+
+
+def v3dg_copy_projection(scene, n_slots: int) -> dict:
+    n = max(int(n_slots), 1)
+    out = dict(mean2=np.zeros((n, 2), np.float32), conic=np.zeros((n, 3), np.float32),
+               rgb=np.zeros((n, 3), np.float32), opacity=np.zeros(n, np.float32), depth=np.zeros(n, np.float32),
+               tiles=np.zeros(n, np.uint32))
+    got = C.c_uint64()
+    _check(lib().v3dg_copy_projection(scene, _p(out["mean2"]), _p(out["conic"]), _p(out["rgb"]),
+                                      _p(out["opacity"]), _p(out["depth"]), _p(out["tiles"]), n, C.byref(got)))
+    return {k: v[: got.value] for k, v in out.items()}
+
+
+def v3dg_copy_sorted_keys(scene, n_keys: int):
+    n = max(int(n_keys), 1)
+    keys = np.zeros(n, np.uint64)
+    vals = np.zeros(n, np.uint32)
+    got = C.c_uint64()
+    _check(lib().v3dg_copy_sorted_keys(scene, _p(keys), _p(vals), n, C.byref(got)))
+    return keys[: got.value], vals[: got.value]
+
+
+def v3dg_set_profiling(scene, on: bool):
+    _check(lib().v3dg_set_profiling(scene, int(bool(on))))
+
+
+def v3dg_collect_profile(scene) -> dict:
+    p = v3dg_profile()
+    _check(lib().v3dg_collect_profile(scene, C.byref(p)))
+    out = {name: getattr(p, name) for name, _ in v3dg_profile._fields_ if name not in ("ms", "launches")}
+    out["stages"] = {s: (float(p.ms[i]), int(p.launches[i])) for i, s in enumerate(STAGES)}
+    return out
+
+
+def v3dg_sort_pairs(keys_ptr, vals_ptr, n, key_bits, hip_stream):
+    _check(lib().v3dg_sort_pairs(keys_ptr, vals_ptr, int(n), int(key_bits), hip_stream))
+
+
+# ---- convenience layer -----------------------------------------------------------
+def make_camera(cam) -> v3dg_camera:
+    """v3dg_camera from any object with width, height, fx, fy, cx, cy,
+    world_to_cam (3x4), near, far and bg attributes."""
+    c = v3dg_camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    v = np.asarray(cam.world_to_cam, np.float32).reshape(12)
+    for i in range(12):
+        c.world_to_cam[i] = float(v[i])
+    c.near_plane, c.far_plane = float(cam.near), float(cam.far)
+    bg = getattr(cam, "bg", (0.0, 0.0, 0.0))
+    for i in range(3):
+        c.bg[i] = float(bg[i])
+    return c
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_ptr():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Selection:
+    def __init__(self, scene: "Scene", handle: C.c_void_p):
+        self.scene = scene
+        self.handle = handle
+
+    def info(self):
+        return v3dg_selection_info(self.handle)
+
+    def ids(self) -> np.ndarray:
+        return v3dg_selection_copy_ids(self.handle)
+
+    def slots(self):
+        return v3dg_selection_copy_slots(self.handle)
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            v3dg_selection_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            if self.scene is not None and self.scene.handle is not None:
+                self.free()
+        except Exception:
+            pass
+
+
+class Scene:
+    """An asset resident in HBM with its instance table."""
+
+    def __init__(self, asset, instances=None, stream=None, flags: int = 0):
+        arrays = dict(
+            self_sphere=np.ascontiguousarray(asset.self_sphere, np.float32),
+            parent_sphere=np.ascontiguousarray(asset.parent_sphere, np.float32),
+            first_row=np.ascontiguousarray(asset.first_row, np.uint32),
+            count=np.ascontiguousarray(asset.count, np.uint8),
+            parent=np.ascontiguousarray(asset.parent, np.int32),
+            first_child=np.ascontiguousarray(asset.first_child, np.int32),
+            n_children=np.ascontiguousarray(asset.n_children, np.uint8),
+            pos=np.ascontiguousarray(asset.pos, np.float32),
+            scale=np.ascontiguousarray(asset.scale, np.float32),
+            rot=np.ascontiguousarray(asset.rot, np.float32),
+            opacity=np.ascontiguousarray(asset.opacity, np.float32),
+            sh=np.ascontiguousarray(asset.sh, np.float32),
+        )
+        d = v3dg_hierarchy_desc()
+        d.n_clusters = arrays["first_row"].shape[0]
+        d.n_rows = arrays["pos"].shape[0]
+        d.sh_degree = int(asset.sh_degree)
+        d.precision = V3DG_FP32
+        for k, v in arrays.items():
+            setattr(d, k, v.ctypes.data)
+        if instances is None:
+            instances = np.hstack([np.eye(3), np.zeros((3, 1))])[None]
+        T = np.ascontiguousarray(np.asarray(instances, np.float64).reshape(-1, 12))
+        self.n_instances = T.shape[0]
+        self.n_clusters = int(d.n_clusters)
+        if stream is None:
+            stream = current_stream_ptr()
+        elif not isinstance(stream, C.c_void_p):
+            stream = C.c_void_p(stream)
+        self.stream = stream
+        self.handle = None
+        self.handle = v3dg_load_hierarchy(d, _p(T), T.shape[0], stream, flags)
+
+    def set_instances(self, instances):
+        T = np.ascontiguousarray(np.asarray(instances, np.float64).reshape(-1, 12))
+        v3dg_set_instances(self.handle, _p(T), T.shape[0])
+
+    def select(self, cam, tau: float, sel: Selection | None = None) -> Selection:
+        c = make_camera(cam)
+        h = v3dg_select(self.handle, c, tau, sel.handle if sel is not None else None)
+        if sel is not None:
+            return sel
+        return Selection(self, h)
+
+    def _image(self, cam, out):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device="cuda")
+        if (not out.is_cuda or out.dtype != torch.float32 or not out.is_contiguous()
+                or tuple(out.shape) != (int(cam.height), int(cam.width), 4)):
+            raise ValueError("image must be a contiguous float32 CUDA tensor of shape (H, W, 4)")
+        return out
+
+    def render(self, cam, sel: Selection, out=None):
+        out = self._image(cam, out)
+        v3dg_render(self.handle, make_camera(cam), sel.handle, C.c_void_p(out.data_ptr()))
+        return out
+
+    def render_full(self, cam, out=None):
+        out = self._image(cam, out)
+        v3dg_render_full(self.handle, make_camera(cam), C.c_void_p(out.data_ptr()))
+        return out
+
+    def frame_stats(self) -> dict:
+        return v3dg_get_frame_stats(self.handle)
+
+    def projection(self) -> dict:
+        return v3dg_copy_projection(self.handle, self.frame_stats()["n_slots"])
+
+    def sorted_keys(self):
+        return v3dg_copy_sorted_keys(self.handle, self.frame_stats()["n_keys"])
+
+    def set_profiling(self, on: bool = True):
+        v3dg_set_profiling(self.handle, on)
+
+    def collect_profile(self) -> dict:
+        return v3dg_collect_profile(self.handle)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            v3dg_scene_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sort_pairs(keys, vals, key_bits: int, stream=None):
+    """Stable radix sort of device tensors (int64 keys as u64, int32 values) in place."""
+    torch = _torch()
+    if keys.dtype != torch.int64 or vals.dtype != torch.int32 or keys.numel() != vals.numel():
+        raise ValueError("keys must be int64 and vals int32 of equal length")
+    if not (keys.is_cuda and vals.is_cuda and keys.is_contiguous() and vals.is_contiguous()):
+        raise ValueError("keys and vals must be contiguous CUDA tensors")
+    st = current_stream_ptr() if stream is None else C.c_void_p(stream)
+    v3dg_sort_pairs(C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()), keys.numel(), key_bits, st)

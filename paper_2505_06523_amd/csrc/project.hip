@@ -1,0 +1,264 @@
+// (c) projection of every slot's Gaussian to a 2D splat.
+//
+// A 3D Gaussian (p, s, q, o, SH colour) is splatted to the image plane with
+// the EWA local affine approximation and no 2D dilation (paper Sec. 2.1 and
+// Sec. 5.1).  With M = J W R(q) diag(s) (2x3), the 2D covariance is M M^T, so
+// its entries are dot products of M's rows and its determinant is the squared
+// length of their cross product: no cancellation in det even for thin splats.
+// Splats with det below 1e-6 are redone in FP64.
+//
+// Outputs per slot: the splat record read by blending, the FP32 depth used as
+// the sort key, and the conservative tile rectangle of the support
+// {alpha >= 1/255} (ellipse d^T Sigma^-1 d <= 2 ln(255 o) plus one pixel).
+#include "v3dg_internal.h"
+
+namespace v3dg {
+
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase, m = -l..l),
+// normalisation K_l^m = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!), written as
+// polynomials of the unit view direction.
+constexpr float sqrtc(double x)
+{
+    // Newton iteration in double, for compile-time constants only
+    double r = x > 1 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return (float)r;
+}
+constexpr double kPiD = 3.14159265358979323846;
+constexpr float kY00 = sqrtc(1.0 / (4.0 * kPiD));
+constexpr float kY1 = sqrtc(3.0 / (4.0 * kPiD));
+constexpr float kY2a = sqrtc(15.0 / (4.0 * kPiD));   // xy, yz, xz
+constexpr float kY2b = sqrtc(5.0 / (16.0 * kPiD));   // 3z^2-1 = 2z^2-x^2-y^2
+constexpr float kY2c = sqrtc(15.0 / (16.0 * kPiD));  // x^2-y^2
+constexpr float kY3a = sqrtc(35.0 / (32.0 * kPiD));  // y(3x^2-y^2), x(x^2-3y^2)
+constexpr float kY3b = sqrtc(105.0 / (4.0 * kPiD));  // xyz
+constexpr float kY3c = sqrtc(21.0 / (32.0 * kPiD));  // y(4z^2-x^2-y^2), x(...)
+constexpr float kY3d = sqrtc(7.0 / (16.0 * kPiD));   // z(2z^2-3x^2-3y^2)
+constexpr float kY3e = sqrtc(105.0 / (16.0 * kPiD)); // z(x^2-y^2)
+
+template <int D>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
+{
+    Y[0] = kY00;
+    if (D >= 1) {
+        Y[1] = -kY1 * y;
+        Y[2] = kY1 * z;
+        Y[3] = -kY1 * x;
+    }
+    if (D >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kY2a * x * y;
+        Y[5] = -kY2a * y * z;
+        Y[6] = kY2b * (2.f * zz - xx - yy);
+        Y[7] = -kY2a * x * z;
+        Y[8] = kY2c * (xx - yy);
+        if (D >= 3) {
+            Y[9] = -kY3a * y * (3.f * xx - yy);
+            Y[10] = kY3b * x * y * z;
+            Y[11] = -kY3c * y * (4.f * zz - xx - yy);
+            Y[12] = kY3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+            Y[13] = -kY3c * x * (4.f * zz - xx - yy);
+            Y[14] = kY3e * z * (xx - yy);
+            Y[15] = -kY3a * x * (xx - 3.f * yy);
+        }
+    }
+}
+
+// FP32 depth of a mean, the cull decision and the sort key:
+// z = ((a20 px + a21 py) + a22 pz) + a23, each product and sum rounded on its
+// own (no contraction), so that every implementation gets the same bits.
+__device__ __forceinline__ float depth_z(const float *A, float px, float py, float pz)
+{
+#pragma clang fp contract(off)
+    float z = A[8] * px;
+    z = z + A[9] * py;
+    z = z + A[10] * pz;
+    z = z + A[11];
+    return z;
+}
+
+// FP64 redo of the 2D covariance for near-degenerate splats.
+__device__ __noinline__ bool cov2_fp64(const float *A, float px, float py, float pz, float z32, const float *q,
+                                       const float *s, const CamArgs &cam, double *abc)
+{
+    const double x = (double)A[0] * px + (double)A[1] * py + (double)A[2] * pz + (double)A[3];
+    const double y = (double)A[4] * px + (double)A[5] * py + (double)A[6] * pz + (double)A[7];
+    const double z = (double)A[8] * px + (double)A[9] * py + (double)A[10] * pz + (double)A[11];
+    (void)z32;
+    const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                         2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                         2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+    double M[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            M[i * 3 + j] = ((double)A[i * 4 + 0] * R[0 * 3 + j] + (double)A[i * 4 + 1] * R[1 * 3 + j] +
+                            (double)A[i * 4 + 2] * R[2 * 3 + j]) *
+                           (double)s[j];
+    double ux = x / z, uy = y / z;
+    ux = fmin(fmax(ux, -(double)cam.limx), (double)cam.limx);
+    uy = fmin(fmax(uy, -(double)cam.limy), (double)cam.limy);
+    const double j00 = cam.fx / z, j02 = -cam.fx * ux / z, j11 = cam.fy / z, j12 = -cam.fy * uy / z;
+    double m1[3], m2[3];
+    for (int j = 0; j < 3; ++j) {
+        m1[j] = j00 * M[0 * 3 + j] + j02 * M[2 * 3 + j];
+        m2[j] = j11 * M[1 * 3 + j] + j12 * M[2 * 3 + j];
+    }
+    abc[0] = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
+    abc[1] = m1[0] * m2[0] + m1[1] * m2[1] + m1[2] * m2[2];
+    abc[2] = m2[0] * m2[0] + m2[1] * m2[1] + m2[2] * m2[2];
+    const double c0 = m1[1] * m2[2] - m1[2] * m2[1];
+    const double c1 = m1[2] * m2[0] - m1[0] * m2[2];
+    const double c2 = m1[0] * m2[1] - m1[1] * m2[0];
+    abc[3] = c0 * c0 + c1 * c1 + c2 * c2;
+    return abc[3] > 0.0;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *__restrict__ planes, uint64_t ps,
+                                                      const uint32_t *__restrict__ slot_row,
+                                                      const uint32_t *__restrict__ slot_inst,
+                                                      const uint32_t *__restrict__ n_dev,
+                                                      const InstRec *__restrict__ itab, ProjectOut out)
+{
+    constexpr int NCOEF = (D + 1) * (D + 1);
+    const uint32_t n = *n_dev;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const uint32_t row = slot_row[t];
+        const uint32_t inst = slot_inst[t];
+        float A[12];
+        {
+            const float4 *ir = reinterpret_cast<const float4 *>(itab + inst);
+            const float4 r0 = ir[0], r1 = ir[1], r2 = ir[2];
+            A[0] = r0.x; A[1] = r0.y; A[2] = r0.z; A[3] = r0.w;
+            A[4] = r1.x; A[5] = r1.y; A[6] = r1.z; A[7] = r1.w;
+            A[8] = r2.x; A[9] = r2.y; A[10] = r2.z; A[11] = r2.w;
+        }
+        const float px = planes[kPlanePX * ps + row];
+        const float py = planes[kPlanePY * ps + row];
+        const float pz = planes[kPlanePZ * ps + row];
+        const float op = planes[kPlaneOP * ps + row];
+        const float z = depth_z(A, px, py, pz);
+        out.depth[t] = z;
+        // alpha = min(0.99, o e^power) <= o, so o < 1/255 never contributes
+        if (!(z > cam.near_plane) || !(z < cam.far_plane) || !(op >= 1.0f / 255.0f)) {
+            out.tiles[t] = 0u;
+            continue;
+        }
+        const float x = fmaf(A[0], px, fmaf(A[1], py, fmaf(A[2], pz, A[3])));
+        const float y = fmaf(A[4], px, fmaf(A[5], py, fmaf(A[6], pz, A[7])));
+        float q[4], s[3];
+        q[0] = planes[kPlaneQW * ps + row];
+        q[1] = planes[kPlaneQX * ps + row];
+        q[2] = planes[kPlaneQY * ps + row];
+        q[3] = planes[kPlaneQZ * ps + row];
+        s[0] = planes[kPlaneSX * ps + row];
+        s[1] = planes[kPlaneSY * ps + row];
+        s[2] = planes[kPlaneSZ * ps + row];
+        const float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+        const float R[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                            2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                            2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+        // M = W R diag(s)
+        float M[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                M[i * 3 + j] = (A[i * 4 + 0] * R[0 * 3 + j] + A[i * 4 + 1] * R[1 * 3 + j] + A[i * 4 + 2] * R[2 * 3 + j]) *
+                               s[j];
+        const float rz = 1.0f / z;
+        const float ux = fminf(fmaxf(x * rz, -cam.limx), cam.limx);
+        const float uy = fminf(fmaxf(y * rz, -cam.limy), cam.limy);
+        const float j00 = cam.fx * rz, j02 = -cam.fx * ux * rz;
+        const float j11 = cam.fy * rz, j12 = -cam.fy * uy * rz;
+        float m1[3], m2[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            m1[j] = j00 * M[0 * 3 + j] + j02 * M[2 * 3 + j];
+            m2[j] = j11 * M[1 * 3 + j] + j12 * M[2 * 3 + j];
+        }
+        float a = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
+        float b = m1[0] * m2[0] + m1[1] * m2[1] + m1[2] * m2[2];
+        float c = m2[0] * m2[0] + m2[1] * m2[1] + m2[2] * m2[2];
+        const float c0 = m1[1] * m2[2] - m1[2] * m2[1];
+        const float c1 = m1[2] * m2[0] - m1[0] * m2[2];
+        const float c2 = m1[0] * m2[1] - m1[1] * m2[0];
+        const float det = c0 * c0 + c1 * c1 + c2 * c2;
+        float ca, cb, cc;
+        if (det >= 1e-6f) {
+            const float inv = 1.0f / det;
+            ca = c * inv;
+            cb = -b * inv;
+            cc = a * inv;
+        } else {
+            double abc[4];
+            if (!cov2_fp64(A, px, py, pz, z, q, s, cam, abc)) {
+                out.tiles[t] = 0u;
+                continue;
+            }
+            const double inv = 1.0 / abc[3];
+            ca = (float)(abc[2] * inv);
+            cb = (float)(-abc[1] * inv);
+            cc = (float)(abc[0] * inv);
+            a = (float)abc[0];
+            c = (float)abc[2];
+        }
+        const float mx = cam.fx * (x * rz) + cam.cx;
+        const float my = cam.fy * (y * rz) + cam.cy;
+        // view-dependent colour in the asset frame
+        const float *ch = itab[inst].chat;
+        float dx = px - ch[0], dy = py - ch[1], dz = pz - ch[2];
+        const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= il;
+        dy *= il;
+        dz *= il;
+        float Y[NCOEF];
+        sh_basis<D>(dx, dy, dz, Y);
+        float col[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < NCOEF; ++k)
+#pragma unroll
+            for (int cch = 0; cch < 3; ++cch) col[cch] = fmaf(planes[(kPlaneSH + 3 * k + cch) * ps + row], Y[k], col[cch]);
+        // tile rectangle of the support
+        const float Q = 2.0f * __logf(255.0f * op);
+        const float hx = sqrtf(Q * a) + 1.0f, hy = sqrtf(Q * c) + 1.0f;
+        const float fx0 = fmaxf(ceilf(mx - hx - 0.5f), 0.0f);
+        const float fx1 = fminf(floorf(mx + hx - 0.5f), (float)(cam.width - 1));
+        const float fy0 = fmaxf(ceilf(my - hy - 0.5f), 0.0f);
+        const float fy1 = fminf(floorf(my + hy - 0.5f), (float)(cam.height - 1));
+        uint32_t ntiles = 0;
+        uint2 rc = make_uint2(0, 0);
+        if (fx0 <= fx1 && fy0 <= fy1) {
+            const uint32_t tx0 = (uint32_t)fx0 / kTile, tx1 = (uint32_t)fx1 / kTile;
+            const uint32_t ty0 = (uint32_t)fy0 / kTile, ty1 = (uint32_t)fy1 / kTile;
+            ntiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        }
+        out.tiles[t] = ntiles;
+        out.rect[t] = rc;
+        float4 *sp = out.splat + 3 * (uint64_t)t;
+        sp[0] = make_float4(mx, my, ca, cb);
+        sp[1] = make_float4(cc, op, fmaxf(col[0], 0.f), fmaxf(col[1], 0.f));
+        sp[2] = make_float4(fmaxf(col[2], 0.f), z, 0.f, 0.f);
+    }
+}
+
+void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uint64_t plane_stride, int sh_degree,
+                    const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
+                    uint64_t max_slots, const InstRec *itab, ProjectOut out)
+{
+    uint64_t blocks = (max_slots + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    dim3 g((uint32_t)blocks), b(256);
+    switch (sh_degree) {
+    case 0: hipLaunchKernelGGL(project_kernel<0>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    }
+}
+
+}  // namespace v3dg

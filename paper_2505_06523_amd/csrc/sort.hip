@@ -1,0 +1,409 @@
+// (d) binning of splats to 16x16 tiles and the stable radix sort of the
+// 64-bit (tile << 32 | depth bits) keys, plus the per-tile key ranges.
+//
+//   scan_tiles   exclusive scan of tiles-touched over the slot stream
+//                (single pass, decoupled look-back over ticketed partitions)
+//   emit         one key per (slot, tile of its rectangle), row-major tiles
+//   sort_hist    digit histograms of every 8-bit pass in one read of the keys
+//   sort_pass    one onesweep pass: wavefront ballot ranking into LDS, per-digit
+//                decoupled look-back across partitions, coalesced scatter
+//   tile_ranges  [start, end) of each tile in the sorted keys
+//
+// The depth is a positive FP32 (z > near > 0), so its bit pattern orders like
+// its value; the stable LSD sort keeps equal (tile, depth) keys in slot order.
+#include "v3dg_internal.h"
+
+namespace v3dg {
+
+constexpr uint32_t kSpinLimitSort = 1u << 24;
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64s(uint64_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t n = __shfl_up(v, o, kWave);
+        if (lane >= o) v += n;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t n = __shfl_up(v, o, kWave);
+        if (lane >= o) v += n;
+    }
+    return v;
+}
+
+// Exclusive scan of one u32 per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_tmp /* 4 */, uint32_t *total)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t incl = wave_incl_scan_u32(v);
+    if (lane == kWave - 1) s_tmp[wid] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        if (w < wid) off += s_tmp[w];
+        tot += s_tmp[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// scan of tiles-touched
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t *__restrict__ tiles,
+                                                                  const uint32_t *__restrict__ n_dev,
+                                                                  uint32_t *__restrict__ offsets,
+                                                                  uint64_t *__restrict__ status, uint32_t *counters)
+{
+    __shared__ uint32_t s_ticket;
+    __shared__ uint64_t s_wave[kScanThreads / kWave];
+    __shared__ uint64_t s_prefix;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t n = *n_dev;
+    const uint32_t nparts = (n + kScanPart - 1) / kScanPart;
+    if (tid == 0)
+        s_ticket = __hip_atomic_fetch_add(&counters[kRenTicketScan], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t p = s_ticket;
+    if (p >= nparts) return;
+    const uint64_t base = (uint64_t)p * kScanPart + (uint64_t)tid * kScanItems;
+    uint32_t v[kScanItems];
+    if (base + kScanItems <= n) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(tiles + base);
+#pragma unroll
+        for (int j = 0; j < kScanItems / 4; ++j) {
+            const uint4 q = src[j];
+            v[4 * j] = q.x;
+            v[4 * j + 1] = q.y;
+            v[4 * j + 2] = q.z;
+            v[4 * j + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) v[j] = (base + j < n) ? tiles[base + j] : 0u;
+    }
+    uint64_t tsum = 0;
+    uint32_t nvis = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t x = v[j];
+        v[j] = (uint32_t)tsum;  // local exclusive (fits: <= 16 * 2^20 tiles)
+        tsum += x;
+        nvis += x != 0u;
+    }
+    nvis = wave_incl_scan_u32(nvis);
+    if (lane == kWave - 1) atomicAdd(&counters[kRenVisible], nvis);
+    const uint64_t incl = wave_incl_scan_u64s(tsum);
+    if (lane == kWave - 1) s_wave[wid] = incl;
+    __syncthreads();
+    uint64_t wave_off = 0, block_total = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        if (w < wid) wave_off += s_wave[w];
+        block_total += s_wave[w];
+    }
+    const uint64_t t_excl = wave_off + incl - tsum;
+    if (tid == 0) {
+        uint64_t prefix = 0;
+        if (p == 0) {
+            __hip_atomic_store(&status[0], (kFlagInc << 62) | block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&status[p], (kFlagAgg << 62) | block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = (int64_t)p - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const uint64_t w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t flag = w >> 62;
+                if (flag == 0) {
+                    if (++spins > kSpinLimitSort) {
+                        atomicOr(&counters[kRenErr], kErrSpin);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                prefix += w & ((1ull << 62) - 1);
+                if (flag == kFlagInc) break;
+                --j;
+            }
+            __hip_atomic_store(&status[p], (kFlagInc << 62) | (prefix + block_total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_prefix = prefix;
+        if (p == nparts - 1) {
+            const uint64_t tot = prefix + block_total;
+            counters[kRenKeysLo] = (uint32_t)tot;
+            counters[kRenKeysHi] = (uint32_t)(tot >> 32);
+        }
+    }
+    __syncthreads();
+    const uint64_t b = s_prefix + t_excl;
+    if ((b + tsum) >> 32) atomicOr(&counters[kRenErr], kErrOverflow);
+    if (base + kScanItems <= n) {
+        uint4 *dst = reinterpret_cast<uint4 *>(offsets + base);
+#pragma unroll
+        for (int j = 0; j < kScanItems / 4; ++j)
+            dst[j] = make_uint4((uint32_t)(b + v[4 * j]), (uint32_t)(b + v[4 * j + 1]), (uint32_t)(b + v[4 * j + 2]),
+                                (uint32_t)(b + v[4 * j + 3]));
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j)
+            if (base + j < n) offsets[base + j] = (uint32_t)(b + v[j]);
+    }
+}
+
+void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *n_dev, uint64_t max_n,
+                       uint32_t *offsets, uint64_t *status, uint32_t *counters)
+{
+    uint64_t blocks = (max_n + kScanPart - 1) / kScanPart;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)blocks), dim3(kScanThreads), 0, st, tiles, n_dev, offsets,
+                       status, counters);
+}
+
+// ---------------------------------------------------------------------------
+// key emission
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) emit_kernel(uint32_t n, const uint32_t *__restrict__ tiles,
+                                                   const uint32_t *__restrict__ offsets,
+                                                   const uint2 *__restrict__ rect, const float *__restrict__ depth,
+                                                   uint32_t tiles_x, uint64_t key_cap, uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ vals)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const uint32_t nt = tiles[t];
+        if (nt == 0) continue;
+        uint64_t off = offsets[t];
+        if (off + nt > key_cap) continue;
+        const uint2 rc = rect[t];
+        const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
+        const uint64_t d = __float_as_uint(depth[t]);
+        for (uint32_t ty = ty0; ty <= ty1; ++ty) {
+            for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+                keys[off] = ((uint64_t)(ty * tiles_x + tx) << 32) | d;
+                vals[off] = t;
+                ++off;
+            }
+        }
+    }
+}
+
+void launch_emit(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
+                 const float *depth, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals)
+{
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(emit_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, n, tiles, offsets, rect, depth, tiles_x,
+                       key_cap, keys, vals);
+}
+
+// ---------------------------------------------------------------------------
+// digit histograms for all passes
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *__restrict__ keys, uint64_t n, int passes,
+                                                        uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_h[8 * kRadix];
+    for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t k = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * kRadix + ((k >> (p * kRadixBits)) & (kRadix - 1))], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+void launch_sort_hist(hipStream_t st, const uint64_t *keys, uint64_t n, int passes, uint32_t *hist)
+{
+    if (n == 0) return;
+    uint64_t blocks = (n + 256 * 32 - 1) / (256 * 32);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(sort_hist_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, keys, n, passes, hist);
+}
+
+// ---------------------------------------------------------------------------
+// one onesweep digit pass
+// ---------------------------------------------------------------------------
+// look-back word: epoch (30 bits) | flag (2 bits) | count (32 bits)
+__device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint32_t v)
+{
+    return ((uint64_t)epoch << 34) | (flag << 32) | v;
+}
+
+__global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t *__restrict__ keys_in,
+                                                                 const uint32_t *__restrict__ vals_in,
+                                                                 uint64_t *__restrict__ keys_out,
+                                                                 uint32_t *__restrict__ vals_out, uint32_t n,
+                                                                 int shift, const uint32_t *__restrict__ hist,
+                                                                 uint64_t *status, uint32_t epoch, uint32_t *ticket,
+                                                                 uint32_t *err)
+{
+    constexpr int NW = kSortThreads / kWave;           // waves per block
+    constexpr int WAVE_KEYS = kSortPart / NW;          // consecutive keys owned by a wave
+    constexpr int ROUNDS = WAVE_KEYS / kWave;          // = kSortItems
+    __shared__ uint64_t s_keys[kSortPart];
+    __shared__ uint32_t s_vals[kSortPart];
+    __shared__ uint32_t s_whist[NW][kRadix];
+    __shared__ uint32_t s_lstart[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_ticket;
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    for (int i = tid; i < NW * kRadix; i += kSortThreads) (&s_whist[0][0])[i] = 0u;
+    if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t p = s_ticket;
+    const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+    if (p >= nparts) return;
+    const uint32_t part_base = p * (uint32_t)kSortPart;
+    const uint32_t wave_base = part_base + (uint32_t)wid * WAVE_KEYS;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+
+    uint64_t key[ROUNDS];
+    uint32_t val[ROUNDS];
+    uint32_t dr[ROUNDS];  // digit | rank-in-wave << 8
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t idx = wave_base + r * kWave + lane;
+        const bool valid = idx < n;
+        const uint64_t k = valid ? keys_in[idx] : 0ull;
+        key[r] = k;
+        val[r] = valid ? vals_in[idx] : 0u;
+        const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t rank_in_round = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        uint32_t old = 0;
+        if (valid) old = s_whist[wid][d];
+        if (valid && rank_in_round == 0) s_whist[wid][d] = old + cnt;
+        dr[r] = d | ((old + rank_in_round) << 8);
+    }
+    __syncthreads();
+
+    // per-digit totals, wave offsets, look-back
+    const int d = tid;  // kSortThreads == kRadix
+    uint32_t c[NW];
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        c[w] = s_whist[w][d];
+        s_whist[w][d] = total;
+        total += c[w];
+    }
+    uint64_t *my = status + (uint64_t)p * kRadix + d;
+    uint32_t prefix = 0;
+    if (p == 0) {
+        __hip_atomic_store(my, lb_word(epoch, kFlagInc, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(my, lb_word(epoch, kFlagAgg, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t j = (int64_t)p - 1;
+        uint32_t spins = 0;
+        while (j >= 0) {
+            const uint64_t w = __hip_atomic_load(status + (uint64_t)j * kRadix + d, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = ((uint32_t)(w >> 34) == epoch) ? ((w >> 32) & 3ull) : 0ull;
+            if (flag == 0) {
+                if (++spins > kSpinLimitSort) {
+                    atomicOr(err, kErrSpin);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            prefix += (uint32_t)w;
+            if (flag == kFlagInc) break;
+            --j;
+        }
+        __hip_atomic_store(my, lb_word(epoch, kFlagInc, prefix + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint32_t tot_all;
+    const uint32_t lstart = block_excl_scan_256(total, s_tmp, &tot_all);
+    uint32_t hist_tot;
+    const uint32_t gstart = block_excl_scan_256(hist[d], s_tmp, &hist_tot);
+    s_lstart[d] = lstart;
+    s_gbase[d] = gstart + prefix;
+    __syncthreads();
+
+    // reorder into LDS by digit (stable: wave order, then round, then lane)
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t idx = wave_base + r * kWave + lane;
+        if (idx < n) {
+            const uint32_t dd = dr[r] & (kRadix - 1);
+            const uint32_t pos = s_lstart[dd] + s_whist[wid][dd] + (dr[r] >> 8);
+            s_keys[pos] = key[r];
+            s_vals[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t n_here = (n - part_base) < (uint32_t)kSortPart ? (n - part_base) : (uint32_t)kSortPart;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t i = tid + r * kSortThreads;
+        if (i < n_here) {
+            const uint64_t k = s_keys[i];
+            const uint32_t dd = (uint32_t)(k >> shift) & (kRadix - 1);
+            const uint32_t o = s_gbase[dd] + (i - s_lstart[dd]);
+            if (o < n) {  // always true when the histogram and look-back agree
+                keys_out[o] = k;
+                vals_out[o] = s_vals[i];
+            }
+        }
+    }
+}
+
+void launch_sort_pass(hipStream_t st, const uint64_t *keys_in, const uint32_t *vals_in, uint64_t *keys_out,
+                      uint32_t *vals_out, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
+                      uint32_t epoch, uint32_t *ticket, uint32_t *err)
+{
+    if (n == 0) return;
+    const uint32_t nparts = (uint32_t)((n + kSortPart - 1) / kSortPart);
+    hipLaunchKernelGGL(sort_pass_kernel, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
+                       vals_out, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix, status, epoch, ticket, err);
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint64_t *__restrict__ keys, uint32_t n,
+                                                          uint2 *__restrict__ ranges)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t t = (uint32_t)(keys[i] >> 32);
+        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = i;
+        if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = i + 1;
+    }
+}
+
+void launch_tile_ranges(hipStream_t st, const uint64_t *keys, uint64_t n, uint2 *ranges)
+{
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(tile_ranges_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, keys, (uint32_t)n, ranges);
+}
+
+}  // namespace v3dg

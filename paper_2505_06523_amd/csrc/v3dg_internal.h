@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP kernels and the C++ runtime of v3dg.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace v3dg {
+
+constexpr int kTile = 16;               // tile edge in pixels
+constexpr int kWave = 64;               // CDNA wavefront width
+
+// Gaussian attribute planes (structure of arrays, one float plane each,
+// plane stride = padded row count).  SH coefficient k, channel c lives in
+// plane kPlaneSH + 3k + c.
+constexpr int kPlanePX = 0, kPlanePY = 1, kPlanePZ = 2;
+constexpr int kPlaneSX = 3, kPlaneSY = 4, kPlaneSZ = 5;
+constexpr int kPlaneQW = 6, kPlaneQX = 7, kPlaneQY = 8, kPlaneQZ = 9;
+constexpr int kPlaneOP = 10, kPlaneSH = 11;
+
+// Per-instance frame record (64 B): A = fl32(V T) row-major 3x4, the camera
+// centre in the asset frame (for view-dependent colour) and the uniform scale.
+struct alignas(16) InstRec {
+    float A[12];
+    float chat[3];
+    float s;
+};
+
+// Camera constants passed by value to kernels.
+struct CamArgs {
+    float V[12];
+    double cw[3];            // camera centre in world space (FP64)
+    float fx, fy, cx, cy;
+    float near_plane, far_plane;
+    float limx, limy;        // guard band of the EWA Jacobian: 1.3 * tan(half fov)
+    float bg[3];
+    uint32_t width, height, tiles_x, tiles_y;
+};
+
+// Look-back status words: two flag bits above the payload.
+constexpr uint64_t kFlagAgg = 1ull;
+constexpr uint64_t kFlagInc = 2ull;
+
+// Device-side frame counters (u32 words) of a selection.
+enum SelCounter : int {
+    kSelTicket = 0,
+    kSelErr = 1,
+    kSelNClusters = 2,
+    kSelNGaussians = 3,
+    kSelCounters = 8
+};
+
+// Device-side frame counters of a render workspace.
+enum RenderCounter : int {
+    kRenTicketScan = 0,
+    kRenErr = 1,
+    kRenKeysLo = 2,       // total keys (64-bit, lo/hi)
+    kRenKeysHi = 3,
+    kRenVisible = 4,      // slots with at least one tile
+    kRenTicketSort = 8,   // 8 passes
+    kRenHist = 16,        // 8 passes x 256 bins
+    kRenCounters = 16 + 8 * 256
+};
+
+// Error flag bits
+constexpr uint32_t kErrSpin = 1u;       // a bounded look-back wait expired
+constexpr uint32_t kErrOverflow = 2u;   // a count did not fit its field
+
+// ---- launch wrappers (implemented in the .hip files) ----------------------
+void launch_frame_setup(hipStream_t st, const CamArgs &cam, const double *T, const float *inst_scale,
+                        uint32_t n_inst, InstRec *itab, uint32_t *clear, uint64_t n_clear);
+
+// select.hip
+constexpr int kSelThreads = 256;
+constexpr int kSelItems = 8;
+constexpr int kSelPart = kSelThreads * kSelItems;
+void launch_select(hipStream_t st, const float4 *self_sph, const float4 *par_sph, const uint2 *rowinfo,
+                   const InstRec *itab, uint32_t n_clusters, uint32_t n_inst, float K, float tau,
+                   uint32_t *gid_out, uint32_t *slot_off_out, uint64_t *status, uint32_t *counters);
+void launch_expand(hipStream_t st, const uint32_t *gid, const uint32_t *slot_off, const uint2 *rowinfo,
+                   uint32_t n_clusters, const uint32_t *counters, uint32_t max_clusters, uint32_t *slot_row,
+                   uint32_t *slot_inst);
+
+// project.hip
+struct ProjectOut {
+    float4 *splat;      // 3 float4 per slot: (mx,my,A,B) (C,o,r,g) (b,depth,0,0)
+    float *depth;
+    uint2 *rect;        // (tx0 | tx1<<16, ty0 | ty1<<16)
+    uint32_t *tiles;
+};
+void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uint64_t plane_stride, int sh_degree,
+                    const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
+                    uint64_t max_slots, const InstRec *itab, ProjectOut out);
+
+// sort.hip
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanPart = kScanThreads * kScanItems;
+void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *n_dev, uint64_t max_n,
+                       uint32_t *offsets, uint64_t *status, uint32_t *counters);
+void launch_emit(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
+                 const float *depth, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals);
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;          // keys per thread
+constexpr int kSortPart = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 256;
+void launch_sort_hist(hipStream_t st, const uint64_t *keys, uint64_t n, int passes, uint32_t *hist);
+void launch_sort_pass(hipStream_t st, const uint64_t *keys_in, const uint32_t *vals_in, uint64_t *keys_out,
+                      uint32_t *vals_out, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
+                      uint32_t epoch, uint32_t *ticket, uint32_t *err);
+void launch_tile_ranges(hipStream_t st, const uint64_t *keys, uint64_t n, uint2 *ranges);
+
+// blend.hip
+void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals,
+                  const uint2 *ranges, float *image, unsigned long long *pairs);
+
+// generic fill
+void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);
+
+}  // namespace v3dg

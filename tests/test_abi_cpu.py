@@ -1,0 +1,123 @@
+"""The C ABI on the CPU: every declared symbol is exported, and the loader's
+host-side validation rejects malformed inputs before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2505_06523_amd as v
+import scenegen as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "v3dg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(v3dg_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 15
+    L = v.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(v.EXPORTS)
+
+
+def test_last_error_initially_empty():
+    assert isinstance(v.last_error(), str)
+
+
+@pytest.fixture
+def small():
+    return sg.make_asset(2048, 1, 4)
+
+
+def _expect(asset, code, instances=None, flags=0):
+    with pytest.raises(v.V3DGError) as ei:
+        v.Scene(asset, instances, stream=0, flags=flags)
+    assert ei.value.code == code, str(ei.value)
+    return str(ei.value)
+
+
+def test_rejects_non_monotone(small):
+    a = small
+    root = a.n_clusters - 1
+    a.self_sphere[root, 3] = np.float32(1e-3)
+    a.parent_sphere[a.parent == root, 3] = np.float32(1e-3)
+    msg = _expect(a, v.V3DG_ERR_NOT_MONOTONE)
+    assert "nest" in msg
+
+
+def test_rejects_parent_copy_mismatch(small):
+    a = small
+    k = a.n_leaf_clusters + 1
+    a.parent_sphere[k, 0] += np.float32(1e-3)
+    _expect(a, v.V3DG_ERR_INVALID_ARG)
+
+
+def test_rejects_leaf_radius(small):
+    a = small
+    a.self_sphere[0, 3] = 0.01
+    _expect(a, v.V3DG_ERR_INVALID_ARG)
+
+
+def test_rejects_bad_quaternion(small):
+    a = small
+    a.rot[5] = [0.9, 0.0, 0.0, 0.0]
+    _expect(a, v.V3DG_ERR_INVALID_ARG)
+
+
+def test_rejects_nan_position(small):
+    a = small
+    a.pos[7, 1] = np.nan
+    _expect(a, v.V3DG_ERR_INVALID_ARG)
+
+
+def test_rejects_bad_opacity(small):
+    a = small
+    a.opacity[3] = 0.0
+    _expect(a, v.V3DG_ERR_INVALID_ARG)
+
+
+def test_rejects_bad_count_and_tree(small):
+    a = small
+    a.count[2] = 0
+    _expect(a, v.V3DG_ERR_INVALID_ARG)
+    b = sg.make_asset(2048, 1, 4)
+    b.parent[3] = 5  # child no longer points back to its parent
+    _expect(b, v.V3DG_ERR_INVALID_ARG)
+
+
+def test_rejects_sheared_or_mirrored_instances(small):
+    T = sg.identity_instances(1).copy()
+    T[0, 0, 1] = 0.3
+    _expect(small, v.V3DG_ERR_INVALID_ARG, T)
+    M = sg.identity_instances(1).copy()
+    M[0, 0, 0] = -1.0
+    _expect(small, v.V3DG_ERR_INVALID_ARG, M)
+    N = sg.identity_instances(1).copy()
+    N[0, 1, 3] = np.inf
+    _expect(small, v.V3DG_ERR_INVALID_ARG, N)
+
+
+def test_rejects_too_many_tests():
+    a = sg.make_asset(64 * 64, 0, 1)  # 85 clusters
+    T = np.tile(sg.identity_instances(1), (800000, 1, 1))  # 85 * 8e5 > 2^26
+    _expect(a, v.V3DG_ERR_CAPACITY, T)
+
+
+def test_null_arguments():
+    L = v.lib()
+    out = C.c_void_p()
+    assert L.v3dg_load_hierarchy(None, None, 0, None, 0, C.byref(out)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_select(None, None, C.c_float(1.0), None) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_render(None, None, None, None) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_sort_pairs(None, None, 10, 0, None) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_sort_pairs(None, None, 0, 8, None) == v.V3DG_OK
+    L.v3dg_selection_free(None)
+    L.v3dg_scene_free(None)
