@@ -57,17 +57,27 @@ def pct(xs, q):
 
 
 def stage_bytes(P: dict, b_row: int) -> dict:
-    """Algorithmic HBM bytes per stage over the profiled frames."""
-    passes = P["sort_passes"] / max(P["frames"], 1)
+    """Algorithmic HBM bytes per stage over the profiled frames.
+
+    Depth-first binning (the default): the depth sort moves 4 B per slot for
+    its histogram and 16 B (key + value, read and written) per slot and pass
+    (4 passes); emission writes 8 B per key; the tile sort reads 4 B per key for
+    its histogram and moves 16 B per key and pass.
+    """
+    fr = max(P["frames"], 1)
+    passes = P["sort_passes"] / fr
+    depth_first = P["depth_sorts"] > 0
+    kb = 4 if depth_first else 8          # key bytes
     return {
         "select": P["tests"] * 32 + P["sel_clusters"] * 8,
         "expand": P["sel_clusters"] * 16 + P["slots"] * 8,
-        "project": P["slots"] * 32 + P["visible"] * ((b_row - 16) + 56),
-        "scan": P["slots"] * 8,
-        "emit": P["slots"] * 4 + P["visible"] * 16 + P["keys"] * 12,
-        "sort_hist": P["keys"] * 8,
-        "sort_pass": P["keys"] * 24 * passes,
-        "ranges": P["keys"] * 8 + P["tiles"] * 8,
+        "project": P["slots"] * 28 + P["visible"] * ((b_row - 16) + 48 + 32 + 8 + 8),
+        "depth_sort": P["slots"] * (4 + 4 * 16) * (P["depth_sorts"] / fr),
+        "scan": P["slots"] * 12,
+        "emit": P["visible"] * (4 + 4 + 8 + 32) + P["keys"] * (kb + 4),
+        "sort_hist": P["keys"] * kb,
+        "sort_pass": P["keys"] * (2 * (kb + 4)) * passes,
+        "ranges": P["keys"] * kb + P["tiles"] * 8,
         "blend": P["keys"] * 52 + P["pixels"] * 16,
     }
 
@@ -196,8 +206,8 @@ def main():
         ach = sb[dom] / n_dom / (t_dom / n_dom * 1e-3) / 1e9
         roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                     traffic=None, bytes_per_launch=sb[dom] / n_dom, avg_launch_ms=t_dom / n_dom)
-    sort_t = P["stages"]["sort_pass"][0] + P["stages"]["sort_hist"][0]
-    sort_b = sb["sort_pass"] + sb["sort_hist"]
+    sort_t = P["stages"]["sort_pass"][0] + P["stages"]["sort_hist"][0] + P["stages"]["depth_sort"][0]
+    sort_b = sb["sort_pass"] + sb["sort_hist"] + sb["depth_sort"]
 
     out = {
         "metric": METRIC,

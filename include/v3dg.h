@@ -85,14 +85,21 @@ typedef struct {
     const float *sh;            /* n_rows x (sh_degree+1)^2 x 3 */
 } v3dg_hierarchy_desc;
 
+/* How each tile's splats are put in front-to-back order (same result):
+ * DEPTH_FIRST sorts the slots by FP32 depth, emits 32-bit tile ids in that
+ * order and stably sorts them by tile; KEYS64 emits (tile << 32 | depth bits)
+ * keys in slot order and sorts all their significant bits. */
+#define V3DG_SORT_DEPTH_FIRST 0
+#define V3DG_SORT_KEYS64 1
+
 /* Counters of the last frame rendered on a scene. */
 typedef struct {
     uint64_t n_slots;    /* Gaussians in the rendered selection            */
     uint64_t n_keys;     /* (tile, splat) pairs sorted                     */
     uint32_t n_tiles;    /* tiles in the image                             */
-    uint32_t key_bits;   /* significant bits of the sort key               */
-    uint32_t sort_passes;
-    uint32_t pad0;
+    uint32_t key_bits;   /* significant bits of the (last) sort key        */
+    uint32_t sort_passes;/* radix passes of the tile / 64-bit key sort     */
+    uint32_t sort_mode;  /* V3DG_SORT_*                                    */
 } v3dg_frame_stats;
 
 /* Kernel stages timed when profiling is on (v3dg_set_profiling). */
@@ -106,7 +113,8 @@ typedef struct {
 #define V3DG_STAGE_SORT_PASS 7
 #define V3DG_STAGE_RANGES 8
 #define V3DG_STAGE_BLEND 9
-#define V3DG_N_STAGES 10
+#define V3DG_STAGE_DEPTH_SORT 10 /* histogram + passes of the depth sort */
+#define V3DG_N_STAGES 11
 
 /* Upload an asset and its instances to HBM and validate it.
  * Validation (paper Sec. 3.4 keeps r_p > r_c so that a cluster and its parent
@@ -170,8 +178,8 @@ int v3dg_get_frame_stats(v3dg_scene *scene, v3dg_frame_stats *out);
 int v3dg_copy_projection(v3dg_scene *scene, float *mean2, float *conic, float *rgb, float *opacity, float *depth,
                          uint32_t *tiles, uint64_t cap, uint64_t *n_out);
 
-/* The last frame's sorted keys (tile << 32 | depth bits) and values (slot)
- * (synchronises). */
+/* The last frame's sorted keys as (tile << 32 | depth bits) and values
+ * (slot), whatever the sort mode (synchronises). */
 int v3dg_copy_sorted_keys(v3dg_scene *scene, uint64_t *keys, uint32_t *vals, uint64_t cap, uint64_t *n_out);
 
 /* Work done and time spent since the previous v3dg_collect_profile. */
@@ -183,9 +191,14 @@ typedef struct {
     uint64_t sel_clusters;             /* selected clusters of the rendered selections*/
     uint64_t slots, visible;           /* Gaussians projected / with a tile           */
     uint64_t keys, tiles, pixels;      /* sorted keys, image tiles, image pixels      */
-    uint64_t sort_passes;              /* digit passes run                            */
+    uint64_t sort_passes;              /* digit passes of the tile / 64-bit key sort  */
+    uint64_t depth_sorts;              /* frames that sorted slots by depth first     */
     uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending  */
 } v3dg_profile;
+
+/* Select the sort strategy for later renders of this scene (default
+ * V3DG_SORT_DEPTH_FIRST).  Both give bit-identical images. */
+int v3dg_set_sort_mode(v3dg_scene *scene, int mode);
 
 /* Stage timing with hipEvents on the scene's stream.  While on, every kernel
  * launch is bracketed by events.  Work counters are kept either way.

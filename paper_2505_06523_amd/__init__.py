@@ -27,7 +27,10 @@ V3DG_ERR_CAPACITY = -5
 V3DG_ERR_DEVICE = -6
 V3DG_FP32 = 0
 V3DG_LOAD_REPAIR_NESTING = 1
-STAGES = ["setup", "select", "expand", "project", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend"]
+V3DG_SORT_DEPTH_FIRST = 0
+V3DG_SORT_KEYS64 = 1
+STAGES = ["setup", "select", "expand", "project", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend",
+          "depth_sort"]
 
 
 class V3DGError(RuntimeError):
@@ -52,21 +55,22 @@ class v3dg_hierarchy_desc(C.Structure):
 
 class v3dg_frame_stats(C.Structure):
     _fields_ = [("n_slots", C.c_uint64), ("n_keys", C.c_uint64), ("n_tiles", C.c_uint32),
-                ("key_bits", C.c_uint32), ("sort_passes", C.c_uint32), ("pad0", C.c_uint32)]
+                ("key_bits", C.c_uint32), ("sort_passes", C.c_uint32), ("sort_mode", C.c_uint32)]
 
 
 class v3dg_profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 10), ("launches", C.c_uint64 * 10), ("frames", C.c_uint64),
+    _fields_ = [("ms", C.c_double * 11), ("launches", C.c_uint64 * 11), ("frames", C.c_uint64),
                 ("selects", C.c_uint64), ("tests", C.c_uint64), ("sel_clusters", C.c_uint64),
                 ("slots", C.c_uint64), ("visible", C.c_uint64), ("keys", C.c_uint64), ("tiles", C.c_uint64),
-                ("pixels", C.c_uint64), ("sort_passes", C.c_uint64), ("pairs", C.c_uint64)]
+                ("pixels", C.c_uint64), ("sort_passes", C.c_uint64), ("depth_sorts", C.c_uint64),
+                ("pairs", C.c_uint64)]
 
 
 EXPORTS = [
     "v3dg_load_hierarchy", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_sorted_keys",
-    "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs", "v3dg_last_error",
+    "v3dg_set_sort_mode", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs", "v3dg_last_error",
 ]
 
 _lib = None
@@ -95,6 +99,7 @@ def lib():
         "v3dg_get_frame_stats": ([P, P], I),
         "v3dg_copy_projection": ([P, P, P, P, P, P, P, U64, P], I),
         "v3dg_copy_sorted_keys": ([P, P, P, U64, P], I),
+        "v3dg_set_sort_mode": ([P, I], I),
         "v3dg_set_profiling": ([P, I], I),
         "v3dg_collect_profile": ([P, P], I),
         "v3dg_sort_pairs": ([P, P, U64, U32, P], I),
@@ -181,7 +186,7 @@ def v3dg_get_frame_stats(scene) -> dict:
     st = v3dg_frame_stats()
     _check(lib().v3dg_get_frame_stats(scene, C.byref(st)))
     return dict(n_slots=st.n_slots, n_keys=st.n_keys, n_tiles=st.n_tiles, key_bits=st.key_bits,
-                sort_passes=st.sort_passes)
+                sort_passes=st.sort_passes, sort_mode=st.sort_mode)
 
 
 def v3dg_copy_projection(scene, n_slots: int) -> dict:
@@ -202,6 +207,10 @@ def v3dg_copy_sorted_keys(scene, n_keys: int):
     got = C.c_uint64()
     _check(lib().v3dg_copy_sorted_keys(scene, _p(keys), _p(vals), n, C.byref(got)))
     return keys[: got.value], vals[: got.value]
+
+
+def v3dg_set_sort_mode(scene, mode: int):
+    _check(lib().v3dg_set_sort_mode(scene, int(mode)))
 
 
 def v3dg_set_profiling(scene, on: bool):
@@ -350,6 +359,9 @@ class Scene:
 
     def sorted_keys(self):
         return v3dg_copy_sorted_keys(self.handle, self.frame_stats()["n_keys"])
+
+    def set_sort_mode(self, mode: int):
+        v3dg_set_sort_mode(self.handle, mode)
 
     def set_profiling(self, on: bool = True):
         v3dg_set_profiling(self.handle, on)

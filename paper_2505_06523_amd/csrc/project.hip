@@ -141,11 +141,11 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
         const float op = planes[kPlaneOP * ps + row];
         const float z = depth_z(A, px, py, pz);
         out.depth[t] = z;
+        out.dval[t] = t;
+        out.dkey[t] = 0xffffffffu;  // culled slots sort last and emit nothing
+        out.tiles[t] = 0u;
         // alpha = min(0.99, o e^power) <= o, so o < 1/255 never contributes
-        if (!(z > cam.near_plane) || !(z < cam.far_plane) || !(op >= 1.0f / 255.0f)) {
-            out.tiles[t] = 0u;
-            continue;
-        }
+        if (!(z > cam.near_plane) || !(z < cam.far_plane) || !(op >= 1.0f / 255.0f)) continue;
         const float x = fmaf(A[0], px, fmaf(A[1], py, fmaf(A[2], pz, A[3])));
         const float y = fmaf(A[4], px, fmaf(A[5], py, fmaf(A[6], pz, A[7])));
         float q[4], s[3];
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
         const float c1 = m1[2] * m2[0] - m1[0] * m2[2];
         const float c2 = m1[0] * m2[1] - m1[1] * m2[0];
         const float det = c0 * c0 + c1 * c1 + c2 * c2;
-        float ca, cb, cc;
+        float ca, cb, cc, det_s = det;
         if (det >= 1e-6f) {
             const float inv = 1.0f / det;
             ca = c * inv;
@@ -194,16 +194,15 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
             cc = a * inv;
         } else {
             double abc[4];
-            if (!cov2_fp64(A, px, py, pz, z, q, s, cam, abc)) {
-                out.tiles[t] = 0u;
-                continue;
-            }
+            if (!cov2_fp64(A, px, py, pz, z, q, s, cam, abc)) continue;
             const double inv = 1.0 / abc[3];
             ca = (float)(abc[2] * inv);
             cb = (float)(-abc[1] * inv);
             cc = (float)(abc[0] * inv);
             a = (float)abc[0];
+            b = (float)abc[1];
             c = (float)abc[2];
+            det_s = (float)abc[3];
         }
         const float mx = cam.fx * (x * rz) + cam.cx;
         const float my = cam.fy * (y * rz) + cam.cy;
@@ -221,27 +220,40 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
         for (int k = 0; k < NCOEF; ++k)
 #pragma unroll
             for (int cch = 0; cch < 3; ++cch) col[cch] = fmaf(planes[(kPlaneSH + 3 * k + cch) * ps + row], Y[k], col[cch]);
-        // tile rectangle of the support
+        // tile coverage of the (enlarged) support
         const float Q = 2.0f * __logf(255.0f * op);
-        const float hx = sqrtf(Q * a) + 1.0f, hy = sqrtf(Q * c) + 1.0f;
+        BinRec br;
+        br.mx = mx;
+        br.my = my;
+        br.sa = a;
+        br.sb = b;
+        br.sc = c;
+        br.det = det_s;
+        br.Qm = 1.05f * Q + 0.05f;
+        br.depth = z;
+        const float hx = sqrtf(br.Qm * a) + 1.0f, hy = sqrtf(br.Qm * c) + 1.0f;
         const float fx0 = fmaxf(ceilf(mx - hx - 0.5f), 0.0f);
         const float fx1 = fminf(floorf(mx + hx - 0.5f), (float)(cam.width - 1));
         const float fy0 = fmaxf(ceilf(my - hy - 0.5f), 0.0f);
         const float fy1 = fminf(floorf(my + hy - 0.5f), (float)(cam.height - 1));
+        if (!(fx0 <= fx1 && fy0 <= fy1)) continue;
+        const uint32_t tx0 = (uint32_t)fx0 / kTile, tx1 = (uint32_t)fx1 / kTile;
+        const uint32_t ty0 = (uint32_t)fy0 / kTile, ty1 = (uint32_t)fy1 / kTile;
         uint32_t ntiles = 0;
-        uint2 rc = make_uint2(0, 0);
-        if (fx0 <= fx1 && fy0 <= fy1) {
-            const uint32_t tx0 = (uint32_t)fx0 / kTile, tx1 = (uint32_t)fx1 / kTile;
-            const uint32_t ty0 = (uint32_t)fy0 / kTile, ty1 = (uint32_t)fy1 / kTile;
-            ntiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-            rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        for (uint32_t ty = ty0; ty <= ty1; ++ty) {
+            uint32_t lo, hi;
+            if (tile_row_span(br, ty, tx0, tx1, &lo, &hi)) ntiles += hi - lo + 1;
         }
+        if (ntiles == 0) continue;
         out.tiles[t] = ntiles;
-        out.rect[t] = rc;
+        out.dkey[t] = __float_as_uint(z);
+        out.rect[t] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        out.bin[t] = br;
         float4 *sp = out.splat + 3 * (uint64_t)t;
         sp[0] = make_float4(mx, my, ca, cb);
         sp[1] = make_float4(cc, op, fmaxf(col[0], 0.f), fmaxf(col[1], 0.f));
-        sp[2] = make_float4(fmaxf(col[2], 0.f), z, 0.f, 0.f);
+        // support half-extents (enlarged like the binning), used to cull per 8x8 block
+        sp[2] = make_float4(fmaxf(col[2], 0.f), z, sqrtf(br.Qm * a), sqrtf(br.Qm * c));
     }
 }
 

@@ -112,10 +112,14 @@ struct v3dg_scene {
     // render workspace
     uint64_t cap_slots = 0;
     float4 *splat = nullptr;
+    BinRec *bin = nullptr;
     float *depth = nullptr;
     uint2 *rect = nullptr;
     uint32_t *tiles = nullptr;
     uint32_t *offsets = nullptr;
+    uint32_t *dkey[2] = {nullptr, nullptr};
+    uint32_t *dval[2] = {nullptr, nullptr};
+    int sort_mode = V3DG_SORT_DEPTH_FIRST;
     uint32_t *rclear = nullptr;  // counters + scan look-back + tile ranges, cleared every frame
     uint64_t rclear_words = 0;
     uint64_t scan_parts = 0;
@@ -278,17 +282,25 @@ int sel_alloc(v3dg_scene *sc, v3dg_selection *s)
 }
 
 // ---- render workspace ----------------------------------------------------------------
+int ensure_status(v3dg_scene *s, uint64_t parts);
+
 int ensure_slots(v3dg_scene *s)
 {
     if (s->splat) return V3DG_OK;
     const uint64_t n = s->cap_slots;
     int rc;
     if ((rc = dev_alloc(&s->splat, 3 * n))) return rc;
+    if ((rc = dev_alloc(&s->bin, n))) return rc;
     if ((rc = dev_alloc(&s->depth, n))) return rc;
     if ((rc = dev_alloc(&s->rect, n))) return rc;
     if ((rc = dev_alloc(&s->tiles, n))) return rc;
     if ((rc = dev_alloc(&s->offsets, n))) return rc;
+    for (int b = 0; b < 2; ++b) {
+        if ((rc = dev_alloc(&s->dkey[b], n))) return rc;
+        if ((rc = dev_alloc(&s->dval[b], n))) return rc;
+    }
     s->scan_parts = (n + kScanPart - 1) / kScanPart;
+    if ((rc = ensure_status(s, (n + kSortPart - 1) / kSortPart))) return rc;
     return V3DG_OK;
 }
 
@@ -303,6 +315,20 @@ int ensure_tiles(v3dg_scene *s, uint32_t n_tiles)
     s->rcounters = s->rclear;
     s->scan_status = reinterpret_cast<uint64_t *>(s->rclear + kRenCounters);
     s->ranges = reinterpret_cast<uint2 *>(s->rclear + kRenCounters + 2 * s->scan_parts);
+    return V3DG_OK;
+}
+
+int ensure_status(v3dg_scene *s, uint64_t parts)
+{
+    if (parts <= s->sort_status_parts) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    dev_free(s->sort_status);
+    const uint64_t np = std::max<uint64_t>(parts + parts / 2, 256);
+    int rc;
+    if ((rc = dev_alloc(&s->sort_status, np * kRadix))) return rc;
+    HIP_TRY(hipMemsetAsync(s->sort_status, 0, np * kRadix * sizeof(uint64_t), s->stream));
+    s->sort_status_parts = np;
+    s->epoch = 0;
     return V3DG_OK;
 }
 
@@ -324,17 +350,7 @@ int ensure_keys(v3dg_scene *s, uint64_t K)
         }
         s->cap_keys = cap;
     }
-    if (parts > s->sort_status_parts) {
-        HIP_TRY(hipStreamSynchronize(s->stream));
-        dev_free(s->sort_status);
-        const uint64_t np = std::max<uint64_t>(parts + parts / 2, 256);
-        int rc;
-        if ((rc = dev_alloc(&s->sort_status, np * kRadix))) return rc;
-        HIP_TRY(hipMemsetAsync(s->sort_status, 0, np * kRadix * sizeof(uint64_t), s->stream));
-        s->sort_status_parts = np;
-        s->epoch = 0;
-    }
-    return V3DG_OK;
+    return ensure_status(s, parts);
 }
 
 uint32_t next_epoch(v3dg_scene *s)
@@ -346,22 +362,23 @@ uint32_t next_epoch(v3dg_scene *s)
     return s->epoch;
 }
 
-// Sort K keys in keys[0]/vals[0] by their low key_bits bits; returns the
-// buffer index that holds the result.
-int run_sort(v3dg_scene *s, uint64_t K, uint32_t key_bits, int *out_buf, uint32_t *passes_out)
+// Stable sort of K (key, value) pairs held in buffer 0 by the low key_bits
+// bits of the keys; *out_buf receives the buffer index holding the result.
+template <typename KT>
+int run_sort(v3dg_scene *s, KT *const kb[2], uint32_t *const vb[2], uint64_t K, uint32_t key_bits, int *out_buf,
+             uint32_t *passes_out)
 {
     const int passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
     *passes_out = (uint32_t)passes;
     int cur = 0;
     {
         Stage st(s, V3DG_STAGE_SORT_HIST);
-        launch_sort_hist(s->stream, s->keys[0], K, passes, s->rcounters + kRenHist);
+        launch_sort_hist<KT>(s->stream, kb[0], K, passes, s->rcounters + kRenHist);
     }
     for (int p = 0; p < passes; ++p) {
         Stage st(s, V3DG_STAGE_SORT_PASS);
-        launch_sort_pass(s->stream, s->keys[cur], s->vals[cur], s->keys[cur ^ 1], s->vals[cur ^ 1], K, p,
-                         s->rcounters + kRenHist, s->sort_status, next_epoch(s), s->rcounters + kRenTicketSort + p,
-                         s->rcounters + kRenErr);
+        launch_sort_pass<KT>(s->stream, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], K, p, s->rcounters + kRenHist,
+                             s->sort_status, next_epoch(s), s->rcounters + kRenTicketSort + p, s->rcounters + kRenErr);
         cur ^= 1;
     }
     *out_buf = cur;
@@ -385,15 +402,33 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
                            (uint64_t)kRenCounters + 2 * s->scan_parts + 2ull * n_tiles);
     }
     const uint32_t *n_dev = sel->counters + kSelNGaussians;
-    ProjectOut po{s->splat, s->depth, s->rect, s->tiles};
+    ProjectOut po{s->splat, s->depth, s->bin, s->rect, s->tiles, s->dkey[0], s->dval[0]};
     {
         Stage st(s, V3DG_STAGE_PROJECT);
         launch_project(s->stream, cam, s->planes, s->plane_stride, (int)s->sh_degree, sel->slot_row, sel->slot_inst,
                        n_dev, s->cap_slots, s->itab, po);
     }
+    const bool depth_first = s->sort_mode == V3DG_SORT_DEPTH_FIRST;
+    if (depth_first) {
+        // stable sort of the slots by FP32 depth bits (culled slots last), on
+        // the device-side slot count
+        {
+            Stage st(s, V3DG_STAGE_DEPTH_SORT);
+            launch_sort_hist_dev(s->stream, s->dkey[0], n_dev, s->cap_slots, 4, s->rcounters + kRenHistDepth);
+        }
+        int cur = 0;
+        for (int p = 0; p < 4; ++p) {
+            Stage st(s, V3DG_STAGE_DEPTH_SORT);
+            launch_sort_pass_dev(s->stream, s->dkey[cur], s->dval[cur], s->dkey[cur ^ 1], s->dval[cur ^ 1], n_dev,
+                                 s->cap_slots, p, s->rcounters + kRenHistDepth, s->sort_status, next_epoch(s),
+                                 s->rcounters + kRenTicketDepth + p, s->rcounters + kRenErr);
+            cur ^= 1;
+        }
+    }
     {
         Stage st(s, V3DG_STAGE_SCAN);
-        launch_scan_tiles(s->stream, s->tiles, n_dev, s->cap_slots, s->offsets, s->scan_status, s->rcounters);
+        launch_scan_tiles(s->stream, s->tiles, depth_first ? s->dval[0] : nullptr, n_dev, s->cap_slots, s->offsets,
+                          s->scan_status, s->rcounters);
     }
     // one wait per frame: slot and key counts decide the launch sizes below
     HIP_TRY(hipMemcpyAsync(s->pinned, s->rcounters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
@@ -408,18 +443,35 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     if ((err & kErrOverflow) || K >= 0xffffffffull)
         return fail(V3DG_ERR_CAPACITY, "frame needs %llu keys; the limit is 2^32-1", (unsigned long long)K);
     if ((rc = ensure_keys(s, K))) return rc;
-    {
-        Stage st(s, V3DG_STAGE_EMIT);
-        launch_emit(s->stream, N, s->tiles, s->offsets, s->rect, s->depth, cam.tiles_x, s->cap_keys, s->keys[0],
-                    s->vals[0]);
-    }
-    const uint32_t key_bits = 32 + std::max<uint32_t>(bits_for(n_tiles), 1);
+    const uint32_t tile_bits = std::max<uint32_t>(bits_for(n_tiles), 1);
     int buf = 0;
     uint32_t passes = 0;
-    if (K > 0) run_sort(s, K, key_bits, &buf, &passes);
-    {
-        Stage st(s, V3DG_STAGE_RANGES);
-        launch_tile_ranges(s->stream, s->keys[buf], K, s->ranges);
+    uint32_t key_bits;
+    if (depth_first) {
+        uint32_t *kb[2] = {reinterpret_cast<uint32_t *>(s->keys[0]), reinterpret_cast<uint32_t *>(s->keys[1])};
+        {
+            Stage st(s, V3DG_STAGE_EMIT);
+            launch_emit32(s->stream, N, s->dval[0], s->tiles, s->offsets, s->rect, s->bin, cam.tiles_x, s->cap_keys,
+                          kb[0], s->vals[0], s->rcounters + kRenErr);
+        }
+        key_bits = tile_bits;
+        if (K > 0) run_sort<uint32_t>(s, kb, s->vals, K, key_bits, &buf, &passes);
+        {
+            Stage st(s, V3DG_STAGE_RANGES);
+            launch_tile_ranges<uint32_t>(s->stream, kb[buf], K, 0, s->ranges);
+        }
+    } else {
+        {
+            Stage st(s, V3DG_STAGE_EMIT);
+            launch_emit64(s->stream, N, s->tiles, s->offsets, s->rect, s->bin, cam.tiles_x, s->cap_keys, s->keys[0],
+                          s->vals[0], s->rcounters + kRenErr);
+        }
+        key_bits = 32 + tile_bits;
+        if (K > 0) run_sort<uint64_t>(s, s->keys, s->vals, K, key_bits, &buf, &passes);
+        {
+            Stage st(s, V3DG_STAGE_RANGES);
+            launch_tile_ranges<uint64_t>(s->stream, s->keys[buf], K, 32, s->ranges);
+        }
     }
     {
         Stage st(s, V3DG_STAGE_BLEND);
@@ -434,10 +486,12 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     s->acc.tiles += n_tiles;
     s->acc.pixels += (uint64_t)cam.width * cam.height;
     s->acc.sort_passes += passes;
+    if (depth_first) s->acc.depth_sorts += 1;
     s->last.n_slots = N;
     s->last.n_keys = K;
     s->last.n_tiles = n_tiles;
     s->last.key_bits = key_bits;
+    s->last.sort_mode = (uint32_t)s->sort_mode;
     s->last.sort_passes = passes;
     s->last_buf = buf;
     return V3DG_OK;
@@ -495,7 +549,12 @@ void scene_release(v3dg_scene *s)
     dev_free(s->scale_dev);
     dev_free(s->itab);
     dev_free(s->splat);
+    dev_free(s->bin);
     dev_free(s->depth);
+    for (int b = 0; b < 2; ++b) {
+        dev_free(s->dkey[b]);
+        dev_free(s->dval[b]);
+    }
     dev_free(s->rect);
     dev_free(s->tiles);
     dev_free(s->offsets);
@@ -878,6 +937,10 @@ int v3dg_get_frame_stats(v3dg_scene *s, v3dg_frame_stats *out)
     if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
     HIP_TRY(hipSetDevice(s->device));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    uint32_t err = 0;
+    if (s->rcounters) HIP_TRY(hipMemcpy(&err, s->rcounters + kRenErr, sizeof(err), hipMemcpyDeviceToHost));
+    if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
+    if (err & kErrOverflow) return fail(V3DG_ERR_DEVICE, "tile counting and key emission disagreed");
     *out = s->last;
     return V3DG_OK;
 }
@@ -921,8 +984,29 @@ int v3dg_copy_sorted_keys(v3dg_scene *s, uint64_t *keys, uint32_t *vals, uint64_
     if (n_out) *n_out = n;
     if (n > cap) return fail(V3DG_ERR_CAPACITY, "%llu keys do not fit in %llu", (unsigned long long)n, (unsigned long long)cap);
     if (n == 0) return V3DG_OK;
-    if (keys) HIP_TRY(hipMemcpy(keys, s->keys[s->last_buf], n * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    if (vals) HIP_TRY(hipMemcpy(vals, s->vals[s->last_buf], n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    std::vector<uint32_t> v(n);
+    HIP_TRY(hipMemcpy(v.data(), s->vals[s->last_buf], n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (keys) {
+        if (s->last.sort_mode == V3DG_SORT_KEYS64) {
+            HIP_TRY(hipMemcpy(keys, s->keys[s->last_buf], n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        } else {  // tile ids; the depth bits come from the slot
+            std::vector<uint32_t> tk(n), dp(s->last.n_slots);
+            HIP_TRY(hipMemcpy(tk.data(), s->keys[s->last_buf], n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(dp.data(), s->depth, dp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            for (uint64_t i = 0; i < n; ++i) keys[i] = ((uint64_t)tk[i] << 32) | dp[v[i]];
+        }
+    }
+    if (vals) std::memcpy(vals, v.data(), n * sizeof(uint32_t));
+    return V3DG_OK;
+}
+
+int v3dg_set_sort_mode(v3dg_scene *s, int mode)
+{
+    g_err.clear();
+    if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
+    if (mode != V3DG_SORT_DEPTH_FIRST && mode != V3DG_SORT_KEYS64)
+        return fail(V3DG_ERR_INVALID_ARG, "unknown sort mode %d", mode);
+    s->sort_mode = mode;
     return V3DG_OK;
 }
 
@@ -983,13 +1067,13 @@ int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t
     if (!rc) {
         launch_fill_u32(st, reinterpret_cast<uint32_t *>(status), 2 * parts * kRadix, 0u);
         launch_fill_u32(st, ctr, kRenCounters, 0u);
-        launch_sort_hist(st, keys_dev, n, passes, ctr + kRenHist);
+        launch_sort_hist<uint64_t>(st, keys_dev, n, passes, ctr + kRenHist);
         uint64_t *kb[2] = {keys_dev, k2};
         uint32_t *vb[2] = {vals_dev, v2};
         int cur = 0;
         for (int p = 0; p < passes; ++p) {
-            launch_sort_pass(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, p, ctr + kRenHist, status,
-                             (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr);
+            launch_sort_pass<uint64_t>(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, p, ctr + kRenHist, status,
+                                       (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr);
             cur ^= 1;
         }
         if (cur == 1) {

@@ -1,16 +1,22 @@
-// (d) binning of splats to 16x16 tiles and the stable radix sort of the
-// 64-bit (tile << 32 | depth bits) keys, plus the per-tile key ranges.
+// (d) binning of splats to 16x16 tiles and the stable radix sorts that order
+// every tile's splats front to back.
 //
-//   scan_tiles   exclusive scan of tiles-touched over the slot stream
-//                (single pass, decoupled look-back over ticketed partitions)
-//   emit         one key per (slot, tile of its rectangle), row-major tiles
-//   sort_hist    digit histograms of every 8-bit pass in one read of the keys
+// Two orderings give the same (tile, depth, slot) order:
+//   depth-first (default): the slots are radix-sorted by their FP32 depth
+//     bits (stable, so equal depths keep slot order); tiles-touched is scanned
+//     in that order; one 32-bit tile id is emitted per (slot, tile); a stable
+//     radix sort by tile id then leaves each tile's splats in depth order.
+//   64-bit keys: one (tile << 32 | depth bits) key per (slot, tile), emitted in
+//     slot order and radix-sorted on all significant bits.
+// The depth is a positive FP32 (z > near > 0), so its bit pattern orders like
+// its value.
+//
+//   scan_tiles   exclusive scan of tiles-touched (decoupled look-back)
+//   emit32/64    keys of every (slot, tile) the support reaches
+//   sort_hist    digit histograms of all passes in one read of the keys
 //   sort_pass    one onesweep pass: wavefront ballot ranking into LDS, per-digit
 //                decoupled look-back across partitions, coalesced scatter
 //   tile_ranges  [start, end) of each tile in the sorted keys
-//
-// The depth is a positive FP32 (z > near > 0), so its bit pattern orders like
-// its value; the stable LSD sort keeps equal (tile, depth) keys in slot order.
 #include "v3dg_internal.h"
 
 namespace v3dg {
@@ -57,10 +63,24 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
     return off + incl - v;
 }
 
+// lanes of the wavefront holding the same 8-bit digit (among valid lanes)
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+    }
+    return peers;
+}
+
 // ---------------------------------------------------------------------------
 // scan of tiles-touched
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t *__restrict__ tiles,
+                                                                  const uint32_t *__restrict__ order,
                                                                   const uint32_t *__restrict__ n_dev,
                                                                   uint32_t *__restrict__ offsets,
                                                                   uint64_t *__restrict__ status, uint32_t *counters)
@@ -78,7 +98,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
     if (p >= nparts) return;
     const uint64_t base = (uint64_t)p * kScanPart + (uint64_t)tid * kScanItems;
     uint32_t v[kScanItems];
-    if (base + kScanItems <= n) {
+    if (order) {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) v[j] = (base + j < n) ? tiles[order[base + j]] : 0u;
+    } else if (base + kScanItems <= n) {
         const uint4 *src = reinterpret_cast<const uint4 *>(tiles + base);
 #pragma unroll
         for (int j = 0; j < kScanItems / 4; ++j) {
@@ -149,7 +172,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
     __syncthreads();
     const uint64_t b = s_prefix + t_excl;
     if ((b + tsum) >> 32) atomicOr(&counters[kRenErr], kErrOverflow);
-    if (base + kScanItems <= n) {
+    if (!order && base + kScanItems <= n) {
         uint4 *dst = reinterpret_cast<uint4 *>(offsets + base);
 #pragma unroll
         for (int j = 0; j < kScanItems / 4; ++j)
@@ -162,78 +185,129 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
     }
 }
 
-void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *n_dev, uint64_t max_n,
-                       uint32_t *offsets, uint64_t *status, uint32_t *counters)
+void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
+                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters)
 {
     uint64_t blocks = (max_n + kScanPart - 1) / kScanPart;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)blocks), dim3(kScanThreads), 0, st, tiles, n_dev, offsets,
-                       status, counters);
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)blocks), dim3(kScanThreads), 0, st, tiles, order, n_dev,
+                       offsets, status, counters);
 }
 
 // ---------------------------------------------------------------------------
-// key emission
+// key emission: one key per tile of every row span of the support
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) emit_kernel(uint32_t n, const uint32_t *__restrict__ tiles,
+template <bool DEPTH_FIRST>
+__global__ void __launch_bounds__(256) emit_kernel(uint32_t n, const uint32_t *__restrict__ order,
+                                                   const uint32_t *__restrict__ tiles,
                                                    const uint32_t *__restrict__ offsets,
-                                                   const uint2 *__restrict__ rect, const float *__restrict__ depth,
-                                                   uint32_t tiles_x, uint64_t key_cap, uint64_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ vals)
+                                                   const uint2 *__restrict__ rect, const BinRec *__restrict__ bin,
+                                                   uint32_t tiles_x, uint64_t key_cap, void *__restrict__ keys_v,
+                                                   uint32_t *__restrict__ vals, uint32_t *err)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const uint32_t t = DEPTH_FIRST ? order[j] : j;
         const uint32_t nt = tiles[t];
         if (nt == 0) continue;
-        uint64_t off = offsets[t];
-        if (off + nt > key_cap) continue;
+        uint64_t off = offsets[j];
+        if (off + nt > key_cap) {
+            atomicOr(err, kErrOverflow);
+            continue;
+        }
+        const uint64_t end = off + nt;
         const uint2 rc = rect[t];
         const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
-        const uint64_t d = __float_as_uint(depth[t]);
+        const BinRec b = bin[t];
+        const uint64_t dbits = __float_as_uint(b.depth);
         for (uint32_t ty = ty0; ty <= ty1; ++ty) {
-            for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-                keys[off] = ((uint64_t)(ty * tiles_x + tx) << 32) | d;
+            uint32_t lo, hi;
+            if (!tile_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
+            for (uint32_t tx = lo; tx <= hi && off < end; ++tx) {
+                const uint32_t tile = ty * tiles_x + tx;
+                if (DEPTH_FIRST)
+                    reinterpret_cast<uint32_t *>(keys_v)[off] = tile;
+                else
+                    reinterpret_cast<uint64_t *>(keys_v)[off] = ((uint64_t)tile << 32) | dbits;
                 vals[off] = t;
                 ++off;
             }
         }
+        if (off != end) atomicOr(err, kErrOverflow);  // counting and emission disagree
     }
 }
 
-void launch_emit(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
-                 const float *depth, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals)
+void launch_emit64(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
+                   const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals,
+                   uint32_t *err)
 {
     if (n == 0) return;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(emit_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, n, tiles, offsets, rect, depth, tiles_x,
-                       key_cap, keys, vals);
+    hipLaunchKernelGGL(emit_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, st, n, (const uint32_t *)nullptr,
+                       tiles, offsets, rect, bin, tiles_x, key_cap, (void *)keys, vals, err);
+}
+
+void launch_emit32(hipStream_t st, uint32_t n, const uint32_t *order, const uint32_t *tiles, const uint32_t *offsets,
+                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint32_t *keys,
+                   uint32_t *vals, uint32_t *err)
+{
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(emit_kernel<true>, dim3((uint32_t)blocks), dim3(256), 0, st, n, order, tiles, offsets, rect,
+                       bin, tiles_x, key_cap, (void *)keys, vals, err);
 }
 
 // ---------------------------------------------------------------------------
-// digit histograms for all passes
+// digit histograms for all passes (one read of the keys).  Lanes holding the
+// same digit are matched by ballot and counted by one LDS atomic.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t *__restrict__ keys, uint64_t n, int passes,
-                                                        uint32_t *__restrict__ hist)
+template <typename K>
+__global__ void __launch_bounds__(256) sort_hist_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
+                                                        uint64_t n_host, int passes, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t s_h[8 * kRadix];
     for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x) s_h[i] = 0;
     __syncthreads();
+    const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lt = (1ull << lane) - 1ull;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * kRadix + ((k >> (p * kRadixBits)) & (kRadix - 1))], 1u);
+    // whole wavefronts iterate together so that ballots see every lane
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
+        const uint64_t i = base + lane;
+        const bool valid = i < n;
+        const K k = valid ? keys[i] : (K)0;
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (uint32_t)(k >> (p * kRadixBits)) & (kRadix - 1);
+            const uint64_t peers = match_digit(d, valid);
+            if (valid && (peers & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
-void launch_sort_hist(hipStream_t st, const uint64_t *keys, uint64_t n, int passes, uint32_t *hist)
+template <typename K>
+void launch_sort_hist(hipStream_t st, const K *keys, uint64_t n, int passes, uint32_t *hist)
 {
     if (n == 0) return;
-    uint64_t blocks = (n + 256 * 32 - 1) / (256 * 32);
+    uint64_t blocks = (n + 256 * 16 - 1) / (256 * 16);
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(sort_hist_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, keys, n, passes, hist);
+    hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, (const uint32_t *)nullptr,
+                       n, passes, hist);
+}
+
+void launch_sort_hist_dev(hipStream_t st, const uint32_t *keys, const uint32_t *n_dev, uint64_t max_n, int passes,
+                          uint32_t *hist)
+{
+    uint64_t blocks = (max_n + 256 * 16 - 1) / (256 * 16);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(sort_hist_kernel<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, n_dev, max_n,
+                       passes, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,10 +319,12 @@ __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint3
     return ((uint64_t)epoch << 34) | (flag << 32) | v;
 }
 
-__global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t *__restrict__ keys_in,
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__restrict__ keys_in,
                                                                  const uint32_t *__restrict__ vals_in,
-                                                                 uint64_t *__restrict__ keys_out,
-                                                                 uint32_t *__restrict__ vals_out, uint32_t n,
+                                                                 K *__restrict__ keys_out,
+                                                                 uint32_t *__restrict__ vals_out,
+                                                                 const uint32_t *__restrict__ n_dev, uint32_t n_host,
                                                                  int shift, const uint32_t *__restrict__ hist,
                                                                  uint64_t *status, uint32_t epoch, uint32_t *ticket,
                                                                  uint32_t *err)
@@ -256,7 +332,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t 
     constexpr int NW = kSortThreads / kWave;           // waves per block
     constexpr int WAVE_KEYS = kSortPart / NW;          // consecutive keys owned by a wave
     constexpr int ROUNDS = WAVE_KEYS / kWave;          // = kSortItems
-    __shared__ uint64_t s_keys[kSortPart];
+    __shared__ K s_keys[kSortPart];
     __shared__ uint32_t s_vals[kSortPart];
     __shared__ uint32_t s_whist[NW][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
@@ -265,6 +341,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t 
     __shared__ uint32_t s_ticket;
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t n = n_dev ? *n_dev : n_host;
     for (int i = tid; i < NW * kRadix; i += kSortThreads) (&s_whist[0][0])[i] = 0u;
     if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -275,24 +352,18 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t 
     const uint32_t wave_base = part_base + (uint32_t)wid * WAVE_KEYS;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    uint64_t key[ROUNDS];
+    K key[ROUNDS];
     uint32_t val[ROUNDS];
     uint32_t dr[ROUNDS];  // digit | rank-in-wave << 8
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t idx = wave_base + r * kWave + lane;
         const bool valid = idx < n;
-        const uint64_t k = valid ? keys_in[idx] : 0ull;
+        const K k = valid ? keys_in[idx] : (K)0;
         key[r] = k;
         val[r] = valid ? vals_in[idx] : 0u;
         const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
+        const uint64_t peers = match_digit(d, valid);
         const uint32_t rank_in_round = (uint32_t)__popcll(peers & lt_mask);
         const uint32_t cnt = (uint32_t)__popcll(peers);
         uint32_t old = 0;
@@ -302,15 +373,14 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t 
     }
     __syncthreads();
 
-    // per-digit totals, wave offsets, look-back
-    const int d = tid;  // kSortThreads == kRadix
-    uint32_t c[NW];
+    // per-digit totals, wave offsets, look-back (thread d handles digit d)
+    const int d = tid;
     uint32_t total = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        c[w] = s_whist[w][d];
+        const uint32_t c = s_whist[w][d];
         s_whist[w][d] = total;
-        total += c[w];
+        total += c;
     }
     uint64_t *my = status + (uint64_t)p * kRadix + d;
     uint32_t prefix = 0;
@@ -363,7 +433,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t 
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t i = tid + r * kSortThreads;
         if (i < n_here) {
-            const uint64_t k = s_keys[i];
+            const K k = s_keys[i];
             const uint32_t dd = (uint32_t)(k >> shift) & (kRadix - 1);
             const uint32_t o = s_gbase[dd] + (i - s_lstart[dd]);
             if (o < n) {  // always true when the histogram and look-back agree
@@ -374,36 +444,60 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const uint64_t 
     }
 }
 
-void launch_sort_pass(hipStream_t st, const uint64_t *keys_in, const uint32_t *vals_in, uint64_t *keys_out,
-                      uint32_t *vals_out, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
-                      uint32_t epoch, uint32_t *ticket, uint32_t *err)
+template <typename K>
+void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
+                      uint64_t n, int pass, const uint32_t *hist, uint64_t *status, uint32_t epoch, uint32_t *ticket,
+                      uint32_t *err)
 {
     if (n == 0) return;
     const uint32_t nparts = (uint32_t)((n + kSortPart - 1) / kSortPart);
-    hipLaunchKernelGGL(sort_pass_kernel, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
-                       vals_out, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix, status, epoch, ticket, err);
+    hipLaunchKernelGGL(sort_pass_kernel<K>, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
+                       vals_out, (const uint32_t *)nullptr, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
+                       status, epoch, ticket, err);
+}
+
+void launch_sort_pass_dev(hipStream_t st, const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                          uint32_t *vals_out, const uint32_t *n_dev, uint64_t max_n, int pass, const uint32_t *hist,
+                          uint64_t *status, uint32_t epoch, uint32_t *ticket, uint32_t *err)
+{
+    uint32_t nparts = (uint32_t)((max_n + kSortPart - 1) / kSortPart);
+    if (nparts < 1) nparts = 1;
+    hipLaunchKernelGGL(sort_pass_kernel<uint32_t>, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
+                       vals_out, n_dev, 0u, pass * kRadixBits, hist + pass * kRadix, status, epoch, ticket, err);
 }
 
 // ---------------------------------------------------------------------------
 // tile ranges
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint64_t *__restrict__ keys, uint32_t n,
+template <typename K>
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, uint32_t n, int shift,
                                                           uint2 *__restrict__ ranges)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t t = (uint32_t)(keys[i] >> 32);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = i;
-        if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = i + 1;
+        const uint32_t t = (uint32_t)(keys[i] >> shift);
+        if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[t].x = i;
+        if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[t].y = i + 1;
     }
 }
 
-void launch_tile_ranges(hipStream_t st, const uint64_t *keys, uint64_t n, uint2 *ranges)
+template <typename K>
+void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint2 *ranges)
 {
     if (n == 0) return;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tile_ranges_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, keys, (uint32_t)n, ranges);
+    hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, (uint32_t)n, shift,
+                       ranges);
 }
+
+template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint32_t *);
+template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, uint64_t, int, uint32_t *);
+template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
+                                         uint64_t, int, const uint32_t *, uint64_t *, uint32_t, uint32_t *, uint32_t *);
+template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
+                                         uint64_t, int, const uint32_t *, uint64_t *, uint32_t, uint32_t *, uint32_t *);
+template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint2 *);
+template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, uint64_t, int, uint2 *);
 
 }  // namespace v3dg

@@ -55,14 +55,59 @@ enum RenderCounter : int {
     kRenKeysLo = 2,       // total keys (64-bit, lo/hi)
     kRenKeysHi = 3,
     kRenVisible = 4,      // slots with at least one tile
-    kRenTicketSort = 8,   // 8 passes
-    kRenHist = 16,        // 8 passes x 256 bins
-    kRenCounters = 16 + 8 * 256
+    kRenTicketSort = 8,   // 8 passes of the tile (or 64-bit) sort
+    kRenTicketDepth = 16, // 4 passes of the depth sort
+    kRenHist = 32,        // 8 passes x 256 bins
+    kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
+    kRenCounters = 32 + 12 * 256
 };
 
 // Error flag bits
 constexpr uint32_t kErrSpin = 1u;       // a bounded look-back wait expired
 constexpr uint32_t kErrOverflow = 2u;   // a count did not fit its field
+
+// ---- conservative tile coverage of a splat's support -----------------------
+// The support of a splat is {d : d^T Sigma^-1 d <= Q}, Q = 2 ln(255 o), the
+// pixels where alpha >= 1/255.  Binning keeps, for every tile row, only the
+// tiles that an enlarged support (Qm = 1.05 Q + 0.05, one extra pixel on each
+// side) reaches, computed from Sigma = [[sa, sb], [sb, sc]] and its determinant.
+// Given dy, the support is an x-interval centred on (sb/sc) dy with half-width
+// sqrt((Qm - dy^2/sc) det/sc); its right end is concave in dy and peaks at the
+// rightmost point dy_r = sb sqrt(Qm/sa), its left end is convex with minimum at
+// -dy_r, so the extreme x over a band of rows is found by clamping dy_r.
+// The same function, compiled without contraction, is used to count the
+// tiles (projection) and to write them (emission), so both agree bit for bit.
+struct BinRec {            // per visible slot, 32 B
+    float mx, my, sa, sb;  // mean, Sigma entries
+    float sc, det, Qm, depth;
+};
+
+__device__ __forceinline__ bool tile_row_span(const BinRec &b, uint32_t ty, uint32_t tx_min, uint32_t tx_max,
+                                              uint32_t *tx_lo, uint32_t *tx_hi)
+{
+#pragma clang fp contract(off)
+    const float ya = (float)(ty * 16u) + 0.5f, yb = ya + 15.0f;
+    const float ymax = sqrtf(b.Qm * b.sc);
+    const float lo = fmaxf(ya - 1.0f - b.my, -ymax);
+    const float hi = fminf(yb + 1.0f - b.my, ymax);
+    if (!(lo <= hi)) return false;
+    const float k = b.sb / b.sc;
+    const float s2 = b.det / b.sc;
+    const float dyr = b.sb * sqrtf(b.Qm / b.sa);
+    const float dr = fminf(fmaxf(dyr, lo), hi);
+    const float dl = fminf(fmaxf(-dyr, lo), hi);
+    const float wr = sqrtf(fmaxf(0.0f, (b.Qm - dr * dr / b.sc) * s2));
+    const float wl = sqrtf(fmaxf(0.0f, (b.Qm - dl * dl / b.sc) * s2));
+    const float xr = b.mx + k * dr + wr + 1.0f;
+    const float xl = b.mx + k * dl - wl - 1.0f;
+    // tile tx holds pixel centres 16 tx + 0.5 .. 16 tx + 15.5
+    const float flo = ceilf((xl - 15.5f) * 0.0625f), fhi = floorf((xr - 0.5f) * 0.0625f);
+    const float clo = fmaxf(flo, (float)tx_min), chi = fminf(fhi, (float)tx_max);
+    if (!(clo <= chi)) return false;
+    *tx_lo = (uint32_t)clo;
+    *tx_hi = (uint32_t)chi;
+    return true;
+}
 
 // ---- launch wrappers (implemented in the .hip files) ----------------------
 void launch_frame_setup(hipStream_t st, const CamArgs &cam, const double *T, const float *inst_scale,
@@ -81,10 +126,13 @@ void launch_expand(hipStream_t st, const uint32_t *gid, const uint32_t *slot_off
 
 // project.hip
 struct ProjectOut {
-    float4 *splat;      // 3 float4 per slot: (mx,my,A,B) (C,o,r,g) (b,depth,0,0)
-    float *depth;
+    float4 *splat;      // 3 float4 per slot: (mx,my,A,B) (C,o,r,g) (b,depth,hx,hy)
+    float *depth;       // FP32 depth of every slot
+    BinRec *bin;        // binning record of visible slots
     uint2 *rect;        // (tx0 | tx1<<16, ty0 | ty1<<16)
-    uint32_t *tiles;
+    uint32_t *tiles;    // tiles the support reaches (0 = culled)
+    uint32_t *dkey;     // depth sort key: FP32 depth bits, 0xffffffff when culled
+    uint32_t *dval;     // slot index (sort payload)
 };
 void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uint64_t plane_stride, int sh_degree,
                     const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
@@ -94,21 +142,37 @@ void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uin
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanPart = kScanThreads * kScanItems;
-void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *n_dev, uint64_t max_n,
-                       uint32_t *offsets, uint64_t *status, uint32_t *counters);
-void launch_emit(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
-                 const float *depth, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals);
+// exclusive scan of tiles[order[j]] (order may be NULL: identity)
+void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
+                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters);
+// 64-bit keys (tile << 32 | depth bits), slot order
+void launch_emit64(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
+                   const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals,
+                   uint32_t *err);
+// 32-bit tile keys in depth order (order[j] = slot of depth rank j)
+void launch_emit32(hipStream_t st, uint32_t n, const uint32_t *order, const uint32_t *tiles, const uint32_t *offsets,
+                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint32_t *keys,
+                   uint32_t *vals, uint32_t *err);
+// device-side count variants used by the depth sort (grid sized for max_n)
+void launch_sort_hist_dev(hipStream_t st, const uint32_t *keys, const uint32_t *n_dev, uint64_t max_n, int passes,
+                          uint32_t *hist);
+void launch_sort_pass_dev(hipStream_t st, const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                          uint32_t *vals_out, const uint32_t *n_dev, uint64_t max_n, int pass, const uint32_t *hist,
+                          uint64_t *status, uint32_t epoch, uint32_t *ticket, uint32_t *err);
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
 constexpr int kSortPart = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 256;
-void launch_sort_hist(hipStream_t st, const uint64_t *keys, uint64_t n, int passes, uint32_t *hist);
-void launch_sort_pass(hipStream_t st, const uint64_t *keys_in, const uint32_t *vals_in, uint64_t *keys_out,
-                      uint32_t *vals_out, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
-                      uint32_t epoch, uint32_t *ticket, uint32_t *err);
-void launch_tile_ranges(hipStream_t st, const uint64_t *keys, uint64_t n, uint2 *ranges);
+template <typename K>
+void launch_sort_hist(hipStream_t st, const K *keys, uint64_t n, int passes, uint32_t *hist);
+template <typename K>
+void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
+                      uint64_t n, int pass, const uint32_t *hist, uint64_t *status, uint32_t epoch,
+                      uint32_t *ticket, uint32_t *err);
+template <typename K>
+void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint2 *ranges);
 
 // blend.hip
 void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals,

@@ -188,6 +188,54 @@ def test_frame_keys_sorted_stable_and_complete(c1, torch):
     assert np.unique(tk).size == tk.size
 
 
+def test_sort_modes_identical(c1, torch):
+    """Depth-first binning and 64-bit keys give the same order and image."""
+    a, sc = c1
+    for cam, tau in [(sg.single_camera_c1(), 1.0), (sg.look_at((0.6, 0.5, 0.4), (0, 0, 0), 333, 250, 1.2), 30.0)]:
+        sel = sc.select(cam, tau)
+        sc.set_sort_mode(v.V3DG_SORT_KEYS64)
+        i64 = sc.render(cam, sel).clone()
+        k64, v64 = sc.sorted_keys()
+        st64 = sc.frame_stats()
+        sc.set_sort_mode(v.V3DG_SORT_DEPTH_FIRST)
+        idf = sc.render(cam, sel).clone()
+        kdf, vdf = sc.sorted_keys()
+        stdf = sc.frame_stats()
+        torch.cuda.synchronize()
+        assert st64["sort_mode"] == 1 and stdf["sort_mode"] == 0
+        assert np.array_equal(k64, kdf) and np.array_equal(v64, vdf)
+        assert torch.equal(i64, idf)
+
+
+def test_tile_coverage_is_conservative(c1, torch):
+    """Every pixel where a kept splat reaches alpha >= 1/255 lies in a tile it was binned to."""
+    a, sc = c1
+    cam = sg.look_at((0.9, -0.7, 0.6), (0, 0, 0), 320, 200, 1.1)
+    sel = sc.select(cam, 1.0)
+    sc.render(cam, sel)
+    keys, vals = sc.sorted_keys()
+    pr = sc.projection()
+    tiles_x = (cam.width + 15) // 16
+    binned = {}
+    for k, t in zip((keys >> np.uint64(32)).astype(np.int64), vals.astype(np.int64)):
+        binned.setdefault(t, set()).add(int(k))
+    vis = np.flatnonzero(pr["tiles"] > 0)
+    rng = np.random.default_rng(1)
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    for t in rng.choice(vis, size=min(1500, vis.size), replace=False):
+        mx, my = pr["mean2"][t]
+        A, B, Cc = pr["conic"][t].astype(np.float64)
+        o = float(pr["opacity"][t])
+        dx = mx - (xs + 0.5)
+        dy = my - (ys + 0.5)
+        power = np.minimum(0.0, -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy)
+        alpha = np.minimum(0.99, o * np.exp(power))
+        hit = alpha >= (1.0 / 255.0) * (1 - 1e-4)
+        need = set(((ys[hit] // 16) * tiles_x + xs[hit] // 16).tolist())
+        assert need <= binned.get(int(t), set()), int(t)
+        assert len(binned[int(t)]) == int(pr["tiles"][t])
+
+
 # ------------------------------------------------------------------------------
 # images
 # ------------------------------------------------------------------------------
