@@ -1,12 +1,10 @@
 // (e) front-to-back alpha compositing (paper Sec. 2.1: the splats covering a
 // pixel are blended in depth order), one 256-thread workgroup per 16x16 tile.
 //
-// Each wavefront owns one 8x8 quarter of the tile, one pixel per lane.  The
+// Each wavefront owns one 8x8 quarter of the tile, one pixel per lane.  A
 // tile's depth-sorted splats are staged through LDS in batches of 256 (one
-// gather per splat per tile); every wavefront then compacts, in order, the
-// batch entries whose enlarged support box reaches its quarter and walks only
-// those.  A wavefront whose 64 pixels are saturated stops evaluating; the
-// workgroup stops once all four are.
+// gather per splat per tile); every wavefront compacts, in order, the batch
+// entries whose enlarged support box reaches its quarter and walks only those.
 //
 // Per (pixel, splat), with d = mean - pixel centre and conic (A, B, C):
 //   power = min(0, -1/2 (A dx^2 + C dy^2) - B dx dy),  alpha = min(0.99, o e^power);
@@ -16,6 +14,21 @@
 // 1/255 test is taken on it before the exponential: alpha < 1/255 exactly when
 // p < -log2(255 o) with p = log2(e) power.
 // Output RGBA: C + T bg, 1 - T.
+//
+// Long lists.  A few tiles of a near view hold tens of thousands of splats and
+// would keep one workgroup busy long after the rest of the frame is done.  A
+// list longer than kChunk keys is cut into chunks of kChunk:
+//   blend_kernel  walks chunk 0 of every tile (with the stop rule);
+//   chunk_kernel  walks every other chunk in parallel, each from T = 1,
+//                 giving per pixel the chunk's colour C_c and transmittance T_c;
+//   fold_kernel   folds the chunks in order, C += T C_c, T *= T_c.  Running
+//                 transmittance only decreases, so the stopping splat lies in
+//                 the first chunk with T T_c < 1e-4 (or that stopped on its own
+//                 from T = 1); pixels without one are finished here;
+//   rewalk_kernel walks each such chunk again, in parallel over (tile, chunk),
+//                 from the folded (T, C) with the stop rule; later chunks are
+//                 ignored.
+// This is the sequential result up to the association of the FP32 products.
 #include "v3dg_internal.h"
 
 namespace v3dg {
@@ -23,46 +36,39 @@ namespace v3dg {
 constexpr int kBlendThreads = kTile * kTile;
 constexpr float kLog2e = 1.4426950408889634f;
 
-__global__ void __launch_bounds__(kBlendThreads) blend_kernel(CamArgs cam, const float4 *__restrict__ splat,
-                                                              const uint32_t *__restrict__ vals,
-                                                              const uint2 *__restrict__ ranges,
-                                                              float4 *__restrict__ image, uint32_t per_xcd,
-                                                              unsigned long long *__restrict__ pairs)
+struct BlendShared {
+    float4 P0[kBlendThreads];  // (mx, my, a, b): p = a dx^2 + b dx dy + c dy^2
+    float4 P1[kBlendThreads];  // (c, log2 threshold, log2 o, -)
+    float4 P2[kBlendThreads];  // (r, g, b, -)
+    uint8_t mask[kBlendThreads];
+    uint8_t idx[4][kBlendThreads];
+};
+
+struct Pix {
+    float T, cr, cg, cb;
+    bool active;          // still compositing
+    uint32_t evaluated;   // (pixel, splat) pairs walked
+};
+
+// Composite keys [b, e) of the tile into the lanes' pixels (every thread of
+// the workgroup calls this with the same range).
+__device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ splat,
+                            const uint32_t *__restrict__ vals, float bx0, float by0, float pxc, float pyc, int wid,
+                            int lane, BlendShared &sh, Pix &px)
 {
-    __shared__ float4 sP0[kBlendThreads];   // (mx, my, a, b): p = a dx^2 + b dx dy + c dy^2
-    __shared__ float4 sP1[kBlendThreads];   // (c, log2 threshold, log2 o, -)
-    __shared__ float4 sP2[kBlendThreads];   // (r, g, b, -)
-    __shared__ uint8_t sMask[kBlendThreads];
-    __shared__ uint8_t sIdx[4][kBlendThreads];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    // workgroups are dealt round-robin to the 8 XCDs: give each XCD a
-    // contiguous band of tiles so neighbouring tiles share its L2
-    const uint32_t tile = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
-    const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
-    if (tile >= n_tiles) return;
-    const uint32_t tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const uint32_t qx = (uint32_t)wid & 1u, qy = (uint32_t)wid >> 1;
-    const uint32_t x = tx * kTile + qx * 8u + ((uint32_t)lane & 7u), y = ty * kTile + qy * 8u + ((uint32_t)lane >> 3);
-    const bool inside = x < cam.width && y < cam.height;
-    const float pxc = (float)x + 0.5f, pyc = (float)y + 0.5f;
-    // pixel-centre boxes of the four quarters
-    const float bx0 = (float)(tx * kTile) + 0.5f, by0 = (float)(ty * kTile) + 0.5f;
-    const uint2 rg = ranges[tile];
-    float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f;
-    bool done = !inside;
-    uint32_t evaluated = 0;
+    const int tid = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint32_t start = rg.x; start < rg.y; start += kBlendThreads) {
-        if (__syncthreads_count(done) == kBlendThreads) break;
+    for (uint32_t start = b; start < e; start += kBlendThreads) {
+        if (__syncthreads_count(px.active) == 0) break;
         const uint32_t i = start + tid;
         uint32_t m = 0;
-        if (i < rg.y) {
+        if (i < e) {
             const float4 *sp = splat + 3 * (uint64_t)vals[i];
             const float4 f0 = sp[0], f1 = sp[1], f2 = sp[2];
             const float lo = __log2f(f1.y);
-            sP0[tid] = make_float4(f0.x, f0.y, -0.5f * kLog2e * f0.z, -kLog2e * f0.w);
-            sP1[tid] = make_float4(-0.5f * kLog2e * f1.x, -(__log2f(255.0f) + lo), lo, 0.f);
-            sP2[tid] = make_float4(f1.z, f1.w, f2.x, 0.f);
+            sh.P0[tid] = make_float4(f0.x, f0.y, -0.5f * kLog2e * f0.z, -kLog2e * f0.w);
+            sh.P1[tid] = make_float4(-0.5f * kLog2e * f1.x, -(__log2f(255.0f) + lo), lo, 0.f);
+            sh.P2[tid] = make_float4(f1.z, f1.w, f2.x, 0.f);
             const float hx = f2.z + 1.0f, hy = f2.w + 1.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -72,42 +78,44 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(CamArgs cam, const
                 m |= (uint32_t)hit << q;
             }
         }
-        sMask[tid] = (uint8_t)m;
+        sh.mask[tid] = (uint8_t)m;
         __syncthreads();
         // in-order compaction of this quarter's entries
         uint32_t cnt = 0;
 #pragma unroll
         for (int c = 0; c < kBlendThreads / kWave; ++c) {
-            const bool hit = (sMask[c * kWave + lane] >> wid) & 1u;
+            const bool hit = (sh.mask[c * kWave + lane] >> wid) & 1u;
             const uint64_t bal = __ballot(hit);
-            if (hit) sIdx[wid][cnt + (uint32_t)__popcll(bal & lt)] = (uint8_t)(c * kWave + lane);
+            if (hit) sh.idx[wid][cnt + (uint32_t)__popcll(bal & lt)] = (uint8_t)(c * kWave + lane);
             cnt += (uint32_t)__popcll(bal);
         }
         __syncthreads();
-        if (__ballot(!done)) {
+        if (__ballot(px.active)) {
             // the walk is uniform across the wavefront: entry j is the same for
             // every lane; lanes differ only in whether they take the splat
-            bool active = !done;
-            uint32_t kend = cnt;  // entries this lane evaluated in this batch
+            const bool was = px.active;
+            uint32_t kend = cnt;
+            float T = px.T, cr = px.cr, cg = px.cg, cb = px.cb;
+            bool active = px.active;
             for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t j = sIdx[wid][k];
-                const float4 a = sP0[j];
-                const float4 b = sP1[j];
+                const uint32_t j = sh.idx[wid][k];
+                const float4 a = sh.P0[j];
+                const float4 c4 = sh.P1[j];
                 const float dx = a.x - pxc, dy = a.y - pyc;
-                const float p = fmaf(a.z * dx, dx, fmaf(a.w * dx, dy, b.x * dy * dy));
-                const bool take = active && !(p < b.y);  // alpha >= 1/255
+                const float p = fmaf(a.z * dx, dx, fmaf(a.w * dx, dy, c4.x * dy * dy));
+                const bool take = active && !(p < c4.y);  // alpha >= 1/255
                 if (__ballot(take) == 0) continue;
                 // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
-                const float e = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + b.z);
-                const float alpha = take ? fminf(0.99f, e) : 0.0f;
+                const float ex = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + c4.z);
+                const float alpha = take ? fminf(0.99f, ex) : 0.0f;
                 const float Tn = T * (1.0f - alpha);
                 const bool stop = take && Tn < 1e-4f;
                 const bool add = take && !stop;
-                const float4 c = sP2[j];
+                const float4 col = sh.P2[j];
                 const float w = add ? alpha * T : 0.0f;
-                cr = fmaf(w, c.x, cr);
-                cg = fmaf(w, c.y, cg);
-                cb = fmaf(w, c.z, cb);
+                cr = fmaf(w, col.x, cr);
+                cg = fmaf(w, col.y, cg);
+                cb = fmaf(w, col.z, cb);
                 T = add ? Tn : T;
                 if (stop) {
                     active = false;
@@ -115,27 +123,292 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(CamArgs cam, const
                 }
                 if (__ballot(active) == 0) break;
             }
-            if (!done) evaluated += kend;
-            done = !active;
+            if (was) px.evaluated += kend;
+            px.T = T;
+            px.cr = cr;
+            px.cg = cg;
+            px.cb = cb;
+            px.active = active;
         }
     }
-    if (inside)
-        image[(uint64_t)y * cam.width + x] =
-            make_float4(cr + T * cam.bg[0], cg + T * cam.bg[1], cb + T * cam.bg[2], 1.0f - T);
-    // pairs evaluated by this wavefront, one atomic per wavefront
-    uint32_t wsum = evaluated;
+}
+
+__device__ __forceinline__ void count_pairs(const Pix &px, int lane, unsigned long long *pairs)
+{
+    uint32_t wsum = px.evaluated;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, kWave);
-    if (lane == 0) atomicAdd(pairs, (unsigned long long)wsum);
+    if (lane == 0 && wsum) atomicAdd(pairs, (unsigned long long)wsum);
+}
+
+struct TileGeo {
+    uint32_t x, y, pix;   // pixel, and its index within the tile
+    bool inside;
+    float pxc, pyc, bx0, by0;
+};
+
+__device__ __forceinline__ TileGeo tile_geo(const CamArgs &cam, uint32_t tile, int wid, int lane)
+{
+    TileGeo g;
+    const uint32_t tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const uint32_t col = ((uint32_t)wid & 1u) * 8u + ((uint32_t)lane & 7u);
+    const uint32_t row = ((uint32_t)wid >> 1) * 8u + ((uint32_t)lane >> 3);
+    g.x = tx * kTile + col;
+    g.y = ty * kTile + row;
+    g.pix = row * kTile + col;
+    g.inside = g.x < cam.width && g.y < cam.height;
+    g.pxc = (float)g.x + 0.5f;
+    g.pyc = (float)g.y + 0.5f;
+    g.bx0 = (float)(tx * kTile) + 0.5f;
+    g.by0 = (float)(ty * kTile) + 0.5f;
+    return g;
+}
+
+__device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g, const Pix &px, float4 *image)
+{
+    if (g.inside)
+        image[(uint64_t)g.y * cam.width + g.x] =
+            make_float4(px.cr + px.T * cam.bg[0], px.cg + px.T * cam.bg[1], px.cb + px.T * cam.bg[2], 1.0f - px.T);
+}
+
+// workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+// band of tiles so that neighbouring tiles share its L2
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t per_xcd) { return (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3); }
+
+// ---------------------------------------------------------------------------
+// chunk plan: chunk base of every long tile and the (tile, chunk >= 1) items
+// ---------------------------------------------------------------------------
+constexpr int kPlanThreads = 1024;
+
+__global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *__restrict__ ranges, uint32_t n_tiles,
+                                                                  uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
+                                                                  uint32_t *__restrict__ counters)
+{
+    __shared__ uint32_t s_w[kPlanThreads / kWave][2];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t per = (n_tiles + kPlanThreads - 1) / kPlanThreads;
+    const uint32_t t0 = min(n_tiles, tid * per), t1 = min(n_tiles, t0 + per);
+    uint32_t nch = 0, nit = 0;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint2 r = ranges[t];
+        const uint32_t L = r.y - r.x;
+        if (L > (uint32_t)kChunk) {
+            const uint32_t m = (L + kChunk - 1) / kChunk;
+            nch += m;
+            nit += m - 1;
+        }
+    }
+    // block exclusive scan of (nch, nit)
+    uint32_t a = nch, b = nit;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t na = __shfl_up(a, o, kWave), nb = __shfl_up(b, o, kWave);
+        if (lane >= o) {
+            a += na;
+            b += nb;
+        }
+    }
+    if (lane == kWave - 1) {
+        s_w[wid][0] = a;
+        s_w[wid][1] = b;
+    }
+    __syncthreads();
+    uint32_t oa = 0, ob = 0, ta = 0, tb = 0;
+    for (int w = 0; w < kPlanThreads / kWave; ++w) {
+        if (w < wid) {
+            oa += s_w[w][0];
+            ob += s_w[w][1];
+        }
+        ta += s_w[w][0];
+        tb += s_w[w][1];
+    }
+    uint32_t ca = oa + a - nch, cb = ob + b - nit;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint2 r = ranges[t];
+        const uint32_t L = r.y - r.x;
+        if (L > (uint32_t)kChunk) {
+            const uint32_t m = (L + kChunk - 1) / kChunk;
+            cbase[t] = ca;
+            for (uint32_t c = 1; c < m; ++c) items[cb + c - 1] = make_uint2(t, c);
+            ca += m;
+            cb += m - 1;
+        }
+    }
+    if (tid == kPlanThreads - 1) {
+        counters[kRenChunks] = ta;
+        counters[kRenItems] = tb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: every tile, up to its first kChunk keys
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlendThreads) blend_kernel(CamArgs cam, const float4 *__restrict__ splat,
+                                                              const uint32_t *__restrict__ vals,
+                                                              const uint2 *__restrict__ ranges,
+                                                              const uint32_t *__restrict__ cbase,
+                                                              float4 *__restrict__ scratch,
+                                                              float4 *__restrict__ image, uint32_t per_xcd,
+                                                              unsigned long long *__restrict__ pairs)
+{
+    __shared__ BlendShared sh;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t tile = xcd_tile(per_xcd);
+    if (tile >= cam.tiles_x * cam.tiles_y) return;
+    const TileGeo g = tile_geo(cam, tile, wid, lane);
+    const uint2 rg = ranges[tile];
+    Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u};
+    const bool long_list = rg.y - rg.x > (uint32_t)kChunk;
+    blend_range(rg.x, long_list ? rg.x + kChunk : rg.y, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+    if (long_list)  // state after chunk 0; a negative T marks a finished pixel
+        scratch[(uint64_t)cbase[tile] * kBlendThreads + g.pix] =
+            make_float4(px.cr, px.cg, px.cb, px.active ? px.T : -px.T);
+    else
+        write_pixel(cam, g, px, image);
+    count_pairs(px, lane, pairs);
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: chunks 1.. of long tiles, in parallel, each from T = 1
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlendThreads) chunk_kernel(CamArgs cam, const float4 *__restrict__ splat,
+                                                              const uint32_t *__restrict__ vals,
+                                                              const uint2 *__restrict__ ranges,
+                                                              const uint32_t *__restrict__ cbase,
+                                                              const uint2 *__restrict__ items,
+                                                              const uint32_t *__restrict__ counters,
+                                                              float4 *__restrict__ scratch,
+                                                              unsigned long long *__restrict__ pairs)
+{
+    __shared__ BlendShared sh;
+    const uint32_t it = blockIdx.x;
+    if (it >= counters[kRenItems]) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint2 item = items[it];
+    const uint32_t tile = item.x, c = item.y;
+    const TileGeo g = tile_geo(cam, tile, wid, lane);
+    const uint2 rg = ranges[tile];
+    const uint64_t base = cbase[tile];
+    const float4 s0 = scratch[base * kBlendThreads + g.pix];
+    Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u};
+    const bool was = px.active;
+    const uint32_t b = rg.x + c * kChunk;
+    blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+    scratch[(base + c) * kBlendThreads + g.pix] =
+        make_float4(px.cr, px.cg, px.cb, (was && !px.active) ? -px.T : px.T);
+    count_pairs(px, lane, pairs);
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: fold the chunk summaries of long tiles; list the chunks to walk again
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNone = 0xffffffffu;
+
+__global__ void __launch_bounds__(kBlendThreads) fold_kernel(CamArgs cam, const uint2 *__restrict__ ranges,
+                                                             const uint32_t *__restrict__ cbase,
+                                                             float4 *__restrict__ scratch, uint32_t *__restrict__ pend,
+                                                             uint32_t *__restrict__ need, uint2 *__restrict__ rewalk,
+                                                             uint32_t *counters, float4 *__restrict__ image,
+                                                             uint32_t per_xcd)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t tile = xcd_tile(per_xcd);
+    if (tile >= cam.tiles_x * cam.tiles_y) return;
+    const uint2 rg = ranges[tile];
+    const uint32_t L = rg.y - rg.x;
+    if (L <= (uint32_t)kChunk) return;
+    const uint32_t m = (L + kChunk - 1) / kChunk;
+    const TileGeo g = tile_geo(cam, tile, wid, lane);
+    const uint64_t base = cbase[tile];
+    for (uint32_t c = tid; c < m; c += kBlendThreads) need[base + c] = 0u;
+    __syncthreads();
+    const float4 s0 = scratch[base * kBlendThreads + g.pix];
+    Pix px{fabsf(s0.w), s0.x, s0.y, s0.z, false, 0u};
+    uint32_t pending = kNone;
+    if (s0.w > 0.0f) {
+        for (uint32_t c = 1; c < m; ++c) {
+            const float4 sc = scratch[(base + c) * kBlendThreads + g.pix];
+            if (sc.w < 0.0f || px.T * sc.w < 1e-4f) {
+                pending = c;
+                break;
+            }
+            px.cr = fmaf(px.T, sc.x, px.cr);
+            px.cg = fmaf(px.T, sc.y, px.cg);
+            px.cb = fmaf(px.T, sc.z, px.cb);
+            px.T *= sc.w;
+        }
+    }
+    if (pending == kNone) {
+        write_pixel(cam, g, px, image);
+    } else {
+        // the folded state goes where chunk 0's was; the chunk to walk again is noted
+        scratch[base * kBlendThreads + g.pix] = make_float4(px.cr, px.cg, px.cb, px.T);
+        need[base + pending] = 1u;
+    }
+    pend[base * kBlendThreads + g.pix] = pending;
+    __syncthreads();
+    for (uint32_t c = tid; c < m; c += kBlendThreads)
+        if (need[base + c]) {
+            const uint32_t slot = atomicAdd(&counters[kRenRewalk], 1u);
+            rewalk[slot] = make_uint2(tile, c);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// pass 4: walk again, with the stop rule, each chunk that holds a stop
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(CamArgs cam, const float4 *__restrict__ splat,
+                                                               const uint32_t *__restrict__ vals,
+                                                               const uint2 *__restrict__ ranges,
+                                                               const uint32_t *__restrict__ cbase,
+                                                               const float4 *__restrict__ scratch,
+                                                               const uint32_t *__restrict__ pend,
+                                                               const uint2 *__restrict__ rewalk,
+                                                               const uint32_t *__restrict__ counters,
+                                                               float4 *__restrict__ image,
+                                                               unsigned long long *__restrict__ pairs)
+{
+    __shared__ BlendShared sh;
+    const uint32_t it = blockIdx.x;
+    if (it >= counters[kRenRewalk]) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint2 item = rewalk[it];
+    const uint32_t tile = item.x, c = item.y;
+    const TileGeo g = tile_geo(cam, tile, wid, lane);
+    const uint2 rg = ranges[tile];
+    const uint64_t base = cbase[tile];
+    const bool mine = pend[base * kBlendThreads + g.pix] == c;
+    const float4 st = scratch[base * kBlendThreads + g.pix];
+    Pix px{st.w, st.x, st.y, st.z, mine, 0u};
+    const uint32_t b = rg.x + c * kChunk;
+    blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+    // a pixel that, through rounding of the folded products, does not stop in
+    // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
+    if (mine) write_pixel(cam, g, px, image);
+    count_pairs(px, lane, pairs);
 }
 
 void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals, const uint2 *ranges,
-                  float *image, unsigned long long *pairs)
+                  uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
+                  float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk, float *image,
+                  unsigned long long *pairs)
 {
     const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
     const uint32_t per_xcd = (n_tiles + 7) / 8;
-    hipLaunchKernelGGL(blend_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, cam, splat, vals, ranges,
-                       reinterpret_cast<float4 *>(image), per_xcd, pairs);
+    float4 *img = reinterpret_cast<float4 *>(image);
+    if (max_items > 0)
+        hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ranges, n_tiles, cbase, items,
+                           counters);
+    hipLaunchKernelGGL(blend_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, cam, splat, vals, ranges, cbase,
+                       scratch, img, per_xcd, pairs);
+    if (max_items > 0) {
+        hipLaunchKernelGGL(chunk_kernel, dim3((uint32_t)max_items), dim3(kBlendThreads), 0, st, cam, splat, vals,
+                           ranges, cbase, items, counters, scratch, pairs);
+        hipLaunchKernelGGL(fold_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, cam, ranges, cbase, scratch,
+                           pend, need, rewalk, counters, img, per_xcd);
+        hipLaunchKernelGGL(rewalk_kernel, dim3((uint32_t)max_chunks), dim3(kBlendThreads), 0, st, cam, splat, vals,
+                           ranges, cbase, scratch, pend, rewalk, counters, img, pairs);
+    }
 }
 
 }  // namespace v3dg

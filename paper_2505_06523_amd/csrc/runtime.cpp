@@ -132,6 +132,13 @@ struct v3dg_scene {
     uint32_t *vals[2] = {nullptr, nullptr};
     uint64_t *sort_status = nullptr;
     uint64_t sort_status_parts = 0;
+    uint32_t *cbase = nullptr;     // per tile: first chunk of a long list
+    uint2 *items = nullptr;        // (tile, chunk) work items
+    float4 *scratch = nullptr;     // per chunk, per pixel (C, T)
+    uint32_t *pend = nullptr;      // per long tile, per pixel: chunk to walk again
+    uint32_t *need = nullptr;      // per chunk: walk it again
+    uint2 *rewalk = nullptr;       // (tile, chunk) to walk again
+    uint64_t cap_chunks = 0;
     uint32_t epoch = 0;
     uint32_t *pinned = nullptr;
     v3dg_frame_stats last{};
@@ -315,6 +322,8 @@ int ensure_tiles(v3dg_scene *s, uint32_t n_tiles)
     s->rcounters = s->rclear;
     s->scan_status = reinterpret_cast<uint64_t *>(s->rclear + kRenCounters);
     s->ranges = reinterpret_cast<uint2 *>(s->rclear + kRenCounters + 2 * s->scan_parts);
+    dev_free(s->cbase);
+    if ((rc = dev_alloc(&s->cbase, s->tiles_cap))) return rc;
     return V3DG_OK;
 }
 
@@ -329,6 +338,27 @@ int ensure_status(v3dg_scene *s, uint64_t parts)
     HIP_TRY(hipMemsetAsync(s->sort_status, 0, np * kRadix * sizeof(uint64_t), s->stream));
     s->sort_status_parts = np;
     s->epoch = 0;
+    return V3DG_OK;
+}
+
+int ensure_chunks(v3dg_scene *s, uint64_t K, uint32_t n_tiles)
+{
+    const uint64_t need = (K + kChunk - 1) / kChunk + n_tiles;
+    if (need <= s->cap_chunks) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    dev_free(s->items);
+    dev_free(s->scratch);
+    dev_free(s->pend);
+    dev_free(s->need);
+    dev_free(s->rewalk);
+    const uint64_t cap = need + need / 2;
+    int rc;
+    if ((rc = dev_alloc(&s->items, cap))) return rc;
+    if ((rc = dev_alloc(&s->scratch, cap * 256))) return rc;
+    if ((rc = dev_alloc(&s->pend, cap * 256))) return rc;
+    if ((rc = dev_alloc(&s->need, cap))) return rc;
+    if ((rc = dev_alloc(&s->rewalk, cap))) return rc;
+    s->cap_chunks = cap;
     return V3DG_OK;
 }
 
@@ -443,6 +473,7 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     if ((err & kErrOverflow) || K >= 0xffffffffull)
         return fail(V3DG_ERR_CAPACITY, "frame needs %llu keys; the limit is 2^32-1", (unsigned long long)K);
     if ((rc = ensure_keys(s, K))) return rc;
+    if ((rc = ensure_chunks(s, K, n_tiles))) return rc;
     const uint32_t tile_bits = std::max<uint32_t>(bits_for(n_tiles), 1);
     int buf = 0;
     uint32_t passes = 0;
@@ -475,7 +506,8 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     }
     {
         Stage st(s, V3DG_STAGE_BLEND);
-        launch_blend(s->stream, cam, s->splat, s->vals[buf], s->ranges, image, s->pairs_dev);
+        launch_blend(s->stream, cam, s->splat, s->vals[buf], s->ranges, s->cbase, s->items, s->rcounters,
+                     K / kChunk, K / kChunk + n_tiles, s->scratch, s->pend, s->need, s->rewalk, image, s->pairs_dev);
     }
     HIP_TRY(hipGetLastError());
     s->acc.frames += 1;
@@ -565,6 +597,12 @@ void scene_release(v3dg_scene *s)
     }
     dev_free(s->sort_status);
     dev_free(s->pairs_dev);
+    dev_free(s->cbase);
+    dev_free(s->items);
+    dev_free(s->scratch);
+    dev_free(s->pend);
+    dev_free(s->need);
+    dev_free(s->rewalk);
     if (s->pinned) (void)hipHostFree(s->pinned);
     s->pinned = nullptr;
     for (auto &r : s->prof) {

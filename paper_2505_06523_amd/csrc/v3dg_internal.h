@@ -55,6 +55,9 @@ enum RenderCounter : int {
     kRenKeysLo = 2,       // total keys (64-bit, lo/hi)
     kRenKeysHi = 3,
     kRenVisible = 4,      // slots with at least one tile
+    kRenChunks = 5,       // chunks of long tiles (blending)
+    kRenItems = 6,        // chunk work items (chunks past the first)
+    kRenRewalk = 7,       // chunks walked again (they hold a pixel's stop)
     kRenTicketSort = 8,   // 8 passes of the tile (or 64-bit) sort
     kRenTicketDepth = 16, // 4 passes of the depth sort
     kRenHist = 32,        // 8 passes x 256 bins
@@ -175,8 +178,11 @@ template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint2 *ranges);
 
 // blend.hip
-void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals,
-                  const uint2 *ranges, float *image, unsigned long long *pairs);
+constexpr int kChunk = 2048;            // keys per chunk of a long tile list
+void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals, const uint2 *ranges,
+                  uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
+                  float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk, float *image,
+                  unsigned long long *pairs);
 
 // generic fill
 void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);

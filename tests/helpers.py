@@ -86,3 +86,49 @@ def random_camera_near(rng, width=64, height=48, dist=(0.05, 30.0)):
     eye = d * np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
     tgt = rng.uniform(-0.3, 0.3, 3)
     return sg.look_at(eye, tgt, width, height, rng.uniform(0.3, 1.5))
+
+
+def flat_asset(pos, scale, rot, opacity, sh, sh_degree=0) -> sg.Asset:
+    """Leaf clusters of up to 64 rows under one root (fan-out <= 255)."""
+    pos = np.asarray(pos, np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    nl = (n + 63) // 64
+    assert 1 <= nl <= 255
+    nc = (sh_degree + 1) ** 2
+    first = np.arange(nl, dtype=np.uint32) * 64
+    count = np.minimum(64, n - first).astype(np.uint8)
+    p64 = pos.astype(np.float64)
+    c = p64.mean(axis=0)
+    r = float(np.linalg.norm(p64 - c, axis=1).max()) * 1.01 + 1e-3
+    # the root's rows: the first min(64, n) Gaussians again (never selected at tau = 0)
+    rows = np.concatenate([np.arange(n), np.arange(min(64, n))])
+    self_sphere = np.zeros((nl + 1, 4), np.float32)
+    self_sphere[:nl, :3] = p64[first].astype(np.float32)
+    self_sphere[nl, :3] = c
+    self_sphere[nl, 3] = r
+    parent_sphere = np.repeat(self_sphere[nl:nl + 1], nl + 1, axis=0)
+    parent_sphere[nl, 3] = np.inf
+    return sg.Asset(
+        sh_degree=sh_degree, pos=pos[rows], scale=np.asarray(scale, np.float32).reshape(n, 3)[rows],
+        rot=np.asarray(rot, np.float32).reshape(n, 4)[rows], opacity=np.asarray(opacity, np.float32).reshape(n)[rows],
+        sh=np.asarray(sh, np.float32).reshape(n, nc, 3)[rows],
+        first_row=np.append(first, n).astype(np.uint32), count=np.append(count, min(64, n)).astype(np.uint8),
+        level=np.array([0] * nl + [1], np.uint8), parent=np.array([nl] * nl + [-1], np.int32),
+        first_child=np.array([-1] * nl + [0], np.int32), n_children=np.array([0] * nl + [nl], np.uint8),
+        self_sphere=self_sphere, parent_sphere=parent_sphere, n_leaf_clusters=nl,
+    )
+
+
+def stacked_splats(n, seed, opacity_range, spread=0.15, depth=(1.0, 4.0)):
+    """n Gaussians stacked in front of the camera over a few tiles."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(depth[0], depth[1], n)
+    xy = rng.normal(0.0, spread, (n, 2)) * z[:, None] * 0.1
+    pos = np.concatenate([xy, z[:, None]], axis=1)
+    scale = np.exp(rng.normal(-4.0, 0.4, (n, 3)))
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q[q[:, 0] < 0] *= -1
+    o = rng.uniform(opacity_range[0], opacity_range[1], n)
+    sh = rng.normal(0.0, 0.3, (n, 1, 3))
+    return flat_asset(pos, scale, q, o, sh)

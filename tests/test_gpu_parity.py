@@ -264,6 +264,29 @@ def test_image_parity_sh3_instances_background(torch):
     sc.close()
 
 
+@pytest.mark.parametrize("opacity,seed", [((0.02, 0.12), 5), ((0.3, 0.95), 6), ((0.05, 0.5), 7)])
+def test_long_tile_lists_chunked_blending(torch, opacity, seed):
+    """Thousands of splats over a few tiles: lists far longer than one chunk,
+    pixels that never saturate, and pixels that stop inside later chunks."""
+    a = H.stacked_splats(12000, seed, opacity)
+    cam = H.identity_camera(72, 56, 300.0, bg=(0.1, 0.2, 0.3))
+    T = sg.identity_instances(1)
+    sc = v.Scene(a, T)
+    sel = sc.select(cam, 0.0)
+    img = sc.render(cam, sel).cpu().numpy()
+    st = sc.frame_stats()
+    keys, _ = sc.sorted_keys()
+    per_tile = np.bincount((keys >> np.uint64(32)).astype(np.int64))
+    _say("long lists: keys %d, longest tile list %d" % (st["n_keys"], per_tile.max()))
+    assert per_tile.max() > 4 * 1024
+    ref, amb, _ = oracle.render(a, T, cam, sel.ids())
+    check_image(img, ref, amb, "stacked o=%s" % (opacity,))
+    sc.set_sort_mode(v.V3DG_SORT_KEYS64)
+    img2 = sc.render(cam, sel).cpu().numpy()
+    assert np.array_equal(img, img2)
+    sc.close()
+
+
 def test_tau0_equals_full_detail_bitwise_and_deterministic(c1, torch):
     a, sc = c1
     cam = sg.single_camera_c1()
