@@ -396,12 +396,12 @@ uint32_t next_epoch(v3dg_scene *s)
 // bits of the keys; *out_buf receives the buffer index holding the result.
 template <typename KT>
 int run_sort(v3dg_scene *s, KT *const kb[2], uint32_t *const vb[2], uint64_t K, uint32_t key_bits, int *out_buf,
-             uint32_t *passes_out)
+             uint32_t *passes_out, bool have_hist)
 {
     const int passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
     *passes_out = (uint32_t)passes;
     int cur = 0;
-    {
+    if (!have_hist) {
         Stage st(s, V3DG_STAGE_SORT_HIST);
         launch_sort_hist<KT>(s->stream, kb[0], K, passes, s->rcounters + kRenHist);
     }
@@ -480,16 +480,17 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     uint32_t key_bits;
     if (depth_first) {
         uint32_t *kb[2] = {reinterpret_cast<uint32_t *>(s->keys[0]), reinterpret_cast<uint32_t *>(s->keys[1])};
+        key_bits = tile_bits;
+        const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
         {
             Stage st(s, V3DG_STAGE_EMIT);
             launch_emit32(s->stream, N, s->dval[0], s->tiles, s->offsets, s->rect, s->bin, cam.tiles_x, s->cap_keys,
-                          kb[0], s->vals[0], s->rcounters + kRenErr);
+                          tpasses, kb[0], s->vals[0], s->rcounters + kRenHist, s->rcounters + kRenErr);
         }
-        key_bits = tile_bits;
-        if (K > 0) run_sort<uint32_t>(s, kb, s->vals, K, key_bits, &buf, &passes);
+        if (K > 0) run_sort<uint32_t>(s, kb, s->vals, K, key_bits, &buf, &passes, true);
         {
             Stage st(s, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint32_t>(s->stream, kb[buf], K, 0, s->ranges);
+            launch_tile_ranges<uint32_t>(s->stream, kb[buf], K, 0, n_tiles, s->ranges);
         }
     } else {
         {
@@ -498,10 +499,10 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
                           s->vals[0], s->rcounters + kRenErr);
         }
         key_bits = 32 + tile_bits;
-        if (K > 0) run_sort<uint64_t>(s, s->keys, s->vals, K, key_bits, &buf, &passes);
+        if (K > 0) run_sort<uint64_t>(s, s->keys, s->vals, K, key_bits, &buf, &passes, false);
         {
             Stage st(s, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint64_t>(s->stream, s->keys[buf], K, 32, s->ranges);
+            launch_tile_ranges<uint64_t>(s->stream, s->keys[buf], K, 32, n_tiles, s->ranges);
         }
     }
     {

@@ -248,15 +248,163 @@ void launch_emit64(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint
                        tiles, offsets, rect, bin, tiles_x, key_cap, (void *)keys, vals, err);
 }
 
+// Depth-first emission.  Every lane takes one depth rank; its keys (one per
+// tile its support reaches, row by row) go to a contiguous run of the output
+// starting at its scanned offset.  Lanes with at most kSmallKeys keys write
+// their own run; larger splats are written by the whole wavefront, one splat
+// at a time: lane r computes the span of tile row r, and the wavefront writes
+// each row's run with consecutive lanes on consecutive keys.  The digit
+// histograms of the tile sort are counted per row span: a span of consecutive
+// tile ids adds one to a run of low digits (a difference array over the 256
+// bins) and to one or two higher digits.
+constexpr int kEmitThreads = 256;
+constexpr uint32_t kSmallKeys = 8;
+
+__device__ __forceinline__ void count_span(uint32_t a, uint32_t b, int passes, uint32_t *s_d0, uint32_t *s_h,
+                                           uint32_t *s_all)
+{
+    // tiles a..b (inclusive): every 256 consecutive ids hold each low digit once
+    const uint32_t len = b - a + 1;
+    if (len >= 256u) atomicAdd(s_all, len >> 8);
+    const uint32_t rem = len & 255u;
+    if (rem) {
+        const uint32_t la = a & 255u, lb = (a + rem - 1) & 255u;
+        atomicAdd(&s_d0[la], 1u);
+        atomicAdd(&s_d0[lb + 1], 0xffffffffu);
+        if (la > lb) {  // wraps past digit 255
+            atomicAdd(&s_d0[256], 0xffffffffu);
+            atomicAdd(&s_d0[0], 1u);
+        }
+    }
+    for (int p = 1; p < passes; ++p) {
+        const int sh = 8 * p;
+        for (uint32_t h = a >> sh; h <= (b >> sh); ++h) {
+            const uint32_t lo = max(a, h << sh), hi = min(b, ((h + 1) << sh) - 1);
+            atomicAdd(&s_h[(p - 1) * 256 + (h & 255u)], hi - lo + 1);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
+    uint32_t n, const uint32_t *__restrict__ order, const uint32_t *__restrict__ tiles,
+    const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect, const BinRec *__restrict__ bin,
+    uint32_t tiles_x, uint64_t key_cap, int passes, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+    uint32_t *__restrict__ hist, uint32_t *err)
+{
+    __shared__ uint32_t s_d0[257];
+    __shared__ uint32_t s_h[2 * 256];
+    __shared__ uint32_t s_all;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    for (int i = tid; i < 257; i += kEmitThreads) s_d0[i] = 0u;
+    for (int i = tid; i < 2 * 256; i += kEmitThreads) s_h[i] = 0u;
+    if (tid == 0) s_all = 0u;
+    __syncthreads();
+    const uint32_t j = blockIdx.x * kEmitThreads + tid;
+    const bool valid = j < n;
+    const uint32_t t = valid ? order[j] : 0u;
+    uint32_t nt = valid ? tiles[t] : 0u;
+    const uint64_t off = valid ? offsets[j] : 0u;
+    if (off + nt > key_cap) {  // never with the capacity the host allocates
+        atomicOr(err, kErrOverflow);
+        nt = 0;
+    }
+    uint2 rc = make_uint2(0u, 0u);
+    BinRec b{};
+    if (nt) {
+        rc = rect[t];
+        b = bin[t];
+    }
+    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
+    // small splats: this lane writes its own run
+    if (nt && nt <= kSmallKeys) {
+        uint64_t o = off;
+        const uint64_t end = off + nt;
+        for (uint32_t ty = ty0; ty <= ty1 && o < end; ++ty) {
+            uint32_t lo, hi;
+            if (!tile_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
+            count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
+            for (uint32_t tx = lo; tx <= hi && o < end; ++tx) {
+                keys[o] = ty * tiles_x + tx;
+                vals[o] = t;
+                ++o;
+            }
+        }
+        if (o != end) atomicOr(err, kErrOverflow);  // counting and emission disagree
+    }
+    // larger splats: the wavefront writes them one after another
+    uint64_t big = __ballot(nt > kSmallKeys);
+    while (big) {
+        const int L = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        const uint32_t bt = __shfl(t, L, kWave);
+        const uint32_t bn = __shfl(nt, L, kWave);
+        uint64_t bo = ((uint64_t)__shfl((uint32_t)(off >> 32), L, kWave) << 32) | __shfl((uint32_t)off, L, kWave);
+        const uint64_t bend = bo + bn;
+        const uint32_t bx0 = __shfl(tx0, L, kWave), bx1 = __shfl(tx1, L, kWave);
+        const uint32_t by0 = __shfl(ty0, L, kWave), by1 = __shfl(ty1, L, kWave);
+        BinRec bb;
+        bb.mx = __shfl(b.mx, L, kWave);
+        bb.my = __shfl(b.my, L, kWave);
+        bb.sa = __shfl(b.sa, L, kWave);
+        bb.sb = __shfl(b.sb, L, kWave);
+        bb.sc = __shfl(b.sc, L, kWave);
+        bb.det = __shfl(b.det, L, kWave);
+        bb.Qm = __shfl(b.Qm, L, kWave);
+        bb.depth = __shfl(b.depth, L, kWave);
+        for (uint32_t rb = by0; rb <= by1; rb += kWave) {
+            const uint32_t ty = rb + (uint32_t)lane;
+            uint32_t lo = 0, len = 0;
+            if (ty <= by1) {
+                uint32_t hi;
+                if (tile_row_span(bb, ty, bx0, bx1, &lo, &hi)) {
+                    len = hi - lo + 1;
+                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
+                }
+            }
+            const uint32_t incl = wave_incl_scan_u32(len);
+            const uint32_t pre = incl - len;
+            const uint32_t rows = min((uint32_t)kWave, by1 - rb + 1);
+            for (uint32_t r = 0; r < rows; ++r) {
+                const uint32_t len_r = __shfl(len, (int)r, kWave);
+                if (len_r == 0) continue;
+                const uint32_t base_tile = (rb + r) * tiles_x + __shfl(lo, (int)r, kWave);
+                const uint64_t o = bo + __shfl(pre, (int)r, kWave);
+                for (uint32_t c = (uint32_t)lane; c < len_r; c += kWave) {
+                    if (o + c < bend) {
+                        keys[o + c] = base_tile + c;
+                        vals[o + c] = bt;
+                    }
+                }
+            }
+            bo += __shfl(incl, kWave - 1, kWave);
+        }
+        if (bo != bend && lane == 0) atomicOr(err, kErrOverflow);  // counting and emission disagree
+    }
+    __syncthreads();
+    // digit histograms: prefix of the difference array gives the low-digit counts
+    if (tid < kWave) {
+        uint32_t run = 0;
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t v = s_d0[c * kWave + tid];
+            const uint32_t incl = wave_incl_scan_u32(v);
+            const uint32_t cntd = run + incl + s_all;
+            if (cntd) atomicAdd(&hist[c * kWave + tid], cntd);
+            run += __shfl(incl, kWave - 1, kWave);
+        }
+    }
+    for (int p = 1; p < passes; ++p)
+        for (int i = tid; i < 256; i += kEmitThreads)
+            if (s_h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], s_h[(p - 1) * 256 + i]);
+}
+
 void launch_emit32(hipStream_t st, uint32_t n, const uint32_t *order, const uint32_t *tiles, const uint32_t *offsets,
-                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint32_t *keys,
-                   uint32_t *vals, uint32_t *err)
+                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, int passes,
+                   uint32_t *keys, uint32_t *vals, uint32_t *hist, uint32_t *err)
 {
     if (n == 0) return;
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(emit_kernel<true>, dim3((uint32_t)blocks), dim3(256), 0, st, n, order, tiles, offsets, rect,
-                       bin, tiles_x, key_cap, (void *)keys, vals, err);
+    const uint32_t blocks = (n + kEmitThreads - 1) / kEmitThreads;
+    hipLaunchKernelGGL(emit32_kernel, dim3(blocks), dim3(kEmitThreads), 0, st, n, order, tiles, offsets, rect,
+                       bin, tiles_x, key_cap, passes, keys, vals, hist, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,28 +615,36 @@ void launch_sort_pass_dev(hipStream_t st, const uint32_t *keys_in, const uint32_
 }
 
 // ---------------------------------------------------------------------------
-// tile ranges
+// tile ranges: [lower_bound(t), lower_bound(t + 1)) in the sorted keys, one
+// binary search per tile instead of a pass over the keys
 // ---------------------------------------------------------------------------
 template <typename K>
-__global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, uint32_t n, int shift,
-                                                          uint2 *__restrict__ ranges)
+__device__ __forceinline__ uint32_t lower_bound_tile(const K *__restrict__ keys, uint32_t n, int shift, uint32_t t)
 {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t t = (uint32_t)(keys[i] >> shift);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[t].x = i;
-        if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[t].y = i + 1;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if ((uint32_t)(keys[mid] >> shift) < t) lo = mid + 1;
+        else hi = mid;
     }
+    return lo;
 }
 
 template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint2 *ranges)
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, uint32_t n, int shift,
+                                                          uint32_t n_tiles, uint2 *__restrict__ ranges)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    ranges[t] = make_uint2(lower_bound_tile(keys, n, shift, t), lower_bound_tile(keys, n, shift, t + 1));
+}
+
+template <typename K>
+void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint32_t n_tiles, uint2 *ranges)
 {
     if (n == 0) return;
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, (uint32_t)n, shift,
-                       ranges);
+    hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, (uint32_t)n, shift,
+                       n_tiles, ranges);
 }
 
 template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint32_t *);
@@ -497,7 +653,7 @@ template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const ui
                                          uint64_t, int, const uint32_t *, uint64_t *, uint32_t, uint32_t *, uint32_t *);
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          uint64_t, int, const uint32_t *, uint64_t *, uint32_t, uint32_t *, uint32_t *);
-template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint2 *);
-template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, uint64_t, int, uint2 *);
+template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint32_t, uint2 *);
+template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, uint64_t, int, uint32_t, uint2 *);
 
 }  // namespace v3dg

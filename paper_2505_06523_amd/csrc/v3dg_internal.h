@@ -152,10 +152,11 @@ void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *or
 void launch_emit64(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
                    const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals,
                    uint32_t *err);
-// 32-bit tile keys in depth order (order[j] = slot of depth rank j)
+// 32-bit tile keys in depth order (order[j] = slot of depth rank j), with the
+// digit histograms of the tile sort (passes <= 3) accumulated into hist
 void launch_emit32(hipStream_t st, uint32_t n, const uint32_t *order, const uint32_t *tiles, const uint32_t *offsets,
-                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint32_t *keys,
-                   uint32_t *vals, uint32_t *err);
+                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, int passes,
+                   uint32_t *keys, uint32_t *vals, uint32_t *hist, uint32_t *err);
 // device-side count variants used by the depth sort (grid sized for max_n)
 void launch_sort_hist_dev(hipStream_t st, const uint32_t *keys, const uint32_t *n_dev, uint64_t max_n, int passes,
                           uint32_t *hist);
@@ -175,7 +176,7 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
                       uint64_t n, int pass, const uint32_t *hist, uint64_t *status, uint32_t epoch,
                       uint32_t *ticket, uint32_t *err);
 template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint2 *ranges);
+void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint32_t n_tiles, uint2 *ranges);
 
 // blend.hip
 constexpr int kChunk = 2048;            // keys per chunk of a long tile list
