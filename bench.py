@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-frames", type=int, default=3, help="frames the CPU oracle renders for its baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extended", action="store_true")
+    ap.add_argument("--no-tiers", action="store_true", help="skip the storage-precision comparison")
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
                     help="time the frames without per-kernel events (the roofline then comes from a second pass)")
@@ -209,6 +210,44 @@ def main():
                                         psnr_vs_full_db_median=float(np.median(q)),
                                         selected_gaussians_mean=P_e["slots"] / max(P_e["frames"], 1))
 
+    # storage tiers: FP32 vs FP16 geometry with BF16 / FP16 SH, at 1080p and 2160p
+    tiers = {}
+    if not args.no_tiers and not args.profile_run:
+        import dataclasses
+        tier_frames = seq[:128] if len(seq) >= 128 else [(cams[i % 64], taus[i // 64 % 2]) for i in range(128)]
+        for res, mul in [("1920x1080", 1), ("3840x2160", 2)]:
+            fr = [(dataclasses.replace(c, width=c.width * mul, height=c.height * mul, fx=c.fx * mul, fy=c.fy * mul,
+                                       cx=c.cx * mul, cy=c.cy * mul), t) for c, t in tier_frames]
+            im = torch.empty((fr[0][0].height, fr[0][0].width, 4), dtype=torch.float32, device="cuda")
+            im32 = torch.empty_like(im)
+            for name in ["fp32", "fp16_bf16sh", "fp16"]:
+                sc = scene if name == "fp32" else v.Scene(asset, precision=name)
+                sel = None
+                for cam, tau in fr[:4]:
+                    sel = sc.select(cam, tau, sel)
+                    sc.render(cam, sel, im)
+                torch.cuda.synchronize()
+                sc.collect_profile()
+                w_t, ms_t, P_t, _ = run_frames(torch, sc, fr, im, full=False, prof=True)
+                q = []
+                for cam, tau in fr[::16]:
+                    sel = sc.select(cam, tau, sel)
+                    sc.render(cam, sel, im)
+                    s32 = scene.select(cam, tau)
+                    scene.render(cam, s32, im32)
+                    mse = float(((im[..., :3].clamp(0, 1) - im32[..., :3].clamp(0, 1)) ** 2).mean())
+                    q.append(float("inf") if mse == 0 else 10 * math.log10(1 / mse))
+                tiers["%s %s" % (name, res)] = dict(
+                    fps=len(fr) / w_t, p50_ms=pct(ms_t, 50), p99_ms=pct(ms_t, 99),
+                    bytes_per_row=b_row if name == "fp32" else 4 * 3 + 2 * 8 + 2 * 3 * 16,
+                    project_ms_per_frame=P_t["stages"]["project"][0] / max(P_t["frames"], 1),
+                    blend_ms_per_frame=P_t["stages"]["blend"][0] / max(P_t["frames"], 1),
+                    psnr_vs_fp32_db_min=float(np.min(q)))
+                log("tier %s %s: %.1f FPS" % (name, res, len(fr) / w_t))
+                if sc is not scene:
+                    sc.close()
+            del im, im32
+
     # per-stage timing and roofline of the dominant kernel
     stages = {k: dict(ms_total=t, launches=n, ms_per_launch=(t / n if n else None))
               for k, (t, n) in P["stages"].items()}
@@ -262,6 +301,7 @@ def main():
         "stages": stages,
         "sort_hbm_gbs": (sort_b / (sort_t * 1e-3) / 1e9) if sort_t > 0 else None,
         "extended_tolerances": extended,
+        "precision_tiers": tiers,
         "roofline": roof,
     }
 

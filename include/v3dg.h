@@ -38,8 +38,15 @@ extern "C" {
 #define V3DG_ERR_CAPACITY (-5)     /* a frame exceeds a 32-bit count                       */
 #define V3DG_ERR_DEVICE (-6)       /* a kernel raised its error flag (bounded wait expired)*/
 
-/* precision of the stored attributes */
+/* Storage precision of the Gaussian attributes (positions always stay FP32;
+ * arithmetic is FP32 in every case).  The library rounds the FP32 input of
+ * v3dg_load_hierarchy to nearest-even:
+ *   V3DG_FP32         everything FP32                          (236 B/row at SH3)
+ *   V3DG_FP16_BF16SH  scale, rotation, opacity FP16; SH BF16   (124 B/row at SH3)
+ *   V3DG_FP16         scale, rotation, opacity and SH FP16     (124 B/row at SH3) */
 #define V3DG_FP32 0u
+#define V3DG_FP16_BF16SH 1u
+#define V3DG_FP16 2u
 /* load flags */
 #define V3DG_LOAD_REPAIR_NESTING 1u /* inflate parent radii bottom-up instead of failing */
 
@@ -68,7 +75,10 @@ typedef struct {
  * self_sphere[parent[k]] bit for bit, and r = +inf for roots (Sec. 3.4).
  * Gaussian rows: pos (x,y,z), scale (linear, > 0), rot unit quaternion
  * (w,x,y,z) within 1e-6, opacity in (0, 1], sh row-major
- * [(sh_degree+1)^2][3] real-SH coefficients (sh_degree 0..3). */
+ * [(sh_degree+1)^2][3] real-SH coefficients (sh_degree 0..3).  All arrays
+ * are FP32; `precision` (V3DG_FP32, V3DG_FP16_BF16SH, V3DG_FP16) selects how
+ * the library stores them.  In the narrow tiers scale and opacity must stay
+ * positive and finite after rounding. */
 typedef struct {
     uint32_t n_clusters, n_rows, sh_degree, precision;
     const float *self_sphere;   /* n_clusters x 4 */
@@ -177,6 +187,14 @@ int v3dg_get_frame_stats(v3dg_scene *scene, v3dg_frame_stats *out);
  * opacity; tiles = tiles touched (0 = culled). */
 int v3dg_copy_projection(v3dg_scene *scene, float *mean2, float *conic, float *rgb, float *opacity, float *depth,
                          uint32_t *tiles, uint64_t cap, uint64_t *n_out);
+
+/* The stored Gaussian attributes of rows [first, first + n), widened to FP32
+ * (synchronises): what the projection reads in the scene's precision tier.
+ * Layouts as in v3dg_hierarchy_desc (pos x3, scale x3, rot x4, opacity,
+ * sh 3 (d+1)^2); any pointer may be NULL.  V3DG_ERR_INVALID_ARG when the
+ * range leaves the table. */
+int v3dg_copy_attributes(v3dg_scene *scene, uint64_t first, uint64_t n, float *pos, float *scale, float *rot,
+                         float *opacity, float *sh);
 
 /* The last frame's sorted keys as (tile << 32 | depth bits) and values
  * (slot), whatever the sort mode (synchronises). */

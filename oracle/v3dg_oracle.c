@@ -291,7 +291,9 @@ static void orc_project_one(const orc_asset *a, const float *A, const double *ch
     double y = (double)A[4] * p[0] + (double)A[5] * p[1] + (double)A[6] * p[2] + (double)A[7];
     double z = (double)A[8] * p[0] + (double)A[9] * p[1] + (double)A[10] * p[2] + (double)A[11];
     const float *q = a->rot + 4 * (size_t)row;
-    double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    /* rotation matrix of the normalised quaternion */
+    double qn = sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
+    double qw = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
     double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
                    2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
                    2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};

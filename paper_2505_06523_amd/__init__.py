@@ -26,6 +26,9 @@ V3DG_ERR_NOT_MONOTONE = -4
 V3DG_ERR_CAPACITY = -5
 V3DG_ERR_DEVICE = -6
 V3DG_FP32 = 0
+V3DG_FP16_BF16SH = 1
+V3DG_FP16 = 2
+PRECISIONS = {"fp32": V3DG_FP32, "fp16_bf16sh": V3DG_FP16_BF16SH, "fp16": V3DG_FP16}
 V3DG_LOAD_REPAIR_NESTING = 1
 V3DG_SORT_DEPTH_FIRST = 0
 V3DG_SORT_KEYS64 = 1
@@ -69,7 +72,7 @@ class v3dg_profile(C.Structure):
 EXPORTS = [
     "v3dg_load_hierarchy", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
-    "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_sorted_keys",
+    "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
     "v3dg_set_sort_mode", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs", "v3dg_last_error",
 ]
 
@@ -98,6 +101,7 @@ def lib():
         "v3dg_scene_free": ([P], None),
         "v3dg_get_frame_stats": ([P, P], I),
         "v3dg_copy_projection": ([P, P, P, P, P, P, P, U64, P], I),
+        "v3dg_copy_attributes": ([P, U64, U64, P, P, P, P, P], I),
         "v3dg_copy_sorted_keys": ([P, P, P, U64, P], I),
         "v3dg_set_sort_mode": ([P, I], I),
         "v3dg_set_profiling": ([P, I], I),
@@ -200,6 +204,16 @@ def v3dg_copy_projection(scene, n_slots: int) -> dict:
     return {k: v[: got.value] for k, v in out.items()}
 
 
+def v3dg_copy_attributes(scene, first: int, n: int, sh_degree: int) -> dict:
+    m = max(int(n), 1)
+    nc = (int(sh_degree) + 1) ** 2
+    out = dict(pos=np.zeros((m, 3), np.float32), scale=np.zeros((m, 3), np.float32), rot=np.zeros((m, 4), np.float32),
+               opacity=np.zeros(m, np.float32), sh=np.zeros((m, nc, 3), np.float32))
+    _check(lib().v3dg_copy_attributes(scene, int(first), int(n), _p(out["pos"]), _p(out["scale"]), _p(out["rot"]),
+                                      _p(out["opacity"]), _p(out["sh"])))
+    return {k: v[: int(n)] for k, v in out.items()}
+
+
 def v3dg_copy_sorted_keys(scene, n_keys: int):
     n = max(int(n_keys), 1)
     keys = np.zeros(n, np.uint64)
@@ -284,9 +298,11 @@ class Selection:
 
 
 class Scene:
-    """An asset resident in HBM with its instance table."""
+    """An asset resident in HBM with its instance table.  ``precision`` is the
+    attribute storage tier: V3DG_FP32, V3DG_FP16_BF16SH or V3DG_FP16 (or its
+    name in PRECISIONS)."""
 
-    def __init__(self, asset, instances=None, stream=None, flags: int = 0):
+    def __init__(self, asset, instances=None, stream=None, flags: int = 0, precision=V3DG_FP32):
         arrays = dict(
             self_sphere=np.ascontiguousarray(asset.self_sphere, np.float32),
             parent_sphere=np.ascontiguousarray(asset.parent_sphere, np.float32),
@@ -305,7 +321,10 @@ class Scene:
         d.n_clusters = arrays["first_row"].shape[0]
         d.n_rows = arrays["pos"].shape[0]
         d.sh_degree = int(asset.sh_degree)
-        d.precision = V3DG_FP32
+        d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.precision = int(d.precision)
+        self.sh_degree = int(asset.sh_degree)
+        self.n_rows = int(d.n_rows)
         for k, v in arrays.items():
             setattr(d, k, v.ctypes.data)
         if instances is None:
@@ -356,6 +375,11 @@ class Scene:
 
     def projection(self) -> dict:
         return v3dg_copy_projection(self.handle, self.frame_stats()["n_slots"])
+
+    def attributes(self, first: int = 0, n: int | None = None) -> dict:
+        """Stored rows widened to FP32 (what the projection reads)."""
+        n = self.n_rows - first if n is None else n
+        return v3dg_copy_attributes(self.handle, first, n, self.sh_degree)
 
     def sorted_keys(self):
         return v3dg_copy_sorted_keys(self.handle, self.frame_stats()["n_keys"])

@@ -10,6 +10,8 @@
 // Outputs per slot: the splat record read by blending, the FP32 depth used as
 // the sort key, and the conservative tile rectangle of the support
 // {alpha >= 1/255} (ellipse d^T Sigma^-1 d <= 2 ln(255 o) plus one pixel).
+#include <hip/hip_fp16.h>
+
 #include "v3dg_internal.h"
 
 namespace v3dg {
@@ -85,7 +87,8 @@ __device__ __noinline__ bool cov2_fp64(const float *A, float px, float py, float
     const double y = (double)A[4] * px + (double)A[5] * py + (double)A[6] * pz + (double)A[7];
     const double z = (double)A[8] * px + (double)A[9] * py + (double)A[10] * pz + (double)A[11];
     (void)z32;
-    const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    const double qn = 1.0 / sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
+    const double qw = q[0] * qn, qx = q[1] * qn, qy = q[2] * qn, qz = q[3] * qn;
     const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
                          2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
                          2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
@@ -114,13 +117,31 @@ __device__ __noinline__ bool cov2_fp64(const float *A, float px, float py, float
     return abc[3] > 0.0;
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *__restrict__ planes, uint64_t ps,
+// attribute loads by storage precision: 0 FP32; 1 FP16 geometry + BF16 SH;
+// 2 FP16 geometry + FP16 SH
+template <int P>
+__device__ __forceinline__ float load_geo(const Attribs &at, int plane, uint32_t row)
+{
+    if (P == 0) return static_cast<const float *>(at.geo)[plane * at.ps + row];
+    return __half2float(static_cast<const __half *>(at.geo)[plane * at.ps + row]);
+}
+
+template <int P>
+__device__ __forceinline__ float load_sh(const Attribs &at, int plane, uint32_t row)
+{
+    if (P == 0) return static_cast<const float *>(at.sh)[plane * at.ps + row];
+    if (P == 1) return __uint_as_float((uint32_t) static_cast<const uint16_t *>(at.sh)[plane * at.ps + row] << 16);
+    return __half2float(static_cast<const __half *>(at.sh)[plane * at.ps + row]);
+}
+
+template <int D, int P>
+__global__ void __launch_bounds__(256) project_kernel(CamArgs cam, Attribs at,
                                                       const uint32_t *__restrict__ slot_row,
                                                       const uint32_t *__restrict__ slot_inst,
                                                       const uint32_t *__restrict__ n_dev,
                                                       const InstRec *__restrict__ itab, ProjectOut out)
 {
+    const uint64_t ps = at.ps;
     constexpr int NCOEF = (D + 1) * (D + 1);
     const uint32_t n = *n_dev;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -135,10 +156,10 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
             A[4] = r1.x; A[5] = r1.y; A[6] = r1.z; A[7] = r1.w;
             A[8] = r2.x; A[9] = r2.y; A[10] = r2.z; A[11] = r2.w;
         }
-        const float px = planes[kPlanePX * ps + row];
-        const float py = planes[kPlanePY * ps + row];
-        const float pz = planes[kPlanePZ * ps + row];
-        const float op = planes[kPlaneOP * ps + row];
+        const float px = at.pos[0 * ps + row];
+        const float py = at.pos[1 * ps + row];
+        const float pz = at.pos[2 * ps + row];
+        const float op = load_geo<P>(at, kGeoOP, row);
         const float z = depth_z(A, px, py, pz);
         out.depth[t] = z;
         out.dval[t] = t;
@@ -149,14 +170,16 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
         const float x = fmaf(A[0], px, fmaf(A[1], py, fmaf(A[2], pz, A[3])));
         const float y = fmaf(A[4], px, fmaf(A[5], py, fmaf(A[6], pz, A[7])));
         float q[4], s[3];
-        q[0] = planes[kPlaneQW * ps + row];
-        q[1] = planes[kPlaneQX * ps + row];
-        q[2] = planes[kPlaneQY * ps + row];
-        q[3] = planes[kPlaneQZ * ps + row];
-        s[0] = planes[kPlaneSX * ps + row];
-        s[1] = planes[kPlaneSY * ps + row];
-        s[2] = planes[kPlaneSZ * ps + row];
-        const float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+        q[0] = load_geo<P>(at, kGeoQW, row);
+        q[1] = load_geo<P>(at, kGeoQX, row);
+        q[2] = load_geo<P>(at, kGeoQY, row);
+        q[3] = load_geo<P>(at, kGeoQZ, row);
+        s[0] = load_geo<P>(at, kGeoSX, row);
+        s[1] = load_geo<P>(at, kGeoSY, row);
+        s[2] = load_geo<P>(at, kGeoSZ, row);
+        // rotation of the normalised quaternion (narrow storage leaves |q| off 1 by ~1e-3)
+        const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const float qw = q[0] * qn, qx = q[1] * qn, qy = q[2] * qn, qz = q[3] * qn;
         const float R[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
                             2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
                             2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
@@ -219,7 +242,7 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
 #pragma unroll
         for (int k = 0; k < NCOEF; ++k)
 #pragma unroll
-            for (int cch = 0; cch < 3; ++cch) col[cch] = fmaf(planes[(kPlaneSH + 3 * k + cch) * ps + row], Y[k], col[cch]);
+            for (int cch = 0; cch < 3; ++cch) col[cch] = fmaf(load_sh<P>(at, 3 * k + cch, row), Y[k], col[cch]);
         // tile coverage of the (enlarged) support
         const float Q = 2.0f * __logf(255.0f * op);
         BinRec br;
@@ -257,7 +280,19 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, const float *
     }
 }
 
-void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uint64_t plane_stride, int sh_degree,
+template <int D>
+static void launch_project_d(hipStream_t st, dim3 g, dim3 b, const CamArgs &cam, const Attribs &at, int precision,
+                             const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_dev,
+                             const InstRec *itab, const ProjectOut &out)
+{
+    switch (precision) {
+    case 0: hipLaunchKernelGGL((project_kernel<D, 0>), g, b, 0, st, cam, at, slot_row, slot_inst, n_dev, itab, out); break;
+    case 1: hipLaunchKernelGGL((project_kernel<D, 1>), g, b, 0, st, cam, at, slot_row, slot_inst, n_dev, itab, out); break;
+    default: hipLaunchKernelGGL((project_kernel<D, 2>), g, b, 0, st, cam, at, slot_row, slot_inst, n_dev, itab, out); break;
+    }
+}
+
+void launch_project(hipStream_t st, const CamArgs &cam, const Attribs &attr, int precision, int sh_degree,
                     const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
                     uint64_t max_slots, const InstRec *itab, ProjectOut out)
 {
@@ -266,10 +301,10 @@ void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uin
     if (blocks < 1) blocks = 1;
     dim3 g((uint32_t)blocks), b(256);
     switch (sh_degree) {
-    case 0: hipLaunchKernelGGL(project_kernel<0>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
-    case 1: hipLaunchKernelGGL(project_kernel<1>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
-    case 2: hipLaunchKernelGGL(project_kernel<2>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
-    default: hipLaunchKernelGGL(project_kernel<3>, g, b, 0, st, cam, planes, plane_stride, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    case 0: launch_project_d<0>(st, g, b, cam, attr, precision, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    case 1: launch_project_d<1>(st, g, b, cam, attr, precision, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    case 2: launch_project_d<2>(st, g, b, cam, attr, precision, slot_row, slot_inst, n_slots_dev, itab, out); break;
+    default: launch_project_d<3>(st, g, b, cam, attr, precision, slot_row, slot_inst, n_slots_dev, itab, out); break;
     }
 }
 

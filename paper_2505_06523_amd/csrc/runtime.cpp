@@ -68,6 +68,64 @@ float round_up_f32(double x)
     return f;
 }
 
+// IEEE binary32 -> binary16, round to nearest, ties to even (overflow -> inf)
+uint16_t f32_to_half(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t sign = (u >> 16) & 0x8000u, ex = (u >> 23) & 0xffu, man = u & 0x7fffffu;
+    if (ex == 0xffu) return (uint16_t)(sign | 0x7c00u | (man ? 0x200u : 0u));
+    const int e = (int)ex - 127 + 15;
+    if (e >= 31) return (uint16_t)(sign | 0x7c00u);
+    if (e <= 0) {  // subnormal half (or zero): unit 2^-24
+        if (e < -10) return (uint16_t)sign;
+        const uint32_t m = man | 0x800000u;
+        const int shift = 14 - e;
+        const uint32_t rem = m & ((1u << shift) - 1u), half = 1u << (shift - 1);
+        uint32_t hm = m >> shift;
+        if (rem > half || (rem == half && (hm & 1u))) ++hm;
+        return (uint16_t)(sign | hm);
+    }
+    uint32_t hm = ((uint32_t)e << 10) | (man >> 13);
+    const uint32_t rem = man & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (hm & 1u))) ++hm;  // a carry moves into the exponent
+    return (uint16_t)(sign | hm);
+}
+
+float half_to_f32(uint16_t h)
+{
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16, ex = (h >> 10) & 0x1fu, man = h & 0x3ffu;
+    uint32_t u;
+    if (ex == 0x1fu) {
+        u = sign | 0x7f800000u | (man << 13);
+    } else if (ex == 0) {
+        const float v = std::ldexp((float)man, -24);
+        return sign ? -v : v;
+    } else {
+        u = sign | ((ex - 15 + 127) << 23) | (man << 13);
+    }
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// IEEE binary32 -> bfloat16, round to nearest, ties to even (finite input)
+uint16_t f32_to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if (std::isnan(f)) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+float bf16_to_f32(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
 uint32_t bits_for(uint32_t n)  // ceil(log2(n)), 0 for n <= 1
 {
     uint32_t b = 0;
@@ -99,8 +157,10 @@ struct v3dg_scene {
     hipStream_t stream = nullptr;
     uint32_t NC = 0, n_rows = 0, sh_degree = 0, n_inst = 0;
     uint64_t plane_stride = 0;
-    int n_planes = 0;
-    float *planes = nullptr;
+    uint32_t precision = V3DG_FP32;
+    float *pos_planes = nullptr;  // 3 FP32 planes
+    void *geo_planes = nullptr;   // 8 planes, FP32 or FP16
+    void *sh_planes = nullptr;    // 3 (d+1)^2 planes, FP32, BF16 or FP16
     float4 *self_sph = nullptr, *par_sph = nullptr;
     uint2 *rowinfo = nullptr;
     double *T_dev = nullptr;
@@ -435,7 +495,8 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     ProjectOut po{s->splat, s->depth, s->bin, s->rect, s->tiles, s->dkey[0], s->dval[0]};
     {
         Stage st(s, V3DG_STAGE_PROJECT);
-        launch_project(s->stream, cam, s->planes, s->plane_stride, (int)s->sh_degree, sel->slot_row, sel->slot_inst,
+        const Attribs attr{s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride};
+        launch_project(s->stream, cam, attr, (int)s->precision, (int)s->sh_degree, sel->slot_row, sel->slot_inst,
                        n_dev, s->cap_slots, s->itab, po);
     }
     const bool depth_first = s->sort_mode == V3DG_SORT_DEPTH_FIRST;
@@ -574,7 +635,9 @@ void scene_release(v3dg_scene *s)
         delete s->full;
         s->full = nullptr;
     }
-    dev_free(s->planes);
+    dev_free(s->pos_planes);
+    dev_free(s->geo_planes);
+    dev_free(s->sh_planes);
     dev_free(s->self_sph);
     dev_free(s->par_sph);
     dev_free(s->rowinfo);
@@ -630,7 +693,7 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     g_err.clear();
     if (!d || !out) return fail(V3DG_ERR_INVALID_ARG, "desc and out must be non-NULL");
     *out = nullptr;
-    if (d->precision != V3DG_FP32) return fail(V3DG_ERR_INVALID_ARG, "unknown precision %u", d->precision);
+    if (d->precision > V3DG_FP16) return fail(V3DG_ERR_INVALID_ARG, "unknown precision %u", d->precision);
     if (d->sh_degree > 3) return fail(V3DG_ERR_INVALID_ARG, "sh_degree %u > 3", d->sh_degree);
     if (d->n_clusters < 1 || d->n_rows < 1) return fail(V3DG_ERR_INVALID_ARG, "empty hierarchy");
     if (!d->self_sphere || !d->parent_sphere || !d->first_row || !d->count || !d->parent || !d->first_child ||
@@ -743,6 +806,24 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     const int ncoef = (int)((d->sh_degree + 1) * (d->sh_degree + 1));
     for (uint64_t i = 0; i < (uint64_t)NR * ncoef * 3; ++i)
         if (!finite_f(d->sh[i])) return fail(V3DG_ERR_INVALID_ARG, "SH coefficient %llu not finite", (unsigned long long)i);
+    // narrow storage: scale and opacity must survive the rounding, SH must stay finite
+    if (d->precision != V3DG_FP32) {
+        for (uint64_t r = 0; r < NR; ++r) {
+            for (int j = 0; j < 3; ++j) {
+                const float sv = half_to_f32(f32_to_half(d->scale[3 * r + j]));
+                if (!(sv > 0.0f) || !finite_f(sv))
+                    return fail(V3DG_ERR_INVALID_ARG, "row %llu scale %g leaves the FP16 range", (unsigned long long)r,
+                                (double)d->scale[3 * r + j]);
+            }
+            if (!(half_to_f32(f32_to_half(d->opacity[r])) > 0.0f))
+                return fail(V3DG_ERR_INVALID_ARG, "row %llu opacity %g rounds to 0 in FP16", (unsigned long long)r,
+                            (double)d->opacity[r]);
+        }
+        for (uint64_t i = 0; i < (uint64_t)NR * ncoef * 3; ++i) {
+            const float v = d->precision == V3DG_FP16 ? half_to_f32(f32_to_half(d->sh[i])) : bf16_to_f32(f32_to_bf16(d->sh[i]));
+            if (!finite_f(v)) return fail(V3DG_ERR_INVALID_ARG, "SH coefficient %llu overflows the storage type", (unsigned long long)i);
+        }
+    }
 
     // ---- max cut (bound on slots of any selection) per instance
     std::vector<uint64_t> mc(NC, 0);
@@ -777,13 +858,17 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     for (uint32_t k = 0; k < NC; ++k)
         if (d->n_children[k] == 0) s->leaf_ids.push_back(k);
     s->plane_stride = ((uint64_t)NR + 63) / 64 * 64;
-    s->n_planes = kPlaneSH + 3 * ncoef;
+    s->precision = d->precision;
+    const uint64_t ps = s->plane_stride;
+    const size_t geo_bytes = d->precision == V3DG_FP32 ? 4 : 2, sh_bytes = geo_bytes;
     auto bail = [&](int code) {
         scene_release(s);
         delete s;
         return code;
     };
-    if ((rc = dev_alloc(&s->planes, s->plane_stride * s->n_planes))) return bail(rc);
+    if ((rc = dev_alloc(&s->pos_planes, 3 * ps))) return bail(rc);
+    if ((rc = dev_alloc((uint8_t **)&s->geo_planes, kGeoPlanes * ps * geo_bytes))) return bail(rc);
+    if ((rc = dev_alloc((uint8_t **)&s->sh_planes, 3ull * ncoef * ps * sh_bytes))) return bail(rc);
     if ((rc = dev_alloc(&s->self_sph, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->par_sph, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->rowinfo, NC))) return bail(rc);
@@ -796,20 +881,32 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     if (hipHostMalloc((void **)&s->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
         return bail(fail(V3DG_ERR_OOM, "pinned allocation failed"));
     {
-        std::vector<float> hp(s->plane_stride * s->n_planes, 0.0f);
-        const uint64_t ps = s->plane_stride;
+        std::vector<float> hpos(3 * ps, 0.0f), hgeo(kGeoPlanes * ps, 0.0f), hsh(3ull * ncoef * ps, 0.0f);
         for (uint64_t r = 0; r < NR; ++r) {
             for (int j = 0; j < 3; ++j) {
-                hp[(kPlanePX + j) * ps + r] = d->pos[3 * r + j];
-                hp[(kPlaneSX + j) * ps + r] = d->scale[3 * r + j];
+                hpos[j * ps + r] = d->pos[3 * r + j];
+                hgeo[(kGeoSX + j) * ps + r] = d->scale[3 * r + j];
             }
-            for (int j = 0; j < 4; ++j) hp[(kPlaneQW + j) * ps + r] = d->rot[4 * r + j];
-            hp[kPlaneOP * ps + r] = d->opacity[r];
-            for (int c = 0; c < 3 * ncoef; ++c) hp[(kPlaneSH + c) * ps + r] = d->sh[(uint64_t)r * 3 * ncoef + c];
+            for (int j = 0; j < 4; ++j) hgeo[(kGeoQW + j) * ps + r] = d->rot[4 * r + j];
+            hgeo[kGeoOP * ps + r] = d->opacity[r];
+            for (int c = 0; c < 3 * ncoef; ++c) hsh[c * ps + r] = d->sh[(uint64_t)r * 3 * ncoef + c];
+        }
+        std::vector<uint16_t> ngeo, nsh;
+        const void *src_geo = hgeo.data(), *src_sh = hsh.data();
+        if (d->precision != V3DG_FP32) {
+            ngeo.resize(hgeo.size());
+            nsh.resize(hsh.size());
+            for (size_t i = 0; i < hgeo.size(); ++i) ngeo[i] = f32_to_half(hgeo[i]);
+            for (size_t i = 0; i < hsh.size(); ++i)
+                nsh[i] = d->precision == V3DG_FP16 ? f32_to_half(hsh[i]) : f32_to_bf16(hsh[i]);
+            src_geo = ngeo.data();
+            src_sh = nsh.data();
         }
         std::vector<uint2> ri(NC);
         for (uint32_t k = 0; k < NC; ++k) ri[k] = make_uint2(d->first_row[k], d->count[k]);
-        e = hipMemcpy(s->planes, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice);
+        e = hipMemcpy(s->pos_planes, hpos.data(), hpos.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s->geo_planes, src_geo, hgeo.size() * geo_bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s->sh_planes, src_sh, hsh.size() * sh_bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->self_sph, self.data(), self.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->par_sph, par.data(), par.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->rowinfo, ri.data(), ri.size() * sizeof(uint2), hipMemcpyHostToDevice);
@@ -1010,6 +1107,65 @@ int v3dg_copy_projection(v3dg_scene *s, float *mean2, float *conic, float *rgb, 
         if (depth) depth[t] = dp[t];
         if (tiles) tiles[t] = tl[t];
     }
+    return V3DG_OK;
+}
+
+int v3dg_copy_attributes(v3dg_scene *s, uint64_t first, uint64_t n, float *pos, float *scale, float *rot,
+                         float *opacity, float *sh)
+{
+    g_err.clear();
+    if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
+    if (first > s->n_rows || n > s->n_rows - first)
+        return fail(V3DG_ERR_INVALID_ARG, "rows [%llu, +%llu) outside the %llu-row table", (unsigned long long)first,
+                    (unsigned long long)n, (unsigned long long)s->n_rows);
+    if (n == 0) return V3DG_OK;
+    HIP_TRY(hipSetDevice(s->device));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const uint64_t ps = s->plane_stride;
+    const int ncoef = (int)((s->sh_degree + 1) * (s->sh_degree + 1));
+    const size_t eb = s->precision == V3DG_FP32 ? 4 : 2;
+    auto widen = [&](const void *base, int plane, bool sh_plane, std::vector<float> &out) -> int {
+        std::vector<uint8_t> raw(n * eb);
+        HIP_TRY(hipMemcpy(raw.data(), (const uint8_t *)base + (plane * ps + first) * eb, n * eb, hipMemcpyDeviceToHost));
+        out.resize(n);
+        for (uint64_t i = 0; i < n; ++i) {
+            if (eb == 4) {
+                std::memcpy(&out[i], &raw[4 * i], 4);
+            } else {
+                uint16_t h;
+                std::memcpy(&h, &raw[2 * i], 2);
+                out[i] = (sh_plane && s->precision == V3DG_FP16_BF16SH) ? bf16_to_f32(h) : half_to_f32(h);
+            }
+        }
+        return V3DG_OK;
+    };
+    std::vector<float> col;
+    int rc;
+    if (pos)
+        for (int j = 0; j < 3; ++j) {
+            col.resize(n);
+            HIP_TRY(hipMemcpy(col.data(), s->pos_planes + j * ps + first, n * sizeof(float), hipMemcpyDeviceToHost));
+            for (uint64_t i = 0; i < n; ++i) pos[3 * i + j] = col[i];
+        }
+    if (scale)
+        for (int j = 0; j < 3; ++j) {
+            if ((rc = widen(s->geo_planes, kGeoSX + j, false, col))) return rc;
+            for (uint64_t i = 0; i < n; ++i) scale[3 * i + j] = col[i];
+        }
+    if (rot)
+        for (int j = 0; j < 4; ++j) {
+            if ((rc = widen(s->geo_planes, kGeoQW + j, false, col))) return rc;
+            for (uint64_t i = 0; i < n; ++i) rot[4 * i + j] = col[i];
+        }
+    if (opacity) {
+        if ((rc = widen(s->geo_planes, kGeoOP, false, col))) return rc;
+        for (uint64_t i = 0; i < n; ++i) opacity[i] = col[i];
+    }
+    if (sh)
+        for (int c = 0; c < 3 * ncoef; ++c) {
+            if ((rc = widen(s->sh_planes, c, true, col))) return rc;
+            for (uint64_t i = 0; i < n; ++i) sh[(uint64_t)3 * ncoef * i + c] = col[i];
+        }
     return V3DG_OK;
 }
 

@@ -8,13 +8,21 @@ namespace v3dg {
 constexpr int kTile = 16;               // tile edge in pixels
 constexpr int kWave = 64;               // CDNA wavefront width
 
-// Gaussian attribute planes (structure of arrays, one float plane each,
-// plane stride = padded row count).  SH coefficient k, channel c lives in
-// plane kPlaneSH + 3k + c.
-constexpr int kPlanePX = 0, kPlanePY = 1, kPlanePZ = 2;
-constexpr int kPlaneSX = 3, kPlaneSY = 4, kPlaneSZ = 5;
-constexpr int kPlaneQW = 6, kPlaneQX = 7, kPlaneQY = 8, kPlaneQZ = 9;
-constexpr int kPlaneOP = 10, kPlaneSH = 11;
+// Gaussian attributes are structure-of-arrays planes with a common stride
+// (the row count rounded up to 64): 3 FP32 position planes; 8 "geometry"
+// planes (scale x/y/z, quaternion w/x/y/z, opacity) in FP32 or FP16; and
+// 3 (d+1)^2 SH planes (coefficient k, channel c at 3k + c) in FP32, BF16 or
+// FP16, by storage precision.
+constexpr int kGeoSX = 0, kGeoSY = 1, kGeoSZ = 2;
+constexpr int kGeoQW = 3, kGeoQX = 4, kGeoQY = 5, kGeoQZ = 6, kGeoOP = 7;
+constexpr int kGeoPlanes = 8;
+
+struct Attribs {
+    const float *pos;   // 3 planes
+    const void *geo;    // 8 planes
+    const void *sh;     // 3 (d+1)^2 planes
+    uint64_t ps;        // plane stride in elements
+};
 
 // Per-instance frame record (64 B): A = fl32(V T) row-major 3x4, the camera
 // centre in the asset frame (for view-dependent colour) and the uniform scale.
@@ -137,7 +145,7 @@ struct ProjectOut {
     uint32_t *dkey;     // depth sort key: FP32 depth bits, 0xffffffff when culled
     uint32_t *dval;     // slot index (sort payload)
 };
-void launch_project(hipStream_t st, const CamArgs &cam, const float *planes, uint64_t plane_stride, int sh_degree,
+void launch_project(hipStream_t st, const CamArgs &cam, const Attribs &attr, int precision, int sh_degree,
                     const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
                     uint64_t max_slots, const InstRec *itab, ProjectOut out);
 

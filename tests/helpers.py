@@ -132,3 +132,28 @@ def stacked_splats(n, seed, opacity_range, spread=0.15, depth=(1.0, 4.0)):
     o = rng.uniform(opacity_range[0], opacity_range[1], n)
     sh = rng.normal(0.0, 0.3, (n, 1, 3))
     return flat_asset(pos, scale, q, o, sh)
+
+
+def round_fp16(x) -> np.ndarray:
+    """FP32 values rounded to binary16 (numpy casts round to nearest even), as FP32."""
+    return np.asarray(x, np.float32).astype(np.float16).astype(np.float32)
+
+
+def round_bf16(x) -> np.ndarray:
+    """FP32 values rounded to bfloat16 (8 significant bits, ties to even) by
+    FP64 arithmetic: x = m 2^e with m in [0.5, 1), step 2^(e - 8)."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    _, e = np.frexp(x)
+    step = np.ldexp(1.0, np.maximum(e, -125) - 8)
+    return (np.rint(x / step) * step).astype(np.float32)
+
+
+def quantized_asset(asset, precision: str):
+    """The asset with scale, rotation and opacity in FP16 and SH in BF16
+    ("fp16_bf16sh") or FP16 ("fp16"), widened back to FP32."""
+    import dataclasses
+    if precision == "fp32":
+        return asset
+    sh = round_bf16(asset.sh) if precision == "fp16_bf16sh" else round_fp16(asset.sh)
+    return dataclasses.replace(asset, scale=round_fp16(asset.scale), rot=round_fp16(asset.rot),
+                               opacity=round_fp16(asset.opacity), sh=sh)

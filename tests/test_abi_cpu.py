@@ -37,9 +37,9 @@ def small():
     return sg.make_asset(2048, 1, 4)
 
 
-def _expect(asset, code, instances=None, flags=0):
+def _expect(asset, code, instances=None, flags=0, precision=0):
     with pytest.raises(v.V3DGError) as ei:
-        v.Scene(asset, instances, stream=0, flags=flags)
+        v.Scene(asset, instances, stream=0, flags=flags, precision=precision)
     assert ei.value.code == code, str(ei.value)
     return str(ei.value)
 
@@ -103,6 +103,29 @@ def test_rejects_sheared_or_mirrored_instances(small):
     N = sg.identity_instances(1).copy()
     N[0, 1, 3] = np.inf
     _expect(small, v.V3DG_ERR_INVALID_ARG, N)
+
+
+def test_rejects_unknown_precision(small):
+    assert "precision" in _expect(small, v.V3DG_ERR_INVALID_ARG, precision=3)
+
+
+@pytest.mark.parametrize("precision", [v.V3DG_FP16_BF16SH, v.V3DG_FP16])
+def test_rejects_values_lost_in_narrow_storage(precision):
+    a = sg.make_asset(2048, 1, 4)
+    a.scale[5, 1] = np.float32(1e-9)  # below half the smallest FP16 subnormal: rounds to 0
+    assert "FP16" in _expect(a, v.V3DG_ERR_INVALID_ARG, precision=precision)
+    a = sg.make_asset(2048, 1, 4)
+    a.scale[7, 0] = np.float32(7e4)  # beyond the FP16 maximum 65504
+    assert "FP16" in _expect(a, v.V3DG_ERR_INVALID_ARG, precision=precision)
+    a = sg.make_asset(2048, 1, 4)
+    a.opacity[9] = np.float32(2e-8)
+    assert "FP16" in _expect(a, v.V3DG_ERR_INVALID_ARG, precision=precision)
+
+
+def test_sh_overflow_only_in_fp16():
+    a = sg.make_asset(2048, 1, 4)
+    a.sh[3, 1, 2] = np.float32(1e5)
+    assert "overflows" in _expect(a, v.V3DG_ERR_INVALID_ARG, precision=v.V3DG_FP16)
 
 
 def test_rejects_too_many_tests():

@@ -238,6 +238,23 @@ def test_onaxis_anisotropic_matches_scipy_rotation(oracle_lib):
         assert got == pytest.approx([ref[0, 0], ref[0, 1], ref[1, 1]], rel=2e-6, abs=1e-6)
 
 
+def test_nonunit_quaternion_is_normalised(oracle_lib):
+    """The covariance uses the rotation of q / |q| (scipy normalises too), so
+    a quaternion stored off unit length (narrow storage) stays a rotation."""
+    f, z = 250.0, 3.0
+    rng = np.random.default_rng(17)
+    for k in range(4):
+        q = rng.standard_normal(4) * (0.5 + k)  # (x, y, z, w) for scipy
+        s = rng.uniform(0.01, 0.1, 3)
+        q32 = np.asarray(q, np.float32)
+        asset = H.single_cluster_asset([[0, 0, z]], [s], [[q32[3], q32[0], q32[1], q32[2]]], [0.5], [[[0, 0, 0]]])
+        out = oracle_lib.project(asset, sg.identity_instances(1), H.identity_camera(64, 64, f), [0])
+        Rm = Rotation.from_quat(q32.astype(np.float64)).as_matrix()
+        S = Rm @ np.diag(np.asarray(s, np.float32).astype(np.float64) ** 2) @ Rm.T
+        ref = (f / z) ** 2 * S[:2, :2]
+        assert out["cov2"][0] == pytest.approx([ref[0, 0], ref[0, 1], ref[1, 1]], rel=1e-9, abs=1e-9)
+
+
 def test_offaxis_jacobian_matches_finite_difference(oracle_lib):
     """Sigma2 = J Sigma J^T with J the derivative of the pinhole map (no guard clamp active)."""
     f = 200.0
