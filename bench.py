@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extended", action="store_true")
     ap.add_argument("--no-tiers", action="store_true", help="skip the storage-precision comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
                     help="time the frames without per-kernel events (the roofline then comes from a second pass)")
@@ -108,6 +109,95 @@ def run_frames(torch, scene, frames, img, full: bool, prof: bool):
     P = scene.collect_profile()
     ms = [a.elapsed_time(b) for a, b in ev]
     return t1 - t0, ms, P, sel
+
+
+SERVING_RUNS = [  # (label, arrival rate req/s (0: all at once), requests, graph replay)
+    ("poisson 30/s", 30.0, 90, True),
+    ("poisson 60/s", 60.0, 180, True),
+    ("poisson 120/s", 120.0, 360, True),
+    ("poisson 240/s", 240.0, 480, True),
+    ("poisson 240/s, direct launches", 240.0, 480, False),
+    ("burst", 0.0, 256, True),
+]
+MAX_OUTSTANDING = 24  # requests handed to the server at once (the rest wait in the front end)
+
+
+def serving_bench(torch, v, sg):
+    """Eight resident scenes, Poisson requests at mixed resolutions through
+    v3dg_server; latency is completion minus scheduled arrival."""
+    import collections
+
+    import numpy as np
+    t0 = time.perf_counter()
+    scn = sg.serving_scenes()
+    log("serving: 8 scenes generated in %.1f s" % (time.perf_counter() - t0))
+    scenes = [v.Scene(a, T) for a, T, _ in scn]
+    extents = [L for _, _, L in scn]
+    pool = {(w, h): [torch.empty((h, w, 4), dtype=torch.float32, device="cuda") for _ in range(MAX_OUTSTANDING)]
+            for w, h in sg.SERVING_RESOLUTIONS}
+    out = {"scenes_leaves_M": list(sg.SERVING_LEAVES_M),
+           "scene_instances": [int(T.shape[0]) for _, T, _ in scn],
+           "resident_rows": int(sum(a.n_rows for a, _, _ in scn)),
+           "runs": {}}
+    for k, (label, rate, n, graphs) in enumerate(SERVING_RUNS):
+        srv = v.Server(scenes, n_contexts=8, max_batch=16, hbm_budget_bytes=96 << 30, use_graphs=graphs)
+        warm = sg.serving_requests(48, 0.0, extents, seed=900 + k)
+        for r in warm:
+            srv.submit(r["scene"], r["cam"], r["tau"])
+            if len(srv.outputs) >= MAX_OUTSTANDING:
+                srv.poll(wait=True)
+        srv.drain()
+        st0 = srv.stats()
+        reqs = collections.deque(sg.serving_requests(n, rate, extents, seed=500 + k))
+        free = {key: list(b) for key, b in pool.items()}
+        live = {}
+        lat, qwait = [], []
+        first = last = None
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        while reqs or live:
+            now = time.perf_counter() - start
+            moved = False
+            while reqs and reqs[0]["t"] <= now and len(live) < MAX_OUTSTANDING:
+                r = reqs[0]
+                key = (r["cam"].width, r["cam"].height)
+                if not free[key]:
+                    break
+                reqs.popleft()
+                buf = free[key].pop()
+                t, _ = srv.submit(r["scene"], r["cam"], r["tau"], buf)
+                live[t] = (r, key, buf)
+                moved = True
+            for rec in srv.poll(wait=False):
+                done_t = time.perf_counter() - start
+                r, key, buf = live.pop(rec["ticket"])
+                free[key].append(buf)
+                if rec["status"] != 0:
+                    raise RuntimeError("serving request failed with %d" % rec["status"])
+                lat.append((done_t - r["t"]) * 1e3)
+                qwait.append(rec["admit_ms"] - rec["submit_ms"])
+                first = r["t"] if first is None else min(first, r["t"])
+                last = done_t if last is None else max(last, done_t)
+                moved = True
+            if not moved:
+                time.sleep(0.0002)
+        st = srv.stats()
+        srv.close()
+        batches = st["batches"] - st0["batches"]
+        run = dict(offered_rps=rate if rate > 0 else None, requests=n, frames_per_s=n / (last - first),
+                   latency_p50_ms=pct(lat, 50), latency_p99_ms=pct(lat, 99), latency_max_ms=max(lat),
+                   server_queue_p99_ms=pct(qwait, 99),
+                   mean_batch=(st["batched_requests"] - st0["batched_requests"]) / max(batches, 1),
+                   retries=st["retries"] - st0["retries"], graph_launches=st["graph_launches"] - st0["graph_launches"],
+                   graph_captures=st["graph_captures"] - st0["graph_captures"], contexts=st["contexts_live"],
+                   peak_workspace_gb=st["peak_workspace_bytes"] / 2 ** 30)
+        out["runs"][label] = run
+        log("serving %s: %.1f frames/s, p50 %.1f ms, p99 %.1f ms" % (label, run["frames_per_s"],
+                                                                      run["latency_p50_ms"], run["latency_p99_ms"]))
+    for sc in scenes:
+        sc.close()
+    del pool
+    return out
 
 
 def main():
@@ -248,6 +338,10 @@ def main():
                     sc.close()
             del im, im32
 
+    serving = None
+    if not args.no_serving and not args.profile_run and not args.quick:
+        serving = serving_bench(torch, v, sg)
+
     # per-stage timing and roofline of the dominant kernel
     stages = {k: dict(ms_total=t, launches=n, ms_per_launch=(t / n if n else None))
               for k, (t, n) in P["stages"].items()}
@@ -302,6 +396,7 @@ def main():
         "sort_hbm_gbs": (sort_b / (sort_t * 1e-3) / 1e9) if sort_t > 0 else None,
         "extended_tolerances": extended,
         "precision_tiers": tiers,
+        "serving": serving,
         "roofline": roof,
     }
 

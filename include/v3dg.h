@@ -3,14 +3,14 @@
  *
  * The library keeps one asset's cluster hierarchy and Gaussians resident in
  * HBM together with a table of rigid instances, and per frame
- *   (a) tests every (instance, cluster) footprint against a tolerance and
- *       compacts the cut (paper Sec. 3.4, "Parallel Selection on Discrete
- *       Clusters"; footprint of Sec. 3.3),
- *   (b) compacts the chosen clusters' Gaussians into a slot stream,
- *   (c) projects each Gaussian to a 2D conic and colour (3D Gaussian splat of
+ *   1. tests every (instance, cluster) footprint against a tolerance and
+ *       compacts the cut (paper Sec. 3.4, selection run in parallel over
+ *       the discrete clusters; footprint of Sec. 3.3),
+ *   2. compacts the chosen clusters' Gaussians into a slot stream,
+ *   3. projects each Gaussian to a 2D conic and colour (3D Gaussian splat of
  *       Sec. 2.1, no 2D dilation as in Sec. 5.1),
- *   (d) bins the splats to 16x16 tiles and radix-sorts 64-bit (tile, depth) keys,
- *   (e) alpha-composites every tile front to back (Sec. 2.1).
+ *   4. bins the splats to 16x16 tiles and radix-sorts 64-bit (tile, depth) keys,
+ *   5. alpha-composites every tile front to back (Sec. 2.1).
  * All device work runs as HIP kernels on the stream given at load time.
  *
  * Conventions for every entry point:
@@ -226,9 +226,78 @@ int v3dg_set_profiling(v3dg_scene *scene, int on);
 int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
 
 /* Stable LSD radix sort of n (key, value) pairs in device memory by the low
- * key_bits bits of the keys (1..64), the primitive used by (d).  Synchronises;
+ * key_bits bits of the keys (1..64), the primitive behind tile binning.  Synchronises;
  * allocates its own temporary buffers. */
 int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, void *hip_stream);
+
+/* ---- serving ----------------------------------------------------------------
+ * A server renders camera requests against several resident scenes with
+ * several frames in flight (continuous batching).  Requests queue on the host;
+ * each v3dg_server_poll retires finished frames and admits queued requests
+ * into free render contexts while the contexts' workspaces fit the HBM
+ * budget.  The requests admitted in one poll are selected together: one
+ * set-up launch, one persistent selection launch over all their (instance,
+ * cluster) tests and one expansion launch.  Each context then renders its
+ * request on its own stream, by replaying a captured HIP graph of the render
+ * chain (one per scene and image size) or by direct launches.  Frames run
+ * without host waits: launches are sized by the context's capacities and
+ * the kernels read every count from device memory; a frame that needs more
+ * keys than its context holds is detected on completion and rendered again
+ * after the context grows.  Images equal those of v3dg_select +
+ * v3dg_render bit for bit.  Single-threaded: one host thread drives a
+ * server; all its scenes must live on the current device. */
+typedef struct v3dg_server v3dg_server;
+
+typedef struct {
+    uint32_t n_contexts;        /* render contexts (frames in flight), 1..64              */
+    uint32_t max_batch;         /* requests admitted per batched selection, 1..64          */
+    uint64_t hbm_budget_bytes;  /* device memory the contexts' workspaces may hold in total */
+    uint32_t use_graphs;        /* 1: replay captured graphs, 0: launch directly          */
+    uint32_t keys_per_pixel;    /* key capacity first provisioned per pixel of an image size
+                                   not seen yet (0: 24); later frames of a size get 1.25 x the
+                                   most keys seen                                          */
+} v3dg_server_config;
+
+typedef struct {
+    uint64_t ticket;            /* from v3dg_server_submit                                */
+    int32_t status;             /* V3DG_OK or a negative error code                       */
+    uint32_t retries;           /* renders repeated after a key-capacity overflow         */
+    uint64_t n_slots, n_keys;   /* Gaussians projected and keys sorted                    */
+    double submit_ms, admit_ms, done_ms;  /* host clock (ms since server creation):
+                                             queued, admitted, completion seen by poll  */
+} v3dg_request_done;
+
+typedef struct {
+    uint64_t submitted, completed, failed, retries;
+    uint64_t batches, batched_requests;  /* selection launches and the requests they served  */
+    uint64_t graph_captures, graph_launches;
+    uint64_t workspace_bytes;            /* device memory the contexts hold now            */
+    uint64_t peak_workspace_bytes;
+    uint32_t contexts_live, queued;
+} v3dg_server_stats;
+
+/* Create a server over n_scenes loaded scenes (not owned: free the server
+ * first).  Errors: V3DG_ERR_INVALID_ARG for a bad configuration or scene,
+ * V3DG_ERR_OOM when not even one context fits the budget. */
+int v3dg_server_create(v3dg_scene *const *scenes, uint32_t n_scenes, const v3dg_server_config *cfg,
+                       v3dg_server **out);
+
+/* Queue a request: render scene `scene` from `cam` at tolerance `tau` into
+ * image_dev (caller-owned device memory, H x W x 4 FP32, untouched by the
+ * caller until the request completes).  Nothing is launched until the next
+ * poll.  *ticket identifies the request in v3dg_request_done. */
+int v3dg_server_submit(v3dg_server *srv, uint32_t scene, const v3dg_camera *cam, float tau, float *image_dev,
+                       uint64_t *ticket);
+
+/* Retire finished frames (up to cap records into done[], count in *n_done),
+ * then admit and launch queued requests.  wait != 0 blocks until at least one
+ * frame has finished when any is in flight. */
+int v3dg_server_poll(v3dg_server *srv, int wait, v3dg_request_done *done, uint32_t cap, uint32_t *n_done);
+
+int v3dg_server_get_stats(v3dg_server *srv, v3dg_server_stats *out);
+
+/* Waits for the frames in flight, then frees every context. */
+void v3dg_server_free(v3dg_server *srv);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *v3dg_last_error(void);

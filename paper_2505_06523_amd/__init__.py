@@ -69,11 +69,31 @@ class v3dg_profile(C.Structure):
                 ("pairs", C.c_uint64)]
 
 
+class v3dg_server_config(C.Structure):
+    _fields_ = [("n_contexts", C.c_uint32), ("max_batch", C.c_uint32), ("hbm_budget_bytes", C.c_uint64),
+                ("use_graphs", C.c_uint32), ("keys_per_pixel", C.c_uint32)]
+
+
+class v3dg_request_done(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("retries", C.c_uint32), ("n_slots", C.c_uint64),
+                ("n_keys", C.c_uint64), ("submit_ms", C.c_double), ("admit_ms", C.c_double),
+                ("done_ms", C.c_double)]
+
+
+class v3dg_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("retries", C.c_uint64), ("batches", C.c_uint64), ("batched_requests", C.c_uint64),
+                ("graph_captures", C.c_uint64), ("graph_launches", C.c_uint64),
+                ("workspace_bytes", C.c_uint64), ("peak_workspace_bytes", C.c_uint64),
+                ("contexts_live", C.c_uint32), ("queued", C.c_uint32)]
+
+
 EXPORTS = [
     "v3dg_load_hierarchy", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
     "v3dg_set_sort_mode", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs", "v3dg_last_error",
+    "v3dg_server_create", "v3dg_server_submit", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
 ]
 
 _lib = None
@@ -108,6 +128,11 @@ def lib():
         "v3dg_collect_profile": ([P, P], I),
         "v3dg_sort_pairs": ([P, P, U64, U32, P], I),
         "v3dg_last_error": ([], C.c_char_p),
+        "v3dg_server_create": ([P, U32, P, P], I),
+        "v3dg_server_submit": ([P, U32, P, C.c_float, P, P], I),
+        "v3dg_server_poll": ([P, I, P, U32, P], I),
+        "v3dg_server_get_stats": ([P, P], I),
+        "v3dg_server_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -241,6 +266,36 @@ def v3dg_collect_profile(scene) -> dict:
 
 def v3dg_sort_pairs(keys_ptr, vals_ptr, n, key_bits, hip_stream):
     _check(lib().v3dg_sort_pairs(keys_ptr, vals_ptr, int(n), int(key_bits), hip_stream))
+
+
+def v3dg_server_create(scene_handles, cfg: v3dg_server_config):
+    arr = (C.c_void_p * len(scene_handles))(*[h.value for h in scene_handles])
+    out = C.c_void_p()
+    _check(lib().v3dg_server_create(arr, len(scene_handles), C.byref(cfg), C.byref(out)))
+    return out
+
+
+def v3dg_server_submit(srv, scene: int, cam: v3dg_camera, tau: float, image_ptr) -> int:
+    t = C.c_uint64()
+    _check(lib().v3dg_server_submit(srv, int(scene), C.byref(cam), float(tau), image_ptr, C.byref(t)))
+    return t.value
+
+
+def v3dg_server_poll(srv, wait: bool, cap: int = 256) -> list:
+    arr = (v3dg_request_done * cap)()
+    n = C.c_uint32()
+    _check(lib().v3dg_server_poll(srv, int(bool(wait)), arr, cap, C.byref(n)))
+    return [{name: getattr(arr[i], name) for name, _ in v3dg_request_done._fields_} for i in range(n.value)]
+
+
+def v3dg_server_get_stats(srv) -> dict:
+    st = v3dg_server_stats()
+    _check(lib().v3dg_server_get_stats(srv, C.byref(st)))
+    return {name: getattr(st, name) for name, _ in v3dg_server_stats._fields_}
+
+
+def v3dg_server_free(srv):
+    lib().v3dg_server_free(srv)
 
 
 # ---- convenience layer -----------------------------------------------------------
@@ -414,3 +469,58 @@ def sort_pairs(keys, vals, key_bits: int, stream=None):
         raise ValueError("keys and vals must be contiguous CUDA tensors")
     st = current_stream_ptr() if stream is None else C.c_void_p(stream)
     v3dg_sort_pairs(C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()), keys.numel(), key_bits, st)
+
+
+class Server:
+    """Continuous-batching renderer over resident scenes (see v3dg_server_*).
+
+    submit() queues a request and keeps the output tensor alive until its
+    completion record comes back from poll()."""
+
+    def __init__(self, scenes, n_contexts: int = 8, max_batch: int = 16, hbm_budget_bytes: int = 64 << 30,
+                 use_graphs: bool = True, keys_per_pixel: int = 0):
+        cfg = v3dg_server_config()
+        cfg.n_contexts, cfg.max_batch = int(n_contexts), int(max_batch)
+        cfg.hbm_budget_bytes, cfg.use_graphs = int(hbm_budget_bytes), int(bool(use_graphs))
+        cfg.keys_per_pixel = int(keys_per_pixel)
+        self.scenes = list(scenes)  # keeps the scenes alive while the server runs
+        self.handle = None
+        self.handle = v3dg_server_create([sc.handle for sc in self.scenes], cfg)
+        self.outputs = {}
+
+    def submit(self, scene: int, cam, tau: float, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device="cuda")
+        if (not out.is_cuda or out.dtype != torch.float32 or not out.is_contiguous()
+                or tuple(out.shape) != (int(cam.height), int(cam.width), 4)):
+            raise ValueError("image must be a contiguous float32 CUDA tensor of shape (H, W, 4)")
+        t = v3dg_server_submit(self.handle, scene, make_camera(cam), tau, C.c_void_p(out.data_ptr()))
+        self.outputs[t] = out
+        return t, out
+
+    def poll(self, wait: bool = False) -> list:
+        recs = v3dg_server_poll(self.handle, wait)
+        for r in recs:
+            r["image"] = self.outputs.pop(r["ticket"], None)
+        return recs
+
+    def drain(self) -> list:
+        out = []
+        while self.outputs:
+            out.extend(self.poll(wait=True))
+        return out
+
+    def stats(self) -> dict:
+        return v3dg_server_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            v3dg_server_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,4 +1,4 @@
-// (e) front-to-back alpha compositing (paper Sec. 2.1: the splats covering a
+// Front-to-back alpha compositing (paper Sec. 2.1: the splats covering a
 // pixel are blended in depth order), one 256-thread workgroup per 16x16 tile.
 //
 // Each wavefront owns one 8x8 quarter of the tile, one pixel per lane.  A
@@ -180,9 +180,11 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t per_xcd) { return (blockId
 // ---------------------------------------------------------------------------
 constexpr int kPlanThreads = 1024;
 
+// A plan that would need more than max_chunks chunks is dropped (chunk count
+// 0): every tile is then blended whole by its pass-1 workgroup.
 __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *__restrict__ ranges, uint32_t n_tiles,
                                                                   uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
-                                                                  uint32_t *__restrict__ counters)
+                                                                  uint32_t *__restrict__ counters, uint32_t max_chunks)
 {
     __shared__ uint32_t s_w[kPlanThreads / kWave][2];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *_
     uint32_t nch = 0, nit = 0;
     for (uint32_t t = t0; t < t1; ++t) {
         const uint2 r = ranges[t];
-        const uint32_t L = r.y - r.x;
+        const uint32_t L = r.y > r.x ? r.y - r.x : 0u;
         if (L > (uint32_t)kChunk) {
             const uint32_t m = (L + kChunk - 1) / kChunk;
             nch += m;
@@ -222,10 +224,11 @@ __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *_
         ta += s_w[w][0];
         tb += s_w[w][1];
     }
+    const bool fits = ta <= max_chunks;
     uint32_t ca = oa + a - nch, cb = ob + b - nit;
-    for (uint32_t t = t0; t < t1; ++t) {
+    for (uint32_t t = t0; t < t1 && fits; ++t) {
         const uint2 r = ranges[t];
-        const uint32_t L = r.y - r.x;
+        const uint32_t L = r.y > r.x ? r.y - r.x : 0u;
         if (L > (uint32_t)kChunk) {
             const uint32_t m = (L + kChunk - 1) / kChunk;
             cbase[t] = ca;
@@ -235,31 +238,35 @@ __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *_
         }
     }
     if (tid == kPlanThreads - 1) {
-        counters[kRenChunks] = ta;
-        counters[kRenItems] = tb;
+        counters[kRenChunks] = fits ? ta : 0u;
+        counters[kRenItems] = fits ? tb : 0u;
     }
 }
 
 // ---------------------------------------------------------------------------
 // pass 1: every tile, up to its first kChunk keys
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlendThreads) blend_kernel(CamArgs cam, const float4 *__restrict__ splat,
+__global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
+                                                              const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ cbase,
-                                                              float4 *__restrict__ scratch,
-                                                              float4 *__restrict__ image, uint32_t per_xcd,
+                                                              const uint32_t *__restrict__ counters,
+                                                              float4 *__restrict__ scratch, uint32_t per_xcd,
                                                               unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const uint32_t tile = xcd_tile(per_xcd);
+    const CamArgs &cam = fd->cam;
+    float4 *image = reinterpret_cast<float4 *>(fd->image);
     if (tile >= cam.tiles_x * cam.tiles_y) return;
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint2 rg = ranges[tile];
     Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u};
-    const bool long_list = rg.y - rg.x > (uint32_t)kChunk;
-    blend_range(rg.x, long_list ? rg.x + kChunk : rg.y, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+    const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
+    const bool long_list = end - rg.x > (uint32_t)kChunk && counters[kRenChunks] != 0u;
+    blend_range(rg.x, long_list ? rg.x + kChunk : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
     if (long_list)  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cbase[tile] * kBlendThreads + g.pix] =
             make_float4(px.cr, px.cg, px.cb, px.active ? px.T : -px.T);
@@ -271,7 +278,8 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(CamArgs cam, const
 // ---------------------------------------------------------------------------
 // pass 2: chunks 1.. of long tiles, in parallel, each from T = 1
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlendThreads) chunk_kernel(CamArgs cam, const float4 *__restrict__ splat,
+__global__ void __launch_bounds__(kBlendThreads) chunk_kernel(const FrameDev *__restrict__ fd,
+                                                              const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ cbase,
@@ -281,22 +289,26 @@ __global__ void __launch_bounds__(kBlendThreads) chunk_kernel(CamArgs cam, const
                                                               unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
-    const uint32_t it = blockIdx.x;
-    if (it >= counters[kRenItems]) return;
+    const uint32_t n_items = counters[kRenItems];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint2 item = items[it];
-    const uint32_t tile = item.x, c = item.y;
-    const TileGeo g = tile_geo(cam, tile, wid, lane);
-    const uint2 rg = ranges[tile];
-    const uint64_t base = cbase[tile];
-    const float4 s0 = scratch[base * kBlendThreads + g.pix];
-    Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u};
-    const bool was = px.active;
-    const uint32_t b = rg.x + c * kChunk;
-    blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
-    scratch[(base + c) * kBlendThreads + g.pix] =
-        make_float4(px.cr, px.cg, px.cb, (was && !px.active) ? -px.T : px.T);
-    count_pairs(px, lane, pairs);
+    const CamArgs &cam = fd->cam;
+    // one workgroup per item (the grid covers the bound on items)
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint2 item = items[it];
+        const uint32_t tile = item.x, c = item.y;
+        const TileGeo g = tile_geo(cam, tile, wid, lane);
+        const uint2 rg = ranges[tile];
+        const uint64_t base = cbase[tile];
+        const float4 s0 = scratch[base * kBlendThreads + g.pix];
+        Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u};
+        const bool was = px.active;
+        const uint32_t b = rg.x + c * kChunk;
+        blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        scratch[(base + c) * kBlendThreads + g.pix] =
+            make_float4(px.cr, px.cg, px.cb, (was && !px.active) ? -px.T : px.T);
+        count_pairs(px, lane, pairs);
+        __syncthreads();  // the next item reuses the staged batch
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -304,19 +316,21 @@ __global__ void __launch_bounds__(kBlendThreads) chunk_kernel(CamArgs cam, const
 // ---------------------------------------------------------------------------
 constexpr uint32_t kNone = 0xffffffffu;
 
-__global__ void __launch_bounds__(kBlendThreads) fold_kernel(CamArgs cam, const uint2 *__restrict__ ranges,
+__global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__restrict__ fd,
+                                                             const uint2 *__restrict__ ranges,
                                                              const uint32_t *__restrict__ cbase,
                                                              float4 *__restrict__ scratch, uint32_t *__restrict__ pend,
                                                              uint32_t *__restrict__ need, uint2 *__restrict__ rewalk,
-                                                             uint32_t *counters, float4 *__restrict__ image,
-                                                             uint32_t per_xcd)
+                                                             uint32_t *counters, uint32_t per_xcd)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const uint32_t tile = xcd_tile(per_xcd);
+    const CamArgs &cam = fd->cam;
+    float4 *image = reinterpret_cast<float4 *>(fd->image);
     if (tile >= cam.tiles_x * cam.tiles_y) return;
     const uint2 rg = ranges[tile];
-    const uint32_t L = rg.y - rg.x;
-    if (L <= (uint32_t)kChunk) return;
+    const uint32_t L = rg.y > rg.x ? rg.y - rg.x : 0u;
+    if (L <= (uint32_t)kChunk || counters[kRenChunks] == 0u) return;
     const uint32_t m = (L + kChunk - 1) / kChunk;
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint64_t base = cbase[tile];
@@ -357,7 +371,8 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(CamArgs cam, const 
 // ---------------------------------------------------------------------------
 // pass 4: walk again, with the stop rule, each chunk that holds a stop
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(CamArgs cam, const float4 *__restrict__ splat,
+__global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *__restrict__ fd,
+                                                               const float4 *__restrict__ splat,
                                                                const uint32_t *__restrict__ vals,
                                                                const uint2 *__restrict__ ranges,
                                                                const uint32_t *__restrict__ cbase,
@@ -365,49 +380,55 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(CamArgs cam, cons
                                                                const uint32_t *__restrict__ pend,
                                                                const uint2 *__restrict__ rewalk,
                                                                const uint32_t *__restrict__ counters,
-                                                               float4 *__restrict__ image,
                                                                unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
-    const uint32_t it = blockIdx.x;
-    if (it >= counters[kRenRewalk]) return;
+    const uint32_t n_items = counters[kRenRewalk];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint2 item = rewalk[it];
-    const uint32_t tile = item.x, c = item.y;
-    const TileGeo g = tile_geo(cam, tile, wid, lane);
-    const uint2 rg = ranges[tile];
-    const uint64_t base = cbase[tile];
-    const bool mine = pend[base * kBlendThreads + g.pix] == c;
-    const float4 st = scratch[base * kBlendThreads + g.pix];
-    Pix px{st.w, st.x, st.y, st.z, mine, 0u};
-    const uint32_t b = rg.x + c * kChunk;
-    blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
-    // a pixel that, through rounding of the folded products, does not stop in
-    // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
-    if (mine) write_pixel(cam, g, px, image);
-    count_pairs(px, lane, pairs);
+    const CamArgs &cam = fd->cam;
+    float4 *image = reinterpret_cast<float4 *>(fd->image);
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint2 item = rewalk[it];
+        const uint32_t tile = item.x, c = item.y;
+        const TileGeo g = tile_geo(cam, tile, wid, lane);
+        const uint2 rg = ranges[tile];
+        const uint64_t base = cbase[tile];
+        const bool mine = pend[base * kBlendThreads + g.pix] == c;
+        const float4 st = scratch[base * kBlendThreads + g.pix];
+        Pix px{st.w, st.x, st.y, st.z, mine, 0u};
+        const uint32_t b = rg.x + c * kChunk;
+        blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        // a pixel that, through rounding of the folded products, does not stop in
+        // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
+        if (mine) write_pixel(cam, g, px, image);
+        count_pairs(px, lane, pairs);
+        __syncthreads();  // the next item reuses the staged batch
+    }
 }
 
-void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals, const uint2 *ranges,
-                  uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
-                  float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk, float *image,
+// max_items / max_chunks bound the chunk work items and chunks (grids are
+// capped and loop over the device-side counts)
+void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat, const uint32_t *vals,
+                  const uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items,
+                  uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk,
                   unsigned long long *pairs)
 {
-    const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
     const uint32_t per_xcd = (n_tiles + 7) / 8;
-    float4 *img = reinterpret_cast<float4 *>(image);
+    constexpr uint64_t kMaxGrid = 1u << 20;  // beyond, workgroups loop over further items
     if (max_items > 0)
         hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ranges, n_tiles, cbase, items,
-                           counters);
-    hipLaunchKernelGGL(blend_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, cam, splat, vals, ranges, cbase,
-                       scratch, img, per_xcd, pairs);
+                           counters, (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull));
+    hipLaunchKernelGGL(blend_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+                       counters, scratch, per_xcd, pairs);
     if (max_items > 0) {
-        hipLaunchKernelGGL(chunk_kernel, dim3((uint32_t)max_items), dim3(kBlendThreads), 0, st, cam, splat, vals,
-                           ranges, cbase, items, counters, scratch, pairs);
-        hipLaunchKernelGGL(fold_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, cam, ranges, cbase, scratch,
-                           pend, need, rewalk, counters, img, per_xcd);
-        hipLaunchKernelGGL(rewalk_kernel, dim3((uint32_t)max_chunks), dim3(kBlendThreads), 0, st, cam, splat, vals,
-                           ranges, cbase, scratch, pend, rewalk, counters, img, pairs);
+        const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
+        const uint32_t gc = (uint32_t)(max_chunks < kMaxGrid ? max_chunks : kMaxGrid);
+        hipLaunchKernelGGL(chunk_kernel, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, items,
+                           counters, scratch, pairs);
+        hipLaunchKernelGGL(fold_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch,
+                           pend, need, rewalk, counters, per_xcd);
+        hipLaunchKernelGGL(rewalk_kernel, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+                           scratch, pend, rewalk, counters, pairs);
     }
 }
 

@@ -1,4 +1,4 @@
-// (c) projection of every slot's Gaussian to a 2D splat.
+// Projection of every slot's Gaussian to a 2D splat.
 //
 // A 3D Gaussian (p, s, q, o, SH colour) is splatted to the image plane with
 // the EWA local affine approximation and no 2D dilation (paper Sec. 2.1 and
@@ -135,13 +135,14 @@ __device__ __forceinline__ float load_sh(const Attribs &at, int plane, uint32_t 
 }
 
 template <int D, int P>
-__global__ void __launch_bounds__(256) project_kernel(CamArgs cam, Attribs at,
+__global__ void __launch_bounds__(256) project_kernel(const FrameDev *__restrict__ fd, Attribs at,
                                                       const uint32_t *__restrict__ slot_row,
                                                       const uint32_t *__restrict__ slot_inst,
                                                       const uint32_t *__restrict__ n_dev,
                                                       const InstRec *__restrict__ itab, ProjectOut out)
 {
     const uint64_t ps = at.ps;
+    const CamArgs cam = fd->cam;
     constexpr int NCOEF = (D + 1) * (D + 1);
     const uint32_t n = *n_dev;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -281,7 +282,7 @@ __global__ void __launch_bounds__(256) project_kernel(CamArgs cam, Attribs at,
 }
 
 template <int D>
-static void launch_project_d(hipStream_t st, dim3 g, dim3 b, const CamArgs &cam, const Attribs &at, int precision,
+static void launch_project_d(hipStream_t st, dim3 g, dim3 b, const FrameDev *cam, const Attribs &at, int precision,
                              const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_dev,
                              const InstRec *itab, const ProjectOut &out)
 {
@@ -292,7 +293,7 @@ static void launch_project_d(hipStream_t st, dim3 g, dim3 b, const CamArgs &cam,
     }
 }
 
-void launch_project(hipStream_t st, const CamArgs &cam, const Attribs &attr, int precision, int sh_degree,
+void launch_project(hipStream_t st, const FrameDev *cam, const Attribs &attr, int precision, int sh_degree,
                     const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
                     uint64_t max_slots, const InstRec *itab, ProjectOut out)
 {

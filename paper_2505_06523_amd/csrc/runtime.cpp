@@ -4,11 +4,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/v3dg.h"
@@ -140,37 +145,16 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
-struct v3dg_selection {
-    v3dg_scene *scene = nullptr;
-    uint64_t cap_tests = 0, cap_slots = 0, n_parts = 0;
-    uint32_t *gid = nullptr;
-    uint32_t *slot_off = nullptr;
-    uint32_t *clear_block = nullptr;  // counters (kSelCounters u32) + look-back words
-    uint32_t *counters = nullptr;
-    uint64_t *status = nullptr;
-    uint32_t *slot_row = nullptr;
-    uint32_t *slot_inst = nullptr;
-};
-
-struct v3dg_scene {
+// Stream, frame state and render workspace of one frame in flight: the one
+// every scene owns (v3dg_render) or one context of a server.
+struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    uint32_t NC = 0, n_rows = 0, sh_degree = 0, n_inst = 0;
-    uint64_t plane_stride = 0;
-    uint32_t precision = V3DG_FP32;
-    float *pos_planes = nullptr;  // 3 FP32 planes
-    void *geo_planes = nullptr;   // 8 planes, FP32 or FP16
-    void *sh_planes = nullptr;    // 3 (d+1)^2 planes, FP32, BF16 or FP16
-    float4 *self_sph = nullptr, *par_sph = nullptr;
-    uint2 *rowinfo = nullptr;
-    double *T_dev = nullptr;
-    float *scale_dev = nullptr;
+    FrameDev *fdev = nullptr;   // camera, image and sort epoch read by the kernels
+    uint64_t epoch_host = 0;    // mirror of fdev->epoch
     InstRec *itab = nullptr;
-    uint64_t maxcut_rows = 0;
-    std::vector<uint32_t> leaf_ids;
-    std::vector<uint32_t> h_count;
-    // render workspace
-    uint64_t cap_slots = 0;
+    uint32_t itab_cap = 0;
+    uint64_t ws_slots = 0;
     float4 *splat = nullptr;
     BinRec *bin = nullptr;
     float *depth = nullptr;
@@ -179,7 +163,6 @@ struct v3dg_scene {
     uint32_t *offsets = nullptr;
     uint32_t *dkey[2] = {nullptr, nullptr};
     uint32_t *dval[2] = {nullptr, nullptr};
-    int sort_mode = V3DG_SORT_DEPTH_FIRST;
     uint32_t *rclear = nullptr;  // counters + scan look-back + tile ranges, cleared every frame
     uint64_t rclear_words = 0;
     uint64_t scan_parts = 0;
@@ -199,11 +182,10 @@ struct v3dg_scene {
     uint32_t *need = nullptr;      // per chunk: walk it again
     uint2 *rewalk = nullptr;       // (tile, chunk) to walk again
     uint64_t cap_chunks = 0;
-    uint32_t epoch = 0;
     uint32_t *pinned = nullptr;
     v3dg_frame_stats last{};
     int last_buf = 0;
-    v3dg_selection *full = nullptr;
+    int sort_mode = V3DG_SORT_DEPTH_FIRST;
     bool profiling = false;
     v3dg_profile acc{};
     unsigned long long *pairs_dev = nullptr;
@@ -211,14 +193,45 @@ struct v3dg_scene {
     std::vector<hipEvent_t> ev_pool;
 };
 
+struct v3dg_selection {
+    v3dg_scene *scene = nullptr;
+    uint64_t cap_tests = 0, cap_slots = 0, n_parts = 0;
+    uint32_t *gid = nullptr;
+    uint32_t *slot_off = nullptr;
+    uint32_t *clear_block = nullptr;  // counters (kSelCounters u32) + look-back words
+    uint32_t *counters = nullptr;
+    uint64_t *status = nullptr;
+    uint32_t *slot_row = nullptr;
+    uint32_t *slot_inst = nullptr;
+};
+
+struct v3dg_scene : Ctx {
+    uint32_t NC = 0, n_rows = 0, sh_degree = 0, n_inst = 0;
+    uint64_t plane_stride = 0;
+    uint32_t precision = V3DG_FP32;
+    float *pos_planes = nullptr;  // 3 FP32 planes
+    void *geo_planes = nullptr;   // 8 planes, FP32 or FP16
+    void *sh_planes = nullptr;    // 3 (d+1)^2 planes, FP32, BF16 or FP16
+    float4 *self_sph = nullptr, *par_sph = nullptr;
+    uint2 *rowinfo = nullptr;
+    double *T_dev = nullptr;
+    float *scale_dev = nullptr;
+    uint64_t maxcut_rows = 0;
+    uint64_t cap_slots = 0;       // bound on the slots of any selection
+    std::vector<uint32_t> leaf_ids;
+    std::vector<uint32_t> h_count;
+    v3dg_selection *full = nullptr;
+    Attribs attribs() const { return Attribs{pos_planes, geo_planes, sh_planes, plane_stride}; }
+};
+
 namespace {
 
 // ---- profiling --------------------------------------------------------------
 struct Stage {
-    v3dg_scene *s;
+    Ctx *s;
     int stage;
     hipEvent_t b = nullptr;
-    Stage(v3dg_scene *sc, int st) : s(sc), stage(st)
+    Stage(Ctx *sc, int st) : s(sc), stage(st)
     {
         if (!s->profiling) return;
         hipEvent_t a = take();
@@ -330,11 +343,11 @@ void sel_release(v3dg_selection *s)
     s->status = nullptr;
 }
 
-int sel_alloc(v3dg_scene *sc, v3dg_selection *s)
+// buffers for selections of up to cap_tests tests and cap_slots slots
+int sel_alloc_caps(v3dg_selection *s, uint64_t cap_tests, uint64_t cap_slots, hipStream_t st)
 {
-    s->scene = sc;
-    s->cap_tests = (uint64_t)sc->NC * sc->n_inst;
-    s->cap_slots = sc->cap_slots;
+    s->cap_tests = cap_tests;
+    s->cap_slots = cap_slots;
     s->n_parts = (s->cap_tests + kSelPart - 1) / kSelPart;
     int rc;
     if ((rc = dev_alloc(&s->gid, s->cap_tests))) return rc;
@@ -344,135 +357,401 @@ int sel_alloc(v3dg_scene *sc, v3dg_selection *s)
     s->status = reinterpret_cast<uint64_t *>(s->clear_block + kSelCounters);
     if ((rc = dev_alloc(&s->slot_row, s->cap_slots))) return rc;
     if ((rc = dev_alloc(&s->slot_inst, s->cap_slots))) return rc;
-    HIP_TRY(hipMemsetAsync(s->clear_block, 0, sizeof(uint32_t) * kSelCounters, sc->stream));
+    HIP_TRY(hipMemsetAsync(s->clear_block, 0, sizeof(uint32_t) * kSelCounters, st));
     return V3DG_OK;
 }
 
-// ---- render workspace ----------------------------------------------------------------
-int ensure_status(v3dg_scene *s, uint64_t parts);
-
-int ensure_slots(v3dg_scene *s)
+int sel_alloc(v3dg_scene *sc, v3dg_selection *s)
 {
-    if (s->splat) return V3DG_OK;
-    const uint64_t n = s->cap_slots;
+    s->scene = sc;
+    return sel_alloc_caps(s, (uint64_t)sc->NC * sc->n_inst, sc->cap_slots, sc->stream);
+}
+
+// one selection request of scene sc into selection buffers sel
+SelReq make_selreq(const v3dg_scene *sc, const InstRec *itab, float K, float tau, v3dg_selection *sel)
+{
+    SelReq q{};
+    q.self_sph = sc->self_sph;
+    q.par_sph = sc->par_sph;
+    q.rowinfo = sc->rowinfo;
+    q.itab = itab;
+    q.gid = sel->gid;
+    q.slot_off = sel->slot_off;
+    q.status = sel->status;
+    q.counters = sel->counters;
+    q.slot_row = sel->slot_row;
+    q.slot_inst = sel->slot_inst;
+    q.NC = sc->NC;
+    q.n_inst = sc->n_inst;
+    q.K = K;
+    q.tau = tau;
+    q.part_begin = 0;
+    q.nparts = (uint32_t)(((uint64_t)sc->NC * sc->n_inst + kSelPart - 1) / kSelPart);
+    return q;
+}
+
+// ---- render contexts --------------------------------------------------------------
+int ctx_init(Ctx *c, int device, hipStream_t stream)
+{
+    c->device = device;
+    c->stream = stream;
     int rc;
-    if ((rc = dev_alloc(&s->splat, 3 * n))) return rc;
-    if ((rc = dev_alloc(&s->bin, n))) return rc;
-    if ((rc = dev_alloc(&s->depth, n))) return rc;
-    if ((rc = dev_alloc(&s->rect, n))) return rc;
-    if ((rc = dev_alloc(&s->tiles, n))) return rc;
-    if ((rc = dev_alloc(&s->offsets, n))) return rc;
-    for (int b = 0; b < 2; ++b) {
-        if ((rc = dev_alloc(&s->dkey[b], n))) return rc;
-        if ((rc = dev_alloc(&s->dval[b], n))) return rc;
+    if ((rc = dev_alloc(&c->fdev, 1))) return rc;
+    if ((rc = dev_alloc(&c->pairs_dev, 1))) return rc;
+    HIP_TRY(hipMemset(c->fdev, 0, sizeof(FrameDev)));
+    HIP_TRY(hipMemset(c->pairs_dev, 0, sizeof(unsigned long long)));
+    if (hipHostMalloc((void **)&c->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        return fail(V3DG_ERR_OOM, "pinned allocation failed");
     }
-    s->scan_parts = (n + kScanPart - 1) / kScanPart;
-    if ((rc = ensure_status(s, (n + kSortPart - 1) / kSortPart))) return rc;
     return V3DG_OK;
 }
 
-int ensure_tiles(v3dg_scene *s, uint32_t n_tiles)
+void ctx_free_slots(Ctx *c)
 {
-    if (s->rclear && n_tiles <= s->tiles_cap) return V3DG_OK;
-    dev_free(s->rclear);
-    s->tiles_cap = std::max<uint32_t>(n_tiles, 8160);
-    s->rclear_words = (uint64_t)kRenCounters + 2 * s->scan_parts + 2ull * s->tiles_cap;
+    dev_free(c->splat);
+    dev_free(c->bin);
+    dev_free(c->depth);
+    for (int b = 0; b < 2; ++b) {
+        dev_free(c->dkey[b]);
+        dev_free(c->dval[b]);
+    }
+    dev_free(c->rect);
+    dev_free(c->tiles);
+    dev_free(c->offsets);
+    dev_free(c->rclear);
+    c->ws_slots = 0;
+    c->tiles_cap = 0;
+}
+
+void ctx_release(Ctx *c)
+{
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    ctx_free_slots(c);
+    dev_free(c->fdev);
+    dev_free(c->itab);
+    for (int b = 0; b < 2; ++b) {
+        dev_free(c->keys[b]);
+        dev_free(c->vals[b]);
+    }
+    dev_free(c->sort_status);
+    dev_free(c->pairs_dev);
+    dev_free(c->cbase);
+    dev_free(c->items);
+    dev_free(c->scratch);
+    dev_free(c->pend);
+    dev_free(c->need);
+    dev_free(c->rewalk);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    for (auto &r : c->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    c->prof.clear();
+    c->ev_pool.clear();
+}
+
+int ensure_status(Ctx *c, uint64_t parts);
+
+int ensure_itab(Ctx *c, uint32_t n)
+{
+    if (n <= c->itab_cap) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    dev_free(c->itab);
     int rc;
-    if ((rc = dev_alloc(&s->rclear, s->rclear_words))) return rc;
-    s->rcounters = s->rclear;
-    s->scan_status = reinterpret_cast<uint64_t *>(s->rclear + kRenCounters);
-    s->ranges = reinterpret_cast<uint2 *>(s->rclear + kRenCounters + 2 * s->scan_parts);
-    dev_free(s->cbase);
-    if ((rc = dev_alloc(&s->cbase, s->tiles_cap))) return rc;
+    if ((rc = dev_alloc(&c->itab, n))) return rc;
+    c->itab_cap = n;
     return V3DG_OK;
 }
 
-int ensure_status(v3dg_scene *s, uint64_t parts)
+int ensure_slots(Ctx *c, uint64_t n)
 {
-    if (parts <= s->sort_status_parts) return V3DG_OK;
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    dev_free(s->sort_status);
+    if (n <= c->ws_slots && c->splat) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    ctx_free_slots(c);
+    int rc;
+    if ((rc = dev_alloc(&c->splat, 3 * n))) return rc;
+    if ((rc = dev_alloc(&c->bin, n))) return rc;
+    if ((rc = dev_alloc(&c->depth, n))) return rc;
+    if ((rc = dev_alloc(&c->rect, n))) return rc;
+    if ((rc = dev_alloc(&c->tiles, n))) return rc;
+    if ((rc = dev_alloc(&c->offsets, n))) return rc;
+    for (int b = 0; b < 2; ++b) {
+        if ((rc = dev_alloc(&c->dkey[b], n))) return rc;
+        if ((rc = dev_alloc(&c->dval[b], n))) return rc;
+    }
+    c->ws_slots = n;
+    c->scan_parts = (n + kScanPart - 1) / kScanPart;
+    if ((rc = ensure_status(c, (n + kSortPart - 1) / kSortPart))) return rc;
+    return V3DG_OK;
+}
+
+int ensure_tiles(Ctx *c, uint32_t n_tiles)
+{
+    if (c->rclear && n_tiles <= c->tiles_cap) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    dev_free(c->rclear);
+    c->tiles_cap = std::max<uint32_t>(n_tiles, 8160);
+    c->rclear_words = (uint64_t)kRenCounters + 2 * c->scan_parts + 2ull * c->tiles_cap;
+    int rc;
+    if ((rc = dev_alloc(&c->rclear, c->rclear_words))) return rc;
+    c->rcounters = c->rclear;
+    c->scan_status = reinterpret_cast<uint64_t *>(c->rclear + kRenCounters);
+    c->ranges = reinterpret_cast<uint2 *>(c->rclear + kRenCounters + 2 * c->scan_parts);
+    dev_free(c->cbase);
+    if ((rc = dev_alloc(&c->cbase, c->tiles_cap))) return rc;
+    return V3DG_OK;
+}
+
+int ensure_status(Ctx *c, uint64_t parts)
+{
+    if (parts <= c->sort_status_parts) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    dev_free(c->sort_status);
     const uint64_t np = std::max<uint64_t>(parts + parts / 2, 256);
     int rc;
-    if ((rc = dev_alloc(&s->sort_status, np * kRadix))) return rc;
-    HIP_TRY(hipMemsetAsync(s->sort_status, 0, np * kRadix * sizeof(uint64_t), s->stream));
-    s->sort_status_parts = np;
-    s->epoch = 0;
+    if ((rc = dev_alloc(&c->sort_status, np * kRadix))) return rc;
+    HIP_TRY(hipMemsetAsync(c->sort_status, 0, np * kRadix * sizeof(uint64_t), c->stream));
+    c->sort_status_parts = np;
     return V3DG_OK;
 }
 
-int ensure_chunks(v3dg_scene *s, uint64_t K, uint32_t n_tiles)
+// chunk buffers for frames of up to K keys over n_tiles tiles
+int ensure_chunks(Ctx *c, uint64_t K, uint32_t n_tiles)
 {
     const uint64_t need = (K + kChunk - 1) / kChunk + n_tiles;
-    if (need <= s->cap_chunks) return V3DG_OK;
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    dev_free(s->items);
-    dev_free(s->scratch);
-    dev_free(s->pend);
-    dev_free(s->need);
-    dev_free(s->rewalk);
+    if (need <= c->cap_chunks) return V3DG_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    dev_free(c->items);
+    dev_free(c->scratch);
+    dev_free(c->pend);
+    dev_free(c->need);
+    dev_free(c->rewalk);
     const uint64_t cap = need + need / 2;
     int rc;
-    if ((rc = dev_alloc(&s->items, cap))) return rc;
-    if ((rc = dev_alloc(&s->scratch, cap * 256))) return rc;
-    if ((rc = dev_alloc(&s->pend, cap * 256))) return rc;
-    if ((rc = dev_alloc(&s->need, cap))) return rc;
-    if ((rc = dev_alloc(&s->rewalk, cap))) return rc;
-    s->cap_chunks = cap;
+    if ((rc = dev_alloc(&c->items, cap))) return rc;
+    if ((rc = dev_alloc(&c->scratch, cap * 256))) return rc;
+    if ((rc = dev_alloc(&c->pend, cap * 256))) return rc;
+    if ((rc = dev_alloc(&c->need, cap))) return rc;
+    if ((rc = dev_alloc(&c->rewalk, cap))) return rc;
+    c->cap_chunks = cap;
     return V3DG_OK;
 }
 
-int ensure_keys(v3dg_scene *s, uint64_t K)
+// key buffers for at least K keys (exact_cap: exactly max(K, 1))
+int ensure_keys(Ctx *c, uint64_t K, bool exact_cap = false)
 {
     const uint64_t parts = (K + kSortPart - 1) / kSortPart;
-    if (K > s->cap_keys) {
-        HIP_TRY(hipStreamSynchronize(s->stream));
+    if (K > c->cap_keys) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
         for (int b = 0; b < 2; ++b) {
-            dev_free(s->keys[b]);
-            dev_free(s->vals[b]);
+            dev_free(c->keys[b]);
+            dev_free(c->vals[b]);
         }
-        uint64_t cap = std::max<uint64_t>(K + K / 2, 1u << 20);
+        uint64_t cap = exact_cap ? std::max<uint64_t>(K, 1) : std::max<uint64_t>(K + K / 2, 1u << 20);
         cap = std::min<uint64_t>(cap, 0xffffffffull);
         int rc;
         for (int b = 0; b < 2; ++b) {
-            if ((rc = dev_alloc(&s->keys[b], cap))) return rc;
-            if ((rc = dev_alloc(&s->vals[b], cap))) return rc;
+            if ((rc = dev_alloc(&c->keys[b], cap))) return rc;
+            if ((rc = dev_alloc(&c->vals[b], cap))) return rc;
         }
-        s->cap_keys = cap;
+        c->cap_keys = cap;
     }
-    return ensure_status(s, parts);
+    return ensure_status(c, parts);
 }
 
-uint32_t next_epoch(v3dg_scene *s)
+// Every frame takes kEpochsPerFrame look-back epochs; before the 30-bit field
+// wraps, the look-back words and the epoch start again from zero.
+void epoch_advance(Ctx *c)
 {
-    if (++s->epoch >= (1u << 30)) {  // wrap: old words could alias new epochs
-        (void)hipMemsetAsync(s->sort_status, 0, s->sort_status_parts * kRadix * sizeof(uint64_t), s->stream);
-        s->epoch = 1;
+    if (c->epoch_host + 2 * kEpochsPerFrame >= kEpochLimit) {
+        if (c->sort_status) launch_fill_u32(c->stream, reinterpret_cast<uint32_t *>(c->sort_status),
+                                            2 * c->sort_status_parts * kRadix, 0u);
+        launch_fill_u32(c->stream, &c->fdev->epoch, 1, 0u);
+        c->epoch_host = 0;
     }
-    return s->epoch;
+    c->epoch_host += kEpochsPerFrame;
 }
 
 // Stable sort of K (key, value) pairs held in buffer 0 by the low key_bits
-// bits of the keys; *out_buf receives the buffer index holding the result.
+// bits; n_dev, when given, is the device-side count (K then bounds it).
 template <typename KT>
-int run_sort(v3dg_scene *s, KT *const kb[2], uint32_t *const vb[2], uint64_t K, uint32_t key_bits, int *out_buf,
-             uint32_t *passes_out, bool have_hist)
+void run_sort(Ctx *c, KT *const kb[2], uint32_t *const vb[2], const uint32_t *n_dev, uint64_t K, uint32_t key_bits,
+              uint32_t epoch_base, int *out_buf, uint32_t *passes_out, bool have_hist)
 {
     const int passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
     *passes_out = (uint32_t)passes;
     int cur = 0;
     if (!have_hist) {
-        Stage st(s, V3DG_STAGE_SORT_HIST);
-        launch_sort_hist<KT>(s->stream, kb[0], K, passes, s->rcounters + kRenHist);
+        Stage st(c, V3DG_STAGE_SORT_HIST);
+        launch_sort_hist<KT>(c->stream, kb[0], n_dev, K, passes, c->rcounters + kRenHist);
     }
     for (int p = 0; p < passes; ++p) {
-        Stage st(s, V3DG_STAGE_SORT_PASS);
-        launch_sort_pass<KT>(s->stream, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], K, p, s->rcounters + kRenHist,
-                             s->sort_status, next_epoch(s), s->rcounters + kRenTicketSort + p, s->rcounters + kRenErr);
+        Stage st(c, V3DG_STAGE_SORT_PASS);
+        launch_sort_pass<KT>(c->stream, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n_dev, K, p, c->rcounters + kRenHist,
+                             c->sort_status, &c->fdev->epoch, epoch_base + (uint32_t)p,
+                             c->rcounters + kRenTicketSort + p, c->rcounters + kRenErr);
         cur ^= 1;
     }
     *out_buf = cur;
+}
+
+struct SelView {
+    const uint32_t *counters;  // kSelNGaussians holds the slot count
+    const uint32_t *slot_row, *slot_inst;
+};
+
+// What one frame's launches were sized for.
+struct FrameInfo {
+    uint64_t K = 0;            // keys (host-sized frames only)
+    uint32_t n_tiles = 0, key_bits = 0, passes = 0, N = 0, n_visible = 0, n_sel_clusters = 0;
+    int buf = 0;
+    bool depth_first = true;
+};
+
+// Enqueue one frame of scene sc on context c.
+//   capacity == false: the counts are read back once after the tile scan
+//     (one host wait), buffers grow to fit and every later launch is sized
+//     exactly.  Used by v3dg_render.
+//   capacity == true: no host wait; launches are sized by the context's
+//     capacities, kernels read every count from device memory and a frame
+//     that needs more keys than cap_keys raises kErrOverflow (its image is
+//     then incomplete).  The caller ensures capacities first; from_fd says
+//     the camera and image were copied into c->fdev.  Capturable in a graph.
+int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, const SelView &sel, bool capacity,
+                  bool from_fd, FrameInfo *fi)
+{
+    int rc;
+    const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
+    fi->n_tiles = n_tiles;
+    if (!capacity) {
+        if ((rc = ensure_itab(c, sc->n_inst))) return rc;
+        if ((rc = ensure_slots(c, sc->cap_slots))) return rc;
+        if ((rc = ensure_tiles(c, n_tiles))) return rc;
+        epoch_advance(c);
+    }
+    const uint64_t S = sc->cap_slots;  // grid bound of the per-slot kernels
+    const uint32_t *n_dev = sel.counters + kSelNGaussians;
+    {
+        Stage st(c, V3DG_STAGE_SETUP);
+        launch_frame_setup(c->stream, cam, image, c->fdev, from_fd, true, sc->T_dev, sc->scale_dev, sc->n_inst,
+                           c->itab, c->rclear, (uint64_t)kRenCounters + 2 * c->scan_parts + 2ull * n_tiles);
+    }
+    ProjectOut po{c->splat, c->depth, c->bin, c->rect, c->tiles, c->dkey[0], c->dval[0]};
+    {
+        Stage st(c, V3DG_STAGE_PROJECT);
+        launch_project(c->stream, c->fdev, sc->attribs(), (int)sc->precision, (int)sc->sh_degree, sel.slot_row,
+                       sel.slot_inst, n_dev, S, c->itab, po);
+    }
+    const bool depth_first = capacity || c->sort_mode == V3DG_SORT_DEPTH_FIRST;
+    fi->depth_first = depth_first;
+    if (depth_first) {
+        // stable sort of the slots by FP32 depth bits (culled slots last)
+        {
+            Stage st(c, V3DG_STAGE_DEPTH_SORT);
+            launch_sort_hist<uint32_t>(c->stream, c->dkey[0], n_dev, S, 4, c->rcounters + kRenHistDepth);
+        }
+        int cur = 0;
+        for (int p = 0; p < 4; ++p) {
+            Stage st(c, V3DG_STAGE_DEPTH_SORT);
+            launch_sort_pass<uint32_t>(c->stream, c->dkey[cur], c->dval[cur], c->dkey[cur ^ 1], c->dval[cur ^ 1], n_dev,
+                                       S, p, c->rcounters + kRenHistDepth, c->sort_status, &c->fdev->epoch,
+                                       (uint32_t)p, c->rcounters + kRenTicketDepth + p, c->rcounters + kRenErr);
+            cur ^= 1;
+        }
+    }
+    {
+        Stage st(c, V3DG_STAGE_SCAN);
+        launch_scan_tiles(c->stream, c->tiles, depth_first ? c->dval[0] : nullptr, n_dev, S, c->offsets,
+                          c->scan_status, c->rcounters, capacity ? c->cap_keys : 0xffffffffull);
+    }
+    uint64_t KL;  // key bound of the launches below
+    if (!capacity) {
+        // one wait per frame: slot and key counts decide the launch sizes below
+        HIP_TRY(hipMemcpyAsync(c->pinned, c->rcounters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->pinned + 8, sel.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        const uint32_t err = c->pinned[kRenErr] | c->pinned[8 + kSelErr];
+        const uint64_t K = (uint64_t)c->pinned[kRenKeysLo] | ((uint64_t)c->pinned[kRenKeysHi] << 32);
+        fi->N = c->pinned[8 + kSelNGaussians];
+        fi->n_visible = c->pinned[kRenVisible];
+        fi->n_sel_clusters = c->pinned[8 + kSelNClusters];
+        if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
+        if ((err & kErrOverflow) || K >= 0xffffffffull)
+            return fail(V3DG_ERR_CAPACITY, "frame needs %llu keys; the limit is 2^32-1", (unsigned long long)K);
+        if ((rc = ensure_keys(c, K))) return rc;
+        if ((rc = ensure_chunks(c, K, n_tiles))) return rc;
+        fi->K = K;
+        KL = K;
+    } else {
+        KL = c->cap_keys;
+    }
+    const uint32_t *k_dev = capacity ? c->rcounters + kRenKeysEff : nullptr;
+    const uint32_t tile_bits = std::max<uint32_t>(bits_for(n_tiles), 1);
+    int buf = 0;
+    uint32_t passes = 0;
+    uint32_t key_bits;
+    if (depth_first) {
+        uint32_t *kb[2] = {reinterpret_cast<uint32_t *>(c->keys[0]), reinterpret_cast<uint32_t *>(c->keys[1])};
+        key_bits = tile_bits;
+        const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
+        {
+            Stage st(c, V3DG_STAGE_EMIT);
+            launch_emit32(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys,
+                          tpasses, kb[0], c->vals[0], c->rcounters + kRenHist, c->rcounters + kRenErr);
+        }
+        if (KL > 0) run_sort<uint32_t>(c, kb, c->vals, k_dev, KL, key_bits, 4, &buf, &passes, true);
+        {
+            Stage st(c, V3DG_STAGE_RANGES);
+            launch_tile_ranges<uint32_t>(c->stream, kb[buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges);
+        }
+    } else {
+        {
+            Stage st(c, V3DG_STAGE_EMIT);
+            launch_emit64(c->stream, n_dev, S, c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys, c->keys[0],
+                          c->vals[0], c->rcounters + kRenErr);
+        }
+        key_bits = 32 + tile_bits;
+        if (KL > 0) run_sort<uint64_t>(c, c->keys, c->vals, k_dev, KL, key_bits, 0, &buf, &passes, false);
+        {
+            Stage st(c, V3DG_STAGE_RANGES);
+            launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, n_tiles, c->ranges);
+        }
+    }
+    {
+        Stage st(c, V3DG_STAGE_BLEND);
+        launch_blend(c->stream, c->fdev, n_tiles, c->splat, c->vals[buf], c->ranges, c->cbase, c->items, c->rcounters,
+                     KL / kChunk, capacity ? c->cap_chunks : KL / kChunk + n_tiles, c->scratch, c->pend, c->need,
+                     c->rewalk, c->pairs_dev);
+    }
+    HIP_TRY(hipGetLastError());
+    fi->key_bits = key_bits;
+    fi->passes = passes;
+    fi->buf = buf;
     return V3DG_OK;
+}
+
+void record_frame(Ctx *c, const FrameInfo &fi, uint64_t pixels)
+{
+    c->acc.frames += 1;
+    c->acc.sel_clusters += fi.n_sel_clusters;
+    c->acc.slots += fi.N;
+    c->acc.visible += fi.n_visible;
+    c->acc.keys += fi.K;
+    c->acc.tiles += fi.n_tiles;
+    c->acc.pixels += pixels;
+    c->acc.sort_passes += fi.passes;
+    if (fi.depth_first) c->acc.depth_sorts += 1;
+    c->last.n_slots = fi.N;
+    c->last.n_keys = fi.K;
+    c->last.n_tiles = fi.n_tiles;
+    c->last.key_bits = fi.key_bits;
+    c->last.sort_mode = fi.depth_first ? V3DG_SORT_DEPTH_FIRST : V3DG_SORT_KEYS64;
+    c->last.sort_passes = fi.passes;
+    c->last_buf = fi.buf;
 }
 
 int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, float *image)
@@ -483,111 +762,10 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     if (!sel || sel->scene != s) return fail(V3DG_ERR_INVALID_ARG, "selection does not belong to this scene");
     if (!image) return fail(V3DG_ERR_INVALID_ARG, "image is NULL");
     HIP_TRY(hipSetDevice(s->device));
-    if ((rc = ensure_slots(s))) return rc;
-    const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
-    if ((rc = ensure_tiles(s, n_tiles))) return rc;
-    {
-        Stage st(s, V3DG_STAGE_SETUP);
-        launch_frame_setup(s->stream, cam, s->T_dev, s->scale_dev, s->n_inst, s->itab, s->rclear,
-                           (uint64_t)kRenCounters + 2 * s->scan_parts + 2ull * n_tiles);
-    }
-    const uint32_t *n_dev = sel->counters + kSelNGaussians;
-    ProjectOut po{s->splat, s->depth, s->bin, s->rect, s->tiles, s->dkey[0], s->dval[0]};
-    {
-        Stage st(s, V3DG_STAGE_PROJECT);
-        const Attribs attr{s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride};
-        launch_project(s->stream, cam, attr, (int)s->precision, (int)s->sh_degree, sel->slot_row, sel->slot_inst,
-                       n_dev, s->cap_slots, s->itab, po);
-    }
-    const bool depth_first = s->sort_mode == V3DG_SORT_DEPTH_FIRST;
-    if (depth_first) {
-        // stable sort of the slots by FP32 depth bits (culled slots last), on
-        // the device-side slot count
-        {
-            Stage st(s, V3DG_STAGE_DEPTH_SORT);
-            launch_sort_hist_dev(s->stream, s->dkey[0], n_dev, s->cap_slots, 4, s->rcounters + kRenHistDepth);
-        }
-        int cur = 0;
-        for (int p = 0; p < 4; ++p) {
-            Stage st(s, V3DG_STAGE_DEPTH_SORT);
-            launch_sort_pass_dev(s->stream, s->dkey[cur], s->dval[cur], s->dkey[cur ^ 1], s->dval[cur ^ 1], n_dev,
-                                 s->cap_slots, p, s->rcounters + kRenHistDepth, s->sort_status, next_epoch(s),
-                                 s->rcounters + kRenTicketDepth + p, s->rcounters + kRenErr);
-            cur ^= 1;
-        }
-    }
-    {
-        Stage st(s, V3DG_STAGE_SCAN);
-        launch_scan_tiles(s->stream, s->tiles, depth_first ? s->dval[0] : nullptr, n_dev, s->cap_slots, s->offsets,
-                          s->scan_status, s->rcounters);
-    }
-    // one wait per frame: slot and key counts decide the launch sizes below
-    HIP_TRY(hipMemcpyAsync(s->pinned, s->rcounters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->pinned + 8, sel->counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    const uint32_t err = s->pinned[kRenErr] | s->pinned[8 + kSelErr];
-    const uint64_t K = (uint64_t)s->pinned[kRenKeysLo] | ((uint64_t)s->pinned[kRenKeysHi] << 32);
-    const uint32_t N = s->pinned[8 + kSelNGaussians];
-    const uint32_t n_visible = s->pinned[kRenVisible];
-    const uint32_t n_sel_clusters = s->pinned[8 + kSelNClusters];
-    if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
-    if ((err & kErrOverflow) || K >= 0xffffffffull)
-        return fail(V3DG_ERR_CAPACITY, "frame needs %llu keys; the limit is 2^32-1", (unsigned long long)K);
-    if ((rc = ensure_keys(s, K))) return rc;
-    if ((rc = ensure_chunks(s, K, n_tiles))) return rc;
-    const uint32_t tile_bits = std::max<uint32_t>(bits_for(n_tiles), 1);
-    int buf = 0;
-    uint32_t passes = 0;
-    uint32_t key_bits;
-    if (depth_first) {
-        uint32_t *kb[2] = {reinterpret_cast<uint32_t *>(s->keys[0]), reinterpret_cast<uint32_t *>(s->keys[1])};
-        key_bits = tile_bits;
-        const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
-        {
-            Stage st(s, V3DG_STAGE_EMIT);
-            launch_emit32(s->stream, N, s->dval[0], s->tiles, s->offsets, s->rect, s->bin, cam.tiles_x, s->cap_keys,
-                          tpasses, kb[0], s->vals[0], s->rcounters + kRenHist, s->rcounters + kRenErr);
-        }
-        if (K > 0) run_sort<uint32_t>(s, kb, s->vals, K, key_bits, &buf, &passes, true);
-        {
-            Stage st(s, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint32_t>(s->stream, kb[buf], K, 0, n_tiles, s->ranges);
-        }
-    } else {
-        {
-            Stage st(s, V3DG_STAGE_EMIT);
-            launch_emit64(s->stream, N, s->tiles, s->offsets, s->rect, s->bin, cam.tiles_x, s->cap_keys, s->keys[0],
-                          s->vals[0], s->rcounters + kRenErr);
-        }
-        key_bits = 32 + tile_bits;
-        if (K > 0) run_sort<uint64_t>(s, s->keys, s->vals, K, key_bits, &buf, &passes, false);
-        {
-            Stage st(s, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint64_t>(s->stream, s->keys[buf], K, 32, n_tiles, s->ranges);
-        }
-    }
-    {
-        Stage st(s, V3DG_STAGE_BLEND);
-        launch_blend(s->stream, cam, s->splat, s->vals[buf], s->ranges, s->cbase, s->items, s->rcounters,
-                     K / kChunk, K / kChunk + n_tiles, s->scratch, s->pend, s->need, s->rewalk, image, s->pairs_dev);
-    }
-    HIP_TRY(hipGetLastError());
-    s->acc.frames += 1;
-    s->acc.sel_clusters += n_sel_clusters;
-    s->acc.slots += N;
-    s->acc.visible += n_visible;
-    s->acc.keys += K;
-    s->acc.tiles += n_tiles;
-    s->acc.pixels += (uint64_t)cam.width * cam.height;
-    s->acc.sort_passes += passes;
-    if (depth_first) s->acc.depth_sorts += 1;
-    s->last.n_slots = N;
-    s->last.n_keys = K;
-    s->last.n_tiles = n_tiles;
-    s->last.key_bits = key_bits;
-    s->last.sort_mode = (uint32_t)s->sort_mode;
-    s->last.sort_passes = passes;
-    s->last_buf = buf;
+    FrameInfo fi;
+    const SelView sv{sel->counters, sel->slot_row, sel->slot_inst};
+    if ((rc = enqueue_frame(s, s, cam, image, sv, false, false, &fi))) return rc;
+    record_frame(s, fi, (uint64_t)cam.width * cam.height);
     return V3DG_OK;
 }
 
@@ -643,39 +821,7 @@ void scene_release(v3dg_scene *s)
     dev_free(s->rowinfo);
     dev_free(s->T_dev);
     dev_free(s->scale_dev);
-    dev_free(s->itab);
-    dev_free(s->splat);
-    dev_free(s->bin);
-    dev_free(s->depth);
-    for (int b = 0; b < 2; ++b) {
-        dev_free(s->dkey[b]);
-        dev_free(s->dval[b]);
-    }
-    dev_free(s->rect);
-    dev_free(s->tiles);
-    dev_free(s->offsets);
-    dev_free(s->rclear);
-    for (int b = 0; b < 2; ++b) {
-        dev_free(s->keys[b]);
-        dev_free(s->vals[b]);
-    }
-    dev_free(s->sort_status);
-    dev_free(s->pairs_dev);
-    dev_free(s->cbase);
-    dev_free(s->items);
-    dev_free(s->scratch);
-    dev_free(s->pend);
-    dev_free(s->need);
-    dev_free(s->rewalk);
-    if (s->pinned) (void)hipHostFree(s->pinned);
-    s->pinned = nullptr;
-    for (auto &r : s->prof) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
-    for (auto e : s->ev_pool) (void)hipEventDestroy(e);
-    s->prof.clear();
-    s->ev_pool.clear();
+    ctx_release(s);
 }
 
 }  // namespace
@@ -874,12 +1020,8 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     if ((rc = dev_alloc(&s->rowinfo, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->T_dev, 12ull * n_instances))) return bail(rc);
     if ((rc = dev_alloc(&s->scale_dev, n_instances))) return bail(rc);
-    if ((rc = dev_alloc(&s->itab, n_instances))) return bail(rc);
-    if ((rc = dev_alloc(&s->pairs_dev, 1))) return bail(rc);
-    if (hipMemset(s->pairs_dev, 0, sizeof(unsigned long long)) != hipSuccess)
-        return bail(fail(V3DG_ERR_HIP, "hipMemset failed"));
-    if (hipHostMalloc((void **)&s->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
-        return bail(fail(V3DG_ERR_OOM, "pinned allocation failed"));
+    if ((rc = ctx_init(s, s->device, s->stream))) return bail(rc);
+    if ((rc = ensure_itab(s, n_instances))) return bail(rc);
     {
         std::vector<float> hpos(3 * ps, 0.0f), hgeo(kGeoPlanes * ps, 0.0f), hsh(3ull * ncoef * ps, 0.0f);
         for (uint64_t r = 0; r < NR; ++r) {
@@ -960,13 +1102,12 @@ int v3dg_select(v3dg_scene *s, const v3dg_camera *c, float tau, v3dg_selection *
     const float K = footprint_K(c);
     {
         Stage st(s, V3DG_STAGE_SETUP);
-        launch_frame_setup(s->stream, cam, s->T_dev, s->scale_dev, s->n_inst, s->itab, sel->clear_block,
-                           (uint64_t)kSelCounters + 2 * sel->n_parts);
+        launch_frame_setup(s->stream, cam, nullptr, nullptr, false, false, s->T_dev, s->scale_dev, s->n_inst, s->itab,
+                           sel->clear_block, (uint64_t)kSelCounters + 2 * sel->n_parts);
     }
     {
         Stage st(s, V3DG_STAGE_SELECT);
-        launch_select(s->stream, s->self_sph, s->par_sph, s->rowinfo, s->itab, s->NC, s->n_inst, K, tau, sel->gid,
-                      sel->slot_off, sel->status, sel->counters);
+        launch_select(s->stream, make_selreq(s, s->itab, K, tau, sel));
     }
     {
         Stage st(s, V3DG_STAGE_EXPAND);
@@ -1262,13 +1403,13 @@ int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t
     if (!rc) {
         launch_fill_u32(st, reinterpret_cast<uint32_t *>(status), 2 * parts * kRadix, 0u);
         launch_fill_u32(st, ctr, kRenCounters, 0u);
-        launch_sort_hist<uint64_t>(st, keys_dev, n, passes, ctr + kRenHist);
+        launch_sort_hist<uint64_t>(st, keys_dev, nullptr, n, passes, ctr + kRenHist);
         uint64_t *kb[2] = {keys_dev, k2};
         uint32_t *vb[2] = {vals_dev, v2};
         int cur = 0;
         for (int p = 0; p < passes; ++p) {
-            launch_sort_pass<uint64_t>(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, p, ctr + kRenHist, status,
-                                       (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr);
+            launch_sort_pass<uint64_t>(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], nullptr, n, p, ctr + kRenHist,
+                                       status, nullptr, (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr);
             cur ^= 1;
         }
         if (cur == 1) {
@@ -1286,6 +1427,515 @@ int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t
     dev_free(status);
     dev_free(ctr);
     return rc;
+}
+
+}  // extern "C"
+
+// =============================================================================
+// serving: render contexts, admission under an HBM budget, batched selection
+// =============================================================================
+namespace {
+
+double now_ms(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct SrvReq {
+    uint64_t ticket = 0;
+    uint32_t scene = 0;
+    CamArgs cam{};
+    float K = 0.f, tau = 0.f;
+    float *image = nullptr;
+    double submit_ms = 0.0, admit_ms = 0.0;
+    uint32_t retries = 0;
+};
+
+using ShapeKey = std::tuple<uint32_t, uint32_t, uint32_t>;  // scene, width, height
+
+struct SrvCtx : Ctx {
+    v3dg_selection sel;                 // selection buffers for the largest scene
+    bool busy = false;
+    SrvReq req;
+    hipEvent_t done = nullptr;
+    FrameDev *stage = nullptr;          // pinned staging of the frame header
+    uint64_t generation = 0;            // advanced whenever a buffer is reallocated
+    std::map<ShapeKey, std::pair<hipGraphExec_t, uint64_t>> graphs;
+    uint64_t bytes = 0;                 // device memory held
+};
+
+struct BatchSlot {
+    SelSetup *h_setup = nullptr;
+    SelReq *h_req = nullptr;
+    SelSetup *d_setup = nullptr;
+    SelReq *d_req = nullptr;
+    uint32_t *d_ticket = nullptr;
+    hipEvent_t ev = nullptr;            // recorded after the batch's launches
+    bool used = false;
+};
+
+constexpr int kBatchRing = 8;
+
+}  // namespace
+
+struct v3dg_server {
+    int device = 0;
+    std::vector<v3dg_scene *> scenes;
+    v3dg_server_config cfg{};
+    hipStream_t sched = nullptr;        // batched selection
+    std::vector<SrvCtx *> ctx;
+    std::deque<SrvReq> queue;
+    BatchSlot ring[kBatchRing];
+    int ring_next = 0;
+    uint64_t next_ticket = 1;
+    uint64_t max_tests = 0, max_slots = 0;
+    uint32_t max_inst = 0;
+    std::map<ShapeKey, uint64_t> keys_seen;
+    std::chrono::steady_clock::time_point t0;
+    v3dg_server_stats st{};
+};
+
+namespace {
+
+uint64_t ctx_bytes(const SrvCtx *c)
+{
+    uint64_t b = c->ws_slots * (48 + 32 + 4 + 8 + 4 + 4 + 16);
+    b += (uint64_t)c->itab_cap * sizeof(InstRec) + sizeof(FrameDev) + 8;
+    b += c->rclear_words * 4 + (uint64_t)c->tiles_cap * 4;
+    b += c->cap_keys * 24 + c->sort_status_parts * kRadix * 8;
+    b += c->cap_chunks * (8 + 256 * 16 + 256 * 4 + 4 + 8);
+    b += c->sel.cap_tests * 8 + ((uint64_t)kSelCounters + 2 * c->sel.n_parts) * 4 + c->sel.cap_slots * 8;
+    return b;
+}
+
+// bytes of a context before any image size or key count is provisioned
+uint64_t ctx_base_bytes(const SrvCtx *c)
+{
+    return c->ws_slots * (48 + 32 + 4 + 8 + 4 + 4 + 16) + (uint64_t)c->itab_cap * sizeof(InstRec) +
+           sizeof(FrameDev) + 8 + c->sel.cap_tests * 8 + ((uint64_t)kSelCounters + 2 * c->sel.n_parts) * 4 +
+           c->sel.cap_slots * 8;
+}
+
+// bytes context c (nullptr: a new one) would add to hold K keys over n_tiles tiles
+uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
+{
+    const uint64_t keys = c ? c->cap_keys : 0, tiles = c ? c->tiles_cap : 0, chunks = c ? c->cap_chunks : 0;
+    uint64_t g = 0;
+    const uint64_t K2 = std::max(K, keys);
+    g += (K2 - keys) * 24 + ((K2 - keys + kSortPart - 1) / kSortPart) * 3 / 2 * kRadix * 8;
+    const uint64_t T2 = std::max<uint64_t>(std::max<uint64_t>(n_tiles, 8160), tiles);
+    g += (T2 - tiles) * 12;
+    const uint64_t ch = (K2 + kChunk - 1) / kChunk + T2;
+    if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 8);
+    return g;
+}
+
+void srv_account(v3dg_server *s)
+{
+    uint64_t tot = 0;
+    for (auto *c : s->ctx) {
+        c->bytes = ctx_bytes(c);
+        tot += c->bytes;
+    }
+    s->st.workspace_bytes = tot;
+    s->st.peak_workspace_bytes = std::max(s->st.peak_workspace_bytes, tot);
+}
+
+void drop_graphs(SrvCtx *c)
+{
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second.first);
+    c->graphs.clear();
+}
+
+void srv_ctx_free(SrvCtx *c)
+{
+    drop_graphs(c);
+    sel_release(&c->sel);
+    if (c->done) (void)hipEventDestroy(c->done);
+    if (c->stage) (void)hipHostFree(c->stage);
+    ctx_release(c);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+// key capacity to provision for a request shape
+uint64_t keys_estimate(v3dg_server *s, const ShapeKey &k, uint64_t pixels)
+{
+    auto it = s->keys_seen.find(k);
+    const uint64_t kpp = s->cfg.keys_per_pixel ? s->cfg.keys_per_pixel : 24;
+    uint64_t e = it != s->keys_seen.end() ? it->second + it->second / 4 : pixels * kpp;
+    e = std::max<uint64_t>(e, 1u << 16);
+    return std::min<uint64_t>(e, 0xfffff000ull);
+}
+
+// Grow c to serve a frame of n_tiles tiles with K keys.  Returns 1 when a
+// buffer was reallocated (captured graphs of c are then stale).
+int srv_provision(SrvCtx *c, uint32_t n_inst, uint32_t n_tiles, uint64_t K, bool *changed)
+{
+    const uint64_t before[4] = {c->itab_cap, c->tiles_cap, c->cap_keys, c->cap_chunks};
+    const uint64_t parts_before = c->sort_status_parts;
+    int rc;
+    if ((rc = ensure_itab(c, n_inst))) return rc;
+    if ((rc = ensure_tiles(c, n_tiles))) return rc;
+    if ((rc = ensure_keys(c, K, true))) return rc;
+    if ((rc = ensure_chunks(c, c->cap_keys, c->tiles_cap))) return rc;
+    const uint64_t after[4] = {c->itab_cap, c->tiles_cap, c->cap_keys, c->cap_chunks};
+    *changed = std::memcmp(before, after, sizeof(before)) != 0 || parts_before != c->sort_status_parts;
+    if (*changed) {
+        ++c->generation;
+        drop_graphs(c);
+    }
+    return V3DG_OK;
+}
+
+int srv_new_ctx(v3dg_server *s, SrvCtx **out)
+{
+    auto *c = new (std::nothrow) SrvCtx();
+    if (!c) return fail(V3DG_ERR_OOM, "host allocation failed");
+    hipStream_t st = nullptr;
+    int rc = V3DG_OK;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) rc = fail(V3DG_ERR_HIP, "stream creation failed");
+    if (!rc) rc = ctx_init(c, s->device, st);
+    if (!rc) rc = sel_alloc_caps(&c->sel, s->max_tests, s->max_slots, st);
+    if (!rc) rc = ensure_itab(c, s->max_inst);
+    if (!rc) rc = ensure_slots(c, s->max_slots);
+    if (!rc && hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess)
+        rc = fail(V3DG_ERR_HIP, "event creation failed");
+    if (!rc && hipHostMalloc((void **)&c->stage, sizeof(FrameDev), hipHostMallocDefault) != hipSuccess) {
+        c->stage = nullptr;
+        rc = fail(V3DG_ERR_OOM, "pinned allocation failed");
+    }
+    if (!rc) rc = hipStreamSynchronize(st) == hipSuccess ? V3DG_OK : fail(V3DG_ERR_HIP, "stream sync failed");
+    if (rc) {
+        srv_ctx_free(c);
+        return rc;
+    }
+    *out = c;
+    return V3DG_OK;
+}
+
+// the render chain of one request on its context, as a replayed graph or as
+// direct launches (the selection has been written into c->sel)
+int srv_launch(v3dg_server *s, SrvCtx *c, hipEvent_t sel_done)
+{
+    v3dg_scene *sc = s->scenes[c->req.scene];
+    const CamArgs &cam = c->req.cam;
+    const SelView sv{c->sel.counters, c->sel.slot_row, c->sel.slot_inst};
+    hipGraphExec_t exec = nullptr;
+    if (s->cfg.use_graphs) {
+        const ShapeKey key{c->req.scene, cam.width, cam.height};
+        auto it = c->graphs.find(key);
+        if (it != c->graphs.end() && it->second.second == c->generation) {
+            exec = it->second.first;
+        } else {
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+            FrameInfo fi;
+            const int rc = enqueue_frame(c, sc, cam, nullptr, sv, true, true, &fi);
+            const hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(V3DG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e2 != hipSuccess) return fail(V3DG_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+            if (it != c->graphs.end()) (void)hipGraphExecDestroy(it->second.first);
+            c->graphs[key] = {exec, c->generation};
+            ++s->st.graph_captures;
+        }
+    }
+    HIP_TRY(hipStreamWaitEvent(c->stream, sel_done, 0));
+    c->stage->cam = cam;
+    c->stage->image = c->req.image;
+    HIP_TRY(hipMemcpyAsync(c->fdev, c->stage, offsetof(FrameDev, epoch), hipMemcpyHostToDevice, c->stream));
+    epoch_advance(c);
+    if (exec) {
+        HIP_TRY(hipGraphLaunch(exec, c->stream));
+        ++s->st.graph_launches;
+    } else {
+        FrameInfo fi;
+        int rc = enqueue_frame(c, sc, cam, nullptr, sv, true, true, &fi);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(c->pinned, c->rcounters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 8, c->sel.counters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipEventRecord(c->done, c->stream));
+    c->busy = true;
+    return V3DG_OK;
+}
+
+// one batched selection for the requests just admitted into ctxs[], then
+// their render chains
+int srv_dispatch(v3dg_server *s, const std::vector<SrvCtx *> &batch)
+{
+    if (batch.empty()) return V3DG_OK;
+    BatchSlot &b = s->ring[s->ring_next];
+    s->ring_next = (s->ring_next + 1) % kBatchRing;
+    if (b.used) HIP_TRY(hipEventSynchronize(b.ev));  // its descriptors may be reused now
+    uint32_t parts = 0, max_clear = 0;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        SrvCtx *c = batch[i];
+        v3dg_scene *sc = s->scenes[c->req.scene];
+        SelReq q = make_selreq(sc, c->itab, c->req.K, c->req.tau, &c->sel);
+        q.part_begin = parts;
+        parts += q.nparts;
+        b.h_req[i] = q;
+        SelSetup su{};
+        su.cam = c->req.cam;
+        su.T = sc->T_dev;
+        su.inst_scale = sc->scale_dev;
+        su.itab = c->itab;
+        su.clear = c->sel.clear_block;
+        su.n_inst = sc->n_inst;
+        su.n_clear = (uint32_t)(kSelCounters + 2 * q.nparts);
+        max_clear = std::max(max_clear, su.n_clear);
+        b.h_setup[i] = su;
+    }
+    const uint32_t n = (uint32_t)batch.size();
+    HIP_TRY(hipMemcpyAsync(b.d_setup, b.h_setup, n * sizeof(SelSetup), hipMemcpyHostToDevice, s->sched));
+    HIP_TRY(hipMemcpyAsync(b.d_req, b.h_req, n * sizeof(SelReq), hipMemcpyHostToDevice, s->sched));
+    launch_select_batch(s->sched, b.d_setup, b.d_req, n, parts, s->max_inst, max_clear, b.d_ticket);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(b.ev, s->sched));
+    b.used = true;
+    s->st.batches += 1;
+    s->st.batched_requests += n;
+    for (SrvCtx *c : batch) {
+        int rc = srv_launch(s, c, b.ev);
+        if (rc) return rc;
+    }
+    return V3DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int v3dg_server_create(v3dg_scene *const *scenes, uint32_t n_scenes, const v3dg_server_config *cfg,
+                       v3dg_server **out)
+{
+    g_err.clear();
+    if (!scenes || n_scenes == 0 || !cfg || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument or no scenes");
+    if (cfg->n_contexts < 1 || cfg->n_contexts > 64 || cfg->max_batch < 1 || cfg->max_batch > 64)
+        return fail(V3DG_ERR_INVALID_ARG, "n_contexts and max_batch must be 1..64");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto *s = new (std::nothrow) v3dg_server();
+    if (!s) return fail(V3DG_ERR_OOM, "host allocation failed");
+    s->device = dev;
+    s->cfg = *cfg;
+    s->t0 = std::chrono::steady_clock::now();
+    for (uint32_t i = 0; i < n_scenes; ++i) {
+        v3dg_scene *sc = scenes[i];
+        if (!sc || sc->device != dev) {
+            delete s;
+            return fail(V3DG_ERR_INVALID_ARG, "scene %u is NULL or on another device", i);
+        }
+        (void)hipStreamSynchronize(sc->stream);
+        s->scenes.push_back(sc);
+        s->max_tests = std::max<uint64_t>(s->max_tests, (uint64_t)sc->NC * sc->n_inst);
+        s->max_slots = std::max<uint64_t>(s->max_slots, sc->cap_slots);
+        s->max_inst = std::max(s->max_inst, sc->n_inst);
+    }
+    int rc = V3DG_OK;
+    if (hipStreamCreateWithFlags(&s->sched, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(V3DG_ERR_HIP, "stream creation failed");
+    for (int r = 0; r < kBatchRing && !rc; ++r) {
+        BatchSlot &b = s->ring[r];
+        if (hipHostMalloc((void **)&b.h_setup, cfg->max_batch * sizeof(SelSetup), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&b.h_req, cfg->max_batch * sizeof(SelReq), hipHostMallocDefault) != hipSuccess)
+            rc = fail(V3DG_ERR_OOM, "pinned allocation failed");
+        if (!rc) rc = dev_alloc(reinterpret_cast<uint8_t **>(&b.d_setup), cfg->max_batch * sizeof(SelSetup));
+        if (!rc) rc = dev_alloc(reinterpret_cast<uint8_t **>(&b.d_req), cfg->max_batch * sizeof(SelReq));
+        if (!rc) rc = dev_alloc(&b.d_ticket, 1);
+        if (!rc && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess)
+            rc = fail(V3DG_ERR_HIP, "event creation failed");
+    }
+    if (!rc) {  // the first context must fit the budget
+        SrvCtx *c = nullptr;
+        rc = srv_new_ctx(s, &c);
+        if (!rc) {
+            s->ctx.push_back(c);
+            srv_account(s);
+            if (s->st.workspace_bytes > cfg->hbm_budget_bytes)
+                rc = fail(V3DG_ERR_OOM, "one render context needs %llu bytes; the budget is %llu",
+                          (unsigned long long)s->st.workspace_bytes, (unsigned long long)cfg->hbm_budget_bytes);
+        }
+    }
+    if (rc) {
+        v3dg_server_free(s);
+        return rc;
+    }
+    *out = s;
+    return V3DG_OK;
+}
+
+int v3dg_server_submit(v3dg_server *s, uint32_t scene, const v3dg_camera *cam, float tau, float *image_dev,
+                       uint64_t *ticket)
+{
+    g_err.clear();
+    if (!s) return fail(V3DG_ERR_INVALID_ARG, "server is NULL");
+    if (scene >= s->scenes.size()) return fail(V3DG_ERR_INVALID_ARG, "scene %u out of range", scene);
+    if (!image_dev) return fail(V3DG_ERR_INVALID_ARG, "image is NULL");
+    if (!std::isfinite(tau) || tau < 0.0f) return fail(V3DG_ERR_INVALID_ARG, "tolerance must be finite and >= 0");
+    SrvReq r;
+    int rc = make_cam(cam, &r.cam);
+    if (rc) return rc;
+    r.ticket = s->next_ticket++;
+    r.scene = scene;
+    r.K = footprint_K(cam);
+    r.tau = tau;
+    r.image = image_dev;
+    r.submit_ms = now_ms(s->t0);
+    s->queue.push_back(r);
+    s->st.submitted += 1;
+    if (ticket) *ticket = r.ticket;
+    return V3DG_OK;
+}
+
+int v3dg_server_poll(v3dg_server *s, int wait, v3dg_request_done *done, uint32_t cap, uint32_t *n_done)
+{
+    g_err.clear();
+    if (!s || !n_done || (cap && !done)) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(s->device));
+    *n_done = 0;
+    // ---- retire
+    for (;;) {
+        bool any_busy = false;
+        for (SrvCtx *c : s->ctx) {
+            if (!c->busy) continue;
+            any_busy = true;
+            if (*n_done >= cap) break;
+            const hipError_t q = hipEventQuery(c->done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return fail(V3DG_ERR_HIP, "frame failed: %s", hipGetErrorString(q));
+            c->busy = false;
+            const uint32_t err = c->pinned[kRenErr] | c->pinned[8 + kSelErr];
+            const uint64_t K = (uint64_t)c->pinned[kRenKeysLo] | ((uint64_t)c->pinned[kRenKeysHi] << 32);
+            const ShapeKey key{c->req.scene, c->req.cam.width, c->req.cam.height};
+            uint64_t &seen = s->keys_seen[key];
+            seen = std::max(seen, K);
+            int status = V3DG_OK;
+            if (err & kErrSpin) {
+                status = V3DG_ERR_DEVICE;
+            } else if (K > c->cap_keys) {
+                if (K >= 0xfffff000ull) {
+                    status = V3DG_ERR_CAPACITY;
+                } else {  // render it again once the context holds K keys
+                    SrvReq r = c->req;
+                    r.retries += 1;
+                    s->st.retries += 1;
+                    s->queue.push_front(r);
+                    continue;
+                }
+            } else if (err & kErrOverflow) {
+                status = V3DG_ERR_DEVICE;  // counting and emission disagreed
+            }
+            v3dg_request_done &d = done[(*n_done)++];
+            d.ticket = c->req.ticket;
+            d.status = status;
+            d.retries = c->req.retries;
+            d.n_slots = c->pinned[8 + kSelNGaussians];
+            d.n_keys = K;
+            d.submit_ms = c->req.submit_ms;
+            d.admit_ms = c->req.admit_ms;
+            d.done_ms = now_ms(s->t0);
+            if (status) s->st.failed += 1;
+            else s->st.completed += 1;
+        }
+        if (!wait || *n_done > 0 || !any_busy) break;
+        // block on the oldest frame in flight
+        SrvCtx *oldest = nullptr;
+        for (SrvCtx *c : s->ctx)
+            if (c->busy && (!oldest || c->req.admit_ms < oldest->req.admit_ms)) oldest = c;
+        if (oldest) HIP_TRY(hipEventSynchronize(oldest->done));
+    }
+    // ---- admit: a free context that needs the least growth, else a new
+    // context, while the budget holds what the front request would add
+    std::vector<SrvCtx *> batch;
+    while (!s->queue.empty() && batch.size() < s->cfg.max_batch) {
+        SrvReq &r = s->queue.front();
+        v3dg_scene *sc = s->scenes[r.scene];
+        const uint32_t n_tiles = r.cam.tiles_x * r.cam.tiles_y;
+        const ShapeKey key{r.scene, r.cam.width, r.cam.height};
+        const uint64_t Kneed = keys_estimate(s, key, (uint64_t)r.cam.width * r.cam.height);
+        SrvCtx *c = nullptr;
+        uint64_t cost = 0;
+        for (SrvCtx *x : s->ctx) {
+            if (x->busy || std::find(batch.begin(), batch.end(), x) != batch.end()) continue;
+            const uint64_t g = growth_bytes(x, Kneed, n_tiles);
+            if (!c || g < cost) {
+                c = x;
+                cost = g;
+            }
+        }
+        const bool create = !c && s->ctx.size() < s->cfg.n_contexts;
+        if (create) cost = ctx_base_bytes(s->ctx[0]) + growth_bytes(nullptr, Kneed, n_tiles);
+        if (!c && !create) break;  // every context is busy
+        if (s->st.workspace_bytes + cost > s->cfg.hbm_budget_bytes) {
+            bool busy = !batch.empty();
+            for (SrvCtx *x : s->ctx) busy |= x->busy;
+            if (busy) break;  // admit it once frames in flight have finished
+            if (!c) break;
+            // alone on the device and still over the budget: the request fails
+            if (*n_done >= cap) break;
+            v3dg_request_done &d = done[(*n_done)++];
+            std::memset(&d, 0, sizeof(d));
+            d.ticket = r.ticket;
+            d.status = V3DG_ERR_OOM;
+            d.submit_ms = r.submit_ms;
+            d.done_ms = now_ms(s->t0);
+            s->st.failed += 1;
+            s->queue.pop_front();
+            continue;
+        }
+        if (create) {
+            int rc = srv_new_ctx(s, &c);
+            if (rc) return rc;
+            s->ctx.push_back(c);
+        }
+        bool changed = false;
+        int rc = srv_provision(c, sc->n_inst, n_tiles, Kneed, &changed);
+        if (rc) return rc;
+        srv_account(s);
+        c->req = r;
+        c->req.admit_ms = now_ms(s->t0);
+        s->queue.pop_front();
+        batch.push_back(c);
+    }
+    int rc = srv_dispatch(s, batch);
+    if (rc) return rc;
+    s->st.queued = (uint32_t)s->queue.size();
+    s->st.contexts_live = (uint32_t)s->ctx.size();
+    return V3DG_OK;
+}
+
+int v3dg_server_get_stats(v3dg_server *s, v3dg_server_stats *out)
+{
+    g_err.clear();
+    if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
+    s->st.queued = (uint32_t)s->queue.size();
+    s->st.contexts_live = (uint32_t)s->ctx.size();
+    *out = s->st;
+    return V3DG_OK;
+}
+
+void v3dg_server_free(v3dg_server *s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    for (SrvCtx *c : s->ctx) srv_ctx_free(c);
+    s->ctx.clear();
+    if (s->sched) (void)hipStreamSynchronize(s->sched);
+    for (auto &b : s->ring) {
+        if (b.h_setup) (void)hipHostFree(b.h_setup);
+        if (b.h_req) (void)hipHostFree(b.h_req);
+        dev_free(b.d_setup);
+        dev_free(b.d_req);
+        dev_free(b.d_ticket);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+    }
+    if (s->sched) (void)hipStreamDestroy(s->sched);
+    delete s;
 }
 
 }  // extern "C"

@@ -1,4 +1,4 @@
-// (a) parallel cluster selection with single-pass compaction, (b) expansion of
+// Parallel cluster selection with single-pass compaction, expansion of
 // the chosen clusters into the slot stream, and the per-frame instance set-up.
 //
 // Selection rule (paper Sec. 3.4): cluster k of instance i is drawn iff its own
@@ -18,16 +18,8 @@ namespace v3dg {
 // rounding), the camera centre in each asset frame, and clearing of the
 // frame's counters / look-back words.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) frame_setup_kernel(CamArgs cam, const double *__restrict__ T,
-                                                          const float *__restrict__ inst_scale, uint32_t n_inst,
-                                                          InstRec *__restrict__ itab, uint32_t *__restrict__ clear,
-                                                          uint64_t n_clear)
+__device__ InstRec make_instrec(const CamArgs &cam, const double *__restrict__ t, float s)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = i; j < n_clear; j += stride) clear[j] = 0u;
-    if (i >= n_inst) return;
-    const double *t = T + 12 * i;
     InstRec r;
 #pragma unroll
     for (int row = 0; row < 3; ++row) {
@@ -50,20 +42,55 @@ __global__ void __launch_bounds__(256) frame_setup_kernel(CamArgs cam, const dou
     r.chat[0] = (float)((a0 * d0 + a1 * d1 + a2 * d2) * inv);
     r.chat[1] = (float)((a3 * d0 + a4 * d1 + a5 * d2) * inv);
     r.chat[2] = (float)((a6 * d0 + a7 * d1 + a8 * d2) * inv);
-    r.s = inst_scale[i];
-    itab[i] = r;
+    r.s = s;
+    return r;
 }
 
-void launch_frame_setup(hipStream_t st, const CamArgs &cam, const double *T, const float *inst_scale,
-                        uint32_t n_inst, InstRec *itab, uint32_t *clear, uint64_t n_clear)
+__global__ void __launch_bounds__(256) frame_setup_kernel(CamArgs cam_val, float *image, FrameDev *fd, int from_fd,
+                                                          int bump_epoch, const double *__restrict__ T,
+                                                          const float *__restrict__ inst_scale, uint32_t n_inst,
+                                                          InstRec *__restrict__ itab, uint32_t *__restrict__ clear,
+                                                          uint64_t n_clear)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = i; j < n_clear; j += stride) clear[j] = 0u;
+    if (i == 0 && fd) {
+        if (!from_fd) {
+            fd->cam = cam_val;
+            fd->image = image;
+        }
+        if (bump_epoch) fd->epoch += kEpochsPerFrame;
+    }
+    if (i >= n_inst) return;
+    itab[i] = make_instrec(from_fd ? fd->cam : cam_val, T + 12 * i, inst_scale[i]);
+}
+
+void launch_frame_setup(hipStream_t st, const CamArgs &cam, float *image, FrameDev *fd, bool from_fd, bool bump_epoch,
+                        const double *T, const float *inst_scale, uint32_t n_inst, InstRec *itab, uint32_t *clear,
+                        uint64_t n_clear)
 {
     uint64_t blocks = (n_inst + 255) / 256;          // one thread per instance
     uint64_t clear_blocks = (n_clear + 255) / 256;   // grid-stride over the words to clear
     if (clear_blocks > 1024) clear_blocks = 1024;
     if (blocks < clear_blocks) blocks = clear_blocks;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(frame_setup_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, cam, T, inst_scale, n_inst, itab,
-                       clear, n_clear);
+    hipLaunchKernelGGL(frame_setup_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, cam, image, fd, (int)from_fd,
+                       (int)bump_epoch, T, inst_scale, n_inst, itab, clear, n_clear);
+}
+
+// set-up of a batch: block row r serves request r; block (0, 0) clears the
+// batch ticket
+__global__ void __launch_bounds__(256) select_setup_batch_kernel(const SelSetup *__restrict__ setups,
+                                                                 uint32_t *__restrict__ batch_ticket)
+{
+    const SelSetup &su = setups[blockIdx.y];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    if (i == 0 && blockIdx.y == 0) *batch_ticket = 0u;
+    for (uint32_t j = i; j < su.n_clear; j += stride) su.clear[j] = 0u;
+    for (uint32_t j = i; j < su.n_inst; j += stride)
+        su.itab[j] = make_instrec(su.cam, su.T + 12 * (uint64_t)j, su.inst_scale[j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -107,27 +134,16 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v)
     return v;
 }
 
-__global__ void __launch_bounds__(kSelThreads) select_kernel(const float4 *__restrict__ self_sph,
-                                                             const float4 *__restrict__ par_sph,
-                                                             const uint2 *__restrict__ rowinfo,
-                                                             const InstRec *__restrict__ itab, uint32_t NC,
-                                                             uint32_t n_inst, float K, float tau,
-                                                             uint32_t *__restrict__ gid_out,
-                                                             uint32_t *__restrict__ slot_off_out,
-                                                             uint64_t *__restrict__ status, uint32_t *counters,
-                                                             uint32_t nparts)
+// One partition (kSelPart consecutive tests) of request q: evaluate, scan,
+// look back across the request's earlier partitions, write the chosen gids.
+__device__ __forceinline__ void select_part(const SelReq &q, uint32_t p, uint64_t *s_wave, uint64_t *s_prefix)
 {
-    __shared__ uint32_t s_ticket;
-    __shared__ uint64_t s_wave[kSelThreads / kWave];
-    __shared__ uint64_t s_prefix;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    if (tid == 0) s_ticket = __hip_atomic_fetch_add(&counters[kSelTicket], 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint32_t p = s_ticket;
-    if (p >= nparts) return;
-    const uint32_t n_tests = NC * n_inst;
+    const uint32_t NC = q.NC;
+    const uint32_t n_tests = NC * q.n_inst;
     const uint32_t g0 = p * (uint32_t)kSelPart + (uint32_t)tid * kSelItems;
+    uint64_t *status = q.status;
+    uint32_t *counters = q.counters;
 
     uint64_t v[kSelItems];
     uint32_t inst = g0 / NC, k = g0 - inst * NC;
@@ -140,7 +156,7 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(const float4 *__res
         uint64_t val = 0;
         if (g < n_tests) {
             if (inst != cur_inst) {
-                const InstRec &ir = itab[inst];
+                const InstRec &ir = q.itab[inst];
                 a0 = ir.A[8];
                 a1 = ir.A[9];
                 a2 = ir.A[10];
@@ -148,9 +164,9 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(const float4 *__res
                 s = ir.s;
                 cur_inst = inst;
             }
-            const bool sel = sel_fits(self_sph[k], a0, a1, a2, a3, s, K, tau) &&
-                             !sel_fits(par_sph[k], a0, a1, a2, a3, s, K, tau);
-            if (sel) val = (1ull << kSelGBits) | (uint64_t)rowinfo[k].y;
+            const bool sel = sel_fits(q.self_sph[k], a0, a1, a2, a3, s, q.K, q.tau) &&
+                             !sel_fits(q.par_sph[k], a0, a1, a2, a3, s, q.K, q.tau);
+            if (sel) val = (1ull << kSelGBits) | (uint64_t)q.rowinfo[k].y;
         }
         v[j] = tsum;
         tsum += val;
@@ -199,8 +215,8 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(const float4 *__res
             __hip_atomic_store(&status[p], (kFlagInc << 62) | (prefix + block_total), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_prefix = prefix;
-        if (p == nparts - 1) {
+        *s_prefix = prefix;
+        if (p == q.nparts - 1) {
             const uint64_t tot = prefix + block_total;
             counters[kSelNClusters] = (uint32_t)(tot >> kSelGBits);
             counters[kSelNGaussians] = (uint32_t)(tot & kSelGMask);
@@ -208,7 +224,7 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(const float4 *__res
         }
     }
     __syncthreads();
-    const uint64_t base = s_prefix + t_excl;
+    const uint64_t base = *s_prefix + t_excl;
 #pragma unroll
     for (int j = 0; j < kSelItems; ++j) {
         // v[j] is the running sum before item j; a selected item adds at least
@@ -217,21 +233,52 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(const float4 *__res
         if (next != v[j]) {
             const uint64_t at = base + v[j];
             const uint32_t pos = (uint32_t)(at >> kSelGBits);
-            gid_out[pos] = g0 + j;
-            slot_off_out[pos] = (uint32_t)(at & kSelGMask);
+            q.gid[pos] = g0 + j;
+            q.slot_off[pos] = (uint32_t)(at & kSelGMask);
         }
     }
 }
 
-void launch_select(hipStream_t st, const float4 *self_sph, const float4 *par_sph, const uint2 *rowinfo,
-                   const InstRec *itab, uint32_t n_clusters, uint32_t n_inst, float K, float tau,
-                   uint32_t *gid_out, uint32_t *slot_off_out, uint64_t *status, uint32_t *counters)
+// Workgroups claim partitions by ticket until all are taken.  A partition
+// waits only on partitions of its own request with smaller tickets, which
+// were claimed earlier by running workgroups, so the look-back always ends.
+// With reqs == nullptr the single request `one` is served.
+__global__ void __launch_bounds__(kSelThreads) select_kernel(SelReq one, const SelReq *__restrict__ reqs,
+                                                             uint32_t n_req, uint32_t total_parts, uint32_t *ticket)
 {
-    const uint64_t n_tests = (uint64_t)n_clusters * n_inst;
-    const uint32_t nparts = (uint32_t)((n_tests + kSelPart - 1) / kSelPart);
-    if (nparts == 0) return;
-    hipLaunchKernelGGL(select_kernel, dim3(nparts), dim3(kSelThreads), 0, st, self_sph, par_sph, rowinfo, itab,
-                       n_clusters, n_inst, K, tau, gid_out, slot_off_out, status, counters, nparts);
+    __shared__ uint32_t s_ticket, s_req;
+    __shared__ uint64_t s_wave[kSelThreads / kWave];
+    __shared__ uint64_t s_prefix;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t r = 0;
+            if (reqs && t < total_parts) {  // last request whose first partition is <= t
+                uint32_t lo = 0, hi = n_req - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (reqs[mid].part_begin <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                r = lo;
+            }
+            s_ticket = t;
+            s_req = r;
+        }
+        __syncthreads();
+        const uint32_t t = s_ticket;
+        if (t >= total_parts) return;
+        const SelReq q = reqs ? reqs[s_req] : one;
+        select_part(q, t - q.part_begin, s_wave, &s_prefix);
+        __syncthreads();
+    }
+}
+
+void launch_select(hipStream_t st, const SelReq &req)
+{
+    if (req.nparts == 0) return;
+    hipLaunchKernelGGL(select_kernel, dim3(req.nparts), dim3(kSelThreads), 0, st, req, (const SelReq *)nullptr, 1u,
+                       req.nparts, req.counters + kSelTicket);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,6 +317,44 @@ void launch_expand(hipStream_t st, const uint32_t *gid, const uint32_t *slot_off
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(expand_kernel, dim3(blocks), dim3(256), 0, st, gid, slot_off, rowinfo, n_clusters, counters,
                        slot_row, slot_inst);
+}
+
+__global__ void __launch_bounds__(256) expand_batch_kernel(const SelReq *__restrict__ reqs, uint32_t n_req)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) / kWave;
+    for (uint32_t r = 0; r < n_req; ++r) {
+        const SelReq &q = reqs[r];
+        const uint32_t n = q.counters[kSelNClusters];
+        for (uint32_t c = wave; c < n; c += nwaves) {
+            const uint32_t g = q.gid[c];
+            const uint32_t inst = g / q.NC;
+            const uint2 ri = q.rowinfo[g - inst * q.NC];
+            const uint32_t off = q.slot_off[c];
+            if (lane < ri.y) {
+                q.slot_row[off + lane] = ri.x + lane;
+                q.slot_inst[off + lane] = inst;
+            }
+        }
+    }
+}
+
+void launch_select_batch(hipStream_t st, const SelSetup *setups, const SelReq *reqs, uint32_t n_req,
+                         uint32_t total_parts, uint32_t max_inst, uint32_t max_clear, uint32_t *batch_ticket)
+{
+    if (n_req == 0) return;
+    uint32_t bx = (max(max_inst, max_clear) + 255) / 256;
+    if (bx > 64) bx = 64;
+    if (bx < 1) bx = 1;
+    hipLaunchKernelGGL(select_setup_batch_kernel, dim3(bx, n_req), dim3(256), 0, st, setups, batch_ticket);
+    if (total_parts) {
+        const uint32_t grid = total_parts < 2048u ? total_parts : 2048u;  // persistent: 8 per CU at most
+        SelReq none{};
+        hipLaunchKernelGGL(select_kernel, dim3(grid), dim3(kSelThreads), 0, st, none, reqs, n_req, total_parts,
+                           batch_ticket);
+    }
+    hipLaunchKernelGGL(expand_batch_kernel, dim3(2048), dim3(256), 0, st, reqs, n_req);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)

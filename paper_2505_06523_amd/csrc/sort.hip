@@ -1,4 +1,4 @@
-// (d) binning of splats to 16x16 tiles and the stable radix sorts that order
+// Binning of splats to 16x16 tiles and the stable radix sorts that order
 // every tile's splats front to back.
 //
 // Two orderings give the same (tile, depth, slot) order:
@@ -83,7 +83,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
                                                                   const uint32_t *__restrict__ order,
                                                                   const uint32_t *__restrict__ n_dev,
                                                                   uint32_t *__restrict__ offsets,
-                                                                  uint64_t *__restrict__ status, uint32_t *counters)
+                                                                  uint64_t *__restrict__ status, uint32_t *counters,
+                                                                  uint64_t key_cap)
 {
     __shared__ uint32_t s_ticket;
     __shared__ uint64_t s_wave[kScanThreads / kWave];
@@ -167,6 +168,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
             const uint64_t tot = prefix + block_total;
             counters[kRenKeysLo] = (uint32_t)tot;
             counters[kRenKeysHi] = (uint32_t)(tot >> 32);
+            // a frame whose keys do not fit leaves holes in the key buffer: it
+            // then sorts, bins and blends nothing (and is flagged)
+            counters[kRenKeysEff] = (uint32_t)(tot <= key_cap ? tot : 0);
+            if (tot > key_cap) atomicOr(&counters[kRenErr], kErrOverflow);
         }
     }
     __syncthreads();
@@ -186,25 +191,30 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
 }
 
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
-                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters)
+                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap)
 {
     uint64_t blocks = (max_n + kScanPart - 1) / kScanPart;
     if (blocks < 1) blocks = 1;
+    if (key_cap > 0xffffffffull) key_cap = 0xffffffffull;
     hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)blocks), dim3(kScanThreads), 0, st, tiles, order, n_dev,
-                       offsets, status, counters);
+                       offsets, status, counters, key_cap);
 }
 
 // ---------------------------------------------------------------------------
 // key emission: one key per tile of every row span of the support
 // ---------------------------------------------------------------------------
 template <bool DEPTH_FIRST>
-__global__ void __launch_bounds__(256) emit_kernel(uint32_t n, const uint32_t *__restrict__ order,
+__global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ n_dev, uint32_t max_n,
+                                                   const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ tiles,
                                                    const uint32_t *__restrict__ offsets,
                                                    const uint2 *__restrict__ rect, const BinRec *__restrict__ bin,
-                                                   uint32_t tiles_x, uint64_t key_cap, void *__restrict__ keys_v,
-                                                   uint32_t *__restrict__ vals, uint32_t *err)
+                                                   const FrameDev *__restrict__ fd, uint64_t key_cap,
+                                                   void *__restrict__ keys_v, uint32_t *__restrict__ vals,
+                                                   uint32_t *err)
 {
+    const uint32_t n = min(*n_dev, max_n);
+    const uint32_t tiles_x = fd->cam.tiles_x;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         const uint32_t t = DEPTH_FIRST ? order[j] : j;
@@ -237,15 +247,15 @@ __global__ void __launch_bounds__(256) emit_kernel(uint32_t n, const uint32_t *_
     }
 }
 
-void launch_emit64(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
-                   const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals,
-                   uint32_t *err)
+void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
+                   const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
+                   uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err)
 {
-    if (n == 0) return;
-    uint64_t blocks = (n + 255) / 256;
+    if (max_n == 0) return;
+    uint64_t blocks = (max_n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(emit_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, st, n, (const uint32_t *)nullptr,
-                       tiles, offsets, rect, bin, tiles_x, key_cap, (void *)keys, vals, err);
+    hipLaunchKernelGGL(emit_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, st, n_dev, (uint32_t)max_n,
+                       (const uint32_t *)nullptr, tiles, offsets, rect, bin, fd, key_cap, (void *)keys, vals, err);
 }
 
 // Depth-first emission.  Every lane takes one depth rank; its keys (one per
@@ -286,14 +296,17 @@ __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, int passes, u
 }
 
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
-    uint32_t n, const uint32_t *__restrict__ order, const uint32_t *__restrict__ tiles,
-    const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect, const BinRec *__restrict__ bin,
-    uint32_t tiles_x, uint64_t key_cap, int passes, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-    uint32_t *__restrict__ hist, uint32_t *err)
+    const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
+    const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
+    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, int passes,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
 {
     __shared__ uint32_t s_d0[257];
     __shared__ uint32_t s_h[2 * 256];
     __shared__ uint32_t s_all;
+    const uint32_t n = min(*n_dev, max_n);
+    if (blockIdx.x * kEmitThreads >= n) return;  // whole workgroup past the end
+    const uint32_t tiles_x = fd->cam.tiles_x;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     for (int i = tid; i < 257; i += kEmitThreads) s_d0[i] = 0u;
     for (int i = tid; i < 2 * 256; i += kEmitThreads) s_h[i] = 0u;
@@ -397,14 +410,15 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
             if (s_h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], s_h[(p - 1) * 256 + i]);
 }
 
-void launch_emit32(hipStream_t st, uint32_t n, const uint32_t *order, const uint32_t *tiles, const uint32_t *offsets,
-                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, int passes,
-                   uint32_t *keys, uint32_t *vals, uint32_t *hist, uint32_t *err)
+void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
+                   const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
+                   const FrameDev *fd, uint64_t key_cap, int passes, uint32_t *keys, uint32_t *vals, uint32_t *hist,
+                   uint32_t *err)
 {
-    if (n == 0) return;
-    const uint32_t blocks = (n + kEmitThreads - 1) / kEmitThreads;
-    hipLaunchKernelGGL(emit32_kernel, dim3(blocks), dim3(kEmitThreads), 0, st, n, order, tiles, offsets, rect,
-                       bin, tiles_x, key_cap, passes, keys, vals, hist, err);
+    if (max_n == 0) return;
+    const uint32_t blocks = (uint32_t)((max_n + kEmitThreads - 1) / kEmitThreads);
+    hipLaunchKernelGGL(emit32_kernel, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order, tiles,
+                       offsets, rect, bin, fd, key_cap, passes, keys, vals, hist, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -418,7 +432,7 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const K *__restrict__ ke
     __shared__ uint32_t s_h[8 * kRadix];
     for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x) s_h[i] = 0;
     __syncthreads();
-    const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
+    const uint64_t n = n_dev ? min((uint64_t)*n_dev, n_host) : n_host;
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -439,23 +453,12 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const K *__restrict__ ke
 }
 
 template <typename K>
-void launch_sort_hist(hipStream_t st, const K *keys, uint64_t n, int passes, uint32_t *hist)
+void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist)
 {
     if (n == 0) return;
     uint64_t blocks = (n + 256 * 16 - 1) / (256 * 16);
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, (const uint32_t *)nullptr,
-                       n, passes, hist);
-}
-
-void launch_sort_hist_dev(hipStream_t st, const uint32_t *keys, const uint32_t *n_dev, uint64_t max_n, int passes,
-                          uint32_t *hist)
-{
-    uint64_t blocks = (max_n + 256 * 16 - 1) / (256 * 16);
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(sort_hist_kernel<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, n_dev, max_n,
-                       passes, hist);
+    hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, n_dev, n, passes, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,8 +477,9 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
                                                                  uint32_t *__restrict__ vals_out,
                                                                  const uint32_t *__restrict__ n_dev, uint32_t n_host,
                                                                  int shift, const uint32_t *__restrict__ hist,
-                                                                 uint64_t *status, uint32_t epoch, uint32_t *ticket,
-                                                                 uint32_t *err)
+                                                                 uint64_t *status,
+                                                                 const uint32_t *__restrict__ epoch_dev,
+                                                                 uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
 {
     constexpr int NW = kSortThreads / kWave;           // waves per block
     constexpr int WAVE_KEYS = kSortPart / NW;          // consecutive keys owned by a wave
@@ -489,7 +493,8 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
     __shared__ uint32_t s_ticket;
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint32_t n = n_dev ? *n_dev : n_host;
+    const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+    const uint32_t epoch = epoch_dev ? *epoch_dev + epoch_arg : epoch_arg;
     for (int i = tid; i < NW * kRadix; i += kSortThreads) (&s_whist[0][0])[i] = 0u;
     if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -594,24 +599,14 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
 
 template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
-                      uint64_t n, int pass, const uint32_t *hist, uint64_t *status, uint32_t epoch, uint32_t *ticket,
-                      uint32_t *err)
+                      const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
+                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err)
 {
     if (n == 0) return;
     const uint32_t nparts = (uint32_t)((n + kSortPart - 1) / kSortPart);
     hipLaunchKernelGGL(sort_pass_kernel<K>, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
-                       vals_out, (const uint32_t *)nullptr, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
-                       status, epoch, ticket, err);
-}
-
-void launch_sort_pass_dev(hipStream_t st, const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
-                          uint32_t *vals_out, const uint32_t *n_dev, uint64_t max_n, int pass, const uint32_t *hist,
-                          uint64_t *status, uint32_t epoch, uint32_t *ticket, uint32_t *err)
-{
-    uint32_t nparts = (uint32_t)((max_n + kSortPart - 1) / kSortPart);
-    if (nparts < 1) nparts = 1;
-    hipLaunchKernelGGL(sort_pass_kernel<uint32_t>, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
-                       vals_out, n_dev, 0u, pass * kRadixBits, hist + pass * kRadix, status, epoch, ticket, err);
+                       vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix, status, epoch_dev, epoch,
+                       ticket, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -631,29 +626,32 @@ __device__ __forceinline__ uint32_t lower_bound_tile(const K *__restrict__ keys,
 }
 
 template <typename K>
-__global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, uint32_t n, int shift,
-                                                          uint32_t n_tiles, uint2 *__restrict__ ranges)
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
+                                                          int shift, uint32_t n_tiles, uint2 *__restrict__ ranges)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
+    const uint32_t n = *n_dev;
     ranges[t] = make_uint2(lower_bound_tile(keys, n, shift, t), lower_bound_tile(keys, n, shift, t + 1));
 }
 
 template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint32_t n_tiles, uint2 *ranges)
+void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
+                        uint2 *ranges)
 {
-    if (n == 0) return;
-    hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, (uint32_t)n, shift,
+    hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, n_dev, shift,
                        n_tiles, ranges);
 }
 
-template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint32_t *);
-template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, uint64_t, int, uint32_t *);
+template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *);
+template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
-                                         uint64_t, int, const uint32_t *, uint64_t *, uint32_t, uint32_t *, uint32_t *);
+                                         const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *);
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
-                                         uint64_t, int, const uint32_t *, uint64_t *, uint32_t, uint32_t *, uint32_t *);
-template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, uint64_t, int, uint32_t, uint2 *);
-template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, uint64_t, int, uint32_t, uint2 *);
+                                         const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *);
+template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *);
+template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *);
 
 }  // namespace v3dg

@@ -43,6 +43,19 @@ struct CamArgs {
     uint32_t width, height, tiles_x, tiles_y;
 };
 
+// Per-frame state of a render context in device memory.  The first kernel of
+// a frame writes it (or, in a replayed graph, the host copies it in before the
+// replay); every later kernel of the frame reads camera, image and sort epoch
+// from here, so a captured chain of launches serves any camera of its size.
+struct FrameDev {
+    CamArgs cam;
+    float *image;        // H x W x 4 FP32 RGBA, caller-owned
+    uint32_t epoch;      // look-back epoch base of the frame's sorts (advanced by kEpochsPerFrame)
+    uint32_t pad;
+};
+constexpr uint32_t kEpochsPerFrame = 8;    // depth sort passes 0..3, tile sort passes 4..7
+constexpr uint32_t kEpochLimit = 1u << 30; // width of the epoch field of a sort look-back word
+
 // Look-back status words: two flag bits above the payload.
 constexpr uint64_t kFlagAgg = 1ull;
 constexpr uint64_t kFlagInc = 2ull;
@@ -70,7 +83,8 @@ enum RenderCounter : int {
     kRenTicketDepth = 16, // 4 passes of the depth sort
     kRenHist = 32,        // 8 passes x 256 bins
     kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
-    kRenCounters = 32 + 12 * 256
+    kRenKeysEff = 32 + 12 * 256,   // keys the frame's buffers hold: min(total, capacity)
+    kRenCounters = 32 + 12 * 256 + 32
 };
 
 // Error flag bits
@@ -121,20 +135,50 @@ __device__ __forceinline__ bool tile_row_span(const BinRec &b, uint32_t ty, uint
 }
 
 // ---- launch wrappers (implemented in the .hip files) ----------------------
-void launch_frame_setup(hipStream_t st, const CamArgs &cam, const double *T, const float *inst_scale,
-                        uint32_t n_inst, InstRec *itab, uint32_t *clear, uint64_t n_clear);
-
 // select.hip
+// Render set-up: itab from the camera and the instances, clearing of the
+// frame's counters and look-back words, and the frame state: with from_fd the
+// camera is read from fd (already copied in), otherwise cam/image are written
+// there.  bump_epoch advances fd->epoch by kEpochsPerFrame.
+void launch_frame_setup(hipStream_t st, const CamArgs &cam, float *image, FrameDev *fd, bool from_fd, bool bump_epoch,
+                        const double *T, const float *inst_scale, uint32_t n_inst, InstRec *itab, uint32_t *clear,
+                        uint64_t n_clear);
 constexpr int kSelThreads = 256;
 constexpr int kSelItems = 8;
 constexpr int kSelPart = kSelThreads * kSelItems;
-void launch_select(hipStream_t st, const float4 *self_sph, const float4 *par_sph, const uint2 *rowinfo,
-                   const InstRec *itab, uint32_t n_clusters, uint32_t n_inst, float K, float tau,
-                   uint32_t *gid_out, uint32_t *slot_off_out, uint64_t *status, uint32_t *counters);
+// One selection request: its asset tables, frame records and outputs.
+struct SelReq {
+    const float4 *self_sph, *par_sph;
+    const uint2 *rowinfo;
+    const InstRec *itab;
+    uint32_t *gid, *slot_off;
+    uint64_t *status;
+    uint32_t *counters;       // kSelCounters words
+    uint32_t *slot_row, *slot_inst;
+    uint32_t NC, n_inst;
+    float K, tau;
+    uint32_t part_begin;      // first partition of this request in the batch
+    uint32_t nparts;
+};
+// Set-up of a batch of selection requests (frame records + clearing).
+struct SelSetup {
+    CamArgs cam;
+    const double *T;
+    const float *inst_scale;
+    InstRec *itab;
+    uint32_t *clear;
+    uint32_t n_inst, n_clear;
+};
+// one request, ticket in req.counters[kSelTicket]
+void launch_select(hipStream_t st, const SelReq &req);
+// A batch of requests (device arrays setups[n_req], reqs[n_req]): one set-up
+// launch, one persistent selection launch over all their partitions (claimed
+// in ticket order from *batch_ticket), and one expansion launch.
+void launch_select_batch(hipStream_t st, const SelSetup *setups, const SelReq *reqs, uint32_t n_req,
+                         uint32_t total_parts, uint32_t max_inst, uint32_t max_clear, uint32_t *batch_ticket);
 void launch_expand(hipStream_t st, const uint32_t *gid, const uint32_t *slot_off, const uint2 *rowinfo,
                    uint32_t n_clusters, const uint32_t *counters, uint32_t max_clusters, uint32_t *slot_row,
                    uint32_t *slot_inst);
-
 // project.hip
 struct ProjectOut {
     float4 *splat;      // 3 float4 per slot: (mx,my,A,B) (C,o,r,g) (b,depth,hx,hy)
@@ -145,54 +189,54 @@ struct ProjectOut {
     uint32_t *dkey;     // depth sort key: FP32 depth bits, 0xffffffff when culled
     uint32_t *dval;     // slot index (sort payload)
 };
-void launch_project(hipStream_t st, const CamArgs &cam, const Attribs &attr, int precision, int sh_degree,
+void launch_project(hipStream_t st, const FrameDev *fd, const Attribs &attr, int precision, int sh_degree,
                     const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
                     uint64_t max_slots, const InstRec *itab, ProjectOut out);
-
 // sort.hip
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanPart = kScanThreads * kScanItems;
-// exclusive scan of tiles[order[j]] (order may be NULL: identity)
+// exclusive scan of tiles[order[j]] (order may be NULL: identity); the total
+// goes to kRenKeysLo/Hi and to kRenKeysEff when it is at most key_cap (else
+// kRenKeysEff = 0 and kErrOverflow is raised: the frame's later steps then
+// have no keys to work on)
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
-                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters);
+                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap);
 // 64-bit keys (tile << 32 | depth bits), slot order
-void launch_emit64(hipStream_t st, uint32_t n, const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect,
-                   const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, uint64_t *keys, uint32_t *vals,
-                   uint32_t *err);
+void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
+                   const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
+                   uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err);
 // 32-bit tile keys in depth order (order[j] = slot of depth rank j), with the
 // digit histograms of the tile sort (passes <= 3) accumulated into hist
-void launch_emit32(hipStream_t st, uint32_t n, const uint32_t *order, const uint32_t *tiles, const uint32_t *offsets,
-                   const uint2 *rect, const BinRec *bin, uint32_t tiles_x, uint64_t key_cap, int passes,
-                   uint32_t *keys, uint32_t *vals, uint32_t *hist, uint32_t *err);
-// device-side count variants used by the depth sort (grid sized for max_n)
-void launch_sort_hist_dev(hipStream_t st, const uint32_t *keys, const uint32_t *n_dev, uint64_t max_n, int passes,
-                          uint32_t *hist);
-void launch_sort_pass_dev(hipStream_t st, const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
-                          uint32_t *vals_out, const uint32_t *n_dev, uint64_t max_n, int pass, const uint32_t *hist,
-                          uint64_t *status, uint32_t epoch, uint32_t *ticket, uint32_t *err);
-
+void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
+                   const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
+                   const FrameDev *fd, uint64_t key_cap, int passes, uint32_t *keys, uint32_t *vals, uint32_t *hist,
+                   uint32_t *err);
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
 constexpr int kSortPart = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 256;
+// Digit histograms of all passes; the key count is n_dev ? *n_dev : n.
 template <typename K>
-void launch_sort_hist(hipStream_t st, const K *keys, uint64_t n, int passes, uint32_t *hist);
+void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist);
+// One onesweep pass over n_dev ? *n_dev : n keys (grid sized for n); the
+// look-back epoch is *epoch_dev + epoch when epoch_dev is given, else epoch.
 template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
-                      uint64_t n, int pass, const uint32_t *hist, uint64_t *status, uint32_t epoch,
-                      uint32_t *ticket, uint32_t *err);
+                      const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
+                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err);
 template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, uint64_t n, int shift, uint32_t n_tiles, uint2 *ranges);
-
+void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
+                        uint2 *ranges);
 // blend.hip
 constexpr int kChunk = 2048;            // keys per chunk of a long tile list
-void launch_blend(hipStream_t st, const CamArgs &cam, const float4 *splat, const uint32_t *vals, const uint2 *ranges,
-                  uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
-                  float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk, float *image,
+// max_chunks bounds the chunks the plan may create (more raise kErrOverflow
+// and blend only the first kChunk keys of every tile)
+void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat, const uint32_t *vals,
+                  const uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items,
+                  uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk,
                   unsigned long long *pairs);
-
 // generic fill
 void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);
 

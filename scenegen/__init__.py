@@ -515,3 +515,45 @@ def flythrough_cameras(n_frames: int = 300, seed: int = 103, width: int = 1920, 
         fwd = np.array([d[0] * math.cos(pitch), d[1] * math.cos(pitch), -math.sin(pitch)])
         cams.append(look_at(p, p + fwd, width, height, fov_x))
     return cams
+
+
+# ---- serving workload -------------------------------------------------------------
+SERVING_LEAVES_M = (1, 2, 4, 6, 8, 12, 16, 20)
+SERVING_RESOLUTIONS = ((1280, 720), (1920, 1080), (3840, 2160))
+SERVING_TOLERANCES = (1.0, 4.0)
+
+
+def serving_scenes(seed: int = 500, base_leaves: int = 1 << 18):
+    """Eight scenes of {1, 2, 4, 6, 8, 12, 16, 20}M leaves, each composed of
+    instances of its own SH3 base asset (2 + j ellipsoids for scene j) on a
+    grid, the way the paper composes its large scenes from instanced assets.
+    Returns [(asset, instances (N,3,4), grid extent)]."""
+    out = []
+    for j, m in enumerate(SERVING_LEAVES_M):
+        n_inst = m * (1 << 20) // base_leaves
+        asset = cached_asset(base_leaves, 3, seed + j, n_ellipsoids=2 + j)
+        side = int(math.ceil(math.sqrt(n_inst)))
+        T = grid_instances(side, 1.5, 0.2, seed + 100 + j)[:n_inst]
+        out.append((asset, T, side * 1.5))
+    return out
+
+
+def serving_requests(n: int, rate: float, extents, seed: int):
+    """n camera requests with Poisson arrivals at `rate` per second (rate 0:
+    all at t = 0): scene uniform, resolution uniform over 720p / 1080p / 2160p,
+    tolerance uniform over {1, 4}, camera on an orbit around the scene's grid
+    (distance log-uniform in [0.35, 2] x extent, elevation 15-75 deg, fov_x pi/4)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n)) if rate > 0 else np.zeros(n)
+    reqs = []
+    for i in range(n):
+        j = int(rng.integers(0, len(extents)))
+        w, h = SERVING_RESOLUTIONS[int(rng.integers(0, len(SERVING_RESOLUTIONS)))]
+        tau = SERVING_TOLERANCES[int(rng.integers(0, len(SERVING_TOLERANCES)))]
+        L = extents[j]
+        d = L * math.exp(rng.uniform(math.log(0.35), math.log(2.0)))
+        az = rng.uniform(0.0, 2 * math.pi)
+        el = math.radians(float(rng.choice([15, 30, 45, 60, 75])))
+        eye = d * np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+        reqs.append(dict(t=float(t[i]), scene=j, cam=look_at(eye, (0.0, 0.0, 0.0), w, h, math.pi / 4), tau=tau))
+    return reqs

@@ -1,0 +1,171 @@
+"""The serving path (v3dg_server_*) through the C ABI.
+
+Every request's image must equal, bit for bit, what v3dg_select +
+v3dg_render produce for it alone (whose parity with the oracle the other GPU
+tests establish), whatever the mix of scenes, image sizes and tolerances in
+flight, with and without graph replay, and after key-capacity retries.
+"""
+import numpy as np
+import pytest
+
+import paper_2505_06523_amd as v
+import scenegen as sg
+from tests import helpers as H
+from tests.test_gpu_parity import _say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    v.lib()
+    return _t
+
+
+@pytest.fixture(scope="module")
+def scenes(torch):
+    a0 = sg.make_asset(16384, 0, 1)
+    a1 = sg.make_asset(8192, 3, 31)
+    a2 = H.stacked_splats(6000, 5, (0.05, 0.5))
+    out = [v.Scene(a0), v.Scene(a1, sg.grid_instances(2, 1.0, 0.2, 5)), v.Scene(a2)]
+    yield out
+    for sc in out:
+        sc.close()
+
+
+def _requests(rng, n):
+    shapes = [(200, 150), (333, 250), (640, 360)]
+    reqs = []
+    for i in range(n):
+        k = int(rng.integers(0, 3))
+        w, h = shapes[int(rng.integers(0, 3))]
+        if k == 2:
+            cam = H.identity_camera(w, h, 300.0 * w / 200.0, bg=(0.1, 0.2, 0.3))
+        else:
+            cam = H.random_camera_near(rng, w, h, dist=(0.8, 6.0))
+        tau = [0.0, 1.0, 50.0][int(rng.integers(0, 3))]
+        reqs.append((k, cam, tau))
+    return reqs
+
+
+def _standalone(scenes, torch, reqs):
+    ref = []
+    for k, cam, tau in reqs:
+        sc = scenes[k]
+        sel = sc.select(cam, tau)
+        img = sc.render(cam, sel).clone()
+        ref.append((img, sel.info()[1]))
+        sel.free()
+    torch.cuda.synchronize()
+    return ref
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_server_images_equal_standalone(scenes, torch, use_graphs):
+    rng = np.random.default_rng(11 + int(use_graphs))
+    reqs = _requests(rng, 30)
+    ref = _standalone(scenes, torch, reqs)
+    srv = v.Server(scenes, n_contexts=4, max_batch=8, use_graphs=use_graphs)
+    tickets = {}
+    done = []
+    # submit in waves with eager work on the default stream in between, so
+    # that graphs replay several times interleaved with other launches
+    for wave in range(3):
+        for i in range(wave * 10, wave * 10 + 10):
+            k, cam, tau = reqs[i]
+            t, _ = srv.submit(k, cam, tau)
+            tickets[t] = i
+        done.extend(srv.poll())
+        scenes[0].render(reqs[0][1], scenes[0].select(reqs[0][1], 1.0))
+        torch.cuda.synchronize()
+    done.extend(srv.drain())
+    st = srv.stats()
+    _say("server graphs=%s: %s" % (use_graphs, st))
+    assert len(done) == len(reqs)
+    for r in done:
+        i = tickets[r["ticket"]]
+        assert r["status"] == 0, r
+        img, n_slots = ref[i]
+        assert r["n_slots"] == n_slots, i
+        assert torch.equal(r["image"], img), (i, reqs[i][0], reqs[i][2])
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["batches"] >= 3 and st["batched_requests"] == len(reqs) + st["retries"]
+    if use_graphs:
+        assert st["graph_launches"] == len(reqs) + st["retries"]
+        assert 0 < st["graph_captures"] <= st["graph_launches"]
+    else:
+        assert st["graph_launches"] == 0
+    srv.close()
+
+
+def test_server_retries_after_key_overflow(scenes, torch):
+    rng = np.random.default_rng(5)
+    reqs = _requests(rng, 12)
+    ref = _standalone(scenes, torch, reqs)
+    srv = v.Server(scenes, n_contexts=3, max_batch=4, keys_per_pixel=1)  # too few keys at first
+    tickets = {}
+    for i, (k, cam, tau) in enumerate(reqs):
+        t, _ = srv.submit(k, cam, tau)
+        tickets[t] = i
+    done = srv.drain()
+    st = srv.stats()
+    _say("retries: %s" % st)
+    assert st["retries"] > 0
+    assert sum(r["retries"] for r in done) == st["retries"]
+    for r in done:
+        i = tickets[r["ticket"]]
+        assert r["status"] == 0
+        assert torch.equal(r["image"], ref[i][0]), i
+    srv.close()
+
+
+def test_server_budget_limits_contexts(scenes, torch):
+    rng = np.random.default_rng(9)
+    reqs = [r for r in _requests(rng, 60) if r[1].width == 640][:8]
+    ref = _standalone(scenes, torch, reqs)
+    probe = v.Server(scenes, n_contexts=1, max_batch=1)
+    base = probe.stats()["workspace_bytes"]
+    probe.submit(*reqs[0])
+    probe.drain()
+    one = probe.stats()["workspace_bytes"]  # one context holding a 640x360 frame
+    probe.close()
+    with pytest.raises(v.V3DGError) as ei:
+        v.Server(scenes, n_contexts=4, max_batch=4, hbm_budget_bytes=base // 2)
+    assert ei.value.code == v.V3DG_ERR_OOM
+    budget = one + base // 2  # room for one such context, not for a second one
+    srv = v.Server(scenes, n_contexts=8, max_batch=8, hbm_budget_bytes=budget)
+    tickets = {}
+    for i, (k, cam, tau) in enumerate(reqs):
+        t, _ = srv.submit(k, cam, tau)
+        tickets[t] = i
+    done = srv.drain()
+    st = srv.stats()
+    _say("budget %d (one context %d): %s" % (budget, one, st))
+    assert st["contexts_live"] == 1
+    assert st["peak_workspace_bytes"] <= budget
+    assert len(done) == len(reqs)
+    for r in done:
+        assert r["status"] == 0
+        assert torch.equal(r["image"], ref[tickets[r["ticket"]]][0])
+    srv.close()
+
+
+def test_server_invalid_arguments(scenes, torch):
+    srv = v.Server(scenes, n_contexts=2, max_batch=2)
+    cam = H.identity_camera(64, 48, 100.0)
+    with pytest.raises(v.V3DGError):
+        srv.submit(7, cam, 1.0)
+    with pytest.raises(v.V3DGError):
+        srv.submit(0, cam, -1.0)
+    with pytest.raises(v.V3DGError):
+        srv.submit(0, cam, float("nan"))
+    bad = H.identity_camera(64, 48, 100.0)
+    bad.fx = 0.0
+    with pytest.raises(v.V3DGError):
+        srv.submit(0, bad, 1.0)
+    assert srv.poll() == []
+    srv.close()
+    with pytest.raises(v.V3DGError):
+        v.Server(scenes, n_contexts=0)
