@@ -50,36 +50,82 @@ struct Pix {
     uint32_t evaluated;   // (pixel, splat) pairs walked
 };
 
+// Stage one batch entry (the splat record of key i) into LDS with its
+// quarter mask.
+__device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid, const float4 &f0, const float4 &f1,
+                                            const float4 &f2, float bx0, float by0)
+{
+    uint32_t m = 0;
+    if (valid) {
+        const float lo = __log2f(f1.y);
+        sh.P0[tid] = make_float4(f0.x, f0.y, -0.5f * kLog2e * f0.z, -kLog2e * f0.w);
+        sh.P1[tid] = make_float4(-0.5f * kLog2e * f1.x, -(__log2f(255.0f) + lo), lo, 0.f);
+        sh.P2[tid] = make_float4(f1.z, f1.w, f2.x, 0.f);
+        const float hx = f2.z + 1.0f, hy = f2.w + 1.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x0 = bx0 + 8.0f * (float)(q & 1), y0 = by0 + 8.0f * (float)(q >> 1);
+            const bool hit = (f0.x + hx >= x0) && (f0.x - hx <= x0 + 7.0f) && (f0.y + hy >= y0) &&
+                             (f0.y - hy <= y0 + 7.0f);
+            m |= (uint32_t)hit << q;
+        }
+    }
+    sh.mask[tid] = (uint8_t)m;
+}
+
+// One splat against the lane's pixel; p is its base-2 quadratic form.
+__device__ __forceinline__ void composite(const BlendShared &sh, uint32_t j, float p, bool take, float &T, float &cr,
+                                          float &cg, float &cb, bool &active, bool &stopped)
+{
+    // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
+    const float ex = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + sh.P1[j].z);
+    const float alpha = take ? fminf(0.99f, ex) : 0.0f;
+    const float Tn = T * (1.0f - alpha);
+    const bool stop = take && Tn < 1e-4f;
+    const bool add = take && !stop;
+    const float4 col = sh.P2[j];
+    const float w = add ? alpha * T : 0.0f;
+    cr = fmaf(w, col.x, cr);
+    cg = fmaf(w, col.y, cg);
+    cb = fmaf(w, col.z, cb);
+    T = add ? Tn : T;
+    if (stop) active = false;
+    stopped = stop;
+}
+
 // Composite keys [b, e) of the tile into the lanes' pixels (every thread of
-// the workgroup calls this with the same range).
+// the workgroup calls this with the same range).  The splat records of the
+// next batch are gathered while the current one is walked, and the index of
+// the batch after that one is read ahead, so no walk waits on global memory.
 __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ splat,
                             const uint32_t *__restrict__ vals, float bx0, float by0, float pxc, float pyc, int wid,
                             int lane, BlendShared &sh, Pix &px)
 {
     const int tid = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
+    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0, f2 = f0;
+    if (b + tid < e) {
+        const float4 *sp = splat + 3 * (uint64_t)vals[b + tid];
+        f0 = sp[0];
+        f1 = sp[1];
+        f2 = sp[2];
+    }
+    uint32_t vnext = (b + kBlendThreads + tid < e) ? vals[b + kBlendThreads + tid] : 0u;
     for (uint32_t start = b; start < e; start += kBlendThreads) {
         if (__syncthreads_count(px.active) == 0) break;
-        const uint32_t i = start + tid;
-        uint32_t m = 0;
-        if (i < e) {
-            const float4 *sp = splat + 3 * (uint64_t)vals[i];
-            const float4 f0 = sp[0], f1 = sp[1], f2 = sp[2];
-            const float lo = __log2f(f1.y);
-            sh.P0[tid] = make_float4(f0.x, f0.y, -0.5f * kLog2e * f0.z, -kLog2e * f0.w);
-            sh.P1[tid] = make_float4(-0.5f * kLog2e * f1.x, -(__log2f(255.0f) + lo), lo, 0.f);
-            sh.P2[tid] = make_float4(f1.z, f1.w, f2.x, 0.f);
-            const float hx = f2.z + 1.0f, hy = f2.w + 1.0f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float x0 = bx0 + 8.0f * (float)(q & 1), y0 = by0 + 8.0f * (float)(q >> 1);
-                const bool hit = (f0.x + hx >= x0) && (f0.x - hx <= x0 + 7.0f) && (f0.y + hy >= y0) &&
-                                 (f0.y - hy <= y0 + 7.0f);
-                m |= (uint32_t)hit << q;
-            }
-        }
-        sh.mask[tid] = (uint8_t)m;
+        stage_entry(sh, tid, start + tid < e, f0, f1, f2, bx0, by0);
         __syncthreads();
+        // read ahead: records of the next batch, index of the one after
+        {
+            const uint32_t i1 = start + kBlendThreads + tid, i2 = i1 + kBlendThreads;
+            if (i1 < e) {
+                const float4 *sp = splat + 3 * (uint64_t)vnext;
+                f0 = sp[0];
+                f1 = sp[1];
+                f2 = sp[2];
+            }
+            vnext = i2 < e ? vals[i2] : 0u;
+        }
         // in-order compaction of this quarter's entries
         uint32_t cnt = 0;
 #pragma unroll
@@ -91,35 +137,35 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
         }
         __syncthreads();
         if (__ballot(px.active)) {
-            // the walk is uniform across the wavefront: entry j is the same for
-            // every lane; lanes differ only in whether they take the splat
+            // the walk is uniform across the wavefront: entries k, k+1 are the
+            // same for every lane; lanes differ only in whether they take them
             const bool was = px.active;
             uint32_t kend = cnt;
             float T = px.T, cr = px.cr, cg = px.cg, cb = px.cb;
             bool active = px.active;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t j = sh.idx[wid][k];
-                const float4 a = sh.P0[j];
-                const float4 c4 = sh.P1[j];
-                const float dx = a.x - pxc, dy = a.y - pyc;
-                const float p = fmaf(a.z * dx, dx, fmaf(a.w * dx, dy, c4.x * dy * dy));
-                const bool take = active && !(p < c4.y);  // alpha >= 1/255
-                if (__ballot(take) == 0) continue;
-                // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
-                const float ex = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + c4.z);
-                const float alpha = take ? fminf(0.99f, ex) : 0.0f;
-                const float Tn = T * (1.0f - alpha);
-                const bool stop = take && Tn < 1e-4f;
-                const bool add = take && !stop;
-                const float4 col = sh.P2[j];
-                const float w = add ? alpha * T : 0.0f;
-                cr = fmaf(w, col.x, cr);
-                cg = fmaf(w, col.y, cg);
-                cb = fmaf(w, col.z, cb);
-                T = add ? Tn : T;
-                if (stop) {
-                    active = false;
-                    kend = k + 1;
+            for (uint32_t k = 0; k < cnt; k += 2) {
+                const uint32_t pr = *reinterpret_cast<const uint16_t *>(&sh.idx[wid][k]);
+                const uint32_t j0 = pr & 0xffu, j1 = pr >> 8;
+                const bool two = k + 1 < cnt;
+                const float4 a0 = sh.P0[j0], a1 = sh.P0[j1];
+                const float2 c0 = *reinterpret_cast<const float2 *>(&sh.P1[j0]);
+                const float2 c1 = *reinterpret_cast<const float2 *>(&sh.P1[j1]);
+                const float dx0 = a0.x - pxc, dy0 = a0.y - pyc;
+                const float dx1 = a1.x - pxc, dy1 = a1.y - pyc;
+                const float p0 = fmaf(a0.z * dx0, dx0, fmaf(a0.w * dx0, dy0, c0.x * dy0 * dy0));
+                const float p1 = fmaf(a1.z * dx1, dx1, fmaf(a1.w * dx1, dy1, c1.x * dy1 * dy1));
+                const bool take0 = active && !(p0 < c0.y);  // alpha >= 1/255
+                const bool pass1 = two && !(p1 < c1.y);
+                if (__ballot(take0 || (active && pass1)) == 0) continue;
+                bool stopped = false;
+                if (__ballot(take0)) {
+                    composite(sh, j0, p0, take0, T, cr, cg, cb, active, stopped);
+                    if (stopped) kend = k + 1;
+                }
+                const bool take1 = active && pass1;
+                if (__ballot(take1)) {
+                    composite(sh, j1, p1, take1, T, cr, cg, cb, active, stopped);
+                    if (stopped) kend = k + 2;
                 }
                 if (__ballot(active) == 0) break;
             }

@@ -79,14 +79,23 @@ __device__ __forceinline__ float depth_z(const float *A, float px, float py, flo
     return z;
 }
 
-// FP64 redo of the 2D covariance for near-degenerate splats.
-__device__ __noinline__ bool cov2_fp64(const float *A, float px, float py, float pz, float z32, const float *q,
-                                       const float *s, const CamArgs &cam, double *abc)
+// FP64 redo of the 2D covariance for near-degenerate splats: (a, b, c) of
+// Sigma2 and its determinant.  Every argument is a value or a pointer to
+// global memory (no local array has its address taken, so nothing spills).
+struct Cov2d {
+    double a, b, c, det;
+};
+
+__device__ __noinline__ Cov2d cov2_fp64(const InstRec *__restrict__ ir, const FrameDev *__restrict__ fd, float px,
+                                        float py, float pz, float4 q4, float sx, float sy, float sz)
 {
+    const float *A = ir->A;
+    const CamArgs &cam = fd->cam;
+    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const float s[3] = {sx, sy, sz};
     const double x = (double)A[0] * px + (double)A[1] * py + (double)A[2] * pz + (double)A[3];
     const double y = (double)A[4] * px + (double)A[5] * py + (double)A[6] * pz + (double)A[7];
     const double z = (double)A[8] * px + (double)A[9] * py + (double)A[10] * pz + (double)A[11];
-    (void)z32;
     const double qn = 1.0 / sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
     const double qw = q[0] * qn, qx = q[1] * qn, qy = q[2] * qn, qz = q[3] * qn;
     const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
@@ -107,14 +116,15 @@ __device__ __noinline__ bool cov2_fp64(const float *A, float px, float py, float
         m1[j] = j00 * M[0 * 3 + j] + j02 * M[2 * 3 + j];
         m2[j] = j11 * M[1 * 3 + j] + j12 * M[2 * 3 + j];
     }
-    abc[0] = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
-    abc[1] = m1[0] * m2[0] + m1[1] * m2[1] + m1[2] * m2[2];
-    abc[2] = m2[0] * m2[0] + m2[1] * m2[1] + m2[2] * m2[2];
+    Cov2d r;
+    r.a = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
+    r.b = m1[0] * m2[0] + m1[1] * m2[1] + m1[2] * m2[2];
+    r.c = m2[0] * m2[0] + m2[1] * m2[1] + m2[2] * m2[2];
     const double c0 = m1[1] * m2[2] - m1[2] * m2[1];
     const double c1 = m1[2] * m2[0] - m1[0] * m2[2];
     const double c2 = m1[0] * m2[1] - m1[1] * m2[0];
-    abc[3] = c0 * c0 + c1 * c1 + c2 * c2;
-    return abc[3] > 0.0;
+    r.det = c0 * c0 + c1 * c1 + c2 * c2;
+    return r;
 }
 
 // attribute loads by storage precision: 0 FP32; 1 FP16 geometry + BF16 SH;
@@ -217,16 +227,16 @@ __global__ void __launch_bounds__(256) project_kernel(const FrameDev *__restrict
             cb = -b * inv;
             cc = a * inv;
         } else {
-            double abc[4];
-            if (!cov2_fp64(A, px, py, pz, z, q, s, cam, abc)) continue;
-            const double inv = 1.0 / abc[3];
-            ca = (float)(abc[2] * inv);
-            cb = (float)(-abc[1] * inv);
-            cc = (float)(abc[0] * inv);
-            a = (float)abc[0];
-            b = (float)abc[1];
-            c = (float)abc[2];
-            det_s = (float)abc[3];
+            const Cov2d r = cov2_fp64(itab + inst, fd, px, py, pz, make_float4(q[0], q[1], q[2], q[3]), s[0], s[1], s[2]);
+            if (!(r.det > 0.0)) continue;
+            const double inv = 1.0 / r.det;
+            ca = (float)(r.c * inv);
+            cb = (float)(-r.b * inv);
+            cc = (float)(r.a * inv);
+            a = (float)r.a;
+            b = (float)r.b;
+            c = (float)r.c;
+            det_s = (float)r.det;
         }
         const float mx = cam.fx * (x * rz) + cam.cx;
         const float my = cam.fy * (y * rz) + cam.cy;
