@@ -218,11 +218,13 @@ typedef struct {
  * V3DG_SORT_DEPTH_FIRST).  Both give bit-identical images. */
 int v3dg_set_sort_mode(v3dg_scene *scene, int mode);
 
-/* Stage timing with hipEvents on the scene's stream.  While on, every kernel
- * launch is bracketed by events.  Work counters are kept either way.
- * v3dg_collect_profile synchronises, fills *out with the totals since the
- * previous collect, and clears them. */
-int v3dg_set_profiling(v3dg_scene *scene, int on);
+/* Stage timing with hipEvents on the scene's stream.  stage_mask selects the
+ * stages whose launches are bracketed by events (bit s for stage s,
+ * V3DG_PROFILE_ALL for every stage, 0 for none).  Work counters are kept
+ * either way.  v3dg_collect_profile synchronises, fills *out with the totals
+ * since the previous collect, and clears them. */
+#define V3DG_PROFILE_ALL 0x7ff
+int v3dg_set_profiling(v3dg_scene *scene, int stage_mask);
 int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
 
 /* Stable LSD radix sort of n (key, value) pairs in device memory by the low

@@ -30,6 +30,7 @@ V3DG_FP16_BF16SH = 1
 V3DG_FP16 = 2
 PRECISIONS = {"fp32": V3DG_FP32, "fp16_bf16sh": V3DG_FP16_BF16SH, "fp16": V3DG_FP16}
 V3DG_LOAD_REPAIR_NESTING = 1
+V3DG_PROFILE_ALL = 0x7FF
 V3DG_SORT_DEPTH_FIRST = 0
 V3DG_SORT_KEYS64 = 1
 STAGES = ["setup", "select", "expand", "project", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend",
@@ -252,8 +253,8 @@ def v3dg_set_sort_mode(scene, mode: int):
     _check(lib().v3dg_set_sort_mode(scene, int(mode)))
 
 
-def v3dg_set_profiling(scene, on: bool):
-    _check(lib().v3dg_set_profiling(scene, int(bool(on))))
+def v3dg_set_profiling(scene, stage_mask: int):
+    _check(lib().v3dg_set_profiling(scene, int(stage_mask)))
 
 
 def v3dg_collect_profile(scene) -> dict:
@@ -442,8 +443,13 @@ class Scene:
     def set_sort_mode(self, mode: int):
         v3dg_set_sort_mode(self.handle, mode)
 
-    def set_profiling(self, on: bool = True):
-        v3dg_set_profiling(self.handle, on)
+    def set_profiling(self, on=True):
+        """True / False, or an iterable of stage names to time."""
+        if on is True or on is False:
+            mask = V3DG_PROFILE_ALL if on else 0
+        else:
+            mask = sum(1 << STAGES.index(s) for s in on)
+        v3dg_set_profiling(self.handle, mask)
 
     def collect_profile(self) -> dict:
         return v3dg_collect_profile(self.handle)

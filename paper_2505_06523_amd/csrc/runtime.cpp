@@ -186,7 +186,7 @@ struct Ctx {
     v3dg_frame_stats last{};
     int last_buf = 0;
     int sort_mode = V3DG_SORT_DEPTH_FIRST;
-    bool profiling = false;
+    uint32_t profiling = 0;   // stages timed with events (bit per stage)
     v3dg_profile acc{};
     unsigned long long *pairs_dev = nullptr;
     std::vector<ProfRec> prof;
@@ -233,7 +233,7 @@ struct Stage {
     hipEvent_t b = nullptr;
     Stage(Ctx *sc, int st) : s(sc), stage(st)
     {
-        if (!s->profiling) return;
+        if (!(s->profiling >> stage & 1u)) return;
         hipEvent_t a = take();
         b = take();
         (void)hipEventRecord(a, s->stream);
@@ -1346,11 +1346,11 @@ int v3dg_set_sort_mode(v3dg_scene *s, int mode)
     return V3DG_OK;
 }
 
-int v3dg_set_profiling(v3dg_scene *s, int on)
+int v3dg_set_profiling(v3dg_scene *s, int stage_mask)
 {
     g_err.clear();
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
-    s->profiling = on != 0;
+    s->profiling = (uint32_t)stage_mask & V3DG_PROFILE_ALL;
     return V3DG_OK;
 }
 
