@@ -259,16 +259,20 @@ void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 }
 
 // Depth-first emission.  Every lane takes one depth rank; its keys (one per
-// tile its support reaches, row by row) go to a contiguous run of the output
-// starting at its scanned offset.  Lanes with at most kSmallKeys keys write
-// their own run; larger splats are written by the whole wavefront, one splat
-// at a time: lane r computes the span of tile row r, and the wavefront writes
-// each row's run with consecutive lanes on consecutive keys.  The digit
-// histograms of the tile sort are counted per row span: a span of consecutive
-// tile ids adds one to a run of low digits (a difference array over the 256
-// bins) and to one or two higher digits.
+// tile its support reaches, row by row) form a contiguous run of the output
+// starting at its scanned offset, so a workgroup's 256 ranks fill one
+// contiguous range.  Lanes with at most kSmallKeys keys produce their own run;
+// larger splats are produced by the whole wavefront, one splat at a time: lane
+// r computes the span of tile row r, and lane l then writes keys l, l + 64, ...
+// of the splat, finding its row by a binary search over the row prefix sums.
+// When the workgroup's range holds at most kStage keys it is assembled in LDS
+// and written out with contiguous stores.  The digit histograms of the tile
+// sort are counted per row span: a span of consecutive tile ids adds one to a
+// run of low digits (a difference array over the 256 bins) and to one or two
+// higher digits.
 constexpr int kEmitThreads = 256;
 constexpr uint32_t kSmallKeys = 8;
+constexpr uint32_t kStage = 2048;
 
 __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, int passes, uint32_t *s_d0, uint32_t *s_h,
                                            uint32_t *s_all)
@@ -295,32 +299,60 @@ __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, int passes, u
     }
 }
 
+struct EmitShared {
+    uint32_t d0[257];
+    uint32_t h[2 * 256];
+    uint32_t all;
+    uint32_t staged;                   // the workgroup's keys go through LDS
+    uint64_t lo, hi;                   // the workgroup's output range
+    uint32_t pre[kEmitThreads / kWave][kWave];   // per wavefront: row prefix sums
+    uint32_t base[kEmitThreads / kWave][kWave];  //   and first tile of each row
+    uint32_t key[kStage], val[kStage];
+};
+
+// key o of the output: into the LDS stage or straight to global memory
+__device__ __forceinline__ void put_key(EmitShared &sh, bool staged, uint64_t o, uint32_t key, uint32_t val,
+                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    if (staged) {
+        sh.key[o - sh.lo] = key;
+        sh.val[o - sh.lo] = val;
+    } else {
+        keys[o] = key;
+        vals[o] = val;
+    }
+}
+
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
     const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
     const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, int passes,
     uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
 {
-    __shared__ uint32_t s_d0[257];
-    __shared__ uint32_t s_h[2 * 256];
-    __shared__ uint32_t s_all;
+    __shared__ EmitShared sh;
     const uint32_t n = min(*n_dev, max_n);
     if (blockIdx.x * kEmitThreads >= n) return;  // whole workgroup past the end
     const uint32_t tiles_x = fd->cam.tiles_x;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    for (int i = tid; i < 257; i += kEmitThreads) s_d0[i] = 0u;
-    for (int i = tid; i < 2 * 256; i += kEmitThreads) s_h[i] = 0u;
-    if (tid == 0) s_all = 0u;
-    __syncthreads();
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    for (int i = tid; i < 257; i += kEmitThreads) sh.d0[i] = 0u;
+    for (int i = tid; i < 2 * 256; i += kEmitThreads) sh.h[i] = 0u;
+    if (tid == 0) sh.all = 0u;
     const uint32_t j = blockIdx.x * kEmitThreads + tid;
     const bool valid = j < n;
     const uint32_t t = valid ? order[j] : 0u;
     uint32_t nt = valid ? tiles[t] : 0u;
     const uint64_t off = valid ? offsets[j] : 0u;
+    // output range of the workgroup: from its first rank to its last rank's end
+    if (tid == 0) sh.lo = off;
+    if (valid && (j + 1 == n || tid == kEmitThreads - 1)) sh.hi = off + nt;
     if (off + nt > key_cap) {  // never with the capacity the host allocates
         atomicOr(err, kErrOverflow);
         nt = 0;
     }
+    __syncthreads();
+    if (tid == 0) sh.staged = (sh.hi <= key_cap && sh.hi - sh.lo <= kStage) ? 1u : 0u;
+    __syncthreads();
+    const bool staged = sh.staged != 0u;
     uint2 rc = make_uint2(0u, 0u);
     BinRec b{};
     if (nt) {
@@ -335,10 +367,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
         for (uint32_t ty = ty0; ty <= ty1 && o < end; ++ty) {
             uint32_t lo, hi;
             if (!tile_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
-            count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
+            count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, sh.d0, sh.h, &sh.all);
             for (uint32_t tx = lo; tx <= hi && o < end; ++tx) {
-                keys[o] = ty * tiles_x + tx;
-                vals[o] = t;
+                put_key(sh, staged, o, ty * tiles_x + tx, t, keys, vals);
                 ++o;
             }
         }
@@ -371,43 +402,51 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
                 uint32_t hi;
                 if (tile_row_span(bb, ty, bx0, bx1, &lo, &hi)) {
                     len = hi - lo + 1;
-                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
+                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, sh.d0, sh.h, &sh.all);
                 }
             }
             const uint32_t incl = wave_incl_scan_u32(len);
             const uint32_t pre = incl - len;
-            const uint32_t rows = min((uint32_t)kWave, by1 - rb + 1);
-            for (uint32_t r = 0; r < rows; ++r) {
-                const uint32_t len_r = __shfl(len, (int)r, kWave);
-                if (len_r == 0) continue;
-                const uint32_t base_tile = (rb + r) * tiles_x + __shfl(lo, (int)r, kWave);
-                const uint64_t o = bo + __shfl(pre, (int)r, kWave);
-                for (uint32_t c = (uint32_t)lane; c < len_r; c += kWave) {
-                    if (o + c < bend) {
-                        keys[o + c] = base_tile + c;
-                        vals[o + c] = bt;
-                    }
-                }
+            const uint32_t total = __shfl(incl, kWave - 1, kWave);
+            sh.pre[wid][lane] = pre;
+            sh.base[wid][lane] = ty * tiles_x + lo;
+            __builtin_amdgcn_wave_barrier();
+            // key q of this block of rows lies in the last row whose prefix is <= q
+            for (uint32_t q = (uint32_t)lane; q < total; q += kWave) {
+                uint32_t r = 0;
+#pragma unroll
+                for (uint32_t step = kWave / 2; step > 0; step >>= 1)
+                    if (sh.pre[wid][r + step] <= q) r += step;
+                const uint64_t o = bo + q;
+                if (o < bend) put_key(sh, staged, o, sh.base[wid][r] + (q - sh.pre[wid][r]), bt, keys, vals);
             }
-            bo += __shfl(incl, kWave - 1, kWave);
+            __builtin_amdgcn_wave_barrier();
+            bo += total;
         }
         if (bo != bend && lane == 0) atomicOr(err, kErrOverflow);  // counting and emission disagree
     }
     __syncthreads();
+    if (staged) {  // contiguous copy of the assembled range
+        const uint32_t cnt = (uint32_t)(sh.hi - sh.lo);
+        for (uint32_t i = tid; i < cnt; i += kEmitThreads) {
+            keys[sh.lo + i] = sh.key[i];
+            vals[sh.lo + i] = sh.val[i];
+        }
+    }
     // digit histograms: prefix of the difference array gives the low-digit counts
     if (tid < kWave) {
         uint32_t run = 0;
         for (int c = 0; c < 4; ++c) {
-            const uint32_t v = s_d0[c * kWave + tid];
+            const uint32_t v = sh.d0[c * kWave + tid];
             const uint32_t incl = wave_incl_scan_u32(v);
-            const uint32_t cntd = run + incl + s_all;
+            const uint32_t cntd = run + incl + sh.all;
             if (cntd) atomicAdd(&hist[c * kWave + tid], cntd);
             run += __shfl(incl, kWave - 1, kWave);
         }
     }
     for (int p = 1; p < passes; ++p)
         for (int i = tid; i < 256; i += kEmitThreads)
-            if (s_h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], s_h[(p - 1) * 256 + i]);
+            if (sh.h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], sh.h[(p - 1) * 256 + i]);
 }
 
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
