@@ -73,24 +73,23 @@ __device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid
     sh.mask[tid] = (uint8_t)m;
 }
 
-// One splat against the lane's pixel; p is its base-2 quadratic form.
-__device__ __forceinline__ void composite(const BlendShared &sh, uint32_t j, float p, bool take, float &T, float &cr,
-                                          float &cg, float &cb, bool &active, bool &stopped)
+// One splat against the lane's pixel, branch-free.  p is its base-2
+// quadratic form, P1 = (c, log2 threshold, log2 o, -), col its colour.  A
+// stopped pixel carries its final transmittance negated, so "active" is
+// T > 0 and needs no flag of its own.
+__device__ __forceinline__ void composite(float p, bool take, float log2o, const float4 &col, float &T, float &cr,
+                                          float &cg, float &cb)
 {
     // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
-    const float ex = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + sh.P1[j].z);
+    const float ex = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + log2o);
     const float alpha = take ? fminf(0.99f, ex) : 0.0f;
     const float Tn = T * (1.0f - alpha);
     const bool stop = take && Tn < 1e-4f;
-    const bool add = take && !stop;
-    const float4 col = sh.P2[j];
-    const float w = add ? alpha * T : 0.0f;
+    const float w = (take && !stop) ? alpha * T : 0.0f;
     cr = fmaf(w, col.x, cr);
     cg = fmaf(w, col.y, cg);
     cb = fmaf(w, col.z, cb);
-    T = add ? Tn : T;
-    if (stop) active = false;
-    stopped = stop;
+    T = stop ? -T : (take ? Tn : T);
 }
 
 // Composite keys [b, e) of the tile into the lanes' pixels (every thread of
@@ -141,40 +140,36 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
             // same for every lane; lanes differ only in whether they take them
             const bool was = px.active;
             uint32_t kend = cnt;
-            float T = px.T, cr = px.cr, cg = px.cg, cb = px.cb;
-            bool active = px.active;
+            float T = px.active ? px.T : -px.T, cr = px.cr, cg = px.cg, cb = px.cb;
             for (uint32_t k = 0; k < cnt; k += 2) {
                 const uint32_t pr = *reinterpret_cast<const uint16_t *>(&sh.idx[wid][k]);
-                const uint32_t j0 = pr & 0xffu, j1 = pr >> 8;
                 const bool two = k + 1 < cnt;
+                // an odd last entry is paired with itself (never taken twice):
+                // every record read belongs to this batch
+                const uint32_t j0 = pr & 0xffu, j1 = two ? pr >> 8 : j0;
                 const float4 a0 = sh.P0[j0], a1 = sh.P0[j1];
-                const float2 c0 = *reinterpret_cast<const float2 *>(&sh.P1[j0]);
-                const float2 c1 = *reinterpret_cast<const float2 *>(&sh.P1[j1]);
+                const float4 c0 = sh.P1[j0], c1 = sh.P1[j1];
                 const float dx0 = a0.x - pxc, dy0 = a0.y - pyc;
                 const float dx1 = a1.x - pxc, dy1 = a1.y - pyc;
                 const float p0 = fmaf(a0.z * dx0, dx0, fmaf(a0.w * dx0, dy0, c0.x * dy0 * dy0));
                 const float p1 = fmaf(a1.z * dx1, dx1, fmaf(a1.w * dx1, dy1, c1.x * dy1 * dy1));
-                const bool take0 = active && !(p0 < c0.y);  // alpha >= 1/255
-                const bool pass1 = two && !(p1 < c1.y);
-                if (__ballot(take0 || (active && pass1)) == 0) continue;
-                bool stopped = false;
-                if (__ballot(take0)) {
-                    composite(sh, j0, p0, take0, T, cr, cg, cb, active, stopped);
-                    if (stopped) kend = k + 1;
-                }
-                const bool take1 = active && pass1;
-                if (__ballot(take1)) {
-                    composite(sh, j1, p1, take1, T, cr, cg, cb, active, stopped);
-                    if (stopped) kend = k + 2;
-                }
-                if (__ballot(active) == 0) break;
+                const bool pass0 = !(p0 < c0.y), pass1 = two && !(p1 < c1.y);  // alpha >= 1/255
+                if (__ballot(T > 0.0f && (pass0 || pass1)) == 0) continue;
+                const float4 col0 = sh.P2[j0], col1 = sh.P2[j1];
+                const bool take0 = T > 0.0f && pass0;
+                composite(p0, take0, c0.z, col0, T, cr, cg, cb);
+                if (take0 && T < 0.0f) kend = k + 1;
+                const bool take1 = T > 0.0f && pass1;
+                composite(p1, take1, c1.z, col1, T, cr, cg, cb);
+                if (take1 && T < 0.0f) kend = k + 2;
+                if (__ballot(T > 0.0f) == 0) break;
             }
             if (was) px.evaluated += kend;
-            px.T = T;
+            px.active = T > 0.0f;
+            px.T = fabsf(T);
             px.cr = cr;
             px.cg = cg;
             px.cb = cb;
-            px.active = active;
         }
     }
 }
