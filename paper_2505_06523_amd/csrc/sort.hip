@@ -547,13 +547,27 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
     K key[ROUNDS];
     uint32_t val[ROUNDS];
     uint32_t dr[ROUNDS];  // digit | rank-in-wave << 8
+    // all loads first, so that the partition's 2 x 16 loads per lane are in
+    // flight together (ranking round by round would wait for each in turn)
+    if (part_base + (uint32_t)kSortPart <= n) {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            key[r] = keys_in[wave_base + r * kWave + lane];
+            val[r] = vals_in[wave_base + r * kWave + lane];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const uint32_t idx = wave_base + r * kWave + lane;
+            key[r] = idx < n ? keys_in[idx] : (K)0;
+            val[r] = idx < n ? vals_in[idx] : 0u;
+        }
+    }
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t idx = wave_base + r * kWave + lane;
         const bool valid = idx < n;
-        const K k = valid ? keys_in[idx] : (K)0;
-        key[r] = k;
-        val[r] = valid ? vals_in[idx] : 0u;
+        const K k = key[r];
         const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         const uint32_t rank_in_round = (uint32_t)__popcll(peers & lt_mask);
