@@ -17,7 +17,10 @@
 //
 // Long lists.  A few tiles of a near view hold tens of thousands of splats and
 // would keep one workgroup busy long after the rest of the frame is done.  A
-// list longer than kChunk keys is cut into chunks of kChunk:
+// list longer than kChunkFirst keys is cut into a first chunk of kChunkFirst
+// keys and further chunks of kChunk (the first chunk is longer because most
+// pixels of opaque content stop within it, which leaves the later chunks
+// nothing to do):
 //   blend_kernel  walks chunk 0 of every tile (with the stop rule);
 //   chunk_kernel  walks every other chunk in parallel, each from T = 1,
 //                 giving per pixel the chunk's colour C_c and transmittance T_c;
@@ -43,6 +46,17 @@ struct BlendShared {
     uint8_t mask[kBlendThreads];
     uint8_t idx[4][kBlendThreads];
 };
+
+// chunk geometry of a tile list of L keys
+__device__ __forceinline__ uint32_t n_chunks(uint32_t L)
+{
+    return L <= (uint32_t)kChunkFirst ? 1u : 1u + (L - kChunkFirst + kChunk - 1) / kChunk;
+}
+__device__ __forceinline__ uint32_t chunk_begin(uint32_t c) { return c == 0 ? 0u : kChunkFirst + (c - 1) * kChunk; }
+__device__ __forceinline__ uint32_t chunk_end(uint32_t c, uint32_t L)
+{
+    return min((uint32_t)kChunkFirst + c * (uint32_t)kChunk, L);
+}
 
 struct Pix {
     float T, cr, cg, cb;
@@ -235,8 +249,8 @@ __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *_
     for (uint32_t t = t0; t < t1; ++t) {
         const uint2 r = ranges[t];
         const uint32_t L = r.y > r.x ? r.y - r.x : 0u;
-        if (L > (uint32_t)kChunk) {
-            const uint32_t m = (L + kChunk - 1) / kChunk;
+        if (L > (uint32_t)kChunkFirst) {
+            const uint32_t m = n_chunks(L);
             nch += m;
             nit += m - 1;
         }
@@ -270,8 +284,8 @@ __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *_
     for (uint32_t t = t0; t < t1 && fits; ++t) {
         const uint2 r = ranges[t];
         const uint32_t L = r.y > r.x ? r.y - r.x : 0u;
-        if (L > (uint32_t)kChunk) {
-            const uint32_t m = (L + kChunk - 1) / kChunk;
+        if (L > (uint32_t)kChunkFirst) {
+            const uint32_t m = n_chunks(L);
             cbase[t] = ca;
             for (uint32_t c = 1; c < m; ++c) items[cb + c - 1] = make_uint2(t, c);
             ca += m;
@@ -285,7 +299,7 @@ __global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *_
 }
 
 // ---------------------------------------------------------------------------
-// pass 1: every tile, up to its first kChunk keys
+// pass 1: every tile, up to its first kChunkFirst keys
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
@@ -306,8 +320,9 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
     const uint2 rg = ranges[tile];
     Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u};
     const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
-    const bool long_list = end - rg.x > (uint32_t)kChunk && counters[kRenChunks] != 0u;
-    blend_range(rg.x, long_list ? rg.x + kChunk : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+    const bool long_list = end - rg.x > (uint32_t)kChunkFirst && counters[kRenChunks] != 0u;
+    blend_range(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
+                px);
     if (long_list)  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cbase[tile] * kBlendThreads + g.pix] =
             make_float4(px.cr, px.cg, px.cb, px.active ? px.T : -px.T);
@@ -343,8 +358,8 @@ __global__ void __launch_bounds__(kBlendThreads) chunk_kernel(const FrameDev *__
         const float4 s0 = scratch[base * kBlendThreads + g.pix];
         Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u};
         const bool was = px.active;
-        const uint32_t b = rg.x + c * kChunk;
-        blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        blend_range(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
+                    g.pyc, wid, lane, sh, px);
         scratch[(base + c) * kBlendThreads + g.pix] =
             make_float4(px.cr, px.cg, px.cb, (was && !px.active) ? -px.T : px.T);
         count_pairs(px, lane, pairs);
@@ -371,8 +386,8 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
     if (tile >= cam.tiles_x * cam.tiles_y) return;
     const uint2 rg = ranges[tile];
     const uint32_t L = rg.y > rg.x ? rg.y - rg.x : 0u;
-    if (L <= (uint32_t)kChunk || counters[kRenChunks] == 0u) return;
-    const uint32_t m = (L + kChunk - 1) / kChunk;
+    if (L <= (uint32_t)kChunkFirst || counters[kRenChunks] == 0u) return;
+    const uint32_t m = n_chunks(L);
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint64_t base = cbase[tile];
     for (uint32_t c = tid; c < m; c += kBlendThreads) need[base + c] = 0u;
@@ -437,8 +452,8 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         const bool mine = pend[base * kBlendThreads + g.pix] == c;
         const float4 st = scratch[base * kBlendThreads + g.pix];
         Pix px{st.w, st.x, st.y, st.z, mine, 0u};
-        const uint32_t b = rg.x + c * kChunk;
-        blend_range(b, min(b + kChunk, rg.y), splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        blend_range(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
+                    g.pyc, wid, lane, sh, px);
         // a pixel that, through rounding of the folded products, does not stop in
         // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
         if (mine) write_pixel(cam, g, px, image);

@@ -230,7 +230,8 @@ template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
                         uint2 *ranges);
 // blend.hip
-constexpr int kChunk = 2048;            // keys per chunk of a long tile list
+constexpr int kChunk = 2048;            // keys per chunk of a long tile list after the first
+constexpr int kChunkFirst = 4096;       // keys of the first chunk (walked by pass 1)
 // max_chunks bounds the chunks the plan may create (more raise kErrOverflow
 // and blend only the first kChunk keys of every tile)
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat, const uint32_t *vals,

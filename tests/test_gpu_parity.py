@@ -268,7 +268,7 @@ def test_image_parity_sh3_instances_background(torch):
 def test_long_tile_lists_chunked_blending(torch, opacity, seed):
     """Thousands of splats over a few tiles: lists far longer than one chunk,
     pixels that never saturate, and pixels that stop inside later chunks."""
-    a = H.stacked_splats(12000, seed, opacity)
+    a = H.stacked_splats(16000, seed, opacity)
     cam = H.identity_camera(72, 56, 300.0, bg=(0.1, 0.2, 0.3))
     T = sg.identity_instances(1)
     sc = v.Scene(a, T)
@@ -278,7 +278,7 @@ def test_long_tile_lists_chunked_blending(torch, opacity, seed):
     keys, _ = sc.sorted_keys()
     per_tile = np.bincount((keys >> np.uint64(32)).astype(np.int64))
     _say("long lists: keys %d, longest tile list %d" % (st["n_keys"], per_tile.max()))
-    assert per_tile.max() > 4 * 1024
+    assert per_tile.max() > 10 * 1024  # a first chunk of 4096 keys and at least three more of 2048
     ref, amb, _ = oracle.render(a, T, cam, sel.ids())
     check_image(img, ref, amb, "stacked o=%s" % (opacity,))
     sc.set_sort_mode(v.V3DG_SORT_KEYS64)

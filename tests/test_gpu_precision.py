@@ -95,7 +95,7 @@ def test_narrow_tier_projection_and_image_parity(torch, precision):
 
 @pytest.mark.parametrize("precision", NARROW)
 def test_narrow_tier_long_lists_and_determinism(torch, precision):
-    a = H.stacked_splats(12000, 6, (0.3, 0.95))
+    a = H.stacked_splats(16000, 6, (0.3, 0.95))
     aq = H.quantized_asset(a, precision)
     cam = H.identity_camera(72, 56, 300.0, bg=(0.1, 0.2, 0.3))
     T = sg.identity_instances(1)
