@@ -593,7 +593,7 @@ void run_sort(Ctx *c, KT *const kb[2], uint32_t *const vb[2], const uint32_t *n_
         Stage st(c, V3DG_STAGE_SORT_PASS);
         launch_sort_pass<KT>(c->stream, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n_dev, K, p, c->rcounters + kRenHist,
                              c->sort_status, &c->fdev->epoch, epoch_base + (uint32_t)p,
-                             c->rcounters + kRenTicketSort + p, c->rcounters + kRenErr);
+                             c->rcounters + kRenTicketSort + p, c->rcounters + kRenErr, K >= kSortWideFrom);
         cur ^= 1;
     }
     *out_buf = cur;
@@ -659,7 +659,8 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
             Stage st(c, V3DG_STAGE_DEPTH_SORT);
             launch_sort_pass<uint32_t>(c->stream, c->dkey[cur], c->dval[cur], c->dkey[cur ^ 1], c->dval[cur ^ 1], n_dev,
                                        S, p, c->rcounters + kRenHistDepth, c->sort_status, &c->fdev->epoch,
-                                       (uint32_t)p, c->rcounters + kRenTicketDepth + p, c->rcounters + kRenErr);
+                                       (uint32_t)p, c->rcounters + kRenTicketDepth + p, c->rcounters + kRenErr,
+                                       S >= kSortWideFrom);
             cur ^= 1;
         }
     }
@@ -1409,7 +1410,8 @@ int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t
         int cur = 0;
         for (int p = 0; p < passes; ++p) {
             launch_sort_pass<uint64_t>(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], nullptr, n, p, ctr + kRenHist,
-                                       status, nullptr, (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr);
+                                       status, nullptr, (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr,
+                                       false);
             cur ^= 1;
         }
         if (cur == 1) {

@@ -509,7 +509,7 @@ __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint3
     return ((uint64_t)epoch << 34) | (flag << 32) | v;
 }
 
-template <typename K>
+template <typename K, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__restrict__ keys_in,
                                                                  const uint32_t *__restrict__ vals_in,
                                                                  K *__restrict__ keys_out,
@@ -521,10 +521,11 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
                                                                  uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
 {
     constexpr int NW = kSortThreads / kWave;           // waves per block
-    constexpr int WAVE_KEYS = kSortPart / NW;          // consecutive keys owned by a wave
-    constexpr int ROUNDS = WAVE_KEYS / kWave;          // = kSortItems
-    __shared__ K s_keys[kSortPart];
-    __shared__ uint32_t s_vals[kSortPart];
+    constexpr int PART = kSortThreads * ITEMS;         // keys of a partition
+    constexpr int WAVE_KEYS = PART / NW;               // consecutive keys owned by a wave
+    constexpr int ROUNDS = WAVE_KEYS / kWave;          // = ITEMS
+    __shared__ K s_keys[PART];
+    __shared__ uint32_t s_vals[PART];
     __shared__ uint32_t s_whist[NW][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
@@ -538,9 +539,9 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
     if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint32_t p = s_ticket;
-    const uint32_t nparts = (n + kSortPart - 1) / kSortPart;
+    const uint32_t nparts = (n + PART - 1) / PART;
     if (p >= nparts) return;
-    const uint32_t part_base = p * (uint32_t)kSortPart;
+    const uint32_t part_base = p * (uint32_t)PART;
     const uint32_t wave_base = part_base + (uint32_t)wid * WAVE_KEYS;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
     uint32_t dr[ROUNDS];  // digit | rank-in-wave << 8
     // all loads first, so that the partition's 2 x 16 loads per lane are in
     // flight together (ranking round by round would wait for each in turn)
-    if (part_base + (uint32_t)kSortPart <= n) {
+    if (part_base + (uint32_t)PART <= n) {
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
             key[r] = keys_in[wave_base + r * kWave + lane];
@@ -634,9 +635,9 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
         }
     }
     __syncthreads();
-    const uint32_t n_here = (n - part_base) < (uint32_t)kSortPart ? (n - part_base) : (uint32_t)kSortPart;
+    const uint32_t n_here = (n - part_base) < (uint32_t)PART ? (n - part_base) : (uint32_t)PART;
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint32_t i = tid + r * kSortThreads;
         if (i < n_here) {
             const K k = s_keys[i];
@@ -653,13 +654,22 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
 template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
-                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err)
+                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide)
 {
     if (n == 0) return;
-    const uint32_t nparts = (uint32_t)((n + kSortPart - 1) / kSortPart);
-    hipLaunchKernelGGL(sort_pass_kernel<K>, dim3(nparts), dim3(kSortThreads), 0, st, keys_in, vals_in, keys_out,
-                       vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix, status, epoch_dev, epoch,
-                       ticket, err);
+    // wide partitions (8192 keys) for large 32-bit sorts: fewer partitions to
+    // look back over and longer digit runs to store
+    if (wide && sizeof(K) == 4) {
+        const uint32_t nparts = (uint32_t)((n + kSortPartWide - 1) / kSortPartWide);
+        hipLaunchKernelGGL((sort_pass_kernel<K, kSortItemsWide>), dim3(nparts), dim3(kSortThreads), 0, st, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
+                           status, epoch_dev, epoch, ticket, err);
+    } else {
+        const uint32_t nparts = (uint32_t)((n + kSortPart - 1) / kSortPart);
+        hipLaunchKernelGGL((sort_pass_kernel<K, kSortItems>), dim3(nparts), dim3(kSortThreads), 0, st, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
+                           status, epoch_dev, epoch, ticket, err);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -700,10 +710,10 @@ template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const ui
 template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
 template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *);
 template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *);
 

@@ -214,7 +214,10 @@ void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
                    uint32_t *err);
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
-constexpr int kSortPart = kSortThreads * kSortItems;
+constexpr int kSortPart = kSortThreads * kSortItems;  // partition (also the unit of look-back capacity)
+constexpr int kSortItemsWide = 32;      // keys per thread of wide partitions
+constexpr int kSortPartWide = kSortThreads * kSortItemsWide;
+constexpr uint64_t kSortWideFrom = 1u << 22;  // sorts of at least this many keys use wide partitions
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 256;
 // Digit histograms of all passes; the key count is n_dev ? *n_dev : n.
@@ -222,10 +225,11 @@ template <typename K>
 void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist);
 // One onesweep pass over n_dev ? *n_dev : n keys (grid sized for n); the
 // look-back epoch is *epoch_dev + epoch when epoch_dev is given, else epoch.
+// wide selects partitions of kSortPartWide keys (32-bit keys only).
 template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
-                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err);
+                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide);
 template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
                         uint2 *ranges);

@@ -167,11 +167,7 @@ def test_sort_pairs_matches_numpy_stable(torch, n, bits):
     assert np.array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
 
 
-def test_frame_keys_sorted_stable_and_complete(c1, torch):
-    a, sc = c1
-    cam = sg.single_camera_c1()
-    sel = sc.select(cam, 1.0)
-    sc.render(cam, sel)
+def _check_frame_keys(sc):
     st = sc.frame_stats()
     keys, vals = sc.sorted_keys()
     proj = sc.projection()
@@ -186,6 +182,15 @@ def test_frame_keys_sorted_stable_and_complete(c1, torch):
     assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), proj["depth"].view(np.uint32)[vals])
     tk = (keys >> np.uint64(32)) * np.uint64(1 << 32) + vals.astype(np.uint64)
     assert np.unique(tk).size == tk.size
+    return st
+
+
+def test_frame_keys_sorted_stable_and_complete(c1, torch):
+    a, sc = c1
+    cam = sg.single_camera_c1()
+    sel = sc.select(cam, 1.0)
+    sc.render(cam, sel)
+    _check_frame_keys(sc)
 
 
 def test_sort_modes_identical(c1, torch):
@@ -369,6 +374,20 @@ def test_c2_selection_bitexact_all_cameras(c2):
             assert np.array_equal(sel.ids(), ref), (ci, tau)
             n += 1
     _say("c2 selection: %d (camera, tau) cases bit-exact" % n)
+
+
+def test_c2_frame_keys_wide_partitions(c2, torch):
+    """A frame with more than 4M keys: the tile sort then uses 8192-key partitions."""
+    a, sc = c2
+    for cam in sg.orbit_cameras(64, 102):
+        sel = sc.select(cam, 1.0)
+        sc.render(cam, sel)
+        k = sc.frame_stats()["n_keys"]
+        if (1 << 22) <= k <= 24_000_000:
+            break
+    st = _check_frame_keys(sc)
+    _say("c2 wide-partition frame: %d keys checked" % st["n_keys"])
+    assert st["n_keys"] >= 1 << 22
 
 
 def test_c2_image_full_frame_parity(c2, torch):
