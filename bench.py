@@ -34,6 +34,11 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # min(0.99, .) (1); 1 - alpha (1); T (1 - alpha) (1); the 1e-4 test (1);
 # w = alpha T (1); three colour fma (3); T update (1) -> 24.
 BLEND_OPS_PER_PAIR = 24
+# HBM bytes per frame of the blend stage on this workload, from rocprofv3
+# FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the 256 timed frames
+# (profiles/hbm_counters_1M_sh3_1080p.md).  Valid only for the blending source
+# they were taken on: the bench reports null once blend.hip has changed.
+BLEND_TRAFFIC = dict(bytes_per_frame=603.5e6, blend_source_sha256_16="f065c9d48a1efb45")
 
 
 def log(*a):
@@ -92,6 +97,17 @@ def stage_bytes(P: dict, b_row: int) -> dict:
         "ranges": P["keys"] * kb + P["tiles"] * 8,
         "blend": P["keys"] * 52 + P["pixels"] * 16,
     }
+
+
+def measured_blend_traffic(args):
+    """HBM bytes per blend-stage launch from the committed counter runs, or None
+    when the workload or the blending source differ from what they measured."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_06523_amd", "csrc", "blend.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if args.quick or args.steps != 256 or sha != BLEND_TRAFFIC["blend_source_sha256_16"]:
+        return None
+    return BLEND_TRAFFIC["bytes_per_frame"]
 
 
 def run_frames(torch, scene, frames, img, full: bool, prof: bool):
@@ -370,7 +386,7 @@ def main():
         flops = P["pairs"] * BLEND_OPS_PER_PAIR
         ach = flops / n_dom / (t_dom / n_dom * 1e-3) / 1e12
         roof = dict(kernel="blend", bound="alu", achieved=ach, peak=VALU_PEAK_TOPS, unit="TFLOP/s",
-                    frac=ach / VALU_PEAK_TOPS, traffic=None,
+                    frac=ach / VALU_PEAK_TOPS, traffic=measured_blend_traffic(args),
                     peak_basis="FP32 VALU issue, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane per clock",
                     pairs_per_launch=P["pairs"] / n_dom, ops_per_pair=BLEND_OPS_PER_PAIR,
                     avg_launch_ms=t_dom / n_dom)
