@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-extended", action="store_true")
     ap.add_argument("--no-tiers", action="store_true", help="skip the storage-precision comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-culling", action="store_true", help="skip the view-culling measurement")
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
                     help="time the frames without any events (the roofline then comes from a second pass)")
@@ -221,6 +222,34 @@ def serving_bench(torch, v, sg):
     return out
 
 
+def culling_bench(torch, v, sg, asset):
+    """100 instances of the asset on a 10 x 10 grid, 100 frames of the 300-frame
+    fly-through inside it at 1920x1080, tolerance 1: view culling off vs on."""
+    T = sg.grid_instances(10, 1.5, 0.2, 3)
+    cams = sg.flythrough_cameras(300, 103)[::3]
+    sc = v.Scene(asset, T)
+    img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    out = {"workload": "100 instances of the 1M-leaf asset (104,857,600 leaves), 100 fly-through frames, "
+                       "1920x1080, tolerance 1"}
+    for on in (False, True):
+        sc.set_culling(on)
+        sel = None
+        for cam in cams[:3]:
+            sel = sc.select(cam, 1.0, sel)
+            sc.render(cam, sel, img)
+        torch.cuda.synchronize()
+        sc.collect_profile()
+        wall, ms, P, _ = run_frames(torch, sc, [(c, 1.0) for c in cams], img, full=False, prof=False)
+        out["on" if on else "off"] = dict(fps=len(cams) / wall, p50_ms=pct(ms, 50), p99_ms=pct(ms, 99),
+                                          slots_per_frame=P["slots"] / max(P["frames"], 1),
+                                          keys_per_frame=P["keys"] / max(P["frames"], 1))
+        log("culling %s: %.1f FPS, %.3g slots per frame" % ("on" if on else "off", len(cams) / wall,
+                                                            P["slots"] / max(P["frames"], 1)))
+    out["speedup"] = out["on"]["fps"] / out["off"]["fps"]
+    sc.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -366,6 +395,9 @@ def main():
                     sc.close()
             del im, im32
 
+    culling = None
+    if not args.no_culling and not args.profile_run and not args.quick:
+        culling = culling_bench(torch, v, sg, asset)
     serving = None
     if not args.no_serving and not args.profile_run and not args.quick:
         serving = serving_bench(torch, v, sg)
@@ -428,6 +460,7 @@ def main():
         "extended_tolerances": extended,
         "precision_tiers": tiers,
         "serving": serving,
+        "culling": culling,
         "roofline": roof,
     }
 

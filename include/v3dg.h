@@ -214,6 +214,15 @@ typedef struct {
     uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending  */
 } v3dg_profile;
 
+/* View culling of the cut (default off).  When on, v3dg_select still returns
+ * the paper's cut (v3dg_selection_copy_ids is unchanged) but gives no slots
+ * to an (instance, cluster) that provably cannot reach the image: behind the
+ * near plane, or with every Gaussian's enlarged support box (half-extent
+ * bounded from the cluster's largest scale) at least 2 pixels outside it.
+ * Images are unchanged bit for bit; fewer Gaussians are projected, sorted
+ * and binned. */
+int v3dg_set_culling(v3dg_scene *scene, int on);
+
 /* Select the sort strategy for later renders of this scene (default
  * V3DG_SORT_DEPTH_FIRST).  Both give bit-identical images. */
 int v3dg_set_sort_mode(v3dg_scene *scene, int mode);
@@ -258,6 +267,8 @@ typedef struct {
     uint32_t keys_per_pixel;    /* key capacity first provisioned per pixel of an image size
                                    not seen yet (0: 24); later frames of a size get 1.25 x the
                                    most keys seen                                          */
+    uint32_t cull;              /* 1: view culling of the cut, as v3dg_set_culling          */
+    uint32_t pad0;
 } v3dg_server_config;
 
 typedef struct {

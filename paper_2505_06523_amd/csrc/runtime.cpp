@@ -218,6 +218,8 @@ struct v3dg_scene : Ctx {
     float *scale_dev = nullptr;
     uint64_t maxcut_rows = 0;
     uint64_t cap_slots = 0;       // bound on the slots of any selection
+    CullRec *cull_dev = nullptr;  // per cluster: sphere of the rows' means, largest scale
+    bool culling = false;         // view culling of cut clusters in v3dg_select
     std::vector<uint32_t> leaf_ids;
     std::vector<uint32_t> h_count;
     v3dg_selection *full = nullptr;
@@ -367,10 +369,35 @@ int sel_alloc(v3dg_scene *sc, v3dg_selection *s)
     return sel_alloc_caps(s, (uint64_t)sc->NC * sc->n_inst, sc->cap_slots, sc->stream);
 }
 
+// Plane coefficients of the cluster view cull for one camera (see CullRec).
+CullCam make_cullcam(const CamArgs &c)
+{
+    CullCam cc{};
+    cc.fx = c.fx;
+    cc.fy = c.fy;
+    cc.al = (double)c.cx + 2.5;
+    cc.ar = (double)c.cx - (double)c.width - 2.5;
+    cc.at = (double)c.cy + 2.5;
+    cc.ab = (double)c.cy - (double)c.height - 2.5;
+    cc.nl = std::sqrt(cc.fx * cc.fx + cc.al * cc.al);
+    cc.nr = std::sqrt(cc.fx * cc.fx + cc.ar * cc.ar);
+    cc.nt = std::sqrt(cc.fy * cc.fy + cc.at * cc.at);
+    cc.nb = std::sqrt(cc.fy * cc.fy + cc.ab * cc.ab);
+    // support half-extent <= sqrt(Qm) |m1| + 1 with Qm <= 1.05 * 2 ln 255 + 0.05 < 3.5^2
+    // and |m1| <= (f / z)(1 + guard band) s smax
+    cc.kx = 3.5 * (1.0 + (double)c.limx) * cc.fx;
+    cc.ky = 3.5 * (1.0 + (double)c.limy) * cc.fy;
+    cc.nearp = c.near_plane;
+    return cc;
+}
+
 // one selection request of scene sc into selection buffers sel
-SelReq make_selreq(const v3dg_scene *sc, const InstRec *itab, float K, float tau, v3dg_selection *sel)
+SelReq make_selreq(const v3dg_scene *sc, const InstRec *itab, float K, float tau, v3dg_selection *sel,
+                   const CamArgs &cam, bool cull)
 {
     SelReq q{};
+    q.cull = cull ? sc->cull_dev : nullptr;
+    q.cc = make_cullcam(cam);
     q.self_sph = sc->self_sph;
     q.par_sph = sc->par_sph;
     q.rowinfo = sc->rowinfo;
@@ -822,6 +849,7 @@ void scene_release(v3dg_scene *s)
     dev_free(s->rowinfo);
     dev_free(s->T_dev);
     dev_free(s->scale_dev);
+    dev_free(s->cull_dev);
     ctx_release(s);
 }
 
@@ -1019,6 +1047,7 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     if ((rc = dev_alloc(&s->self_sph, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->par_sph, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->rowinfo, NC))) return bail(rc);
+    if ((rc = dev_alloc(&s->cull_dev, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->T_dev, 12ull * n_instances))) return bail(rc);
     if ((rc = dev_alloc(&s->scale_dev, n_instances))) return bail(rc);
     if ((rc = ctx_init(s, s->device, s->stream))) return bail(rc);
@@ -1047,12 +1076,38 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
         }
         std::vector<uint2> ri(NC);
         for (uint32_t k = 0; k < NC; ++k) ri[k] = make_uint2(d->first_row[k], d->count[k]);
+        // view-cull table: sphere of each cluster's row means (FP64, radius
+        // rounded up) and its largest scale (enlarged to cover FP16 storage)
+        std::vector<CullRec> cr(NC);
+        for (uint32_t k = 0; k < NC; ++k) {
+            const uint64_t r0 = d->first_row[k], n = d->count[k];
+            double c[3] = {0, 0, 0}, smax = 0.0;
+            for (uint64_t r = r0; r < r0 + n; ++r)
+                for (int j = 0; j < 3; ++j) {
+                    c[j] += d->pos[3 * r + j];
+                    smax = std::max(smax, (double)d->scale[3 * r + j]);
+                }
+            for (int j = 0; j < 3; ++j) c[j] /= (double)std::max<uint64_t>(n, 1);
+            const float cf[3] = {(float)c[0], (float)c[1], (float)c[2]};
+            double rad = 0.0;
+            for (uint64_t r = r0; r < r0 + n; ++r) {
+                double q = 0.0;
+                for (int j = 0; j < 3; ++j) {
+                    const double dd = (double)d->pos[3 * r + j] - (double)cf[j];
+                    q += dd * dd;
+                }
+                rad = std::max(rad, std::sqrt(q));
+            }
+            cr[k].sph = make_float4(cf[0], cf[1], cf[2], round_up_f32(rad * (1.0 + 1e-6) + 1e-7));
+            cr[k].smax = round_up_f32(smax * (1.0 + 1.0 / 1024.0));
+        }
         e = hipMemcpy(s->pos_planes, hpos.data(), hpos.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->geo_planes, src_geo, hgeo.size() * geo_bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->sh_planes, src_sh, hsh.size() * sh_bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->self_sph, self.data(), self.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->par_sph, par.data(), par.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->rowinfo, ri.data(), ri.size() * sizeof(uint2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s->cull_dev, cr.data(), cr.size() * sizeof(CullRec), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->T_dev, instances_3x4, 12ull * n_instances * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->scale_dev, inst_scale.data(), n_instances * sizeof(float), hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(fail(V3DG_ERR_HIP, "upload failed: %s", hipGetErrorString(e)));
@@ -1108,7 +1163,7 @@ int v3dg_select(v3dg_scene *s, const v3dg_camera *c, float tau, v3dg_selection *
     }
     {
         Stage st(s, V3DG_STAGE_SELECT);
-        launch_select(s->stream, make_selreq(s, s->itab, K, tau, sel));
+        launch_select(s->stream, make_selreq(s, s->itab, K, tau, sel, cam, s->culling));
     }
     {
         Stage st(s, V3DG_STAGE_EXPAND);
@@ -1344,6 +1399,14 @@ int v3dg_set_sort_mode(v3dg_scene *s, int mode)
     if (mode != V3DG_SORT_DEPTH_FIRST && mode != V3DG_SORT_KEYS64)
         return fail(V3DG_ERR_INVALID_ARG, "unknown sort mode %d", mode);
     s->sort_mode = mode;
+    return V3DG_OK;
+}
+
+int v3dg_set_culling(v3dg_scene *s, int on)
+{
+    g_err.clear();
+    if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
+    s->culling = on != 0;
     return V3DG_OK;
 }
 
@@ -1677,7 +1740,7 @@ int srv_dispatch(v3dg_server *s, const std::vector<SrvCtx *> &batch)
     for (size_t i = 0; i < batch.size(); ++i) {
         SrvCtx *c = batch[i];
         v3dg_scene *sc = s->scenes[c->req.scene];
-        SelReq q = make_selreq(sc, c->itab, c->req.K, c->req.tau, &c->sel);
+        SelReq q = make_selreq(sc, c->itab, c->req.K, c->req.tau, &c->sel, c->req.cam, s->cfg.cull != 0);
         q.part_begin = parts;
         parts += q.nparts;
         b.h_req[i] = q;

@@ -117,6 +117,26 @@ __device__ __forceinline__ bool sel_fits(float4 sp, float a0, float a1, float a2
     return lhs <= rhs;
 }
 
+// true when no Gaussian of the cluster can reach the image through this
+// instance (the planes of CullCam; see CullRec)
+__device__ __forceinline__ bool cull_cluster(const CullRec &cr, const InstRec &ir, const CullCam &cc)
+{
+    const double cx = cr.sph.x, cy = cr.sph.y, cz = cr.sph.z;
+    const double x = (double)ir.A[0] * cx + (double)ir.A[1] * cy + (double)ir.A[2] * cz + (double)ir.A[3];
+    const double y = (double)ir.A[4] * cx + (double)ir.A[5] * cy + (double)ir.A[6] * cz + (double)ir.A[7];
+    const double z = (double)ir.A[8] * cx + (double)ir.A[9] * cy + (double)ir.A[10] * cz + (double)ir.A[11];
+    const double s = ir.s;
+    const double r = (double)cr.sph.w * s * (1.0 + 1e-5) + 1e-5 * (1.0 + fabs(z));
+    if (z + r <= cc.nearp) return true;
+    const double e = (double)cr.smax * s;
+    const double kx = cc.kx * e, ky = cc.ky * e;
+    if (cc.fx * x + cc.al * z + r * cc.nl + kx < 0.0) return true;
+    if (cc.fx * x + cc.ar * z - r * cc.nr - kx > 0.0) return true;
+    if (cc.fy * y + cc.at * z + r * cc.nt + ky < 0.0) return true;
+    if (cc.fy * y + cc.ab * z - r * cc.nb - ky > 0.0) return true;
+    return false;
+}
+
 // packed scan payload: selected clusters in bits 36..61, Gaussians in 0..35
 constexpr int kSelGBits = 36;
 constexpr uint64_t kSelGMask = (1ull << kSelGBits) - 1;
@@ -166,7 +186,9 @@ __device__ __forceinline__ void select_part(const SelReq &q, uint32_t p, uint64_
             }
             const bool sel = sel_fits(q.self_sph[k], a0, a1, a2, a3, s, q.K, q.tau) &&
                              !sel_fits(q.par_sph[k], a0, a1, a2, a3, s, q.K, q.tau);
-            if (sel) val = (1ull << kSelGBits) | (uint64_t)q.rowinfo[k].y;
+            // a culled cluster stays in the cut but contributes no slots
+            if (sel) val = (1ull << kSelGBits) |
+                           ((q.cull && cull_cluster(q.cull[k], q.itab[inst], q.cc)) ? 0ull : (uint64_t)q.rowinfo[k].y);
         }
         v[j] = tsum;
         tsum += val;
@@ -291,7 +313,7 @@ __global__ void __launch_bounds__(256) expand_kernel(const uint32_t *__restrict_
                                                      const uint32_t *__restrict__ counters,
                                                      uint32_t *__restrict__ slot_row, uint32_t *__restrict__ slot_inst)
 {
-    const uint32_t n = counters[kSelNClusters];
+    const uint32_t n = counters[kSelNClusters], total = counters[kSelNGaussians];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint32_t nwaves = (gridDim.x * blockDim.x) / kWave;
@@ -301,7 +323,9 @@ __global__ void __launch_bounds__(256) expand_kernel(const uint32_t *__restrict_
         const uint32_t k = g - inst * NC;
         const uint2 ri = rowinfo[k];
         const uint32_t off = slot_off[c];
-        if (lane < ri.y) {
+        // the slot count is what the scan gave the cluster (0 when culled)
+        const uint32_t cnt = (c + 1 < n ? slot_off[c + 1] : total) - off;
+        if (lane < cnt) {
             slot_row[off + lane] = ri.x + lane;
             slot_inst[off + lane] = inst;
         }
@@ -326,13 +350,14 @@ __global__ void __launch_bounds__(256) expand_batch_kernel(const SelReq *__restr
     const uint32_t nwaves = (gridDim.x * blockDim.x) / kWave;
     for (uint32_t r = 0; r < n_req; ++r) {
         const SelReq &q = reqs[r];
-        const uint32_t n = q.counters[kSelNClusters];
+        const uint32_t n = q.counters[kSelNClusters], total = q.counters[kSelNGaussians];
         for (uint32_t c = wave; c < n; c += nwaves) {
             const uint32_t g = q.gid[c];
             const uint32_t inst = g / q.NC;
             const uint2 ri = q.rowinfo[g - inst * q.NC];
             const uint32_t off = q.slot_off[c];
-            if (lane < ri.y) {
+            const uint32_t cnt = (c + 1 < n ? q.slot_off[c + 1] : total) - off;
+            if (lane < cnt) {
                 q.slot_row[off + lane] = ri.x + lane;
                 q.slot_inst[off + lane] = inst;
             }

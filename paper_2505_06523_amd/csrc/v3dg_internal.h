@@ -146,6 +146,26 @@ void launch_frame_setup(hipStream_t st, const CamArgs &cam, float *image, FrameD
 constexpr int kSelThreads = 256;
 constexpr int kSelItems = 8;
 constexpr int kSelPart = kSelThreads * kSelItems;
+// View culling of cut clusters (optional).  A cluster whose rows' means lie
+// in the sphere sph (asset frame) and whose scales are at most smax cannot
+// reach the image when, for every point of the sphere seen through an
+// instance, the enlarged support box of a Gaussian there (half-extent at most
+// 3.5 (1 + guard band) f s smax / z + 1 pixels) stays 2 pixels outside the
+// image, or the sphere lies behind the near plane.  Each side is a plane test
+// on the sphere in camera space (all in FP64).
+struct CullRec {
+    float4 sph;     // centre and radius of the rows' means
+    float smax;     // largest scale of the rows
+    float pad[3];
+};
+struct CullCam {    // plane coefficients of one camera (host-computed in FP64)
+    double fx, fy;
+    double al, ar, at, ab;   // z coefficients: left/right/top/bottom
+    double nl, nr, nt, nb;   // norms of (f, coefficient)
+    double kx, ky;           // 3.5 (1 + guard band) f
+    double nearp;
+};
+
 // One selection request: its asset tables, frame records and outputs.
 struct SelReq {
     const float4 *self_sph, *par_sph;
@@ -159,6 +179,8 @@ struct SelReq {
     float K, tau;
     uint32_t part_begin;      // first partition of this request in the batch
     uint32_t nparts;
+    const CullRec *cull;      // nullptr: no culling
+    CullCam cc;
 };
 // Set-up of a batch of selection requests (frame records + clearing).
 struct SelSetup {
