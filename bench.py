@@ -151,16 +151,18 @@ def serving_bench(torch, v, sg):
 
     import numpy as np
     t0 = time.perf_counter()
-    scn = sg.serving_scenes()
-    log("serving: 8 scenes generated in %.1f s" % (time.perf_counter() - t0))
-    scenes = [v.Scene(a, T) for a, T, _ in scn]
-    extents = [L for _, _, L in scn]
+    scenes, extents, rows, leaves = [], [], 0, 0
+    for a, T, L in sg.serving_scenes():  # one scene at a time: its host arrays are freed once resident
+        scenes.append(v.Scene(a, T))
+        extents.append(L)
+        rows += a.n_rows
+        leaves += int(a.n_leaf_clusters) * 64
+        del a
+    log("serving: 8 scenes (%d rows) generated and loaded in %.1f s" % (rows, time.perf_counter() - t0))
     pool = {(w, h): [torch.empty((h, w, 4), dtype=torch.float32, device="cuda") for _ in range(MAX_OUTSTANDING)]
             for w, h in sg.SERVING_RESOLUTIONS}
-    out = {"scenes_leaves_M": list(sg.SERVING_LEAVES_M),
-           "scene_instances": [int(T.shape[0]) for _, T, _ in scn],
-           "resident_rows": int(sum(a.n_rows for a, _, _ in scn)),
-           "runs": {}}
+    out = {"scenes_leaves_M": list(sg.SERVING_LEAVES_M), "resident_leaves": leaves, "resident_rows": rows,
+           "resident_gb": rows * 236 / 1e9, "runs": {}}
     for k, (label, rate, n, graphs) in enumerate(SERVING_RUNS):
         srv = v.Server(scenes, n_contexts=8, max_batch=16, hbm_budget_bytes=96 << 30, use_graphs=graphs)
         warm = sg.serving_requests(48, 0.0, extents, seed=900 + k)

@@ -523,19 +523,61 @@ SERVING_RESOLUTIONS = ((1280, 720), (1920, 1080), (3840, 2160))
 SERVING_TOLERANCES = (1.0, 4.0)
 
 
+def compose_copies(asset: Asset, T: np.ndarray) -> Asset:
+    """One asset made of rigid copies of ``asset``: copy c takes the rows
+    ``[c R, (c+1) R)`` and the clusters ``[c C, (c+1) C)`` (copy-major, each with
+    its own root), positions, rotations and sphere centres moved by
+    ``T[c] = [Rot | t]``.  The rows are physically distinct; scales, opacity and
+    SH coefficients are copied as they are (view-dependent colour is not
+    rotated with the copy)."""
+    T = np.asarray(T, np.float64).reshape(-1, 3, 4)
+    n, R, C = T.shape[0], asset.n_rows, asset.n_clusters
+    rot_m, t = T[:, :, :3], T[:, :, 3]
+    pos = (np.einsum("cij,rj->cri", rot_m, asset.pos.astype(np.float64)) + t[:, None, :]).astype(np.float32)
+    qr = _mat_to_quat(rot_m)  # (n, 4) w, x, y, z
+    q = asset.rot.astype(np.float64)
+    w1, x1, y1, z1 = (qr[:, None, i] for i in range(4))
+    w2, x2, y2, z2 = (q[None, :, i] for i in range(4))
+    qq = np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                   w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], axis=-1)
+    qq /= np.linalg.norm(qq, axis=-1, keepdims=True)
+    qq[qq[..., 0] < 0] *= -1
+    sph = asset.self_sphere.astype(np.float64)
+    centres = (np.einsum("cij,kj->cki", rot_m, sph[:, :3]) + t[:, None, :]).astype(np.float32)
+    self_sphere = np.concatenate([centres, np.broadcast_to(asset.self_sphere[None, :, 3:], (n, C, 1))], axis=2)
+    self_sphere = self_sphere.reshape(-1, 4).astype(np.float32)
+    off_c = (np.arange(n, dtype=np.int64) * C)[:, None]
+    parent = np.where(asset.parent[None, :] >= 0, asset.parent[None, :] + off_c, -1).astype(np.int32).reshape(-1)
+    first_child = np.where(asset.first_child[None, :] >= 0, asset.first_child[None, :] + off_c,
+                           -1).astype(np.int32).reshape(-1)
+    parent_sphere = np.empty_like(self_sphere)
+    inner = parent >= 0
+    parent_sphere[inner] = self_sphere[parent[inner]]          # bit-identical copies of the parents' own spheres
+    parent_sphere[~inner, :3] = self_sphere[~inner, :3]
+    parent_sphere[~inner, 3] = np.inf
+    first_row = (asset.first_row[None, :].astype(np.int64) + (np.arange(n, dtype=np.int64) * R)[:, None])
+    assert first_row.max() + 64 < (1 << 32)
+    return Asset(
+        sh_degree=asset.sh_degree, pos=pos.reshape(-1, 3), scale=np.tile(asset.scale, (n, 1)),
+        rot=qq.astype(np.float32).reshape(-1, 4), opacity=np.tile(asset.opacity, n),
+        sh=np.tile(asset.sh, (n, 1, 1)), first_row=first_row.astype(np.uint32).reshape(-1),
+        count=np.tile(asset.count, n), level=np.tile(asset.level, n), parent=parent, first_child=first_child,
+        n_children=np.tile(asset.n_children, n), self_sphere=self_sphere, parent_sphere=parent_sphere,
+        n_leaf_clusters=asset.n_leaf_clusters * n, meta=dict(asset.meta, copies=n))
+
+
 def serving_scenes(seed: int = 500, base_leaves: int = 1 << 18):
-    """Eight scenes of {1, 2, 4, 6, 8, 12, 16, 20}M leaves, each composed of
-    instances of its own SH3 base asset (2 + j ellipsoids for scene j) on a
-    grid, the way the paper composes its large scenes from instanced assets.
-    Returns [(asset, instances (N,3,4), grid extent)]."""
-    out = []
+    """Eight scenes of {1, 2, 4, 6, 8, 12, 16, 20}M leaves.  Scene j is one
+    asset of L / base_leaves rigid copies (on a grid with jitter and yaw) of its
+    own SH3 base asset with 2 + j ellipsoids, so that every scene's rows are
+    distinct and resident.  Yields (asset, identity instance, grid extent), one
+    scene at a time, so that a caller can free each after loading it."""
     for j, m in enumerate(SERVING_LEAVES_M):
-        n_inst = m * (1 << 20) // base_leaves
-        asset = cached_asset(base_leaves, 3, seed + j, n_ellipsoids=2 + j)
-        side = int(math.ceil(math.sqrt(n_inst)))
-        T = grid_instances(side, 1.5, 0.2, seed + 100 + j)[:n_inst]
-        out.append((asset, T, side * 1.5))
-    return out
+        n_copies = m * (1 << 20) // base_leaves
+        base = cached_asset(base_leaves, 3, seed + j, n_ellipsoids=2 + j)
+        side = int(math.ceil(math.sqrt(n_copies)))
+        T = grid_instances(side, 1.5, 0.2, seed + 100 + j)[:n_copies]
+        yield compose_copies(base, T), identity_instances(1), side * 1.5
 
 
 def serving_requests(n: int, rate: float, extents, seed: int):
