@@ -226,9 +226,31 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
             make_float4(px.cr + px.T * cam.bg[0], px.cg + px.T * cam.bg[1], px.cb + px.T * cam.bg[2], 1.0f - px.T);
 }
 
-// workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous
-// band of tiles so that neighbouring tiles share its L2
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t per_xcd) { return (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3); }
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
+// b mod 8), each with its own L2.  The tile grid is cut into blocks of
+// kXcdBlock x kXcdBlock tiles and block q goes to XCD q mod 8: neighbouring
+// tiles, which share splats, run on one XCD, and every XCD gets blocks from
+// the whole image, so that a crowded region is spread over all of them.
+// Returns kNoTile for the padding workgroups of partial blocks.
+constexpr uint32_t kXcdBlock = 4;
+constexpr uint32_t kNoTile = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t xcd_tile(const CamArgs &cam)
+{
+    constexpr uint32_t kB2 = kXcdBlock * kXcdBlock;
+    const uint32_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
+    const uint32_t q = x + 8u * (j / kB2), r = j % kB2;
+    const uint32_t nbx = (cam.tiles_x + kXcdBlock - 1) / kXcdBlock;
+    const uint32_t tx = (q % nbx) * kXcdBlock + r % kXcdBlock, ty = (q / nbx) * kXcdBlock + r / kXcdBlock;
+    return (tx < cam.tiles_x && ty < cam.tiles_y) ? ty * cam.tiles_x + tx : kNoTile;
+}
+
+// workgroups that cover every tile of a tiles_x x tiles_y grid through xcd_tile
+static uint32_t xcd_grid(uint32_t tiles_x, uint32_t tiles_y)
+{
+    const uint32_t nb = ((tiles_x + kXcdBlock - 1) / kXcdBlock) * ((tiles_y + kXcdBlock - 1) / kXcdBlock);
+    return 8u * ((nb + 7u) / 8u) * kXcdBlock * kXcdBlock;
+}
 
 // ---------------------------------------------------------------------------
 // chunk plan: chunk base of every long tile and the (tile, chunk >= 1) items
@@ -307,15 +329,15 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
                                                               const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ cbase,
                                                               const uint32_t *__restrict__ counters,
-                                                              float4 *__restrict__ scratch, uint32_t per_xcd,
+                                                              float4 *__restrict__ scratch,
                                                               unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint32_t tile = xcd_tile(per_xcd);
     const CamArgs &cam = fd->cam;
+    const uint32_t tile = xcd_tile(cam);
     float4 *image = reinterpret_cast<float4 *>(fd->image);
-    if (tile >= cam.tiles_x * cam.tiles_y) return;
+    if (tile == kNoTile) return;
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint2 rg = ranges[tile];
     Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u};
@@ -377,13 +399,13 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
                                                              const uint32_t *__restrict__ cbase,
                                                              float4 *__restrict__ scratch, uint32_t *__restrict__ pend,
                                                              uint32_t *__restrict__ need, uint2 *__restrict__ rewalk,
-                                                             uint32_t *counters, uint32_t per_xcd)
+                                                             uint32_t *counters)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint32_t tile = xcd_tile(per_xcd);
     const CamArgs &cam = fd->cam;
+    const uint32_t tile = xcd_tile(cam);
     float4 *image = reinterpret_cast<float4 *>(fd->image);
-    if (tile >= cam.tiles_x * cam.tiles_y) return;
+    if (tile == kNoTile) return;
     const uint2 rg = ranges[tile];
     const uint32_t L = rg.y > rg.x ? rg.y - rg.x : 0u;
     if (L <= (uint32_t)kChunkFirst || counters[kRenChunks] == 0u) return;
@@ -464,25 +486,26 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
 
 // max_items / max_chunks bound the chunk work items and chunks (grids are
 // capped and loop over the device-side counts)
-void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat, const uint32_t *vals,
+void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
+                  const uint32_t *vals,
                   const uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items,
                   uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk,
                   unsigned long long *pairs)
 {
-    const uint32_t per_xcd = (n_tiles + 7) / 8;
+    const uint32_t n_tiles = tiles_x * tiles_y, grid = xcd_grid(tiles_x, tiles_y);
     constexpr uint64_t kMaxGrid = 1u << 20;  // beyond, workgroups loop over further items
     if (max_items > 0)
         hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ranges, n_tiles, cbase, items,
                            counters, (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull));
-    hipLaunchKernelGGL(blend_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
-                       counters, scratch, per_xcd, pairs);
+    hipLaunchKernelGGL(blend_kernel, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, counters,
+                       scratch, pairs);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
         const uint32_t gc = (uint32_t)(max_chunks < kMaxGrid ? max_chunks : kMaxGrid);
         hipLaunchKernelGGL(chunk_kernel, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, items,
                            counters, scratch, pairs);
-        hipLaunchKernelGGL(fold_kernel, dim3(per_xcd * 8), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch,
-                           pend, need, rewalk, counters, per_xcd);
+        hipLaunchKernelGGL(fold_kernel, dim3(grid), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
+                           need, rewalk, counters);
         hipLaunchKernelGGL(rewalk_kernel, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                            scratch, pend, rewalk, counters, pairs);
     }

@@ -751,7 +751,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     }
     {
         Stage st(c, V3DG_STAGE_BLEND);
-        launch_blend(c->stream, c->fdev, n_tiles, c->splat, c->vals[buf], c->ranges, c->cbase, c->items, c->rcounters,
+        launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase, c->items, c->rcounters,
                      KL / kChunk, capacity ? c->cap_chunks : KL / kChunk + n_tiles, c->scratch, c->pend, c->need,
                      c->rewalk, c->pairs_dev);
     }

@@ -258,9 +258,10 @@ void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, in
 // blend.hip
 constexpr int kChunk = 2048;            // keys per chunk of a long tile list after the first
 constexpr int kChunkFirst = 4096;       // keys of the first chunk (walked by pass 1)
-// max_chunks bounds the chunks the plan may create (more raise kErrOverflow
-// and blend only the first kChunk keys of every tile)
-void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat, const uint32_t *vals,
+// max_chunks bounds the chunks the plan may create (a plan that needs more is
+// dropped and every tile is blended whole by one workgroup)
+void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
+                  const uint32_t *vals,
                   const uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items,
                   uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk,
                   unsigned long long *pairs);
