@@ -20,7 +20,8 @@
 // list longer than kChunkFirst keys is cut into a first chunk of kChunkFirst
 // keys and further chunks of kChunk (the first chunk is longer because most
 // pixels of opaque content stop within it, which leaves the later chunks
-// nothing to do):
+// nothing to do).  The tile-range kernel has given every long tile its chunk
+// records and listed the work items (tile, chunk >= 1); then
 //   blend_kernel  walks chunk 0 of every tile (with the stop rule);
 //   chunk_kernel  walks every other chunk in parallel, each from T = 1,
 //                 giving per pixel the chunk's colour C_c and transmittance T_c;
@@ -47,21 +48,10 @@ struct BlendShared {
     uint8_t idx[4][kBlendThreads];
 };
 
-// chunk geometry of a tile list of L keys
-__device__ __forceinline__ uint32_t n_chunks(uint32_t L)
-{
-    return L <= (uint32_t)kChunkFirst ? 1u : 1u + (L - kChunkFirst + kChunk - 1) / kChunk;
-}
-__device__ __forceinline__ uint32_t chunk_begin(uint32_t c) { return c == 0 ? 0u : kChunkFirst + (c - 1) * kChunk; }
-__device__ __forceinline__ uint32_t chunk_end(uint32_t c, uint32_t L)
-{
-    return min((uint32_t)kChunkFirst + c * (uint32_t)kChunk, L);
-}
-
 struct Pix {
     float T, cr, cg, cb;
     bool active;          // still compositing
-    uint32_t evaluated;   // (pixel, splat) pairs walked
+    uint32_t walked;      // (pixel, splat) pairs walked by the wavefront's active pixels (uniform)
 };
 
 // Stage one batch entry (the splat record of key i) into LDS with its
@@ -88,22 +78,25 @@ __device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid
 }
 
 // One splat against the lane's pixel, branch-free.  p is its base-2
-// quadratic form, P1 = (c, log2 threshold, log2 o, -), col its colour.  A
-// stopped pixel carries its final transmittance negated, so "active" is
-// T > 0 and needs no flag of its own.
+// quadratic form, log2o = log2 of its opacity, col its colour; take says the
+// pixel is active and the splat passes the 1/255 test.  A stopped pixel
+// carries its final transmittance negated, so "active" is T > 0 and needs no
+// flag of its own.
 __device__ __forceinline__ void composite(float p, bool take, float log2o, const float4 &col, float &T, float &cr,
                                           float &cg, float &cb)
 {
     // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
-    const float ex = __builtin_amdgcn_exp2f((p < 0.0f ? p : 0.0f) + log2o);
+    const float ex = __builtin_amdgcn_exp2f(fminf(p, 0.0f) + log2o);
     const float alpha = take ? fminf(0.99f, ex) : 0.0f;
-    const float Tn = T * (1.0f - alpha);
-    const bool stop = take && Tn < 1e-4f;
-    const float w = (take && !stop) ? alpha * T : 0.0f;
+    const float Tn = fmaf(-alpha, T, T);
+    // a pixel that does not take the splat keeps Tn = T: >= 1e-4 while
+    // active, negative once stopped
+    const bool keep = Tn >= 1e-4f;
+    const float w = keep ? alpha * T : 0.0f;
     cr = fmaf(w, col.x, cr);
     cg = fmaf(w, col.y, cg);
     cb = fmaf(w, col.z, cb);
-    T = stop ? -T : (take ? Tn : T);
+    T = keep ? Tn : -fabsf(T);
 }
 
 // Composite keys [b, e) of the tile into the lanes' pixels (every thread of
@@ -149,13 +142,14 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
             cnt += (uint32_t)__popcll(bal);
         }
         __syncthreads();
-        if (__ballot(px.active)) {
-            // the walk is uniform across the wavefront: entries k, k+1 are the
-            // same for every lane; lanes differ only in whether they take them
-            const bool was = px.active;
-            uint32_t kend = cnt;
+        uint64_t am = __ballot(px.active);  // active pixels (uniform)
+        if (am) {
+            // The walk is uniform across the wavefront: entries k, k+1 are the
+            // same for every lane; lanes differ only in whether they take them.
+            // An entry counts as walked for the pixels active when it is reached.
             float T = px.active ? px.T : -px.T, cr = px.cr, cg = px.cg, cb = px.cb;
-            for (uint32_t k = 0; k < cnt; k += 2) {
+            uint32_t walked = 0;
+            for (uint32_t k = 0; am != 0 && k < cnt; k += 2) {
                 const uint32_t pr = *reinterpret_cast<const uint16_t *>(&sh.idx[wid][k]);
                 const bool two = k + 1 < cnt;
                 // an odd last entry is paired with itself (never taken twice):
@@ -168,17 +162,18 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
                 const float p0 = fmaf(a0.z * dx0, dx0, fmaf(a0.w * dx0, dy0, c0.x * dy0 * dy0));
                 const float p1 = fmaf(a1.z * dx1, dx1, fmaf(a1.w * dx1, dy1, c1.x * dy1 * dy1));
                 const bool pass0 = !(p0 < c0.y), pass1 = two && !(p1 < c1.y);  // alpha >= 1/255
-                if (__ballot(T > 0.0f && (pass0 || pass1)) == 0) continue;
-                const float4 col0 = sh.P2[j0], col1 = sh.P2[j1];
-                const bool take0 = T > 0.0f && pass0;
-                composite(p0, take0, c0.z, col0, T, cr, cg, cb);
-                if (take0 && T < 0.0f) kend = k + 1;
-                const bool take1 = T > 0.0f && pass1;
-                composite(p1, take1, c1.z, col1, T, cr, cg, cb);
-                if (take1 && T < 0.0f) kend = k + 2;
-                if (__ballot(T > 0.0f) == 0) break;
+                uint64_t amid = am;  // active after entry k
+                if (__ballot(T > 0.0f && (pass0 || pass1)) != 0) {
+                    const float4 col0 = sh.P2[j0], col1 = sh.P2[j1];
+                    composite(p0, T > 0.0f && pass0, c0.z, col0, T, cr, cg, cb);
+                    const bool act1 = T > 0.0f;
+                    amid = __ballot(act1);
+                    composite(p1, act1 && pass1, c1.z, col1, T, cr, cg, cb);
+                }
+                walked += (uint32_t)__popcll(am) + (two ? (uint32_t)__popcll(amid) : 0u);
+                am = __ballot(T > 0.0f);
             }
-            if (was) px.evaluated += kend;
+            px.walked += walked;
             px.active = T > 0.0f;
             px.T = fabsf(T);
             px.cr = cr;
@@ -190,10 +185,7 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
 
 __device__ __forceinline__ void count_pairs(const Pix &px, int lane, unsigned long long *pairs)
 {
-    uint32_t wsum = px.evaluated;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, kWave);
-    if (lane == 0 && wsum) atomicAdd(pairs, (unsigned long long)wsum);
+    if (lane == 0 && px.walked) atomicAdd(pairs, (unsigned long long)px.walked);
 }
 
 struct TileGeo {
@@ -226,127 +218,36 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
             make_float4(px.cr + px.T * cam.bg[0], px.cg + px.T * cam.bg[1], px.cb + px.T * cam.bg[2], 1.0f - px.T);
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
-// b mod 8), each with its own L2.  The tile grid is cut into blocks of
-// kXcdBlock x kXcdBlock tiles and block q goes to XCD q mod 8: neighbouring
-// tiles, which share splats, run on one XCD, and every XCD gets blocks from
-// the whole image, so that a crowded region is spread over all of them.
-// Returns kNoTile for the padding workgroups of partial blocks.
-constexpr uint32_t kXcdBlock = 4;
-constexpr uint32_t kNoTile = 0xffffffffu;
-
-__device__ __forceinline__ uint32_t xcd_tile(const CamArgs &cam)
-{
-    constexpr uint32_t kB2 = kXcdBlock * kXcdBlock;
-    const uint32_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
-    const uint32_t q = x + 8u * (j / kB2), r = j % kB2;
-    const uint32_t nbx = (cam.tiles_x + kXcdBlock - 1) / kXcdBlock;
-    const uint32_t tx = (q % nbx) * kXcdBlock + r % kXcdBlock, ty = (q / nbx) * kXcdBlock + r / kXcdBlock;
-    return (tx < cam.tiles_x && ty < cam.tiles_y) ? ty * cam.tiles_x + tx : kNoTile;
-}
-
-// workgroups that cover every tile of a tiles_x x tiles_y grid through xcd_tile
-static uint32_t xcd_grid(uint32_t tiles_x, uint32_t tiles_y)
-{
-    const uint32_t nb = ((tiles_x + kXcdBlock - 1) / kXcdBlock) * ((tiles_y + kXcdBlock - 1) / kXcdBlock);
-    return 8u * ((nb + 7u) / 8u) * kXcdBlock * kXcdBlock;
-}
-
-// ---------------------------------------------------------------------------
-// chunk plan: chunk base of every long tile and the (tile, chunk >= 1) items
-// ---------------------------------------------------------------------------
-constexpr int kPlanThreads = 1024;
-
-// A plan that would need more than max_chunks chunks is dropped (chunk count
-// 0): every tile is then blended whole by its pass-1 workgroup.
-__global__ void __launch_bounds__(kPlanThreads) chunk_plan_kernel(const uint2 *__restrict__ ranges, uint32_t n_tiles,
-                                                                  uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
-                                                                  uint32_t *__restrict__ counters, uint32_t max_chunks)
-{
-    __shared__ uint32_t s_w[kPlanThreads / kWave][2];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint32_t per = (n_tiles + kPlanThreads - 1) / kPlanThreads;
-    const uint32_t t0 = min(n_tiles, tid * per), t1 = min(n_tiles, t0 + per);
-    uint32_t nch = 0, nit = 0;
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint2 r = ranges[t];
-        const uint32_t L = r.y > r.x ? r.y - r.x : 0u;
-        if (L > (uint32_t)kChunkFirst) {
-            const uint32_t m = n_chunks(L);
-            nch += m;
-            nit += m - 1;
-        }
-    }
-    // block exclusive scan of (nch, nit)
-    uint32_t a = nch, b = nit;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t na = __shfl_up(a, o, kWave), nb = __shfl_up(b, o, kWave);
-        if (lane >= o) {
-            a += na;
-            b += nb;
-        }
-    }
-    if (lane == kWave - 1) {
-        s_w[wid][0] = a;
-        s_w[wid][1] = b;
-    }
-    __syncthreads();
-    uint32_t oa = 0, ob = 0, ta = 0, tb = 0;
-    for (int w = 0; w < kPlanThreads / kWave; ++w) {
-        if (w < wid) {
-            oa += s_w[w][0];
-            ob += s_w[w][1];
-        }
-        ta += s_w[w][0];
-        tb += s_w[w][1];
-    }
-    const bool fits = ta <= max_chunks;
-    uint32_t ca = oa + a - nch, cb = ob + b - nit;
-    for (uint32_t t = t0; t < t1 && fits; ++t) {
-        const uint2 r = ranges[t];
-        const uint32_t L = r.y > r.x ? r.y - r.x : 0u;
-        if (L > (uint32_t)kChunkFirst) {
-            const uint32_t m = n_chunks(L);
-            cbase[t] = ca;
-            for (uint32_t c = 1; c < m; ++c) items[cb + c - 1] = make_uint2(t, c);
-            ca += m;
-            cb += m - 1;
-        }
-    }
-    if (tid == kPlanThreads - 1) {
-        counters[kRenChunks] = fits ? ta : 0u;
-        counters[kRenItems] = fits ? tb : 0u;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // pass 1: every tile, up to its first kChunkFirst keys
 // ---------------------------------------------------------------------------
+// Workgroup b blends tile order[b]: the tiles with the longest first chunks
+// come first, so that their walks do not start last and leave the rest of the
+// chip idle.
 __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ cbase,
-                                                              const uint32_t *__restrict__ counters,
+                                                              const uint32_t *__restrict__ order,
                                                               float4 *__restrict__ scratch,
                                                               unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const CamArgs &cam = fd->cam;
-    const uint32_t tile = xcd_tile(cam);
     float4 *image = reinterpret_cast<float4 *>(fd->image);
-    if (tile == kNoTile) return;
+    const uint32_t tile = order[blockIdx.x];
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint2 rg = ranges[tile];
     Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u};
     const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
-    const bool long_list = end - rg.x > (uint32_t)kChunkFirst && counters[kRenChunks] != 0u;
+    const uint32_t cb = cbase[tile];  // kNoChunk: blended whole
+    const bool long_list = cb != kNoChunk && end - rg.x > (uint32_t)kChunkFirst;
     blend_range(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
                 px);
     if (long_list)  // state after chunk 0; a negative T marks a finished pixel
-        scratch[(uint64_t)cbase[tile] * kBlendThreads + g.pix] =
+        scratch[(uint64_t)cb * kBlendThreads + g.pix] =
             make_float4(px.cr, px.cg, px.cb, px.active ? px.T : -px.T);
     else
         write_pixel(cam, g, px, image);
@@ -403,12 +304,11 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const CamArgs &cam = fd->cam;
-    const uint32_t tile = xcd_tile(cam);
+    const uint32_t tile = blockIdx.x;
     float4 *image = reinterpret_cast<float4 *>(fd->image);
-    if (tile == kNoTile) return;
     const uint2 rg = ranges[tile];
     const uint32_t L = rg.y > rg.x ? rg.y - rg.x : 0u;
-    if (L <= (uint32_t)kChunkFirst || counters[kRenChunks] == 0u) return;
+    if (L <= (uint32_t)kChunkFirst || cbase[tile] == kNoChunk) return;
     const uint32_t m = n_chunks(L);
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint64_t base = cbase[tile];
@@ -473,7 +373,7 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         const uint64_t base = cbase[tile];
         const bool mine = pend[base * kBlendThreads + g.pix] == c;
         const float4 st = scratch[base * kBlendThreads + g.pix];
-        Pix px{st.w, st.x, st.y, st.z, mine, 0u};
+        Pix px{fabsf(st.w), st.x, st.y, st.z, mine, 0u};  // a pixel finished before holds -T
         blend_range(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
                     g.pyc, wid, lane, sh, px);
         // a pixel that, through rounding of the folded products, does not stop in
@@ -487,24 +387,20 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
 // max_items / max_chunks bound the chunk work items and chunks (grids are
 // capped and loop over the device-side counts)
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
-                  const uint32_t *vals,
-                  const uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items,
-                  uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk,
-                  unsigned long long *pairs)
+                  const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
+                  const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
+                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs)
 {
-    const uint32_t n_tiles = tiles_x * tiles_y, grid = xcd_grid(tiles_x, tiles_y);
+    const uint32_t n_tiles = tiles_x * tiles_y;
     constexpr uint64_t kMaxGrid = 1u << 20;  // beyond, workgroups loop over further items
-    if (max_items > 0)
-        hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, ranges, n_tiles, cbase, items,
-                           counters, (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull));
-    hipLaunchKernelGGL(blend_kernel, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, counters,
+    hipLaunchKernelGGL(blend_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, order,
                        scratch, pairs);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
         const uint32_t gc = (uint32_t)(max_chunks < kMaxGrid ? max_chunks : kMaxGrid);
         hipLaunchKernelGGL(chunk_kernel, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, items,
                            counters, scratch, pairs);
-        hipLaunchKernelGGL(fold_kernel, dim3(grid), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
+        hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
                            need, rewalk, counters);
         hipLaunchKernelGGL(rewalk_kernel, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                            scratch, pend, rewalk, counters, pairs);

@@ -175,7 +175,7 @@ struct Ctx {
     uint32_t *vals[2] = {nullptr, nullptr};
     uint64_t *sort_status = nullptr;
     uint64_t sort_status_parts = 0;
-    uint32_t *cbase = nullptr;     // per tile: first chunk of a long list
+    uint32_t *cbase = nullptr;     // per tile: first chunk of a long list; then the blend order (tiles_cap each)
     uint2 *items = nullptr;        // (tile, chunk) work items
     float4 *scratch = nullptr;     // per chunk, per pixel (C, T)
     uint32_t *pend = nullptr;      // per long tile, per pixel: chunk to walk again
@@ -529,7 +529,7 @@ int ensure_tiles(Ctx *c, uint32_t n_tiles)
     c->scan_status = reinterpret_cast<uint64_t *>(c->rclear + kRenCounters);
     c->ranges = reinterpret_cast<uint2 *>(c->rclear + kRenCounters + 2 * c->scan_parts);
     dev_free(c->cbase);
-    if ((rc = dev_alloc(&c->cbase, c->tiles_cap))) return rc;
+    if ((rc = dev_alloc(&c->cbase, 2ull * c->tiles_cap))) return rc;
     return V3DG_OK;
 }
 
@@ -718,6 +718,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         KL = c->cap_keys;
     }
     const uint32_t *k_dev = capacity ? c->rcounters + kRenKeysEff : nullptr;
+    const uint64_t max_chunks = capacity ? c->cap_chunks : KL / kChunk + n_tiles;  // chunk records the plan may use
     const uint32_t tile_bits = std::max<uint32_t>(bits_for(n_tiles), 1);
     int buf = 0;
     uint32_t passes = 0;
@@ -734,7 +735,8 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         if (KL > 0) run_sort<uint32_t>(c, kb, c->vals, k_dev, KL, key_bits, 4, &buf, &passes, true);
         {
             Stage st(c, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint32_t>(c->stream, kb[buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges);
+            launch_tile_ranges<uint32_t>(c->stream, kb[buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges,
+                                         c->cbase, c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
         }
     } else {
         {
@@ -746,14 +748,15 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         if (KL > 0) run_sort<uint64_t>(c, c->keys, c->vals, k_dev, KL, key_bits, 0, &buf, &passes, false);
         {
             Stage st(c, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, n_tiles, c->ranges);
+            launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, n_tiles, c->ranges,
+                                         c->cbase, c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
         }
     }
     {
         Stage st(c, V3DG_STAGE_BLEND);
-        launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase, c->items, c->rcounters,
-                     KL / kChunk, capacity ? c->cap_chunks : KL / kChunk + n_tiles, c->scratch, c->pend, c->need,
-                     c->rewalk, c->pairs_dev);
+        launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase,
+                     c->items, c->cbase + c->tiles_cap, c->rcounters, KL / kChunk, max_chunks, c->scratch, c->pend,
+                     c->need, c->rewalk, c->pairs_dev);
     }
     HIP_TRY(hipGetLastError());
     fi->key_bits = key_bits;
@@ -1566,7 +1569,7 @@ uint64_t ctx_bytes(const SrvCtx *c)
 {
     uint64_t b = c->ws_slots * (48 + 32 + 4 + 8 + 4 + 4 + 16);
     b += (uint64_t)c->itab_cap * sizeof(InstRec) + sizeof(FrameDev) + 8;
-    b += c->rclear_words * 4 + (uint64_t)c->tiles_cap * 4;
+    b += c->rclear_words * 4 + (uint64_t)c->tiles_cap * 8;
     b += c->cap_keys * 24 + c->sort_status_parts * kRadix * 8;
     b += c->cap_chunks * (8 + 256 * 16 + 256 * 4 + 4 + 8);
     b += c->sel.cap_tests * 8 + ((uint64_t)kSelCounters + 2 * c->sel.n_parts) * 4 + c->sel.cap_slots * 8;
@@ -1589,7 +1592,7 @@ uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
     const uint64_t K2 = std::max(K, keys);
     g += (K2 - keys) * 24 + ((K2 - keys + kSortPart - 1) / kSortPart) * 3 / 2 * kRadix * 8;
     const uint64_t T2 = std::max<uint64_t>(std::max<uint64_t>(n_tiles, 8160), tiles);
-    g += (T2 - tiles) * 12;
+    g += (T2 - tiles) * 16;
     const uint64_t ch = (K2 + kChunk - 1) / kChunk + T2;
     if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 8);
     return g;

@@ -690,20 +690,58 @@ __device__ __forceinline__ uint32_t lower_bound_tile(const K *__restrict__ keys,
 
 template <typename K>
 __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
-                                                          int shift, uint32_t n_tiles, uint2 *__restrict__ ranges)
+                                                          int shift, uint32_t n_tiles, uint2 *__restrict__ ranges,
+                                                          uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
+                                                          uint32_t *__restrict__ order, uint32_t *counters,
+                                                          uint32_t max_chunks)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint32_t n = *n_dev;
-    ranges[t] = make_uint2(lower_bound_tile(keys, n, shift, t), lower_bound_tile(keys, n, shift, t + 1));
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const bool in = t < n_tiles;
+    uint32_t L = 0;
+    if (in) {
+        const uint32_t n = *n_dev;
+        const uint2 r = make_uint2(lower_bound_tile(keys, n, shift, t), lower_bound_tile(keys, n, shift, t + 1));
+        ranges[t] = r;
+        L = r.y - r.x;
+    }
+    // chunk records and work items, one atomic per wavefront for each
+    const uint32_t m = (in && L > (uint32_t)kChunkFirst) ? n_chunks(L) : 0u;
+    const uint32_t m_incl = wave_incl_scan_u32(m);
+    uint32_t m_base = 0;
+    if (lane == kWave - 1 && m_incl) m_base = atomicAdd(&counters[kRenChunks], m_incl);
+    const uint32_t first = __shfl(m_base, kWave - 1, kWave) + m_incl - m;
+    const bool ok = m != 0 && (uint64_t)first + m <= max_chunks;
+    if (in) cbase[t] = ok ? first : kNoChunk;
+    const uint32_t it = ok ? m - 1 : 0u;
+    const uint32_t it_incl = wave_incl_scan_u32(it);
+    uint32_t it_base = 0;
+    if (lane == kWave - 1 && it_incl) it_base = atomicAdd(&counters[kRenItems], it_incl);
+    const uint32_t it_first = __shfl(it_base, kWave - 1, kWave) + it_incl - it;
+    for (uint32_t c = 1; c <= it; ++c) items[it_first + c - 1] = make_uint2(t, c);
+    // blend order: full first chunks at the front, the rest from the back
+    const bool heavy = in && L >= (uint32_t)kChunkFirst;
+    const uint64_t hb = __ballot(heavy), lb = __ballot(in && !heavy);
+    uint32_t fb = 0, bb = 0;
+    if (lane == 0) {
+        if (hb) fb = atomicAdd(&counters[kRenFront], (uint32_t)__popcll(hb));
+        if (lb) bb = atomicAdd(&counters[kRenBack], (uint32_t)__popcll(lb));
+    }
+    fb = __shfl(fb, 0, kWave);
+    bb = __shfl(bb, 0, kWave);
+    if (heavy) order[fb + (uint32_t)__popcll(hb & lt)] = t;
+    else if (in) order[n_tiles - 1u - (bb + (uint32_t)__popcll(lb & lt))] = t;
 }
 
 template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
-                        uint2 *ranges)
+                        uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *order, uint32_t *counters,
+                        uint64_t max_chunks)
 {
     hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, n_dev, shift,
-                       n_tiles, ranges);
+                       n_tiles, ranges, cbase, items, order, counters,
+                       (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull));
 }
 
 template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *);
@@ -714,7 +752,9 @@ template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const ui
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
-template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *);
-template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *);
+template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *,
+                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
+template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *,
+                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
 
 }  // namespace v3dg

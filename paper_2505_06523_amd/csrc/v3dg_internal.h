@@ -81,6 +81,8 @@ enum RenderCounter : int {
     kRenRewalk = 7,       // chunks walked again (they hold a pixel's stop)
     kRenTicketSort = 8,   // 8 passes of the tile (or 64-bit) sort
     kRenTicketDepth = 16, // 4 passes of the depth sort
+    kRenFront = 20,       // tiles placed at the front of the blend order (long lists)
+    kRenBack = 21,        // tiles placed at its back
     kRenHist = 32,        // 8 passes x 256 bins
     kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
     kRenKeysEff = 32 + 12 * 256,   // keys the frame's buffers hold: min(total, capacity)
@@ -252,19 +254,37 @@ template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide);
-template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
-                        uint2 *ranges);
-// blend.hip
+// Chunks of long tile lists (blending): a list of L > kChunkFirst keys is
+// cut into a first chunk of kChunkFirst keys and further chunks of kChunk.
 constexpr int kChunk = 2048;            // keys per chunk of a long tile list after the first
 constexpr int kChunkFirst = 4096;       // keys of the first chunk (walked by pass 1)
-// max_chunks bounds the chunks the plan may create (a plan that needs more is
-// dropped and every tile is blended whole by one workgroup)
+constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whole
+__device__ __forceinline__ uint32_t n_chunks(uint32_t L)
+{
+    return L <= (uint32_t)kChunkFirst ? 1u : 1u + (L - kChunkFirst + kChunk - 1) / kChunk;
+}
+__device__ __forceinline__ uint32_t chunk_begin(uint32_t c) { return c == 0 ? 0u : kChunkFirst + (c - 1) * kChunk; }
+__device__ __forceinline__ uint32_t chunk_end(uint32_t c, uint32_t L)
+{
+    return min((uint32_t)kChunkFirst + c * (uint32_t)kChunk, L);
+}
+// Per tile t < n_tiles: ranges[t] = [first, end) of its keys in the sorted
+// keys, and the blend plan.  A tile of L > kChunkFirst keys gets n_chunks(L)
+// consecutive chunk records from cbase[t] (kNoChunk for other tiles, and for
+// long ones beyond max_chunks records, which are then blended whole) and one
+// work item (t, c) per chunk c >= 1 (items: counters[kRenItems]).  order is
+// a permutation of the tiles with the lists of at least kChunkFirst keys
+// first, so that the longest walks start first.
+template <typename K>
+void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
+                        uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *order, uint32_t *counters,
+                        uint64_t max_chunks);
+// blend.hip
+// max_items / max_chunks bound the work items and chunks of the plan (grid sizes)
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
-                  const uint32_t *vals,
-                  const uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *counters, uint64_t max_items,
-                  uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk,
-                  unsigned long long *pairs);
+                  const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
+                  const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
+                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs);
 // generic fill
 void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);
 
