@@ -626,6 +626,27 @@ void run_sort(Ctx *c, KT *const kb[2], uint32_t *const vb[2], const uint32_t *n_
     *out_buf = cur;
 }
 
+// Depth-first binning: tile-id keys of type KT in depth order, their stable
+// sort, and the tile ranges with the blend plan.
+template <typename KT>
+void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev, uint64_t KL, uint32_t key_bits,
+               uint32_t n_tiles, uint64_t max_chunks, int *buf, uint32_t *passes)
+{
+    KT *kb[2] = {reinterpret_cast<KT *>(c->keys[0]), reinterpret_cast<KT *>(c->keys[1])};
+    const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
+    {
+        Stage st(c, V3DG_STAGE_EMIT);
+        launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys,
+                          tpasses, kb[0], c->vals[0], c->rcounters + kRenHist, c->rcounters + kRenErr);
+    }
+    if (KL > 0) run_sort<KT>(c, kb, c->vals, k_dev, KL, key_bits, 4, buf, passes, true);
+    {
+        Stage st(c, V3DG_STAGE_RANGES);
+        launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges, c->cbase,
+                               c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
+    }
+}
+
 struct SelView {
     const uint32_t *counters;  // kSelNGaussians holds the slot count
     const uint32_t *slot_row, *slot_inst;
@@ -724,20 +745,11 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     uint32_t passes = 0;
     uint32_t key_bits;
     if (depth_first) {
-        uint32_t *kb[2] = {reinterpret_cast<uint32_t *>(c->keys[0]), reinterpret_cast<uint32_t *>(c->keys[1])};
         key_bits = tile_bits;
-        const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
-        {
-            Stage st(c, V3DG_STAGE_EMIT);
-            launch_emit32(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys,
-                          tpasses, kb[0], c->vals[0], c->rcounters + kRenHist, c->rcounters + kRenErr);
-        }
-        if (KL > 0) run_sort<uint32_t>(c, kb, c->vals, k_dev, KL, key_bits, 4, &buf, &passes, true);
-        {
-            Stage st(c, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint32_t>(c->stream, kb[buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges,
-                                         c->cbase, c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
-        }
+        if (n_tiles <= kTileKey16Max)
+            tile_keys<uint16_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes);
+        else
+            tile_keys<uint32_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes);
     } else {
         {
             Stage st(c, V3DG_STAGE_EMIT);
@@ -1384,9 +1396,15 @@ int v3dg_copy_sorted_keys(v3dg_scene *s, uint64_t *keys, uint32_t *vals, uint64_
     if (keys) {
         if (s->last.sort_mode == V3DG_SORT_KEYS64) {
             HIP_TRY(hipMemcpy(keys, s->keys[s->last_buf], n * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        } else {  // tile ids; the depth bits come from the slot
+        } else {  // tile ids (16 bits on grids of at most kTileKey16Max tiles); the depth bits come from the slot
             std::vector<uint32_t> tk(n), dp(s->last.n_slots);
-            HIP_TRY(hipMemcpy(tk.data(), s->keys[s->last_buf], n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            if (s->last.n_tiles <= kTileKey16Max) {
+                std::vector<uint16_t> t16(n);
+                HIP_TRY(hipMemcpy(t16.data(), s->keys[s->last_buf], n * sizeof(uint16_t), hipMemcpyDeviceToHost));
+                for (uint64_t i = 0; i < n; ++i) tk[i] = t16[i];
+            } else {
+                HIP_TRY(hipMemcpy(tk.data(), s->keys[s->last_buf], n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            }
             HIP_TRY(hipMemcpy(dp.data(), s->depth, dp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
             for (uint64_t i = 0; i < n; ++i) keys[i] = ((uint64_t)tk[i] << 32) | dp[v[i]];
         }

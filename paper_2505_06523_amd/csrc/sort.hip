@@ -311,23 +311,26 @@ struct EmitShared {
 };
 
 // key o of the output: into the LDS stage or straight to global memory
+template <typename KT>
 __device__ __forceinline__ void put_key(EmitShared &sh, bool staged, uint64_t o, uint32_t key, uint32_t val,
-                                        uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                                        KT *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     if (staged) {
         sh.key[o - sh.lo] = key;
         sh.val[o - sh.lo] = val;
     } else {
-        keys[o] = key;
+        keys[o] = (KT)key;
         vals[o] = val;
     }
 }
 
+// KT: uint16_t when every tile id fits in 16 bits, else uint32_t
+template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
     const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
     const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, int passes,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
+    KT *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
 {
     __shared__ EmitShared sh;
     const uint32_t n = min(*n_dev, max_n);
@@ -429,7 +432,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     if (staged) {  // contiguous copy of the assembled range
         const uint32_t cnt = (uint32_t)(sh.hi - sh.lo);
         for (uint32_t i = tid; i < cnt; i += kEmitThreads) {
-            keys[sh.lo + i] = sh.key[i];
+            keys[sh.lo + i] = (KT)sh.key[i];
             vals[sh.lo + i] = sh.val[i];
         }
     }
@@ -449,15 +452,16 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
             if (sh.h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], sh.h[(p - 1) * 256 + i]);
 }
 
+template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
                    const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
-                   const FrameDev *fd, uint64_t key_cap, int passes, uint32_t *keys, uint32_t *vals, uint32_t *hist,
+                   const FrameDev *fd, uint64_t key_cap, int passes, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *err)
 {
     if (max_n == 0) return;
     const uint32_t blocks = (uint32_t)((max_n + kEmitThreads - 1) / kEmitThreads);
-    hipLaunchKernelGGL(emit32_kernel, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order, tiles,
-                       offsets, rect, bin, fd, key_cap, passes, keys, vals, hist, err);
+    hipLaunchKernelGGL(emit32_kernel<KT>, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order,
+                       tiles, offsets, rect, bin, fd, key_cap, passes, keys, vals, hist, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -659,7 +663,7 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
     if (n == 0) return;
     // wide partitions (8192 keys) for large 32-bit sorts: fewer partitions to
     // look back over and longer digit runs to store
-    if (wide && sizeof(K) == 4) {
+    if (wide && sizeof(K) <= 4) {
         const uint32_t nparts = (uint32_t)((n + kSortPartWide - 1) / kSortPartWide);
         hipLaunchKernelGGL((sort_pass_kernel<K, kSortItemsWide>), dim3(nparts), dim3(kSortThreads), 0, st, keys_in,
                            vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
@@ -744,14 +748,26 @@ void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, in
                        (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull));
 }
 
+template void launch_emit32<uint16_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
+                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t, int,
+                                      uint16_t *, uint32_t *, uint32_t *, uint32_t *);
+template void launch_emit32<uint32_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
+                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t, int,
+                                      uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+template void launch_sort_hist<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *);
+template void launch_sort_pass<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint16_t *, uint32_t *,
+                                         const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
 template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
+template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint2 *,
+                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
 template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *,
                                           uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
 template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *,

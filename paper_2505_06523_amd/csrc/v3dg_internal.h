@@ -230,11 +230,14 @@ void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *or
 void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
                    const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
                    uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err);
-// 32-bit tile keys in depth order (order[j] = slot of depth rank j), with the
-// digit histograms of the tile sort (passes <= 3) accumulated into hist
+// Tile-id keys in depth order (order[j] = slot of depth rank j), with the
+// digit histograms of the tile sort (passes <= 3) accumulated into hist.
+// KT = uint16_t for grids of at most kTileKey16Max tiles, else uint32_t.
+constexpr uint32_t kTileKey16Max = 1u << 16;
+template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
                    const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
-                   const FrameDev *fd, uint64_t key_cap, int passes, uint32_t *keys, uint32_t *vals, uint32_t *hist,
+                   const FrameDev *fd, uint64_t key_cap, int passes, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *err);
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
@@ -249,7 +252,7 @@ template <typename K>
 void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist);
 // One onesweep pass over n_dev ? *n_dev : n keys (grid sized for n); the
 // look-back epoch is *epoch_dev + epoch when epoch_dev is given, else epoch.
-// wide selects partitions of kSortPartWide keys (32-bit keys only).
+// wide selects partitions of kSortPartWide keys (keys of at most 32 bits).
 template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
