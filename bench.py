@@ -31,14 +31,14 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Lane-op slots per evaluated (pixel, splat) pair under the compositing rule:
 # dx, dy (2); the quadratic a dx^2 + b dx dy + c dy^2 (4 mul + 2 fma); the
 # 1/255 test (1); clamp to <= 0 (1); + log2 o (1); exp2 (quarter rate: 4);
-# min(0.99, .) (1); 1 - alpha (1); T (1 - alpha) (1); the 1e-4 test (1);
-# w = alpha T (1); three colour fma (3); T update (1) -> 24.
-BLEND_OPS_PER_PAIR = 24
+# min(0.99, .) (1); T (1 - alpha) as T - alpha T (1 fma); the 1e-4 test (1);
+# w = alpha T (1); three colour fma (3); T update (1) -> 23.
+BLEND_OPS_PER_PAIR = 23
 # HBM bytes per frame of the blend stage on this workload, from rocprofv3
 # FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the 256 timed frames
 # (profiles/hbm_counters_1M_sh3_1080p.md).  Valid only for the blending source
 # they were taken on: the bench reports null once blend.hip has changed.
-BLEND_TRAFFIC = dict(bytes_per_frame=603.5e6, blend_source_sha256_16="f065c9d48a1efb45")
+BLEND_TRAFFIC = dict(bytes_per_frame=759.5e6, blend_source_sha256_16="f81570bdd25a1645")
 
 
 def log(*a):
