@@ -271,7 +271,7 @@ void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 // run of low digits (a difference array over the 256 bins) and to one or two
 // higher digits.
 constexpr int kEmitThreads = 256;
-constexpr uint32_t kSmallKeys = 8;
+constexpr uint32_t kSmallKeys = 48;  // measured best of 8..256 on 1080p orbits
 constexpr uint32_t kStage = 2048;
 
 __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, int passes, uint32_t *s_d0, uint32_t *s_h,
