@@ -157,3 +157,12 @@ def quantized_asset(asset, precision: str):
     sh = round_bf16(asset.sh) if precision == "fp16_bf16sh" else round_fp16(asset.sh)
     return dataclasses.replace(asset, scale=round_fp16(asset.scale), rot=round_fp16(asset.rot),
                                opacity=round_fp16(asset.opacity), sh=sh)
+
+
+def bundle_asset(b: dict, sh_degree: int) -> sg.Asset:
+    """A bundle (offline-build arrays) as a scene-generator Asset."""
+    return sg.Asset(sh_degree=sh_degree, pos=b["pos"], scale=b["scale"], rot=b["rot"], opacity=b["opacity"],
+                    sh=b["sh"].reshape(len(b["pos"]), (sh_degree + 1) ** 2, 3), first_row=b["first_row"],
+                    count=b["count"], level=b["level"], parent=b["parent"], first_child=b["first_child"],
+                    n_children=b["n_children"], self_sphere=b["self_sphere"], parent_sphere=b["parent_sphere"],
+                    n_leaf_clusters=int(b["n_leaf_clusters"]))
