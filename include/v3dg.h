@@ -312,6 +312,47 @@ int v3dg_server_get_stats(v3dg_server *srv, v3dg_server_stats *out);
 /* Waits for the frames in flight, then frees every context. */
 void v3dg_server_free(v3dg_server *srv);
 
+/* ---- Offline build (paper Sec. 3.1-3.2, Algorithm 1), on the GPU -------------
+ * Builds the cluster bundle of an asset from its n Gaussians: a binary median
+ * split into clusters of at most cluster_size Gaussians (layer C_0); then,
+ * while a layer holds two clusters or more, the same split pairs its clusters
+ * into cluster groups, every group is halved to the ceil(m/2) Gaussians with
+ * the largest ((sx sy) sz) opacity (ties: the earlier one in the group), whose
+ * scales grow by float(2^(1/6)), and these form one cluster of the next layer.
+ * The group's bounding sphere (centre: FP64 mean of its Gaussians' positions,
+ * rounded to FP32; radius: the farthest of them, rounded up) is the new
+ * cluster's own sphere and its members' parent sphere; it is grown to
+ * (|c_p - c_c| + r_c)(1 + 2^-10) over every member so that spheres nest.
+ * Leaves have radius 0 (centre: their mean); the root's parent radius is +inf.
+ * Split of a set larger than the limit: the axis of the largest FP32 extent
+ * (the first on ties), a stable order along it, ceil(s/2) items to the left.
+ * The local-splatting refinement of simplified Gaussians is not performed.
+ *
+ * Inputs are host arrays: pos, scale (n x 3), rot (n x 4), opacity (n), sh
+ * (n x (sh_degree+1)^2 x 3), all FP32; 1 <= n < 2^31, sh_degree <= 3,
+ * 2 <= cluster_size <= 64.  The result (cluster ids layer-major, within a layer
+ * in grouping order; rows in cluster order) is owned by *out until
+ * v3dg_bundle_free and is loadable with v3dg_load_hierarchy.  Synchronises.
+ * Errors: V3DG_ERR_INVALID_ARG, V3DG_ERR_OOM, V3DG_ERR_HIP, V3DG_ERR_DEVICE. */
+typedef struct v3dg_bundle v3dg_bundle;
+int v3dg_build_bundle(const float *pos, const float *scale, const float *rot, const float *opacity, const float *sh,
+                      uint32_t n, uint32_t sh_degree, uint32_t cluster_size, v3dg_bundle **out);
+
+/* Sizes of a built bundle: clusters, rows, leaf clusters (ids 0 .. n_leaf-1)
+ * and layers. */
+int v3dg_bundle_sizes(const v3dg_bundle *b, uint32_t *n_clusters, uint32_t *n_rows, uint32_t *n_leaf_clusters,
+                      uint32_t *n_layers);
+
+/* Copy a built bundle into caller arrays sized by v3dg_bundle_sizes (any may
+ * be NULL): rows as in v3dg_hierarchy_desc, clusters likewise plus level[k];
+ * src[i] is the input Gaussian of row i and gen[i] the simplifications it
+ * went through (its scales are the input's grown gen[i] times). */
+int v3dg_bundle_copy(const v3dg_bundle *b, float *pos, float *scale, float *rot, float *opacity, float *sh,
+                     float *self_sphere, float *parent_sphere, uint32_t *first_row, uint8_t *count, uint8_t *level,
+                     int32_t *parent, int32_t *first_child, uint8_t *n_children, uint32_t *src, uint8_t *gen);
+
+void v3dg_bundle_free(v3dg_bundle *b);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *v3dg_last_error(void);
 

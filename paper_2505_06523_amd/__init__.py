@@ -11,6 +11,7 @@ loading fails loudly when it is missing.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -97,6 +98,7 @@ EXPORTS = [
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
     "v3dg_last_error",
     "v3dg_server_create", "v3dg_server_submit", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
+    "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_free",
 ]
 
 _lib = None
@@ -137,6 +139,10 @@ def lib():
         "v3dg_server_poll": ([P, I, P, U32, P], I),
         "v3dg_server_get_stats": ([P, P], I),
         "v3dg_server_free": ([P], None),
+        "v3dg_build_bundle": ([P, P, P, P, P, U32, U32, U32, P], I),
+        "v3dg_bundle_sizes": ([P, P, P, P, P], I),
+        "v3dg_bundle_copy": ([P] + [P] * 15, I),
+        "v3dg_bundle_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -474,6 +480,39 @@ class Scene:
             self.close()
         except Exception:
             pass
+
+
+def build_bundle(pos, scale, rot, opacity, sh, cluster_size: int = 64) -> dict:
+    """Offline build on the GPU (v3dg_build_bundle) of n Gaussians given as
+    host arrays; returns the bundle arrays (rows, clusters, src and gen)."""
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    pos, scale, rot, opacity, sh = f32(pos), f32(scale), f32(rot), f32(opacity), f32(sh)
+    n = pos.shape[0]
+    k = sh.reshape(n, -1).shape[1] // 3
+    sh_degree = int(round(math.sqrt(k))) - 1
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+    _check(lib().v3dg_build_bundle(ptr(pos), ptr(scale), ptr(rot), ptr(opacity), ptr(sh), n, sh_degree,
+                                   int(cluster_size), C.byref(h)))
+    try:
+        nc, nr, nl, ny = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib().v3dg_bundle_sizes(h, C.byref(nc), C.byref(nr), C.byref(nl), C.byref(ny)))
+        Cn, R = nc.value, nr.value
+        out = dict(pos=np.empty((R, 3), np.float32), scale=np.empty((R, 3), np.float32),
+                   rot=np.empty((R, 4), np.float32), opacity=np.empty(R, np.float32),
+                   sh=np.empty((R, k, 3), np.float32), self_sphere=np.empty((Cn, 4), np.float32),
+                   parent_sphere=np.empty((Cn, 4), np.float32), first_row=np.empty(Cn, np.uint32),
+                   count=np.empty(Cn, np.uint8), level=np.empty(Cn, np.uint8), parent=np.empty(Cn, np.int32),
+                   first_child=np.empty(Cn, np.int32), n_children=np.empty(Cn, np.uint8),
+                   src=np.empty(R, np.uint32), gen=np.empty(R, np.uint8))
+        names = ["pos", "scale", "rot", "opacity", "sh", "self_sphere", "parent_sphere", "first_row", "count",
+                 "level", "parent", "first_child", "n_children", "src", "gen"]
+        _check(lib().v3dg_bundle_copy(h, *[ptr(out[x]) for x in names]))
+        out["n_leaf_clusters"] = nl.value
+        out["n_layers"] = ny.value
+        return out
+    finally:
+        lib().v3dg_bundle_free(h)
 
 
 def sort_pairs(keys, vals, key_bits: int, stream=None):

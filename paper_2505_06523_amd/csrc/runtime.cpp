@@ -2025,3 +2025,378 @@ void v3dg_server_free(v3dg_server *s)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Offline build (paper Sec. 3.1-3.2, Algorithm 1), structural part
+// ---------------------------------------------------------------------------
+struct v3dg_bundle {
+    uint32_t n_clusters = 0, n_rows = 0, n_leaf = 0, n_layers = 0, sh_floats = 0;
+    std::vector<float> pos, scale, rot, opacity, sh, self_sphere, parent_sphere;
+    std::vector<uint32_t> first_row, src;
+    std::vector<uint8_t> count, level, n_children, gen;
+    std::vector<int32_t> parent, first_child;
+};
+
+namespace {
+
+// Sets of a median split of m items into sets of at most n, layer by layer:
+// starts[l], splits[l] describe the sets entering layer l of the split, and
+// the final sets are (fstart, fsize).  The sizes depend on m and n only.
+struct SplitPlan {
+    std::vector<std::vector<uint32_t>> starts;
+    std::vector<std::vector<uint8_t>> splits;
+    std::vector<uint32_t> fstart, fsize;
+};
+
+SplitPlan plan_split(uint32_t m, uint32_t n)
+{
+    SplitPlan p;
+    std::vector<uint32_t> st{0}, sz{m};
+    for (;;) {
+        bool any = false;
+        for (uint32_t z : sz) any |= z > n;
+        if (!any) break;
+        std::vector<uint8_t> sp(sz.size());
+        std::vector<uint32_t> nst, nsz;
+        for (size_t i = 0; i < sz.size(); ++i) {
+            sp[i] = sz[i] > n ? 1 : 0;
+            if (sp[i]) {
+                const uint32_t h = (sz[i] + 1) / 2;
+                nst.push_back(st[i]);
+                nsz.push_back(h);
+                nst.push_back(st[i] + h);
+                nsz.push_back(sz[i] - h);
+            } else {
+                nst.push_back(st[i]);
+                nsz.push_back(sz[i]);
+            }
+        }
+        p.starts.push_back(st);
+        p.splits.push_back(sp);
+        st.swap(nst);
+        sz.swap(nsz);
+    }
+    p.fstart = st;
+    p.fsize = sz;
+    return p;
+}
+
+struct DevBuf {  // a device allocation freed on scope exit (movable, not copyable)
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p) { o.p = nullptr; }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        std::swap(p, o.p);
+        return *this;
+    }
+    ~DevBuf() { dev_free(p); }
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+template <class T>
+int dev_make(DevBuf &b, uint64_t count)
+{
+    T *q = nullptr;
+    const int rc = dev_alloc(&q, count);
+    b.p = q;
+    return rc;
+}
+
+template <class T>
+int upload(DevBuf &b, const T *h, uint64_t count)
+{
+    int rc = dev_make<T>(b, count);
+    if (rc) return rc;
+    if (count) HIP_TRY(hipMemcpy(b.p, h, count * sizeof(T), hipMemcpyHostToDevice));
+    return V3DG_OK;
+}
+
+// device-to-host copy after the stream's work so far
+int d2h(void *dst, const void *src, uint64_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return V3DG_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return V3DG_OK;
+}
+
+uint32_t bits_of(uint64_t v)  // bits to hold 0 .. v
+{
+    uint32_t b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+// Median split of the m items in *items (device, current order, replaced by
+// the split order) by their points (x y z per item id) into sets of at most n.
+int device_split(hipStream_t st, const float *pts, DevBuf &items, DevBuf &spare, uint32_t m, uint32_t n,
+                 std::vector<uint32_t> *fstart, std::vector<uint32_t> *fsize)
+{
+    const SplitPlan plan = plan_split(m, n);
+    DevBuf keys, box, d_start, d_split;
+    int rc;
+    if ((rc = dev_make<uint64_t>(keys, m))) return rc;
+    for (size_t l = 0; l < plan.starts.size(); ++l) {
+        const uint32_t ns = (uint32_t)plan.starts[l].size();
+        DevBuf a, b, c;
+        if ((rc = upload(a, plan.starts[l].data(), ns))) return rc;
+        if ((rc = upload(b, plan.splits[l].data(), ns))) return rc;
+        if ((rc = dev_make<uint32_t>(c, 6ull * ns))) return rc;
+        launch_split_layer(st, pts, items.as<uint32_t>(), m, a.as<uint32_t>(), b.as<uint8_t>(), ns, c.as<uint32_t>(),
+                           keys.as<uint64_t>(), spare.as<uint32_t>());
+        HIP_TRY(hipGetLastError());
+        if ((rc = v3dg_sort_pairs(keys.as<uint64_t>(), spare.as<uint32_t>(), m, 32 + std::max<uint32_t>(bits_of(ns - 1), 1),
+                                  st)))
+            return rc;
+        std::swap(items.p, spare.p);
+    }
+    *fstart = plan.fstart;
+    *fsize = plan.fsize;
+    return V3DG_OK;
+}
+
+// One layer of the bundle during the build: its clusters (in the order they
+// were made), their rows in a layer-local row store, own spheres, children
+// (positions in the previous layer's grouping order) and the grouping order.
+struct BuildLayer {
+    DevBuf rows, first, count, sph;
+    std::vector<uint32_t> h_first, h_count, h_rows, perm;
+    std::vector<float> h_sph;
+    std::vector<uint32_t> child_first, child_n;
+};
+
+int build_impl(const float *pos, const float *scale, const float *rot, const float *opacity, const float *sh,
+               uint32_t n, uint32_t sh_degree, uint32_t cap, hipStream_t st, v3dg_bundle *B)
+{
+    const uint32_t shf = 3u * (sh_degree + 1u) * (sh_degree + 1u);
+    DevBuf d_pos, d_scale, d_opacity, spare, err;
+    int rc;
+    if ((rc = upload(d_pos, pos, 3ull * n))) return rc;
+    if ((rc = upload(d_scale, scale, 3ull * n))) return rc;
+    if ((rc = upload(d_opacity, opacity, (uint64_t)n))) return rc;
+    if ((rc = dev_make<uint32_t>(err, 1))) return rc;
+    HIP_TRY(hipMemset(err.p, 0, sizeof(uint32_t)));
+
+    std::vector<BuildLayer> L(1);
+    {  // layer C_0: the split of the Gaussians
+        std::vector<uint32_t> iota(n);
+        for (uint32_t i = 0; i < n; ++i) iota[i] = i;
+        if ((rc = upload(L[0].rows, iota.data(), (uint64_t)n))) return rc;
+        if ((rc = dev_make<uint32_t>(spare, n))) return rc;
+        if ((rc = device_split(st, d_pos.as<float>(), L[0].rows, spare, n, cap, &L[0].h_first, &L[0].h_count)))
+            return rc;
+        const uint32_t C = (uint32_t)L[0].h_first.size();
+        if ((rc = upload(L[0].first, L[0].h_first.data(), C))) return rc;
+        if ((rc = upload(L[0].count, L[0].h_count.data(), C))) return rc;
+        if ((rc = dev_make<float>(L[0].sph, 4ull * C))) return rc;
+        DevBuf mean;
+        if ((rc = dev_make<float>(mean, 3ull * C))) return rc;
+        launch_cluster_mean(st, d_pos.as<float>(), L[0].rows.as<uint32_t>(), L[0].first.as<uint32_t>(),
+                            L[0].count.as<uint32_t>(), C, mean.as<float>(), L[0].sph.as<float>());
+        HIP_TRY(hipGetLastError());
+        L[0].child_first.assign(C, 0);
+        L[0].child_n.assign(C, 0);
+    }
+    // coarser layers while a layer holds two clusters or more
+    for (uint32_t gen = 0;; ++gen) {
+        BuildLayer &cur = L.back();
+        const uint32_t C = (uint32_t)cur.h_first.size();
+        if (C < 2) {
+            cur.perm.assign(C, 0);
+            for (uint32_t k = 0; k < C; ++k) cur.perm[k] = k;
+            break;
+        }
+        if (gen >= 250) return fail(V3DG_ERR_DEVICE, "offline build: too many layers");
+        DevBuf mean, gitems, gspare, d_gfirst, d_gsize;
+        if ((rc = dev_make<float>(mean, 3ull * C))) return rc;
+        launch_cluster_mean(st, d_pos.as<float>(), cur.rows.as<uint32_t>(), cur.first.as<uint32_t>(),
+                            cur.count.as<uint32_t>(), C, mean.as<float>(), nullptr);
+        HIP_TRY(hipGetLastError());
+        std::vector<uint32_t> iota(C), gfirst, gsize;
+        for (uint32_t k = 0; k < C; ++k) iota[k] = k;
+        if ((rc = upload(gitems, iota.data(), C))) return rc;
+        if ((rc = dev_make<uint32_t>(gspare, C))) return rc;
+        if ((rc = device_split(st, mean.as<float>(), gitems, gspare, C, 2, &gfirst, &gsize))) return rc;
+        cur.perm.resize(C);
+        if ((rc = d2h(cur.perm.data(), gitems.p, C * sizeof(uint32_t), st))) return rc;
+        const uint32_t G = (uint32_t)gfirst.size();
+        if ((rc = upload(d_gfirst, gfirst.data(), G))) return rc;
+        if ((rc = upload(d_gsize, gsize.data(), G))) return rc;
+        BuildLayer nx;
+        if ((rc = dev_make<uint32_t>(nx.rows, (uint64_t)G * cap))) return rc;
+        if ((rc = dev_make<uint32_t>(nx.count, G))) return rc;
+        if ((rc = dev_make<float>(nx.sph, 4ull * G))) return rc;
+        launch_group(st, d_pos.as<float>(), d_scale.as<float>(), d_opacity.as<float>(), gen, cur.rows.as<uint32_t>(),
+                     cur.first.as<uint32_t>(), cur.count.as<uint32_t>(), cur.sph.as<float>(), gitems.as<uint32_t>(),
+                     d_gfirst.as<uint32_t>(), d_gsize.as<uint32_t>(), G, cap, nx.rows.as<uint32_t>(),
+                     nx.count.as<uint32_t>(), nx.sph.as<float>(), err.as<uint32_t>());
+        HIP_TRY(hipGetLastError());
+        nx.h_first.resize(G);
+        for (uint32_t g = 0; g < G; ++g) nx.h_first[g] = g * cap;
+        if ((rc = upload(nx.first, nx.h_first.data(), G))) return rc;
+        nx.h_count.resize(G);
+        if ((rc = d2h(nx.h_count.data(), nx.count.p, G * sizeof(uint32_t), st))) return rc;
+        nx.child_first = gfirst;
+        nx.child_n = gsize;
+        L.push_back(std::move(nx));
+    }
+    uint32_t e = 0;
+    if ((rc = d2h(&e, err.p, sizeof(uint32_t), st))) return rc;
+    if (e) return fail(V3DG_ERR_DEVICE, "offline build: a cluster group exceeded its bounds");
+
+    // ids (layer-major, grouping order), rows, links
+    const uint32_t NL = (uint32_t)L.size();
+    std::vector<uint32_t> base(NL + 1, 0);
+    for (uint32_t l = 0; l < NL; ++l) base[l + 1] = base[l] + (uint32_t)L[l].h_first.size();
+    const uint32_t C = base[NL];
+    B->n_clusters = C;
+    B->n_leaf = base[1];
+    B->n_layers = NL;
+    B->sh_floats = shf;
+    B->first_row.assign(C, 0);
+    B->count.assign(C, 0);
+    B->level.assign(C, 0);
+    B->parent.assign(C, -1);
+    B->first_child.assign(C, -1);
+    B->n_children.assign(C, 0);
+    B->self_sphere.assign(4ull * C, 0.f);
+    B->parent_sphere.assign(4ull * C, 0.f);
+    uint64_t row = 0;
+    for (uint32_t l = 0; l < NL; ++l) {
+        BuildLayer &ly = L[l];
+        const uint32_t Cl = (uint32_t)ly.h_first.size();
+        ly.h_sph.resize(4ull * Cl);
+        if ((rc = d2h(ly.h_sph.data(), ly.sph.p, 4ull * Cl * sizeof(float), st))) return rc;
+        uint64_t store = 0;
+        for (uint32_t k = 0; k < Cl; ++k) store = std::max<uint64_t>(store, (uint64_t)ly.h_first[k] + ly.h_count[k]);
+        ly.h_rows.resize(store);
+        if ((rc = d2h(ly.h_rows.data(), ly.rows.p, store * sizeof(uint32_t), st))) return rc;
+        for (uint32_t p = 0; p < Cl; ++p) {
+            const uint32_t k = ly.perm[p], id = base[l] + p;
+            B->first_row[id] = (uint32_t)row;
+            B->count[id] = (uint8_t)ly.h_count[k];
+            B->level[id] = (uint8_t)l;
+            for (int a = 0; a < 4; ++a) B->self_sphere[4ull * id + a] = ly.h_sph[4ull * k + a];
+            if (l > 0) {
+                B->first_child[id] = (int32_t)(base[l - 1] + ly.child_first[k]);
+                B->n_children[id] = (uint8_t)ly.child_n[k];
+                for (uint32_t i = 0; i < ly.child_n[k]; ++i) B->parent[base[l - 1] + ly.child_first[k] + i] = (int32_t)id;
+            }
+            for (uint32_t i = 0; i < ly.h_count[k]; ++i) {
+                B->src.push_back(ly.h_rows[ly.h_first[k] + i]);
+                B->gen.push_back((uint8_t)l);
+            }
+            row += ly.h_count[k];
+        }
+    }
+    for (uint32_t id = 0; id < C; ++id) {
+        const int32_t par = B->parent[id];
+        for (int a = 0; a < 4; ++a)
+            B->parent_sphere[4ull * id + a] = par < 0 ? (a == 3 ? INFINITY : B->self_sphere[4ull * id + a])
+                                                      : B->self_sphere[4ull * par + a];
+    }
+    // rows: the input Gaussians with grown scales, gathered on the device
+    const uint32_t R = (uint32_t)row;
+    B->n_rows = R;
+    DevBuf d_rot, d_sh, d_src, d_gen, o_pos, o_scale, o_rot, o_op, o_sh;
+    if ((rc = upload(d_rot, rot, 4ull * n))) return rc;
+    if ((rc = upload(d_sh, sh, (uint64_t)shf * n))) return rc;
+    if ((rc = upload(d_src, B->src.data(), R))) return rc;
+    if ((rc = upload(d_gen, B->gen.data(), R))) return rc;
+    if ((rc = dev_make<float>(o_pos, 3ull * R))) return rc;
+    if ((rc = dev_make<float>(o_scale, 3ull * R))) return rc;
+    if ((rc = dev_make<float>(o_rot, 4ull * R))) return rc;
+    if ((rc = dev_make<float>(o_op, R))) return rc;
+    if ((rc = dev_make<float>(o_sh, (uint64_t)shf * R))) return rc;
+    launch_bundle_rows(st, d_pos.as<float>(), d_scale.as<float>(), d_rot.as<float>(), d_opacity.as<float>(),
+                       d_sh.as<float>(), shf, d_src.as<uint32_t>(), d_gen.as<uint8_t>(), R, o_pos.as<float>(),
+                       o_scale.as<float>(), o_rot.as<float>(), o_op.as<float>(), o_sh.as<float>());
+    HIP_TRY(hipGetLastError());
+    B->pos.resize(3ull * R);
+    B->scale.resize(3ull * R);
+    B->rot.resize(4ull * R);
+    B->opacity.resize(R);
+    B->sh.resize((uint64_t)shf * R);
+    HIP_TRY(hipMemcpyAsync(B->pos.data(), o_pos.p, 3ull * R * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(B->scale.data(), o_scale.p, 3ull * R * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(B->rot.data(), o_rot.p, 4ull * R * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(B->opacity.data(), o_op.p, (uint64_t)R * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(B->sh.data(), o_sh.p, (uint64_t)shf * R * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return V3DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int v3dg_build_bundle(const float *pos, const float *scale, const float *rot, const float *opacity, const float *sh,
+                      uint32_t n, uint32_t sh_degree, uint32_t cluster_size, v3dg_bundle **out)
+{
+    g_err.clear();
+    if (!out) return fail(V3DG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!pos || !scale || !rot || !opacity || !sh) return fail(V3DG_ERR_INVALID_ARG, "NULL input array");
+    if (n == 0 || n >= (1u << 31)) return fail(V3DG_ERR_INVALID_ARG, "n must be 1 .. 2^31-1");
+    if (sh_degree > 3) return fail(V3DG_ERR_INVALID_ARG, "sh_degree must be 0..3");
+    if (cluster_size < 2 || cluster_size > 64) return fail(V3DG_ERR_INVALID_ARG, "cluster_size must be 2..64");
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreate(&st));  // blocking: the synchronous uploads are ordered with its work
+    v3dg_bundle *B = new v3dg_bundle();
+    const int rc = build_impl(pos, scale, rot, opacity, sh, n, sh_degree, cluster_size, st, B);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (rc) {
+        delete B;
+        return rc;
+    }
+    *out = B;
+    return V3DG_OK;
+}
+
+int v3dg_bundle_sizes(const v3dg_bundle *b, uint32_t *n_clusters, uint32_t *n_rows, uint32_t *n_leaf_clusters,
+                      uint32_t *n_layers)
+{
+    g_err.clear();
+    if (!b) return fail(V3DG_ERR_INVALID_ARG, "bundle is NULL");
+    if (n_clusters) *n_clusters = b->n_clusters;
+    if (n_rows) *n_rows = b->n_rows;
+    if (n_leaf_clusters) *n_leaf_clusters = b->n_leaf;
+    if (n_layers) *n_layers = b->n_layers;
+    return V3DG_OK;
+}
+
+int v3dg_bundle_copy(const v3dg_bundle *b, float *pos, float *scale, float *rot, float *opacity, float *sh,
+                     float *self_sphere, float *parent_sphere, uint32_t *first_row, uint8_t *count, uint8_t *level,
+                     int32_t *parent, int32_t *first_child, uint8_t *n_children, uint32_t *src, uint8_t *gen)
+{
+    g_err.clear();
+    if (!b) return fail(V3DG_ERR_INVALID_ARG, "bundle is NULL");
+    auto cp = [](void *dst, const void *from, size_t bytes) {
+        if (dst && bytes) std::memcpy(dst, from, bytes);
+    };
+    cp(pos, b->pos.data(), b->pos.size() * 4);
+    cp(scale, b->scale.data(), b->scale.size() * 4);
+    cp(rot, b->rot.data(), b->rot.size() * 4);
+    cp(opacity, b->opacity.data(), b->opacity.size() * 4);
+    cp(sh, b->sh.data(), b->sh.size() * 4);
+    cp(self_sphere, b->self_sphere.data(), b->self_sphere.size() * 4);
+    cp(parent_sphere, b->parent_sphere.data(), b->parent_sphere.size() * 4);
+    cp(first_row, b->first_row.data(), b->first_row.size() * 4);
+    cp(count, b->count.data(), b->count.size());
+    cp(level, b->level.data(), b->level.size());
+    cp(parent, b->parent.data(), b->parent.size() * 4);
+    cp(first_child, b->first_child.data(), b->first_child.size() * 4);
+    cp(n_children, b->n_children.data(), b->n_children.size());
+    cp(src, b->src.data(), b->src.size() * 4);
+    cp(gen, b->gen.data(), b->gen.size());
+    return V3DG_OK;
+}
+
+void v3dg_bundle_free(v3dg_bundle *b) { delete b; }
+
+}  // extern "C"

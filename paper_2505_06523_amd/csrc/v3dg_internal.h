@@ -291,4 +291,26 @@ void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t
 // generic fill
 void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);
 
+// build.hip (offline build)
+constexpr double kScaleGrowth = 1.122462048309373;  // 2^(1/6): scale growth of a simplified Gaussian
+constexpr double kNestSlack = 1.0 + 1.0 / 1024.0;   // parent radius over (distance + child radius)
+// One layer of a median split of m items (item ids into pts, x y z per id):
+// sets start at start[0..n_sets) and split where splits[s] != 0; writes
+// keys (set << 32 | coordinate bits) and vals (items) for the stable sort.
+void launch_split_layer(hipStream_t st, const float *pts, const uint32_t *items, uint32_t m, const uint32_t *start,
+                        const uint8_t *splits, uint32_t n_sets, uint32_t *box, uint64_t *keys, uint32_t *vals);
+// mean[k] = FP64 mean (row order) of the positions of cluster k's rows
+// rows[first[k] ..], in FP32; sph4 (optional) = (mean, 0)
+void launch_cluster_mean(hipStream_t st, const float *pos, const uint32_t *rows, const uint32_t *first,
+                         const uint32_t *count, uint32_t n, float *mean, float *sph4);
+// Simplification of n_groups cluster groups into one cluster each (see build.hip)
+void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, uint32_t gen,
+                  const uint32_t *rows, const uint32_t *first, const uint32_t *count, const float *msph,
+                  const uint32_t *perm, const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap,
+                  uint32_t *out_rows, uint32_t *out_count, float *sph, uint32_t *err);
+// bundle row i = input Gaussian src[i] with its scales grown gen[i] times
+void launch_bundle_rows(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
+                        const float *sh, uint32_t sh_floats, const uint32_t *src, const uint8_t *gen, uint32_t n_rows,
+                        float *opos, float *oscale, float *orot, float *oopacity, float *osh);
+
 }  // namespace v3dg

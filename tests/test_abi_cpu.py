@@ -144,3 +144,27 @@ def test_null_arguments():
     assert L.v3dg_sort_pairs(None, None, 0, 8, None) == v.V3DG_OK
     L.v3dg_selection_free(None)
     L.v3dg_scene_free(None)
+
+
+def test_build_bundle_rejects_bad_arguments():
+    L = v.lib()
+    n = 16
+    pos = np.zeros((n, 3), np.float32)
+    scale = np.ones((n, 3), np.float32)
+    rot = np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1))
+    op = np.ones(n, np.float32)
+    sh = np.zeros((n, 4, 3), np.float32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+    args = [p(pos), p(scale), p(rot), p(op), p(sh)]
+    assert L.v3dg_build_bundle(*args, n, 1, 64, None) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, 0, 1, 64, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 4, 64, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 1, 1, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 1, 65, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert "cluster_size" in v.last_error()
+    assert L.v3dg_build_bundle(None, *args[1:], n, 1, 64, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert not h.value
+    assert L.v3dg_bundle_sizes(None, None, None, None, None) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_bundle_copy(None, *([None] * 15)) == v.V3DG_ERR_INVALID_ARG
+    L.v3dg_bundle_free(None)
