@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-tiers", action="store_true", help="skip the storage-precision comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-culling", action="store_true", help="skip the view-culling measurement")
+    ap.add_argument("--no-build", action="store_true", help="skip the offline-build measurement")
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
                     help="time the frames without any events (the roofline then comes from a second pass)")
@@ -221,6 +222,36 @@ def serving_bench(torch, v, sg):
     for sc in scenes:
         sc.close()
     del pool
+    return out
+
+
+def build_bench(v, asset, with_oracle: bool):
+    """Offline build (paper Algorithm 1, structural part) of the asset's 1M leaf
+    Gaussians on the GPU, host arrays in and out; the oracle on the same input."""
+    import numpy as np
+    L = asset.n_leaf_rows
+    g_in = (asset.pos[:L], asset.scale[:L], asset.rot[:L], asset.opacity[:L], asset.sh[:L])
+    v.build_bundle(*(x[:4096] for x in g_in), 64)  # first use: kernel loading
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        b = v.build_bundle(*g_in, 64)
+        times.append(time.perf_counter() - t0)
+    out = {"workload": "%d leaf Gaussians (SH3) of the benchmark asset, clusters of 64, groups of 2" % L,
+           "gpu_ms": 1e3 * float(np.median(times)), "gpu_gaussians_per_s": L / float(np.median(times)),
+           "clusters": int(len(b["count"])), "rows": int(len(b["src"])), "layers": int(b["n_layers"]),
+           "includes": "host-to-device upload, all build launches, row gather and device-to-host copy"}
+    log("offline build: %d Gaussians -> %d clusters, %d rows in %.1f ms on the GPU" % (L, out["clusters"],
+                                                                                      out["rows"], out["gpu_ms"]))
+    if with_oracle:
+        from oracle import offline_build as ob
+        t0 = time.perf_counter()
+        ob.build_bundle(*g_in, 64)
+        t = time.perf_counter() - t0
+        out["oracle_s"] = t
+        out["oracle_gaussians_per_s"] = L / t
+        out["oracle_kind"] = "numpy oracle, one host process"
+        log("offline build oracle: %.1f s" % t)
     return out
 
 
@@ -400,6 +431,9 @@ def main():
     culling = None
     if not args.no_culling and not args.profile_run and not args.quick:
         culling = culling_bench(torch, v, sg, asset)
+    build = None
+    if not args.no_build and not args.profile_run and not args.quick:
+        build = build_bench(v, asset, not args.no_cpu)
     serving = None
     if not args.no_serving and not args.profile_run and not args.quick:
         serving = serving_bench(torch, v, sg)
@@ -463,6 +497,7 @@ def main():
         "precision_tiers": tiers,
         "serving": serving,
         "culling": culling,
+        "offline_build": build,
         "roofline": roof,
     }
 
