@@ -225,6 +225,34 @@ def serving_bench(torch, v, sg):
     return out
 
 
+def tau_sweep(torch, scene, cams, taus, img, img2, fps_full):
+    """FPS, p50/p99, speed-up over full detail, LOD factor and PSNR against full
+    detail (every 8th camera) at each tolerance."""
+    import numpy as np
+    out = {}
+    for tau in taus:
+        fr = [(c, tau) for c in cams]
+        w_e, ms_e, P_e, _ = run_frames(torch, scene, fr, img, full=False, prof=False)
+        q, fac = [], []
+        sel = None
+        for cam, _ in fr[::8]:
+            sel = scene.select(cam, tau, sel)
+            scene.render(cam, sel, img)
+            n_sel = scene.frame_stats()["n_slots"]
+            scene.render_full(cam, img2)
+            n_full = scene.frame_stats()["n_slots"]
+            mse = float(((img[..., :3].clamp(0, 1) - img2[..., :3].clamp(0, 1)) ** 2).mean())
+            q.append(float("inf") if mse == 0 else 10 * math.log10(1 / mse))
+            fac.append(n_full / max(n_sel, 1))
+        out["%g" % tau] = dict(fps=len(fr) / w_e, p50_ms=pct(ms_e, 50), p99_ms=pct(ms_e, 99),
+                               speedup_vs_full=(len(fr) / w_e) / fps_full,
+                               allowed_factor_mean=float(np.mean(fac)),
+                               psnr_vs_full_db_min=float(np.min(q)),
+                               psnr_vs_full_db_median=float(np.median(q)),
+                               selected_gaussians_mean=P_e["slots"] / max(P_e["frames"], 1))
+    return out
+
+
 def build_bench(v, asset, with_oracle: bool):
     """Offline build (paper Algorithm 1, structural part) of the asset's 1M leaf
     Gaussians on the GPU, host arrays in and out; the oracle on the same input."""
@@ -369,26 +397,34 @@ def main():
 
     extended = {}
     if not args.no_extended:
-        for tau in [64.0, 256.0, 1024.0, 4096.0]:
-            fr = [(c, tau) for c in cams]
-            w_e, ms_e, P_e, _ = run_frames(torch, scene, fr, img, full=False, prof=False)
-            q, fac = [], []
-            sel = None
-            for cam, _ in fr[::8]:
-                sel = scene.select(cam, tau, sel)
-                scene.render(cam, sel, img)
-                n_sel = scene.frame_stats()["n_slots"]
-                scene.render_full(cam, img2)
-                n_full = scene.frame_stats()["n_slots"]
-                mse = float(((img[..., :3].clamp(0, 1) - img2[..., :3].clamp(0, 1)) ** 2).mean())
-                q.append(float("inf") if mse == 0 else 10 * math.log10(1 / mse))
-                fac.append(n_full / max(n_sel, 1))
-            extended["%g" % tau] = dict(fps=len(fr) / w_e, p50_ms=pct(ms_e, 50), p99_ms=pct(ms_e, 99),
-                                        speedup_vs_full=(len(fr) / w_e) / fps_full,
-                                        allowed_factor_mean=float(np.mean(fac)),
-                                        psnr_vs_full_db_min=float(np.min(q)),
-                                        psnr_vs_full_db_median=float(np.median(q)),
-                                        selected_gaussians_mean=P_e["slots"] / max(P_e["frames"], 1))
+        extended = tau_sweep(torch, scene, cams, [64.0, 256.0, 1024.0, 4096.0], img, img2, fps_full)
+
+    # the same leaves built into a bundle by the paper's Algorithm 1 on the GPU
+    # (halving with 2^(1/6) scale growth instead of the generator's merges)
+    built = None
+    if not args.no_extended and not args.no_build:
+        L = asset.n_leaf_rows
+        t0 = time.perf_counter()
+        bb = v.build_bundle(asset.pos[:L], asset.scale[:L], asset.rot[:L], asset.opacity[:L], asset.sh[:L], 64)
+        t_b = time.perf_counter() - t0
+        bscene = v.Scene(sg.Asset(sh_degree=3, pos=bb["pos"], scale=bb["scale"], rot=bb["rot"],
+                                  opacity=bb["opacity"], sh=bb["sh"], first_row=bb["first_row"], count=bb["count"],
+                                  level=bb["level"], parent=bb["parent"], first_child=bb["first_child"],
+                                  n_children=bb["n_children"], self_sphere=bb["self_sphere"],
+                                  parent_sphere=bb["parent_sphere"], n_leaf_clusters=bb["n_leaf_clusters"]))
+        fr = [(c, 0.0) for c in cams]
+        run_frames(torch, bscene, fr[:8], img, full=True, prof=False)  # warm-up: the scene's first buffers
+        run_frames(torch, bscene, [(c, 4096.0) for c in cams[:8]], img, full=False, prof=False)
+        w_bf, _, _, _ = run_frames(torch, bscene, fr, img, full=True, prof=False)
+        built = dict(build_s=t_b, clusters=int(len(bb["count"])), rows=int(len(bb["src"])),
+                     full_detail_fps=len(fr) / w_bf,
+                     tolerances=tau_sweep(torch, bscene, cams, [1.0, 64.0, 256.0, 1024.0, 4096.0], img, img2,
+                                          len(fr) / w_bf))
+        for k, e in built["tolerances"].items():
+            log("built bundle tau %s: %.1f FPS (%.2fx full detail), PSNR min %.1f dB" % (
+                k, e["fps"], e["speedup_vs_full"], e["psnr_vs_full_db_min"]))
+        bscene.close()
+        del bb
 
     # storage tiers: FP32 vs FP16 geometry with BF16 / FP16 SH, at 1080p and 2160p
     tiers = {}
@@ -494,6 +530,7 @@ def main():
         "stages": stages,
         "sort_hbm_gbs": (sort_b / (sort_t * 1e-3) / 1e9) if sort_t > 0 else None,
         "extended_tolerances": extended,
+        "built_bundle": built,
         "precision_tiers": tiers,
         "serving": serving,
         "culling": culling,
