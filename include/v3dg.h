@@ -353,6 +353,31 @@ int v3dg_bundle_copy(const v3dg_bundle *b, float *pos, float *scale, float *rot,
 
 void v3dg_bundle_free(v3dg_bundle *b);
 
+/* Local splatting of cluster groups (paper Sec. 3.2), on the GPU.  Group g
+ * fits its simplified ("fitted") Gaussians, rows fit_first[g] .. +
+ * fit_count[g] - 1 (at most 64), to its original Gaussians, rows orig_first[g]
+ * .. + orig_count[g] - 1 (at most 128): for view i < iters, both sets are
+ * splatted at 64 x 64 from c + 4 r d_i towards the centre c of sphere[g] =
+ * (cx, cy, cz, r > 0), with d_i = view_dirs[3i .. 3i+2] (normalised here; up
+ * = +z unless |d_z| > 0.99, then +y; focal 32 / tan(asin(1/4))).  Splatting
+ * is the renderer's (no dilation, alpha = min(0.99, o e^power), skip below
+ * 1/255, stop before T < 1e-4, background 0) with colour max(0, C0 dc + 0.5)
+ * from the degree-0 SH term dc.  Loss: mean |rgb - target| + 0.1 mean |alpha -
+ * target alpha|; one Adam step (0.9, 0.999, eps 1e-15) per view on position,
+ * log scale, quaternion, logit opacity and dc with learning rates 1.6e-5 (the
+ * paper's), 5e-3, 1e-3, 5e-2, 2.5e-3.  Rows are host arrays: pos, scale (x 3),
+ * rot (x 4, w x y z), opacity, dc (x 3); the fitted rows are updated in place
+ * (quaternions returned unit).  losses (n_groups x iters, before each step)
+ * and grad_first (14 per fitted row: the gradients of the first view) may be
+ * NULL.  Synchronises.  Errors: V3DG_ERR_INVALID_ARG, V3DG_ERR_OOM,
+ * V3DG_ERR_HIP, V3DG_ERR_DEVICE. */
+int v3dg_local_splat(uint32_t n_groups, const uint32_t *orig_first, const uint32_t *orig_count,
+                     const uint32_t *fit_first, const uint32_t *fit_count, const float *sphere, const float *orig_pos,
+                     const float *orig_scale, const float *orig_rot, const float *orig_opacity, const float *orig_dc,
+                     uint32_t n_orig, float *fit_pos, float *fit_scale, float *fit_rot, float *fit_opacity,
+                     float *fit_dc, uint32_t n_fit, const float *view_dirs, uint32_t iters, float *losses,
+                     float *grad_first);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *v3dg_last_error(void);
 

@@ -150,7 +150,7 @@ def local_splat(orig, simp, center, radius, dirs, iters):
         for t in ps.values():
             t.grad = None
         loss.backward()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
         if g_first is None:
             g_first = {k: t.grad.detach().numpy().copy() for k, t in ps.items()}
         with torch.no_grad():

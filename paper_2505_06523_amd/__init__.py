@@ -98,7 +98,7 @@ EXPORTS = [
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
     "v3dg_last_error",
     "v3dg_server_create", "v3dg_server_submit", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
-    "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_free",
+    "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_free", "v3dg_local_splat",
 ]
 
 _lib = None
@@ -143,6 +143,7 @@ def lib():
         "v3dg_bundle_sizes": ([P, P, P, P, P], I),
         "v3dg_bundle_copy": ([P] + [P] * 15, I),
         "v3dg_bundle_free": ([P], None),
+        "v3dg_local_splat": ([U32] + [P] * 10 + [U32] + [P] * 5 + [U32, P, U32, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -513,6 +514,30 @@ def build_bundle(pos, scale, rot, opacity, sh, cluster_size: int = 64) -> dict:
         return out
     finally:
         lib().v3dg_bundle_free(h)
+
+
+def local_splat(groups, orig: dict, fit: dict, view_dirs, iters: int):
+    """Local splatting on the GPU (v3dg_local_splat).  groups: list of
+    (orig_first, orig_count, fit_first, fit_count, (cx, cy, cz, r)); orig /
+    fit: dicts of host rows pos, scale, rot, opacity, dc.  Returns the fitted
+    rows, losses (groups x iters) and the first view's gradients (rows x 14)."""
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    u32 = lambda a: np.ascontiguousarray(a, np.uint32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    G = len(groups)
+    of, oc, ff, fc = (u32([g[i] for g in groups]) for i in range(4))
+    sph = f32([g[4] for g in groups]).reshape(G, 4)
+    o = {k: f32(orig[k]) for k in ("pos", "scale", "rot", "opacity", "dc")}
+    f = {k: f32(fit[k]).copy() for k in ("pos", "scale", "rot", "opacity", "dc")}
+    dirs = f32(view_dirs).reshape(-1, 3)
+    n_o, n_f = len(o["opacity"]), len(f["opacity"])
+    losses = np.zeros((G, iters), np.float32)
+    grads = np.zeros((n_f, 14), np.float32)
+    _check(lib().v3dg_local_splat(G, ptr(of), ptr(oc), ptr(ff), ptr(fc), ptr(sph), ptr(o["pos"]), ptr(o["scale"]),
+                                  ptr(o["rot"]), ptr(o["opacity"]), ptr(o["dc"]), n_o, ptr(f["pos"]),
+                                  ptr(f["scale"]), ptr(f["rot"]), ptr(f["opacity"]), ptr(f["dc"]), n_f, ptr(dirs),
+                                  int(iters), ptr(losses), ptr(grads)))
+    return f, losses, grads
 
 
 def sort_pairs(keys, vals, key_bits: int, stream=None):

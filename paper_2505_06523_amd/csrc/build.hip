@@ -328,4 +328,478 @@ void launch_bundle_rows(hipStream_t st, const float *pos, const float *scale, co
                        osh);
 }
 
+
+// ---------------------------------------------------------------------------
+// Local splatting of cluster groups (paper Sec. 3.2): the simplified
+// Gaussians of a group are fitted to its original ones.  For every
+// pseudo-view (the group centre seen from four radii away along dirs[it]),
+// both sets are splatted at 64 x 64 as in the renderer (EWA without
+// dilation, guard band 1.3 tan(fov/2), alpha = min(0.99, o e^power), skip
+// below 1/255, stop before T falls below 1e-4, background 0), with the
+// SH degree-0 colour max(0, C0 dc + 0.5); the loss is mean |rgb - target| +
+// 0.1 mean |alpha - target alpha|, and one Adam step (0.9, 0.999, 1e-15)
+// updates position, log scale, quaternion, logit opacity and dc with rates
+// 1.6e-5, 5e-3, 1e-3, 5e-2, 2.5e-3.
+//
+// One 256-thread workgroup per group; each wavefront renders one image row
+// per round (lane = pixel).  The backward walk runs over the fitted splats
+// in reverse depth order, recovering T by division; the per-splat sums of a
+// wavefront are reduced across lanes and kept per wavefront, so every sum is
+// taken in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kLsThreads = 256;
+constexpr int kLsRes = 64;
+constexpr int kLsMaxO = 128;
+constexpr int kLsMaxS = 64;
+constexpr int kLsP = 14;  // pos 0-2, log scale 3-5, quaternion 6-9, logit 10, dc 11-13
+constexpr float kLsC0 = 0.28209479177387814f;
+
+struct LsShared {
+    float prm[kLsMaxS][kLsP], m1[kLsMaxS][kLsP], m2[kLsMaxS][kLsP];
+    float opos[kLsMaxO][3], oscl[kLsMaxO][3], oq[kLsMaxO][4], oop[kLsMaxO], orgb[kLsMaxO][3];
+    // splats of the current view: originals 0 .. 127, fitted ones 128 .. 191
+    float pu[192], pv[192], pca[192], pcb[192], pcc[192], pop[192], psyy[192], pz[192], prgb[192][3];
+    uint8_t pvalid[192];
+    uint8_t ord[192];
+    uint32_t n_o, n_s;
+    float acc[kLsThreads / kWave][kLsMaxS][9];  // per wavefront: du dv dca dcb dcc dop dr dg db
+    float cam[12];                                // world-to-camera rows, eye
+    float red[kLsThreads / kWave];
+};
+
+__device__ __forceinline__ float ls_sigmoid(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// trainable forms of scale and opacity; the originals are rendered through
+// the same forms, so a set fitted to itself renders bit for bit like its target
+__device__ __forceinline__ float ls_logit(float o)
+{
+    o = fminf(fmaxf(o, 1e-6f), 1.0f - 1e-6f);
+    return __logf(o / (1.0f - o));
+}
+
+// camera-space point, screen position, conic and Sigma2_yy of a Gaussian
+__device__ bool ls_project(const float *cam, const float *p, const float *s, const float *qr, float &u, float &v,
+                           float &ca, float &cb, float &cc, float &syy, float &zo)
+{
+    constexpr float f = 123.93546707863734f;  // 32 / tan(asin(1/4)) = 32 sqrt(15)
+    const float dp[3] = {p[0] - cam[9], p[1] - cam[10], p[2] - cam[11]};
+    float pc[3];
+    for (int r = 0; r < 3; ++r) pc[r] = cam[3 * r] * dp[0] + cam[3 * r + 1] * dp[1] + cam[3 * r + 2] * dp[2];
+    zo = pc[2];
+    if (!(pc[2] > 0.01f)) return false;
+    const float z = pc[2];
+    u = f * pc[0] / z + 32.0f;
+    v = f * pc[1] / z + 32.0f;
+    const float lim = 1.3f * 32.0f / f;
+    const float tx = fminf(fmaxf(pc[0] / z, -lim), lim) * z, ty = fminf(fmaxf(pc[1] / z, -lim), lim) * z;
+    const float J[2][3] = {{f / z, 0.0f, -f * tx / (z * z)}, {0.0f, f / z, -f * ty / (z * z)}};
+    float T[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) T[r][c] = J[r][0] * cam[c] + J[r][1] * cam[3 + c] + J[r][2] * cam[6 + c];
+    const float qn = sqrtf(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+    const float w = qr[0] / qn, x = qr[1] / qn, y = qr[2] / qn, zq = qr[3] / qn;
+    const float R[3][3] = {{1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y)},
+                           {2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x)},
+                           {2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)}};
+    float TM[2][3];  // T R S
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) TM[r][c] = (T[r][0] * R[0][c] + T[r][1] * R[1][c] + T[r][2] * R[2][c]) * s[c];
+    const float a = TM[0][0] * TM[0][0] + TM[0][1] * TM[0][1] + TM[0][2] * TM[0][2];
+    const float b = TM[0][0] * TM[1][0] + TM[0][1] * TM[1][1] + TM[0][2] * TM[1][2];
+    const float c = TM[1][0] * TM[1][0] + TM[1][1] * TM[1][1] + TM[1][2] * TM[1][2];
+    const float det = a * c - b * b;
+    if (!(det > 0.0f)) return false;
+    ca = c / det;
+    cb = -b / det;
+    cc = a / det;
+    syy = c;
+    return true;
+}
+
+// the splat reaches the row (pixel centre y) with alpha >= 1/255 somewhere:
+// the largest power over the row is -dy^2 / (2 Sigma2_yy)
+__device__ __forceinline__ bool ls_row_hit(float v, float syy, float op, float yc)
+{
+    const float dy = v - yc;
+    const float lim = 2.0f * syy * __logf(255.0f * op) * 1.01f + 1e-4f;
+    return op * 255.0f >= 1.0f && dy * dy <= lim;
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
+    const uint32_t *__restrict__ ofirst, const uint32_t *__restrict__ ocount, const uint32_t *__restrict__ sfirst,
+    const uint32_t *__restrict__ scount, const float *__restrict__ sphere, const float *__restrict__ opos,
+    const float *__restrict__ oscale, const float *__restrict__ orot, const float *__restrict__ oopacity,
+    const float *__restrict__ odc, uint32_t odc_stride, float *spos, float *sscale, float *srot, float *sopacity,
+    float *sdc, uint32_t sdc_stride, const float *__restrict__ dirs, uint32_t iters, uint32_t n_groups,
+    float *__restrict__ losses, float *__restrict__ grad_first, uint32_t *err)
+{
+    __shared__ LsShared sh;
+    const uint32_t g = blockIdx.x;
+    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    if (g >= n_groups) return;
+    const uint32_t no = ocount[g], ns = scount[g], of = ofirst[g], sf = sfirst[g];
+    if (no > (uint32_t)kLsMaxO || ns > (uint32_t)kLsMaxS) {
+        if (t == 0) atomicOr(err, 2u);
+        return;
+    }
+    if (ns == 0) return;
+    if ((uint32_t)t < no) {
+        for (int a = 0; a < 3; ++a) {
+            sh.opos[t][a] = opos[3ull * (of + t) + a];
+            sh.oscl[t][a] = __expf(__logf(oscale[3ull * (of + t) + a]));
+            sh.orgb[t][a] = fmaxf(0.0f, kLsC0 * odc[(uint64_t)odc_stride * (of + t) + a] + 0.5f);
+        }
+        for (int a = 0; a < 4; ++a) sh.oq[t][a] = orot[4ull * (of + t) + a];
+        sh.oop[t] = ls_sigmoid(ls_logit(oopacity[of + t]));
+    }
+    for (int i = t; i < (int)ns * kLsP; i += kLsThreads) {
+        const int k = i / kLsP, j = i % kLsP;
+        const uint64_t r = sf + k;
+        float val;
+        if (j < 3) val = spos[3 * r + j];
+        else if (j < 6) val = __logf(sscale[3 * r + j - 3]);
+        else if (j < 10) val = srot[4 * r + j - 6];
+        else if (j == 10) val = ls_logit(sopacity[r]);
+        else val = sdc[(uint64_t)sdc_stride * r + j - 11];
+        sh.prm[k][j] = val;
+        sh.m1[k][j] = 0.0f;
+        sh.m2[k][j] = 0.0f;
+    }
+    for (int i = t; i < kLsThreads / kWave * kLsMaxS * 9; i += kLsThreads) (&sh.acc[0][0][0])[i] = 0.0f;
+    const float cx = sphere[4ull * g], cy = sphere[4ull * g + 1], cz = sphere[4ull * g + 2],
+                rad = sphere[4ull * g + 3];
+    const float wr = 1.0f / (float)(kLsRes * kLsRes * 3), wa = 0.1f / (float)(kLsRes * kLsRes);
+    for (uint32_t it = 0; it < iters; ++it) {
+        if (t == 0) {  // pseudo-view it (FP64, rounded)
+            double d[3] = {dirs[3 * it], dirs[3 * it + 1], dirs[3 * it + 2]};
+            const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double eye[3] = {cx + 4.0 * rad * d[0] / dn, cy + 4.0 * rad * d[1] / dn, cz + 4.0 * rad * d[2] / dn};
+            const double fw[3] = {-d[0] / dn, -d[1] / dn, -d[2] / dn};
+            const double up[3] = {0.0, fabs(d[2] / dn) > 0.99 ? 1.0 : 0.0, fabs(d[2] / dn) > 0.99 ? 0.0 : 1.0};
+            double rt[3] = {fw[1] * up[2] - fw[2] * up[1], fw[2] * up[0] - fw[0] * up[2], fw[0] * up[1] - fw[1] * up[0]};
+            const double rn = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+            for (int a = 0; a < 3; ++a) rt[a] /= rn;
+            const double dw[3] = {fw[1] * rt[2] - fw[2] * rt[1], fw[2] * rt[0] - fw[0] * rt[2],
+                                  fw[0] * rt[1] - fw[1] * rt[0]};
+            for (int a = 0; a < 3; ++a) {
+                sh.cam[a] = (float)rt[a];
+                sh.cam[3 + a] = (float)dw[a];
+                sh.cam[6 + a] = (float)fw[a];
+                sh.cam[9 + a] = (float)eye[a];
+            }
+        }
+        __syncthreads();
+        // splats of this view
+        if ((uint32_t)t < no || (t >= kLsMaxO && (uint32_t)(t - kLsMaxO) < ns)) {
+            const bool orig = t < kLsMaxO;
+            const int k = orig ? t : t - kLsMaxO;
+            float p[3], s[3], q[4], op;
+            if (orig) {
+                for (int a = 0; a < 3; ++a) {
+                    p[a] = sh.opos[k][a];
+                    s[a] = sh.oscl[k][a];
+                }
+                for (int a = 0; a < 4; ++a) q[a] = sh.oq[k][a];
+                op = sh.oop[k];
+            } else {
+                for (int a = 0; a < 3; ++a) {
+                    p[a] = sh.prm[k][a];
+                    s[a] = __expf(sh.prm[k][3 + a]);
+                }
+                for (int a = 0; a < 4; ++a) q[a] = sh.prm[k][6 + a];
+                op = ls_sigmoid(sh.prm[k][10]);
+            }
+            float u = 0, v = 0, ca = 0, cb = 0, cc = 0, syy = 0, z = 0;
+            const bool ok = ls_project(sh.cam, p, s, q, u, v, ca, cb, cc, syy, z);
+            sh.pu[t] = u;
+            sh.pv[t] = v;
+            sh.pca[t] = ca;
+            sh.pcb[t] = cb;
+            sh.pcc[t] = cc;
+            sh.psyy[t] = syy;
+            sh.pz[t] = z;
+            sh.pop[t] = op;
+            sh.pvalid[t] = ok ? 1 : 0;
+            for (int a = 0; a < 3; ++a)
+                sh.prgb[t][a] = orig ? sh.orgb[k][a] : fmaxf(0.0f, kLsC0 * sh.prm[k][11 + a] + 0.5f);
+        }
+        __syncthreads();
+        // depth order of the valid splats of each set (ties: index)
+        if ((uint32_t)t < no || (t >= kLsMaxO && (uint32_t)(t - kLsMaxO) < ns)) {
+            const bool orig = t < kLsMaxO;
+            const int base = orig ? 0 : kLsMaxO, cnt = orig ? (int)no : (int)ns, k = t - base;
+            if (sh.pvalid[t]) {
+                int rank = 0;
+                for (int j = 0; j < cnt; ++j)
+                    if (sh.pvalid[base + j] && (sh.pz[base + j] < sh.pz[t] || (sh.pz[base + j] == sh.pz[t] && j < k)))
+                        ++rank;
+                sh.ord[base + rank] = (uint8_t)k;
+            }
+        }
+        if (t == 0) {
+            uint32_t a = 0, b = 0;
+            for (uint32_t j = 0; j < no; ++j) a += sh.pvalid[j];
+            for (uint32_t j = 0; j < ns; ++j) b += sh.pvalid[kLsMaxO + j];
+            sh.n_o = a;
+            sh.n_s = b;
+        }
+        __syncthreads();
+        const int n_o = (int)sh.n_o, n_s = (int)sh.n_s;
+        float lsum = 0.0f;
+        for (int rr = 0; rr < kLsRes / (kLsThreads / kWave); ++rr) {
+            const float yc = (float)(wid * (kLsRes / (kLsThreads / kWave)) + rr) + 0.5f, xc = (float)lane + 0.5f;
+            float tgt[4];
+            float res[4];
+            int kstop = n_s;
+            for (int set = 0; set < 2; ++set) {
+                const int base = set == 0 ? 0 : kLsMaxO, n = set == 0 ? n_o : n_s;
+                float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                bool live = true;
+                for (int k = 0; k < n; ++k) {
+                    const int i = base + sh.ord[base + k];
+                    if (!ls_row_hit(sh.pv[i], sh.psyy[i], sh.pop[i], yc)) continue;
+                    const float dx = sh.pu[i] - xc, dy = sh.pv[i] - yc;
+                    const float pw = fminf(0.0f, -0.5f * (sh.pca[i] * dx * dx + sh.pcc[i] * dy * dy) -
+                                                     sh.pcb[i] * dx * dy);
+                    const float al = fminf(0.99f, sh.pop[i] * __expf(pw));
+                    const bool take = live && al >= 1.0f / 255.0f;
+                    const float Tn = T * (1.0f - al);
+                    const bool stop = take && Tn < 1e-4f;
+                    if (take && !stop) {
+                        c0 += al * T * sh.prgb[i][0];
+                        c1 += al * T * sh.prgb[i][1];
+                        c2 += al * T * sh.prgb[i][2];
+                        T = Tn;
+                    }
+                    if (stop) {
+                        live = false;
+                        if (set == 1) kstop = k;
+                    }
+                    if (__ballot(live) == 0) break;
+                }
+                float *o4 = set == 0 ? tgt : res;
+                o4[0] = c0;
+                o4[1] = c1;
+                o4[2] = c2;
+                o4[3] = 1.0f - T;
+            }
+            const float Ts = 1.0f - res[3];
+            float gc[3];
+            for (int a = 0; a < 3; ++a) {
+                const float df = res[a] - tgt[a];
+                gc[a] = df > 0.0f ? wr : (df < 0.0f ? -wr : 0.0f);
+                lsum += fabsf(df) * wr;
+            }
+            const float dfa = res[3] - tgt[3];
+            const float ga = dfa > 0.0f ? wa : (dfa < 0.0f ? -wa : 0.0f);
+            lsum += fabsf(dfa) * wa;
+            // reverse walk over the fitted splats this pixel went through
+            int kmax = kstop;
+            for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+            float Tc = Ts, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f;
+            for (int k = kmax - 1; k >= 0; --k) {
+                const int j = sh.ord[kLsMaxO + k], i = kLsMaxO + j;
+                if (!ls_row_hit(sh.pv[i], sh.psyy[i], sh.pop[i], yc)) continue;
+                const float dx = sh.pu[i] - xc, dy = sh.pv[i] - yc;
+                const float raw = -0.5f * (sh.pca[i] * dx * dx + sh.pcc[i] * dy * dy) - sh.pcb[i] * dx * dy;
+                const float G = __expf(fminf(0.0f, raw));
+                const float ao = sh.pop[i] * G;
+                const float al = fminf(0.99f, ao);
+                const bool added = k < kstop && al >= 1.0f / 255.0f;
+                float v9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                if (added) {
+                    const float Tk = Tc / (1.0f - al);
+                    const float cg = sh.prgb[i][0] * gc[0] + sh.prgb[i][1] * gc[1] + sh.prgb[i][2] * gc[2];
+                    const float bg = B0 * gc[0] + B1 * gc[1] + B2 * gc[2];
+                    const float dal = Tk * cg - bg / (1.0f - al) + ga * Ts / (1.0f - al);
+                    v9[6] = al * Tk * gc[0];
+                    v9[7] = al * Tk * gc[1];
+                    v9[8] = al * Tk * gc[2];
+                    B0 += sh.prgb[i][0] * al * Tk;
+                    B1 += sh.prgb[i][1] * al * Tk;
+                    B2 += sh.prgb[i][2] * al * Tk;
+                    Tc = Tk;
+                    if (ao < 0.99f) {
+                        v9[5] = dal * G;
+                        const float dpw = raw < 0.0f ? dal * al : 0.0f;
+                        v9[0] = -dpw * (sh.pca[i] * dx + sh.pcb[i] * dy);
+                        v9[1] = -dpw * (sh.pcb[i] * dx + sh.pcc[i] * dy);
+                        v9[2] = -0.5f * dpw * dx * dx;
+                        v9[3] = -dpw * dx * dy;
+                        v9[4] = -0.5f * dpw * dy * dy;
+                    }
+                }
+                if (__ballot(added) == 0) continue;
+                for (int a = 0; a < 9; ++a) {
+                    const float s9 = wave_sum(v9[a]);
+                    if (lane == 0) sh.acc[wid][j][a] += s9;
+                }
+            }
+        }
+        const float lw = wave_sum(lsum);
+        if (lane == 0) sh.red[wid] = lw;
+        __syncthreads();
+        if (losses && t == 0) losses[(uint64_t)g * iters + it] = sh.red[0] + sh.red[1] + sh.red[2] + sh.red[3];
+        // chain rule and Adam step, one thread per fitted Gaussian
+        if ((uint32_t)t < ns) {
+            const int k = t, i = kLsMaxO + k;
+            float gd[9];
+            for (int a = 0; a < 9; ++a) {
+                gd[a] = sh.acc[0][k][a] + sh.acc[1][k][a] + sh.acc[2][k][a] + sh.acc[3][k][a];
+                sh.acc[0][k][a] = sh.acc[1][k][a] = sh.acc[2][k][a] = sh.acc[3][k][a] = 0.0f;
+            }
+            float gp[kLsP];
+            for (int a = 0; a < kLsP; ++a) gp[a] = 0.0f;
+            const float op = sh.pop[i];
+            gp[10] = gd[5] * op * (1.0f - op);
+            for (int a = 0; a < 3; ++a) gp[11 + a] = (kLsC0 * sh.prm[k][11 + a] + 0.5f > 0.0f) ? kLsC0 * gd[6 + a] : 0.0f;
+            if (sh.pvalid[i]) {
+                constexpr float f = 123.93546707863734f;
+                const float *cam = sh.cam;
+                const float dp[3] = {sh.prm[k][0] - cam[9], sh.prm[k][1] - cam[10], sh.prm[k][2] - cam[11]};
+                float pc[3];
+                for (int r = 0; r < 3; ++r) pc[r] = cam[3 * r] * dp[0] + cam[3 * r + 1] * dp[1] + cam[3 * r + 2] * dp[2];
+                const float z = pc[2];
+                const float lim = 1.3f * 32.0f / f;
+                const float rx = pc[0] / z, ry = pc[1] / z;
+                const bool clx = rx < -lim || rx > lim, cly = ry < -lim || ry > lim;
+                const float tx = fminf(fmaxf(rx, -lim), lim) * z, ty = fminf(fmaxf(ry, -lim), lim) * z;
+                const float J[2][3] = {{f / z, 0.0f, -f * tx / (z * z)}, {0.0f, f / z, -f * ty / (z * z)}};
+                float T[2][3];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 3; ++c) T[r][c] = J[r][0] * cam[c] + J[r][1] * cam[3 + c] + J[r][2] * cam[6 + c];
+                const float *qr = &sh.prm[k][6];
+                const float qn = sqrtf(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+                const float w = qr[0] / qn, x = qr[1] / qn, y = qr[2] / qn, zq = qr[3] / qn;
+                const float R[3][3] = {{1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y)},
+                                       {2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x)},
+                                       {2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)}};
+                float s[3], M[3][3], S3[3][3];
+                for (int a = 0; a < 3; ++a) s[a] = __expf(sh.prm[k][3 + a]);
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) M[r][c] = R[r][c] * s[c];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) S3[r][c] = M[r][0] * M[c][0] + M[r][1] * M[c][1] + M[r][2] * M[c][2];
+                // conic -> Sigma2 = [[a, b], [b, c]] (b read once, as Sigma2[0][1])
+                float TS[2][3];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 3; ++c) TS[r][c] = T[r][0] * S3[0][c] + T[r][1] * S3[1][c] + T[r][2] * S3[2][c];
+                const float a2 = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2];
+                const float b2 = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+                const float c2 = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2];
+                const float det = a2 * c2 - b2 * b2, id2 = 1.0f / (det * det);
+                const float dca = gd[2], dcb = gd[3], dcc = gd[4];
+                const float da = (-c2 * c2 * dca + b2 * c2 * dcb - b2 * b2 * dcc) * id2;
+                const float db = (2.0f * b2 * c2 * dca - (det + 2.0f * b2 * b2) * dcb + 2.0f * a2 * b2 * dcc) * id2;
+                const float dc = (-b2 * b2 * dca + a2 * b2 * dcb - a2 * a2 * dcc) * id2;
+                const float G2[2][2] = {{da, db}, {0.0f, dc}};
+                const float Gs[2][2] = {{2.0f * da, db}, {db, 2.0f * dc}};  // G2 + G2^T
+                // dL/dS3 = T^T G2 T ; dL/dT = (G2 + G2^T) T S3
+                float G3[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        float acc = 0.0f;
+                        for (int m = 0; m < 2; ++m)
+                            for (int nn = 0; nn < 2; ++nn) acc += T[m][r] * G2[m][nn] * T[nn][c];
+                        G3[r][c] = acc;
+                    }
+                float dT[2][3];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 3; ++c) dT[r][c] = Gs[r][0] * TS[0][c] + Gs[r][1] * TS[1][c];
+                // dL/dJ = dL/dT Rv^T
+                float dJ[2][3];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 3; ++c) dJ[r][c] = dT[r][0] * cam[3 * c] + dT[r][1] * cam[3 * c + 1] + dT[r][2] * cam[3 * c + 2];
+                // camera-space point: through J and through (u, v)
+                float dpc[3] = {0.0f, 0.0f, 0.0f};
+                dpc[0] += gd[0] * f / z;
+                dpc[1] += gd[1] * f / z;
+                dpc[2] += -gd[0] * f * pc[0] / (z * z) - gd[1] * f * pc[1] / (z * z);
+                dpc[2] += -(dJ[0][0] + dJ[1][1]) * f / (z * z);
+                if (!clx) {
+                    dpc[0] += -dJ[0][2] * f / (z * z);
+                    dpc[2] += dJ[0][2] * 2.0f * f * pc[0] / (z * z * z);
+                } else {
+                    dpc[2] += dJ[0][2] * f * (tx / z) / (z * z);
+                }
+                if (!cly) {
+                    dpc[1] += -dJ[1][2] * f / (z * z);
+                    dpc[2] += dJ[1][2] * 2.0f * f * pc[1] / (z * z * z);
+                } else {
+                    dpc[2] += dJ[1][2] * f * (ty / z) / (z * z);
+                }
+                for (int a = 0; a < 3; ++a) gp[a] = cam[a] * dpc[0] + cam[3 + a] * dpc[1] + cam[6 + a] * dpc[2];
+                // S3 = M M^T: dL/dM = (G3 + G3^T) M
+                float dM[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        dM[r][c] = (G3[r][0] + G3[0][r]) * M[0][c] + (G3[r][1] + G3[1][r]) * M[1][c] +
+                                   (G3[r][2] + G3[2][r]) * M[2][c];
+                float dR[3][3];
+                for (int c = 0; c < 3; ++c) {
+                    const float ds = dM[0][c] * R[0][c] + dM[1][c] * R[1][c] + dM[2][c] * R[2][c];
+                    gp[3 + c] = ds * s[c];
+                    for (int r = 0; r < 3; ++r) dR[r][c] = dM[r][c] * s[c];
+                }
+                const float gw = 2.0f * (-zq * dR[0][1] + y * dR[0][2] + zq * dR[1][0] - x * dR[1][2] - y * dR[2][0] +
+                                         x * dR[2][1]);
+                const float gx = 2.0f * (y * dR[0][1] + zq * dR[0][2] + y * dR[1][0] - 2.0f * x * dR[1][1] -
+                                         w * dR[1][2] + zq * dR[2][0] + w * dR[2][1] - 2.0f * x * dR[2][2]);
+                const float gy = 2.0f * (-2.0f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] +
+                                         zq * dR[1][2] - w * dR[2][0] + zq * dR[2][1] - 2.0f * y * dR[2][2]);
+                const float gz = 2.0f * (-2.0f * zq * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] -
+                                         2.0f * zq * dR[1][1] + y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+                const float dot = w * gw + x * gx + y * gy + zq * gz;
+                gp[6] = (gw - w * dot) / qn;
+                gp[7] = (gx - x * dot) / qn;
+                gp[8] = (gy - y * dot) / qn;
+                gp[9] = (gz - zq * dot) / qn;
+            }
+            if (grad_first && it == 0)
+                for (int a = 0; a < kLsP; ++a) grad_first[(uint64_t)kLsP * (sf + k) + a] = gp[a];
+            const float b1t = 1.0f - powf(0.9f, (float)(it + 1)), b2t = 1.0f - powf(0.999f, (float)(it + 1));
+            for (int a = 0; a < kLsP; ++a) {
+                const float lr = a < 3 ? 1.6e-5f : (a < 6 ? 5e-3f : (a < 10 ? 1e-3f : (a == 10 ? 5e-2f : 2.5e-3f)));
+                sh.m1[k][a] = 0.9f * sh.m1[k][a] + 0.1f * gp[a];
+                sh.m2[k][a] = 0.999f * sh.m2[k][a] + 0.001f * gp[a] * gp[a];
+                sh.prm[k][a] -= lr * (sh.m1[k][a] / b1t) / (sqrtf(sh.m2[k][a] / b2t) + 1e-15f);
+            }
+        }
+        __syncthreads();
+    }
+    // fitted rows back
+    if ((uint32_t)t < ns) {
+        const int k = t;
+        const uint64_t r = sf + k;
+        for (int a = 0; a < 3; ++a) {
+            spos[3 * r + a] = sh.prm[k][a];
+            sscale[3 * r + a] = __expf(sh.prm[k][3 + a]);
+            sdc[(uint64_t)sdc_stride * r + a] = sh.prm[k][11 + a];
+        }
+        const float *qr = &sh.prm[k][6];
+        const float qn = sqrtf(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+        for (int a = 0; a < 4; ++a) srot[4 * r + a] = qr[a] / qn;
+        sopacity[r] = ls_sigmoid(sh.prm[k][10]);
+    }
+}
+
+void launch_local_splat(hipStream_t st, const uint32_t *ofirst, const uint32_t *ocount, const uint32_t *sfirst,
+                        const uint32_t *scount, const float *sphere, const float *opos, const float *oscale,
+                        const float *orot, const float *oopacity, const float *odc, uint32_t odc_stride, float *spos,
+                        float *sscale, float *srot, float *sopacity, float *sdc, uint32_t sdc_stride,
+                        const float *dirs, uint32_t iters, uint32_t n_groups, float *losses, float *grad_first,
+                        uint32_t *err)
+{
+    if (n_groups == 0) return;
+    hipLaunchKernelGGL(local_splat_kernel, dim3(n_groups), dim3(kLsThreads), 0, st, ofirst, ocount, sfirst, scount,
+                       sphere, opos, oscale, orot, oopacity, odc, odc_stride, spos, sscale, srot, sopacity, sdc,
+                       sdc_stride, dirs, iters, n_groups, losses, grad_first, err);
+}
+
 }  // namespace v3dg

@@ -2399,4 +2399,58 @@ int v3dg_bundle_copy(const v3dg_bundle *b, float *pos, float *scale, float *rot,
 
 void v3dg_bundle_free(v3dg_bundle *b) { delete b; }
 
+int v3dg_local_splat(uint32_t n_groups, const uint32_t *orig_first, const uint32_t *orig_count,
+                     const uint32_t *fit_first, const uint32_t *fit_count, const float *sphere, const float *orig_pos,
+                     const float *orig_scale, const float *orig_rot, const float *orig_opacity, const float *orig_dc,
+                     uint32_t n_orig, float *fit_pos, float *fit_scale, float *fit_rot, float *fit_opacity,
+                     float *fit_dc, uint32_t n_fit, const float *view_dirs, uint32_t iters, float *losses,
+                     float *grad_first)
+{
+    g_err.clear();
+    if (n_groups == 0) return V3DG_OK;
+    if (!orig_first || !orig_count || !fit_first || !fit_count || !sphere || !orig_pos || !orig_scale || !orig_rot ||
+        !orig_opacity || !orig_dc || !fit_pos || !fit_scale || !fit_rot || !fit_opacity || !fit_dc ||
+        (iters && !view_dirs))
+        return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
+    for (uint32_t g = 0; g < n_groups; ++g) {
+        if (orig_count[g] > 128 || fit_count[g] > 64)
+            return fail(V3DG_ERR_INVALID_ARG, "group %u: at most 128 original and 64 fitted Gaussians", g);
+        if ((uint64_t)orig_first[g] + orig_count[g] > n_orig || (uint64_t)fit_first[g] + fit_count[g] > n_fit)
+            return fail(V3DG_ERR_INVALID_ARG, "group %u: rows out of range", g);
+        if (!(sphere[4ull * g + 3] > 0.0f)) return fail(V3DG_ERR_INVALID_ARG, "group %u: radius must be > 0", g);
+    }
+    DevBuf of, oc, ff, fc, sp, op, os, orr, oo, od, fp, fs, fr, fo, fd, dr, lo, gf, err;
+    int rc;
+    if ((rc = upload(of, orig_first, n_groups)) || (rc = upload(oc, orig_count, n_groups)) ||
+        (rc = upload(ff, fit_first, n_groups)) || (rc = upload(fc, fit_count, n_groups)) ||
+        (rc = upload(sp, sphere, 4ull * n_groups)) || (rc = upload(op, orig_pos, 3ull * n_orig)) ||
+        (rc = upload(os, orig_scale, 3ull * n_orig)) || (rc = upload(orr, orig_rot, 4ull * n_orig)) ||
+        (rc = upload(oo, orig_opacity, (uint64_t)n_orig)) || (rc = upload(od, orig_dc, 3ull * n_orig)) ||
+        (rc = upload(fp, fit_pos, 3ull * n_fit)) || (rc = upload(fs, fit_scale, 3ull * n_fit)) ||
+        (rc = upload(fr, fit_rot, 4ull * n_fit)) || (rc = upload(fo, fit_opacity, (uint64_t)n_fit)) ||
+        (rc = upload(fd, fit_dc, 3ull * n_fit)) || (rc = upload(dr, view_dirs, 3ull * iters)) ||
+        (rc = dev_make<float>(lo, (uint64_t)n_groups * iters)) || (rc = dev_make<float>(gf, 14ull * n_fit)) ||
+        (rc = dev_make<uint32_t>(err, 1)))
+        return rc;
+    HIP_TRY(hipMemset(err.p, 0, sizeof(uint32_t)));
+    launch_local_splat(nullptr, of.as<uint32_t>(), oc.as<uint32_t>(), ff.as<uint32_t>(), fc.as<uint32_t>(),
+                       sp.as<float>(), op.as<float>(), os.as<float>(), orr.as<float>(), oo.as<float>(),
+                       od.as<float>(), 3, fp.as<float>(), fs.as<float>(), fr.as<float>(), fo.as<float>(),
+                       fd.as<float>(), 3, dr.as<float>(), iters, n_groups, lo.as<float>(), gf.as<float>(),
+                       err.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+    uint32_t e = 0;
+    HIP_TRY(hipMemcpy(&e, err.p, sizeof(e), hipMemcpyDeviceToHost));
+    if (e) return fail(V3DG_ERR_DEVICE, "local splatting: group bounds exceeded");
+    HIP_TRY(hipMemcpy(fit_pos, fp.p, 3ull * n_fit * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(fit_scale, fs.p, 3ull * n_fit * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(fit_rot, fr.p, 4ull * n_fit * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(fit_opacity, fo.p, (uint64_t)n_fit * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(fit_dc, fd.p, 3ull * n_fit * 4, hipMemcpyDeviceToHost));
+    if (losses && iters) HIP_TRY(hipMemcpy(losses, lo.p, (uint64_t)n_groups * iters * 4, hipMemcpyDeviceToHost));
+    if (grad_first && iters) HIP_TRY(hipMemcpy(grad_first, gf.p, 14ull * n_fit * 4, hipMemcpyDeviceToHost));
+    return V3DG_OK;
+}
+
 }  // extern "C"

@@ -308,6 +308,17 @@ void launch_group(hipStream_t st, const float *pos, const float *scale, const fl
                   const uint32_t *rows, const uint32_t *first, const uint32_t *count, const float *msph,
                   const uint32_t *perm, const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap,
                   uint32_t *out_rows, uint32_t *out_count, float *sph, uint32_t *err);
+// Local splatting of n_groups cluster groups: group g fits the fitted rows
+// sfirst[g] .. + scount[g] (<= 64; position, scale, rotation, opacity, dc at
+// sdc + stride * row) to the original rows ofirst[g] .. + ocount[g] (<= 128)
+// over views dirs[0 .. iters) around sphere[g]; losses (n_groups x iters)
+// and grad_first (14 per fitted row) are optional.
+void launch_local_splat(hipStream_t st, const uint32_t *ofirst, const uint32_t *ocount, const uint32_t *sfirst,
+                        const uint32_t *scount, const float *sphere, const float *opos, const float *oscale,
+                        const float *orot, const float *oopacity, const float *odc, uint32_t odc_stride, float *spos,
+                        float *sscale, float *srot, float *sopacity, float *sdc, uint32_t sdc_stride,
+                        const float *dirs, uint32_t iters, uint32_t n_groups, float *losses, float *grad_first,
+                        uint32_t *err);
 // bundle row i = input Gaussian src[i] with its scales grown gen[i] times
 void launch_bundle_rows(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
                         const float *sh, uint32_t sh_floats, const uint32_t *src, const uint8_t *gen, uint32_t n_rows,

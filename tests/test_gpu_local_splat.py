@@ -1,0 +1,113 @@
+"""Local splatting on the GPU (v3dg_local_splat) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import local_splat as ls
+import paper_2505_06523_amd as v
+from tests.test_gpu_parity import _say
+from tests.test_oracle_local_splat import _group
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [("pos", 0, 3), ("log_scale", 3, 6), ("quat", 6, 10), ("logit", 10, 11), ("dc", 11, 14)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    v.lib()
+    return _t
+
+
+def _rows(g):
+    return dict(pos=g["pos"], scale=g["scale"], rot=g["rot"], opacity=g["opacity"], dc=g["sh"][:, 0, :])
+
+
+def _halve(g):
+    score = ((g["scale"][:, 0] * g["scale"][:, 1]) * g["scale"][:, 2]) * g["opacity"]
+    keep = np.sort(np.argsort(-score, kind="stable")[:(len(score) + 1) // 2])
+    s = {k: x[keep].copy() for k, x in g.items()}
+    s["scale"] = s["scale"] * np.float32(2 ** (1 / 6))
+    return s
+
+
+def _dirs(n, seed):
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+
+
+def _sphere(g):
+    c = g["pos"].astype(np.float64).mean(0)
+    r = float(np.sqrt(((g["pos"] - c) ** 2).sum(1)).max()) * 1.05 + 0.05
+    return c.astype(np.float32), np.float32(r)
+
+
+@pytest.mark.parametrize("m,seed", [(8, 1), (60, 2), (128, 3)])
+def test_first_view_gradients_and_loss_match_oracle(torch, m, seed):
+    orig = _group(m, seed)
+    fit = _halve(orig)
+    c, r = _sphere(orig)
+    dirs = _dirs(30, seed)
+    out, lg, gg = v.local_splat([(0, m, 0, len(fit["opacity"]), (c[0], c[1], c[2], r))], _rows(orig), _rows(fit),
+                                dirs, 30)
+    ref, lr_, gr = ls.local_splat(orig, fit, c.astype(np.float64), float(r), dirs.astype(np.float64), 30)
+    assert abs(lg[0, 0] - lr_[0]) <= 1e-4 * lr_[0] + 1e-7, (lg[0, 0], lr_[0])
+    for name, a, b in BLOCKS:
+        x, y = gg[:, a:b].astype(np.float64), gr[name].reshape(len(gg), -1)
+        ny = np.linalg.norm(y)
+        if ny == 0:
+            assert np.linalg.norm(x) == 0
+            continue
+        rel = np.linalg.norm(x - y) / ny
+        cos = float((x * y).sum() / (np.linalg.norm(x) * ny))
+        _say("m=%d %-9s grad rel err %.2e cos %.6f" % (m, name, rel, cos))
+        assert rel < 2e-2 and cos > 0.999, (name, rel, cos)
+    # the fit follows the oracle's
+    np.testing.assert_allclose(lg[0].astype(np.float64), lr_, rtol=5e-2, atol=1e-5)
+
+
+def test_fitting_lowers_the_loss(torch):
+    """Over 200 views the loss on the views goes down, as in the oracle."""
+    orig = _group(96, 12)
+    fit = _halve(orig)
+    c, r = _sphere(orig)
+    dirs = _dirs(200, 7)
+    _, lg, _ = v.local_splat([(0, 96, 0, len(fit["opacity"]), (c[0], c[1], c[2], r))], _rows(orig), _rows(fit),
+                             dirs, 200)
+    lg = lg[0].astype(np.float64)
+    _say("loss first 20 views %.5f, last 20 %.5f" % (lg[:20].mean(), lg[-20:].mean()))
+    assert lg[-20:].mean() < 0.9 * lg[:20].mean()
+
+
+def test_a_set_fitted_to_itself_stays(torch):
+    g = _group(40, 9)
+    c, r = _sphere(g)
+    out, lg, gg = v.local_splat([(0, 40, 0, 40, (c[0], c[1], c[2], r))], _rows(g), _rows(g), _dirs(5, 1), 5)
+    assert lg.max() == 0.0 and np.abs(gg).max() == 0.0
+    np.testing.assert_array_equal(out["pos"], g["pos"])
+    np.testing.assert_allclose(out["scale"], g["scale"], rtol=1e-6)
+    np.testing.assert_allclose(out["opacity"], g["opacity"], rtol=1e-5)
+
+
+def test_batched_groups_equal_single_groups(torch):
+    gs = [_group(m, 20 + m) for m in (128, 17, 64, 3)]
+    fits = [_halve(g) for g in gs]
+    orig = {k: np.concatenate([_rows(g)[k] for g in gs]) for k in ("pos", "scale", "rot", "opacity", "dc")}
+    fit = {k: np.concatenate([_rows(f)[k] for f in fits]) for k in ("pos", "scale", "rot", "opacity", "dc")}
+    groups, o0, f0 = [], 0, 0
+    for g, f in zip(gs, fits):
+        c, r = _sphere(g)
+        groups.append((o0, len(g["opacity"]), f0, len(f["opacity"]), (c[0], c[1], c[2], r)))
+        o0 += len(g["opacity"])
+        f0 += len(f["opacity"])
+    dirs = _dirs(12, 4)
+    out, lb, gb = v.local_splat(groups, orig, fit, dirs, 12)
+    for i, (g, f) in enumerate(zip(gs, fits)):
+        c, r = _sphere(g)
+        o1, l1, g1 = v.local_splat([(0, len(g["opacity"]), 0, len(f["opacity"]), (c[0], c[1], c[2], r))], _rows(g),
+                                   _rows(f), dirs, 12)
+        a, n = groups[i][2], groups[i][3]
+        for k in o1:
+            np.testing.assert_array_equal(out[k][a:a + n], o1[k])
+        np.testing.assert_array_equal(lb[i], l1[0])
