@@ -326,7 +326,16 @@ void v3dg_server_free(v3dg_server *srv);
  * Leaves have radius 0 (centre: their mean); the root's parent radius is +inf.
  * Split of a set larger than the limit: the axis of the largest FP32 extent
  * (the first on ties), a stable order along it, ceil(s/2) items to the left.
- * The local-splatting refinement of simplified Gaussians is not performed.
+ * Every coarser layer is made from the current rows of the layer below it:
+ * means, spheres and halving scores use them as they stand.
+ *
+ * With fit_iters > 0, every group's kept Gaussians are refined right after
+ * the halving by local splatting (Sec. 3.2, as v3dg_local_splat: the group's
+ * Gaussians are the originals, its sphere places the pseudo-views, view i
+ * looks along view_dirs[3i .. 3i+2], the same directions for every group);
+ * with fit_iters = 0 the rows of a layer are plain copies of rows below
+ * (structural build).  view_dirs: host, 3 x fit_iters finite non-zero floats
+ * (normalised here), may be NULL when fit_iters = 0; fit_iters <= 2^20.
  *
  * Inputs are host arrays: pos, scale (n x 3), rot (n x 4), opacity (n), sh
  * (n x (sh_degree+1)^2 x 3), all FP32; 1 <= n < 2^31, sh_degree <= 3,
@@ -336,7 +345,8 @@ void v3dg_server_free(v3dg_server *srv);
  * Errors: V3DG_ERR_INVALID_ARG, V3DG_ERR_OOM, V3DG_ERR_HIP, V3DG_ERR_DEVICE. */
 typedef struct v3dg_bundle v3dg_bundle;
 int v3dg_build_bundle(const float *pos, const float *scale, const float *rot, const float *opacity, const float *sh,
-                      uint32_t n, uint32_t sh_degree, uint32_t cluster_size, v3dg_bundle **out);
+                      uint32_t n, uint32_t sh_degree, uint32_t cluster_size, uint32_t fit_iters,
+                      const float *view_dirs, v3dg_bundle **out);
 
 /* Sizes of a built bundle: clusters, rows, leaf clusters (ids 0 .. n_leaf-1)
  * and layers. */
@@ -345,11 +355,18 @@ int v3dg_bundle_sizes(const v3dg_bundle *b, uint32_t *n_clusters, uint32_t *n_ro
 
 /* Copy a built bundle into caller arrays sized by v3dg_bundle_sizes (any may
  * be NULL): rows as in v3dg_hierarchy_desc, clusters likewise plus level[k];
- * src[i] is the input Gaussian of row i and gen[i] the simplifications it
- * went through (its scales are the input's grown gen[i] times). */
+ * src[i] is the input Gaussian row i descends from and gen[i] the
+ * simplifications it went through (in a structural build its scales are the
+ * input's grown gen[i] times, the rest of it a copy). */
 int v3dg_bundle_copy(const v3dg_bundle *b, float *pos, float *scale, float *rot, float *opacity, float *sh,
                      float *self_sphere, float *parent_sphere, uint32_t *first_row, uint8_t *count, uint8_t *level,
                      int32_t *parent, int32_t *first_child, uint8_t *n_children, uint32_t *src, uint8_t *gen);
+
+/* Mean local-splatting loss of a built bundle: loss[(l - 1) * fit_iters + i]
+ * is the mean over the groups that made layer l (1 .. n_layers - 1) of their
+ * loss at view i, before its step; (n_layers - 1) x fit_iters floats, none
+ * when fit_iters = 0. */
+int v3dg_bundle_fit_loss(const v3dg_bundle *b, float *loss);
 
 void v3dg_bundle_free(v3dg_bundle *b);
 

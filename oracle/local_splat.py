@@ -132,8 +132,9 @@ def loss_of(p, target, Rv, eye):
 def local_splat(orig, simp, center, radius, dirs, iters):
     """Fit the simplified Gaussians (dict of numpy rows: pos, scale, rot,
     opacity, sh) to the originals over views dirs[0 .. iters-1].  Returns the
-    fitted rows, the loss of every iteration (before its step) and the
-    gradients of the first iteration."""
+    fitted rows (quaternions as unit quaternions, which rotate as the fitted
+    ones do), the loss of every iteration (before its step) and the gradients
+    of the first iteration."""
     po = params_from(orig["pos"], orig["scale"], orig["rot"], orig["opacity"], orig["sh"])
     ps = params_from(simp["pos"], simp["scale"], simp["rot"], simp["opacity"], simp["sh"])
     for t in ps.values():
@@ -165,6 +166,8 @@ def local_splat(orig, simp, center, radius, dirs, iters):
     with torch.no_grad():
         sh = np.asarray(simp["sh"], np.float64).reshape(len(simp["opacity"]), -1, 3).copy()
         sh[:, 0, :] = ps["dc"].numpy()
-        out = dict(pos=ps["pos"].numpy().copy(), scale=np.exp(ps["log_scale"].numpy()), rot=ps["quat"].numpy().copy(),
+        q = ps["quat"].numpy()
+        out = dict(pos=ps["pos"].numpy().copy(), scale=np.exp(ps["log_scale"].numpy()),
+                   rot=q / np.linalg.norm(q, axis=1, keepdims=True),
                    opacity=1.0 / (1.0 + np.exp(-ps["logit"].numpy())), sh=sh)
     return out, losses, g_first

@@ -1,4 +1,4 @@
-"""CPU oracle of the offline build (paper Sec. 3.1-3.2, Algorithm 1), structural part.
+"""CPU oracle of the offline build (paper Sec. 3.1-3.2, Algorithm 1).
 
 TEST INFRASTRUCTURE ONLY: only ``tests/`` and the benchmark's baseline leg may
 import it.  It shares no code with the HIP library.
@@ -11,8 +11,12 @@ Gaussians (those with the larger product of scale and opacity, scales grown by
 2^(1/6)) and the simplified Gaussians form the clusters of the next layer.  A
 group's bounding sphere (centre: mean Gaussian position; radius: farthest
 Gaussian) becomes the own sphere of the simplified cluster and the parent
-sphere of the group's clusters.  The local-splatting refinement of the
-simplified Gaussians is not part of this oracle.
+sphere of the group's clusters.  Optionally (iters > 0) the simplified
+Gaussians of every group are then refined by local splatting (Sec. 3.2, the
+local-splatting oracle) against the group's Gaussians, with the group sphere
+placing the pseudo-views and the same view directions for every group.
+Every layer is made from the current rows of the layer below (positions for
+means and spheres, scales and opacities for the scores).
 
 Where the paper leaves a choice open, this file fixes it (the readings are
 listed with the design notes):
@@ -82,29 +86,35 @@ def seq_mean64(p: np.ndarray) -> np.ndarray:
     return np.cumsum(p.astype(np.float64), axis=0)[-1] / float(len(p))
 
 
-def scales_of(scale: np.ndarray, src: np.ndarray, j: np.ndarray) -> np.ndarray:
-    """Current FP32 scales: the input scales multiplied j times by 2^(1/6)."""
-    s = scale[src].astype(np.float32).copy()
-    for t in range(1, int(j.max(initial=0)) + 1):
-        sel = j >= t
-        s[sel] = s[sel] * SCALE_GROWTH
-    return s
+FIELDS = ("pos", "scale", "rot", "opacity", "sh", "src", "gen")
 
 
-def simplify(scale, opacity, src, j):
-    """Keep the ceil(m/2) Gaussians with the largest scale product x opacity."""
-    m = len(src)
-    s = scales_of(scale, src, j)
-    score = ((s[:, 0] * s[:, 1]) * s[:, 2]) * opacity[src].astype(np.float32)
+def take(rows: dict, idx) -> dict:
+    return {k: v[idx].copy() for k, v in rows.items()}
+
+
+def concat(parts: list) -> dict:
+    return {k: np.concatenate([p[k] for p in parts]) for k in FIELDS}
+
+
+def simplify(rows: dict) -> dict:
+    """Keep the ceil(m/2) Gaussians with the largest scale product x opacity
+    (FP32, ties: the earlier one), in group order, scales grown by 2^(1/6)."""
+    m = len(rows["src"])
+    s = rows["scale"]
+    score = ((s[:, 0] * s[:, 1]) * s[:, 2]) * rows["opacity"]
     order = np.argsort(-score.astype(np.float64), kind="stable")  # descending, ties: earlier first
-    k = (m + 1) // 2
-    keep = np.sort(order[:k])
-    return src[keep], j[keep] + 1
+    keep = np.sort(order[:(m + 1) // 2])
+    out = take(rows, keep)
+    out["scale"] = out["scale"] * SCALE_GROWTH
+    out["gen"] = out["gen"] + 1
+    return out
 
 
-def group_sphere(pos, src, child_sph):
-    """Centre, radius of a group of Gaussians; grown to hold the child spheres."""
-    p = pos[src].astype(np.float32)
+def group_sphere(p, child_sph):
+    """Centre, radius of a group of Gaussians at positions p (FP32); grown
+    to hold the child spheres."""
+    p = np.asarray(p, np.float32)
     c32 = seq_mean64(p).astype(np.float32)
     c = c32.astype(np.float64)
     r = 0.0
@@ -119,18 +129,33 @@ def group_sphere(pos, src, child_sph):
     return np.array([c32[0], c32[1], c32[2], np.float32(r)], dtype=np.float32)
 
 
-def build_bundle(pos, scale, rot, opacity, sh, n: int = 64) -> dict:
-    """Algorithm 1 (structural part) on N Gaussians; returns the bundle arrays."""
+def fit(orig: dict, simp: dict, sph: np.ndarray, dirs, iters: int) -> dict:
+    """Local splatting of a group's simplified Gaussians; FP32 rows back."""
+    from oracle import local_splat as ls
+    out, _, _ = ls.local_splat(orig, simp, sph[:3].astype(np.float64), float(sph[3]),
+                               np.asarray(dirs, np.float64), iters)
+    res = dict(simp)
+    for k in ("pos", "scale", "rot", "opacity", "sh"):
+        res[k] = np.asarray(out[k], np.float64).astype(np.float32).reshape(simp[k].shape)
+    return res
+
+
+def build_bundle(pos, scale, rot, opacity, sh, n: int = 64, iters: int = 0, dirs=None) -> dict:
+    """Algorithm 1 on N Gaussians (local splatting with iters views along
+    dirs when iters > 0); returns the bundle arrays."""
     pos = np.ascontiguousarray(pos, np.float32)
     N = pos.shape[0]
+    inp = dict(pos=pos, scale=np.asarray(scale, np.float32), rot=np.asarray(rot, np.float32),
+               opacity=np.asarray(opacity, np.float32), sh=np.asarray(sh, np.float32).reshape(N, -1, 3),
+               src=np.arange(N, dtype=np.int64), gen=np.zeros(N, np.int64))
     # layer C_0
     sets = split(pos, np.arange(N), n)
-    cur = [(s, np.zeros(len(s), np.int64)) for s in sets]
-    cur_sph = [np.concatenate([seq_mean64(pos[s]).astype(np.float32), [np.float32(0)]]) for s, _ in cur]
+    cur = [take(inp, s) for s in sets]
+    cur_sph = [np.concatenate([seq_mean64(c["pos"]).astype(np.float32), [np.float32(0)]]) for c in cur]
     cur_children = [None] * len(cur)
     layers = []
     while len(cur) >= 2:
-        cent = np.array([seq_mean64(pos[s]).astype(np.float32) for s, _ in cur], dtype=np.float32)
+        cent = np.array([seq_mean64(c["pos"]).astype(np.float32) for c in cur], dtype=np.float32)
         groups = split(cent, np.arange(len(cur)), 2)
         order = np.concatenate(groups)
         cur = [cur[k] for k in order]
@@ -142,11 +167,13 @@ def build_bundle(pos, scale, rot, opacity, sh, n: int = 64) -> dict:
         for g in groups:
             members = list(range(first, first + len(g)))
             first += len(g)
-            src = np.concatenate([cur[m][0] for m in members])
-            jj = np.concatenate([cur[m][1] for m in members])
-            ks, kj = simplify(scale, opacity, src, jj)
-            nxt.append((ks, kj))
-            nxt_sph.append(group_sphere(pos, src, [cur_sph[m] for m in members]))
+            rows = concat([cur[m] for m in members])
+            sph = group_sphere(rows["pos"], [cur_sph[m] for m in members])
+            kept = simplify(rows)
+            if iters:
+                kept = fit(rows, kept, sph, dirs, iters)
+            nxt.append(kept)
+            nxt_sph.append(sph)
             nxt_children.append((members[0], len(members)))
         cur, cur_sph, cur_children = nxt, nxt_sph, nxt_children
     layers.append((cur, cur_sph, cur_children))
@@ -161,13 +188,13 @@ def build_bundle(pos, scale, rot, opacity, sh, n: int = 64) -> dict:
     first_child = np.full(C, -1, np.int32)
     n_children = np.zeros(C, np.uint8)
     self_sphere = np.zeros((C, 4), np.float32)
-    srcs, js = [], []
+    parts = []
     row = 0
     for li, (cl, sph, ch) in enumerate(layers):
-        for k, (s, j) in enumerate(cl):
+        for k, rows in enumerate(cl):
             cid = int(base[li]) + k
             first_row[cid] = row
-            count[cid] = len(s)
+            count[cid] = len(rows["src"])
             level[cid] = li
             self_sphere[cid] = sph[k]
             if ch[k] is not None:
@@ -175,11 +202,9 @@ def build_bundle(pos, scale, rot, opacity, sh, n: int = 64) -> dict:
                 n_children[cid] = ch[k][1]
                 for m in range(ch[k][1]):
                     parent[int(base[li - 1]) + ch[k][0] + m] = cid
-            srcs.append(s)
-            js.append(j)
-            row += len(s)
-    src = np.concatenate(srcs)
-    j = np.concatenate(js)
+            parts.append(rows)
+            row += len(rows["src"])
+    allr = concat(parts)
     parent_sphere = np.zeros((C, 4), np.float32)
     for cid in range(C):
         if parent[cid] < 0:
@@ -187,8 +212,8 @@ def build_bundle(pos, scale, rot, opacity, sh, n: int = 64) -> dict:
                                           np.float32)
         else:
             parent_sphere[cid] = self_sphere[parent[cid]]
-    return dict(pos=pos[src].copy(), scale=scales_of(scale, src, j), rot=np.asarray(rot, np.float32)[src].copy(),
-                opacity=np.asarray(opacity, np.float32)[src].copy(), sh=np.asarray(sh, np.float32)[src].copy(),
+    sh_out = allr["sh"].reshape((len(allr["src"]),) + np.asarray(sh).shape[1:])
+    return dict(pos=allr["pos"], scale=allr["scale"], rot=allr["rot"], opacity=allr["opacity"], sh=sh_out,
                 first_row=first_row, count=count, level=level, parent=parent, first_child=first_child,
                 n_children=n_children, self_sphere=self_sphere, parent_sphere=parent_sphere,
-                n_leaf_clusters=int(base[1]), src=src.astype(np.int64), gen=j.astype(np.int64))
+                n_leaf_clusters=int(base[1]), src=allr["src"].astype(np.int64), gen=allr["gen"].astype(np.int64))

@@ -98,7 +98,7 @@ EXPORTS = [
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
     "v3dg_last_error",
     "v3dg_server_create", "v3dg_server_submit", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
-    "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_free", "v3dg_local_splat",
+    "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_fit_loss", "v3dg_bundle_free", "v3dg_local_splat",
 ]
 
 _lib = None
@@ -139,7 +139,8 @@ def lib():
         "v3dg_server_poll": ([P, I, P, U32, P], I),
         "v3dg_server_get_stats": ([P, P], I),
         "v3dg_server_free": ([P], None),
-        "v3dg_build_bundle": ([P, P, P, P, P, U32, U32, U32, P], I),
+        "v3dg_build_bundle": ([P, P, P, P, P, U32, U32, U32, U32, P, P], I),
+        "v3dg_bundle_fit_loss": ([P, P], I),
         "v3dg_bundle_sizes": ([P, P, P, P, P], I),
         "v3dg_bundle_copy": ([P] + [P] * 15, I),
         "v3dg_bundle_free": ([P], None),
@@ -483,18 +484,26 @@ class Scene:
             pass
 
 
-def build_bundle(pos, scale, rot, opacity, sh, cluster_size: int = 64) -> dict:
+def build_bundle(pos, scale, rot, opacity, sh, cluster_size: int = 64, fit_iters: int = 0, view_dirs=None) -> dict:
     """Offline build on the GPU (v3dg_build_bundle) of n Gaussians given as
-    host arrays; returns the bundle arrays (rows, clusters, src and gen)."""
+    host arrays, with fit_iters local-splatting views along view_dirs
+    (fit_iters x 3) per group; returns the bundle arrays (rows, clusters, src
+    and gen) and fit_loss ((n_layers - 1) x fit_iters)."""
     f32 = lambda a: np.ascontiguousarray(a, np.float32)
     pos, scale, rot, opacity, sh = f32(pos), f32(scale), f32(rot), f32(opacity), f32(sh)
     n = pos.shape[0]
     k = sh.reshape(n, -1).shape[1] // 3
     sh_degree = int(round(math.sqrt(k))) - 1
     ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    dirs = None
+    if fit_iters:
+        dirs = f32(view_dirs).reshape(-1, 3)
+        if len(dirs) < fit_iters:
+            raise ValueError("view_dirs must hold fit_iters directions")
     h = C.c_void_p()
     _check(lib().v3dg_build_bundle(ptr(pos), ptr(scale), ptr(rot), ptr(opacity), ptr(sh), n, sh_degree,
-                                   int(cluster_size), C.byref(h)))
+                                   int(cluster_size), int(fit_iters), None if dirs is None else ptr(dirs),
+                                   C.byref(h)))
     try:
         nc, nr, nl, ny = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
         _check(lib().v3dg_bundle_sizes(h, C.byref(nc), C.byref(nr), C.byref(nl), C.byref(ny)))
@@ -511,6 +520,8 @@ def build_bundle(pos, scale, rot, opacity, sh, cluster_size: int = 64) -> dict:
         _check(lib().v3dg_bundle_copy(h, *[ptr(out[x]) for x in names]))
         out["n_leaf_clusters"] = nl.value
         out["n_layers"] = ny.value
+        out["fit_loss"] = np.zeros((max(ny.value - 1, 0), int(fit_iters)), np.float32)
+        _check(lib().v3dg_bundle_fit_loss(h, ptr(out["fit_loss"])))
         return out
     finally:
         lib().v3dg_bundle_free(h)

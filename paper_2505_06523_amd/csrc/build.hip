@@ -183,15 +183,16 @@ __device__ __forceinline__ double dist64(const float *p, double cx, double cy, d
 // One workgroup per cluster group (its member clusters are layer positions
 // gfirst[g] .. gfirst[g] + gsize[g] - 1 of the permuted layer: perm[pos] is
 // the cluster's index before the grouping).  The group's Gaussians G_o are
-// the members' rows in member order; the ceil(m/2) with the largest
-// ((sx sy) sz) o (current scales: the input's grown gen times; ties to the
-// earlier one) are kept in G_o order as the new cluster g's rows at out_rows
-// + g * cap.  sph[g] = the group sphere grown over the members' spheres.
+// the members' rows in member order (ids into the layer's row store, written
+// to go_rows[g * kGroupMax ..], their number to go_count[g]); the ceil(m/2)
+// with the largest ((sx sy) sz) o (the rows' current values; ties to the
+// earlier one) are kept in G_o order, their ids at kept + g * cap.  sph[g] =
+// the group sphere over G_o, grown over the members' spheres.
 constexpr int kGroupMax = 128;
 
 __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restrict__ pos,
                                                           const float *__restrict__ scale,
-                                                          const float *__restrict__ opacity, uint32_t gen,
+                                                          const float *__restrict__ opacity,
                                                           const uint32_t *__restrict__ rows,
                                                           const uint32_t *__restrict__ first,
                                                           const uint32_t *__restrict__ count,
@@ -199,9 +200,10 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
                                                           const uint32_t *__restrict__ perm,
                                                           const uint32_t *__restrict__ gfirst,
                                                           const uint32_t *__restrict__ gsize, uint32_t n_groups,
-                                                          uint32_t cap, uint32_t *__restrict__ out_rows,
+                                                          uint32_t cap, uint32_t *__restrict__ kept,
                                                           uint32_t *__restrict__ out_count, float *__restrict__ sph,
-                                                          uint32_t *err)
+                                                          uint32_t *__restrict__ go_rows,
+                                                          uint32_t *__restrict__ go_count, uint32_t *err)
 {
     __shared__ float s_score[kGroupMax];
     __shared__ uint32_t s_src[kGroupMax];
@@ -229,16 +231,12 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
         const uint32_t mi = (gsize[g] > 1 && (uint32_t)t >= s_base[1]) ? 1u : 0u;
         const uint32_t k = perm[gfirst[g] + mi];
         const uint32_t src = rows[first[k] + ((uint32_t)t - s_base[mi])];
-        float sx = scale[3ull * src], sy = scale[3ull * src + 1], sz = scale[3ull * src + 2];
-        const float grow = (float)kScaleGrowth;
-        for (uint32_t j = 0; j < gen; ++j) {
-            sx = __fmul_rn(sx, grow);
-            sy = __fmul_rn(sy, grow);
-            sz = __fmul_rn(sz, grow);
-        }
+        const float sx = scale[3ull * src], sy = scale[3ull * src + 1], sz = scale[3ull * src + 2];
         s_score[t] = __fmul_rn(__fmul_rn(__fmul_rn(sx, sy), sz), opacity[src]);
         s_src[t] = src;
+        go_rows[(uint64_t)g * kGroupMax + t] = src;
     }
+    if (t == 0) go_count[g] = m;
     __syncthreads();
     // rank among the group: larger scores first, the earlier Gaussian on ties
     bool keep = false;
@@ -257,7 +255,7 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
         const uint64_t mine = t < kWave ? b0 : b1;
         const uint32_t lane = t & (kWave - 1);
         const uint32_t at = (t < kWave ? 0u : s_cnt[0]) + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
-        if (keep) out_rows[(uint64_t)g * cap + at] = s_src[t];
+        if (keep) kept[(uint64_t)g * cap + at] = s_src[t];
         if (t == 0) out_count[g] = (m + 1) / 2;
     }
     // sphere: FP64 mean in G_o order, then the farthest Gaussian
@@ -286,46 +284,83 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
     }
 }
 
-void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, uint32_t gen,
-                  const uint32_t *rows, const uint32_t *first, const uint32_t *count, const float *msph,
-                  const uint32_t *perm, const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap,
-                  uint32_t *out_rows, uint32_t *out_count, float *sph, uint32_t *err)
+void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, const uint32_t *rows,
+                  const uint32_t *first, const uint32_t *count, const float *msph, const uint32_t *perm,
+                  const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap, uint32_t *kept,
+                  uint32_t *out_count, float *sph, uint32_t *go_rows, uint32_t *go_count, uint32_t *err)
 {
     if (n_groups == 0) return;
-    hipLaunchKernelGGL(group_kernel, dim3(n_groups), dim3(kGroupMax), 0, st, pos, scale, opacity, gen, rows, first,
-                       count, msph, perm, gfirst, gsize, n_groups, cap, out_rows, out_count, sph, err);
+    hipLaunchKernelGGL(group_kernel, dim3(n_groups), dim3(kGroupMax), 0, st, pos, scale, opacity, rows, first, count,
+                       msph, perm, gfirst, gsize, n_groups, cap, kept, out_count, sph, go_rows, go_count, err);
 }
 
-// Bundle rows: row i is input Gaussian src[i] with its scales grown gen[i] times.
-__global__ void __launch_bounds__(kBuildThreads) bundle_rows_kernel(
+// The next layer's row store: slot g * cap + i (i < count[g]) is a copy of
+// the kept row kept[g * cap + i] of the current store with its scales grown
+// once by float(2^(1/6)); src carries the input Gaussian it descends from
+// (the current store's src, or the row id itself for the input); rows[slot]
+// = slot.
+__global__ void __launch_bounds__(kBuildThreads) spawn_kernel(
+    const float *__restrict__ pos, const float *__restrict__ scale, const float *__restrict__ rot,
+    const float *__restrict__ opacity, const float *__restrict__ sh, const uint32_t *__restrict__ src,
+    uint32_t sh_floats, const uint32_t *__restrict__ kept, const uint32_t *__restrict__ count, uint32_t n_groups,
+    uint32_t cap, float *__restrict__ npos, float *__restrict__ nscale, float *__restrict__ nrot,
+    float *__restrict__ nopacity, float *__restrict__ nsh, uint32_t *__restrict__ nsrc, uint32_t *__restrict__ nrows)
+{
+    const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= (uint64_t)n_groups * cap) return;
+    const uint32_t g = (uint32_t)(slot / cap), i = (uint32_t)(slot % cap);
+    if (i >= count[g]) return;
+    const uint64_t r = kept[slot];
+    const float grow = (float)kScaleGrowth;
+    for (int a = 0; a < 3; ++a) {
+        npos[3 * slot + a] = pos[3 * r + a];
+        nscale[3 * slot + a] = __fmul_rn(scale[3 * r + a], grow);
+    }
+    for (int a = 0; a < 4; ++a) nrot[4 * slot + a] = rot[4 * r + a];
+    nopacity[slot] = opacity[r];
+    for (uint32_t a = 0; a < sh_floats; ++a) nsh[(uint64_t)sh_floats * slot + a] = sh[(uint64_t)sh_floats * r + a];
+    nsrc[slot] = src ? src[r] : (uint32_t)r;
+    nrows[slot] = (uint32_t)slot;
+}
+
+void launch_spawn(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
+                  const float *sh, const uint32_t *src, uint32_t sh_floats, const uint32_t *kept,
+                  const uint32_t *count, uint32_t n_groups, uint32_t cap, float *npos, float *nscale, float *nrot,
+                  float *nopacity, float *nsh, uint32_t *nsrc, uint32_t *nrows)
+{
+    const uint64_t n = (uint64_t)n_groups * cap;
+    if (n == 0) return;
+    hipLaunchKernelGGL(spawn_kernel, dim3((uint32_t)((n + kBuildThreads - 1) / kBuildThreads)), dim3(kBuildThreads), 0,
+                       st, pos, scale, rot, opacity, sh, src, sh_floats, kept, count, n_groups, cap, npos, nscale,
+                       nrot, nopacity, nsh, nsrc, nrows);
+}
+
+// Bundle rows of one layer: output row i is row idx[i] of the layer's store.
+__global__ void __launch_bounds__(kBuildThreads) gather_rows_kernel(
     const float *__restrict__ pos, const float *__restrict__ scale, const float *__restrict__ rot,
     const float *__restrict__ opacity, const float *__restrict__ sh, uint32_t sh_floats,
-    const uint32_t *__restrict__ src, const uint8_t *__restrict__ gen, uint32_t n_rows, float *__restrict__ opos,
-    float *__restrict__ oscale, float *__restrict__ orot, float *__restrict__ oopacity, float *__restrict__ osh)
+    const uint32_t *__restrict__ idx, uint32_t n_rows, float *__restrict__ opos, float *__restrict__ oscale,
+    float *__restrict__ orot, float *__restrict__ oopacity, float *__restrict__ osh)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_rows) return;
-    const uint64_t s = src[i];
-    const float grow = (float)kScaleGrowth;
+    const uint64_t s = idx[i];
     for (int a = 0; a < 3; ++a) {
         opos[3ull * i + a] = pos[3 * s + a];
-        float v = scale[3 * s + a];
-        for (uint32_t j = 0; j < gen[i]; ++j) v = __fmul_rn(v, grow);
-        oscale[3ull * i + a] = v;
+        oscale[3ull * i + a] = scale[3 * s + a];
     }
     for (int a = 0; a < 4; ++a) orot[4ull * i + a] = rot[4 * s + a];
     oopacity[i] = opacity[s];
     for (uint32_t a = 0; a < sh_floats; ++a) osh[(uint64_t)sh_floats * i + a] = sh[sh_floats * s + a];
 }
 
-void launch_bundle_rows(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
-                        const float *sh, uint32_t sh_floats, const uint32_t *src, const uint8_t *gen, uint32_t n_rows,
-                        float *opos, float *oscale, float *orot, float *oopacity, float *osh)
+void launch_gather_rows(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
+                        const float *sh, uint32_t sh_floats, const uint32_t *idx, uint32_t n_rows, float *opos,
+                        float *oscale, float *orot, float *oopacity, float *osh)
 {
     if (n_rows == 0) return;
-    hipLaunchKernelGGL(bundle_rows_kernel, dim3((n_rows + kBuildThreads - 1) / kBuildThreads), dim3(kBuildThreads), 0,
-                       st, pos, scale, rot, opacity, sh, sh_floats, src, gen, n_rows, opos, oscale, orot, oopacity,
-                       osh);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((n_rows + kBuildThreads - 1) / kBuildThreads), dim3(kBuildThreads), 0,
+                       st, pos, scale, rot, opacity, sh, sh_floats, idx, n_rows, opos, oscale, orot, oopacity, osh);
 }
 
 
@@ -435,7 +470,7 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
     const uint32_t *__restrict__ ofirst, const uint32_t *__restrict__ ocount, const uint32_t *__restrict__ sfirst,
     const uint32_t *__restrict__ scount, const float *__restrict__ sphere, const float *__restrict__ opos,
     const float *__restrict__ oscale, const float *__restrict__ orot, const float *__restrict__ oopacity,
-    const float *__restrict__ odc, uint32_t odc_stride, float *spos, float *sscale, float *srot, float *sopacity,
+    const float *__restrict__ odc, uint32_t odc_stride, const uint32_t *__restrict__ orows, float *spos, float *sscale, float *srot, float *sopacity,
     float *sdc, uint32_t sdc_stride, const float *__restrict__ dirs, uint32_t iters, uint32_t n_groups,
     float *__restrict__ losses, float *__restrict__ grad_first, uint32_t *err)
 {
@@ -450,13 +485,14 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
     }
     if (ns == 0) return;
     if ((uint32_t)t < no) {
+        const uint64_t r = orows ? orows[of + t] : of + t;
         for (int a = 0; a < 3; ++a) {
-            sh.opos[t][a] = opos[3ull * (of + t) + a];
-            sh.oscl[t][a] = __expf(__logf(oscale[3ull * (of + t) + a]));
-            sh.orgb[t][a] = fmaxf(0.0f, kLsC0 * odc[(uint64_t)odc_stride * (of + t) + a] + 0.5f);
+            sh.opos[t][a] = opos[3 * r + a];
+            sh.oscl[t][a] = __expf(__logf(oscale[3 * r + a]));
+            sh.orgb[t][a] = fmaxf(0.0f, kLsC0 * odc[odc_stride * r + a] + 0.5f);
         }
-        for (int a = 0; a < 4; ++a) sh.oq[t][a] = orot[4ull * (of + t) + a];
-        sh.oop[t] = ls_sigmoid(ls_logit(oopacity[of + t]));
+        for (int a = 0; a < 4; ++a) sh.oq[t][a] = orot[4 * r + a];
+        sh.oop[t] = ls_sigmoid(ls_logit(oopacity[r]));
     }
     for (int i = t; i < (int)ns * kLsP; i += kLsThreads) {
         const int k = i / kLsP, j = i % kLsP;
@@ -791,14 +827,15 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
 
 void launch_local_splat(hipStream_t st, const uint32_t *ofirst, const uint32_t *ocount, const uint32_t *sfirst,
                         const uint32_t *scount, const float *sphere, const float *opos, const float *oscale,
-                        const float *orot, const float *oopacity, const float *odc, uint32_t odc_stride, float *spos,
+                        const float *orot, const float *oopacity, const float *odc, uint32_t odc_stride,
+                        const uint32_t *orows, float *spos,
                         float *sscale, float *srot, float *sopacity, float *sdc, uint32_t sdc_stride,
                         const float *dirs, uint32_t iters, uint32_t n_groups, float *losses, float *grad_first,
                         uint32_t *err)
 {
     if (n_groups == 0) return;
     hipLaunchKernelGGL(local_splat_kernel, dim3(n_groups), dim3(kLsThreads), 0, st, ofirst, ocount, sfirst, scount,
-                       sphere, opos, oscale, orot, oopacity, odc, odc_stride, spos, sscale, srot, sopacity, sdc,
+                       sphere, opos, oscale, orot, oopacity, odc, odc_stride, orows, spos, sscale, srot, sopacity, sdc,
                        sdc_stride, dirs, iters, n_groups, losses, grad_first, err);
 }
 

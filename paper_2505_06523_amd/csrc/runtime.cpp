@@ -2030,7 +2030,8 @@ void v3dg_server_free(v3dg_server *s)
 // Offline build (paper Sec. 3.1-3.2, Algorithm 1), structural part
 // ---------------------------------------------------------------------------
 struct v3dg_bundle {
-    uint32_t n_clusters = 0, n_rows = 0, n_leaf = 0, n_layers = 0, sh_floats = 0;
+    uint32_t n_clusters = 0, n_rows = 0, n_leaf = 0, n_layers = 0, sh_floats = 0, fit_iters = 0;
+    std::vector<float> fit_loss;  // per coarse layer and view: the mean loss over the layer's groups
     std::vector<float> pos, scale, rot, opacity, sh, self_sphere, parent_sphere;
     std::vector<uint32_t> first_row, src;
     std::vector<uint8_t> count, level, n_children, gen;
@@ -2160,26 +2161,45 @@ int device_split(hipStream_t st, const float *pts, DevBuf &items, DevBuf &spare,
 }
 
 // One layer of the bundle during the build: its clusters (in the order they
-// were made), their rows in a layer-local row store, own spheres, children
-// (positions in the previous layer's grouping order) and the grouping order.
+// were made), their rows (ids into the layer's row store), own spheres,
+// children (positions in the previous layer's grouping order) and the
+// grouping order.  Layers above C_0 own their row store (slot g * cap + i of
+// cluster g); C_0's store is the input.
 struct BuildLayer {
     DevBuf rows, first, count, sph;
+    DevBuf pos, scale, rot, op, sh, src;
     std::vector<uint32_t> h_first, h_count, h_rows, perm;
     std::vector<float> h_sph;
     std::vector<uint32_t> child_first, child_n;
 };
 
+struct RowStore {
+    const float *pos, *scale, *rot, *op, *sh;
+    const uint32_t *src;  // input Gaussian of each row; NULL: the row id itself
+};
+
 int build_impl(const float *pos, const float *scale, const float *rot, const float *opacity, const float *sh,
-               uint32_t n, uint32_t sh_degree, uint32_t cap, hipStream_t st, v3dg_bundle *B)
+               uint32_t n, uint32_t sh_degree, uint32_t cap, uint32_t iters, const float *dirs, hipStream_t st,
+               v3dg_bundle *B)
 {
     const uint32_t shf = 3u * (sh_degree + 1u) * (sh_degree + 1u);
-    DevBuf d_pos, d_scale, d_opacity, spare, err;
+    DevBuf d_pos, d_scale, d_rot, d_opacity, d_sh, d_dirs, spare, err;
     int rc;
     if ((rc = upload(d_pos, pos, 3ull * n))) return rc;
     if ((rc = upload(d_scale, scale, 3ull * n))) return rc;
+    if ((rc = upload(d_rot, rot, 4ull * n))) return rc;
     if ((rc = upload(d_opacity, opacity, (uint64_t)n))) return rc;
+    if ((rc = upload(d_sh, sh, (uint64_t)shf * n))) return rc;
+    if (iters && (rc = upload(d_dirs, dirs, 3ull * iters))) return rc;
     if ((rc = dev_make<uint32_t>(err, 1))) return rc;
     HIP_TRY(hipMemset(err.p, 0, sizeof(uint32_t)));
+    auto store_of = [&](const BuildLayer &ly, bool input) {
+        if (input)
+            return RowStore{d_pos.as<float>(), d_scale.as<float>(), d_rot.as<float>(), d_opacity.as<float>(),
+                            d_sh.as<float>(), nullptr};
+        return RowStore{ly.pos.as<float>(), ly.scale.as<float>(), ly.rot.as<float>(), ly.op.as<float>(),
+                        ly.sh.as<float>(), ly.src.as<uint32_t>()};
+    };
 
     std::vector<BuildLayer> L(1);
     {  // layer C_0: the split of the Gaussians
@@ -2204,6 +2224,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
     // coarser layers while a layer holds two clusters or more
     for (uint32_t gen = 0;; ++gen) {
         BuildLayer &cur = L.back();
+        const RowStore S = store_of(cur, gen == 0);
         const uint32_t C = (uint32_t)cur.h_first.size();
         if (C < 2) {
             cur.perm.assign(C, 0);
@@ -2211,10 +2232,10 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
             break;
         }
         if (gen >= 250) return fail(V3DG_ERR_DEVICE, "offline build: too many layers");
-        DevBuf mean, gitems, gspare, d_gfirst, d_gsize;
+        DevBuf mean, gitems, gspare, d_gfirst, d_gsize, kept, go_rows, go_count, go_first, losses;
         if ((rc = dev_make<float>(mean, 3ull * C))) return rc;
-        launch_cluster_mean(st, d_pos.as<float>(), cur.rows.as<uint32_t>(), cur.first.as<uint32_t>(),
-                            cur.count.as<uint32_t>(), C, mean.as<float>(), nullptr);
+        launch_cluster_mean(st, S.pos, cur.rows.as<uint32_t>(), cur.first.as<uint32_t>(), cur.count.as<uint32_t>(), C,
+                            mean.as<float>(), nullptr);
         HIP_TRY(hipGetLastError());
         std::vector<uint32_t> iota(C), gfirst, gsize;
         for (uint32_t k = 0; k < C; ++k) iota[k] = k;
@@ -2224,20 +2245,48 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
         cur.perm.resize(C);
         if ((rc = d2h(cur.perm.data(), gitems.p, C * sizeof(uint32_t), st))) return rc;
         const uint32_t G = (uint32_t)gfirst.size();
+        const uint64_t slots = (uint64_t)G * cap;
         if ((rc = upload(d_gfirst, gfirst.data(), G))) return rc;
         if ((rc = upload(d_gsize, gsize.data(), G))) return rc;
         BuildLayer nx;
-        if ((rc = dev_make<uint32_t>(nx.rows, (uint64_t)G * cap))) return rc;
-        if ((rc = dev_make<uint32_t>(nx.count, G))) return rc;
-        if ((rc = dev_make<float>(nx.sph, 4ull * G))) return rc;
-        launch_group(st, d_pos.as<float>(), d_scale.as<float>(), d_opacity.as<float>(), gen, cur.rows.as<uint32_t>(),
-                     cur.first.as<uint32_t>(), cur.count.as<uint32_t>(), cur.sph.as<float>(), gitems.as<uint32_t>(),
-                     d_gfirst.as<uint32_t>(), d_gsize.as<uint32_t>(), G, cap, nx.rows.as<uint32_t>(),
-                     nx.count.as<uint32_t>(), nx.sph.as<float>(), err.as<uint32_t>());
+        if ((rc = dev_make<uint32_t>(kept, slots)) || (rc = dev_make<uint32_t>(go_rows, 128ull * G)) ||
+            (rc = dev_make<uint32_t>(go_count, G)) || (rc = dev_make<uint32_t>(nx.rows, slots)) ||
+            (rc = dev_make<uint32_t>(nx.count, G)) || (rc = dev_make<float>(nx.sph, 4ull * G)) ||
+            (rc = dev_make<float>(nx.pos, 3 * slots)) || (rc = dev_make<float>(nx.scale, 3 * slots)) ||
+            (rc = dev_make<float>(nx.rot, 4 * slots)) || (rc = dev_make<float>(nx.op, slots)) ||
+            (rc = dev_make<float>(nx.sh, shf * slots)) || (rc = dev_make<uint32_t>(nx.src, slots)))
+            return rc;
+        launch_group(st, S.pos, S.scale, S.op, cur.rows.as<uint32_t>(), cur.first.as<uint32_t>(),
+                     cur.count.as<uint32_t>(), cur.sph.as<float>(), gitems.as<uint32_t>(), d_gfirst.as<uint32_t>(),
+                     d_gsize.as<uint32_t>(), G, cap, kept.as<uint32_t>(), nx.count.as<uint32_t>(), nx.sph.as<float>(),
+                     go_rows.as<uint32_t>(), go_count.as<uint32_t>(), err.as<uint32_t>());
+        HIP_TRY(hipGetLastError());
+        launch_spawn(st, S.pos, S.scale, S.rot, S.op, S.sh, S.src, shf, kept.as<uint32_t>(), nx.count.as<uint32_t>(),
+                     G, cap, nx.pos.as<float>(), nx.scale.as<float>(), nx.rot.as<float>(), nx.op.as<float>(),
+                     nx.sh.as<float>(), nx.src.as<uint32_t>(), nx.rows.as<uint32_t>());
         HIP_TRY(hipGetLastError());
         nx.h_first.resize(G);
         for (uint32_t g = 0; g < G; ++g) nx.h_first[g] = g * cap;
         if ((rc = upload(nx.first, nx.h_first.data(), G))) return rc;
+        if (iters) {  // local splatting of every group (Sec. 3.2)
+            std::vector<uint32_t> gof(G);
+            for (uint32_t g = 0; g < G; ++g) gof[g] = 128u * g;
+            if ((rc = upload(go_first, gof.data(), G))) return rc;
+            if ((rc = dev_make<float>(losses, (uint64_t)G * iters))) return rc;
+            launch_local_splat(st, go_first.as<uint32_t>(), go_count.as<uint32_t>(), nx.first.as<uint32_t>(),
+                               nx.count.as<uint32_t>(), nx.sph.as<float>(), S.pos, S.scale, S.rot, S.op, S.sh, shf,
+                               go_rows.as<uint32_t>(), nx.pos.as<float>(), nx.scale.as<float>(), nx.rot.as<float>(),
+                               nx.op.as<float>(), nx.sh.as<float>(), shf, d_dirs.as<float>(), iters, G,
+                               losses.as<float>(), nullptr, err.as<uint32_t>());
+            HIP_TRY(hipGetLastError());
+            std::vector<float> h((uint64_t)G * iters);
+            if ((rc = d2h(h.data(), losses.p, h.size() * sizeof(float), st))) return rc;
+            for (uint32_t it = 0; it < iters; ++it) {
+                double acc = 0.0;
+                for (uint32_t g = 0; g < G; ++g) acc += h[(uint64_t)g * iters + it];
+                B->fit_loss.push_back((float)(acc / G));
+            }
+        }
         nx.h_count.resize(G);
         if ((rc = d2h(nx.h_count.data(), nx.count.p, G * sizeof(uint32_t), st))) return rc;
         nx.child_first = gfirst;
@@ -2257,6 +2306,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
     B->n_leaf = base[1];
     B->n_layers = NL;
     B->sh_floats = shf;
+    B->fit_iters = iters;
     B->first_row.assign(C, 0);
     B->count.assign(C, 0);
     B->level.assign(C, 0);
@@ -2265,6 +2315,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
     B->n_children.assign(C, 0);
     B->self_sphere.assign(4ull * C, 0.f);
     B->parent_sphere.assign(4ull * C, 0.f);
+    std::vector<std::vector<uint32_t>> idx(NL);  // per layer: store row of each bundle row
     uint64_t row = 0;
     for (uint32_t l = 0; l < NL; ++l) {
         BuildLayer &ly = L[l];
@@ -2275,6 +2326,11 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
         for (uint32_t k = 0; k < Cl; ++k) store = std::max<uint64_t>(store, (uint64_t)ly.h_first[k] + ly.h_count[k]);
         ly.h_rows.resize(store);
         if ((rc = d2h(ly.h_rows.data(), ly.rows.p, store * sizeof(uint32_t), st))) return rc;
+        std::vector<uint32_t> lsrc;
+        if (l > 0) {
+            lsrc.resize(store);
+            if ((rc = d2h(lsrc.data(), ly.src.p, store * sizeof(uint32_t), st))) return rc;
+        }
         for (uint32_t p = 0; p < Cl; ++p) {
             const uint32_t k = ly.perm[p], id = base[l] + p;
             B->first_row[id] = (uint32_t)row;
@@ -2287,7 +2343,9 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
                 for (uint32_t i = 0; i < ly.child_n[k]; ++i) B->parent[base[l - 1] + ly.child_first[k] + i] = (int32_t)id;
             }
             for (uint32_t i = 0; i < ly.h_count[k]; ++i) {
-                B->src.push_back(ly.h_rows[ly.h_first[k] + i]);
+                const uint32_t r = ly.h_rows[ly.h_first[k] + i];
+                idx[l].push_back(r);
+                B->src.push_back(l == 0 ? r : lsrc[r]);
                 B->gen.push_back((uint8_t)l);
             }
             row += ly.h_count[k];
@@ -2299,23 +2357,27 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
             B->parent_sphere[4ull * id + a] = par < 0 ? (a == 3 ? INFINITY : B->self_sphere[4ull * id + a])
                                                       : B->self_sphere[4ull * par + a];
     }
-    // rows: the input Gaussians with grown scales, gathered on the device
+    // rows: gathered layer by layer from the row stores on the device
     const uint32_t R = (uint32_t)row;
     B->n_rows = R;
-    DevBuf d_rot, d_sh, d_src, d_gen, o_pos, o_scale, o_rot, o_op, o_sh;
-    if ((rc = upload(d_rot, rot, 4ull * n))) return rc;
-    if ((rc = upload(d_sh, sh, (uint64_t)shf * n))) return rc;
-    if ((rc = upload(d_src, B->src.data(), R))) return rc;
-    if ((rc = upload(d_gen, B->gen.data(), R))) return rc;
+    DevBuf o_pos, o_scale, o_rot, o_op, o_sh;
     if ((rc = dev_make<float>(o_pos, 3ull * R))) return rc;
     if ((rc = dev_make<float>(o_scale, 3ull * R))) return rc;
     if ((rc = dev_make<float>(o_rot, 4ull * R))) return rc;
     if ((rc = dev_make<float>(o_op, R))) return rc;
     if ((rc = dev_make<float>(o_sh, (uint64_t)shf * R))) return rc;
-    launch_bundle_rows(st, d_pos.as<float>(), d_scale.as<float>(), d_rot.as<float>(), d_opacity.as<float>(),
-                       d_sh.as<float>(), shf, d_src.as<uint32_t>(), d_gen.as<uint8_t>(), R, o_pos.as<float>(),
-                       o_scale.as<float>(), o_rot.as<float>(), o_op.as<float>(), o_sh.as<float>());
-    HIP_TRY(hipGetLastError());
+    uint64_t r0 = 0;
+    std::vector<DevBuf> d_idx(NL);
+    for (uint32_t l = 0; l < NL; ++l) {
+        const uint32_t nr = (uint32_t)idx[l].size();
+        if ((rc = upload(d_idx[l], idx[l].data(), nr))) return rc;
+        const RowStore S = store_of(L[l], l == 0);
+        launch_gather_rows(st, S.pos, S.scale, S.rot, S.op, S.sh, shf, d_idx[l].as<uint32_t>(), nr,
+                           o_pos.as<float>() + 3 * r0, o_scale.as<float>() + 3 * r0, o_rot.as<float>() + 4 * r0,
+                           o_op.as<float>() + r0, o_sh.as<float>() + (uint64_t)shf * r0);
+        HIP_TRY(hipGetLastError());
+        r0 += nr;
+    }
     B->pos.resize(3ull * R);
     B->scale.resize(3ull * R);
     B->rot.resize(4ull * R);
@@ -2330,12 +2392,23 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
     return V3DG_OK;
 }
 
+// unit-length-able view directions: finite and not zero
+bool dirs_ok(const float *d, uint32_t n)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        const double x = d[3 * i], y = d[3 * i + 1], z = d[3 * i + 2], q = x * x + y * y + z * z;
+        if (!std::isfinite(q) || !(q > 1e-12)) return false;
+    }
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
 
 int v3dg_build_bundle(const float *pos, const float *scale, const float *rot, const float *opacity, const float *sh,
-                      uint32_t n, uint32_t sh_degree, uint32_t cluster_size, v3dg_bundle **out)
+                      uint32_t n, uint32_t sh_degree, uint32_t cluster_size, uint32_t fit_iters,
+                      const float *view_dirs, v3dg_bundle **out)
 {
     g_err.clear();
     if (!out) return fail(V3DG_ERR_INVALID_ARG, "out is NULL");
@@ -2344,10 +2417,13 @@ int v3dg_build_bundle(const float *pos, const float *scale, const float *rot, co
     if (n == 0 || n >= (1u << 31)) return fail(V3DG_ERR_INVALID_ARG, "n must be 1 .. 2^31-1");
     if (sh_degree > 3) return fail(V3DG_ERR_INVALID_ARG, "sh_degree must be 0..3");
     if (cluster_size < 2 || cluster_size > 64) return fail(V3DG_ERR_INVALID_ARG, "cluster_size must be 2..64");
+    if (fit_iters > (1u << 20)) return fail(V3DG_ERR_INVALID_ARG, "fit_iters must be at most 2^20");
+    if (fit_iters && (!view_dirs || !dirs_ok(view_dirs, fit_iters)))
+        return fail(V3DG_ERR_INVALID_ARG, "view_dirs must hold fit_iters finite non-zero directions");
     hipStream_t st = nullptr;
     HIP_TRY(hipStreamCreate(&st));  // blocking: the synchronous uploads are ordered with its work
     v3dg_bundle *B = new v3dg_bundle();
-    const int rc = build_impl(pos, scale, rot, opacity, sh, n, sh_degree, cluster_size, st, B);
+    const int rc = build_impl(pos, scale, rot, opacity, sh, n, sh_degree, cluster_size, fit_iters, view_dirs, st, B);
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
     if (rc) {
@@ -2397,6 +2473,14 @@ int v3dg_bundle_copy(const v3dg_bundle *b, float *pos, float *scale, float *rot,
     return V3DG_OK;
 }
 
+int v3dg_bundle_fit_loss(const v3dg_bundle *b, float *loss)
+{
+    g_err.clear();
+    if (!b) return fail(V3DG_ERR_INVALID_ARG, "bundle is NULL");
+    if (loss && !b->fit_loss.empty()) std::memcpy(loss, b->fit_loss.data(), b->fit_loss.size() * sizeof(float));
+    return V3DG_OK;
+}
+
 void v3dg_bundle_free(v3dg_bundle *b) { delete b; }
 
 int v3dg_local_splat(uint32_t n_groups, const uint32_t *orig_first, const uint32_t *orig_count,
@@ -2412,6 +2496,8 @@ int v3dg_local_splat(uint32_t n_groups, const uint32_t *orig_first, const uint32
         !orig_opacity || !orig_dc || !fit_pos || !fit_scale || !fit_rot || !fit_opacity || !fit_dc ||
         (iters && !view_dirs))
         return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
+    if (iters && !dirs_ok(view_dirs, iters))
+        return fail(V3DG_ERR_INVALID_ARG, "view_dirs must hold iters finite non-zero directions");
     for (uint32_t g = 0; g < n_groups; ++g) {
         if (orig_count[g] > 128 || fit_count[g] > 64)
             return fail(V3DG_ERR_INVALID_ARG, "group %u: at most 128 original and 64 fitted Gaussians", g);
@@ -2435,7 +2521,7 @@ int v3dg_local_splat(uint32_t n_groups, const uint32_t *orig_first, const uint32
     HIP_TRY(hipMemset(err.p, 0, sizeof(uint32_t)));
     launch_local_splat(nullptr, of.as<uint32_t>(), oc.as<uint32_t>(), ff.as<uint32_t>(), fc.as<uint32_t>(),
                        sp.as<float>(), op.as<float>(), os.as<float>(), orr.as<float>(), oo.as<float>(),
-                       od.as<float>(), 3, fp.as<float>(), fs.as<float>(), fr.as<float>(), fo.as<float>(),
+                       od.as<float>(), 3, nullptr, fp.as<float>(), fs.as<float>(), fr.as<float>(), fo.as<float>(),
                        fd.as<float>(), 3, dr.as<float>(), iters, n_groups, lo.as<float>(), gf.as<float>(),
                        err.as<uint32_t>());
     HIP_TRY(hipGetLastError());

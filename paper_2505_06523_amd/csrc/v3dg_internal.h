@@ -303,25 +303,35 @@ void launch_split_layer(hipStream_t st, const float *pts, const uint32_t *items,
 // rows[first[k] ..], in FP32; sph4 (optional) = (mean, 0)
 void launch_cluster_mean(hipStream_t st, const float *pos, const uint32_t *rows, const uint32_t *first,
                          const uint32_t *count, uint32_t n, float *mean, float *sph4);
-// Simplification of n_groups cluster groups into one cluster each (see build.hip)
-void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, uint32_t gen,
-                  const uint32_t *rows, const uint32_t *first, const uint32_t *count, const float *msph,
-                  const uint32_t *perm, const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap,
-                  uint32_t *out_rows, uint32_t *out_count, float *sph, uint32_t *err);
+// Simplification of n_groups cluster groups into one cluster each: the
+// group's rows (ids into the current row store) go to go_rows[g * 128 ..] and
+// go_count[g], the kept ones to kept[g * cap ..], their number to out_count[g],
+// the group sphere to sph[g]
+void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, const uint32_t *rows,
+                  const uint32_t *first, const uint32_t *count, const float *msph, const uint32_t *perm,
+                  const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap, uint32_t *kept,
+                  uint32_t *out_count, float *sph, uint32_t *go_rows, uint32_t *go_count, uint32_t *err);
+// The next layer's row store from the kept rows (scales grown once); src
+// (nullable: the row id itself) carries the input Gaussian of each row.
+void launch_spawn(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
+                  const float *sh, const uint32_t *src, uint32_t sh_floats, const uint32_t *kept,
+                  const uint32_t *count, uint32_t n_groups, uint32_t cap, float *npos, float *nscale, float *nrot,
+                  float *nopacity, float *nsh, uint32_t *nsrc, uint32_t *nrows);
 // Local splatting of n_groups cluster groups: group g fits the fitted rows
 // sfirst[g] .. + scount[g] (<= 64; position, scale, rotation, opacity, dc at
-// sdc + stride * row) to the original rows ofirst[g] .. + ocount[g] (<= 128)
-// over views dirs[0 .. iters) around sphere[g]; losses (n_groups x iters)
-// and grad_first (14 per fitted row) are optional.
+// sdc + stride * row) to its ocount[g] (<= 128) original rows, rows
+// orows[ofirst[g] + k] (orows nullable: rows ofirst[g] + k), over views
+// dirs[0 .. iters) around sphere[g]; losses (n_groups x iters) and
+// grad_first (14 per fitted row) are optional.
 void launch_local_splat(hipStream_t st, const uint32_t *ofirst, const uint32_t *ocount, const uint32_t *sfirst,
                         const uint32_t *scount, const float *sphere, const float *opos, const float *oscale,
-                        const float *orot, const float *oopacity, const float *odc, uint32_t odc_stride, float *spos,
-                        float *sscale, float *srot, float *sopacity, float *sdc, uint32_t sdc_stride,
-                        const float *dirs, uint32_t iters, uint32_t n_groups, float *losses, float *grad_first,
-                        uint32_t *err);
-// bundle row i = input Gaussian src[i] with its scales grown gen[i] times
-void launch_bundle_rows(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
-                        const float *sh, uint32_t sh_floats, const uint32_t *src, const uint8_t *gen, uint32_t n_rows,
-                        float *opos, float *oscale, float *orot, float *oopacity, float *osh);
+                        const float *orot, const float *oopacity, const float *odc, uint32_t odc_stride,
+                        const uint32_t *orows, float *spos, float *sscale, float *srot, float *sopacity, float *sdc,
+                        uint32_t sdc_stride, const float *dirs, uint32_t iters, uint32_t n_groups, float *losses,
+                        float *grad_first, uint32_t *err);
+// bundle rows of one layer: output row i = row idx[i] of the layer's store
+void launch_gather_rows(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,
+                        const float *sh, uint32_t sh_floats, const uint32_t *idx, uint32_t n_rows, float *opos,
+                        float *oscale, float *orot, float *oopacity, float *osh);
 
 }  // namespace v3dg

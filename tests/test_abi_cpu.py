@@ -157,14 +157,23 @@ def test_build_bundle_rejects_bad_arguments():
     p = lambda a: a.ctypes.data_as(C.c_void_p)
     h = C.c_void_p()
     args = [p(pos), p(scale), p(rot), p(op), p(sh)]
-    assert L.v3dg_build_bundle(*args, n, 1, 64, None) == v.V3DG_ERR_INVALID_ARG
-    assert L.v3dg_build_bundle(*args, 0, 1, 64, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
-    assert L.v3dg_build_bundle(*args, n, 4, 64, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
-    assert L.v3dg_build_bundle(*args, n, 1, 1, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
-    assert L.v3dg_build_bundle(*args, n, 1, 65, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 1, 64, 0, None, None) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, 0, 1, 64, 0, None, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 4, 64, 0, None, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 1, 1, 0, None, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 1, 65, 0, None, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
     assert "cluster_size" in v.last_error()
-    assert L.v3dg_build_bundle(None, *args[1:], n, 1, 64, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(None, *args[1:], n, 1, 64, 0, None, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    # fitting needs its view directions, finite and non-zero
+    assert L.v3dg_build_bundle(*args, n, 1, 64, 3, None, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    dirs = np.array([[0, 0, 1], [0, 0, 0], [1, 0, 0]], np.float32)
+    assert L.v3dg_build_bundle(*args, n, 1, 64, 3, p(dirs), C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert "view_dirs" in v.last_error()
+    dirs[1, 0] = np.nan
+    assert L.v3dg_build_bundle(*args, n, 1, 64, 3, p(dirs), C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_build_bundle(*args, n, 1, 64, (1 << 20) + 1, p(dirs), C.byref(h)) == v.V3DG_ERR_INVALID_ARG
     assert not h.value
     assert L.v3dg_bundle_sizes(None, None, None, None, None) == v.V3DG_ERR_INVALID_ARG
     assert L.v3dg_bundle_copy(None, *([None] * 15)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_bundle_fit_loss(None, None) == v.V3DG_ERR_INVALID_ARG
     L.v3dg_bundle_free(None)

@@ -115,3 +115,124 @@ def test_build_c2_size_sampled(torch):
     # the loader accepts it
     sc = v.Scene(H.bundle_asset(g, 3), sg.identity_instances(1))
     sc.close()
+
+
+# ---- builds with local splatting (Sec. 3.2) ---------------------------------
+ROWS = ("pos", "scale", "rot", "opacity", "sh", "src", "gen")
+LR = dict(pos=1.6e-5, log_scale=5e-3, quat=1e-3, logit=5e-2, dc=2.5e-3)
+
+
+def _unit_dirs(n, seed):
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+
+
+def _group_of(b, p):
+    """Rows of the cluster group that made cluster p: its children's rows in
+    child order, and the children's ids."""
+    kids = range(int(b["first_child"][p]), int(b["first_child"][p]) + int(b["n_children"][p]))
+    idx = np.concatenate([np.arange(b["first_row"][c], b["first_row"][c] + b["count"][c]) for c in kids])
+    return idx, list(kids)
+
+
+def _halved(b, idx):
+    """The group's kept rows before the fit: the ceil(m/2) largest
+    ((sx sy) sz) o (ties: the earlier), scales grown once."""
+    s, o = b["scale"][idx], b["opacity"][idx]
+    score = ((s[:, 0] * s[:, 1]) * s[:, 2]) * o
+    keep = np.sort(np.argsort(-score.astype(np.float64), kind="stable")[:(len(idx) + 1) // 2])
+    init = {k: b[k][idx][keep].copy() for k in ROWS}
+    init["scale"] = init["scale"] * GROW
+    return init
+
+
+GROW = np.float32(2.0 ** (1.0 / 6.0))
+
+
+def _rows_of(b, idx):
+    return {k: b[k][idx] for k in ROWS}
+
+
+def test_fitted_build_every_group_matches_oracle(torch):
+    """Every group of a build with local splatting, taken on the GPU's own
+    inputs (its children's rows as built): the kept Gaussians are the top
+    half by score, the sphere is the oracle's bit for bit, and the fitted rows
+    follow the FP64 local-splatting oracle (differences measured in Adam
+    steps of each parameter's learning rate); the leaves equal the
+    structural oracle's."""
+    from oracle import local_splat as ls
+    iters = 6
+    dirs = _unit_dirs(iters, 17)
+    pos, scale, rot, opacity, sh = _input(1000, 1, 23)
+    g = v.build_bundle(pos, scale, rot, opacity, sh, 64, fit_iters=iters, view_dirs=dirs)
+    r = ob.build_bundle(pos, scale, rot, opacity, sh, 64)
+    nl = g["n_leaf_clusters"]
+    assert nl == r["n_leaf_clusters"] and g["n_layers"] == int(r["level"].max()) + 1
+    L = int(g["first_row"][nl - 1]) + int(g["count"][nl - 1])
+    for k in ROWS + ("first_row", "count", "self_sphere"):
+        a, b_ = np.asarray(g[k]), np.asarray(r[k]).astype(np.asarray(g[k]).dtype).reshape(np.asarray(g[k]).shape)
+        sel = slice(0, L) if k in ROWS else slice(0, nl)
+        np.testing.assert_array_equal(a[sel], b_[sel], err_msg=k)
+    assert g["fit_loss"].shape == (g["n_layers"] - 1, iters)
+    errs = {k: [] for k in LR}
+    for p in range(nl, len(g["count"])):
+        idx, kids = _group_of(g, p)
+        rows = _rows_of(g, idx)
+        init = _halved(g, idx)
+        mine = np.arange(g["first_row"][p], g["first_row"][p] + g["count"][p])
+        np.testing.assert_array_equal(g["src"][mine], init["src"])
+        assert (g["gen"][mine] == g["level"][p]).all()
+        sph = ob.group_sphere(rows["pos"], [g["self_sphere"][c] for c in kids])
+        np.testing.assert_array_equal(g["self_sphere"][p], sph)
+        out, _, _ = ls.local_splat(rows, init, sph[:3].astype(np.float64), float(sph[3]), dirs.astype(np.float64),
+                                   iters)
+        errs["pos"].append(np.abs(g["pos"][mine] - out["pos"]).ravel() / LR["pos"])
+        errs["log_scale"].append(np.abs(np.log(g["scale"][mine]) - np.log(out["scale"])).ravel() / LR["log_scale"])
+        qd = np.minimum(np.abs(g["rot"][mine] - out["rot"]).max(1), np.abs(g["rot"][mine] + out["rot"]).max(1))
+        errs["quat"].append(qd / LR["quat"])
+        lo = lambda o: np.log(o / (1 - o))
+        errs["logit"].append(np.abs(lo(g["opacity"][mine].astype(np.float64)) - lo(out["opacity"])) / LR["logit"])
+        errs["dc"].append(np.abs(g["sh"][mine][:, 0, :] - out["sh"][:, 0, :]).ravel() / LR["dc"])
+    for k, e in errs.items():
+        e = np.concatenate(e)
+        _say("fitted build %-9s |gpu - oracle| in steps of lr: median %.2e  99%% %.2e  max %.2e"
+             % (k, np.median(e), np.quantile(e, 0.99), e.max()))
+        # within half an Adam step of the parameter everywhere (a step moves it by about lr)
+        assert np.median(e) < 0.01 and e.max() < 0.5, (k, np.median(e), e.max())
+
+
+def test_fitted_build_equals_the_local_splat_entry_point(torch):
+    """The build's refinement is v3dg_local_splat on each group's rows: every
+    coarse cluster of a 20000-Gaussian build equals, bit for bit, the entry
+    point run on its children's rows and its kept rows before the fit."""
+    iters = 20
+    dirs = _unit_dirs(iters, 3)
+    pos, scale, rot, opacity, sh = _input(20000, 2, 31)
+    g = v.build_bundle(pos, scale, rot, opacity, sh, 64, fit_iters=iters, view_dirs=dirs)
+    nl = g["n_leaf_clusters"]
+    groups, orig, fit, mine = [], [], [], []
+    o0 = f0 = 0
+    for p in range(nl, len(g["count"])):
+        idx, _ = _group_of(g, p)
+        init = _halved(g, idx)
+        orig.append(_rows_of(g, idx))
+        fit.append(init)
+        mine.append(np.arange(g["first_row"][p], g["first_row"][p] + g["count"][p]))
+        groups.append((o0, len(idx), f0, len(init["src"]), tuple(g["self_sphere"][p])))
+        o0 += len(idx)
+        f0 += len(init["src"])
+    cat = lambda parts: {k: np.concatenate([q[k] for q in parts]) for k in ROWS}
+    o, f = cat(orig), cat(fit)
+    o["dc"], f["dc"] = o["sh"][:, 0, :], f["sh"][:, 0, :]
+    out, losses, _ = v.local_splat(groups, o, f, dirs, iters)
+    rows = np.concatenate(mine)
+    for k in ("pos", "scale", "rot", "opacity"):
+        np.testing.assert_array_equal(g[k][rows], out[k], err_msg=k)
+    np.testing.assert_array_equal(g["sh"][rows][:, 0, :], out["dc"])
+    np.testing.assert_array_equal(g["sh"][rows][:, 1:, :], f["sh"][:, 1:, :])
+    # the layer means of the losses
+    lvl = g["level"][nl:]
+    for l in range(1, g["n_layers"]):
+        np.testing.assert_allclose(g["fit_loss"][l - 1], losses[lvl == l].astype(np.float64).mean(0), rtol=1e-5)
+    _say("fitted build: %d groups, layer-1 loss %.4f -> %.4f" % (len(groups), g["fit_loss"][0, 0],
+                                                                 g["fit_loss"][0, -1]))

@@ -154,3 +154,46 @@ def test_build_passes_the_loader_checks():
         sc.close()
     except v.V3DGError as e:  # on a machine without a GPU the upload is what fails
         assert e.code == v.V3DG_ERR_HIP, str(e)
+
+
+def _unit_dirs(n, seed):
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def test_local_splatting_brings_the_coarse_layer_closer():
+    """Sec. 3.2: fitting the halved Gaussians to their group makes the coarse
+    cluster look more like the Gaussians it stands for.  Two leaf clusters of
+    64 form one group; on views not used by the fit, the root's render is
+    closer (L1 of rgb and alpha) to the leaves' render after the fit than
+    with the plain halved copies.  The fit leaves the structure alone: the
+    split, the kept Gaussians and the spheres equal the structural build's."""
+    import torch
+    from oracle import local_splat as ls
+    from tests.test_oracle_local_splat import _group
+    g = _group(128, 31)
+    args = (g["pos"], g["scale"], g["rot"], g["opacity"], g["sh"])
+    plain = ob.build_bundle(*args, 64)
+    fitted = ob.build_bundle(*args, 64, iters=80, dirs=_unit_dirs(80, 5))
+    for k in ("first_row", "count", "level", "parent", "first_child", "n_children", "src", "gen", "self_sphere"):
+        np.testing.assert_array_equal(fitted[k], plain[k], err_msg=k)
+    leaves = slice(0, 128)
+    np.testing.assert_array_equal(fitted["pos"][leaves], plain["pos"][leaves])
+    sph = plain["self_sphere"][2]
+
+    def rend(b, rows, d):
+        Rv, eye = ls.view_camera(sph[:3].astype(np.float64), float(sph[3]), d)
+        p = ls.params_from(b["pos"][rows], b["scale"][rows], b["rot"][rows], b["opacity"][rows], b["sh"][rows])
+        with torch.no_grad():
+            rgb, a = ls.render(p["pos"], torch.exp(p["log_scale"]), p["quat"], torch.sigmoid(p["logit"]), p["dc"],
+                               Rv, eye)
+        return rgb.numpy(), a.numpy()
+
+    root = slice(128, 192)
+    err = {"plain": 0.0, "fitted": 0.0}
+    for d in _unit_dirs(8, 99):
+        ref_rgb, ref_a = rend(plain, leaves, d)
+        for name, b in (("plain", plain), ("fitted", fitted)):
+            rgb, a = rend(b, root, d)
+            err[name] += np.abs(rgb - ref_rgb).mean() + 0.1 * np.abs(a - ref_a).mean()
+    assert err["fitted"] < 0.9 * err["plain"], err
