@@ -253,13 +253,25 @@ def tau_sweep(torch, scene, cams, taus, img, img2, fps_full):
     return out
 
 
+FIT_ITERS = 640  # pseudo-views per cluster group (the paper's setting)
+
+
+def unit_dirs(n, seed):
+    import numpy as np
+    d = np.random.default_rng(seed).standard_normal((n, 3))
+    return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+
+
 def build_bench(v, asset, with_oracle: bool):
-    """Offline build (paper Algorithm 1, structural part) of the asset's 1M leaf
-    Gaussians on the GPU, host arrays in and out; the oracle on the same input."""
+    """Offline build (paper Algorithm 1) of the asset's 1M leaf Gaussians on
+    the GPU, host arrays in and out: structural, and with local splatting over
+    640 pseudo-views per group; the oracles on the same input (the structural
+    build whole, the local-splatting fit on one group over a few views)."""
     import numpy as np
     L = asset.n_leaf_rows
     g_in = (asset.pos[:L], asset.scale[:L], asset.rot[:L], asset.opacity[:L], asset.sh[:L])
-    v.build_bundle(*(x[:4096] for x in g_in), 64)  # first use: kernel loading
+    dirs = unit_dirs(FIT_ITERS, 7)
+    v.build_bundle(*(x[:4096] for x in g_in), 64, fit_iters=2, view_dirs=dirs)  # first use: kernel loading
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
@@ -271,8 +283,21 @@ def build_bench(v, asset, with_oracle: bool):
            "includes": "host-to-device upload, all build launches, row gather and device-to-host copy"}
     log("offline build: %d Gaussians -> %d clusters, %d rows in %.1f ms on the GPU" % (L, out["clusters"],
                                                                                       out["rows"], out["gpu_ms"]))
+    t0 = time.perf_counter()
+    bf = v.build_bundle(*g_in, 64, fit_iters=FIT_ITERS, view_dirs=dirs)
+    t_f = time.perf_counter() - t0
+    groups = int(len(bf["count"]) - bf["n_leaf_clusters"])
+    fit_s = max(t_f - out["gpu_ms"] / 1e3, 1e-9)
+    out["local_splatting"] = {
+        "views_per_group": FIT_ITERS, "groups": groups, "gpu_s": t_f,
+        "fit_s_over_structural": fit_s,
+        "fit_us_per_group_view": 1e6 * fit_s / (groups * FIT_ITERS),
+        "mean_loss_first_view_by_layer": [float(x) for x in bf["fit_loss"][:, 0]],
+        "mean_loss_last_64_views_by_layer": [float(x) for x in bf["fit_loss"][:, -64:].mean(1)]}
+    log("offline build with local splatting (%d views per group, %d groups): %.2f s" % (FIT_ITERS, groups, t_f))
     if with_oracle:
         from oracle import offline_build as ob
+        from oracle import local_splat as ls
         t0 = time.perf_counter()
         ob.build_bundle(*g_in, 64)
         t = time.perf_counter() - t0
@@ -280,6 +305,20 @@ def build_bench(v, asset, with_oracle: bool):
         out["oracle_gaussians_per_s"] = L / t
         out["oracle_kind"] = "numpy oracle, one host process"
         log("offline build oracle: %.1f s" % t)
+        # one coarse group of the fitted bundle (two leaf clusters) over 24 views
+        p = int(bf["n_leaf_clusters"])
+        c0 = int(bf["first_child"][p])
+        idx = np.arange(bf["first_row"][c0], bf["first_row"][c0] + int(bf["count"][c0]) + int(bf["count"][c0 + 1]))
+        rows = {k: bf[k][idx] for k in ("pos", "scale", "rot", "opacity", "sh")}
+        simp = {k: x[::2].copy() for k, x in rows.items()}
+        sph = bf["self_sphere"][p].astype(np.float64)
+        t0 = time.perf_counter()
+        ls.local_splat(rows, simp, sph[:3], float(sph[3]), dirs[:24].astype(np.float64), 24)
+        t = time.perf_counter() - t0
+        out["local_splatting"]["oracle_us_per_group_view"] = 1e6 * t / 24
+        out["local_splatting"]["oracle_sample"] = "one group of %d Gaussians fitting %d, 24 views (FP64 PyTorch " \
+                                                  "with autograd, host)" % (len(idx), len(simp["opacity"]))
+        log("local splatting oracle: %.0f ms per group and view" % (1e3 * t / 24))
     return out
 
 
@@ -400,31 +439,36 @@ def main():
         extended = tau_sweep(torch, scene, cams, [64.0, 256.0, 1024.0, 4096.0], img, img2, fps_full)
 
     # the same leaves built into a bundle by the paper's Algorithm 1 on the GPU
-    # (halving with 2^(1/6) scale growth instead of the generator's merges)
+    # (halving with 2^(1/6) scale growth instead of the generator's merges),
+    # structural and with local splatting
     built = None
     if not args.no_extended and not args.no_build:
+        built = {}
         L = asset.n_leaf_rows
-        t0 = time.perf_counter()
-        bb = v.build_bundle(asset.pos[:L], asset.scale[:L], asset.rot[:L], asset.opacity[:L], asset.sh[:L], 64)
-        t_b = time.perf_counter() - t0
-        bscene = v.Scene(sg.Asset(sh_degree=3, pos=bb["pos"], scale=bb["scale"], rot=bb["rot"],
-                                  opacity=bb["opacity"], sh=bb["sh"], first_row=bb["first_row"], count=bb["count"],
-                                  level=bb["level"], parent=bb["parent"], first_child=bb["first_child"],
-                                  n_children=bb["n_children"], self_sphere=bb["self_sphere"],
-                                  parent_sphere=bb["parent_sphere"], n_leaf_clusters=bb["n_leaf_clusters"]))
-        fr = [(c, 0.0) for c in cams]
-        run_frames(torch, bscene, fr[:8], img, full=True, prof=False)  # warm-up: the scene's first buffers
-        run_frames(torch, bscene, [(c, 4096.0) for c in cams[:8]], img, full=False, prof=False)
-        w_bf, _, _, _ = run_frames(torch, bscene, fr, img, full=True, prof=False)
-        built = dict(build_s=t_b, clusters=int(len(bb["count"])), rows=int(len(bb["src"])),
-                     full_detail_fps=len(fr) / w_bf,
-                     tolerances=tau_sweep(torch, bscene, cams, [1.0, 64.0, 256.0, 1024.0, 4096.0], img, img2,
-                                          len(fr) / w_bf))
-        for k, e in built["tolerances"].items():
-            log("built bundle tau %s: %.1f FPS (%.2fx full detail), PSNR min %.1f dB" % (
-                k, e["fps"], e["speedup_vs_full"], e["psnr_vs_full_db_min"]))
-        bscene.close()
-        del bb
+        for name, iters in (("structural", 0), ("local_splatting_%d" % FIT_ITERS, FIT_ITERS)):
+            t0 = time.perf_counter()
+            bb = v.build_bundle(asset.pos[:L], asset.scale[:L], asset.rot[:L], asset.opacity[:L], asset.sh[:L], 64,
+                                fit_iters=iters, view_dirs=unit_dirs(FIT_ITERS, 7))
+            t_b = time.perf_counter() - t0
+            bscene = v.Scene(sg.Asset(sh_degree=3, pos=bb["pos"], scale=bb["scale"], rot=bb["rot"],
+                                      opacity=bb["opacity"], sh=bb["sh"], first_row=bb["first_row"],
+                                      count=bb["count"], level=bb["level"], parent=bb["parent"],
+                                      first_child=bb["first_child"], n_children=bb["n_children"],
+                                      self_sphere=bb["self_sphere"], parent_sphere=bb["parent_sphere"],
+                                      n_leaf_clusters=bb["n_leaf_clusters"]))
+            fr = [(c, 0.0) for c in cams]
+            run_frames(torch, bscene, fr[:8], img, full=True, prof=False)  # warm-up: the scene's first buffers
+            run_frames(torch, bscene, [(c, 4096.0) for c in cams[:8]], img, full=False, prof=False)
+            w_bf, _, _, _ = run_frames(torch, bscene, fr, img, full=True, prof=False)
+            built[name] = dict(build_s=t_b, clusters=int(len(bb["count"])), rows=int(len(bb["src"])),
+                               full_detail_fps=len(fr) / w_bf,
+                               tolerances=tau_sweep(torch, bscene, cams, [1.0, 64.0, 256.0, 1024.0, 4096.0], img,
+                                                    img2, len(fr) / w_bf))
+            for k, e in built[name]["tolerances"].items():
+                log("built bundle (%s) tau %s: %.1f FPS (%.2fx full detail), PSNR min %.1f / median %.1f dB" % (
+                    name, k, e["fps"], e["speedup_vs_full"], e["psnr_vs_full_db_min"], e["psnr_vs_full_db_median"]))
+            bscene.close()
+            del bb
 
     # storage tiers: FP32 vs FP16 geometry with BF16 / FP16 SH, at 1080p and 2160p
     tiers = {}

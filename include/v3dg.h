@@ -331,8 +331,11 @@ void v3dg_server_free(v3dg_server *srv);
  *
  * With fit_iters > 0, every group's kept Gaussians are refined right after
  * the halving by local splatting (Sec. 3.2, as v3dg_local_splat: the group's
- * Gaussians are the originals, its sphere places the pseudo-views, view i
- * looks along view_dirs[3i .. 3i+2], the same directions for every group);
+ * Gaussians are the originals; the pseudo-views face the group centre from
+ * four times the group's reach, the largest |p - c| + 3 max(sx, sy, sz) of
+ * its Gaussians (FP64, rounded up to FP32), so that they frame the Gaussians'
+ * 3-sigma extents; view i looks along view_dirs[3i .. 3i+2], the same
+ * directions for every group);
  * with fit_iters = 0 the rows of a layer are plain copies of rows below
  * (structural build).  view_dirs: host, 3 x fit_iters finite non-zero floats
  * (normalised here), may be NULL when fit_iters = 0; fit_iters <= 2^20.

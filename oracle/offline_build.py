@@ -13,8 +13,9 @@ group's bounding sphere (centre: mean Gaussian position; radius: farthest
 Gaussian) becomes the own sphere of the simplified cluster and the parent
 sphere of the group's clusters.  Optionally (iters > 0) the simplified
 Gaussians of every group are then refined by local splatting (Sec. 3.2, the
-local-splatting oracle) against the group's Gaussians, with the group sphere
-placing the pseudo-views and the same view directions for every group.
+local-splatting oracle) against the group's Gaussians, with the same view
+directions for every group; the views face the group centre from four times
+the group's reach, the farthest 3-sigma extent of its Gaussians.
 Every layer is made from the current rows of the layer below (positions for
 means and spheres, scales and opacities for the scores).
 
@@ -129,6 +130,18 @@ def group_sphere(p, child_sph):
     return np.array([c32[0], c32[1], c32[2], np.float32(r)], dtype=np.float32)
 
 
+def view_sphere(rows: dict, sph: np.ndarray) -> np.ndarray:
+    """Sphere framing a group's pseudo-views: the group centre and the
+    farthest 3-sigma reach |p - c| + 3 max(sx, sy, sz) of its Gaussians (FP64,
+    rounded up to FP32), so that the views hold the Gaussians' extents."""
+    c = sph[:3].astype(np.float64)
+    r = 0.0
+    for q, s in zip(rows["pos"].astype(np.float64), rows["scale"]):
+        d = q - c
+        r = max(r, math.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) + 3.0 * float(s.max()))
+    return np.array([sph[0], sph[1], sph[2], round_up32(r)], np.float32)
+
+
 def fit(orig: dict, simp: dict, sph: np.ndarray, dirs, iters: int) -> dict:
     """Local splatting of a group's simplified Gaussians; FP32 rows back."""
     from oracle import local_splat as ls
@@ -171,7 +184,7 @@ def build_bundle(pos, scale, rot, opacity, sh, n: int = 64, iters: int = 0, dirs
             sph = group_sphere(rows["pos"], [cur_sph[m] for m in members])
             kept = simplify(rows)
             if iters:
-                kept = fit(rows, kept, sph, dirs, iters)
+                kept = fit(rows, kept, view_sphere(rows, sph), dirs, iters)
             nxt.append(kept)
             nxt_sph.append(sph)
             nxt_children.append((members[0], len(members)))

@@ -187,7 +187,9 @@ __device__ __forceinline__ double dist64(const float *p, double cx, double cy, d
 // to go_rows[g * kGroupMax ..], their number to go_count[g]); the ceil(m/2)
 // with the largest ((sx sy) sz) o (the rows' current values; ties to the
 // earlier one) are kept in G_o order, their ids at kept + g * cap.  sph[g] =
-// the group sphere over G_o, grown over the members' spheres.
+// the group sphere over G_o, grown over the members' spheres; vsph[g] = its
+// centre with the radius that frames the group's pseudo-views: the farthest
+// 3-sigma reach |p - c| + 3 max(sx, sy, sz) of a Gaussian of G_o, rounded up.
 constexpr int kGroupMax = 128;
 
 __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restrict__ pos,
@@ -202,12 +204,13 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
                                                           const uint32_t *__restrict__ gsize, uint32_t n_groups,
                                                           uint32_t cap, uint32_t *__restrict__ kept,
                                                           uint32_t *__restrict__ out_count, float *__restrict__ sph,
-                                                          uint32_t *__restrict__ go_rows,
+                                                          float *__restrict__ vsph, uint32_t *__restrict__ go_rows,
                                                           uint32_t *__restrict__ go_count, uint32_t *err)
 {
     __shared__ float s_score[kGroupMax];
     __shared__ uint32_t s_src[kGroupMax];
-    __shared__ double s_r[kGroupMax];
+    __shared__ double s_r[kGroupMax], s_v[kGroupMax];
+    __shared__ float s_ms[kGroupMax];
     __shared__ double s_c[3];
     __shared__ uint32_t s_m, s_base[2];
     const uint32_t g = blockIdx.x;
@@ -233,6 +236,7 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
         const uint32_t src = rows[first[k] + ((uint32_t)t - s_base[mi])];
         const float sx = scale[3ull * src], sy = scale[3ull * src + 1], sz = scale[3ull * src + 2];
         s_score[t] = __fmul_rn(__fmul_rn(__fmul_rn(sx, sy), sz), opacity[src]);
+        s_ms[t] = fmaxf(fmaxf(sx, sy), sz);
         s_src[t] = src;
         go_rows[(uint64_t)g * kGroupMax + t] = src;
     }
@@ -267,10 +271,18 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
     }
     __syncthreads();
     s_r[t] = (uint32_t)t < m ? dist64(pos + 3ull * s_src[t], s_c[0], s_c[1], s_c[2]) : 0.0;
+    s_v[t] = (uint32_t)t < m ? __dadd_rn(s_r[t], __dmul_rn(3.0, (double)s_ms[t])) : 0.0;
     __syncthreads();
     if (t == 0) {
-        double r = 0.0;
-        for (uint32_t q = 0; q < m; ++q) r = fmax(r, s_r[q]);
+        double r = 0.0, rv = 0.0;
+        for (uint32_t q = 0; q < m; ++q) {
+            r = fmax(r, s_r[q]);
+            rv = fmax(rv, s_v[q]);
+        }
+        vsph[4ull * g] = (float)s_c[0];
+        vsph[4ull * g + 1] = (float)s_c[1];
+        vsph[4ull * g + 2] = (float)s_c[2];
+        vsph[4ull * g + 3] = round_up_f32(rv);
         float rf = round_up_f32(r);
         for (uint32_t i = 0; i < gsize[g]; ++i) {
             const float *cs = msph + 4ull * perm[gfirst[g] + i];
@@ -287,11 +299,11 @@ __global__ void __launch_bounds__(kGroupMax) group_kernel(const float *__restric
 void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, const uint32_t *rows,
                   const uint32_t *first, const uint32_t *count, const float *msph, const uint32_t *perm,
                   const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap, uint32_t *kept,
-                  uint32_t *out_count, float *sph, uint32_t *go_rows, uint32_t *go_count, uint32_t *err)
+                  uint32_t *out_count, float *sph, float *vsph, uint32_t *go_rows, uint32_t *go_count, uint32_t *err)
 {
     if (n_groups == 0) return;
     hipLaunchKernelGGL(group_kernel, dim3(n_groups), dim3(kGroupMax), 0, st, pos, scale, opacity, rows, first, count,
-                       msph, perm, gfirst, gsize, n_groups, cap, kept, out_count, sph, go_rows, go_count, err);
+                       msph, perm, gfirst, gsize, n_groups, cap, kept, out_count, sph, vsph, go_rows, go_count, err);
 }
 
 // The next layer's row store: slot g * cap + i (i < count[g]) is a copy of

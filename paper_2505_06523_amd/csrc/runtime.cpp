@@ -2232,7 +2232,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
             break;
         }
         if (gen >= 250) return fail(V3DG_ERR_DEVICE, "offline build: too many layers");
-        DevBuf mean, gitems, gspare, d_gfirst, d_gsize, kept, go_rows, go_count, go_first, losses;
+        DevBuf mean, gitems, gspare, d_gfirst, d_gsize, kept, go_rows, go_count, go_first, losses, vsph;
         if ((rc = dev_make<float>(mean, 3ull * C))) return rc;
         launch_cluster_mean(st, S.pos, cur.rows.as<uint32_t>(), cur.first.as<uint32_t>(), cur.count.as<uint32_t>(), C,
                             mean.as<float>(), nullptr);
@@ -2252,6 +2252,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
         if ((rc = dev_make<uint32_t>(kept, slots)) || (rc = dev_make<uint32_t>(go_rows, 128ull * G)) ||
             (rc = dev_make<uint32_t>(go_count, G)) || (rc = dev_make<uint32_t>(nx.rows, slots)) ||
             (rc = dev_make<uint32_t>(nx.count, G)) || (rc = dev_make<float>(nx.sph, 4ull * G)) ||
+            (rc = dev_make<float>(vsph, 4ull * G)) ||
             (rc = dev_make<float>(nx.pos, 3 * slots)) || (rc = dev_make<float>(nx.scale, 3 * slots)) ||
             (rc = dev_make<float>(nx.rot, 4 * slots)) || (rc = dev_make<float>(nx.op, slots)) ||
             (rc = dev_make<float>(nx.sh, shf * slots)) || (rc = dev_make<uint32_t>(nx.src, slots)))
@@ -2259,7 +2260,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
         launch_group(st, S.pos, S.scale, S.op, cur.rows.as<uint32_t>(), cur.first.as<uint32_t>(),
                      cur.count.as<uint32_t>(), cur.sph.as<float>(), gitems.as<uint32_t>(), d_gfirst.as<uint32_t>(),
                      d_gsize.as<uint32_t>(), G, cap, kept.as<uint32_t>(), nx.count.as<uint32_t>(), nx.sph.as<float>(),
-                     go_rows.as<uint32_t>(), go_count.as<uint32_t>(), err.as<uint32_t>());
+                     vsph.as<float>(), go_rows.as<uint32_t>(), go_count.as<uint32_t>(), err.as<uint32_t>());
         HIP_TRY(hipGetLastError());
         launch_spawn(st, S.pos, S.scale, S.rot, S.op, S.sh, S.src, shf, kept.as<uint32_t>(), nx.count.as<uint32_t>(),
                      G, cap, nx.pos.as<float>(), nx.scale.as<float>(), nx.rot.as<float>(), nx.op.as<float>(),
@@ -2274,7 +2275,7 @@ int build_impl(const float *pos, const float *scale, const float *rot, const flo
             if ((rc = upload(go_first, gof.data(), G))) return rc;
             if ((rc = dev_make<float>(losses, (uint64_t)G * iters))) return rc;
             launch_local_splat(st, go_first.as<uint32_t>(), go_count.as<uint32_t>(), nx.first.as<uint32_t>(),
-                               nx.count.as<uint32_t>(), nx.sph.as<float>(), S.pos, S.scale, S.rot, S.op, S.sh, shf,
+                               nx.count.as<uint32_t>(), vsph.as<float>(), S.pos, S.scale, S.rot, S.op, S.sh, shf,
                                go_rows.as<uint32_t>(), nx.pos.as<float>(), nx.scale.as<float>(), nx.rot.as<float>(),
                                nx.op.as<float>(), nx.sh.as<float>(), shf, d_dirs.as<float>(), iters, G,
                                losses.as<float>(), nullptr, err.as<uint32_t>());

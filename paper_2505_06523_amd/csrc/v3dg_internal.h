@@ -306,11 +306,12 @@ void launch_cluster_mean(hipStream_t st, const float *pos, const uint32_t *rows,
 // Simplification of n_groups cluster groups into one cluster each: the
 // group's rows (ids into the current row store) go to go_rows[g * 128 ..] and
 // go_count[g], the kept ones to kept[g * cap ..], their number to out_count[g],
-// the group sphere to sph[g]
+// the group sphere to sph[g], the sphere framing its pseudo-views to vsph[g]
 void launch_group(hipStream_t st, const float *pos, const float *scale, const float *opacity, const uint32_t *rows,
                   const uint32_t *first, const uint32_t *count, const float *msph, const uint32_t *perm,
                   const uint32_t *gfirst, const uint32_t *gsize, uint32_t n_groups, uint32_t cap, uint32_t *kept,
-                  uint32_t *out_count, float *sph, uint32_t *go_rows, uint32_t *go_count, uint32_t *err);
+                  uint32_t *out_count, float *sph, float *vsph, uint32_t *go_rows, uint32_t *go_count,
+                  uint32_t *err);
 // The next layer's row store from the kept rows (scales grown once); src
 // (nullable: the row id itself) carries the input Gaussian of each row.
 void launch_spawn(hipStream_t st, const float *pos, const float *scale, const float *rot, const float *opacity,

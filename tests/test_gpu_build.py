@@ -184,7 +184,8 @@ def test_fitted_build_every_group_matches_oracle(torch):
         assert (g["gen"][mine] == g["level"][p]).all()
         sph = ob.group_sphere(rows["pos"], [g["self_sphere"][c] for c in kids])
         np.testing.assert_array_equal(g["self_sphere"][p], sph)
-        out, _, _ = ls.local_splat(rows, init, sph[:3].astype(np.float64), float(sph[3]), dirs.astype(np.float64),
+        vs = ob.view_sphere(rows, sph)
+        out, _, _ = ls.local_splat(rows, init, vs[:3].astype(np.float64), float(vs[3]), dirs.astype(np.float64),
                                    iters)
         errs["pos"].append(np.abs(g["pos"][mine] - out["pos"]).ravel() / LR["pos"])
         errs["log_scale"].append(np.abs(np.log(g["scale"][mine]) - np.log(out["scale"])).ravel() / LR["log_scale"])
@@ -204,7 +205,9 @@ def test_fitted_build_every_group_matches_oracle(torch):
 def test_fitted_build_equals_the_local_splat_entry_point(torch):
     """The build's refinement is v3dg_local_splat on each group's rows: every
     coarse cluster of a 20000-Gaussian build equals, bit for bit, the entry
-    point run on its children's rows and its kept rows before the fit."""
+    point run on its children's rows and its kept rows before the fit, with
+    the oracle's view sphere (so the build frames its views bit for bit as
+    the oracle does)."""
     iters = 20
     dirs = _unit_dirs(iters, 3)
     pos, scale, rot, opacity, sh = _input(20000, 2, 31)
@@ -218,7 +221,7 @@ def test_fitted_build_equals_the_local_splat_entry_point(torch):
         orig.append(_rows_of(g, idx))
         fit.append(init)
         mine.append(np.arange(g["first_row"][p], g["first_row"][p] + g["count"][p]))
-        groups.append((o0, len(idx), f0, len(init["src"]), tuple(g["self_sphere"][p])))
+        groups.append((o0, len(idx), f0, len(init["src"]), tuple(ob.view_sphere(_rows_of(g, idx), g["self_sphere"][p]))))
         o0 += len(idx)
         f0 += len(init["src"])
     cat = lambda parts: {k: np.concatenate([q[k] for q in parts]) for k in ROWS}

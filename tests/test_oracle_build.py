@@ -179,7 +179,8 @@ def test_local_splatting_brings_the_coarse_layer_closer():
         np.testing.assert_array_equal(fitted[k], plain[k], err_msg=k)
     leaves = slice(0, 128)
     np.testing.assert_array_equal(fitted["pos"][leaves], plain["pos"][leaves])
-    sph = plain["self_sphere"][2]
+    sph = ob.view_sphere({k: plain[k][:128] for k in ("pos", "scale")}, plain["self_sphere"][2])
+    assert sph[3] > plain["self_sphere"][2][3]
 
     def rend(b, rows, d):
         Rv, eye = ls.view_camera(sph[:3].astype(np.float64), float(sph[3]), d)
@@ -197,3 +198,13 @@ def test_local_splatting_brings_the_coarse_layer_closer():
             rgb, a = rend(b, root, d)
             err[name] += np.abs(rgb - ref_rgb).mean() + 0.1 * np.abs(a - ref_a).mean()
     assert err["fitted"] < 0.9 * err["plain"], err
+
+
+def test_view_sphere_hand_worked():
+    """Two Gaussians at x = +-1 around the origin: the reach is the larger of
+    1 + 3 * 0.3 and 1 + 3 * 0.5 (each one's largest scale)."""
+    rows = dict(pos=np.array([[1, 0, 0], [-1, 0, 0]], np.float32),
+                scale=np.array([[0.1, 0.2, 0.3], [0.5, 0.1, 0.1]], np.float32))
+    vs = ob.view_sphere(rows, np.array([0, 0, 0, 1], np.float32))
+    assert list(vs[:3]) == [0, 0, 0]
+    assert vs[3] == ob.round_up32(1.0 + 3.0 * float(np.float32(0.5)))
