@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-tiers", action="store_true", help="skip the storage-precision comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-culling", action="store_true", help="skip the view-culling measurement")
+    ap.add_argument("--no-stream", action="store_true", help="skip the cluster-streaming measurement")
     ap.add_argument("--no-build", action="store_true", help="skip the offline-build measurement")
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
@@ -350,6 +351,70 @@ def culling_bench(torch, v, sg, asset):
     return out
 
 
+def stream_bench(torch, v, sg, asset):
+    """A close walk through the 1M-leaf asset (100 cameras looking along a
+    circle of radius 0.45 inside it, 1920x1080, tolerance 1, culling on) with
+    the rows streamed from host memory: first through a pool of every cluster
+    (the largest cut of the walk is its working set), then through a pool
+    25 % above that working set, against the resident scene; every 10th image
+    compared bit for bit."""
+    import numpy as np
+    cams = sg.tangent_path_cameras(100)
+    img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    img2 = torch.empty_like(img)
+    res = v.Scene(asset)
+    res.set_culling(True)
+    fr = [(c, 1.0) for c in cams]
+    run_frames(torch, res, fr[:3], img, full=False, prof=False)
+    w_res, ms_res, _, _ = run_frames(torch, res, fr, img, full=False, prof=False)
+    row_bytes = 4 * (3 + 8) + 4 * 3 * (asset.sh_degree + 1) ** 2
+    out = {"workload": "close walk through the 1M-leaf asset (100 cameras along a circle of radius 0.45, "
+                       "1920x1080, tolerance 1, culling on), rows streamed from host memory",
+           "resident": dict(fps=len(fr) / w_res, p50_ms=pct(ms_res, 50), p99_ms=pct(ms_res, 99),
+                            row_bytes_in_hbm=int(asset.n_rows) * row_bytes)}
+    work = None
+    for name in ("pool_all", "pool_working_set_x1.25"):
+        pool = asset.n_clusters if work is None else int(math.ceil(1.25 * work))
+        sc = v.Scene(asset, pool_clusters=pool)
+        sc.set_culling(True)
+        used, pages, equal = [], [], True
+        sel = None
+        ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for cam, tau in fr:
+            a = time.perf_counter()
+            sel = sc.select(cam, tau, sel)
+            sc.render(cam, sel, img)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - a))
+            st = sc.stream_stats()
+            used.append(st["last_resident_used"])
+            pages.append(st["last_pages_in"])
+        wall = time.perf_counter() - t0
+        for cam, tau in fr[::10]:  # bit-equal images against the resident scene
+            sel = sc.select(cam, tau, sel)
+            sc.render(cam, sel, img)
+            s2 = res.select(cam, tau)
+            res.render(cam, s2, img2)
+            torch.cuda.synchronize()
+            equal = equal and bool(torch.equal(img, img2))
+            s2.free()
+        st = sc.stream_stats()
+        out[name] = dict(pool_clusters=pool, pool_bytes=pool * 64 * row_bytes, fps=len(fr) / wall,
+                         p50_ms=pct(ms, 50), p99_ms=pct(ms, 99), max_clusters_per_cut=int(max(used)),
+                         mean_clusters_per_cut=float(np.mean(used)),
+                         mean_pages_in_per_frame=float(np.mean(pages[1:])),
+                         mean_mb_in_per_frame=float(np.mean(pages[1:])) * 64 * row_bytes / 1e6,
+                         evictions=int(st["evictions"]), images_equal_resident=equal)
+        log("streamed %s (%d pages): %.1f FPS, %.1f pages in per frame, %d evictions, equal %s" % (
+            name, pool, len(fr) / wall, float(np.mean(pages[1:])), st["evictions"], equal))
+        work = int(max(used)) if work is None else work
+        sc.close()
+    res.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -511,6 +576,9 @@ def main():
     culling = None
     if not args.no_culling and not args.profile_run and not args.quick:
         culling = culling_bench(torch, v, sg, asset)
+    streaming = None
+    if not args.no_stream and not args.profile_run and not args.quick:
+        streaming = stream_bench(torch, v, sg, asset)
     build = None
     if not args.no_build and not args.profile_run and not args.quick:
         build = build_bench(v, asset, not args.no_cpu)
@@ -578,6 +646,7 @@ def main():
         "precision_tiers": tiers,
         "serving": serving,
         "culling": culling,
+        "streaming": streaming,
         "offline_build": build,
         "roofline": roof,
     }

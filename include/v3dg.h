@@ -141,6 +141,40 @@ typedef struct {
 int v3dg_load_hierarchy(const v3dg_hierarchy_desc *desc, const double *instances_3x4, uint32_t n_instances,
                         void *hip_stream, uint32_t flags, v3dg_scene **out);
 
+/* Streamed load (the streaming module the paper's conclusion and discussion
+ * leaves to future work): as v3dg_load_hierarchy, but the Gaussian rows stay
+ * in host memory as one page image per cluster, and device memory holds a
+ * pool of pool_clusters pages of 64 rows (1 <= pool_clusters < 2^26; a
+ * larger pool than the scene's cluster count is cut to it; 0 loads the rows
+ * resident, as v3dg_load_hierarchy).  Cluster tables, spheres and instances
+ * stay resident.  v3dg_select reads the cut back (it synchronises the stream),
+ * keeps the resident clusters it uses, and pages in the others in place of
+ * the least recently used pages that this cut does not use: the page images
+ * are staged in pinned host memory, copied in one transfer per 2048 clusters
+ * and scattered into their pages on the scene's stream.  Images equal those of
+ * the resident scene bit for bit.  A cut that needs more clusters than the
+ * pool holds fails with V3DG_ERR_CAPACITY and pages nothing.  A selection is
+ * renderable until a later select pages out one of its clusters; rendering it
+ * after that fails with V3DG_ERR_INVALID_ARG.  Slot rows name pool rows.
+ * v3dg_render_full pages in every leaf.  v3dg_copy_attributes and the server
+ * take resident scenes only. */
+int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *desc, const double *instances_3x4,
+                                 uint32_t n_instances, void *hip_stream, uint32_t flags, uint32_t pool_clusters,
+                                 v3dg_scene **out);
+
+/* Paging counters of a streamed scene (zeros for a resident one). */
+typedef struct {
+    uint64_t frames;            /* cuts paged in (selects and full renders)          */
+    uint64_t pages_in;          /* clusters copied into the pool                     */
+    uint64_t bytes_in;          /* host-to-device bytes of those page images         */
+    uint64_t evictions;         /* resident clusters whose page was given to another */
+    uint64_t last_pages_in;     /* clusters paged in by the latest cut               */
+    uint32_t last_resident_used;/* resident clusters the latest cut uses             */
+    uint32_t pool_clusters;     /* pages in the pool                                 */
+    uint32_t resident;          /* clusters resident now                             */
+} v3dg_stream_stats;
+int v3dg_get_stream_stats(const v3dg_scene *scene, v3dg_stream_stats *out);
+
 /* Replace the instance transforms (same count), e.g. every frame of a dynamic
  * scene of rigid objects (paper Appendix A.3). */
 int v3dg_set_instances(v3dg_scene *scene, const double *instances_3x4, uint32_t n_instances);

@@ -63,6 +63,12 @@ class v3dg_frame_stats(C.Structure):
                 ("key_bits", C.c_uint32), ("sort_passes", C.c_uint32), ("sort_mode", C.c_uint32)]
 
 
+class v3dg_stream_stats(C.Structure):
+    _fields_ = [("frames", C.c_uint64), ("pages_in", C.c_uint64), ("bytes_in", C.c_uint64),
+                ("evictions", C.c_uint64), ("last_pages_in", C.c_uint64), ("last_resident_used", C.c_uint32),
+                ("pool_clusters", C.c_uint32), ("resident", C.c_uint32)]
+
+
 class v3dg_profile(C.Structure):
     _fields_ = [("ms", C.c_double * 11), ("launches", C.c_uint64 * 11), ("frames", C.c_uint64),
                 ("selects", C.c_uint64), ("tests", C.c_uint64), ("sel_clusters", C.c_uint64),
@@ -92,7 +98,7 @@ class v3dg_server_stats(C.Structure):
 
 
 EXPORTS = [
-    "v3dg_load_hierarchy", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
+    "v3dg_load_hierarchy", "v3dg_load_hierarchy_streamed", "v3dg_get_stream_stats", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
@@ -115,6 +121,8 @@ def lib():
     P, U32, U64, I = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
     sig = {
         "v3dg_load_hierarchy": ([P, P, U32, P, U32, P], I),
+        "v3dg_load_hierarchy_streamed": ([P, P, U32, P, U32, U32, P], I),
+        "v3dg_get_stream_stats": ([P, P], I),
         "v3dg_set_instances": ([P, P, U32], I),
         "v3dg_select": ([P, P, C.c_float, P], I),
         "v3dg_render": ([P, P, P, P], I),
@@ -168,10 +176,21 @@ def _p(a: np.ndarray):
 
 
 # ---- one-to-one wrappers of the C ABI ------------------------------------------
-def v3dg_load_hierarchy(desc, instances_3x4, n_instances, hip_stream, flags):
+def v3dg_load_hierarchy(desc, instances_3x4, n_instances, hip_stream, flags, pool_clusters: int = 0):
     out = C.c_void_p()
-    _check(lib().v3dg_load_hierarchy(C.byref(desc), instances_3x4, n_instances, hip_stream, flags, C.byref(out)))
+    if pool_clusters:
+        _check(lib().v3dg_load_hierarchy_streamed(C.byref(desc), instances_3x4, n_instances, hip_stream, flags,
+                                                  int(pool_clusters), C.byref(out)))
+    else:
+        _check(lib().v3dg_load_hierarchy(C.byref(desc), instances_3x4, n_instances, hip_stream, flags,
+                                         C.byref(out)))
     return out
+
+
+def v3dg_get_stream_stats(scene) -> dict:
+    st = v3dg_stream_stats()
+    _check(lib().v3dg_get_stream_stats(scene, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
 
 
 def v3dg_set_instances(scene, instances_3x4, n_instances):
@@ -369,11 +388,13 @@ class Selection:
 
 
 class Scene:
-    """An asset resident in HBM with its instance table.  ``precision`` is the
+    """An asset in HBM with its instance table.  ``precision`` is the
     attribute storage tier: V3DG_FP32, V3DG_FP16_BF16SH or V3DG_FP16 (or its
-    name in PRECISIONS)."""
+    name in PRECISIONS).  ``pool_clusters`` > 0 streams the rows from host
+    memory through a pool of that many 64-row pages (v3dg_load_hierarchy_streamed)."""
 
-    def __init__(self, asset, instances=None, stream=None, flags: int = 0, precision=V3DG_FP32):
+    def __init__(self, asset, instances=None, stream=None, flags: int = 0, precision=V3DG_FP32,
+                 pool_clusters: int = 0):
         arrays = dict(
             self_sphere=np.ascontiguousarray(asset.self_sphere, np.float32),
             parent_sphere=np.ascontiguousarray(asset.parent_sphere, np.float32),
@@ -409,7 +430,7 @@ class Scene:
             stream = C.c_void_p(stream)
         self.stream = stream
         self.handle = None
-        self.handle = v3dg_load_hierarchy(d, _p(T), T.shape[0], stream, flags)
+        self.handle = v3dg_load_hierarchy(d, _p(T), T.shape[0], stream, flags, pool_clusters)
 
     def set_instances(self, instances):
         T = np.ascontiguousarray(np.asarray(instances, np.float64).reshape(-1, 12))
@@ -443,6 +464,9 @@ class Scene:
 
     def frame_stats(self) -> dict:
         return v3dg_get_frame_stats(self.handle)
+
+    def stream_stats(self) -> dict:
+        return v3dg_get_stream_stats(self.handle)
 
     def projection(self) -> dict:
         return v3dg_copy_projection(self.handle, self.frame_stats()["n_slots"])

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libv3dg.so")
-SOURCES = ["select.hip", "project.hip", "sort.hip", "blend.hip", "build.hip", "runtime.cpp"]
+SOURCES = ["select.hip", "project.hip", "sort.hip", "blend.hip", "build.hip", "stream.hip", "runtime.cpp"]
 ARCH = os.environ.get("V3DG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code

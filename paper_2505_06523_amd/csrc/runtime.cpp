@@ -203,7 +203,10 @@ struct v3dg_selection {
     uint64_t *status = nullptr;
     uint32_t *slot_row = nullptr;
     uint32_t *slot_inst = nullptr;
+    uint64_t stream_frame = 0;  // streamed scenes: the paging frame of the cut
 };
+
+constexpr uint32_t kNoPage = 0xffffffffu;
 
 struct v3dg_scene : Ctx {
     uint32_t NC = 0, n_rows = 0, sh_degree = 0, n_inst = 0;
@@ -223,6 +226,22 @@ struct v3dg_scene : Ctx {
     std::vector<uint32_t> leaf_ids;
     std::vector<uint32_t> h_count;
     v3dg_selection *full = nullptr;
+    std::vector<uint32_t> full_gid, full_off;  // the full-detail cut, on the host
+    uint32_t full_total = 0;
+    // ---- cluster streaming (pool_clusters > 0): the rows live on the host as
+    // one page image per cluster; the planes above are a pool of pages of 64
+    // rows (plane_stride = 64 pool_clusters); rowinfo[k].x is the first pool
+    // row of a resident cluster.  Pages form an LRU list (head: most recent).
+    uint32_t pool_clusters = 0, page_bytes = 0, geo_bytes = 4, sh_bytes = 4, n_sh = 0, stage_cap = 0;
+    std::vector<uint8_t> h_pages;
+    std::vector<uint32_t> page_of, cluster_of, lru_prev, lru_next;
+    std::vector<uint64_t> page_stamp, miss_stamp;
+    uint32_t lru_head = kNoPage, lru_tail = kNoPage;
+    uint64_t frame = 0, max_evicted_stamp = 0;
+    uint8_t *stage_h = nullptr, *stage_d = nullptr;
+    uint4 *ups_h = nullptr, *ups_d = nullptr;
+    std::vector<uint32_t> cut_gid, cut_off;
+    v3dg_stream_stats sstats{};
     Attribs attribs() const { return Attribs{pos_planes, geo_planes, sh_planes, plane_stride}; }
 };
 
@@ -804,6 +823,8 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     if (rc) return rc;
     if (!sel || sel->scene != s) return fail(V3DG_ERR_INVALID_ARG, "selection does not belong to this scene");
     if (!image) return fail(V3DG_ERR_INVALID_ARG, "image is NULL");
+    if (s->pool_clusters && sel->stream_frame <= s->max_evicted_stamp)
+        return fail(V3DG_ERR_INVALID_ARG, "the selection's clusters were paged out by a later select: select again");
     HIP_TRY(hipSetDevice(s->device));
     FrameInfo fi;
     const SelView sv{sel->counters, sel->slot_row, sel->slot_inst};
@@ -833,6 +854,9 @@ int build_full_selection(v3dg_scene *s)
             off[q] = (uint32_t)acc;
             acc += s->h_count[s->leaf_ids[j]];
         }
+    s->full_gid = gid;
+    s->full_off = off;
+    s->full_total = (uint32_t)acc;
     uint32_t ctr[kSelCounters] = {0};
     ctr[kSelNClusters] = (uint32_t)gid.size();
     ctr[kSelNGaussians] = (uint32_t)acc;
@@ -843,6 +867,95 @@ int build_full_selection(v3dg_scene *s)
                   sel->slot_row, sel->slot_inst);
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->full = sel;
+    return V3DG_OK;
+}
+
+// ---- cluster streaming ----------------------------------------------------
+void lru_unlink(v3dg_scene *s, uint32_t p)
+{
+    const uint32_t a = s->lru_prev[p], b = s->lru_next[p];
+    if (a != kNoPage) s->lru_next[a] = b;
+    else s->lru_head = b;
+    if (b != kNoPage) s->lru_prev[b] = a;
+    else s->lru_tail = a;
+    s->lru_prev[p] = s->lru_next[p] = kNoPage;
+}
+
+void lru_front(v3dg_scene *s, uint32_t p)
+{
+    s->lru_prev[p] = kNoPage;
+    s->lru_next[p] = s->lru_head;
+    if (s->lru_head != kNoPage) s->lru_prev[s->lru_head] = p;
+    s->lru_head = p;
+    if (s->lru_tail == kNoPage) s->lru_tail = p;
+}
+
+// Pages in every cluster with slots in a cut (gid, slot offsets, n clusters,
+// total slots; host arrays) as paging frame ++frame.  Resident clusters are
+// moved to the front of the LRU list; the others take the least recently used
+// pages not used by this cut, are staged and copied in one transfer per
+// stage_cap clusters and scattered into their pages on the scene's stream.
+// V3DG_ERR_CAPACITY (nothing paged) when the cut needs more pages than the
+// pool holds.
+int page_in(v3dg_scene *s, const uint32_t *gid, const uint32_t *off, uint32_t n, uint32_t total)
+{
+    const uint64_t f = ++s->frame;
+    std::vector<uint32_t> miss;
+    uint32_t touched = 0;
+    for (uint32_t c = 0; c < n; ++c) {
+        const uint32_t cnt = (c + 1 < n ? off[c + 1] : total) - off[c];
+        if (cnt == 0) continue;
+        const uint32_t k = gid[c] % s->NC;
+        const uint32_t pg = s->page_of[k];
+        if (pg != kNoPage) {
+            if (s->page_stamp[pg] != f) {
+                s->page_stamp[pg] = f;
+                lru_unlink(s, pg);
+                lru_front(s, pg);
+                ++touched;
+            }
+        } else if (s->miss_stamp[k] != f) {
+            s->miss_stamp[k] = f;
+            miss.push_back(k);
+        }
+    }
+    if ((uint64_t)touched + miss.size() > s->pool_clusters)
+        return fail(V3DG_ERR_CAPACITY, "the cut needs %llu resident clusters, the pool holds %u",
+                    (unsigned long long)touched + miss.size(), s->pool_clusters);
+    for (uint32_t k : miss) {  // the tail is the least recently used page, never one of this cut
+        const uint32_t pg = s->lru_tail;
+        const uint32_t old = s->cluster_of[pg];
+        if (old != kNoPage) {
+            s->page_of[old] = kNoPage;
+            s->max_evicted_stamp = std::max(s->max_evicted_stamp, s->page_stamp[pg]);
+            s->sstats.evictions += 1;
+        }
+        s->cluster_of[pg] = k;
+        s->page_of[k] = pg;
+        s->page_stamp[pg] = f;
+        lru_unlink(s, pg);
+        lru_front(s, pg);
+    }
+    for (size_t i = 0; i < miss.size(); i += s->stage_cap) {
+        const uint32_t m = (uint32_t)std::min<size_t>(s->stage_cap, miss.size() - i);
+        for (uint32_t j = 0; j < m; ++j) {
+            const uint32_t k = miss[i + j];
+            std::memcpy(s->stage_h + (uint64_t)j * s->page_bytes, s->h_pages.data() + (uint64_t)k * s->page_bytes,
+                        s->page_bytes);
+            s->ups_h[j] = make_uint4(k, s->page_of[k], s->h_count[k], 0u);
+        }
+        HIP_TRY(hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, s->stream));
+        launch_stream_scatter(s->stream, s->stage_d, s->ups_d, m, s->page_bytes, s->geo_bytes, s->sh_bytes, s->n_sh,
+                              s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride, s->rowinfo);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s->stream));  // the staging buffers are reused
+    }
+    s->sstats.frames += 1;
+    s->sstats.pages_in += miss.size();
+    s->sstats.bytes_in += (uint64_t)miss.size() * s->page_bytes;
+    s->sstats.last_pages_in = miss.size();
+    s->sstats.last_resident_used = touched + (uint32_t)miss.size();
     return V3DG_OK;
 }
 
@@ -865,6 +978,10 @@ void scene_release(v3dg_scene *s)
     dev_free(s->T_dev);
     dev_free(s->scale_dev);
     dev_free(s->cull_dev);
+    dev_free(s->stage_d);
+    dev_free(s->ups_d);
+    if (s->stage_h) (void)hipHostFree(s->stage_h);
+    if (s->ups_h) (void)hipHostFree(s->ups_h);
     ctx_release(s);
 }
 
@@ -880,8 +997,15 @@ const char *v3dg_last_error(void) { return g_err.c_str(); }
 int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x4, uint32_t n_instances,
                         void *hip_stream, uint32_t flags, v3dg_scene **out)
 {
+    return v3dg_load_hierarchy_streamed(d, instances_3x4, n_instances, hip_stream, flags, 0, out);
+}
+
+int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *d, const double *instances_3x4, uint32_t n_instances,
+                                 void *hip_stream, uint32_t flags, uint32_t pool_clusters, v3dg_scene **out)
+{
     g_err.clear();
     if (!d || !out) return fail(V3DG_ERR_INVALID_ARG, "desc and out must be non-NULL");
+    if (pool_clusters >= (1u << 26)) return fail(V3DG_ERR_INVALID_ARG, "pool_clusters must be < 2^26");
     *out = nullptr;
     if (d->precision > V3DG_FP16) return fail(V3DG_ERR_INVALID_ARG, "unknown precision %u", d->precision);
     if (d->sh_degree > 3) return fail(V3DG_ERR_INVALID_ARG, "sh_degree %u > 3", d->sh_degree);
@@ -1047,18 +1171,21 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
     s->h_count.assign(d->count, d->count + NC);
     for (uint32_t k = 0; k < NC; ++k)
         if (d->n_children[k] == 0) s->leaf_ids.push_back(k);
-    s->plane_stride = ((uint64_t)NR + 63) / 64 * 64;
+    const uint64_t ps = ((uint64_t)NR + 63) / 64 * 64;  // host plane stride
     s->precision = d->precision;
-    const uint64_t ps = s->plane_stride;
     const size_t geo_bytes = d->precision == V3DG_FP32 ? 4 : 2, sh_bytes = geo_bytes;
     auto bail = [&](int code) {
         scene_release(s);
         delete s;
         return code;
     };
-    if ((rc = dev_alloc(&s->pos_planes, 3 * ps))) return bail(rc);
-    if ((rc = dev_alloc((uint8_t **)&s->geo_planes, kGeoPlanes * ps * geo_bytes))) return bail(rc);
-    if ((rc = dev_alloc((uint8_t **)&s->sh_planes, 3ull * ncoef * ps * sh_bytes))) return bail(rc);
+    s->pool_clusters = std::min(pool_clusters, NC);
+    const bool streamed = s->pool_clusters > 0;
+    s->plane_stride = streamed ? 64ull * s->pool_clusters : ps;
+    const uint64_t dps = s->plane_stride;
+    if ((rc = dev_alloc(&s->pos_planes, 3 * dps))) return bail(rc);
+    if ((rc = dev_alloc((uint8_t **)&s->geo_planes, kGeoPlanes * dps * geo_bytes))) return bail(rc);
+    if ((rc = dev_alloc((uint8_t **)&s->sh_planes, 3ull * ncoef * dps * sh_bytes))) return bail(rc);
     if ((rc = dev_alloc(&s->self_sph, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->par_sph, NC))) return bail(rc);
     if ((rc = dev_alloc(&s->rowinfo, NC))) return bail(rc);
@@ -1090,7 +1217,44 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
             src_sh = nsh.data();
         }
         std::vector<uint2> ri(NC);
-        for (uint32_t k = 0; k < NC; ++k) ri[k] = make_uint2(d->first_row[k], d->count[k]);
+        for (uint32_t k = 0; k < NC; ++k) ri[k] = make_uint2(streamed ? 0u : d->first_row[k], d->count[k]);
+        if (streamed) {  // page images of the clusters; an empty pool
+            s->geo_bytes = (uint32_t)geo_bytes;
+            s->sh_bytes = (uint32_t)sh_bytes;
+            s->n_sh = 3u * (uint32_t)ncoef;
+            s->page_bytes = 3u * 256u + (uint32_t)kGeoPlanes * 64u * s->geo_bytes + s->n_sh * 64u * s->sh_bytes;
+            s->h_pages.assign((uint64_t)NC * s->page_bytes, 0);
+            for (uint32_t k = 0; k < NC; ++k) {
+                uint8_t *img = s->h_pages.data() + (uint64_t)k * s->page_bytes;
+                const uint64_t r0 = d->first_row[k], cnt = d->count[k];
+                for (int j = 0; j < 3; ++j) std::memcpy(img + 256u * j, &hpos[j * ps + r0], cnt * 4);
+                uint8_t *g = img + 768;
+                for (int j = 0; j < kGeoPlanes; ++j)
+                    std::memcpy(g + (uint64_t)j * 64 * geo_bytes, (const uint8_t *)src_geo + (j * ps + r0) * geo_bytes,
+                                cnt * geo_bytes);
+                uint8_t *h = g + (uint64_t)kGeoPlanes * 64 * geo_bytes;
+                for (uint32_t j = 0; j < s->n_sh; ++j)
+                    std::memcpy(h + (uint64_t)j * 64 * sh_bytes, (const uint8_t *)src_sh + (j * ps + r0) * sh_bytes,
+                                cnt * sh_bytes);
+            }
+            const uint32_t P = s->pool_clusters;
+            s->page_of.assign(NC, kNoPage);
+            s->miss_stamp.assign(NC, 0);
+            s->cluster_of.assign(P, kNoPage);
+            s->page_stamp.assign(P, 0);
+            s->lru_prev.assign(P, kNoPage);
+            s->lru_next.assign(P, kNoPage);
+            for (uint32_t q = 0; q < P; ++q) lru_front(s, q);
+            s->stage_cap = std::min<uint32_t>(P, 2048u);
+            s->sstats.pool_clusters = P;
+            if (hipHostMalloc((void **)&s->stage_h, (uint64_t)s->stage_cap * s->page_bytes, hipHostMallocDefault) !=
+                    hipSuccess ||
+                hipHostMalloc((void **)&s->ups_h, s->stage_cap * sizeof(uint4), hipHostMallocDefault) != hipSuccess) {
+                return bail(fail(V3DG_ERR_OOM, "pinned staging allocation failed"));
+            }
+            if ((rc = dev_alloc(&s->stage_d, (uint64_t)s->stage_cap * s->page_bytes))) return bail(rc);
+            if ((rc = dev_alloc(&s->ups_d, s->stage_cap))) return bail(rc);
+        }
         // view-cull table: sphere of each cluster's row means (FP64, radius
         // rounded up) and its largest scale (enlarged to cover FP16 storage)
         std::vector<CullRec> cr(NC);
@@ -1116,9 +1280,12 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
             cr[k].sph = make_float4(cf[0], cf[1], cf[2], round_up_f32(rad * (1.0 + 1e-6) + 1e-7));
             cr[k].smax = round_up_f32(smax * (1.0 + 1.0 / 1024.0));
         }
-        e = hipMemcpy(s->pos_planes, hpos.data(), hpos.size() * sizeof(float), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(s->geo_planes, src_geo, hgeo.size() * geo_bytes, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(s->sh_planes, src_sh, hsh.size() * sh_bytes, hipMemcpyHostToDevice);
+        e = hipSuccess;
+        if (!streamed) {
+            e = hipMemcpy(s->pos_planes, hpos.data(), hpos.size() * sizeof(float), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(s->geo_planes, src_geo, hgeo.size() * geo_bytes, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(s->sh_planes, src_sh, hsh.size() * sh_bytes, hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess) e = hipMemcpy(s->self_sph, self.data(), self.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->par_sph, par.data(), par.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->rowinfo, ri.data(), ri.size() * sizeof(uint2), hipMemcpyHostToDevice);
@@ -1128,6 +1295,16 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
         if (e != hipSuccess) return bail(fail(V3DG_ERR_HIP, "upload failed: %s", hipGetErrorString(e)));
     }
     *out = s;
+    return V3DG_OK;
+}
+
+int v3dg_get_stream_stats(const v3dg_scene *s, v3dg_stream_stats *out)
+{
+    g_err.clear();
+    if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "scene and out must be non-NULL");
+    *out = s->sstats;
+    out->resident = 0;
+    for (uint32_t c : s->cluster_of) out->resident += c != kNoPage ? 1u : 0u;
     return V3DG_OK;
 }
 
@@ -1144,6 +1321,25 @@ int v3dg_set_instances(v3dg_scene *s, const double *instances_3x4, uint32_t n)
     HIP_TRY(hipMemcpyAsync(s->T_dev, instances_3x4, 12ull * n * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->scale_dev, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    return V3DG_OK;
+}
+
+// Streamed scenes: read a selected cut back (synchronises) and page it in.
+static int stream_cut(v3dg_scene *s, v3dg_selection *sel)
+{
+    HIP_TRY(hipMemcpyAsync(s->pinned + 8, sel->counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->pinned[8 + kSelErr] & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
+    const uint32_t n = s->pinned[8 + kSelNClusters], total = s->pinned[8 + kSelNGaussians];
+    s->cut_gid.resize(n);
+    s->cut_off.resize(n);
+    if (n) {
+        HIP_TRY(hipMemcpy(s->cut_gid.data(), sel->gid, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(s->cut_off.data(), sel->slot_off, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    }
+    const int rc = page_in(s, s->cut_gid.data(), s->cut_off.data(), n, total);
+    if (rc) return rc;
+    sel->stream_frame = s->frame;
     return V3DG_OK;
 }
 
@@ -1180,6 +1376,17 @@ int v3dg_select(v3dg_scene *s, const v3dg_camera *c, float tau, v3dg_selection *
         Stage st(s, V3DG_STAGE_SELECT);
         launch_select(s->stream, make_selreq(s, s->itab, K, tau, sel, cam, s->culling));
     }
+    if (s->pool_clusters) {  // streamed: read the cut back, page in what it lacks
+        rc = stream_cut(s, sel);
+        if (rc) {
+            sel->stream_frame = 0;  // its cut is not expanded: never renderable
+            if (fresh) {
+                sel_release(sel);
+                delete sel;
+            }
+            return rc;
+        }
+    }
     {
         Stage st(s, V3DG_STAGE_EXPAND);
         launch_expand(s->stream, sel->gid, sel->slot_off, s->rowinfo, s->NC, sel->counters,
@@ -1215,6 +1422,15 @@ int v3dg_render_full(v3dg_scene *s, const v3dg_camera *c, float *image)
     if (rc) return rc;
     HIP_TRY(hipSetDevice(s->device));
     if ((rc = build_full_selection(s))) return rc;
+    if (s->pool_clusters) {  // streamed: page in every leaf, then place the slots on the pages
+        v3dg_selection *f = s->full;
+        if ((rc = page_in(s, s->full_gid.data(), s->full_off.data(), (uint32_t)s->full_gid.size(), s->full_total)))
+            return rc;
+        f->stream_frame = s->frame;
+        launch_expand(s->stream, f->gid, f->slot_off, s->rowinfo, s->NC, f->counters, (uint32_t)s->full_gid.size(),
+                      f->slot_row, f->slot_inst);
+        HIP_TRY(hipGetLastError());
+    }
     return render_impl(s, c, s->full, image);
 }
 
@@ -1327,6 +1543,7 @@ int v3dg_copy_attributes(v3dg_scene *s, uint64_t first, uint64_t n, float *pos, 
 {
     g_err.clear();
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
+    if (s->pool_clusters) return fail(V3DG_ERR_INVALID_ARG, "a streamed scene keeps its rows on the host");
     if (first > s->n_rows || n > s->n_rows - first)
         return fail(V3DG_ERR_INVALID_ARG, "rows [%llu, +%llu) outside the %llu-row table", (unsigned long long)first,
                     (unsigned long long)n, (unsigned long long)s->n_rows);
@@ -1815,6 +2032,10 @@ int v3dg_server_create(v3dg_scene *const *scenes, uint32_t n_scenes, const v3dg_
         if (!sc || sc->device != dev) {
             delete s;
             return fail(V3DG_ERR_INVALID_ARG, "scene %u is NULL or on another device", i);
+        }
+        if (sc->pool_clusters) {
+            delete s;
+            return fail(V3DG_ERR_INVALID_ARG, "scene %u is streamed; the server takes resident scenes", i);
         }
         (void)hipStreamSynchronize(sc->stream);
         s->scenes.push_back(sc);

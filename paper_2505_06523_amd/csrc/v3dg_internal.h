@@ -335,4 +335,10 @@ void launch_gather_rows(hipStream_t st, const float *pos, const float *scale, co
                         const float *sh, uint32_t sh_floats, const uint32_t *idx, uint32_t n_rows, float *opos,
                         float *oscale, float *orot, float *oopacity, float *osh);
 
+// stream.hip (cluster streaming): scatter n_up staged page images (layout in
+// stream.hip) into the pool planes and point rowinfo[cluster] at each page
+void launch_stream_scatter(hipStream_t st, const uint8_t *staging, const uint4 *ups, uint32_t n_up,
+                           uint32_t page_bytes, uint32_t geo_bytes, uint32_t sh_bytes, uint32_t n_sh,
+                           float *pos_planes, void *geo_planes, void *sh_planes, uint64_t stride, uint2 *rowinfo);
+
 }  // namespace v3dg

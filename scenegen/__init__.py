@@ -452,6 +452,20 @@ def orbit_cameras(n: int, seed: int, width: int = 1920, height: int = 1080, fov_
     return cams
 
 
+def tangent_path_cameras(n: int = 100, radius: float = 0.45, height: float = 0.05, width: int = 1920,
+                         heig: int = 1080, fov_x: float = math.pi / 3):
+    """A close walk through an asset: n cameras on a horizontal circle of
+    ``radius`` around the origin at ``height``, each looking along the circle
+    (counter-clockwise), so that every view holds only a part of the asset."""
+    cams = []
+    for i in range(n):
+        th = 2 * math.pi * i / n
+        eye = (radius * math.cos(th), radius * math.sin(th), height)
+        tgt = (eye[0] - math.sin(th), eye[1] + math.cos(th), height)
+        cams.append(look_at(eye, tgt, width, heig, fov_x))
+    return cams
+
+
 def single_camera_c1(seed: int = 101) -> Camera:
     """The small case: 256x256, fov 60 deg, distance 2, elevation 30 deg, seeded azimuth."""
     rng = np.random.default_rng(seed)

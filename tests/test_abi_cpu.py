@@ -177,3 +177,14 @@ def test_build_bundle_rejects_bad_arguments():
     assert L.v3dg_bundle_copy(None, *([None] * 15)) == v.V3DG_ERR_INVALID_ARG
     assert L.v3dg_bundle_fit_loss(None, None) == v.V3DG_ERR_INVALID_ARG
     L.v3dg_bundle_free(None)
+
+
+def test_streamed_load_rejects_bad_arguments():
+    L = v.lib()
+    h = C.c_void_p()
+    d = v.v3dg_hierarchy_desc()
+    assert L.v3dg_load_hierarchy_streamed(None, None, 1, None, 0, 8, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert L.v3dg_load_hierarchy_streamed(C.byref(d), None, 1, None, 0, 1 << 26, C.byref(h)) == v.V3DG_ERR_INVALID_ARG
+    assert "pool_clusters" in v.last_error()
+    assert not h.value
+    assert L.v3dg_get_stream_stats(None, None) == v.V3DG_ERR_INVALID_ARG

@@ -1,0 +1,145 @@
+"""Cluster streaming (v3dg_load_hierarchy_streamed) through the C ABI.
+
+A streamed scene keeps its rows on the host and pages the clusters of each
+cut into a pool of 64-row pages.  Its cuts and images must equal the resident
+scene's bit for bit, whatever the pool size and history of evictions; slots
+differ only in naming pool rows that hold the same Gaussians.
+"""
+import numpy as np
+import pytest
+
+import paper_2505_06523_amd as v
+import scenegen as sg
+from tests import helpers as H
+from tests.test_gpu_parity import _say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    v.lib()
+    return _t
+
+
+@pytest.fixture(scope="module")
+def world():
+    a = sg.make_asset(16384, 3, 91)
+    T = sg.grid_instances(3, 1.2, 0.2, 5)
+    return a, T
+
+
+def _frames(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for it in range(n):
+        cam = H.random_camera_near(rng, int(rng.integers(64, 320)), int(rng.integers(48, 240)), dist=(0.05, 8.0))
+        out.append((cam, float([100.0, 1e3, 1e4, 1e5][it % 4])))
+    return out
+
+
+# cuts of these 20 frames need 1 .. 335 of the asset's 341 clusters, their
+# union all of them: pools below 341 evict, pools below 335 refuse some cuts
+@pytest.mark.parametrize("pool_frac,culling,precision", [(1.0, False, "fp32"), (0.8, False, "fp32"),
+                                                         (0.8, True, "fp32"), (0.99, False, "fp16")])
+def test_streamed_equals_resident(torch, world, pool_frac, culling, precision):
+    a, T = world
+    res = v.Scene(a, T, precision=precision)
+    pool = max(1, int(pool_frac * a.n_clusters))
+    st = v.Scene(a, T, precision=precision, pool_clusters=pool)
+    res.set_culling(culling)
+    st.set_culling(culling)
+    n_checked = 0
+    for it, (cam, tau) in enumerate(_frames(20, 7)):
+        s0 = res.select(cam, tau)
+        try:
+            s1 = st.select(cam, tau)
+        except v.V3DGError as e:
+            assert e.code == v.V3DG_ERR_CAPACITY and pool < a.n_clusters, (it, e)
+            s0.free()
+            continue
+        assert np.array_equal(s0.ids(), s1.ids()), it
+        r0, i0 = s0.slots()
+        r1, i1 = s1.slots()
+        assert np.array_equal(i0, i1), it
+        assert r1.size == r0.size and (r1.size == 0 or r1.max() < 64 * pool), it
+        # each slot's pool row is its cluster's page + the row's place in the cluster
+        np.testing.assert_array_equal(r1 % 64, (r0 - a.first_row[np.searchsorted(a.first_row, r0, "right") - 1]) % 64)
+        img0 = res.render(cam, s0).clone()
+        img1 = st.render(cam, s1).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(img0, img1), (it, float((img0 - img1).abs().max()))
+        n_checked += 1
+        s0.free()
+        s1.free()
+    stats = st.stream_stats()
+    _say("pool %d of %d clusters, culling %s, %s: %d frames equal, %d pages in, %d evictions"
+         % (pool, a.n_clusters, culling, precision, n_checked, stats["pages_in"], stats["evictions"]))
+    assert n_checked >= 8
+    assert stats["pool_clusters"] == pool and stats["resident"] <= pool
+    if pool_frac < 1.0 and not culling:
+        assert stats["evictions"] > 0
+    res.close()
+    st.close()
+
+
+def test_render_full_pages_in_the_leaves(torch, world):
+    a, T = world
+    n_leaf = int(a.n_leaf_clusters)
+    res = v.Scene(a, T)
+    cam = sg.look_at((2.5, -2.0, 1.5), (0, 0, 0), 200, 150, 1.0)
+    ref = res.render_full(cam).clone()
+    big = v.Scene(a, T, pool_clusters=n_leaf)
+    img = big.render_full(cam).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(ref, img)
+    assert big.stream_stats()["resident"] == n_leaf
+    small = v.Scene(a, T, pool_clusters=n_leaf - 1)
+    with pytest.raises(v.V3DGError) as e:
+        small.render_full(cam)
+    assert e.value.code == v.V3DG_ERR_CAPACITY
+    assert small.stream_stats()["pages_in"] == 0
+    # a cut that fits (11 clusters) still works after the refusal
+    s = small.select(cam, 1e4)
+    s0 = res.select(cam, 1e4)
+    torch.cuda.synchronize()
+    assert torch.equal(small.render(cam, s).clone(), res.render(cam, s0).clone())
+    for sc in (res, big, small):
+        sc.close()
+
+
+def test_a_paged_out_selection_is_refused(torch, world):
+    """A far cut (the root, one page) stays renderable until a later cut
+    takes its page: the mid view at tolerance 1000 needs 198 clusters, the
+    root not among them (the selection oracle's count), all of a 198-page
+    pool, so it evicts exactly the least recently used page, the root's.  Rendering the far selection is then
+    refused; selecting again restores it."""
+    a, T = world
+    st = v.Scene(a, T, pool_clusters=198)
+    res = v.Scene(a, T)
+    far = sg.look_at((60.0, -50.0, 30.0), (0, 0, 0), 64, 48, 0.5)
+    mid = sg.look_at((2.0, -1.5, 1.0), (0, 0, 0), 160, 120, 1.0)
+    s_far = st.select(far, 1e9)
+    img_far = st.render(far, s_far).clone()
+    s = st.select(mid, 1e3)
+    s_ref = res.select(mid, 1e3)
+    img = st.render(mid, s).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(img, res.render(mid, s_ref).clone())
+    stats = st.stream_stats()
+    assert stats["last_pages_in"] == 198 and stats["evictions"] == 1, stats
+    with pytest.raises(v.V3DGError) as e:
+        st.render(far, s_far)
+    assert e.value.code == v.V3DG_ERR_INVALID_ARG and "paged out" in str(e.value)
+    # the mid selection stays renderable; selecting the far view again restores it
+    torch.cuda.synchronize()
+    assert torch.equal(st.render(mid, s).clone(), img)
+    s_far = st.select(far, 1e9, s_far)
+    s_ref2 = res.select(far, 1e9)
+    img2 = st.render(far, s_far).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(img_far, img2) and torch.equal(img2, res.render(far, s_ref2).clone())
+    st.close()
+    res.close()
