@@ -405,11 +405,11 @@ struct LsShared {
     float prm[kLsMaxS][kLsP], m1[kLsMaxS][kLsP], m2[kLsMaxS][kLsP];
     float opos[kLsMaxO][3], oscl[kLsMaxO][3], oq[kLsMaxO][4], oop[kLsMaxO], orgb[kLsMaxO][3];
     // splats of the current view: originals 0 .. 127, fitted ones 128 .. 191
-    float pu[192], pv[192], pca[192], pcb[192], pcc[192], pop[192], psyy[192], pz[192], prgb[192][3];
+    float pu[192], pv[192], pca[192], pcb[192], pcc[192], pop[192], prow[192], pz[192], prgb[192][3];
     uint8_t pvalid[192];
     uint8_t ord[192];
     uint32_t n_o, n_s;
-    float acc[kLsThreads / kWave][kLsMaxS][9];  // per wavefront: du dv dca dcb dcc dop dr dg db
+    float acc[kLsThreads / kWave][kLsMaxS][9];  // per wavefront: du dv dca dcb dcc dop dr dg db (per fitted index)
     float cam[12];                                // world-to-camera rows, eye
     float red[kLsThreads / kWave];
 };
@@ -463,19 +463,48 @@ __device__ bool ls_project(const float *cam, const float *p, const float *s, con
     return true;
 }
 
-// the splat reaches the row (pixel centre y) with alpha >= 1/255 somewhere:
-// the largest power over the row is -dy^2 / (2 Sigma2_yy)
-__device__ __forceinline__ bool ls_row_hit(float v, float syy, float op, float yc)
+// Largest squared row distance dy^2 at which a splat still reaches alpha >=
+// 1/255 on the row (pixel centre y): the largest power over a row is
+// -dy^2 / (2 Sigma2_yy), so dy^2 <= 2 Sigma2_yy ln(255 o), enlarged by 1 %
+// and 1e-4 so that the test never drops a contributing splat; -1 when o <
+// 1/255 (the splat reaches no row).
+__device__ __forceinline__ float ls_row_limit(float syy, float op)
 {
-    const float dy = v - yc;
-    const float lim = 2.0f * syy * __logf(255.0f * op) * 1.01f + 1e-4f;
-    return op * 255.0f >= 1.0f && dy * dy <= lim;
+    return op * 255.0f >= 1.0f ? 2.0f * syy * __logf(255.0f * op) * 1.01f + 1e-4f : -1.0f;
 }
 
 __device__ __forceinline__ float wave_sum(float x)
 {
     for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
     return x;
+}
+
+// value of x in lane k (k uniform across the wavefront)
+__device__ __forceinline__ float lane_value(float x, int k)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), k));
+}
+
+template <int kCtrl, int kRowMask, int kBankMask>
+__device__ __forceinline__ float dpp_from(float x)  // 0 where the source lane is out of range or masked
+{
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, kRowMask, kBankMask, false));
+}
+
+// Sum over the wavefront by data-parallel moves within rows of 16 lanes and
+// row broadcasts (row_shr 1, 2, 4, 8; row_bcast 15, 31): lane 63 ends with
+// the total, which is returned to every lane.  The order of the additions is
+// fixed, so the sum is deterministic.
+__device__ __forceinline__ float wave_total(float x)
+{
+    x += dpp_from<0x111, 0xf, 0xf>(x);
+    x += dpp_from<0x112, 0xf, 0xf>(x);
+    x += dpp_from<0x114, 0xf, 0xe>(x);
+    x += dpp_from<0x118, 0xf, 0xc>(x);
+    x += dpp_from<0x142, 0xa, 0xf>(x);
+    x += dpp_from<0x143, 0xc, 0xf>(x);
+    return lane_value(x, kWave - 1);
 }
 
 __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
@@ -570,7 +599,7 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
             sh.pca[t] = ca;
             sh.pcb[t] = cb;
             sh.pcc[t] = cc;
-            sh.psyy[t] = syy;
+            sh.prow[t] = ls_row_limit(syy, op);
             sh.pz[t] = z;
             sh.pop[t] = op;
             sh.pvalid[t] = ok ? 1 : 0;
@@ -599,43 +628,91 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
         }
         __syncthreads();
         const int n_o = (int)sh.n_o, n_s = (int)sh.n_s;
+        // the view's splats in depth order, in registers: lane l holds the
+        // original depth slots l and 64 + l and the fitted depth slot l; the
+        // walks below read slot k of every lane with lane_value(., k)
+        float oU[2], oV[2], oA[2], oB[2], oC[2], oO[2], oR[2], oQ0[2], oQ1[2], oQ2[2];
+        for (int h = 0; h < 2; ++h) {
+            const int slot = h * kWave + lane;
+            const int i = slot < n_o ? (int)sh.ord[slot] : 0;
+            oU[h] = sh.pu[i];
+            oV[h] = sh.pv[i];
+            oA[h] = sh.pca[i];
+            oB[h] = sh.pcb[i];
+            oC[h] = sh.pcc[i];
+            oO[h] = sh.pop[i];
+            oR[h] = slot < n_o ? sh.prow[i] : -1.0f;
+            oQ0[h] = sh.prgb[i][0];
+            oQ1[h] = sh.prgb[i][1];
+            oQ2[h] = sh.prgb[i][2];
+        }
+        const int js = lane < n_s ? (int)sh.ord[kLsMaxO + lane] : 0, is = kLsMaxO + js;
+        const float sU = sh.pu[is], sV = sh.pv[is], sA = sh.pca[is], sB = sh.pcb[is], sC = sh.pcc[is],
+                    sO = sh.pop[is], sR = lane < n_s ? sh.prow[is] : -1.0f, sQ0 = sh.prgb[is][0],
+                    sQ1 = sh.prgb[is][1], sQ2 = sh.prgb[is][2];
+        float acc9[9];
+        for (int a = 0; a < 9; ++a) acc9[a] = 0.0f;  // gradient sums of fitted depth slot `lane`
         float lsum = 0.0f;
         for (int rr = 0; rr < kLsRes / (kLsThreads / kWave); ++rr) {
             const float yc = (float)(wid * (kLsRes / (kLsThreads / kWave)) + rr) + 0.5f, xc = (float)lane + 0.5f;
-            float tgt[4];
-            float res[4];
-            int kstop = n_s;
-            for (int set = 0; set < 2; ++set) {
-                const int base = set == 0 ? 0 : kLsMaxO, n = set == 0 ? n_o : n_s;
+            // depth slots whose splat reaches this row, as bit masks
+            const float d0 = oV[0] - yc, d1 = oV[1] - yc, ds = sV - yc;
+            const uint64_t mo[2] = {__ballot(d0 * d0 <= oR[0]), __ballot(d1 * d1 <= oR[1])};
+            const uint64_t msf = __ballot(ds * ds <= sR);
+            // front-to-back compositing of one splat (the renderer's rule)
+            auto blend = [&](float u, float v, float ca, float cb, float cc, float op, float q0, float q1, float q2,
+                             float &T, float &c0, float &c1, float &c2, bool &live) -> bool {
+                const float dx = u - xc, dy = v - yc;
+                const float pw = fminf(0.0f, -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy);
+                const float al = fminf(0.99f, op * __expf(pw));
+                const bool take = live && al >= 1.0f / 255.0f;
+                const float Tn = T * (1.0f - al);
+                const bool stop = take && Tn < 1e-4f;
+                if (take && !stop) {
+                    c0 += al * T * q0;
+                    c1 += al * T * q1;
+                    c2 += al * T * q2;
+                    T = Tn;
+                }
+                if (stop) live = false;
+                return stop;
+            };
+            float tgt[4], res[4];
+            {  // the originals: the target
                 float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
                 bool live = true;
-                for (int k = 0; k < n; ++k) {
-                    const int i = base + sh.ord[base + k];
-                    if (!ls_row_hit(sh.pv[i], sh.psyy[i], sh.pop[i], yc)) continue;
-                    const float dx = sh.pu[i] - xc, dy = sh.pv[i] - yc;
-                    const float pw = fminf(0.0f, -0.5f * (sh.pca[i] * dx * dx + sh.pcc[i] * dy * dy) -
-                                                     sh.pcb[i] * dx * dy);
-                    const float al = fminf(0.99f, sh.pop[i] * __expf(pw));
-                    const bool take = live && al >= 1.0f / 255.0f;
-                    const float Tn = T * (1.0f - al);
-                    const bool stop = take && Tn < 1e-4f;
-                    if (take && !stop) {
-                        c0 += al * T * sh.prgb[i][0];
-                        c1 += al * T * sh.prgb[i][1];
-                        c2 += al * T * sh.prgb[i][2];
-                        T = Tn;
+                for (int h = 0; h < 2; ++h) {
+                    uint64_t m = mo[h];
+                    while (m && __ballot(live)) {
+                        const int k = __builtin_ctzll(m);
+                        m &= m - 1;
+                        blend(lane_value(oU[h], k), lane_value(oV[h], k), lane_value(oA[h], k), lane_value(oB[h], k),
+                              lane_value(oC[h], k), lane_value(oO[h], k), lane_value(oQ0[h], k), lane_value(oQ1[h], k),
+                              lane_value(oQ2[h], k), T, c0, c1, c2, live);
                     }
-                    if (stop) {
-                        live = false;
-                        if (set == 1) kstop = k;
-                    }
-                    if (__ballot(live) == 0) break;
                 }
-                float *o4 = set == 0 ? tgt : res;
-                o4[0] = c0;
-                o4[1] = c1;
-                o4[2] = c2;
-                o4[3] = 1.0f - T;
+                tgt[0] = c0;
+                tgt[1] = c1;
+                tgt[2] = c2;
+                tgt[3] = 1.0f - T;
+            }
+            int kstop = n_s;  // depth slot where this pixel stopped
+            {  // the fitted splats
+                float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+                bool live = true;
+                uint64_t m = msf;
+                while (m && __ballot(live)) {
+                    const int k = __builtin_ctzll(m);
+                    m &= m - 1;
+                    if (blend(lane_value(sU, k), lane_value(sV, k), lane_value(sA, k), lane_value(sB, k),
+                              lane_value(sC, k), lane_value(sO, k), lane_value(sQ0, k), lane_value(sQ1, k),
+                              lane_value(sQ2, k), T, c0, c1, c2, live))
+                        kstop = k;
+                }
+                res[0] = c0;
+                res[1] = c1;
+                res[2] = c2;
+                res[3] = 1.0f - T;
             }
             const float Ts = 1.0f - res[3];
             float gc[3];
@@ -647,37 +724,42 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
             const float dfa = res[3] - tgt[3];
             const float ga = dfa > 0.0f ? wa : (dfa < 0.0f ? -wa : 0.0f);
             lsum += fabsf(dfa) * wa;
-            // reverse walk over the fitted splats this pixel went through
+            // back-to-front over the fitted splats this row reaches, up to the
+            // last slot any pixel of the wavefront blended
             int kmax = kstop;
             for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+            uint64_t m = kmax >= kWave ? msf : (msf & ((1ull << kmax) - 1ull));
             float Tc = Ts, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f;
-            for (int k = kmax - 1; k >= 0; --k) {
-                const int j = sh.ord[kLsMaxO + k], i = kLsMaxO + j;
-                if (!ls_row_hit(sh.pv[i], sh.psyy[i], sh.pop[i], yc)) continue;
-                const float dx = sh.pu[i] - xc, dy = sh.pv[i] - yc;
-                const float raw = -0.5f * (sh.pca[i] * dx * dx + sh.pcc[i] * dy * dy) - sh.pcb[i] * dx * dy;
+            while (m) {
+                const int k = 63 - __builtin_clzll(m);
+                m &= ~(1ull << k);
+                const float u = lane_value(sU, k), v = lane_value(sV, k), ca = lane_value(sA, k),
+                            cb = lane_value(sB, k), cc = lane_value(sC, k), op = lane_value(sO, k),
+                            q0 = lane_value(sQ0, k), q1 = lane_value(sQ1, k), q2 = lane_value(sQ2, k);
+                const float dx = u - xc, dy = v - yc;
+                const float raw = -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy;
                 const float G = __expf(fminf(0.0f, raw));
-                const float ao = sh.pop[i] * G;
+                const float ao = op * G;
                 const float al = fminf(0.99f, ao);
                 const bool added = k < kstop && al >= 1.0f / 255.0f;
                 float v9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
                 if (added) {
                     const float Tk = Tc / (1.0f - al);
-                    const float cg = sh.prgb[i][0] * gc[0] + sh.prgb[i][1] * gc[1] + sh.prgb[i][2] * gc[2];
+                    const float cg = q0 * gc[0] + q1 * gc[1] + q2 * gc[2];
                     const float bg = B0 * gc[0] + B1 * gc[1] + B2 * gc[2];
                     const float dal = Tk * cg - bg / (1.0f - al) + ga * Ts / (1.0f - al);
                     v9[6] = al * Tk * gc[0];
                     v9[7] = al * Tk * gc[1];
                     v9[8] = al * Tk * gc[2];
-                    B0 += sh.prgb[i][0] * al * Tk;
-                    B1 += sh.prgb[i][1] * al * Tk;
-                    B2 += sh.prgb[i][2] * al * Tk;
+                    B0 += q0 * al * Tk;
+                    B1 += q1 * al * Tk;
+                    B2 += q2 * al * Tk;
                     Tc = Tk;
                     if (ao < 0.99f) {
                         v9[5] = dal * G;
                         const float dpw = raw < 0.0f ? dal * al : 0.0f;
-                        v9[0] = -dpw * (sh.pca[i] * dx + sh.pcb[i] * dy);
-                        v9[1] = -dpw * (sh.pcb[i] * dx + sh.pcc[i] * dy);
+                        v9[0] = -dpw * (ca * dx + cb * dy);
+                        v9[1] = -dpw * (cb * dx + cc * dy);
                         v9[2] = -0.5f * dpw * dx * dx;
                         v9[3] = -dpw * dx * dy;
                         v9[4] = -0.5f * dpw * dy * dy;
@@ -685,11 +767,13 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
                 }
                 if (__ballot(added) == 0) continue;
                 for (int a = 0; a < 9; ++a) {
-                    const float s9 = wave_sum(v9[a]);
-                    if (lane == 0) sh.acc[wid][j][a] += s9;
+                    const float s9 = wave_total(v9[a]);
+                    if (lane == k) acc9[a] += s9;
                 }
             }
         }
+        if (lane < n_s)
+            for (int a = 0; a < 9; ++a) sh.acc[wid][js][a] = acc9[a];
         const float lw = wave_sum(lsum);
         if (lane == 0) sh.red[wid] = lw;
         __syncthreads();
