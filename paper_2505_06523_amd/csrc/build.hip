@@ -394,7 +394,7 @@ void launch_gather_rows(hipStream_t st, const float *pos, const float *scale, co
 // wavefront are reduced across lanes and kept per wavefront, so every sum is
 // taken in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kLsThreads = 256;
+constexpr int kLsThreads = 1024;
 constexpr int kLsRes = 64;
 constexpr int kLsMaxO = 128;
 constexpr int kLsMaxS = 64;
@@ -408,7 +408,9 @@ struct LsShared {
     float pu[192], pv[192], pca[192], pcb[192], pcc[192], pop[192], prow[192], pz[192], prgb[192][3];
     uint8_t pvalid[192];
     uint8_t ord[192];
-    uint32_t n_o, n_s;
+    // the view's valid splats in depth order: originals at 0 .., fitted at
+    // 128 ..; (u, v, ca, cb), (cc, o, r, g), (b, row limit, -, -)
+    float4 sp1[192], sp2[192], sp3[192];
     float acc[kLsThreads / kWave][kLsMaxS][9];  // per wavefront: du dv dca dcb dcc dop dr dg db (per fitted index)
     float cam[12];                                // world-to-camera rows, eye
     float red[kLsThreads / kWave];
@@ -617,39 +619,24 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
                     if (sh.pvalid[base + j] && (sh.pz[base + j] < sh.pz[t] || (sh.pz[base + j] == sh.pz[t] && j < k)))
                         ++rank;
                 sh.ord[base + rank] = (uint8_t)k;
+                sh.sp1[base + rank] = make_float4(sh.pu[t], sh.pv[t], sh.pca[t], sh.pcb[t]);
+                sh.sp2[base + rank] = make_float4(sh.pcc[t], sh.pop[t], sh.prgb[t][0], sh.prgb[t][1]);
+                sh.sp3[base + rank] = make_float4(sh.prgb[t][2], sh.prow[t], 0.0f, 0.0f);
             }
         }
-        if (t == 0) {
-            uint32_t a = 0, b = 0;
-            for (uint32_t j = 0; j < no; ++j) a += sh.pvalid[j];
-            for (uint32_t j = 0; j < ns; ++j) b += sh.pvalid[kLsMaxO + j];
-            sh.n_o = a;
-            sh.n_s = b;
-        }
-        __syncthreads();
-        const int n_o = (int)sh.n_o, n_s = (int)sh.n_s;
-        // the view's splats in depth order, in registers: lane l holds the
-        // original depth slots l and 64 + l and the fitted depth slot l; the
-        // walks below read slot k of every lane with lane_value(., k)
-        float oU[2], oV[2], oA[2], oB[2], oC[2], oO[2], oR[2], oQ0[2], oQ1[2], oQ2[2];
+        const int n_o = __syncthreads_count((uint32_t)t < no && sh.pvalid[t]);
+        const int n_s = __syncthreads_count(t >= kLsMaxO && (uint32_t)(t - kLsMaxO) < ns && sh.pvalid[t]);
+        // row tests in registers (lane l: original slots l and 64 + l,
+        // fitted slot l); the walks read slot k's parameters from LDS, the
+        // same address in every lane
+        float oV[2], oR[2];
         for (int h = 0; h < 2; ++h) {
             const int slot = h * kWave + lane;
-            const int i = slot < n_o ? (int)sh.ord[slot] : 0;
-            oU[h] = sh.pu[i];
-            oV[h] = sh.pv[i];
-            oA[h] = sh.pca[i];
-            oB[h] = sh.pcb[i];
-            oC[h] = sh.pcc[i];
-            oO[h] = sh.pop[i];
-            oR[h] = slot < n_o ? sh.prow[i] : -1.0f;
-            oQ0[h] = sh.prgb[i][0];
-            oQ1[h] = sh.prgb[i][1];
-            oQ2[h] = sh.prgb[i][2];
+            oV[h] = slot < n_o ? sh.sp1[slot].y : 0.0f;
+            oR[h] = slot < n_o ? sh.sp3[slot].y : -1.0f;
         }
-        const int js = lane < n_s ? (int)sh.ord[kLsMaxO + lane] : 0, is = kLsMaxO + js;
-        const float sU = sh.pu[is], sV = sh.pv[is], sA = sh.pca[is], sB = sh.pcb[is], sC = sh.pcc[is],
-                    sO = sh.pop[is], sR = lane < n_s ? sh.prow[is] : -1.0f, sQ0 = sh.prgb[is][0],
-                    sQ1 = sh.prgb[is][1], sQ2 = sh.prgb[is][2];
+        const int js = lane < n_s ? (int)sh.ord[kLsMaxO + lane] : 0;
+        const float sV = lane < n_s ? sh.sp1[kLsMaxO + lane].y : 0.0f, sR = lane < n_s ? sh.sp3[kLsMaxO + lane].y : -1.0f;
         float acc9[9];
         for (int a = 0; a < 9; ++a) acc9[a] = 0.0f;  // gradient sums of fitted depth slot `lane`
         float lsum = 0.0f;
@@ -659,19 +646,19 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
             const float d0 = oV[0] - yc, d1 = oV[1] - yc, ds = sV - yc;
             const uint64_t mo[2] = {__ballot(d0 * d0 <= oR[0]), __ballot(d1 * d1 <= oR[1])};
             const uint64_t msf = __ballot(ds * ds <= sR);
-            // front-to-back compositing of one splat (the renderer's rule)
-            auto blend = [&](float u, float v, float ca, float cb, float cc, float op, float q0, float q1, float q2,
-                             float &T, float &c0, float &c1, float &c2, bool &live) -> bool {
-                const float dx = u - xc, dy = v - yc;
-                const float pw = fminf(0.0f, -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy);
-                const float al = fminf(0.99f, op * __expf(pw));
+            // front-to-back compositing of the splat in sorted slot q (the renderer's rule)
+            auto blend = [&](int q, float &T, float &c0, float &c1, float &c2, bool &live) -> bool {
+                const float4 p1 = sh.sp1[q], p2 = sh.sp2[q], p3 = sh.sp3[q];
+                const float dx = p1.x - xc, dy = p1.y - yc;
+                const float pw = fminf(0.0f, -0.5f * (p1.z * dx * dx + p2.x * dy * dy) - p1.w * dx * dy);
+                const float al = fminf(0.99f, p2.y * __expf(pw));
                 const bool take = live && al >= 1.0f / 255.0f;
                 const float Tn = T * (1.0f - al);
                 const bool stop = take && Tn < 1e-4f;
                 if (take && !stop) {
-                    c0 += al * T * q0;
-                    c1 += al * T * q1;
-                    c2 += al * T * q2;
+                    c0 += al * T * p2.z;
+                    c1 += al * T * p2.w;
+                    c2 += al * T * p3.x;
                     T = Tn;
                 }
                 if (stop) live = false;
@@ -686,9 +673,7 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
                     while (m && __ballot(live)) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
-                        blend(lane_value(oU[h], k), lane_value(oV[h], k), lane_value(oA[h], k), lane_value(oB[h], k),
-                              lane_value(oC[h], k), lane_value(oO[h], k), lane_value(oQ0[h], k), lane_value(oQ1[h], k),
-                              lane_value(oQ2[h], k), T, c0, c1, c2, live);
+                        blend(h * kWave + k, T, c0, c1, c2, live);
                     }
                 }
                 tgt[0] = c0;
@@ -704,10 +689,7 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
                 while (m && __ballot(live)) {
                     const int k = __builtin_ctzll(m);
                     m &= m - 1;
-                    if (blend(lane_value(sU, k), lane_value(sV, k), lane_value(sA, k), lane_value(sB, k),
-                              lane_value(sC, k), lane_value(sO, k), lane_value(sQ0, k), lane_value(sQ1, k),
-                              lane_value(sQ2, k), T, c0, c1, c2, live))
-                        kstop = k;
+                    if (blend(kLsMaxO + k, T, c0, c1, c2, live)) kstop = k;
                 }
                 res[0] = c0;
                 res[1] = c1;
@@ -733,9 +715,9 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
             while (m) {
                 const int k = 63 - __builtin_clzll(m);
                 m &= ~(1ull << k);
-                const float u = lane_value(sU, k), v = lane_value(sV, k), ca = lane_value(sA, k),
-                            cb = lane_value(sB, k), cc = lane_value(sC, k), op = lane_value(sO, k),
-                            q0 = lane_value(sQ0, k), q1 = lane_value(sQ1, k), q2 = lane_value(sQ2, k);
+                const float4 p1 = sh.sp1[kLsMaxO + k], p2 = sh.sp2[kLsMaxO + k], p3 = sh.sp3[kLsMaxO + k];
+                const float u = p1.x, v = p1.y, ca = p1.z, cb = p1.w, cc = p2.x, op = p2.y, q0 = p2.z, q1 = p2.w,
+                            q2 = p3.x;
                 const float dx = u - xc, dy = v - yc;
                 const float raw = -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy;
                 const float G = __expf(fminf(0.0f, raw));
@@ -777,14 +759,21 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
         const float lw = wave_sum(lsum);
         if (lane == 0) sh.red[wid] = lw;
         __syncthreads();
-        if (losses && t == 0) losses[(uint64_t)g * iters + it] = sh.red[0] + sh.red[1] + sh.red[2] + sh.red[3];
+        if (losses && t == 0) {
+            float l = 0.0f;
+            for (int w = 0; w < kLsThreads / kWave; ++w) l += sh.red[w];
+            losses[(uint64_t)g * iters + it] = l;
+        }
         // chain rule and Adam step, one thread per fitted Gaussian
         if ((uint32_t)t < ns) {
             const int k = t, i = kLsMaxO + k;
             float gd[9];
-            for (int a = 0; a < 9; ++a) {
-                gd[a] = sh.acc[0][k][a] + sh.acc[1][k][a] + sh.acc[2][k][a] + sh.acc[3][k][a];
-                sh.acc[0][k][a] = sh.acc[1][k][a] = sh.acc[2][k][a] = sh.acc[3][k][a] = 0.0f;
+            for (int a = 0; a < 9; ++a) {  // over the wavefronts in order
+                gd[a] = 0.0f;
+                for (int w = 0; w < kLsThreads / kWave; ++w) {
+                    gd[a] += sh.acc[w][k][a];
+                    sh.acc[w][k][a] = 0.0f;
+                }
             }
             float gp[kLsP];
             for (int a = 0; a < kLsP; ++a) gp[a] = 0.0f;
