@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
                     help="time the frames without any events (the roofline then comes from a second pass)")
+    ap.add_argument("--only", choices=["build", "stream"],
+                    help="run only the offline-build or the streaming measurement and print its JSON (for rocprofv3)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the warm-up and one pass of the timed V3DG frames (for rocprofv3: with --warmup 0 its "
                          "per-kernel averages cover exactly the launches of the roofline)")
@@ -435,6 +437,10 @@ def main():
     n_leaves = 1 << 16 if args.quick else 1 << 20
     log("generating asset (%d leaves, SH3)" % n_leaves)
     asset = sg.cached_asset(n_leaves, 3, 2)
+    if args.only:  # one side measurement alone, not the headline line
+        res = build_bench(v, asset, not args.no_cpu) if args.only == "build" else stream_bench(torch, v, sg, asset)
+        print(json.dumps({args.only: res}), flush=True)
+        return
     b_row = 4 * (3 + 3 + 4 + 1 + 3 * 16)
     cams = sg.orbit_cameras(64, 102)
     taus = [0.0, 1.0, 4.0, 16.0]

@@ -640,117 +640,179 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
         float acc9[9];
         for (int a = 0; a < 9; ++a) acc9[a] = 0.0f;  // gradient sums of fitted depth slot `lane`
         float lsum = 0.0f;
-        for (int rr = 0; rr < kLsRes / (kLsThreads / kWave); ++rr) {
-            const float yc = (float)(wid * (kLsRes / (kLsThreads / kWave)) + rr) + 0.5f, xc = (float)lane + 0.5f;
-            // depth slots whose splat reaches this row, as bit masks
-            const float d0 = oV[0] - yc, d1 = oV[1] - yc, ds = sV - yc;
-            const uint64_t mo[2] = {__ballot(d0 * d0 <= oR[0]), __ballot(d1 * d1 <= oR[1])};
-            const uint64_t msf = __ballot(ds * ds <= sR);
-            // front-to-back compositing of the splat in sorted slot q (the renderer's rule)
-            auto blend = [&](int q, float &T, float &c0, float &c1, float &c2, bool &live) -> bool {
-                const float4 p1 = sh.sp1[q], p2 = sh.sp2[q], p3 = sh.sp3[q];
-                const float dx = p1.x - xc, dy = p1.y - yc;
-                const float pw = fminf(0.0f, -0.5f * (p1.z * dx * dx + p2.x * dy * dy) - p1.w * dx * dy);
-                const float al = fminf(0.99f, p2.y * __expf(pw));
-                const bool take = live && al >= 1.0f / 255.0f;
-                const float Tn = T * (1.0f - al);
-                const bool stop = take && Tn < 1e-4f;
-                if (take && !stop) {
-                    c0 += al * T * p2.z;
-                    c1 += al * T * p2.w;
-                    c2 += al * T * p3.x;
-                    T = Tn;
-                }
-                if (stop) live = false;
-                return stop;
-            };
-            float tgt[4], res[4];
+        // the wavefront's kR rows are walked together: a splat's parameters
+        // are read once for all of them, and its gradient terms are summed over
+        // them in each lane before one wavefront sum
+        constexpr int kR = kLsRes / (kLsThreads / kWave);
+        const float xc = (float)lane + 0.5f;
+        float yc[kR];
+        uint64_t mo[kR][2], ms[kR], uo[2] = {0ull, 0ull}, us = 0ull;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {  // depth slots whose splat reaches row r, as bit masks
+            yc[r] = (float)(wid * kR + r) + 0.5f;
+            const float d0 = oV[0] - yc[r], d1 = oV[1] - yc[r], ds = sV - yc[r];
+            mo[r][0] = __ballot(d0 * d0 <= oR[0]);
+            mo[r][1] = __ballot(d1 * d1 <= oR[1]);
+            ms[r] = __ballot(ds * ds <= sR);
+            uo[0] |= mo[r][0];
+            uo[1] |= mo[r][1];
+            us |= ms[r];
+        }
+        // front-to-back compositing of one splat at one pixel (the renderer's rule)
+        auto blend = [&](const float4 &p1, const float4 &p2, const float4 &p3, float yr, float &T, float &c0,
+                         float &c1, float &c2, bool &live) -> bool {
+            const float dx = p1.x - xc, dy = p1.y - yr;
+            const float pw = fminf(0.0f, -0.5f * (p1.z * dx * dx + p2.x * dy * dy) - p1.w * dx * dy);
+            const float al = fminf(0.99f, p2.y * __expf(pw));
+            const bool take = live && al >= 1.0f / 255.0f;
+            const float Tn = T * (1.0f - al);
+            const bool stop = take && Tn < 1e-4f;
+            if (take && !stop) {
+                c0 += al * T * p2.z;
+                c1 += al * T * p2.w;
+                c2 += al * T * p3.x;
+                T = Tn;
+            }
+            if (stop) live = false;
+            return stop;
+        };
+        float gc0[kR], gc1[kR], gc2[kR], ga[kR], Ts[kR];
+        int kstop[kR];  // fitted depth slot where each pixel stopped
+        {
+            float tg0[kR], tg1[kR], tg2[kR], tga[kR];
             {  // the originals: the target
-                float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-                bool live = true;
+                float T[kR], c0[kR], c1[kR], c2[kR];
+                bool live[kR];
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    T[r] = 1.0f;
+                    c0[r] = c1[r] = c2[r] = 0.0f;
+                    live[r] = true;
+                }
+#pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    uint64_t m = mo[h];
-                    while (m && __ballot(live)) {
+                    uint64_t m = uo[h];
+                    while (m) {
+                        bool any = false;
+#pragma unroll
+                        for (int r = 0; r < kR; ++r) any |= live[r];
+                        if (__ballot(any) == 0) break;
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
-                        blend(h * kWave + k, T, c0, c1, c2, live);
+                        const float4 p1 = sh.sp1[h * kWave + k], p2 = sh.sp2[h * kWave + k], p3 = sh.sp3[h * kWave + k];
+#pragma unroll
+                        for (int r = 0; r < kR; ++r)
+                            if ((mo[r][h] >> k) & 1ull) blend(p1, p2, p3, yc[r], T[r], c0[r], c1[r], c2[r], live[r]);
                     }
                 }
-                tgt[0] = c0;
-                tgt[1] = c1;
-                tgt[2] = c2;
-                tgt[3] = 1.0f - T;
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    tg0[r] = c0[r];
+                    tg1[r] = c1[r];
+                    tg2[r] = c2[r];
+                    tga[r] = 1.0f - T[r];
+                }
             }
-            int kstop = n_s;  // depth slot where this pixel stopped
             {  // the fitted splats
-                float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-                bool live = true;
-                uint64_t m = msf;
-                while (m && __ballot(live)) {
+                float T[kR], c0[kR], c1[kR], c2[kR];
+                bool live[kR];
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    T[r] = 1.0f;
+                    c0[r] = c1[r] = c2[r] = 0.0f;
+                    live[r] = true;
+                    kstop[r] = n_s;
+                }
+                uint64_t m = us;
+                while (m) {
+                    bool any = false;
+#pragma unroll
+                    for (int r = 0; r < kR; ++r) any |= live[r];
+                    if (__ballot(any) == 0) break;
                     const int k = __builtin_ctzll(m);
                     m &= m - 1;
-                    if (blend(kLsMaxO + k, T, c0, c1, c2, live)) kstop = k;
+                    const float4 p1 = sh.sp1[kLsMaxO + k], p2 = sh.sp2[kLsMaxO + k], p3 = sh.sp3[kLsMaxO + k];
+#pragma unroll
+                    for (int r = 0; r < kR; ++r)
+                        if (((ms[r] >> k) & 1ull) && blend(p1, p2, p3, yc[r], T[r], c0[r], c1[r], c2[r], live[r]))
+                            kstop[r] = k;
                 }
-                res[0] = c0;
-                res[1] = c1;
-                res[2] = c2;
-                res[3] = 1.0f - T;
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {  // loss and the gradients of its L1 terms
+                    const float d[3] = {c0[r] - tg0[r], c1[r] - tg1[r], c2[r] - tg2[r]};
+                    float g[3];
+                    for (int a = 0; a < 3; ++a) {
+                        g[a] = d[a] > 0.0f ? wr : (d[a] < 0.0f ? -wr : 0.0f);
+                        lsum += fabsf(d[a]) * wr;
+                    }
+                    gc0[r] = g[0];
+                    gc1[r] = g[1];
+                    gc2[r] = g[2];
+                    const float dfa = (1.0f - T[r]) - tga[r];
+                    ga[r] = dfa > 0.0f ? wa : (dfa < 0.0f ? -wa : 0.0f);
+                    lsum += fabsf(dfa) * wa;
+                    Ts[r] = T[r];
+                }
             }
-            const float Ts = 1.0f - res[3];
-            float gc[3];
-            for (int a = 0; a < 3; ++a) {
-                const float df = res[a] - tgt[a];
-                gc[a] = df > 0.0f ? wr : (df < 0.0f ? -wr : 0.0f);
-                lsum += fabsf(df) * wr;
+        }
+        // back-to-front over the fitted splats the rows reach, up to the last
+        // slot any pixel of the wavefront blended
+        int kmax = kstop[0];
+#pragma unroll
+        for (int r = 1; r < kR; ++r) kmax = max(kmax, kstop[r]);
+        for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
+        {
+            float Tc[kR], B0[kR], B1[kR], B2[kR];
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                Tc[r] = Ts[r];
+                B0[r] = B1[r] = B2[r] = 0.0f;
             }
-            const float dfa = res[3] - tgt[3];
-            const float ga = dfa > 0.0f ? wa : (dfa < 0.0f ? -wa : 0.0f);
-            lsum += fabsf(dfa) * wa;
-            // back-to-front over the fitted splats this row reaches, up to the
-            // last slot any pixel of the wavefront blended
-            int kmax = kstop;
-            for (int o = kWave / 2; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, kWave));
-            uint64_t m = kmax >= kWave ? msf : (msf & ((1ull << kmax) - 1ull));
-            float Tc = Ts, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f;
+            uint64_t m = kmax >= kWave ? us : (us & ((1ull << kmax) - 1ull));
             while (m) {
                 const int k = 63 - __builtin_clzll(m);
                 m &= ~(1ull << k);
                 const float4 p1 = sh.sp1[kLsMaxO + k], p2 = sh.sp2[kLsMaxO + k], p3 = sh.sp3[kLsMaxO + k];
-                const float u = p1.x, v = p1.y, ca = p1.z, cb = p1.w, cc = p2.x, op = p2.y, q0 = p2.z, q1 = p2.w,
-                            q2 = p3.x;
-                const float dx = u - xc, dy = v - yc;
-                const float raw = -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy;
-                const float G = __expf(fminf(0.0f, raw));
-                const float ao = op * G;
-                const float al = fminf(0.99f, ao);
-                const bool added = k < kstop && al >= 1.0f / 255.0f;
-                float v9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-                if (added) {
-                    const float Tk = Tc / (1.0f - al);
-                    const float cg = q0 * gc[0] + q1 * gc[1] + q2 * gc[2];
-                    const float bg = B0 * gc[0] + B1 * gc[1] + B2 * gc[2];
-                    const float dal = Tk * cg - bg / (1.0f - al) + ga * Ts / (1.0f - al);
-                    v9[6] = al * Tk * gc[0];
-                    v9[7] = al * Tk * gc[1];
-                    v9[8] = al * Tk * gc[2];
-                    B0 += q0 * al * Tk;
-                    B1 += q1 * al * Tk;
-                    B2 += q2 * al * Tk;
-                    Tc = Tk;
-                    if (ao < 0.99f) {
-                        v9[5] = dal * G;
-                        const float dpw = raw < 0.0f ? dal * al : 0.0f;
-                        v9[0] = -dpw * (ca * dx + cb * dy);
-                        v9[1] = -dpw * (cb * dx + cc * dy);
-                        v9[2] = -0.5f * dpw * dx * dx;
-                        v9[3] = -dpw * dx * dy;
-                        v9[4] = -0.5f * dpw * dy * dy;
+                const float u = p1.x, ca = p1.z, cb = p1.w, cc = p2.x, op = p2.y, q0 = p2.z, q1 = p2.w, q2 = p3.x;
+                float s9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                bool any_added = false;
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    if (!((ms[r] >> k) & 1ull)) continue;
+                    const float dx = u - xc, dy = p1.y - yc[r];
+                    const float raw = -0.5f * (ca * dx * dx + cc * dy * dy) - cb * dx * dy;
+                    const float G = __expf(fminf(0.0f, raw));
+                    const float ao = op * G;
+                    const float al = fminf(0.99f, ao);
+                    const bool added = k < kstop[r] && al >= 1.0f / 255.0f;
+                    if (added) {
+                        const float Tk = Tc[r] / (1.0f - al);
+                        const float cg = q0 * gc0[r] + q1 * gc1[r] + q2 * gc2[r];
+                        const float bg = B0[r] * gc0[r] + B1[r] * gc1[r] + B2[r] * gc2[r];
+                        const float dal = Tk * cg - bg / (1.0f - al) + ga[r] * Ts[r] / (1.0f - al);
+                        s9[6] += al * Tk * gc0[r];
+                        s9[7] += al * Tk * gc1[r];
+                        s9[8] += al * Tk * gc2[r];
+                        B0[r] += q0 * al * Tk;
+                        B1[r] += q1 * al * Tk;
+                        B2[r] += q2 * al * Tk;
+                        Tc[r] = Tk;
+                        if (ao < 0.99f) {
+                            s9[5] += dal * G;
+                            const float dpw = raw < 0.0f ? dal * al : 0.0f;
+                            s9[0] += -dpw * (ca * dx + cb * dy);
+                            s9[1] += -dpw * (cb * dx + cc * dy);
+                            s9[2] += -0.5f * dpw * dx * dx;
+                            s9[3] += -dpw * dx * dy;
+                            s9[4] += -0.5f * dpw * dy * dy;
+                        }
                     }
+                    any_added |= added;
                 }
-                if (__ballot(added) == 0) continue;
+                if (__ballot(any_added) == 0) continue;
                 for (int a = 0; a < 9; ++a) {
-                    const float s9 = wave_total(v9[a]);
-                    if (lane == k) acc9[a] += s9;
+                    const float tot = wave_total(s9[a]);
+                    if (lane == k) acc9[a] += tot;
                 }
             }
         }
