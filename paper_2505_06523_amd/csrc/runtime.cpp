@@ -944,12 +944,23 @@ int page_in(v3dg_scene *s, const uint32_t *gid, const uint32_t *off, uint32_t n,
                         s->page_bytes);
             s->ups_h[j] = make_uint4(k, s->page_of[k], s->h_count[k], 0u);
         }
-        HIP_TRY(hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice, s->stream));
-        HIP_TRY(hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, s->stream));
-        launch_stream_scatter(s->stream, s->stage_d, s->ups_d, m, s->page_bytes, s->geo_bytes, s->sh_bytes, s->n_sh,
-                              s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride, s->rowinfo);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipStreamSynchronize(s->stream));  // the staging buffers are reused
+        hipError_t e = hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice,
+                                      s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) {
+            launch_stream_scatter(s->stream, s->stage_d, s->ups_d, m, s->page_bytes, s->geo_bytes, s->sh_bytes,
+                                  s->n_sh, s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride, s->rowinfo);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the staging buffers are reused
+        if (e != hipSuccess) {  // the pages of this chunk and the rest hold nothing valid: free them
+            for (size_t q = i; q < miss.size(); ++q) {
+                const uint32_t k = miss[q];
+                s->cluster_of[s->page_of[k]] = kNoPage;
+                s->page_of[k] = kNoPage;
+            }
+            return fail(V3DG_ERR_HIP, "paging in clusters failed: %s", hipGetErrorString(e));
+        }
     }
     s->sstats.frames += 1;
     s->sstats.pages_in += miss.size();
