@@ -239,3 +239,44 @@ def test_fitted_build_equals_the_local_splat_entry_point(torch):
         np.testing.assert_allclose(g["fit_loss"][l - 1], losses[lvl == l].astype(np.float64).mean(0), rtol=1e-5)
     _say("fitted build: %d groups, layer-1 loss %.4f -> %.4f" % (len(groups), g["fit_loss"][0, 0],
                                                                  g["fit_loss"][0, -1]))
+
+
+def test_fitted_build_full_size_sampled(torch):
+    """The benchmark asset's 1M leaves built with local splatting (16 views
+    per group, the launch shape of the 640-view build): sampled groups of the
+    first, a middle and the top layer, taken on the GPU's own inputs, keep the
+    oracle's kept set and sphere bit for bit and follow the FP64 oracle's fit
+    within half an Adam step."""
+    from oracle import local_splat as ls
+    iters = 16
+    dirs = _unit_dirs(iters, 29)
+    a = sg.cached_asset(1 << 20, 3, 2)
+    L = a.n_leaf_rows
+    g = v.build_bundle(a.pos[:L], a.scale[:L], a.rot[:L], a.opacity[:L], a.sh[:L], 64, fit_iters=iters,
+                       view_dirs=dirs)
+    nl = g["n_leaf_clusters"]
+    lv = g["level"]
+    picks = []
+    for layer in (1, int(lv.max()) // 2, int(lv.max())):
+        ids = np.flatnonzero(lv == layer)
+        picks += list(ids[np.linspace(0, len(ids) - 1, 2).astype(int)]) if len(ids) > 1 else list(ids)
+    worst = 0.0
+    for p in sorted(set(int(x) for x in picks)):
+        idx, kids = _group_of(g, p)
+        rows = _rows_of(g, idx)
+        init = _halved(g, idx)
+        mine = np.arange(g["first_row"][p], g["first_row"][p] + g["count"][p])
+        np.testing.assert_array_equal(g["src"][mine], init["src"])
+        sph = ob.group_sphere(rows["pos"], [g["self_sphere"][c] for c in kids])
+        np.testing.assert_array_equal(g["self_sphere"][p], sph)
+        vs = ob.view_sphere(rows, sph)
+        out, _, _ = ls.local_splat(rows, init, vs[:3].astype(np.float64), float(vs[3]), dirs.astype(np.float64), iters)
+        e_pos = np.abs(g["pos"][mine] - out["pos"]).max() / LR["pos"]
+        e_ls = np.abs(np.log(g["scale"][mine]) - np.log(out["scale"])).max() / LR["log_scale"]
+        lo = lambda o: np.log(o / (1 - o))
+        e_op = np.abs(lo(g["opacity"][mine].astype(np.float64)) - lo(out["opacity"])).max() / LR["logit"]
+        e_dc = np.abs(g["sh"][mine][:, 0, :] - out["sh"][:, 0, :]).max() / LR["dc"]
+        worst = max(worst, e_pos, e_ls, e_op, e_dc)
+        assert max(e_pos, e_ls, e_op, e_dc) < 0.5, (p, lv[p], e_pos, e_ls, e_op, e_dc)
+    _say("1M fitted build: %d sampled groups (layers 1 .. %d) within %.2e Adam steps of the oracle"
+         % (len(set(picks)), int(lv.max()), worst))

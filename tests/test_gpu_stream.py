@@ -143,3 +143,31 @@ def test_a_paged_out_selection_is_refused(torch, world):
     assert torch.equal(img_far, img2) and torch.equal(img2, res.render(far, s_ref2).clone())
     st.close()
     res.close()
+
+
+def test_streamed_walk_full_size(torch):
+    """The benchmark asset (1M leaves, SH3) on 12 frames of the close walk at
+    1920x1080, culling on, streamed through a pool of 7,430 clusters (1.25
+    times the walk's largest cut): every image equals the resident scene's bit
+    for bit, with pages evicted on the way."""
+    a = sg.cached_asset(1 << 20, 3, 2)
+    cams = sg.tangent_path_cameras(100)[::8]
+    res = v.Scene(a)
+    st = v.Scene(a, pool_clusters=7430)
+    res.set_culling(True)
+    st.set_culling(True)
+    s0 = s1 = None
+    for i, cam in enumerate(cams):
+        s0 = res.select(cam, 1.0, s0)
+        s1 = st.select(cam, 1.0, s1)
+        assert np.array_equal(s0.ids(), s1.ids()), i
+        img0 = res.render(cam, s0).clone()
+        img1 = st.render(cam, s1).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(img0, img1), (i, float((img0 - img1).abs().max()))
+    stats = st.stream_stats()
+    _say("1M walk streamed: %d frames equal, %d pages in, %d evictions" % (len(cams), stats["pages_in"],
+                                                                         stats["evictions"]))
+    assert stats["evictions"] > 0
+    res.close()
+    st.close()
