@@ -242,8 +242,9 @@ void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
 constexpr int kSortPart = kSortThreads * kSortItems;  // partition (also the unit of look-back capacity)
-constexpr int kSortItemsWide = 32;      // keys per thread of wide partitions
+constexpr int kSortItemsWide = 24;      // keys per thread of wide partitions
 constexpr int kSortPartWide = kSortThreads * kSortItemsWide;
+static_assert(kSortPartWide >= kSortPart, "look-back status is sized for partitions of kSortPart keys");
 constexpr uint64_t kSortWideFrom = 1u << 22;  // sorts of at least this many keys use wide partitions
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 256;
