@@ -37,8 +37,9 @@ BLEND_OPS_PER_PAIR = 23
 # HBM bytes per frame of the blend stage on this workload, from rocprofv3
 # FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the 256 timed frames
 # (profiles/hbm_counters_1M_sh3_1080p.md).  Valid only for the blending source
-# they were taken on: the bench reports null once blend.hip has changed.
-BLEND_TRAFFIC = dict(bytes_per_frame=759.5e6, blend_source_sha256_16="f81570bdd25a1645")
+# they were taken on (blend.hip and the constants of v3dg_internal.h, such as
+# the chunk sizes): the bench reports null once either has changed.
+BLEND_TRAFFIC = dict(bytes_per_frame=1066.8e6, blend_source_sha256_16="cb81928e4fdf5ac3")
 
 
 def log(*a):
@@ -108,8 +109,11 @@ def measured_blend_traffic(args):
     """HBM bytes per blend-stage launch from the committed counter runs, or None
     when the workload or the blending source differ from what they measured."""
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_06523_amd", "csrc", "blend.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_06523_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("blend.hip", "v3dg_internal.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    sha = h.hexdigest()[:16]
     if args.quick or args.steps != 256 or sha != BLEND_TRAFFIC["blend_source_sha256_16"]:
         return None
     return BLEND_TRAFFIC["bytes_per_frame"]

@@ -260,7 +260,7 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide);
 // Chunks of long tile lists (blending): a list of L > kChunkFirst keys is
 // cut into a first chunk of kChunkFirst keys and further chunks of kChunk.
-constexpr int kChunk = 2048;            // keys per chunk of a long tile list after the first
+constexpr int kChunk = 1024;            // keys per chunk of a long tile list after the first
 constexpr int kChunkFirst = 4096;       // keys of the first chunk (walked by pass 1)
 constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whole
 __device__ __forceinline__ uint32_t n_chunks(uint32_t L)
