@@ -526,7 +526,11 @@ __global__ void __launch_bounds__(kLsThreads) local_splat_kernel(
         if (t == 0) atomicOr(err, 2u);
         return;
     }
-    if (ns == 0) return;
+    if (ns == 0) {  // nothing to fit: zero losses
+        if (losses)
+            for (uint32_t it = (uint32_t)t; it < iters; it += kLsThreads) losses[(uint64_t)g * iters + it] = 0.0f;
+        return;
+    }
     if ((uint32_t)t < no) {
         const uint64_t r = orows ? orows[of + t] : of + t;
         for (int a = 0; a < 3; ++a) {

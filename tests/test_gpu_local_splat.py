@@ -111,3 +111,20 @@ def test_batched_groups_equal_single_groups(torch):
         for k in o1:
             np.testing.assert_array_equal(out[k][a:a + n], o1[k])
         np.testing.assert_array_equal(lb[i], l1[0])
+
+
+def test_empty_groups_give_zero_losses(torch):
+    """A group with no fitted Gaussians fits nothing and reports zero losses;
+    the other groups of the launch are unaffected."""
+    g = _group(40, 13)
+    f = _halve(g)
+    c, r = _sphere(g)
+    sph = (c[0], c[1], c[2], r)
+    n_f = len(f["opacity"])
+    out, lb, _ = v.local_splat([(0, 40, 0, 0, sph), (0, 40, 0, n_f, sph), (0, 40, n_f, 0, sph)], _rows(g), _rows(f),
+                               _dirs(6, 2), 6)
+    o1, l1, _ = v.local_splat([(0, 40, 0, n_f, sph)], _rows(g), _rows(f), _dirs(6, 2), 6)
+    assert (lb[0] == 0).all() and (lb[2] == 0).all()
+    np.testing.assert_array_equal(lb[1], l1[0])
+    for k in o1:
+        np.testing.assert_array_equal(out[k], o1[k])
