@@ -161,6 +161,7 @@ struct Ctx {
     uint2 *rect = nullptr;
     uint32_t *tiles = nullptr;
     uint32_t *offsets = nullptr;
+    uint32_t *big = nullptr;  // splats emitted by the large-splat kernel
     uint32_t *dkey[2] = {nullptr, nullptr};
     uint32_t *dval[2] = {nullptr, nullptr};
     uint32_t *rclear = nullptr;  // counters + scan look-back + tile ranges, cleared every frame
@@ -465,6 +466,7 @@ void ctx_free_slots(Ctx *c)
     dev_free(c->rect);
     dev_free(c->tiles);
     dev_free(c->offsets);
+    dev_free(c->big);
     dev_free(c->rclear);
     c->ws_slots = 0;
     c->tiles_cap = 0;
@@ -525,6 +527,7 @@ int ensure_slots(Ctx *c, uint64_t n)
     if ((rc = dev_alloc(&c->rect, n))) return rc;
     if ((rc = dev_alloc(&c->tiles, n))) return rc;
     if ((rc = dev_alloc(&c->offsets, n))) return rc;
+    if ((rc = dev_alloc(&c->big, n))) return rc;
     for (int b = 0; b < 2; ++b) {
         if ((rc = dev_alloc(&c->dkey[b], n))) return rc;
         if ((rc = dev_alloc(&c->dval[b], n))) return rc;
@@ -656,7 +659,8 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
     {
         Stage st(c, V3DG_STAGE_EMIT);
         launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys,
-                          tpasses, kb[0], c->vals[0], c->rcounters + kRenHist, c->rcounters + kRenErr);
+                          tpasses, kb[0], c->vals[0], c->rcounters + kRenHist, c->big, c->rcounters + kRenBig,
+                          c->rcounters + kRenErr);
     }
     if (KL > 0) run_sort<KT>(c, kb, c->vals, k_dev, KL, key_bits, 4, buf, passes, true);
     {

@@ -325,12 +325,19 @@ __device__ __forceinline__ void put_key(EmitShared &sh, bool staged, uint64_t o,
 }
 
 // KT: uint16_t when every tile id fits in 16 bits, else uint32_t
+// Splats of more than kBigKeys keys are left to emit_big_kernel: the
+// emission kernel lists them (their rank j) in big[], counted in *n_big.  A
+// workgroup that lists one spans more than kStage keys, so it is never staged
+// and the two kernels never write the same keys.
+constexpr uint32_t kBigKeys = kStage;
+
 template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
     const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
     const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, int passes,
-    KT *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
+    KT *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *__restrict__ big,
+    uint32_t *n_big, uint32_t *err)
 {
     __shared__ EmitShared sh;
     const uint32_t n = min(*n_dev, max_n);
@@ -378,11 +385,13 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
         }
         if (o != end) atomicOr(err, kErrOverflow);  // counting and emission disagree
     }
+    // the largest splats: listed for emit_big_kernel
+    if (nt > kBigKeys) big[atomicAdd(n_big, 1u)] = j;
     // larger splats: the wavefront writes them one after another
-    uint64_t big = __ballot(nt > kSmallKeys);
-    while (big) {
-        const int L = __ffsll((unsigned long long)big) - 1;
-        big &= big - 1;
+    uint64_t mid = __ballot(nt > kSmallKeys && nt <= kBigKeys);
+    while (mid) {
+        const int L = __ffsll((unsigned long long)mid) - 1;
+        mid &= mid - 1;
         const uint32_t bt = __shfl(t, L, kWave);
         const uint32_t bn = __shfl(nt, L, kWave);
         uint64_t bo = ((uint64_t)__shfl((uint32_t)(off >> 32), L, kWave) << 32) | __shfl((uint32_t)off, L, kWave);
@@ -452,16 +461,94 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
             if (sh.h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], sh.h[(p - 1) * 256 + i]);
 }
 
+// The listed splats, one workgroup at a time per splat: the threads take its
+// tile rows 256 at a time, a workgroup scan of the row lengths places the rows,
+// and all threads write the keys (key q lies in the last row whose prefix is
+// <= q).  Digit histograms as in emit32_kernel.
+template <typename KT>
+__global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
+    const uint32_t *__restrict__ n_big, const uint32_t *__restrict__ big, const uint32_t *__restrict__ order,
+    const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
+    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, int passes, KT *__restrict__ keys,
+    uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
+{
+    __shared__ uint32_t s_d0[257], s_h[2 * 256], s_all, s_tmp[4];
+    __shared__ uint32_t s_pre[kEmitThreads], s_base[kEmitThreads];
+    const uint32_t nb = *n_big;
+    if (blockIdx.x >= nb) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 257; i += kEmitThreads) s_d0[i] = 0u;
+    for (int i = tid; i < 2 * 256; i += kEmitThreads) s_h[i] = 0u;
+    if (tid == 0) s_all = 0u;
+    __syncthreads();
+    const uint32_t tiles_x = fd->cam.tiles_x;
+    for (uint32_t e = blockIdx.x; e < nb; e += gridDim.x) {
+        const uint32_t j = big[e], t = order[j], nt = tiles[t];
+        const uint64_t off = offsets[j];
+        const uint2 rc = rect[t];
+        const BinRec b = bin[t];
+        const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
+        uint64_t o = off;
+        for (uint32_t rb = ty0; rb <= ty1; rb += kEmitThreads) {
+            const uint32_t ty = rb + (uint32_t)tid;
+            uint32_t lo = 0, len = 0;
+            if (ty <= ty1) {
+                uint32_t hi;
+                if (tile_row_span(b, ty, tx0, tx1, &lo, &hi)) {
+                    len = hi - lo + 1;
+                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
+                }
+            }
+            uint32_t total;
+            const uint32_t pre = block_excl_scan_256(len, s_tmp, &total);
+            s_pre[tid] = pre;
+            s_base[tid] = ty * tiles_x + lo;
+            __syncthreads();
+            for (uint32_t q = (uint32_t)tid; q < total; q += kEmitThreads) {
+                uint32_t r = 0;
+#pragma unroll
+                for (uint32_t step = kEmitThreads / 2; step > 0; step >>= 1)
+                    if (s_pre[r + step] <= q) r += step;
+                if (o + q < off + nt) {
+                    keys[o + q] = (KT)(s_base[r] + (q - s_pre[r]));
+                    vals[o + q] = t;
+                }
+            }
+            __syncthreads();
+            o += total;
+        }
+        if (o != off + nt && tid == 0) atomicOr(err, kErrOverflow);  // counting and emission disagree
+    }
+    __syncthreads();
+    if (tid < kWave) {
+        uint32_t run = 0;
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t v = s_d0[c * kWave + tid];
+            const uint32_t incl = wave_incl_scan_u32(v);
+            const uint32_t cntd = run + incl + s_all;
+            if (cntd) atomicAdd(&hist[c * kWave + tid], cntd);
+            run += __shfl(incl, kWave - 1, kWave);
+        }
+    }
+    for (int p = 1; p < passes; ++p)
+        for (int i = tid; i < 256; i += kEmitThreads)
+            if (s_h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], s_h[(p - 1) * 256 + i]);
+}
+
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
                    const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
                    const FrameDev *fd, uint64_t key_cap, int passes, KT *keys, uint32_t *vals, uint32_t *hist,
-                   uint32_t *err)
+                   uint32_t *big, uint32_t *n_big, uint32_t *err)
 {
     if (max_n == 0) return;
     const uint32_t blocks = (uint32_t)((max_n + kEmitThreads - 1) / kEmitThreads);
     hipLaunchKernelGGL(emit32_kernel<KT>, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order,
-                       tiles, offsets, rect, bin, fd, key_cap, passes, keys, vals, hist, err);
+                       tiles, offsets, rect, bin, fd, key_cap, passes, keys, vals, hist, big, n_big, err);
+    // a fixed grid walks the list (any number of its slots may be large)
+    const uint32_t bblocks = (uint32_t)(max_n < 2048 ? max_n : 2048);
+    hipLaunchKernelGGL(emit_big_kernel<KT>, dim3(bblocks), dim3(kEmitThreads), 0, st, n_big, big, order, tiles,
+                       offsets, rect, bin, fd, passes, keys, vals, hist, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -750,10 +837,10 @@ void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, in
 
 template void launch_emit32<uint16_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
                                       const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t, int,
-                                      uint16_t *, uint32_t *, uint32_t *, uint32_t *);
+                                      uint16_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *);
 template void launch_emit32<uint32_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
                                       const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t, int,
-                                      uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+                                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *);
 template void launch_sort_hist<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *);

@@ -86,6 +86,7 @@ enum RenderCounter : int {
     kRenHist = 32,        // 8 passes x 256 bins
     kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
     kRenKeysEff = 32 + 12 * 256,   // keys the frame's buffers hold: min(total, capacity)
+    kRenBig = 32 + 12 * 256 + 1,   // splats left to the large-splat emission
     kRenCounters = 32 + 12 * 256 + 32
 };
 
@@ -234,11 +235,13 @@ void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 // digit histograms of the tile sort (passes <= 3) accumulated into hist.
 // KT = uint16_t for grids of at most kTileKey16Max tiles, else uint32_t.
 constexpr uint32_t kTileKey16Max = 1u << 16;
+// (splats of more than 2048 keys are listed in big[] (n_big: a cleared
+// counter; big: max_n entries) and emitted by one workgroup each)
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
                    const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
                    const FrameDev *fd, uint64_t key_cap, int passes, KT *keys, uint32_t *vals, uint32_t *hist,
-                   uint32_t *err);
+                   uint32_t *big, uint32_t *n_big, uint32_t *err);
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
 constexpr int kSortPart = kSortThreads * kSortItems;  // partition (also the unit of look-back capacity)
