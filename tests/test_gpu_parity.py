@@ -283,7 +283,7 @@ def test_long_tile_lists_chunked_blending(torch, opacity, seed):
     keys, _ = sc.sorted_keys()
     per_tile = np.bincount((keys >> np.uint64(32)).astype(np.int64))
     _say("long lists: keys %d, longest tile list %d" % (st["n_keys"], per_tile.max()))
-    assert per_tile.max() > 10 * 1024  # a first chunk of 4096 keys and at least three more of 2048
+    assert per_tile.max() > 10 * 1024  # a first chunk of 4096 keys and at least six more of 1024
     ref, amb, _ = oracle.render(a, T, cam, sel.ids())
     check_image(img, ref, amb, "stacked o=%s" % (opacity,))
     sc.set_sort_mode(v.V3DG_SORT_KEYS64)
@@ -377,7 +377,7 @@ def test_c2_selection_bitexact_all_cameras(c2):
 
 
 def test_c2_frame_keys_wide_partitions(c2, torch):
-    """A frame with more than 4M keys: the tile sort then uses 8192-key partitions."""
+    """A frame with more than 4M keys: the tile sort then uses its wide (6144-key) partitions."""
     a, sc = c2
     for cam in sg.orbit_cameras(64, 102):
         sel = sc.select(cam, 1.0)
@@ -432,4 +432,44 @@ def test_c3_selection_bitexact_flythrough(c2, torch):
         assert np.array_equal(sel.ids(), ref), f
         nc, ng = sel.info()
         _say("c3 frame %d: %d clusters, %d Gaussians selected" % (f, nc, ng))
+    sc.close()
+
+
+def test_large_splats_and_32bit_tile_ids(torch):
+    """A 4160 x 4160 image (67,600 tiles: 32-bit tile ids) of the c1-sized
+    asset seen from close by, so that near splats cover thousands of tiles and
+    go through the large-splat emission: the image and the sorted keys equal
+    the 64-bit-key mode (whose emission has no large-splat path) bit for bit,
+    and sampled pixels match the oracle."""
+    a = sg.make_asset(16384, 3, 41)
+    T = sg.identity_instances(1)
+    sc = v.Scene(a, T)
+    cam = sg.look_at((0.35, -0.3, 0.25), (0, 0, 0), 4160, 4160, 1.4)
+    sel = sc.select(cam, 1.0)
+    sc.set_sort_mode(v.V3DG_SORT_KEYS64)
+    i64 = sc.render(cam, sel).clone()
+    k64, v64 = sc.sorted_keys()
+    sc.set_sort_mode(v.V3DG_SORT_DEPTH_FIRST)
+    idf = sc.render(cam, sel).clone()
+    kdf, vdf = sc.sorted_keys()
+    st = sc.frame_stats()
+    torch.cuda.synchronize()
+    assert st["n_tiles"] == 260 * 260 and st["key_bits"] > 16
+    # splats with more than 2048 tiles exist in this frame
+    proj = sc.projection()
+    tiles = np.asarray(proj["tiles"])
+    n_big = int((tiles > 2048).sum())
+    assert n_big > 0
+    assert np.array_equal(k64, kdf) and np.array_equal(v64, vdf)
+    assert torch.equal(i64, idf)
+    img = idf.cpu().numpy()
+    rng = np.random.default_rng(5)
+    pix = np.stack([rng.integers(0, cam.width, 2000), rng.integers(0, cam.height, 2000)], axis=1).astype(np.uint32)
+    ref, amb, _ = oracle.render_pixels(a, T, cam, sel.ids(), pix)
+    got = img[pix[:, 1], pix[:, 0]]
+    ok = amb == 0
+    err = np.abs(got - ref)[ok].max()
+    _say("4160x4160 close view: %d splats over 2048 tiles, %d keys, sampled max_abs %.3g"
+         % (n_big, st["n_keys"], err))
+    assert err <= MAX_ABS and psnr(got[None], ref[None]) >= MIN_PSNR
     sc.close()
