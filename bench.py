@@ -385,19 +385,20 @@ def stream_bench(torch, v, sg, asset):
         sc.set_culling(True)
         used, pages, equal = [], [], True
         sel = None
-        ms = []
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fr]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for cam, tau in fr:
-            a = time.perf_counter()
+        for i, (cam, tau) in enumerate(fr):  # no host wait between frames, as for the resident scene
+            ev[i][0].record()
             sel = sc.select(cam, tau, sel)
             sc.render(cam, sel, img)
-            torch.cuda.synchronize()
-            ms.append(1e3 * (time.perf_counter() - a))
-            st = sc.stream_stats()
+            ev[i][1].record()
+            st = sc.stream_stats()  # host-side counters
             used.append(st["last_resident_used"])
             pages.append(st["last_pages_in"])
+        torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        ms = [x.elapsed_time(y) for x, y in ev]
         for cam, tau in fr[::10]:  # bit-equal images against the resident scene
             sel = sc.select(cam, tau, sel)
             sc.render(cam, sel, img)

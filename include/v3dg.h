@@ -147,11 +147,14 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *desc, const double *instances
  * pool of pool_clusters pages of 64 rows (1 <= pool_clusters < 2^26; a
  * larger pool than the scene's cluster count is cut to it; 0 loads the rows
  * resident, as v3dg_load_hierarchy).  Cluster tables, spheres and instances
- * stay resident.  v3dg_select reads the cut back (it synchronises the stream),
- * keeps the resident clusters it uses, and pages in the others in place of
- * the least recently used pages that this cut does not use: the page images
- * are staged in pinned host memory, copied in one transfer per 2048 clusters
- * and scattered into their pages on the scene's stream.  Images equal those of
+ * stay resident.  v3dg_select runs on a stream of the scene's own, once the
+ * previous render has projected its Gaussians; it reads the cut back (waiting
+ * for that stream only, so the previous render's later stages go on), keeps
+ * the resident clusters it uses, and pages in the others in place of the
+ * least recently used pages that this cut does not use: the page images are
+ * staged in pinned host memory, copied in one transfer per 2048 clusters and
+ * scattered into their pages.  Work enqueued on the scene's stream after the
+ * select waits for it on the device.  Images equal those of
  * the resident scene bit for bit.  A cut that needs more clusters than the
  * pool holds fails with V3DG_ERR_CAPACITY and pages nothing.  A selection is
  * renderable until a later select pages out one of its clusters; rendering it

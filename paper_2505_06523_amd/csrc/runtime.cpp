@@ -208,6 +208,9 @@ struct v3dg_selection {
 };
 
 constexpr uint32_t kNoPage = 0xffffffffu;
+// a streamed frame's own copy of its slot count, among the spare render counters
+constexpr int kRenSlots = kRenBig + 1;
+static_assert(kRenSlots < kRenCounters, "render counter out of range");
 
 struct v3dg_scene : Ctx {
     uint32_t NC = 0, n_rows = 0, sh_degree = 0, n_inst = 0;
@@ -243,6 +246,11 @@ struct v3dg_scene : Ctx {
     uint4 *ups_h = nullptr, *ups_d = nullptr;
     std::vector<uint32_t> cut_gid, cut_off;
     v3dg_stream_stats sstats{};
+    // selects of a streamed scene run on sel_stream, after the projection of
+    // the frame before (ev_proj) and before the render that follows (ev_sel),
+    // so that their read-back and paging overlap that frame's later stages
+    hipStream_t sel_stream = nullptr;
+    hipEvent_t ev_proj = nullptr, ev_sel = nullptr;
     Attribs attribs() const { return Attribs{pos_planes, geo_planes, sh_planes, plane_stride}; }
 };
 
@@ -252,18 +260,19 @@ namespace {
 struct Stage {
     Ctx *s;
     int stage;
+    hipStream_t q;  // the stream the stage's launches go to
     hipEvent_t b = nullptr;
-    Stage(Ctx *sc, int st) : s(sc), stage(st)
+    Stage(Ctx *sc, int st, hipStream_t on = nullptr) : s(sc), stage(st), q(on ? on : sc->stream)
     {
         if (!(s->profiling >> stage & 1u)) return;
         hipEvent_t a = take();
         b = take();
-        (void)hipEventRecord(a, s->stream);
+        (void)hipEventRecord(a, q);
         s->prof.push_back({stage, a, b});
     }
     ~Stage()
     {
-        if (b) (void)hipEventRecord(b, s->stream);
+        if (b) (void)hipEventRecord(b, q);
     }
     hipEvent_t take()
     {
@@ -386,7 +395,8 @@ int sel_alloc_caps(v3dg_selection *s, uint64_t cap_tests, uint64_t cap_slots, hi
 int sel_alloc(v3dg_scene *sc, v3dg_selection *s)
 {
     s->scene = sc;
-    return sel_alloc_caps(s, (uint64_t)sc->NC * sc->n_inst, sc->cap_slots, sc->stream);
+    return sel_alloc_caps(s, (uint64_t)sc->NC * sc->n_inst, sc->cap_slots,
+                          sc->pool_clusters ? sc->sel_stream : sc->stream);
 }
 
 // Plane coefficients of the cluster view cull for one camera (see CullRec).
@@ -711,12 +721,17 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         launch_frame_setup(c->stream, cam, image, c->fdev, from_fd, true, sc->T_dev, sc->scale_dev, sc->n_inst,
                            c->itab, c->rclear, (uint64_t)kRenCounters + 2 * c->scan_parts + 2ull * n_tiles);
     }
+    if (sc->pool_clusters) {  // streamed: the next select may rewrite the selection once projection is done
+        HIP_TRY(hipMemcpyAsync(c->rcounters + kRenSlots, n_dev, sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+        n_dev = c->rcounters + kRenSlots;
+    }
     ProjectOut po{c->splat, c->depth, c->bin, c->rect, c->tiles, c->dkey[0], c->dval[0]};
     {
         Stage st(c, V3DG_STAGE_PROJECT);
         launch_project(c->stream, c->fdev, sc->attribs(), (int)sc->precision, (int)sc->sh_degree, sel.slot_row,
                        sel.slot_inst, n_dev, S, c->itab, po);
     }
+    if (sc->pool_clusters) HIP_TRY(hipEventRecord(sc->ev_proj, c->stream));
     const bool depth_first = capacity || c->sort_mode == V3DG_SORT_DEPTH_FIRST;
     fi->depth_first = depth_first;
     if (depth_first) {
@@ -901,7 +916,7 @@ void lru_front(v3dg_scene *s, uint32_t p)
 // stage_cap clusters and scattered into their pages on the scene's stream.
 // V3DG_ERR_CAPACITY (nothing paged) when the cut needs more pages than the
 // pool holds.
-int page_in(v3dg_scene *s, const uint32_t *gid, const uint32_t *off, uint32_t n, uint32_t total)
+int page_in(v3dg_scene *s, hipStream_t st, const uint32_t *gid, const uint32_t *off, uint32_t n, uint32_t total)
 {
     const uint64_t f = ++s->frame;
     std::vector<uint32_t> miss;
@@ -948,15 +963,14 @@ int page_in(v3dg_scene *s, const uint32_t *gid, const uint32_t *off, uint32_t n,
                         s->page_bytes);
             s->ups_h[j] = make_uint4(k, s->page_of[k], s->h_count[k], 0u);
         }
-        hipError_t e = hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice,
-                                      s->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, s->stream);
+        hipError_t e = hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) {
-            launch_stream_scatter(s->stream, s->stage_d, s->ups_d, m, s->page_bytes, s->geo_bytes, s->sh_bytes,
+            launch_stream_scatter(st, s->stage_d, s->ups_d, m, s->page_bytes, s->geo_bytes, s->sh_bytes,
                                   s->n_sh, s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride, s->rowinfo);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the staging buffers are reused
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // the staging buffers are reused
         if (e != hipSuccess) {  // the pages of this chunk and the rest hold nothing valid: free them
             for (size_t q = i; q < miss.size(); ++q) {
                 const uint32_t k = miss[q];
@@ -979,6 +993,7 @@ void scene_release(v3dg_scene *s)
     if (!s) return;
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->sel_stream) (void)hipStreamSynchronize(s->sel_stream);
     if (s->full) {
         sel_release(s->full);
         delete s->full;
@@ -995,6 +1010,9 @@ void scene_release(v3dg_scene *s)
     dev_free(s->cull_dev);
     dev_free(s->stage_d);
     dev_free(s->ups_d);
+    if (s->ev_proj) (void)hipEventDestroy(s->ev_proj);
+    if (s->ev_sel) (void)hipEventDestroy(s->ev_sel);
+    if (s->sel_stream) (void)hipStreamDestroy(s->sel_stream);
     if (s->stage_h) (void)hipHostFree(s->stage_h);
     if (s->ups_h) (void)hipHostFree(s->ups_h);
     ctx_release(s);
@@ -1269,6 +1287,12 @@ int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *d, const double *ins
             }
             if ((rc = dev_alloc(&s->stage_d, (uint64_t)s->stage_cap * s->page_bytes))) return bail(rc);
             if ((rc = dev_alloc(&s->ups_d, s->stage_cap))) return bail(rc);
+            // non-blocking: no implicit wait for work on the null stream (the
+            // scene's stream may be it); ordering is by the two events alone
+            if (hipStreamCreateWithFlags(&s->sel_stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s->ev_sel, hipEventDisableTiming) != hipSuccess)
+                return bail(fail(V3DG_ERR_HIP, "stream or event creation failed"));
         }
         // view-cull table: sphere of each cluster's row means (FP64, radius
         // rounded up) and its largest scale (enlarged to cover FP16 storage)
@@ -1342,17 +1366,20 @@ int v3dg_set_instances(v3dg_scene *s, const double *instances_3x4, uint32_t n)
 // Streamed scenes: read a selected cut back (synchronises) and page it in.
 static int stream_cut(v3dg_scene *s, v3dg_selection *sel)
 {
-    HIP_TRY(hipMemcpyAsync(s->pinned + 8, sel->counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpyAsync(s->pinned + 8, sel->counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->sel_stream));
+    HIP_TRY(hipStreamSynchronize(s->sel_stream));
     if (s->pinned[8 + kSelErr] & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
     const uint32_t n = s->pinned[8 + kSelNClusters], total = s->pinned[8 + kSelNGaussians];
     s->cut_gid.resize(n);
     s->cut_off.resize(n);
-    if (n) {
-        HIP_TRY(hipMemcpy(s->cut_gid.data(), sel->gid, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(s->cut_off.data(), sel->slot_off, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (n) {  // on the select stream only: the previous render's later stages go on meanwhile
+        HIP_TRY(hipMemcpyAsync(s->cut_gid.data(), sel->gid, n * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s->sel_stream));
+        HIP_TRY(hipMemcpyAsync(s->cut_off.data(), sel->slot_off, n * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s->sel_stream));
+        HIP_TRY(hipStreamSynchronize(s->sel_stream));
     }
-    const int rc = page_in(s, s->cut_gid.data(), s->cut_off.data(), n, total);
+    const int rc = page_in(s, s->sel_stream, s->cut_gid.data(), s->cut_off.data(), n, total);
     if (rc) return rc;
     sel->stream_frame = s->frame;
     return V3DG_OK;
@@ -1382,19 +1409,24 @@ int v3dg_select(v3dg_scene *s, const v3dg_camera *c, float tau, v3dg_selection *
         fresh = true;
     }
     const float K = footprint_K(c);
+    // a streamed scene selects on its own stream, once the frame before has
+    // been projected (it rewrites the instance table, the selection and pages)
+    const hipStream_t qs = s->pool_clusters ? s->sel_stream : s->stream;
+    if (s->pool_clusters) HIP_TRY(hipStreamWaitEvent(qs, s->ev_proj, 0));
     {
-        Stage st(s, V3DG_STAGE_SETUP);
-        launch_frame_setup(s->stream, cam, nullptr, nullptr, false, false, s->T_dev, s->scale_dev, s->n_inst, s->itab,
+        Stage st(s, V3DG_STAGE_SETUP, qs);
+        launch_frame_setup(qs, cam, nullptr, nullptr, false, false, s->T_dev, s->scale_dev, s->n_inst, s->itab,
                            sel->clear_block, (uint64_t)kSelCounters + 2 * sel->n_parts);
     }
     {
-        Stage st(s, V3DG_STAGE_SELECT);
-        launch_select(s->stream, make_selreq(s, s->itab, K, tau, sel, cam, s->culling));
+        Stage st(s, V3DG_STAGE_SELECT, qs);
+        launch_select(qs, make_selreq(s, s->itab, K, tau, sel, cam, s->culling));
     }
     if (s->pool_clusters) {  // streamed: read the cut back, page in what it lacks
         rc = stream_cut(s, sel);
         if (rc) {
             sel->stream_frame = 0;  // its cut is not expanded: never renderable
+            (void)hipStreamSynchronize(s->sel_stream);
             if (fresh) {
                 sel_release(sel);
                 delete sel;
@@ -1403,9 +1435,13 @@ int v3dg_select(v3dg_scene *s, const v3dg_camera *c, float tau, v3dg_selection *
         }
     }
     {
-        Stage st(s, V3DG_STAGE_EXPAND);
-        launch_expand(s->stream, sel->gid, sel->slot_off, s->rowinfo, s->NC, sel->counters,
+        Stage st(s, V3DG_STAGE_EXPAND, qs);
+        launch_expand(qs, sel->gid, sel->slot_off, s->rowinfo, s->NC, sel->counters,
                       (uint32_t)std::min<uint64_t>(sel->cap_tests, 0xffffffffull), sel->slot_row, sel->slot_inst);
+    }
+    if (s->pool_clusters) {  // whatever comes next on the scene's stream waits for this select
+        HIP_TRY(hipEventRecord(s->ev_sel, qs));
+        HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_sel, 0));
     }
     s->acc.selects += 1;
     s->acc.tests += (uint64_t)s->NC * s->n_inst;
@@ -1439,7 +1475,8 @@ int v3dg_render_full(v3dg_scene *s, const v3dg_camera *c, float *image)
     if ((rc = build_full_selection(s))) return rc;
     if (s->pool_clusters) {  // streamed: page in every leaf, then place the slots on the pages
         v3dg_selection *f = s->full;
-        if ((rc = page_in(s, s->full_gid.data(), s->full_off.data(), (uint32_t)s->full_gid.size(), s->full_total)))
+        if ((rc = page_in(s, s->stream, s->full_gid.data(), s->full_off.data(), (uint32_t)s->full_gid.size(),
+                          s->full_total)))
             return rc;
         f->stream_frame = s->frame;
         launch_expand(s->stream, f->gid, f->slot_off, s->rowinfo, s->NC, f->counters, (uint32_t)s->full_gid.size(),
@@ -1498,6 +1535,7 @@ void v3dg_selection_free(v3dg_selection *sel)
     if (sel->scene) {
         (void)hipSetDevice(sel->scene->device);
         (void)hipStreamSynchronize(sel->scene->stream);
+        if (sel->scene->sel_stream) (void)hipStreamSynchronize(sel->scene->sel_stream);
     }
     sel_release(sel);
     delete sel;

@@ -171,3 +171,30 @@ def test_streamed_walk_full_size(torch):
     assert stats["evictions"] > 0
     res.close()
     st.close()
+
+
+def test_streamed_frames_in_flight(torch):
+    """Selects issued while the previous frame still renders (no host wait
+    between frames, one selection object rewritten every frame, a pool small
+    enough to evict): every image, read after the last frame, equals the
+    resident scene's."""
+    a = sg.cached_asset(1 << 20, 3, 2)
+    cams = sg.tangent_path_cameras(100)[3::8]
+    st = v.Scene(a, pool_clusters=7430)
+    st.set_culling(True)
+    imgs, sel = [], None
+    for cam in cams:
+        sel = st.select(cam, 1.0, sel)
+        imgs.append(st.render(cam, sel))
+    torch.cuda.synchronize()
+    res = v.Scene(a)
+    res.set_culling(True)
+    for i, cam in enumerate(cams):
+        s0 = res.select(cam, 1.0)
+        ref = res.render(cam, s0)
+        torch.cuda.synchronize()
+        assert torch.equal(imgs[i], ref), (i, float((imgs[i] - ref).abs().max()))
+        s0.free()
+    assert st.stream_stats()["evictions"] > 0
+    st.close()
+    res.close()
