@@ -388,11 +388,12 @@ void launch_gather_rows(hipStream_t st, const float *pos, const float *scale, co
 // updates position, log scale, quaternion, logit opacity and dc with rates
 // 1.6e-5, 5e-3, 1e-3, 5e-2, 2.5e-3.
 //
-// One 256-thread workgroup per group; each wavefront renders one image row
-// per round (lane = pixel).  The backward walk runs over the fitted splats
-// in reverse depth order, recovering T by division; the per-splat sums of a
-// wavefront are reduced across lanes and kept per wavefront, so every sum is
-// taken in a fixed order.
+// One 1024-thread workgroup per group: 16 wavefronts of 4 image rows each
+// (lane = pixel), walking their rows together over the depth-sorted splats
+// that reach them.  The backward walk runs over the fitted splats in reverse
+// depth order, recovering T by division; each splat's gradient terms are
+// summed over a wavefront's rows in every lane, then across the lanes, and
+// kept per wavefront, so every sum is taken in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kLsThreads = 1024;
 constexpr int kLsRes = 64;
