@@ -18,6 +18,7 @@
 
 #include "../../include/v3dg.h"
 #include "v3dg_internal.h"
+#include "page_lru.h"
 
 using namespace v3dg;
 
@@ -207,7 +208,6 @@ struct v3dg_selection {
     uint64_t stream_frame = 0;  // streamed scenes: the paging frame of the cut
 };
 
-constexpr uint32_t kNoPage = 0xffffffffu;
 // a streamed frame's own copy of its slot count, among the spare render counters
 constexpr int kRenSlots = kRenBig + 1;
 static_assert(kRenSlots < kRenCounters, "render counter out of range");
@@ -238,10 +238,7 @@ struct v3dg_scene : Ctx {
     // row of a resident cluster.  Pages form an LRU list (head: most recent).
     uint32_t pool_clusters = 0, page_bytes = 0, geo_bytes = 4, sh_bytes = 4, n_sh = 0, stage_cap = 0;
     std::vector<uint8_t> h_pages;
-    std::vector<uint32_t> page_of, cluster_of, lru_prev, lru_next;
-    std::vector<uint64_t> page_stamp, miss_stamp;
-    uint32_t lru_head = kNoPage, lru_tail = kNoPage;
-    uint64_t frame = 0, max_evicted_stamp = 0;
+    PageLRU lru;  // which cluster holds which page
     uint8_t *stage_h = nullptr, *stage_d = nullptr;
     uint4 *ups_h = nullptr, *ups_d = nullptr;
     std::vector<uint32_t> cut_gid, cut_off;
@@ -842,7 +839,7 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     if (rc) return rc;
     if (!sel || sel->scene != s) return fail(V3DG_ERR_INVALID_ARG, "selection does not belong to this scene");
     if (!image) return fail(V3DG_ERR_INVALID_ARG, "image is NULL");
-    if (s->pool_clusters && sel->stream_frame <= s->max_evicted_stamp)
+    if (s->pool_clusters && sel->stream_frame <= s->lru.max_evicted_stamp)
         return fail(V3DG_ERR_INVALID_ARG, "the selection's clusters were paged out by a later select: select again");
     HIP_TRY(hipSetDevice(s->device));
     FrameInfo fi;
@@ -890,78 +887,28 @@ int build_full_selection(v3dg_scene *s)
 }
 
 // ---- cluster streaming ----------------------------------------------------
-void lru_unlink(v3dg_scene *s, uint32_t p)
-{
-    const uint32_t a = s->lru_prev[p], b = s->lru_next[p];
-    if (a != kNoPage) s->lru_next[a] = b;
-    else s->lru_head = b;
-    if (b != kNoPage) s->lru_prev[b] = a;
-    else s->lru_tail = a;
-    s->lru_prev[p] = s->lru_next[p] = kNoPage;
-}
-
-void lru_front(v3dg_scene *s, uint32_t p)
-{
-    s->lru_prev[p] = kNoPage;
-    s->lru_next[p] = s->lru_head;
-    if (s->lru_head != kNoPage) s->lru_prev[s->lru_head] = p;
-    s->lru_head = p;
-    if (s->lru_tail == kNoPage) s->lru_tail = p;
-}
-
 // Pages in every cluster with slots in a cut (gid, slot offsets, n clusters,
-// total slots; host arrays) as paging frame ++frame.  Resident clusters are
-// moved to the front of the LRU list; the others take the least recently used
-// pages not used by this cut, are staged and copied in one transfer per
-// stage_cap clusters and scattered into their pages on the scene's stream.
-// V3DG_ERR_CAPACITY (nothing paged) when the cut needs more pages than the
-// pool holds.
+// total slots; host arrays) as a new paging frame: the page-replacement plan
+// (PageLRU) assigns pages to the missing clusters; their page images are
+// staged and copied in one transfer per stage_cap clusters and scattered into
+// their pages on stream st.  V3DG_ERR_CAPACITY (nothing paged) when the cut
+// needs more pages than the pool holds.
 int page_in(v3dg_scene *s, hipStream_t st, const uint32_t *gid, const uint32_t *off, uint32_t n, uint32_t total)
 {
-    const uint64_t f = ++s->frame;
-    std::vector<uint32_t> miss;
+    std::vector<uint32_t> ks, miss;
+    ks.reserve(n);
+    for (uint32_t c = 0; c < n; ++c)
+        if ((c + 1 < n ? off[c + 1] : total) != off[c]) ks.push_back(gid[c] % s->NC);
     uint32_t touched = 0;
-    for (uint32_t c = 0; c < n; ++c) {
-        const uint32_t cnt = (c + 1 < n ? off[c + 1] : total) - off[c];
-        if (cnt == 0) continue;
-        const uint32_t k = gid[c] % s->NC;
-        const uint32_t pg = s->page_of[k];
-        if (pg != kNoPage) {
-            if (s->page_stamp[pg] != f) {
-                s->page_stamp[pg] = f;
-                lru_unlink(s, pg);
-                lru_front(s, pg);
-                ++touched;
-            }
-        } else if (s->miss_stamp[k] != f) {
-            s->miss_stamp[k] = f;
-            miss.push_back(k);
-        }
-    }
-    if ((uint64_t)touched + miss.size() > s->pool_clusters)
-        return fail(V3DG_ERR_CAPACITY, "the cut needs %llu resident clusters, the pool holds %u",
-                    (unsigned long long)touched + miss.size(), s->pool_clusters);
-    for (uint32_t k : miss) {  // the tail is the least recently used page, never one of this cut
-        const uint32_t pg = s->lru_tail;
-        const uint32_t old = s->cluster_of[pg];
-        if (old != kNoPage) {
-            s->page_of[old] = kNoPage;
-            s->max_evicted_stamp = std::max(s->max_evicted_stamp, s->page_stamp[pg]);
-            s->sstats.evictions += 1;
-        }
-        s->cluster_of[pg] = k;
-        s->page_of[k] = pg;
-        s->page_stamp[pg] = f;
-        lru_unlink(s, pg);
-        lru_front(s, pg);
-    }
+    if (!s->lru.plan(ks.data(), ks.size(), miss, touched))
+        return fail(V3DG_ERR_CAPACITY, "the cut needs more resident clusters than the pool's %u", s->pool_clusters);
     for (size_t i = 0; i < miss.size(); i += s->stage_cap) {
         const uint32_t m = (uint32_t)std::min<size_t>(s->stage_cap, miss.size() - i);
         for (uint32_t j = 0; j < m; ++j) {
             const uint32_t k = miss[i + j];
             std::memcpy(s->stage_h + (uint64_t)j * s->page_bytes, s->h_pages.data() + (uint64_t)k * s->page_bytes,
                         s->page_bytes);
-            s->ups_h[j] = make_uint4(k, s->page_of[k], s->h_count[k], 0u);
+            s->ups_h[j] = make_uint4(k, s->lru.page_of(k), s->h_count[k], 0u);
         }
         hipError_t e = hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, st);
@@ -972,17 +919,14 @@ int page_in(v3dg_scene *s, hipStream_t st, const uint32_t *gid, const uint32_t *
         }
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // the staging buffers are reused
         if (e != hipSuccess) {  // the pages of this chunk and the rest hold nothing valid: free them
-            for (size_t q = i; q < miss.size(); ++q) {
-                const uint32_t k = miss[q];
-                s->cluster_of[s->page_of[k]] = kNoPage;
-                s->page_of[k] = kNoPage;
-            }
+            for (size_t q = i; q < miss.size(); ++q) s->lru.release(miss[q]);
             return fail(V3DG_ERR_HIP, "paging in clusters failed: %s", hipGetErrorString(e));
         }
     }
     s->sstats.frames += 1;
     s->sstats.pages_in += miss.size();
     s->sstats.bytes_in += (uint64_t)miss.size() * s->page_bytes;
+    s->sstats.evictions = s->lru.evictions;
     s->sstats.last_pages_in = miss.size();
     s->sstats.last_resident_used = touched + (uint32_t)miss.size();
     return V3DG_OK;
@@ -1271,13 +1215,7 @@ int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *d, const double *ins
                                 cnt * sh_bytes);
             }
             const uint32_t P = s->pool_clusters;
-            s->page_of.assign(NC, kNoPage);
-            s->miss_stamp.assign(NC, 0);
-            s->cluster_of.assign(P, kNoPage);
-            s->page_stamp.assign(P, 0);
-            s->lru_prev.assign(P, kNoPage);
-            s->lru_next.assign(P, kNoPage);
-            for (uint32_t q = 0; q < P; ++q) lru_front(s, q);
+            s->lru.init(NC, P);
             s->stage_cap = std::min<uint32_t>(P, 2048u);
             s->sstats.pool_clusters = P;
             if (hipHostMalloc((void **)&s->stage_h, (uint64_t)s->stage_cap * s->page_bytes, hipHostMallocDefault) !=
@@ -1342,8 +1280,7 @@ int v3dg_get_stream_stats(const v3dg_scene *s, v3dg_stream_stats *out)
     g_err.clear();
     if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "scene and out must be non-NULL");
     *out = s->sstats;
-    out->resident = 0;
-    for (uint32_t c : s->cluster_of) out->resident += c != kNoPage ? 1u : 0u;
+    out->resident = s->pool_clusters ? s->lru.resident() : 0u;
     return V3DG_OK;
 }
 
@@ -1381,7 +1318,7 @@ static int stream_cut(v3dg_scene *s, v3dg_selection *sel)
     }
     const int rc = page_in(s, s->sel_stream, s->cut_gid.data(), s->cut_off.data(), n, total);
     if (rc) return rc;
-    sel->stream_frame = s->frame;
+    sel->stream_frame = s->lru.frame;
     return V3DG_OK;
 }
 
@@ -1478,7 +1415,7 @@ int v3dg_render_full(v3dg_scene *s, const v3dg_camera *c, float *image)
         if ((rc = page_in(s, s->stream, s->full_gid.data(), s->full_off.data(), (uint32_t)s->full_gid.size(),
                           s->full_total)))
             return rc;
-        f->stream_frame = s->frame;
+        f->stream_frame = s->lru.frame;
         launch_expand(s->stream, f->gid, f->slot_off, s->rowinfo, s->NC, f->counters, (uint32_t)s->full_gid.size(),
                       f->slot_row, f->slot_inst);
         HIP_TRY(hipGetLastError());
