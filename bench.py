@@ -269,11 +269,11 @@ def unit_dirs(n, seed):
     return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
 
 
-def build_bench(v, asset, with_oracle: bool):
+def build_bench(v, asset):
     """Offline build (paper Algorithm 1) of the asset's 1M leaf Gaussians on
     the GPU, host arrays in and out: structural, and with local splatting over
-    640 pseudo-views per group; the oracles on the same input (the structural
-    build whole, the local-splatting fit on one group over a few views)."""
+    640 pseudo-views per group.  Returns the results and the inputs the CPU
+    baseline leg times the oracles on."""
     import numpy as np
     L = asset.n_leaf_rows
     g_in = (asset.pos[:L], asset.scale[:L], asset.rot[:L], asset.opacity[:L], asset.sh[:L])
@@ -302,30 +302,57 @@ def build_bench(v, asset, with_oracle: bool):
         "mean_loss_first_view_by_layer": [float(x) for x in bf["fit_loss"][:, 0]],
         "mean_loss_last_64_views_by_layer": [float(x) for x in bf["fit_loss"][:, -64:].mean(1)]}
     log("offline build with local splatting (%d views per group, %d groups): %.2f s" % (FIT_ITERS, groups, t_f))
-    if with_oracle:
-        from oracle import offline_build as ob
-        from oracle import local_splat as ls
+    # one coarse group of the fitted bundle (two leaf clusters) for the oracle's fit timing
+    p = int(bf["n_leaf_clusters"])
+    c0 = int(bf["first_child"][p])
+    idx = np.arange(bf["first_row"][c0], bf["first_row"][c0] + int(bf["count"][c0]) + int(bf["count"][c0 + 1]))
+    rows = {k: bf[k][idx].copy() for k in ("pos", "scale", "rot", "opacity", "sh")}
+    sample = dict(g_in=g_in, rows=rows, simp={k: x[::2].copy() for k, x in rows.items()},
+                  sph=bf["self_sphere"][p].astype(np.float64), dirs=dirs[:24].astype(np.float64))
+    return out, sample
+
+
+def cpu_baseline(sg, asset, frames, build_sample):
+    """The CPU baseline leg, the one part of the benchmark that runs the
+    oracle: frames of the timed sequence (selection walk + FP64 renderer on
+    the host's threads) and, when given, the offline-build oracles on the
+    benchmark asset's leaves (the structural build whole; local splatting of
+    one group over 24 views)."""
+    import numpy as np
+    import oracle
+    from oracle import local_splat as ls
+    from oracle import offline_build as ob
+    out = {}
+    if frames:
+        nth = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        nth = max(1, min(nth, os.cpu_count() or 1))
+        T = sg.identity_instances(1)
+        log("CPU oracle baseline: %d frames on %d threads" % (len(frames), nth))
+        t0 = time.perf_counter()
+        for cam, tau in frames:
+            gids = oracle.mask_to_gids(oracle.select_walk(asset, T, cam, tau))
+            oracle.render(asset, T, cam, gids, use_index=True, n_threads=nth)
+        tc = time.perf_counter() - t0
+        out.update(value=len(frames) / tc, unit="FPS", cores=nth, kind="oracle",
+                   sample="first %d frames of the timed sequence (tolerance 0, full 1080p frames), FP64 "
+                          "recursive-walk selection + bucket-indexed per-pixel compositing" % len(frames))
+    if build_sample is not None:
+        g_in = build_sample["g_in"]
         t0 = time.perf_counter()
         ob.build_bundle(*g_in, 64)
         t = time.perf_counter() - t0
-        out["oracle_s"] = t
-        out["oracle_gaussians_per_s"] = L / t
-        out["oracle_kind"] = "numpy oracle, one host process"
         log("offline build oracle: %.1f s" % t)
-        # one coarse group of the fitted bundle (two leaf clusters) over 24 views
-        p = int(bf["n_leaf_clusters"])
-        c0 = int(bf["first_child"][p])
-        idx = np.arange(bf["first_row"][c0], bf["first_row"][c0] + int(bf["count"][c0]) + int(bf["count"][c0 + 1]))
-        rows = {k: bf[k][idx] for k in ("pos", "scale", "rot", "opacity", "sh")}
-        simp = {k: x[::2].copy() for k, x in rows.items()}
-        sph = bf["self_sphere"][p].astype(np.float64)
         t0 = time.perf_counter()
-        ls.local_splat(rows, simp, sph[:3], float(sph[3]), dirs[:24].astype(np.float64), 24)
-        t = time.perf_counter() - t0
-        out["local_splatting"]["oracle_us_per_group_view"] = 1e6 * t / 24
-        out["local_splatting"]["oracle_sample"] = "one group of %d Gaussians fitting %d, 24 views (FP64 PyTorch " \
-                                                  "with autograd, host)" % (len(idx), len(simp["opacity"]))
-        log("local splatting oracle: %.0f ms per group and view" % (1e3 * t / 24))
+        ls.local_splat(build_sample["rows"], build_sample["simp"], build_sample["sph"][:3],
+                       float(build_sample["sph"][3]), build_sample["dirs"], len(build_sample["dirs"]))
+        tl = (time.perf_counter() - t0) / len(build_sample["dirs"])
+        log("local splatting oracle: %.0f ms per group and view" % (1e3 * tl))
+        out["offline_build"] = dict(
+            structural_s=t, gaussians_per_s=len(g_in[0]) / t, kind="numpy oracle, one host process",
+            local_splatting_us_per_group_view=1e6 * tl,
+            local_splatting_sample="one group of %d Gaussians fitting %d, %d views (FP64 PyTorch with autograd, host)"
+                                   % (len(build_sample["rows"]["opacity"]), len(build_sample["simp"]["opacity"]),
+                                      len(build_sample["dirs"])))
     return out
 
 
@@ -443,8 +470,14 @@ def main():
     log("generating asset (%d leaves, SH3)" % n_leaves)
     asset = sg.cached_asset(n_leaves, 3, 2)
     if args.only:  # one side measurement alone, not the headline line
-        res = build_bench(v, asset, not args.no_cpu) if args.only == "build" else stream_bench(torch, v, sg, asset)
-        print(json.dumps({args.only: res}), flush=True)
+        if args.only == "build":
+            res, sample = build_bench(v, asset)
+            line = {"build": res}
+            if not args.no_cpu:
+                line["cpu_baseline"] = cpu_baseline(sg, asset, [], sample)
+        else:
+            line = {"stream": stream_bench(torch, v, sg, asset)}
+        print(json.dumps(line), flush=True)
         return
     b_row = 4 * (3 + 3 + 4 + 1 + 3 * 16)
     cams = sg.orbit_cameras(64, 102)
@@ -590,9 +623,9 @@ def main():
     streaming = None
     if not args.no_stream and not args.profile_run and not args.quick:
         streaming = stream_bench(torch, v, sg, asset)
-    build = None
+    build, build_sample = None, None
     if not args.no_build and not args.profile_run and not args.quick:
-        build = build_bench(v, asset, not args.no_cpu)
+        build, build_sample = build_bench(v, asset)
     serving = None
     if not args.no_serving and not args.profile_run and not args.quick:
         serving = serving_bench(torch, v, sg)
@@ -663,21 +696,7 @@ def main():
     }
 
     if not args.no_cpu:
-        import oracle
-        nth = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        nth = max(1, min(nth, os.cpu_count() or 1))
-        T = sg.identity_instances(1)
-        frames = seq[: args.cpu_frames]
-        log("CPU oracle baseline: %d frames on %d threads" % (len(frames), nth))
-        t0 = time.perf_counter()
-        for cam, tau in frames:
-            gids = oracle.mask_to_gids(oracle.select_walk(asset, T, cam, tau))
-            oracle.render(asset, T, cam, gids, use_index=True, n_threads=nth)
-        tc = time.perf_counter() - t0
-        out["cpu_baseline"] = dict(value=len(frames) / tc, unit="FPS", cores=nth, kind="oracle",
-                                   sample="first %d frames of the timed sequence (tolerance 0, full 1080p frames), "
-                                          "FP64 recursive-walk selection + bucket-indexed per-pixel compositing"
-                                          % len(frames))
+        out["cpu_baseline"] = cpu_baseline(sg, asset, seq[: args.cpu_frames], build_sample)
     print(json.dumps(out), flush=True)
 
 
