@@ -45,7 +45,9 @@ struct BlendShared {
     float4 P1[kBlendThreads];  // (c, log2 threshold, log2 o, -)
     float4 P2[kBlendThreads];  // (r, g, b, -)
     uint8_t mask[kBlendThreads];
-    uint8_t idx[4][kBlendThreads];
+    // per wavefront, its entries in order as byte offsets into P0 / P1 / P2;
+    // + one pair read ahead past the last entry
+    uint16_t idx[4][kBlendThreads + 2];
 };
 
 struct Pix {
@@ -77,6 +79,12 @@ __device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid
     sh.mask[tid] = (uint8_t)m;
 }
 
+// Record of a staged entry by its byte offset (entry number x 16).
+__device__ __forceinline__ float4 rec(const float4 *base, uint32_t off)
+{
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // One splat against the lane's pixel, branch-free.  p is its base-2
 // quadratic form, log2o = log2 of its opacity, col its colour; take says the
 // pixel is active and the splat passes the 1/255 test.  A stopped pixel
@@ -86,7 +94,9 @@ __device__ __forceinline__ void composite(float p, bool take, float log2o, const
                                           float &cg, float &cb)
 {
     // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
-    const float ex = __builtin_amdgcn_exp2f(fminf(p, 0.0f) + log2o);
+    // min(p, 0) as one integer min on the bit pattern (p is never NaN; a
+    // negative float is a negative integer, -0 gives the same exponent as 0)
+    const float ex = __builtin_amdgcn_exp2f(__int_as_float(min(__float_as_int(p), 0)) + log2o);
     const float alpha = take ? fminf(0.99f, ex) : 0.0f;
     const float Tn = fmaf(-alpha, T, T);
     // a pixel that does not take the splat keeps Tn = T: >= 1e-4 while
@@ -138,10 +148,13 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
         for (int c = 0; c < kBlendThreads / kWave; ++c) {
             const bool hit = (sh.mask[c * kWave + lane] >> wid) & 1u;
             const uint64_t bal = __ballot(hit);
-            if (hit) sh.idx[wid][cnt + (uint32_t)__popcll(bal & lt)] = (uint8_t)(c * kWave + lane);
+            if (hit) sh.idx[wid][cnt + (uint32_t)__popcll(bal & lt)] = (uint16_t)((c * kWave + lane) * sizeof(float4));
             cnt += (uint32_t)__popcll(bal);
         }
         __syncthreads();
+        // an odd last entry is paired with itself (never taken twice), so every
+        // record read belongs to this batch
+        if ((cnt & 1u) && lane == 0) sh.idx[wid][cnt] = sh.idx[wid][cnt - 1];
         uint64_t am = __ballot(px.active);  // active pixels (uniform)
         if (am) {
             // The walk is uniform across the wavefront: entries k, k+1 are the
@@ -149,14 +162,16 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
             // An entry counts as walked for the pixels active when it is reached.
             float T = px.active ? px.T : -px.T, cr = px.cr, cg = px.cg, cb = px.cb;
             uint32_t walked = 0;
+            uint32_t prn = *reinterpret_cast<const uint32_t *>(&sh.idx[wid][0]);
             for (uint32_t k = 0; am != 0 && k < cnt; k += 2) {
-                const uint32_t pr = *reinterpret_cast<const uint16_t *>(&sh.idx[wid][k]);
+                // the next pair's offsets are read one iteration ahead (past the
+                // last entry they are stale values of the row and never used)
+                const uint32_t pr = prn;
+                prn = *reinterpret_cast<const uint32_t *>(&sh.idx[wid][k + 2]);
                 const bool two = k + 1 < cnt;
-                // an odd last entry is paired with itself (never taken twice):
-                // every record read belongs to this batch
-                const uint32_t j0 = pr & 0xffu, j1 = two ? pr >> 8 : j0;
-                const float4 a0 = sh.P0[j0], a1 = sh.P0[j1];
-                const float4 c0 = sh.P1[j0], c1 = sh.P1[j1];
+                const uint32_t o0 = pr & 0xffffu, o1 = pr >> 16;
+                const float4 a0 = rec(sh.P0, o0), a1 = rec(sh.P0, o1);
+                const float4 c0 = rec(sh.P1, o0), c1 = rec(sh.P1, o1);
                 const float dx0 = a0.x - pxc, dy0 = a0.y - pyc;
                 const float dx1 = a1.x - pxc, dy1 = a1.y - pyc;
                 const float p0 = fmaf(a0.z * dx0, dx0, fmaf(a0.w * dx0, dy0, c0.x * dy0 * dy0));
@@ -164,7 +179,7 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
                 const bool pass0 = !(p0 < c0.y), pass1 = two && !(p1 < c1.y);  // alpha >= 1/255
                 uint64_t amid = am;  // active after entry k
                 if (__ballot(T > 0.0f && (pass0 || pass1)) != 0) {
-                    const float4 col0 = sh.P2[j0], col1 = sh.P2[j1];
+                    const float4 col0 = rec(sh.P2, o0), col1 = rec(sh.P2, o1);
                     composite(p0, T > 0.0f && pass0, c0.z, col0, T, cr, cg, cb);
                     const bool act1 = T > 0.0f;
                     amid = __ballot(act1);
@@ -224,7 +239,7 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
 // Workgroup b blends tile order[b]: the tiles with the longest first chunks
 // come first, so that their walks do not start last and leave the rest of the
 // chip idle.
-__global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) blend_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
@@ -257,7 +272,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
 // ---------------------------------------------------------------------------
 // pass 2: chunks 1.. of long tiles, in parallel, each from T = 1
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlendThreads) chunk_kernel(const FrameDev *__restrict__ fd,
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) chunk_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
