@@ -174,8 +174,9 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
                 const float4 c0 = rec(sh.P1, o0), c1 = rec(sh.P1, o1);
                 const float dx0 = a0.x - pxc, dy0 = a0.y - pyc;
                 const float dx1 = a1.x - pxc, dy1 = a1.y - pyc;
-                const float p0 = fmaf(a0.z * dx0, dx0, fmaf(a0.w * dx0, dy0, c0.x * dy0 * dy0));
-                const float p1 = fmaf(a1.z * dx1, dx1, fmaf(a1.w * dx1, dy1, c1.x * dy1 * dy1));
+                // p = (a dx + b dy) dx + c dy^2
+                const float p0 = fmaf(fmaf(a0.z, dx0, a0.w * dy0), dx0, c0.x * dy0 * dy0);
+                const float p1 = fmaf(fmaf(a1.z, dx1, a1.w * dy1), dx1, c1.x * dy1 * dy1);
                 const bool pass0 = !(p0 < c0.y), pass1 = two && !(p1 < c1.y);  // alpha >= 1/255
                 uint64_t amid = am;  // active after entry k
                 if (__ballot(T > 0.0f && (pass0 || pass1)) != 0) {
