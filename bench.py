@@ -29,11 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # operation per lane per clock (an FMA is one operation).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Lane-op slots per evaluated (pixel, splat) pair under the compositing rule:
-# dx, dy (2); the quadratic a dx^2 + b dx dy + c dy^2 (4 mul + 2 fma); the
-# 1/255 test (1); clamp to <= 0 (1); + log2 o (1); exp2 (quarter rate: 4);
-# min(0.99, .) (1); T (1 - alpha) as T - alpha T (1 fma); the 1e-4 test (1);
-# w = alpha T (1); three colour fma (3); T update (1) -> 23.
-BLEND_OPS_PER_PAIR = 23
+# dx, dy (2); the quadratic a dx^2 + b dx dy + c dy^2 as (a dx + b dy) dx +
+# c dy^2 (3 mul + 2 fma); the 1/255 test (1); clamp to <= 0 (1); + log2 o (1);
+# exp2 (quarter rate: 4); min(0.99, .) (1); T (1 - alpha) as T - alpha T
+# (1 fma); the 1e-4 test (1); w = alpha T (1); three colour fma (3); T update
+# (1) -> 22.
+BLEND_OPS_PER_PAIR = 22
 # HBM bytes per frame of the blend stage on this workload, from rocprofv3
 # FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the 256 timed frames
 # (profiles/hbm_counters_1M_sh3_1080p.md).  Valid only for the blending source

@@ -45,6 +45,7 @@ struct BlendShared {
     float4 P1[kBlendThreads];  // (c, log2 threshold, log2 o, -)
     float4 P2[kBlendThreads];  // (r, g, b, -)
     uint8_t mask[kBlendThreads];
+    uint32_t alive;  // byte w: wavefront w has an active pixel
     // per wavefront, its entries in order as byte offsets into P0 / P1 / P2;
     // + one pair read ahead past the last entry
     uint16_t idx[4][kBlendThreads + 2];
@@ -77,6 +78,14 @@ __device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid
         }
     }
     sh.mask[tid] = (uint8_t)m;
+}
+
+// Orders this wavefront's LDS stores before its later loads (other lanes').
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Record of a staged entry by its byte offset (entry number x 16).
@@ -128,7 +137,12 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
     }
     uint32_t vnext = (b + kBlendThreads + tid < e) ? vals[b + kBlendThreads + tid] : 0u;
     for (uint32_t start = b; start < e; start += kBlendThreads) {
-        if (__syncthreads_count(px.active) == 0) break;
+        // each wavefront notes whether it has an active pixel; the barrier also
+        // ends every walk of the previous batch before its records are replaced
+        const bool alive = __ballot(px.active) != 0;
+        if (lane == 0) reinterpret_cast<uint8_t *>(&sh.alive)[wid] = alive ? 1u : 0u;
+        __syncthreads();
+        if (sh.alive == 0u) break;
         stage_entry(sh, tid, start + tid < e, f0, f1, f2, bx0, by0);
         __syncthreads();
         // read ahead: records of the next batch, index of the one after
@@ -151,10 +165,14 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
             if (hit) sh.idx[wid][cnt + (uint32_t)__popcll(bal & lt)] = (uint16_t)((c * kWave + lane) * sizeof(float4));
             cnt += (uint32_t)__popcll(bal);
         }
-        __syncthreads();
+        // The entry list is this wavefront's own and the LDS operations of a
+        // wavefront complete in order: the walk needs no workgroup barrier,
+        // only the compiler must keep the list's stores before its loads.
+        wave_sync();
         // an odd last entry is paired with itself (never taken twice), so every
         // record read belongs to this batch
         if ((cnt & 1u) && lane == 0) sh.idx[wid][cnt] = sh.idx[wid][cnt - 1];
+        wave_sync();
         uint64_t am = __ballot(px.active);  // active pixels (uniform)
         if (am) {
             // The walk is uniform across the wavefront: entries k, k+1 are the
