@@ -129,13 +129,7 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
     const int tid = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
     float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0, f2 = f0;
-    if (b + tid < e) {
-        const float4 *sp = splat + 3 * (uint64_t)vals[b + tid];
-        f0 = sp[0];
-        f1 = sp[1];
-        f2 = sp[2];
-    }
-    uint32_t vnext = (b + kBlendThreads + tid < e) ? vals[b + kBlendThreads + tid] : 0u;
+    uint32_t vnext = 0;
     for (uint32_t start = b; start < e; start += kBlendThreads) {
         // each wavefront notes whether it has an active pixel; the barrier also
         // ends every walk of the previous batch before its records are replaced
@@ -143,6 +137,17 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
         if (lane == 0) reinterpret_cast<uint8_t *>(&sh.alive)[wid] = alive ? 1u : 0u;
         __syncthreads();
         if (sh.alive == 0u) break;
+        if (start == b) {
+            // the first batch is loaded only once a pixel is known to be active:
+            // a later chunk of a tile that its first chunk finished loads nothing
+            if (b + tid < e) {
+                const float4 *sp = splat + 3 * (uint64_t)vals[b + tid];
+                f0 = sp[0];
+                f1 = sp[1];
+                f2 = sp[2];
+            }
+            vnext = (b + kBlendThreads + tid < e) ? vals[b + kBlendThreads + tid] : 0u;
+        }
         stage_entry(sh, tid, start + tid < e, f0, f1, f2, bx0, by0);
         __syncthreads();
         // read ahead: records of the next batch, index of the one after
