@@ -263,13 +263,14 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
 // Workgroup b blends tile order[b]: the tiles with the longest first chunks
 // come first, so that their walks do not start last and leave the rest of the
 // chip idle.
-__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) blend_kernel(const FrameDev *__restrict__ fd,
+__global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ cbase,
                                                               const uint32_t *__restrict__ order,
                                                               float4 *__restrict__ scratch,
+                                                              uint32_t *__restrict__ need,
                                                               unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
@@ -285,11 +286,17 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
     const bool long_list = cb != kNoChunk && end - rg.x > (uint32_t)kChunkFirst;
     blend_range(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
                 px);
-    if (long_list)  // state after chunk 0; a negative T marks a finished pixel
+    if (long_list) {  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cb * kBlendThreads + g.pix] =
             make_float4(px.cr, px.cg, px.cb, px.active ? px.T : -px.T);
-    else
+        // need[] of chunk 0 (cleared by the fold) notes, one byte per
+        // wavefront, whether a pixel is still active: the later chunks of a
+        // finished tile do nothing
+        const bool any = __ballot(px.active) != 0;
+        if (lane == 0) reinterpret_cast<uint8_t *>(need + cb)[wid] = any ? 1u : 0u;
+    } else {
         write_pixel(cam, g, px, image);
+    }
     count_pairs(px, lane, pairs);
 }
 
@@ -304,6 +311,7 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
                                                               const uint2 *__restrict__ items,
                                                               const uint32_t *__restrict__ counters,
                                                               float4 *__restrict__ scratch,
+                                                              const uint32_t *__restrict__ need,
                                                               unsigned long long *__restrict__ pairs)
 {
     __shared__ BlendShared sh;
@@ -317,13 +325,16 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
         const TileGeo g = tile_geo(cam, tile, wid, lane);
         const uint2 rg = ranges[tile];
         const uint64_t base = cbase[tile];
+        if (need[base] == 0u) continue;  // every pixel finished in chunk 0 (uniform)
         const float4 s0 = scratch[base * kBlendThreads + g.pix];
         Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u};
         const bool was = px.active;
         blend_range(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
                     g.pyc, wid, lane, sh, px);
-        scratch[(base + c) * kBlendThreads + g.pix] =
-            make_float4(px.cr, px.cg, px.cb, (was && !px.active) ? -px.T : px.T);
+        // the fold reads later chunks only for pixels active after chunk 0
+        if (was)
+            scratch[(base + c) * kBlendThreads + g.pix] =
+                make_float4(px.cr, px.cg, px.cb, !px.active ? -px.T : px.T);
         count_pairs(px, lane, pairs);
         __syncthreads();  // the next item reuses the staged batch
     }
@@ -433,12 +444,12 @@ void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t
     const uint32_t n_tiles = tiles_x * tiles_y;
     constexpr uint64_t kMaxGrid = 1u << 20;  // beyond, workgroups loop over further items
     hipLaunchKernelGGL(blend_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, order,
-                       scratch, pairs);
+                       scratch, need, pairs);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
         const uint32_t gc = (uint32_t)(max_chunks < kMaxGrid ? max_chunks : kMaxGrid);
         hipLaunchKernelGGL(chunk_kernel, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, items,
-                           counters, scratch, pairs);
+                           counters, scratch, need, pairs);
         hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
                            need, rewalk, counters);
         hipLaunchKernelGGL(rewalk_kernel, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
