@@ -447,7 +447,10 @@ void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t
                        scratch, need, pairs);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
-        const uint32_t gc = (uint32_t)(max_chunks < kMaxGrid ? max_chunks : kMaxGrid);
+        // few chunks hold a stop to walk again: 2048 workgroups loop over them
+        // rather than one per chunk of the bound (mostly empty workgroups)
+        constexpr uint64_t kRewalkGrid = 2048;
+        const uint32_t gc = (uint32_t)(max_chunks < kRewalkGrid ? max_chunks : kRewalkGrid);
         hipLaunchKernelGGL(chunk_kernel, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, items,
                            counters, scratch, need, pairs);
         hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
