@@ -119,7 +119,8 @@ __device__ __forceinline__ void composite(float p, bool take, float log2o, const
 }
 
 // Composite keys [b, e) of the tile into the lanes' pixels (every thread of
-// the workgroup calls this with the same range).  The splat records of the
+// the workgroup calls this with the same range).  The first batch is loaded
+// once a pixel is known to be active; after that the splat records of the
 // next batch are gathered while the current one is walked, and the index of
 // the batch after that one is read ahead, so no walk waits on global memory.
 __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ splat,
