@@ -372,18 +372,33 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
     // small splats: this lane writes its own run
     if (nt && nt <= kSmallKeys) {
+        // keys left to write; a 32-bit index into the stage when the
+        // workgroup's range is assembled in LDS (uniform), else global stores
+        uint32_t left = nt;
+        uint32_t ol = staged ? (uint32_t)(off - sh.lo) : 0u;
         uint64_t o = off;
-        const uint64_t end = off + nt;
-        for (uint32_t ty = ty0; ty <= ty1 && o < end; ++ty) {
+        for (uint32_t ty = ty0; ty <= ty1 && left != 0u; ++ty) {
             uint32_t lo, hi;
             if (!tile_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
-            count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, sh.d0, sh.h, &sh.all);
-            for (uint32_t tx = lo; tx <= hi && o < end; ++tx) {
-                put_key(sh, staged, o, ty * tiles_x + tx, t, keys, vals);
-                ++o;
+            const uint32_t row = ty * tiles_x;
+            count_span(row + lo, row + hi, passes, sh.d0, sh.h, &sh.all);
+            const uint32_t m = min(hi - lo + 1u, left);
+            if (staged) {
+                for (uint32_t i = 0; i < m; ++i) {
+                    sh.key[ol + i] = row + lo + i;
+                    sh.val[ol + i] = t;
+                }
+                ol += m;
+            } else {
+                for (uint32_t i = 0; i < m; ++i) {
+                    keys[o + i] = (KT)(row + lo + i);
+                    vals[o + i] = t;
+                }
+                o += m;
             }
+            left -= m;
         }
-        if (o != end) atomicOr(err, kErrOverflow);  // counting and emission disagree
+        if (left != 0u) atomicOr(err, kErrOverflow);  // counting and emission disagree
     }
     // the largest splats: listed for emit_big_kernel
     if (nt > kBigKeys) big[atomicAdd(n_big, 1u)] = j;
