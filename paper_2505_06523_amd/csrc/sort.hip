@@ -570,9 +570,14 @@ void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 // digit histograms for all passes (one read of the keys).  Lanes holding the
 // same digit are matched by ballot and counted by one LDS atomic.
 // ---------------------------------------------------------------------------
+// 1,024 threads of a workgroup, kHistItems keys each per stride
+constexpr int kHistThreads = 1024;
+constexpr int kHistItems = 4;
+
 template <typename K>
-__global__ void __launch_bounds__(256) sort_hist_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
-                                                        uint64_t n_host, int passes, uint32_t *__restrict__ hist)
+__global__ void __launch_bounds__(kHistThreads) sort_hist_kernel(const K *__restrict__ keys,
+                                                                 const uint32_t *__restrict__ n_dev, uint64_t n_host,
+                                                                 int passes, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t s_h[8 * kRadix];
     for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x) s_h[i] = 0;
@@ -581,15 +586,25 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const K *__restrict__ ke
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // whole wavefronts iterate together so that ballots see every lane
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
-        const uint64_t i = base + lane;
-        const bool valid = i < n;
-        const K k = valid ? keys[i] : (K)0;
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t d = (uint32_t)(k >> (p * kRadixBits)) & (kRadix - 1);
-            const uint64_t peers = match_digit(d, valid);
-            if (valid && (peers & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(peers));
+    // whole wavefronts iterate together so that ballots see every lane; the
+    // keys of kHistItems strides are loaded before any is counted, so their
+    // loads are in flight together
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n;
+         base += stride * kHistItems) {
+        K kk[kHistItems];
+#pragma unroll
+        for (int u = 0; u < kHistItems; ++u) {
+            const uint64_t i = base + u * stride + lane;
+            kk[u] = i < n ? keys[i] : (K)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kHistItems; ++u) {
+            const bool valid = base + u * stride + lane < n;
+            for (int p = 0; p < passes; ++p) {
+                const uint32_t d = (uint32_t)(kk[u] >> (p * kRadixBits)) & (kRadix - 1);
+                const uint64_t peers = match_digit(d, valid);
+                if (valid && (peers & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(peers));
+            }
         }
     }
     __syncthreads();
@@ -601,9 +616,10 @@ template <typename K>
 void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist)
 {
     if (n == 0) return;
-    uint64_t blocks = (n + 256 * 16 - 1) / (256 * 16);
+    uint64_t blocks = (n + kHistThreads * kHistItems - 1) / (kHistThreads * kHistItems);
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((uint32_t)blocks), dim3(256), 0, st, keys, n_dev, n, passes, hist);
+    hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((uint32_t)blocks), dim3(kHistThreads), 0, st, keys, n_dev, n, passes,
+                       hist);
 }
 
 // ---------------------------------------------------------------------------
