@@ -99,7 +99,21 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
     if (p >= nparts) return;
     const uint64_t base = (uint64_t)p * kScanPart + (uint64_t)tid * kScanItems;
     uint32_t v[kScanItems];
-    if (order) {
+    if (order && base + kScanItems <= n) {
+        // a whole run: its ranks in 16-byte loads, then the gathers
+        const uint4 *src = reinterpret_cast<const uint4 *>(order + base);
+        uint32_t o[kScanItems];
+#pragma unroll
+        for (int j = 0; j < kScanItems / 4; ++j) {
+            const uint4 q = src[j];
+            o[4 * j] = q.x;
+            o[4 * j + 1] = q.y;
+            o[4 * j + 2] = q.z;
+            o[4 * j + 3] = q.w;
+        }
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) v[j] = tiles[o[j]];
+    } else if (order) {
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) v[j] = (base + j < n) ? tiles[order[base + j]] : 0u;
     } else if (base + kScanItems <= n) {
@@ -177,7 +191,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
     __syncthreads();
     const uint64_t b = s_prefix + t_excl;
     if ((b + tsum) >> 32) atomicOr(&counters[kRenErr], kErrOverflow);
-    if (!order && base + kScanItems <= n) {
+    if (base + kScanItems <= n) {
         uint4 *dst = reinterpret_cast<uint4 *>(offsets + base);
 #pragma unroll
         for (int j = 0; j < kScanItems / 4; ++j)
