@@ -40,7 +40,7 @@ BLEND_OPS_PER_PAIR = 22
 # (profiles/hbm_counters_1M_sh3_1080p.md).  Valid only for the blending source
 # they were taken on (blend.hip and the constants of v3dg_internal.h, such as
 # the chunk sizes): the bench reports null once either has changed.
-BLEND_TRAFFIC = dict(bytes_per_frame=391.9e6, blend_source_sha256_16="122432009c729812")
+BLEND_TRAFFIC = dict(bytes_per_frame=391.9e6, blend_source_sha256_16="979b8ec30b503cf1")
 
 
 def log(*a):

@@ -147,7 +147,7 @@ void launch_frame_setup(hipStream_t st, const CamArgs &cam, float *image, FrameD
                         const double *T, const float *inst_scale, uint32_t n_inst, InstRec *itab, uint32_t *clear,
                         uint64_t n_clear);
 constexpr int kSelThreads = 256;
-constexpr int kSelItems = 8;
+constexpr int kSelItems = 2;
 constexpr int kSelPart = kSelThreads * kSelItems;
 // View culling of cut clusters (optional).  A cluster whose rows' means lie
 // in the sphere sph (asset frame) and whose scales are at most smax cannot
