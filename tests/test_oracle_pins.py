@@ -418,3 +418,74 @@ def test_anisotropic_offaxis_splat_image(oracle_lib):
     ca, cb, cc = out["conic"][0]
     sa, sb, sc = out["cov2"][0]
     assert np.allclose(np.array([[ca, cb], [cb, cc]]) @ np.array([[sa, sb], [sb, sc]]), np.eye(2), atol=1e-9)
+
+
+def test_guard_band_clamps_the_jacobian(oracle_lib):
+    """Sec. 2.1 EWA splat with the 3DGS guard band: beyond |x/z| = 1.3 (W/2)/fx
+    (and |y/z| = 1.3 (H/2)/fy) the Jacobian is taken at the clamped point.
+    For an isotropic Gaussian of scale s under the identity camera,
+    J J^T = (f/z)^2 [[1 + ux^2, ux uy], [ux uy, 1 + uy^2]] with (ux, uy) the
+    clamped (x/z, y/z), so Sigma2 = s^2 (f/z)^2 [[1 + ux^2, ux uy], [ux uy, 1 + uy^2]]."""
+    f, W, Hh, z, s = 100.0, 64, 48, 2.0, 0.03
+    limx = 1.3 * (W / 2) / f  # 0.416
+    limy = 1.3 * (Hh / 2) / f  # 0.312
+    # (x/z, y/z): both clamped; x clamped on the negative side only; neither clamped
+    cases = [(0.6, -0.5), (-0.9, 0.1), (0.2, -0.25)]
+    pos = [[u * z, v * z, z] for u, v in cases]
+    asset = H.single_cluster_asset(pos, [[s] * 3] * 3, [[1, 0, 0, 0]] * 3, [0.5] * 3, [[[0, 0, 0]]] * 3)
+    out = oracle_lib.project(asset, sg.identity_instances(1), H.identity_camera(W, Hh, f), [0])
+    s32 = float(np.float32(s))
+    for i, (u, v) in enumerate(cases):
+        p = np.asarray(pos[i], np.float32).astype(np.float64)
+        ux = min(max(p[0] / p[2], -limx), limx)
+        uy = min(max(p[1] / p[2], -limy), limy)
+        k = s32 * s32 * (f / p[2]) ** 2
+        assert out["valid"][i] == 1
+        assert out["cov2"][i] == pytest.approx([k * (1 + ux * ux), k * ux * uy, k * (1 + uy * uy)], rel=1e-9)
+        # the mean is not clamped: it is the pinhole projection of the centre
+        assert out["mean2"][i] == pytest.approx([f * p[0] / p[2] + W / 2, f * p[1] / p[2] + Hh / 2], rel=1e-12)
+    # the first case really is outside the band on both axes, the last inside
+    assert abs(cases[0][0]) > limx and abs(cases[0][1]) > limy
+    assert abs(cases[2][0]) < limx and abs(cases[2][1]) < limy
+
+
+def test_far_plane_culls(oracle_lib):
+    """A splat is kept only for near < z < far (FP32 depth), so z = far and
+    beyond are culled while z just in front of the far plane is kept."""
+    far = 50.0
+    zs = [49.0, 50.0, 51.0, 1.0]
+    asset = H.single_cluster_asset([[0, 0, z] for z in zs], [[0.5] * 3] * 4, [[1, 0, 0, 0]] * 4, [0.5] * 4,
+                                   [[[0, 0, 0]]] * 4)
+    out = oracle_lib.project(asset, sg.identity_instances(1), H.identity_camera(far=far), [0])
+    assert out["valid"].tolist() == [1, 0, 0, 1]
+
+
+def _sh1_asset(coef_m_neg1, coef_m_pos1):
+    """One Gaussian at the origin, SH degree 1 with DC 0 and two l = 1
+    coefficients: index 1 (m = -1, the y term) and index 3 (m = +1, the x term)."""
+    sh = np.zeros((1, 4, 3), np.float32)
+    sh[0, 1] = coef_m_neg1
+    sh[0, 3] = coef_m_pos1
+    return H.single_cluster_asset([[0, 0, 0]], [[0.05] * 3], [[1, 0, 0, 0]], [0.6], sh, sh_degree=1)
+
+
+def test_sh_view_direction_and_asset_frame(oracle_lib):
+    """View-dependent colour (Sec. 2.1): the SH are evaluated at the unit
+    direction from the camera centre to the Gaussian, p - c, in the asset's
+    own frame.  With Y_1,-1 = -c1 y and Y_1,1 = -c1 x (c1 = sqrt(3 / 4 pi)):
+      camera at +5 x, identity instance: d = (-1, 0, 0), so only the m = +1
+        term is lit, with Y = +c1;
+      the same camera, asset yawed by +90 deg about z: the camera sits at
+        (0, -5, 0) in the asset frame, d = (0, 1, 0), so only the m = -1
+        term is lit, with Y = -c1."""
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    a = 0.4
+    asset = _sh1_asset([a, 0, 0], [0, a, 0])
+    cam = sg.look_at((5.0, 0.0, 0.0), (0.0, 0.0, 0.0), 64, 64, 1.0)
+    out = oracle_lib.project(asset, sg.identity_instances(1), cam, [0])
+    assert out["valid"][0] == 1
+    assert out["rgb"][0] == pytest.approx([0.5, 0.5 + a * c1, 0.5], abs=1e-7)
+    yaw = np.array([[[0.0, -1.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0]]])
+    out = oracle_lib.project(asset, yaw, cam, [0])
+    assert out["valid"][0] == 1
+    assert out["rgb"][0] == pytest.approx([0.5 - a * c1, 0.5, 0.5], abs=1e-7)
