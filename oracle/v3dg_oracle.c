@@ -266,7 +266,8 @@ typedef struct {
     double mx, my, ca, cb, cc, r, g, b, o, sxx, sxy, syy;
 } orc_splat;
 
-/* One Gaussian through one instance (Sec. 2.1, EWA splatting):
+/* One Gaussian through one instance (Sec. 2.1, EWA splatting); the colour
+ * is computed by orc_colour_one:
  *   camera-space mean m = A p; the cull and the sort key use the FP32 depth
  *   z32 = ((a20*px + a21*py) + a22*pz) + a23 (near < z32 < far);
  *   Sigma = R(q) diag(s^2) R(q)^T;  Sigma_cam = W Sigma W^T, W = A's 3x3;
@@ -356,6 +357,12 @@ static void orc_project_one(const orc_asset *a, const float *A, const double *ch
     o->mx = fx * x / z + (double)cam->cx;
     o->my = fy * y / z + (double)cam->cy;
     o->o = a->opacity[row];
+}
+
+/* The colour of a valid splat (see orc_project_one). */
+static void orc_colour_one(const orc_asset *a, const double *chat, uint32_t row, orc_splat *o)
+{
+    const float *p = a->pos + 3 * (size_t)row;
     int deg = (int)a->sh_degree, nc = (deg + 1) * (deg + 1);
     double dir[3] = {(double)p[0] - chat[0], (double)p[1] - chat[1], (double)p[2] - chat[2]};
     double Y[16];
@@ -372,7 +379,8 @@ static void orc_project_one(const orc_asset *a, const float *A, const double *ch
 typedef struct {
     uint64_t n_slots, n_valid;
     orc_splat *sp;       /* per slot */
-    uint64_t *order;     /* valid slots, sorted by (depth, slot) */
+    uint64_t n_order;    /* entries of order[] */
+    uint64_t *order;     /* valid slots (with the index: those whose box meets the image), by (depth, slot) */
     /* bucket index */
     uint32_t bw, bh, nbx, nby;
     uint64_t *bstart;    /* nbx*nby+1 */
@@ -425,20 +433,74 @@ static int orc_prepare(const orc_asset *a, uint32_t n_inst, const double *T, con
     uint32_t *inst = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
     uint32_t *row = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
     orc_build_slots(a, n_gids, gids, inst, row);
-    f->sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
+    uint64_t nv = 0, nvalid = 0;
+    if (!use_index) {
+        f->sp = (orc_splat *)malloc(sizeof(orc_splat) * (n ? n : 1));
 #pragma omp parallel for schedule(static)
-    for (int64_t t = 0; t < (int64_t)n; ++t)
-        orc_project_one(a, A + 12 * (size_t)inst[t], ch + 3 * (size_t)inst[t], cam, row[t], &f->sp[t]);
+        for (int64_t t = 0; t < (int64_t)n; ++t) {
+            const double *cht = ch + 3 * (size_t)inst[t];
+            orc_project_one(a, A + 12 * (size_t)inst[t], cht, cam, row[t], &f->sp[t]);
+            if (f->sp[t].valid) orc_colour_one(a, cht, row[t], &f->sp[t]);
+        }
+        f->order = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
+        for (uint64_t t = 0; t < n; ++t)
+            if (f->sp[t].valid) f->order[nv++] = t;
+        nvalid = nv;
+    } else {
+        /* With the index, a slot whose box misses the image is in no pixel's
+         * bucket list, so it is left out altogether: its record is not kept
+         * and it is not sorted.  The kept records are stored in slot order
+         * (their positions order them as their slots do), so the same pixels
+         * visit the same splats in the same order.  Two passes over fixed
+         * blocks of slots: count the kept ones, then store them. */
+        const uint64_t blk = 1u << 16, nb = (n + blk - 1) / blk;
+        uint64_t *bcnt = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+        uint64_t *bval = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t b = 0; b < (int64_t)nb; ++b) {
+            uint64_t kept = 0, valid = 0;
+            for (uint64_t t = (uint64_t)b * blk; t < n && t < (uint64_t)(b + 1) * blk; ++t) {
+                orc_splat sp;
+                int x0, x1, y0, y1;
+                orc_project_one(a, A + 12 * (size_t)inst[t], ch + 3 * (size_t)inst[t], cam, row[t], &sp);
+                valid += sp.valid;
+                kept += (uint64_t)orc_box(&sp, cam, &x0, &x1, &y0, &y1);
+            }
+            bcnt[b + 1] = kept;
+            bval[b + 1] = valid;
+        }
+        for (uint64_t b = 0; b < nb; ++b) {
+            bcnt[b + 1] += bcnt[b];
+            nvalid += bval[b + 1];
+        }
+        nv = bcnt[nb];
+        f->sp = (orc_splat *)malloc(sizeof(orc_splat) * (nv ? nv : 1));
+        f->order = (uint64_t *)malloc(sizeof(uint64_t) * (nv ? nv : 1));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t b = 0; b < (int64_t)nb; ++b) {
+            uint64_t j = bcnt[b];
+            for (uint64_t t = (uint64_t)b * blk; t < n && t < (uint64_t)(b + 1) * blk; ++t) {
+                orc_splat sp;
+                int x0, x1, y0, y1;
+                const double *cht = ch + 3 * (size_t)inst[t];
+                orc_project_one(a, A + 12 * (size_t)inst[t], cht, cam, row[t], &sp);
+                if (!orc_box(&sp, cam, &x0, &x1, &y0, &y1)) continue;
+                orc_colour_one(a, cht, row[t], &sp);
+                f->sp[j] = sp;
+                f->order[j] = j;
+                ++j;
+            }
+        }
+        free(bcnt);
+        free(bval);
+    }
     free(inst);
     free(row);
     free(A);
     free(sc);
     free(ch);
-    f->order = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
-    uint64_t nv = 0;
-    for (uint64_t t = 0; t < n; ++t)
-        if (f->sp[t].valid) f->order[nv++] = t;
-    f->n_valid = nv;
+    f->n_valid = nvalid;
+    f->n_order = nv;
     /* stable order by FP32 depth; equal depths keep slot order */
     g_sort_sp = f->sp;
     qsort(f->order, nv, sizeof(uint64_t), orc_cmp);
@@ -499,7 +561,7 @@ static void orc_pixel(const orc_frame *f, const orc_camera *cam, int px, int py,
         lst = f->blist;
     } else {
         j0 = 0;
-        j1 = f->n_valid;
+        j1 = f->n_order;
     }
     uint8_t ambiguous = 0;
     uint64_t np = 0;
