@@ -9,7 +9,11 @@
  *   2. compacts the chosen clusters' Gaussians into a slot stream,
  *   3. projects each Gaussian to a 2D conic and colour (3D Gaussian splat of
  *       Sec. 2.1, no 2D dilation as in Sec. 5.1),
- *   4. bins the splats to 16x16 tiles and radix-sorts 64-bit (tile, depth) keys,
+ *   4. bins the splats to 16x16 tiles and puts every tile's splats in depth
+ *       order: a stable radix sort of the slots by FP32 depth, then tile ids
+ *       emitted in that order (16-bit up to 65,536 tiles, else 32-bit) and
+ *       stably radix-sorted (the same order as 64-bit (tile, depth) keys, which
+ *       remain selectable with v3dg_set_sort_mode),
  *   5. alpha-composites every tile front to back (Sec. 2.1).
  * All device work runs as HIP kernels on the stream given at load time.
  *
@@ -96,9 +100,10 @@ typedef struct {
 } v3dg_hierarchy_desc;
 
 /* How each tile's splats are put in front-to-back order (same result):
- * DEPTH_FIRST sorts the slots by FP32 depth, emits 32-bit tile ids in that
- * order and stably sorts them by tile; KEYS64 emits (tile << 32 | depth bits)
- * keys in slot order and sorts all their significant bits. */
+ * DEPTH_FIRST sorts the slots by FP32 depth, emits tile ids in that order
+ * (16-bit on grids of up to 65,536 tiles, 32-bit beyond) and stably sorts them
+ * by tile; KEYS64 emits (tile << 32 | depth bits) keys in slot order and sorts
+ * all their significant bits. */
 #define V3DG_SORT_DEPTH_FIRST 0
 #define V3DG_SORT_KEYS64 1
 
@@ -110,6 +115,12 @@ typedef struct {
     uint32_t key_bits;   /* significant bits of the (last) sort key        */
     uint32_t sort_passes;/* radix passes of the tile / 64-bit key sort     */
     uint32_t sort_mode;  /* V3DG_SORT_*                                    */
+    uint32_t n_fp64_conics;    /* splats whose 2D covariance determinant fell below
+                                  1e-6 px^4 and was redone in FP64               */
+    uint32_t n_conics_clamped; /* splats with a conic entry beyond 1e38 in
+                                  magnitude, stored as +-1e38 (thinner than
+                                  ~1e-19 px across: an axis-aligned needle still
+                                  covers the pixel centres it runs through)      */
 } v3dg_frame_stats;
 
 /* Kernel stages timed when profiling is on (v3dg_set_profiling). */
@@ -278,6 +289,7 @@ int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
  * allocates its own temporary buffers. */
 int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, void *hip_stream);
 
+
 /* ---- serving ----------------------------------------------------------------
  * A server renders camera requests against several resident scenes with
  * several frames in flight (continuous batching).  Requests queue on the host;
@@ -341,7 +353,8 @@ int v3dg_server_submit(v3dg_server *srv, uint32_t scene, const v3dg_camera *cam,
 
 /* Retire finished frames (up to cap records into done[], count in *n_done),
  * then admit and launch queued requests.  wait != 0 blocks until at least one
- * frame has finished when any is in flight. */
+ * frame has finished when any is in flight; it needs cap >= 1
+ * (V3DG_ERR_INVALID_ARG otherwise). */
 int v3dg_server_poll(v3dg_server *srv, int wait, v3dg_request_done *done, uint32_t cap, uint32_t *n_done);
 
 int v3dg_server_get_stats(v3dg_server *srv, v3dg_server_stats *out);

@@ -103,8 +103,8 @@ __device__ __forceinline__ void composite(float p, bool take, float log2o, const
                                           float &cg, float &cb)
 {
     // the exponent lies in [log2(1/255), 0]: the hardware exp2 is exact enough
-    // min(p, 0) as one integer min on the bit pattern (p is never NaN; a
-    // negative float is a negative integer, -0 gives the same exponent as 0)
+    // min(p, 0) as one integer min on the bit pattern (a negative float is a
+    // negative integer, -0 gives the same exponent as 0; a NaN p is never taken)
     const float ex = __builtin_amdgcn_exp2f(__int_as_float(min(__float_as_int(p), 0)) + log2o);
     const float alpha = take ? fminf(0.99f, ex) : 0.0f;
     const float Tn = fmaf(-alpha, T, T);
@@ -201,7 +201,9 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
                 // p = (a dx + b dy) dx + c dy^2
                 const float p0 = fmaf(fmaf(a0.z, dx0, a0.w * dy0), dx0, c0.x * dy0 * dy0);
                 const float p1 = fmaf(fmaf(a1.z, dx1, a1.w * dy1), dx1, c1.x * dy1 * dy1);
-                const bool pass0 = !(p0 < c0.y), pass1 = two && !(p1 < c1.y);  // alpha >= 1/255
+                // alpha >= 1/255; a NaN quadratic form (0 times a clamped conic
+                // entry of a needle thinner than FP32 resolves) is not taken
+                const bool pass0 = p0 >= c0.y, pass1 = two && p1 >= c1.y;
                 uint64_t amid = am;  // active after entry k
                 if (__ballot(T > 0.0f && (pass0 || pass1)) != 0) {
                     const float4 col0 = rec(sh.P2, o0), col1 = rec(sh.P2, o1);

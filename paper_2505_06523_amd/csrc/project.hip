@@ -5,7 +5,7 @@
 // Sec. 5.1).  With M = J W R(q) diag(s) (2x3), the 2D covariance is M M^T, so
 // its entries are dot products of M's rows and its determinant is the squared
 // length of their cross product: no cancellation in det even for thin splats.
-// Splats with det below 1e-6 are redone in FP64.
+// Splats with det below 1e-6 are redone in FP64 (counted per frame).
 //
 // Outputs per slot: the splat record read by blending, the FP32 depth used as
 // the sort key, and the conservative tile rectangle of the support
@@ -85,6 +85,7 @@ __device__ __forceinline__ float depth_z(const float *A, float px, float py, flo
 struct Cov2d {
     double a, b, c, det;
 };
+constexpr double kBinEps2 = 1e-12;
 
 __device__ __noinline__ Cov2d cov2_fp64(const InstRec *__restrict__ ir, const FrameDev *__restrict__ fd, float px,
                                         float py, float pz, float4 q4, float sx, float sy, float sz)
@@ -229,14 +230,29 @@ __global__ void __launch_bounds__(256) project_kernel(const FrameDev *__restrict
         } else {
             const Cov2d r = cov2_fp64(itab + inst, fd, px, py, pz, make_float4(q[0], q[1], q[2], q[3]), s[0], s[1], s[2]);
             if (!(r.det > 0.0)) continue;
+            atomicAdd(&out.counters[kRenFp64], 1u);
             const double inv = 1.0 / r.det;
             ca = (float)(r.c * inv);
             cb = (float)(-r.b * inv);
             cc = (float)(r.a * inv);
-            a = (float)r.a;
+            // The binning record takes Sigma + eps I (eps = 1e-12 px^2): its
+            // support contains this splat's, and every entry and the
+            // determinant stay normal FP32 numbers, so the per-row tile spans
+            // keep full precision even for a needle of subnormal width.
+            a = (float)(r.a + kBinEps2);
             b = (float)r.b;
-            c = (float)r.c;
-            det_s = (float)r.det;
+            c = (float)(r.c + kBinEps2);
+            det_s = (float)(r.det + kBinEps2 * (r.a + r.c) + kBinEps2 * kBinEps2);
+        }
+        // A conic entry beyond +-kConicMax (a splat thinner than ~1e-19 px
+        // across, or one overflowing FP32) is clamped: blending then still
+        // draws an axis-aligned needle on the pixel row or column it runs
+        // through, and elsewhere its quadratic form overflows (no contribution).
+        if (!(fabsf(ca) <= kConicMax && fabsf(cb) <= kConicMax && fabsf(cc) <= kConicMax)) {
+            atomicAdd(&out.counters[kRenConicClamp], 1u);
+            ca = fminf(fmaxf(ca, -kConicMax), kConicMax);
+            cb = fminf(fmaxf(cb, -kConicMax), kConicMax);
+            cc = fminf(fmaxf(cc, -kConicMax), kConicMax);
         }
         const float mx = cam.fx * (x * rz) + cam.cx;
         const float my = cam.fy * (y * rz) + cam.cy;

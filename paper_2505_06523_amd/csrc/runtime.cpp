@@ -722,7 +722,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         HIP_TRY(hipMemcpyAsync(c->rcounters + kRenSlots, n_dev, sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
         n_dev = c->rcounters + kRenSlots;
     }
-    ProjectOut po{c->splat, c->depth, c->bin, c->rect, c->tiles, c->dkey[0], c->dval[0]};
+    ProjectOut po{c->splat, c->depth, c->bin, c->rect, c->tiles, c->dkey[0], c->dval[0], c->rcounters};
     {
         Stage st(c, V3DG_STAGE_PROJECT);
         launch_project(c->stream, c->fdev, sc->attribs(), (int)sc->precision, (int)sc->sh_degree, sel.slot_row,
@@ -1491,11 +1491,15 @@ int v3dg_get_frame_stats(v3dg_scene *s, v3dg_frame_stats *out)
     if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
     HIP_TRY(hipSetDevice(s->device));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    uint32_t err = 0;
-    if (s->rcounters) HIP_TRY(hipMemcpy(&err, s->rcounters + kRenErr, sizeof(err), hipMemcpyDeviceToHost));
+    static_assert(kRenErr < 32 && kRenFp64 < 32 && kRenConicClamp < 32, "frame stats read the first 32 counters");
+    uint32_t ctr[32] = {0};
+    if (s->rcounters) HIP_TRY(hipMemcpy(ctr, s->rcounters, sizeof(ctr), hipMemcpyDeviceToHost));
+    const uint32_t err = ctr[kRenErr];
     if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
     if (err & kErrOverflow) return fail(V3DG_ERR_DEVICE, "tile counting and key emission disagreed");
     *out = s->last;
+    out->n_fp64_conics = ctr[kRenFp64];
+    out->n_conics_clamped = ctr[kRenConicClamp];
     return V3DG_OK;
 }
 
@@ -2093,6 +2097,7 @@ int v3dg_server_poll(v3dg_server *s, int wait, v3dg_request_done *done, uint32_t
 {
     g_err.clear();
     if (!s || !n_done || (cap && !done)) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
+    if (wait && cap == 0) return fail(V3DG_ERR_INVALID_ARG, "a waiting poll needs room for one record (cap >= 1)");
     HIP_TRY(hipSetDevice(s->device));
     *n_done = 0;
     // ---- retire

@@ -83,6 +83,8 @@ enum RenderCounter : int {
     kRenTicketDepth = 16, // 4 passes of the depth sort
     kRenFront = 20,       // tiles placed at the front of the blend order (long lists)
     kRenBack = 21,        // tiles placed at its back
+    kRenFp64 = 22,        // splats whose 2D covariance was redone in FP64 (det < 1e-6)
+    kRenConicClamp = 23,  // splats with a conic entry clamped to +-kConicMax
     kRenHist = 32,        // 8 passes x 256 bins
     kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
     kRenKeysEff = 32 + 12 * 256,   // keys the frame's buffers hold: min(total, capacity)
@@ -213,7 +215,11 @@ struct ProjectOut {
     uint32_t *tiles;    // tiles the support reaches (0 = culled)
     uint32_t *dkey;     // depth sort key: FP32 depth bits, 0xffffffff when culled
     uint32_t *dval;     // slot index (sort payload)
+    uint32_t *counters; // render counters (kRenFp64, kRenConicClamp)
 };
+// Largest conic entry stored for blending: the conic is scaled by -log2(e)
+// when staged, which must stay finite.
+constexpr float kConicMax = 1.0e38f;
 void launch_project(hipStream_t st, const FrameDev *fd, const Attribs &attr, int precision, int sh_degree,
                     const uint32_t *slot_row, const uint32_t *slot_inst, const uint32_t *n_slots_dev,
                     uint64_t max_slots, const InstRec *itab, ProjectOut out);

@@ -420,10 +420,18 @@ def test_c2_image_sampled_parity(c2, torch):
         assert psnr(got[None], ref[None]) >= MIN_PSNR
 
 
-def test_c3_selection_bitexact_flythrough(c2, torch):
+@pytest.fixture(scope="module")
+def c3(c2):
+    """100 instances of the 1M-leaf asset on a 10 x 10 grid (about 105M virtual leaves)."""
     a, _ = c2
     T = sg.grid_instances(10, 1.5, 0.2, 3)
     sc = v.Scene(a, T)
+    yield a, T, sc
+    sc.close()
+
+
+def test_c3_selection_bitexact_flythrough(c3, torch):
+    a, T, sc = c3
     cams = sg.flythrough_cameras(300, 103)
     sel = None
     for f in [0, 37, 150, 299]:
@@ -432,7 +440,34 @@ def test_c3_selection_bitexact_flythrough(c2, torch):
         assert np.array_equal(sel.ids(), ref), f
         nc, ng = sel.info()
         _say("c3 frame %d: %d clusters, %d Gaussians selected" % (f, nc, ng))
-    sc.close()
+
+
+@pytest.mark.parametrize("frame,cull", [(37, False), (150, True)])
+def test_c3_image_sampled_parity(c3, torch, frame, cull):
+    """Fly-through frames of the composed scene at 1920x1080, tolerance 1:
+    sampled pixels against the oracle (which projects all ~105M slots)."""
+    a, T, sc = c3
+    cam = sg.flythrough_cameras(300, 103)[frame]
+    sc.set_culling(cull)
+    try:
+        sel = sc.select(cam, 1.0)
+        img = sc.render(cam, sel).cpu().numpy()
+        st = sc.frame_stats()
+    finally:
+        sc.set_culling(False)
+    rng = np.random.default_rng(frame)
+    pix = np.stack([rng.integers(0, cam.width, 3000), rng.integers(0, cam.height, 3000)], axis=1).astype(np.uint32)
+    ref, amb, ost = oracle.render_pixels(a, T, cam, sel.ids(), pix)
+    got = img[pix[:, 1], pix[:, 0]]
+    ok = amb == 0
+    err = np.abs(got - ref)[ok].max()
+    lit = int((ref[:, 3] > 0.01).sum())
+    _say("c3 frame %d (culling %s): %d slots projected (oracle %d), %d keys, sampled max_abs %.3g amb %d, "
+         "%d sampled pixels covered" % (frame, cull, st["n_slots"], ost["n_slots"], st["n_keys"], err,
+                                        int((~ok).sum()), lit))
+    assert lit > 300  # the frame shows the scene
+    assert err <= MAX_ABS
+    assert psnr(got[None], ref[None]) >= MIN_PSNR
 
 
 def test_large_splats_and_32bit_tile_ids(torch):

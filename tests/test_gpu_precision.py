@@ -131,3 +131,35 @@ def test_c2_narrow_tier_sampled_parity(torch):
         assert err <= MAX_ABS
         assert psnr(got[None], ref[None]) >= MIN_PSNR
     sc.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16_bf16sh"])
+def test_c2_3840x2160_sampled_parity(torch, precision):
+    """The 1M-leaf SH3 asset at 3840x2160 (32,400 tiles), FP32 and FP16 +
+    BF16-SH storage, against the oracle on the stored attributes."""
+    import dataclasses
+    a = sg.cached_asset(1 << 20, 3, 2)
+    aq = H.quantized_asset(a, precision)
+    sc = v.Scene(a, precision=precision)
+    T = sg.identity_instances(1)
+    cams = sg.orbit_cameras(64, 102)
+    rng = np.random.default_rng(9)
+    for ci, tau in [(3, 1.0), (40, 4.0)]:
+        c = cams[ci]
+        cam = dataclasses.replace(c, width=2 * c.width, height=2 * c.height, fx=2 * c.fx, fy=2 * c.fy,
+                                  cx=2 * c.cx, cy=2 * c.cy)
+        sel = sc.select(cam, tau)
+        assert np.array_equal(sel.ids(), oracle.mask_to_gids(oracle.select_walk(a, T, cam, tau)))
+        img = sc.render(cam, sel).cpu().numpy()
+        st = sc.frame_stats()
+        assert st["n_tiles"] == 240 * 135
+        pix = np.stack([rng.integers(0, cam.width, 3000), rng.integers(0, cam.height, 3000)], axis=1).astype(np.uint32)
+        ref, amb, _ = oracle.render_pixels(aq, T, cam, sel.ids(), pix)
+        got = img[pix[:, 1], pix[:, 0]]
+        ok = amb == 0
+        err = np.abs(got - ref)[ok].max()
+        _say("c2 %s 3840x2160 cam %d tau %g: %d keys, sampled max_abs %.3g amb %d, psnr %.1f"
+             % (precision, ci, tau, st["n_keys"], err, int((~ok).sum()), psnr(got[None], ref[None])))
+        assert err <= MAX_ABS
+        assert psnr(got[None], ref[None]) >= MIN_PSNR
+    sc.close()

@@ -1,17 +1,20 @@
 """The serving path (v3dg_server_*) through the C ABI.
 
 Every request's image must equal, bit for bit, what v3dg_select +
-v3dg_render produce for it alone (whose parity with the oracle the other GPU
-tests establish), whatever the mix of scenes, image sizes and tolerances in
-flight, with and without graph replay, and after key-capacity retries.
+v3dg_render produce for it alone, whatever the mix of scenes, image sizes and
+tolerances in flight, with and without graph replay, and after key-capacity
+retries.  Served images are also checked against the oracle directly: whole
+small frames, and sampled pixels of mixed-resolution requests (up to
+3840x2160) on scenes shaped like the serving workload's.
 """
 import numpy as np
 import pytest
 
+import oracle
 import paper_2505_06523_amd as v
 import scenegen as sg
 from tests import helpers as H
-from tests.test_gpu_parity import _say
+from tests.test_gpu_parity import MAX_ABS, MIN_PSNR, _say, check_image, psnr
 
 pytestmark = pytest.mark.gpu
 
@@ -25,11 +28,15 @@ def torch():
 
 
 @pytest.fixture(scope="module")
-def scenes(torch):
-    a0 = sg.make_asset(16384, 0, 1)
-    a1 = sg.make_asset(8192, 3, 31)
-    a2 = H.stacked_splats(6000, 5, (0.05, 0.5))
-    out = [v.Scene(a0), v.Scene(a1, sg.grid_instances(2, 1.0, 0.2, 5)), v.Scene(a2)]
+def worlds():
+    return [(sg.make_asset(16384, 0, 1), sg.identity_instances(1)),
+            (sg.make_asset(8192, 3, 31), sg.grid_instances(2, 1.0, 0.2, 5)),
+            (H.stacked_splats(6000, 5, (0.05, 0.5)), sg.identity_instances(1))]
+
+
+@pytest.fixture(scope="module")
+def scenes(torch, worlds):
+    out = [v.Scene(a, T) for a, T in worlds]
     yield out
     for sc in out:
         sc.close()
@@ -166,6 +173,78 @@ def test_server_invalid_arguments(scenes, torch):
     with pytest.raises(v.V3DGError):
         srv.submit(0, bad, 1.0)
     assert srv.poll() == []
+    # a waiting poll with no room for a record is refused (it could never return one)
+    with pytest.raises(v.V3DGError) as ei:
+        v.v3dg_server_poll(srv.handle, True, cap=0)
+    assert ei.value.code == v.V3DG_ERR_INVALID_ARG
+    assert v.v3dg_server_poll(srv.handle, False, cap=0) == []
     srv.close()
     with pytest.raises(v.V3DGError):
         v.Server(scenes, n_contexts=0)
+
+
+def test_served_images_match_the_oracle(scenes, worlds, torch):
+    """Whole served frames (three scenes, three image sizes, three tolerances,
+    graph replay) against the FP64 oracle."""
+    rng = np.random.default_rng(23)
+    reqs = _requests(rng, 12)
+    srv = v.Server(scenes, n_contexts=4, max_batch=8, use_graphs=True)
+    tickets = {}
+    for i, (k, cam, tau) in enumerate(reqs):
+        t, _ = srv.submit(k, cam, tau)
+        tickets[t] = i
+    done = srv.drain()
+    assert len(done) == len(reqs)
+    for r in done:
+        i = tickets[r["ticket"]]
+        k, cam, tau = reqs[i]
+        a, T = worlds[k]
+        assert r["status"] == 0
+        gids = oracle.mask_to_gids(oracle.select_walk(a, T, cam, tau))
+        ref, amb, _ = oracle.render(a, T, cam, gids)
+        check_image(r["image"].cpu().numpy(), ref, amb, "served %d (scene %d, %dx%d, tau %g)"
+                    % (i, k, cam.width, cam.height, tau))
+    srv.close()
+
+
+def test_served_mixed_resolutions_sampled_against_the_oracle(torch):
+    """The first two scenes of the serving workload (1M and 2M leaves: rigid
+    copies of 262,144-leaf SH3 bases), Poisson-style requests at 1280x720,
+    1920x1080 and 3840x2160 with tolerances 1 and 4, all in flight together:
+    sampled pixels of every served image against the oracle."""
+    gen = sg.serving_scenes()
+    worlds = [next(gen) for _ in range(2)]
+    gen.close()
+    scs = [v.Scene(a) for a, _, _ in worlds]
+    extents = [L for _, _, L in worlds]
+    reqs = sg.serving_requests(8, 0.0, extents, seed=77)
+    srv = v.Server(scs, n_contexts=4, max_batch=8, use_graphs=True)
+    tickets = {}
+    for i, r in enumerate(reqs):
+        t, _ = srv.submit(r["scene"], r["cam"], r["tau"])
+        tickets[t] = i
+    done = srv.drain()
+    assert len(done) == len(reqs)
+    sizes = set()
+    rng = np.random.default_rng(78)
+    for d in done:
+        i = tickets[d["ticket"]]
+        r = reqs[i]
+        cam, a = r["cam"], worlds[r["scene"]][0]
+        T = sg.identity_instances(1)
+        assert d["status"] == 0
+        sizes.add((cam.width, cam.height))
+        gids = oracle.mask_to_gids(oracle.select_walk(a, T, cam, r["tau"]))
+        pix = np.stack([rng.integers(0, cam.width, 2000), rng.integers(0, cam.height, 2000)], axis=1).astype(np.uint32)
+        ref, amb, _ = oracle.render_pixels(a, T, cam, gids, pix)
+        got = d["image"].cpu().numpy()[pix[:, 1], pix[:, 0]]
+        ok = amb == 0
+        err = np.abs(got - ref)[ok].max()
+        _say("served %d: scene %d %dx%d tau %g, %d slots, sampled max_abs %.3g psnr %.1f"
+             % (i, r["scene"], cam.width, cam.height, r["tau"], d["n_slots"], err, psnr(got[None], ref[None])))
+        assert d["n_slots"] == int(a.count[gids % a.n_clusters].sum())
+        assert err <= MAX_ABS and psnr(got[None], ref[None]) >= MIN_PSNR
+    assert len(sizes) >= 2
+    srv.close()
+    for sc in scs:
+        sc.close()

@@ -3,15 +3,17 @@
 A streamed scene keeps its rows on the host and pages the clusters of each
 cut into a pool of 64-row pages.  Its cuts and images must equal the resident
 scene's bit for bit, whatever the pool size and history of evictions; slots
-differ only in naming pool rows that hold the same Gaussians.
+differ only in naming pool rows that hold the same Gaussians.  Frames taken
+after evictions are also checked against the oracle directly.
 """
 import numpy as np
 import pytest
 
+import oracle
 import paper_2505_06523_amd as v
 import scenegen as sg
 from tests import helpers as H
-from tests.test_gpu_parity import _say
+from tests.test_gpu_parity import MAX_ABS, MIN_PSNR, _say, check_image, psnr
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +132,11 @@ def test_a_paged_out_selection_is_refused(torch, world):
     assert torch.equal(img, res.render(mid, s_ref).clone())
     stats = st.stream_stats()
     assert stats["last_pages_in"] == 198 and stats["evictions"] == 1, stats
+    # the evicting frame against the oracle directly
+    gids = oracle.mask_to_gids(oracle.select_walk(a, T, mid, 1e3))
+    assert np.array_equal(s.ids(), gids)
+    ref, amb, _ = oracle.render(a, T, mid, gids)
+    check_image(img.cpu().numpy(), ref, amb, "streamed, evicting")
     with pytest.raises(v.V3DGError) as e:
         st.render(far, s_far)
     assert e.value.code == v.V3DG_ERR_INVALID_ARG and "paged out" in str(e.value)
@@ -169,6 +176,18 @@ def test_streamed_walk_full_size(torch):
     _say("1M walk streamed: %d frames equal, %d pages in, %d evictions" % (len(cams), stats["pages_in"],
                                                                          stats["evictions"]))
     assert stats["evictions"] > 0
+    # the last streamed frame (after evictions) against the oracle, sampled
+    cam = cams[-1]
+    gids = oracle.mask_to_gids(oracle.select_walk(a, sg.identity_instances(1), cam, 1.0))
+    assert np.array_equal(s1.ids(), gids)
+    rng = np.random.default_rng(12)
+    pix = np.stack([rng.integers(0, cam.width, 3000), rng.integers(0, cam.height, 3000)], axis=1).astype(np.uint32)
+    ref, amb, _ = oracle.render_pixels(a, sg.identity_instances(1), cam, gids, pix)
+    got = img1.cpu().numpy()[pix[:, 1], pix[:, 0]]
+    ok = amb == 0
+    err = np.abs(got - ref)[ok].max()
+    _say("1M walk streamed, last frame: sampled max_abs %.3g, psnr %.1f" % (err, psnr(got[None], ref[None])))
+    assert err <= MAX_ABS and psnr(got[None], ref[None]) >= MIN_PSNR
     res.close()
     st.close()
 
