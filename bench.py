@@ -20,27 +20,28 @@ import sys
 import time
 
 METRIC = "FPS at 1080p, V3DG-selected vs full-detail on same GPU; p50/p99 frame ms"
-WORKLOAD = ("1,048,576-leaf SH3 asset (1,398,080 rows, 21,845 clusters), 1920x1080, fov_x pi/4, "
-            "64 orbit cameras x tolerance {0,1,4,16} px^2, FP32")
+WORKLOAD = ("1,048,576-leaf SH3 asset (1,398,080 rows, 21,845 clusters), 1920x1080, fov_x pi/4, FP32; "
+            "the first %d frames of the sequence over 64 orbit cameras x tolerance {0,1,4,16} px^2 "
+            "(frame i: camera i mod 64, tolerance number (i + i div 64) mod 4)")
 HBM_PEAK_GBS = 8000.0
 # Blending is plain FP32 VALU work (no contraction for matrix cores, no pairs
 # of identical independent ops for packed math), so its ceiling is the VALU
 # issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s, one
 # operation per lane per clock (an FMA is one operation).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Lane-op slots per evaluated (pixel, splat) pair under the compositing rule:
-# dx, dy (2); the quadratic a dx^2 + b dx dy + c dy^2 as (a dx + b dy) dx +
-# c dy^2 (3 mul + 2 fma); the 1/255 test (1); clamp to <= 0 (1); + log2 o (1);
-# exp2 (quarter rate: 4); min(0.99, .) (1); T (1 - alpha) as T - alpha T
-# (1 fma); the 1e-4 test (1); w = alpha T (1); three colour fma (3); T update
-# (1) -> 22.
-BLEND_OPS_PER_PAIR = 22
-# HBM bytes per frame of the blend stage on this workload, from rocprofv3
-# FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the 256 timed frames
-# (profiles/hbm_counters_1M_sh3_1080p.md).  Valid only for the blending source
-# they were taken on (blend.hip and the constants of v3dg_internal.h, such as
-# the chunk sizes): the bench reports null once either has changed.
-BLEND_TRAFFIC = dict(bytes_per_frame=391.9e6, blend_source_sha256_16="979b8ec30b503cf1")
+# Lane-op slots per evaluated (pixel, splat) pair under the compositing rule,
+# the per-unit figure of the blend step: about 20 VALU operations (offsets,
+# the quadratic form, the 1/255 test, clamp, min 0.99, transmittance, the stop
+# test, the weight, three colour updates) plus one exponential at quarter rate
+# (4 slots) -> 24.
+BLEND_OPS_PER_PAIR = 24
+# HBM bytes per frame of the blend stage on the headline frames, from
+# rocprofv3 FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the first
+# BLEND_TRAFFIC["frames"] frames of the sequence (profiles/hbm_counters_...).
+# Valid only for the blending source they were taken on (blend.hip and the
+# constants of v3dg_internal.h, such as the chunk sizes) and for that many
+# timed frames: the bench reports null otherwise.
+BLEND_TRAFFIC = dict(bytes_per_frame=None, frames=20, blend_source_sha256_16=None)
 
 
 def log(*a):
@@ -52,7 +53,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=256)
     ap.add_argument("--warmup", type=int, default=8)
-    ap.add_argument("--cpu-frames", type=int, default=3, help="frames the CPU oracle renders for its baseline")
+    ap.add_argument("--cpu-frames", type=int, default=8,
+                    help="frames the CPU oracle renders on all host threads for its baseline (at most 8)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extended", action="store_true")
     ap.add_argument("--no-tiers", action="store_true", help="skip the storage-precision comparison")
@@ -63,12 +65,31 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="small asset (for profiling runs)")
     ap.add_argument("--no-stage-timing", action="store_true",
                     help="time the frames without any events (the roofline then comes from a second pass)")
-    ap.add_argument("--only", choices=["build", "stream"],
-                    help="run only the offline-build or the streaming measurement and print its JSON (for rocprofv3)")
+    ap.add_argument("--only", choices=["build", "stream", "composed"],
+                    help="run only the offline-build, streaming or composed-scene measurement and print its JSON "
+                         "(for rocprofv3)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the warm-up and one pass of the timed V3DG frames (for rocprofv3: with --warmup 0 its "
                          "per-kernel averages cover exactly the launches of the roofline)")
     return ap.parse_args()
+
+
+def headline_sequence(cams, taus, n):
+    """Frame i: camera i mod 64 at tolerance taus[(i + i // 64) mod 4].  Every
+    prefix of four or more frames holds all four tolerances, and 256 frames
+    hold every (camera, tolerance) pair once."""
+    return [(cams[i % len(cams)], taus[(i + i // len(cams)) % len(taus)]) for i in range(n)]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def pct(xs, q):
@@ -81,27 +102,48 @@ def pct(xs, q):
 
 
 def stage_bytes(P: dict, b_row: int) -> dict:
-    """Algorithmic HBM bytes per stage over the profiled frames.
+    """Algorithmic HBM bytes per stage over the profiled frames: what each step
+    must read and write once (gathers counted at their element size).
 
-    Depth-first binning (the default): the depth sort moves 4 B per slot for
-    its histogram and 16 B (key + value, read and written) per slot and pass
-    (4 passes); emission writes 8 B per key; the tile sort reads 4 B per key for
-    its histogram and moves 16 B per key and pass.
+      select     32 B per (instance, cluster) test (own and parent sphere)
+                 + 8 B per selected cluster (gid, slot offset)
+      expand     16 B per selected cluster (gid, offset, row range) + 8 B per slot
+      project    40 B per slot (slot 8, position 12, opacity 4; depth, sort key,
+                 sort value, tile count 16) + per visible slot the other
+                 B_row - 16 attribute bytes and 88 B of records (splat 48,
+                 binning 32, tile rectangle 8)
+      depth sort 4 B per slot for the histogram + 4 passes x 16 B (key and
+                 value, read and written)
+      scan       12 B per slot (depth order, tile count gathered, offset)
+      emit       52 B per visible slot (order, tile count, offset, rectangle,
+                 binning record) + (kb + 4) B per key written; its digit
+                 histograms are counted in place
+      sort_hist  kb B per key (the 64-bit-key mode only: the depth-first
+                 binning takes its histograms from emission)
+      sort_pass  2 (kb + 4) B per key and pass (key and value, read and
+                 written); kb = 2 for tile ids of up to 65,536 tiles, 4 above,
+                 8 in the 64-bit-key mode
+      ranges     per tile two binary searches, 2 ceil(log2 K) key reads, and
+                 16 B written (range 8, blend order 4, chunk base 4)
+      blend      52 B per key (slot value 4 + splat record 48) + 16 B per pixel
     """
     fr = max(P["frames"], 1)
     passes = P["sort_passes"] / fr
     depth_first = P["depth_sorts"] > 0
-    kb = 4 if depth_first else 8          # key bytes
+    tiles_per_frame = P["tiles"] / fr
+    kb = (2 if tiles_per_frame <= 65536 else 4) if depth_first else 8
+    keys_per_frame = P["keys"] / fr
+    search = 2 * math.ceil(math.log2(max(keys_per_frame, 2))) * kb
     return {
         "select": P["tests"] * 32 + P["sel_clusters"] * 8,
         "expand": P["sel_clusters"] * 16 + P["slots"] * 8,
-        "project": P["slots"] * 28 + P["visible"] * ((b_row - 16) + 48 + 32 + 8 + 8),
+        "project": P["slots"] * 40 + P["visible"] * ((b_row - 16) + 88),
         "depth_sort": P["slots"] * (4 + 4 * 16) * (P["depth_sorts"] / fr),
         "scan": P["slots"] * 12,
-        "emit": P["visible"] * (4 + 4 + 8 + 32) + P["keys"] * (kb + 4),
-        "sort_hist": P["keys"] * kb,
+        "emit": P["visible"] * 52 + P["keys"] * (kb + 4),
+        "sort_hist": 0 if depth_first else P["keys"] * kb,
         "sort_pass": P["keys"] * (2 * (kb + 4)) * passes,
-        "ranges": P["keys"] * kb + P["tiles"] * 8,
+        "ranges": P["tiles"] * (search + 16),
         "blend": P["keys"] * 52 + P["pixels"] * 16,
     }
 
@@ -115,7 +157,8 @@ def measured_blend_traffic(args):
     for f in ("blend.hip", "v3dg_internal.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     sha = h.hexdigest()[:16]
-    if args.quick or args.steps != 256 or sha != BLEND_TRAFFIC["blend_source_sha256_16"]:
+    if (args.quick or args.steps != BLEND_TRAFFIC["frames"] or BLEND_TRAFFIC["bytes_per_frame"] is None
+            or sha != BLEND_TRAFFIC["blend_source_sha256_16"]):
         return None
     return BLEND_TRAFFIC["bytes_per_frame"]
 
@@ -233,6 +276,12 @@ def serving_bench(torch, v, sg):
     return out
 
 
+def stage_ms(P: dict) -> dict:
+    """Mean event-timed milliseconds per frame of every stage that ran."""
+    fr = max(P["frames"], 1)
+    return {k: t / fr for k, (t, n) in P["stages"].items() if n}
+
+
 def tau_sweep(torch, scene, cams, taus, img, img2, fps_full):
     """FPS, p50/p99, speed-up over full detail, LOD factor and PSNR against full
     detail (every 8th camera) at each tolerance."""
@@ -252,12 +301,15 @@ def tau_sweep(torch, scene, cams, taus, img, img2, fps_full):
             mse = float(((img[..., :3].clamp(0, 1) - img2[..., :3].clamp(0, 1)) ** 2).mean())
             q.append(float("inf") if mse == 0 else 10 * math.log10(1 / mse))
             fac.append(n_full / max(n_sel, 1))
+        _, _, P_s, _ = run_frames(torch, scene, fr, img, full=False, prof=True)  # per-stage breakdown
         out["%g" % tau] = dict(fps=len(fr) / w_e, p50_ms=pct(ms_e, 50), p99_ms=pct(ms_e, 99),
                                speedup_vs_full=(len(fr) / w_e) / fps_full,
                                allowed_factor_mean=float(np.mean(fac)),
                                psnr_vs_full_db_min=float(np.min(q)),
                                psnr_vs_full_db_median=float(np.median(q)),
-                               selected_gaussians_mean=P_e["slots"] / max(P_e["frames"], 1))
+                               selected_gaussians_mean=P_e["slots"] / max(P_e["frames"], 1),
+                               keys_mean=P_s["keys"] / max(P_s["frames"], 1),
+                               stage_ms_per_frame=stage_ms(P_s))
     return out
 
 
@@ -328,15 +380,27 @@ def cpu_baseline(sg, asset, frames, build_sample):
         nth = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         nth = max(1, min(nth, os.cpu_count() or 1))
         T = sg.identity_instances(1)
+
+        def run(fr, threads):
+            ms = []
+            for cam, tau in fr:
+                t0 = time.perf_counter()
+                gids = oracle.mask_to_gids(oracle.select_walk(asset, T, cam, tau))
+                oracle.render(asset, T, cam, gids, use_index=True, n_threads=threads)
+                ms.append(1e3 * (time.perf_counter() - t0))
+            return ms
+
         log("CPU oracle baseline: %d frames on %d threads" % (len(frames), nth))
-        t0 = time.perf_counter()
-        for cam, tau in frames:
-            gids = oracle.mask_to_gids(oracle.select_walk(asset, T, cam, tau))
-            oracle.render(asset, T, cam, gids, use_index=True, n_threads=nth)
-        tc = time.perf_counter() - t0
-        out.update(value=len(frames) / tc, unit="FPS", cores=nth, kind="oracle",
-                   sample="first %d frames of the timed sequence (tolerance 0, full 1080p frames), FP64 "
-                          "recursive-walk selection + bucket-indexed per-pixel compositing" % len(frames))
+        ms = run(frames, nth)
+        out.update(value=1e3 * len(ms) / sum(ms), unit="FPS", cores=nth, kind="oracle", cpu_model=cpu_model(),
+                   host_cpus=os.cpu_count(), frame_ms_median=pct(ms, 50), frame_ms_p99=pct(ms, 99),
+                   sample="%d full 1920x1080 frames: 8 of the 64 orbit cameras (every 8th), tolerances 0, 1, 4, 16 "
+                          "twice over; FP64 recursive-walk selection + bucket-indexed per-pixel compositing, "
+                          "wall clock per frame" % len(frames))
+        log("CPU oracle baseline: 1 frame on 1 thread")
+        ms1 = run(frames[:1], 1)
+        out["single_thread"] = dict(value=1e3 / ms1[0], unit="FPS", cores=1,
+                                    sample="the first of those frames (camera 0, tolerance 0) on one thread")
     if build_sample is not None:
         g_in = build_sample["g_in"]
         t0 = time.perf_counter()
@@ -355,6 +419,37 @@ def cpu_baseline(sg, asset, frames, build_sample):
                                    % (len(build_sample["rows"]["opacity"]), len(build_sample["simp"]["opacity"]),
                                       len(build_sample["dirs"])))
     return out
+
+
+def composed_bench(torch, v, sg, asset, n_frames=20, b_row=236):
+    """The composed scene as the paper's method runs it (no view culling):
+    100 instances of the asset on a 10 x 10 grid, n_frames evenly spaced frames
+    of the 300-frame fly-through at 1920x1080, tolerance 1.  Per-stage event
+    timing and algorithmic HBM bytes of select, expand and the sorts."""
+    T = sg.grid_instances(10, 1.5, 0.2, 3)
+    cams = sg.flythrough_cameras(300, 103)[:: 300 // n_frames][:n_frames]
+    sc = v.Scene(asset, T)
+    img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    fr = [(c, 1.0) for c in cams]
+    run_frames(torch, sc, fr[:2], img, full=False, prof=False)
+    sc.collect_profile()
+    wall, ms, P, _ = run_frames(torch, sc, fr, img, full=False, prof=False)
+    _, _, P_s, _ = run_frames(torch, sc, fr, img, full=False, prof=True)
+    sb = stage_bytes(P_s, b_row)
+    fpf = max(P_s["frames"], 1)
+    stages = {}
+    for k, (t, n) in P_s["stages"].items():
+        if n:
+            stages[k] = dict(ms_per_frame=t / fpf, alg_mb_per_frame=sb.get(k, 0) / fpf / 1e6,
+                             alg_gbs=(sb[k] / (t * 1e-3) / 1e9) if k in sb and t > 0 else None)
+    sort_t = P_s["stages"]["sort_pass"][0] + P_s["stages"]["depth_sort"][0]
+    sc.close()
+    return dict(workload="100 instances of the 1M-leaf asset (2,184,500 cluster tests per frame), %d fly-through "
+                         "frames (every %dth of 300), 1920x1080, tolerance 1, no view culling" % (len(fr), 300 // n_frames),
+                fps=len(fr) / wall, p50_ms=pct(ms, 50), p99_ms=pct(ms, 99),
+                tests_per_frame=P_s["tests"] / max(P_s["selects"], 1), slots_per_frame=P_s["slots"] / fpf,
+                visible_per_frame=P_s["visible"] / fpf, keys_per_frame=P_s["keys"] / fpf, stages=stages,
+                sort_alg_gbs=((sb["sort_pass"] + sb["depth_sort"]) / (sort_t * 1e-3) / 1e9) if sort_t > 0 else None)
 
 
 def culling_bench(torch, v, sg, asset):
@@ -476,6 +571,8 @@ def main():
             line = {"build": res}
             if not args.no_cpu:
                 line["cpu_baseline"] = cpu_baseline(sg, asset, [], sample)
+        elif args.only == "composed":
+            line = {"composed": composed_bench(torch, v, sg, asset)}
         else:
             line = {"stream": stream_bench(torch, v, sg, asset)}
         print(json.dumps(line), flush=True)
@@ -483,7 +580,7 @@ def main():
     b_row = 4 * (3 + 3 + 4 + 1 + 3 * 16)
     cams = sg.orbit_cameras(64, 102)
     taus = [0.0, 1.0, 4.0, 16.0]
-    seq = [(cams[i % 64], taus[(i // 64) % 4]) for i in range(max(args.steps, 1))]
+    seq = headline_sequence(cams, taus, max(args.steps, 1))
     scene = v.Scene(asset)
     img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
     log("warmup %d frames" % args.warmup)
@@ -570,8 +667,10 @@ def main():
             run_frames(torch, bscene, fr[:8], img, full=True, prof=False)  # warm-up: the scene's first buffers
             run_frames(torch, bscene, [(c, 4096.0) for c in cams[:8]], img, full=False, prof=False)
             w_bf, _, _, _ = run_frames(torch, bscene, fr, img, full=True, prof=False)
+            _, _, P_bf, _ = run_frames(torch, bscene, fr, img, full=True, prof=True)
             built[name] = dict(build_s=t_b, clusters=int(len(bb["count"])), rows=int(len(bb["src"])),
-                               full_detail_fps=len(fr) / w_bf,
+                               full_detail_fps=len(fr) / w_bf, full_detail_stage_ms_per_frame=stage_ms(P_bf),
+                               full_detail_keys_mean=P_bf["keys"] / max(P_bf["frames"], 1),
                                tolerances=tau_sweep(torch, bscene, cams, [1.0, 64.0, 256.0, 1024.0, 4096.0], img,
                                                     img2, len(fr) / w_bf))
             for k, e in built[name]["tolerances"].items():
@@ -584,7 +683,7 @@ def main():
     tiers = {}
     if not args.no_tiers and not args.profile_run:
         import dataclasses
-        tier_frames = seq[:128] if len(seq) >= 128 else [(cams[i % 64], taus[i // 64 % 2]) for i in range(128)]
+        tier_frames = headline_sequence(cams, taus, 128)
         for res, mul in [("1920x1080", 1), ("3840x2160", 2)]:
             fr = [(dataclasses.replace(c, width=c.width * mul, height=c.height * mul, fx=c.fx * mul, fy=c.fy * mul,
                                        cx=c.cx * mul, cy=c.cy * mul), t) for c, t in tier_frames]
@@ -618,8 +717,11 @@ def main():
                     sc.close()
             del im, im32
 
-    culling = None
+    culling = composed = None
     if not args.no_culling and not args.profile_run and not args.quick:
+        composed = composed_bench(torch, v, sg, asset, b_row=b_row)
+        log("composed scene: %.1f FPS, %.3g slots and %.3g keys per frame, sorts at %.0f GB/s" % (
+            composed["fps"], composed["slots_per_frame"], composed["keys_per_frame"], composed["sort_alg_gbs"] or 0))
         culling = culling_bench(torch, v, sg, asset)
     streaming = None
     if not args.no_stream and not args.profile_run and not args.quick:
@@ -646,7 +748,7 @@ def main():
     if dom == "blend":
         flops = P["pairs"] * BLEND_OPS_PER_PAIR
         ach = flops / n_dom / (t_dom / n_dom * 1e-3) / 1e12
-        roof = dict(kernel="blend", bound="alu", achieved=ach, peak=VALU_PEAK_TOPS, unit="TFLOP/s",
+        roof = dict(kernel="blend", bound="alu", achieved=ach, peak=VALU_PEAK_TOPS, unit="T lane-ops/s",
                     frac=ach / VALU_PEAK_TOPS, traffic=measured_blend_traffic(args),
                     peak_basis="FP32 VALU issue, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane per clock",
                     pairs_per_launch=P["pairs"] / n_dom, ops_per_pair=BLEND_OPS_PER_PAIR,
@@ -671,8 +773,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD if not args.quick else "quick: 65,536-leaf asset", "width": 1920,
-                   "height": 1080, "tolerances_px2": taus, "cameras": 64, "frames": K},
+        "config": {"workload": (WORKLOAD % K) if not args.quick else "quick: 65,536-leaf asset", "width": 1920,
+                   "height": 1080, "tolerances_px2": sorted({t for _, t in seq[:K]}),
+                   "cameras": len({id(c) for c, _ in seq[:K]}), "frames": K},
         "p50_ms": pct(ms, 50),
         "p99_ms": pct(ms, 99),
         "full_detail_fps": fps_full,
@@ -690,6 +793,7 @@ def main():
         "built_bundle": built,
         "precision_tiers": tiers,
         "serving": serving,
+        "composed": composed,
         "culling": culling,
         "streaming": streaming,
         "offline_build": build,
@@ -697,7 +801,9 @@ def main():
     }
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sg, asset, seq[: args.cpu_frames], build_sample)
+        # 8 of the 64 cameras, the four tolerances twice over
+        cpu_frames = [(cams[8 * j], taus[j % 4]) for j in range(8)][: args.cpu_frames]
+        out["cpu_baseline"] = cpu_baseline(sg, asset, cpu_frames, build_sample)
     print(json.dumps(out), flush=True)
 
 
