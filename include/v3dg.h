@@ -289,6 +289,19 @@ int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
  * allocates its own temporary buffers. */
 int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): v3dg_sort_pairs
+ * without any allocation.  Its temporaries (alternate keys and values,
+ * look-back words, counters) live in one fixed device array per GPU, about
+ * 12.6 MB, held until the process ends; the array is looked up (not
+ * allocated) on the first call on a device.  n <= V3DG_SORT_NOALLOC_MAX, else
+ * V3DG_ERR_CAPACITY with nothing sorted.  Same arguments, result and errors
+ * as v3dg_sort_pairs; synchronises.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other host threads, other streams)
+ * race and must be serialised by the caller. */
+#define V3DG_SORT_NOALLOC_MAX (1u << 20)
+int v3dg_sort_pairs_noalloc(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits,
+                            void *hip_stream);
 
 /* ---- serving ----------------------------------------------------------------
  * A server renders camera requests against several resident scenes with

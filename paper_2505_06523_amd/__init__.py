@@ -103,7 +103,7 @@ EXPORTS = [
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
-    "v3dg_last_error",
+    "v3dg_sort_pairs_noalloc", "v3dg_last_error",
     "v3dg_server_create", "v3dg_server_submit", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
     "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_fit_loss", "v3dg_bundle_free", "v3dg_local_splat",
 ]
@@ -142,6 +142,7 @@ def lib():
         "v3dg_set_profiling": ([P, I], I),
         "v3dg_collect_profile": ([P, P], I),
         "v3dg_sort_pairs": ([P, P, U64, U32, P], I),
+        "v3dg_sort_pairs_noalloc": ([P, P, U64, U32, P], I),
         "v3dg_last_error": ([], C.c_char_p),
         "v3dg_server_create": ([P, U32, P, P], I),
         "v3dg_server_submit": ([P, U32, P, C.c_float, P, P], I),
@@ -303,6 +304,13 @@ def v3dg_collect_profile(scene) -> dict:
 
 def v3dg_sort_pairs(keys_ptr, vals_ptr, n, key_bits, hip_stream):
     _check(lib().v3dg_sort_pairs(keys_ptr, vals_ptr, int(n), int(key_bits), hip_stream))
+
+
+V3DG_SORT_NOALLOC_MAX = 1 << 20
+
+
+def v3dg_sort_pairs_noalloc(keys_ptr, vals_ptr, n, key_bits, hip_stream):
+    _check(lib().v3dg_sort_pairs_noalloc(keys_ptr, vals_ptr, int(n), int(key_bits), hip_stream))
 
 
 def v3dg_server_create(scene_handles, cfg: v3dg_server_config):
@@ -586,6 +594,18 @@ def sort_pairs(keys, vals, key_bits: int, stream=None):
         raise ValueError("keys and vals must be contiguous CUDA tensors")
     st = current_stream_ptr() if stream is None else C.c_void_p(stream)
     v3dg_sort_pairs(C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()), keys.numel(), key_bits, st)
+
+
+def sort_pairs_noalloc(keys, vals, key_bits: int, stream=None):
+    """sort_pairs through the entry point that allocates nothing (at most
+    V3DG_SORT_NOALLOC_MAX pairs)."""
+    torch = _torch()
+    if keys.dtype != torch.int64 or vals.dtype != torch.int32 or keys.numel() != vals.numel():
+        raise ValueError("keys must be int64 and vals int32 of equal length")
+    if not (keys.is_cuda and vals.is_cuda and keys.is_contiguous() and vals.is_contiguous()):
+        raise ValueError("keys and vals must be contiguous CUDA tensors")
+    st = current_stream_ptr() if stream is None else C.c_void_p(stream)
+    v3dg_sort_pairs_noalloc(C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()), keys.numel(), key_bits, st)
 
 
 class Server:

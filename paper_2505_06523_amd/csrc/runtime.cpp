@@ -12,6 +12,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -964,6 +965,84 @@ void scene_release(v3dg_scene *s)
 
 }  // namespace
 
+namespace {
+
+// ---- sort primitive ---------------------------------------------------------
+// Stable LSD sort of n (key, value) pairs by the low key_bits bits through the
+// given temporaries: k2 / v2 (n entries each), status (look-back words for
+// ceil(n / kSortPart) partitions) and ctr (kRenCounters words); status and
+// ctr are cleared here by fill kernels.  Synchronises to read the error flag.
+int sort_pairs_in(hipStream_t st, uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, uint64_t *k2,
+                  uint32_t *v2, uint64_t *status, uint32_t *ctr)
+{
+    const int passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
+    const uint64_t parts = (n + kSortPart - 1) / kSortPart;
+    launch_fill_u32(st, reinterpret_cast<uint32_t *>(status), 2 * parts * kRadix, 0u);
+    launch_fill_u32(st, ctr, kRenCounters, 0u);
+    launch_sort_hist<uint64_t>(st, keys_dev, nullptr, n, passes, ctr + kRenHist);
+    uint64_t *kb[2] = {keys_dev, k2};
+    uint32_t *vb[2] = {vals_dev, v2};
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+        launch_sort_pass<uint64_t>(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], nullptr, n, p, ctr + kRenHist, status,
+                                   nullptr, (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr, false);
+        cur ^= 1;
+    }
+    if (cur == 1) {
+        HIP_TRY(hipMemcpyAsync(keys_dev, k2, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(vals_dev, v2, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    }
+    uint32_t err = 0;
+    hipError_t e = hipMemcpyAsync(&err, ctr + kRenErr, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(V3DG_ERR_HIP, "sort failed: %s", hipGetErrorString(e));
+    if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
+    return V3DG_OK;
+}
+
+// ---- scratch of the allocation-free sort --------------------------------------
+// One fixed device array per GPU, laid out as the sort's temporaries for
+// V3DG_SORT_NOALLOC_MAX pairs: alternate keys, alternate values, look-back
+// words and counters.  Its device address is looked up once per device (the
+// name itself is a host-side stand-in) and kept; every call on that device
+// shares the array.
+constexpr uint64_t kNaMaxParts = (V3DG_SORT_NOALLOC_MAX + kSortPart - 1) / kSortPart;
+constexpr uint64_t kNaKeysOff = 0;
+constexpr uint64_t kNaValsOff = kNaKeysOff + 8ull * V3DG_SORT_NOALLOC_MAX;
+constexpr uint64_t kNaStatusOff = (kNaValsOff + 4ull * V3DG_SORT_NOALLOC_MAX + 255) / 256 * 256;
+constexpr uint64_t kNaCtrOff = kNaStatusOff + 8ull * kNaMaxParts * kRadix;
+constexpr uint64_t kNaBytes = (kNaCtrOff + 4ull * kRenCounters + 255) / 256 * 256;
+static_assert(kNaBytes <= (16ull << 20), "the allocation-free sort's scratch stays below 16 MiB");
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mutex;
+uint8_t *g_na_ptr[kNaMaxDevices] = {};
+
+int noalloc_scratch(uint8_t **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(V3DG_ERR_INVALID_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(V3DG_ERR_HIP, "scratch address lookup failed: %s", hipGetErrorString(e));
+        g_na_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_na_ptr[dev];
+    return V3DG_OK;
+}
+
+}  // namespace
+
 // =============================================================================
 // C ABI
 // =============================================================================
@@ -1687,8 +1766,6 @@ int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t
     if (n >= 0xffffffffull) return fail(V3DG_ERR_CAPACITY, "n must be < 2^32");
     if (n == 0) return V3DG_OK;
     if (!keys_dev || !vals_dev) return fail(V3DG_ERR_INVALID_ARG, "NULL buffer");
-    hipStream_t st = (hipStream_t)hip_stream;
-    const int passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
     const uint64_t parts = (n + kSortPart - 1) / kSortPart;
     uint64_t *k2 = nullptr, *status = nullptr;
     uint32_t *v2 = nullptr, *ctr = nullptr;
@@ -1696,34 +1773,31 @@ int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t
     if (!rc) rc = dev_alloc(&v2, n);
     if (!rc) rc = dev_alloc(&status, parts * kRadix);
     if (!rc) rc = dev_alloc(&ctr, (uint64_t)kRenCounters);
-    if (!rc) {
-        launch_fill_u32(st, reinterpret_cast<uint32_t *>(status), 2 * parts * kRadix, 0u);
-        launch_fill_u32(st, ctr, kRenCounters, 0u);
-        launch_sort_hist<uint64_t>(st, keys_dev, nullptr, n, passes, ctr + kRenHist);
-        uint64_t *kb[2] = {keys_dev, k2};
-        uint32_t *vb[2] = {vals_dev, v2};
-        int cur = 0;
-        for (int p = 0; p < passes; ++p) {
-            launch_sort_pass<uint64_t>(st, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], nullptr, n, p, ctr + kRenHist,
-                                       status, nullptr, (uint32_t)(p + 1), ctr + kRenTicketSort + p, ctr + kRenErr,
-                                       false);
-            cur ^= 1;
-        }
-        if (cur == 1) {
-            (void)hipMemcpyAsync(keys_dev, k2, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
-            (void)hipMemcpyAsync(vals_dev, v2, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-        }
-        uint32_t err = 0;
-        hipError_t e = hipMemcpyAsync(&err, ctr + kRenErr, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) rc = fail(V3DG_ERR_HIP, "sort failed: %s", hipGetErrorString(e));
-        else if (err & kErrSpin) rc = fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
-    }
+    if (!rc) rc = sort_pairs_in((hipStream_t)hip_stream, keys_dev, vals_dev, n, key_bits, k2, v2, status, ctr);
     dev_free(k2);
     dev_free(v2);
     dev_free(status);
     dev_free(ctr);
     return rc;
+}
+
+int v3dg_sort_pairs_noalloc(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, void *hip_stream)
+{
+    g_err.clear();
+    if (key_bits < 1 || key_bits > 64) return fail(V3DG_ERR_INVALID_ARG, "key_bits must be 1..64");
+    if (n > V3DG_SORT_NOALLOC_MAX)
+        return fail(V3DG_ERR_CAPACITY, "%llu pairs exceed the %u this entry point sorts without allocating",
+                    (unsigned long long)n, (unsigned)V3DG_SORT_NOALLOC_MAX);
+    if (n == 0) return V3DG_OK;
+    if (!keys_dev || !vals_dev) return fail(V3DG_ERR_INVALID_ARG, "NULL buffer");
+    uint8_t *base = nullptr;
+    int rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    uint64_t *k2 = reinterpret_cast<uint64_t *>(base + kNaKeysOff);
+    uint32_t *v2 = reinterpret_cast<uint32_t *>(base + kNaValsOff);
+    uint64_t *status = reinterpret_cast<uint64_t *>(base + kNaStatusOff);
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(base + kNaCtrOff);
+    return sort_pairs_in((hipStream_t)hip_stream, keys_dev, vals_dev, n, key_bits, k2, v2, status, ctr);
 }
 
 }  // extern "C"
