@@ -47,7 +47,7 @@ class OrcCamera(C.Structure):
 
 class OrcStats(C.Structure):
     _fields_ = [("n_slots", C.c_uint64), ("n_valid", C.c_uint64), ("n_ambiguous", C.c_uint64),
-                ("n_pairs", C.c_uint64)]
+                ("n_pairs", C.c_uint64), ("n_hits", C.c_uint64)]
 
 
 def lib():
@@ -213,7 +213,8 @@ def render(asset, T, cam, gids, use_index: bool = True, n_threads: int = 0):
     c = _camera(cam)
     lib().orc_render(C.byref(b.struct), T.shape[0], _ptr(T), C.byref(c), g.size, _ptr(g), int(bool(use_index)),
                      int(n_threads), _ptr(img), _ptr(amb), C.byref(st))
-    return img, amb, dict(n_slots=st.n_slots, n_valid=st.n_valid, n_ambiguous=st.n_ambiguous, n_pairs=st.n_pairs)
+    return img, amb, dict(n_slots=st.n_slots, n_valid=st.n_valid, n_ambiguous=st.n_ambiguous, n_pairs=st.n_pairs,
+                             n_hits=st.n_hits)
 
 
 def render_pixels(asset, T, cam, gids, pix_xy, n_threads: int = 0):
@@ -228,4 +229,5 @@ def render_pixels(asset, T, cam, gids, pix_xy, n_threads: int = 0):
     c = _camera(cam)
     lib().orc_render_pixels(C.byref(b.struct), T.shape[0], _ptr(T), C.byref(c), g.size, _ptr(g), pix.shape[0],
                             _ptr(pix), int(n_threads), _ptr(out), _ptr(amb), C.byref(st))
-    return out, amb, dict(n_slots=st.n_slots, n_valid=st.n_valid, n_ambiguous=st.n_ambiguous, n_pairs=st.n_pairs)
+    return out, amb, dict(n_slots=st.n_slots, n_valid=st.n_valid, n_ambiguous=st.n_ambiguous, n_pairs=st.n_pairs,
+                             n_hits=st.n_hits)

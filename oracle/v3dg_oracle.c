@@ -548,7 +548,7 @@ static int orc_near(double v, double thr) { return fabs(v - thr) <= AMBIG_REL * 
  *   pixel is finished and this splat is not added;  C += alpha T rgb;  T = T'.
  *   Output RGB = C + T bg, A = 1 - T. */
 static void orc_pixel(const orc_frame *f, const orc_camera *cam, int px, int py, int use_index,
-                      double *out4, uint8_t *amb, uint64_t *pairs)
+                      double *out4, uint8_t *amb, uint64_t *pairs, uint64_t *hits)
 {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
     double pcx = px + 0.5, pcy = py + 0.5;
@@ -564,7 +564,7 @@ static void orc_pixel(const orc_frame *f, const orc_camera *cam, int px, int py,
         j1 = f->n_order;
     }
     uint8_t ambiguous = 0;
-    uint64_t np = 0;
+    uint64_t np = 0, nh = 0;
     for (uint64_t jj = j0; jj < j1; ++jj) {
         uint64_t j = lst ? lst[jj] : jj;
         const orc_splat *s = &f->sp[f->order[j]];
@@ -576,6 +576,7 @@ static void orc_pixel(const orc_frame *f, const orc_camera *cam, int px, int py,
         ++np;
         if (orc_near(alpha, 1.0 / 255.0)) ambiguous = 1;
         if (alpha < 1.0 / 255.0) continue;
+        ++nh; /* this splat is composited, or it ends the pixel */
         double Tn = T * (1.0 - alpha);
         if (orc_near(Tn, 1e-4)) ambiguous = 1;
         if (Tn < 1e-4) break;
@@ -590,6 +591,7 @@ static void orc_pixel(const orc_frame *f, const orc_camera *cam, int px, int py,
     out4[3] = 1.0 - T;
     if (amb) *amb = ambiguous;
     *pairs += np;
+    *hits += nh;
 }
 
 void orc_project(const orc_asset *a, uint32_t n_inst, const double *T, const orc_camera *cam,
@@ -630,14 +632,14 @@ int orc_render(const orc_asset *a, uint32_t n_inst, const double *T, const orc_c
 #endif
     orc_frame f;
     orc_prepare(a, n_inst, T, cam, n_gids, gids, use_index, &f);
-    uint64_t pairs = 0, namb = 0;
+    uint64_t pairs = 0, hits = 0, namb = 0;
     int W = (int)cam->width, H = (int)cam->height;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : pairs, namb)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : pairs, hits, namb)
     for (int py = 0; py < H; ++py) {
         for (int px = 0; px < W; ++px) {
             uint8_t amb = 0;
             size_t idx = (size_t)py * W + px;
-            orc_pixel(&f, cam, px, py, use_index, rgba_out + 4 * idx, &amb, &pairs);
+            orc_pixel(&f, cam, px, py, use_index, rgba_out + 4 * idx, &amb, &pairs, &hits);
             if (ambiguous_out) ambiguous_out[idx] = amb;
             namb += amb;
         }
@@ -647,6 +649,7 @@ int orc_render(const orc_asset *a, uint32_t n_inst, const double *T, const orc_c
         stats->n_valid = f.n_valid;
         stats->n_ambiguous = namb;
         stats->n_pairs = pairs;
+        stats->n_hits = hits;
     }
     orc_frame_free(&f);
     return 0;
@@ -663,11 +666,11 @@ int orc_render_pixels(const orc_asset *a, uint32_t n_inst, const double *T, cons
 #endif
     orc_frame f;
     orc_prepare(a, n_inst, T, cam, n_gids, gids, 1, &f);
-    uint64_t pairs = 0, namb = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : pairs, namb)
+    uint64_t pairs = 0, hits = 0, namb = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : pairs, hits, namb)
     for (int64_t i = 0; i < (int64_t)n_pix; ++i) {
         uint8_t amb = 0;
-        orc_pixel(&f, cam, (int)pix_xy[2 * i], (int)pix_xy[2 * i + 1], 1, rgba_out + 4 * i, &amb, &pairs);
+        orc_pixel(&f, cam, (int)pix_xy[2 * i], (int)pix_xy[2 * i + 1], 1, rgba_out + 4 * i, &amb, &pairs, &hits);
         if (ambiguous_out) ambiguous_out[i] = amb;
         namb += amb;
     }
@@ -676,6 +679,7 @@ int orc_render_pixels(const orc_asset *a, uint32_t n_inst, const double *T, cons
         stats->n_valid = f.n_valid;
         stats->n_ambiguous = namb;
         stats->n_pairs = pairs;
+        stats->n_hits = hits;
     }
     orc_frame_free(&f);
     return 0;

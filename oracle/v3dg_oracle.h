@@ -49,8 +49,11 @@ typedef struct {
     float pad0;
 } orc_camera;
 
+/* n_pairs: (pixel, splat) pairs visited (the bucket's splats up to the
+ * pixel's end); n_hits: of those, the splats with alpha >= 1/255, i.e. the
+ * ones composited plus the one that ends the pixel. */
 typedef struct {
-    uint64_t n_slots, n_valid, n_ambiguous, n_pairs;
+    uint64_t n_slots, n_valid, n_ambiguous, n_pairs, n_hits;
 } orc_stats;
 
 /* Per-instance frame quantities: A = fl32(V T) composed in FP64, s = fl32 of

@@ -314,6 +314,8 @@ def test_single_isotropic_splat_closed_form(oracle_lib):
     rgb_exp = a[..., None] * col + (1 - a[..., None]) * np.asarray(bg)
     ok = amb == 0
     assert ok.mean() > 0.95
+    # one contributing (pixel, splat) pair per pixel where alpha >= 1/255
+    assert abs(st["n_hits"] - int((a > 0).sum())) <= int((~ok).sum())
     assert np.abs(img[..., :3] - rgb_exp)[ok].max() < 1e-6
     assert np.abs(img[..., 3] - a)[ok].max() < 1e-6
     assert (img[..., 3][a == 0] == 0).all()
@@ -350,6 +352,8 @@ def test_opaque_stack_stops(oracle_lib):
     # first: 0.99*red; second: T=0.01 -> adds 0.99*0.01 green, T=1e-4 (not below); third would push
     # T to 1e-6 < 1e-4: stop without adding blue
     assert px[0] == pytest.approx(0.99, abs=1e-4)
+    _, _, st1 = oracle_lib.render_pixels(asset, sg.identity_instances(1), cam, [0], np.array([[4, 4]], np.uint32))
+    assert st1["n_hits"] == 3  # two composited splats and the one that ends the pixel
     assert px[1] == pytest.approx(0.0099, abs=1e-5)
     assert px[2] == pytest.approx(0.0, abs=1e-9)
 
