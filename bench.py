@@ -483,10 +483,12 @@ def culling_bench(torch, v, sg, asset):
 def stream_bench(torch, v, sg, asset):
     """A close walk through the 1M-leaf asset (100 cameras looking along a
     circle of radius 0.45 inside it, 1920x1080, tolerance 1, culling on) with
-    the rows streamed from host memory: first through a pool of every cluster
-    (the largest cut of the walk is its working set), then through a pool
-    25 % above that working set, against the resident scene; every 10th image
-    compared bit for bit."""
+    the rows streamed: from host memory through a pool of every cluster (the
+    largest cut of the walk is its working set), then through a pool 25 % above
+    that working set, then through the same pool from a page file on disk
+    (direct reads where the file system allows them, then through the page
+    cache), against the resident scene; every 10th image compared bit for
+    bit."""
     import numpy as np
     cams = sg.tangent_path_cameras(100)
     img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
@@ -501,10 +503,16 @@ def stream_bench(torch, v, sg, asset):
                        "1920x1080, tolerance 1, culling on), rows streamed from host memory",
            "resident": dict(fps=len(fr) / w_res, p50_ms=pct(ms_res, 50), p99_ms=pct(ms_res, 99),
                             row_bytes_in_hbm=int(asset.n_rows) * row_bytes)}
+    import tempfile
     work = None
-    for name in ("pool_all", "pool_working_set_x1.25"):
+    for name in ("pool_all", "pool_working_set_x1.25", "file_working_set_x1.25_direct",
+                 "file_working_set_x1.25_buffered"):
         pool = asset.n_clusters if work is None else int(math.ceil(1.25 * work))
-        sc = v.Scene(asset, pool_clusters=pool)
+        page_file, ff = None, 0
+        if name.startswith("file"):  # the page images in a file on disk, read at each select
+            page_file = os.path.join(tempfile.gettempdir(), "v3dg_pages_%d.bin" % os.getpid())
+            ff = v.V3DG_PAGE_FILE_DIRECT if name.endswith("direct") else 0
+        sc = v.Scene(asset, pool_clusters=pool, page_file=page_file, file_flags=ff)
         sc.set_culling(True)
         used, pages, equal = [], [], True
         sel = None
@@ -536,7 +544,9 @@ def stream_bench(torch, v, sg, asset):
                          mean_clusters_per_cut=float(np.mean(used)),
                          mean_pages_in_per_frame=float(np.mean(pages[1:])),
                          mean_mb_in_per_frame=float(np.mean(pages[1:])) * 64 * row_bytes / 1e6,
-                         evictions=int(st["evictions"]), images_equal_resident=equal)
+                         evictions=int(st["evictions"]), images_equal_resident=equal,
+                         page_store=["host memory", "file, page cache", "file, direct reads"][st["tier"]],
+                         file_reads=int(st["file_reads"]))
         log("streamed %s (%d pages): %.1f FPS, %.1f pages in per frame, %d evictions, equal %s" % (
             name, pool, len(fr) / wall, float(np.mean(pages[1:])), st["evictions"], equal))
         work = int(max(used)) if work is None else work

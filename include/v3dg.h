@@ -22,7 +22,8 @@
  *     failure on the calling thread is available from v3dg_last_error();
  *   - nothing is written to caller memory when a call fails;
  *   - calls are asynchronous on the scene's stream unless marked "synchronises";
- *     v3dg_render also waits once, mid-frame, for the device-side key count;
+ *     the first v3dg_render of an image size also waits once, mid-frame, for
+ *     the device-side key count (later frames of that size do not wait);
  *   - host arrays passed in are only read during the call; device pointers
  *     (the image) stay owned by the caller.
  */
@@ -41,6 +42,7 @@ extern "C" {
 #define V3DG_ERR_NOT_MONOTONE (-4) /* parent sphere does not nest its child (see load)     */
 #define V3DG_ERR_CAPACITY (-5)     /* a frame exceeds a 32-bit count                       */
 #define V3DG_ERR_DEVICE (-6)       /* a kernel raised its error flag (bounded wait expired)*/
+#define V3DG_ERR_IO (-7)           /* a page file could not be written or read            */
 
 /* Storage precision of the Gaussian attributes (positions always stay FP32;
  * arithmetic is FP32 in every case).  The library rounds the FP32 input of
@@ -176,6 +178,23 @@ int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *desc, const double *
                                  uint32_t n_instances, void *hip_stream, uint32_t flags, uint32_t pool_clusters,
                                  v3dg_scene **out);
 
+/* The same with the page images in a file on disk instead of host memory
+ * (the tier below host memory).  The library creates (or truncates) page_file,
+ * writes every cluster's image at a 4 KiB-aligned slot during the load, and
+ * each select reads the images it pages in with positioned reads, one per
+ * run of consecutive clusters, into the pinned stage.  file_flags:
+ * V3DG_PAGE_FILE_DIRECT asks for reads that bypass the operating system's page
+ * cache (O_DIRECT; where the file system refuses it the reads are buffered,
+ * see v3dg_stream_stats.tier); V3DG_PAGE_FILE_KEEP keeps the file when the
+ * scene is freed (it is removed otherwise).  pool_clusters must be > 0.  A
+ * failed write or read returns V3DG_ERR_IO (a failed read pages nothing).
+ * Images equal those of the resident scene bit for bit. */
+#define V3DG_PAGE_FILE_DIRECT 1u
+#define V3DG_PAGE_FILE_KEEP 2u
+int v3dg_load_hierarchy_streamed_file(const v3dg_hierarchy_desc *desc, const double *instances_3x4,
+                                      uint32_t n_instances, void *hip_stream, uint32_t flags, uint32_t pool_clusters,
+                                      const char *page_file, uint32_t file_flags, v3dg_scene **out);
+
 /* Paging counters of a streamed scene (zeros for a resident one). */
 typedef struct {
     uint64_t frames;            /* cuts paged in (selects and full renders)          */
@@ -186,6 +205,10 @@ typedef struct {
     uint32_t last_resident_used;/* resident clusters the latest cut uses             */
     uint32_t pool_clusters;     /* pages in the pool                                 */
     uint32_t resident;          /* clusters resident now                             */
+    uint32_t tier;              /* where the page images live: 0 host memory, 1 a
+                                   file read through the page cache, 2 a file read
+                                   directly (O_DIRECT)                              */
+    uint64_t file_reads;        /* positioned reads of the page file so far          */
 } v3dg_stream_stats;
 int v3dg_get_stream_stats(const v3dg_scene *scene, v3dg_stream_stats *out);
 
@@ -207,7 +230,17 @@ int v3dg_select(v3dg_scene *scene, const v3dg_camera *cam, float tolerance, v3dg
 
 /* Render a selection: project, bin, sort, blend.  image_rgba_dev is a device
  * buffer of height x width x 4 floats (RGB = sum + T bg, A = 1 - T), written
- * completely.  Synchronises once mid-frame to size the key buffers. */
+ * completely.  The first frame of an image size (and every frame in the
+ * 64-bit-key sort mode) synchronises once mid-frame to size the key buffers
+ * exactly.  Later frames of that size run without any host wait: their
+ * launches are sized by a key capacity of at least 2^20 keys, 16 keys per
+ * pixel and twice the most keys any frame needed, the kernels read their counts on the
+ * device, and each frame publishes its counts to pinned host memory, read
+ * when a later call finds the frame finished.  A frame that needs more keys
+ * than the capacity is still rendered exactly, by every tile walking all
+ * visible splats in depth order (slower); the capacity then grows for the
+ * frames after.  Such a frame's sorted keys are not available
+ * (v3dg_copy_sorted_keys fails with V3DG_ERR_CAPACITY). */
 int v3dg_render(v3dg_scene *scene, const v3dg_camera *cam, const v3dg_selection *sel, float *image_rgba_dev);
 
 /* Full-detail baseline: every leaf cluster of every instance (no selection). */
@@ -259,7 +292,14 @@ typedef struct {
     uint64_t keys, tiles, pixels;      /* sorted keys, image tiles, image pixels      */
     uint64_t sort_passes;              /* digit passes of the tile / 64-bit key sort  */
     uint64_t depth_sorts;              /* frames that sorted slots by depth first     */
-    uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending  */
+    uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending: for
+                                          each splat of a quarter's list, the quarter's
+                                          pixels still compositing when it is reached    */
+    uint64_t pairs_taken;              /* of those, pairs with alpha >= 1/255 (composited,
+                                          or ending the pixel); later chunks of long tile
+                                          lists are walked from T = 1 and count pairs a
+                                          sequential walk would not reach.  Counted only
+                                          with V3DG_PROFILE_PAIR_AUDIT, else 0            */
 } v3dg_profile;
 
 /* View culling of the cut (default off).  When on, v3dg_select still returns
@@ -281,6 +321,10 @@ int v3dg_set_sort_mode(v3dg_scene *scene, int mode);
  * either way.  v3dg_collect_profile synchronises, fills *out with the totals
  * since the previous collect, and clears them. */
 #define V3DG_PROFILE_ALL 0x7ff
+/* Added to stage_mask: blending also counts the pairs it takes
+ * (v3dg_profile.pairs_taken, otherwise 0).  The count costs a few scalar
+ * operations per pair on the walk's critical path, so it is off by default. */
+#define V3DG_PROFILE_PAIR_AUDIT 0x800
 int v3dg_set_profiling(v3dg_scene *scene, int stage_mask);
 int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
 

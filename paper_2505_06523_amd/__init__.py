@@ -26,12 +26,16 @@ V3DG_ERR_HIP = -3
 V3DG_ERR_NOT_MONOTONE = -4
 V3DG_ERR_CAPACITY = -5
 V3DG_ERR_DEVICE = -6
+V3DG_ERR_IO = -7
+V3DG_PAGE_FILE_DIRECT = 1
+V3DG_PAGE_FILE_KEEP = 2
 V3DG_FP32 = 0
 V3DG_FP16_BF16SH = 1
 V3DG_FP16 = 2
 PRECISIONS = {"fp32": V3DG_FP32, "fp16_bf16sh": V3DG_FP16_BF16SH, "fp16": V3DG_FP16}
 V3DG_LOAD_REPAIR_NESTING = 1
 V3DG_PROFILE_ALL = 0x7FF
+V3DG_PROFILE_PAIR_AUDIT = 0x800
 V3DG_SORT_DEPTH_FIRST = 0
 V3DG_SORT_KEYS64 = 1
 STAGES = ["setup", "select", "expand", "project", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend",
@@ -67,7 +71,8 @@ class v3dg_frame_stats(C.Structure):
 class v3dg_stream_stats(C.Structure):
     _fields_ = [("frames", C.c_uint64), ("pages_in", C.c_uint64), ("bytes_in", C.c_uint64),
                 ("evictions", C.c_uint64), ("last_pages_in", C.c_uint64), ("last_resident_used", C.c_uint32),
-                ("pool_clusters", C.c_uint32), ("resident", C.c_uint32)]
+                ("pool_clusters", C.c_uint32), ("resident", C.c_uint32), ("tier", C.c_uint32),
+                ("file_reads", C.c_uint64)]
 
 
 class v3dg_profile(C.Structure):
@@ -75,7 +80,7 @@ class v3dg_profile(C.Structure):
                 ("selects", C.c_uint64), ("tests", C.c_uint64), ("sel_clusters", C.c_uint64),
                 ("slots", C.c_uint64), ("visible", C.c_uint64), ("keys", C.c_uint64), ("tiles", C.c_uint64),
                 ("pixels", C.c_uint64), ("sort_passes", C.c_uint64), ("depth_sorts", C.c_uint64),
-                ("pairs", C.c_uint64)]
+                ("pairs", C.c_uint64), ("pairs_taken", C.c_uint64)]
 
 
 class v3dg_server_config(C.Structure):
@@ -99,7 +104,8 @@ class v3dg_server_stats(C.Structure):
 
 
 EXPORTS = [
-    "v3dg_load_hierarchy", "v3dg_load_hierarchy_streamed", "v3dg_get_stream_stats", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
+    "v3dg_load_hierarchy", "v3dg_load_hierarchy_streamed", "v3dg_load_hierarchy_streamed_file",
+    "v3dg_get_stream_stats", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
@@ -123,6 +129,7 @@ def lib():
     sig = {
         "v3dg_load_hierarchy": ([P, P, U32, P, U32, P], I),
         "v3dg_load_hierarchy_streamed": ([P, P, U32, P, U32, U32, P], I),
+        "v3dg_load_hierarchy_streamed_file": ([P, P, U32, P, U32, U32, C.c_char_p, U32, P], I),
         "v3dg_get_stream_stats": ([P, P], I),
         "v3dg_set_instances": ([P, P, U32], I),
         "v3dg_select": ([P, P, C.c_float, P], I),
@@ -178,9 +185,14 @@ def _p(a: np.ndarray):
 
 
 # ---- one-to-one wrappers of the C ABI ------------------------------------------
-def v3dg_load_hierarchy(desc, instances_3x4, n_instances, hip_stream, flags, pool_clusters: int = 0):
+def v3dg_load_hierarchy(desc, instances_3x4, n_instances, hip_stream, flags, pool_clusters: int = 0,
+                        page_file: str | None = None, file_flags: int = 0):
     out = C.c_void_p()
-    if pool_clusters:
+    if page_file is not None:
+        _check(lib().v3dg_load_hierarchy_streamed_file(C.byref(desc), instances_3x4, n_instances, hip_stream, flags,
+                                                       int(pool_clusters), os.fsencode(page_file), int(file_flags),
+                                                       C.byref(out)))
+    elif pool_clusters:
         _check(lib().v3dg_load_hierarchy_streamed(C.byref(desc), instances_3x4, n_instances, hip_stream, flags,
                                                   int(pool_clusters), C.byref(out)))
     else:
@@ -401,10 +413,12 @@ class Scene:
     """An asset in HBM with its instance table.  ``precision`` is the
     attribute storage tier: V3DG_FP32, V3DG_FP16_BF16SH or V3DG_FP16 (or its
     name in PRECISIONS).  ``pool_clusters`` > 0 streams the rows from host
-    memory through a pool of that many 64-row pages (v3dg_load_hierarchy_streamed)."""
+    memory through a pool of that many 64-row pages (v3dg_load_hierarchy_streamed);
+    with ``page_file`` the page images live in that file on disk instead
+    (v3dg_load_hierarchy_streamed_file, ``file_flags`` V3DG_PAGE_FILE_*)."""
 
     def __init__(self, asset, instances=None, stream=None, flags: int = 0, precision=V3DG_FP32,
-                 pool_clusters: int = 0):
+                 pool_clusters: int = 0, page_file: str | None = None, file_flags: int = 0):
         arrays = dict(
             self_sphere=np.ascontiguousarray(asset.self_sphere, np.float32),
             parent_sphere=np.ascontiguousarray(asset.parent_sphere, np.float32),
@@ -440,7 +454,7 @@ class Scene:
             stream = C.c_void_p(stream)
         self.stream = stream
         self.handle = None
-        self.handle = v3dg_load_hierarchy(d, _p(T), T.shape[0], stream, flags, pool_clusters)
+        self.handle = v3dg_load_hierarchy(d, _p(T), T.shape[0], stream, flags, pool_clusters, page_file, file_flags)
 
     def set_instances(self, instances):
         T = np.ascontiguousarray(np.asarray(instances, np.float64).reshape(-1, 12))
@@ -495,13 +509,14 @@ class Scene:
     def set_culling(self, on: bool = True):
         v3dg_set_culling(self.handle, on)
 
-    def set_profiling(self, on=True):
-        """True / False, or an iterable of stage names to time."""
+    def set_profiling(self, on=True, audit_pairs: bool = False):
+        """True / False, or an iterable of stage names to time; audit_pairs
+        also counts the pairs blending takes (profile "pairs_taken")."""
         if on is True or on is False:
             mask = V3DG_PROFILE_ALL if on else 0
         else:
             mask = sum(1 << STAGES.index(s) for s in on)
-        v3dg_set_profiling(self.handle, mask)
+        v3dg_set_profiling(self.handle, mask | (V3DG_PROFILE_PAIR_AUDIT if audit_pairs else 0))
 
     def collect_profile(self) -> dict:
         return v3dg_collect_profile(self.handle)

@@ -55,6 +55,7 @@ struct Pix {
     float T, cr, cg, cb;
     bool active;          // still compositing
     uint32_t walked;      // (pixel, splat) pairs walked by the wavefront's active pixels (uniform)
+    uint32_t taken;       // of those, pairs with alpha >= 1/255 (composited, or ending the pixel) (uniform)
 };
 
 // Stage one batch entry (the splat record of key i) into LDS with its
@@ -123,6 +124,9 @@ __device__ __forceinline__ void composite(float p, bool take, float log2o, const
 // once a pixel is known to be active; after that the splat records of the
 // next batch are gathered while the current one is walked, and the index of
 // the batch after that one is read ahead, so no walk waits on global memory.
+// kAudit also counts the pairs taken (a few scalar operations per pair, on
+// the walk's critical path: only when the profile asks for it).
+template <bool kAudit>
 __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ splat,
                             const uint32_t *__restrict__ vals, float bx0, float by0, float pxc, float pyc, int wid,
                             int lane, BlendShared &sh, Pix &px)
@@ -185,7 +189,7 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
             // same for every lane; lanes differ only in whether they take them.
             // An entry counts as walked for the pixels active when it is reached.
             float T = px.active ? px.T : -px.T, cr = px.cr, cg = px.cg, cb = px.cb;
-            uint32_t walked = 0;
+            uint32_t walked = 0, taken = 0;
             uint32_t prn = *reinterpret_cast<const uint32_t *>(&sh.idx[wid][0]);
             for (uint32_t k = 0; am != 0 && k < cnt; k += 2) {
                 // the next pair's offsets are read one iteration ahead (past the
@@ -213,9 +217,13 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
                     composite(p1, act1 && pass1, c1.z, col1, T, cr, cg, cb);
                 }
                 walked += (uint32_t)__popcll(am) + (two ? (uint32_t)__popcll(amid) : 0u);
+                // the pass masks are the compares' own lane masks: counted on the scalar unit
+                if constexpr (kAudit)
+                    taken += (uint32_t)__popcll(am & __ballot(pass0)) + (uint32_t)__popcll(amid & __ballot(pass1));
                 am = __ballot(T > 0.0f);
             }
             px.walked += walked;
+            px.taken += taken;
             px.active = T > 0.0f;
             px.T = fabsf(T);
             px.cr = cr;
@@ -225,9 +233,11 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
     }
 }
 
+// pairs[0]: walked pairs; pairs[1]: taken pairs
 __device__ __forceinline__ void count_pairs(const Pix &px, int lane, unsigned long long *pairs)
 {
     if (lane == 0 && px.walked) atomicAdd(pairs, (unsigned long long)px.walked);
+    if (lane == 0 && px.taken) atomicAdd(pairs + 1, (unsigned long long)px.taken);
 }
 
 struct TileGeo {
@@ -266,6 +276,7 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
 // Workgroup b blends tile order[b]: the tiles with the longest first chunks
 // come first, so that their walks do not start last and leave the rest of the
 // chip idle.
+template <bool kAudit>
 __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
@@ -283,11 +294,11 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
     const uint32_t tile = order[blockIdx.x];
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint2 rg = ranges[tile];
-    Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u};
+    Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u, 0u};
     const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
     const uint32_t cb = cbase[tile];  // kNoChunk: blended whole
     const bool long_list = cb != kNoChunk && end - rg.x > (uint32_t)kChunkFirst;
-    blend_range(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
+    blend_range<kAudit>(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
                 px);
     if (long_list) {  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cb * kBlendThreads + g.pix] =
@@ -306,6 +317,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
 // ---------------------------------------------------------------------------
 // pass 2: chunks 1.. of long tiles, in parallel, each from T = 1
 // ---------------------------------------------------------------------------
+template <bool kAudit>
 __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) chunk_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
@@ -330,9 +342,9 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
         const uint64_t base = cbase[tile];
         if (need[base] == 0u) continue;  // every pixel finished in chunk 0 (uniform)
         const float4 s0 = scratch[base * kBlendThreads + g.pix];
-        Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u};
+        Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u, 0u};
         const bool was = px.active;
-        blend_range(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
+        blend_range<kAudit>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
                     g.pyc, wid, lane, sh, px);
         // the fold reads later chunks only for pixels active after chunk 0
         if (was)
@@ -368,7 +380,7 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
     for (uint32_t c = tid; c < m; c += kBlendThreads) need[base + c] = 0u;
     __syncthreads();
     const float4 s0 = scratch[base * kBlendThreads + g.pix];
-    Pix px{fabsf(s0.w), s0.x, s0.y, s0.z, false, 0u};
+    Pix px{fabsf(s0.w), s0.x, s0.y, s0.z, false, 0u, 0u};
     uint32_t pending = kNone;
     if (s0.w > 0.0f) {
         for (uint32_t c = 1; c < m; ++c) {
@@ -402,6 +414,7 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
 // ---------------------------------------------------------------------------
 // pass 4: walk again, with the stop rule, each chunk that holds a stop
 // ---------------------------------------------------------------------------
+template <bool kAudit>
 __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *__restrict__ fd,
                                                                const float4 *__restrict__ splat,
                                                                const uint32_t *__restrict__ vals,
@@ -426,8 +439,8 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         const uint64_t base = cbase[tile];
         const bool mine = pend[base * kBlendThreads + g.pix] == c;
         const float4 st = scratch[base * kBlendThreads + g.pix];
-        Pix px{fabsf(st.w), st.x, st.y, st.z, mine, 0u};  // a pixel finished before holds -T
-        blend_range(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
+        Pix px{fabsf(st.w), st.x, st.y, st.z, mine, 0u, 0u};  // a pixel finished before holds -T
+        blend_range<kAudit>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
                     g.pyc, wid, lane, sh, px);
         // a pixel that, through rounding of the folded products, does not stop in
         // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
@@ -437,30 +450,90 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
     }
 }
 
-// max_items / max_chunks bound the chunk work items and chunks (grids are
-// capped and loop over the device-side counts)
-void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
-                  const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
-                  const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
-                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs)
+// ---------------------------------------------------------------------------
+// a frame whose keys exceeded its key buffers (kErrKeyCap; its sort and the
+// passes above then had no keys and wrote the background): every tile walks
+// all visible splats in depth order instead, and the quarter tests of the
+// staging keep only those whose support can reach it.  The image is the
+// sequential result, only slower to get.
+// ---------------------------------------------------------------------------
+template <bool kAudit>
+__global__ void __launch_bounds__(kBlendThreads) blend_all_kernel(const FrameDev *__restrict__ fd,
+                                                                  const float4 *__restrict__ splat,
+                                                                  const uint32_t *__restrict__ order,
+                                                                  const uint32_t *__restrict__ counters,
+                                                                  unsigned long long *__restrict__ pairs)
 {
-    const uint32_t n_tiles = tiles_x * tiles_y;
-    constexpr uint64_t kMaxGrid = 1u << 20;  // beyond, workgroups loop over further items
-    hipLaunchKernelGGL(blend_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, order,
-                       scratch, need, pairs);
+    if (!(counters[kRenErr] & kErrKeyCap)) return;  // uniform: the frame had room for its keys
+    __shared__ BlendShared sh;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const CamArgs &cam = fd->cam;
+    float4 *image = reinterpret_cast<float4 *>(fd->image);
+    const uint32_t n_vis = counters[kRenVisible];
+    for (uint32_t tile = blockIdx.x; tile < cam.tiles_x * cam.tiles_y; tile += gridDim.x) {
+        const TileGeo g = tile_geo(cam, tile, wid, lane);
+        Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u, 0u};
+        blend_range<kAudit>(0, n_vis, splat, order, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        write_pixel(cam, g, px, image);
+        count_pairs(px, lane, pairs);
+        __syncthreads();  // the next tile reuses the staged batch
+    }
+}
+
+// launched after every frame sized by capacity: a small grid, since it
+// returns at once unless the frame's keys did not fit
+void launch_blend_all(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
+                      const uint32_t *order, const uint32_t *counters, unsigned long long *pairs, bool audit)
+{
+    const uint32_t grid = n_tiles < 1024u ? n_tiles : 1024u;
+    if (audit)
+        hipLaunchKernelGGL(blend_all_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order, counters,
+                           pairs);
+    else
+        hipLaunchKernelGGL(blend_all_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order,
+                           counters, pairs);
+}
+
+template <bool kAudit>
+static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
+                           const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
+                           const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
+                           float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs)
+{
+    // beyond kMaxGrid items workgroups loop over further ones: a capacity-sized
+    // bound on the items (frames sized without a host wait) launches no more
+    constexpr uint64_t kMaxGrid = 16384;
+    hipLaunchKernelGGL(blend_kernel<kAudit>, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+                       order, scratch, need, pairs);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
         // few chunks hold a stop to walk again: 2048 workgroups loop over them
         // rather than one per chunk of the bound (mostly empty workgroups)
         constexpr uint64_t kRewalkGrid = 2048;
         const uint32_t gc = (uint32_t)(max_chunks < kRewalkGrid ? max_chunks : kRewalkGrid);
-        hipLaunchKernelGGL(chunk_kernel, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase, items,
-                           counters, scratch, need, pairs);
+        hipLaunchKernelGGL(chunk_kernel<kAudit>, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+                           items, counters, scratch, need, pairs);
         hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
                            need, rewalk, counters);
-        hipLaunchKernelGGL(rewalk_kernel, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+        hipLaunchKernelGGL(rewalk_kernel<kAudit>, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                            scratch, pend, rewalk, counters, pairs);
     }
+}
+
+// max_items / max_chunks bound the chunk work items and chunks (grids are
+// capped and loop over the device-side counts)
+void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
+                  const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
+                  const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
+                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, bool audit)
+{
+    const uint32_t n_tiles = tiles_x * tiles_y;
+    if (audit)
+        launch_blend_t<true>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
+                             scratch, pend, need, rewalk, pairs);
+    else
+        launch_blend_t<false>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items,
+                              max_chunks, scratch, pend, need, rewalk, pairs);
 }
 
 }  // namespace v3dg

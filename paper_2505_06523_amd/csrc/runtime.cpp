@@ -20,6 +20,7 @@
 #include "../../include/v3dg.h"
 #include "v3dg_internal.h"
 #include "page_lru.h"
+#include "page_store.h"
 
 using namespace v3dg;
 
@@ -190,10 +191,19 @@ struct Ctx {
     int last_buf = 0;
     int sort_mode = V3DG_SORT_DEPTH_FIRST;
     uint32_t profiling = 0;   // stages timed with events (bit per stage)
+    bool audit_pairs = false; // blending also counts the pairs it takes
     v3dg_profile acc{};
-    unsigned long long *pairs_dev = nullptr;
+    unsigned long long *pairs_dev = nullptr;  // walked and taken (pixel, splat) pairs
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
+    // frames sized by capacity publish their counts into a ring of records in
+    // mapped pinned memory (FrameRec); the host reads a record once the
+    // frame's event has completed
+    static constexpr uint32_t kRecRing = 16;
+    FrameRec *rec_h = nullptr, *rec_d = nullptr;
+    hipEvent_t rec_ev[kRecRing] = {};
+    uint32_t rec_want[kRecRing] = {};  // the tag each record must carry
+    uint32_t rec_head = 0, rec_n = 0, rec_seq = 0;
 };
 
 struct v3dg_selection {
@@ -238,7 +248,8 @@ struct v3dg_scene : Ctx {
     // rows (plane_stride = 64 pool_clusters); rowinfo[k].x is the first pool
     // row of a resident cluster.  Pages form an LRU list (head: most recent).
     uint32_t pool_clusters = 0, page_bytes = 0, geo_bytes = 4, sh_bytes = 4, n_sh = 0, stage_cap = 0;
-    std::vector<uint8_t> h_pages;
+    uint64_t stage_stride = 0;  // bytes between staged images (the store's slot)
+    PageStore pages;            // page images: host memory or a file
     PageLRU lru;  // which cluster holds which page
     uint8_t *stage_h = nullptr, *stage_d = nullptr;
     uint4 *ups_h = nullptr, *ups_d = nullptr;
@@ -249,6 +260,14 @@ struct v3dg_scene : Ctx {
     // so that their read-back and paging overlap that frame's later stages
     hipStream_t sel_stream = nullptr;
     hipEvent_t ev_proj = nullptr, ev_sel = nullptr;
+    // v3dg_render without host waits: the first frame of an image size is
+    // sized exactly (one wait after the tile scan); later frames of that size
+    // run on key buffers of at least kRenderKeysPerPixel keys per pixel and
+    // twice the most keys seen, and their counts come back through FrameRec
+    uint32_t rend_tiles = 0;        // tiles of the image size the capacity is set for (0: none)
+    uint64_t keys_seen = 0;         // most keys of any frame seen
+    uint32_t rend_err = 0;          // error flags of capacity frames read back since the last frame stats
+    bool last_keycap = false;       // the last frame's keys exceeded its buffers (blended without them)
     Attribs attribs() const { return Attribs{pos_planes, geo_planes, sh_planes, plane_stride}; }
 };
 
@@ -452,13 +471,21 @@ int ctx_init(Ctx *c, int device, hipStream_t stream)
     c->stream = stream;
     int rc;
     if ((rc = dev_alloc(&c->fdev, 1))) return rc;
-    if ((rc = dev_alloc(&c->pairs_dev, 1))) return rc;
+    if ((rc = dev_alloc(&c->pairs_dev, 2))) return rc;
     HIP_TRY(hipMemset(c->fdev, 0, sizeof(FrameDev)));
-    HIP_TRY(hipMemset(c->pairs_dev, 0, sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(c->pairs_dev, 0, 2 * sizeof(unsigned long long)));
     if (hipHostMalloc((void **)&c->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         c->pinned = nullptr;
         return fail(V3DG_ERR_OOM, "pinned allocation failed");
     }
+    if (hipHostMalloc((void **)&c->rec_h, Ctx::kRecRing * sizeof(FrameRec), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
+        c->rec_h = nullptr;
+        return fail(V3DG_ERR_OOM, "pinned allocation failed");
+    }
+    std::memset(c->rec_h, 0, Ctx::kRecRing * sizeof(FrameRec));
+    HIP_TRY(hipHostGetDevicePointer((void **)&c->rec_d, c->rec_h, 0));
+    for (uint32_t i = 0; i < Ctx::kRecRing; ++i) HIP_TRY(hipEventCreateWithFlags(&c->rec_ev[i], hipEventDisableTiming));
     return V3DG_OK;
 }
 
@@ -501,6 +528,10 @@ void ctx_release(Ctx *c)
     dev_free(c->rewalk);
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
+    if (c->rec_h) (void)hipHostFree(c->rec_h);
+    c->rec_h = c->rec_d = nullptr;
+    for (uint32_t i = 0; i < Ctx::kRecRing; ++i)
+        if (c->rec_ev[i]) (void)hipEventDestroy(c->rec_ev[i]);
     for (auto &r : c->prof) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -658,9 +689,17 @@ void run_sort(Ctx *c, KT *const kb[2], uint32_t *const vb[2], const uint32_t *n_
 
 // Depth-first binning: tile-id keys of type KT in depth order, their stable
 // sort, and the tile ranges with the blend plan.
+// Where a frame publishes its counts (capacity-sized frames of v3dg_render)
+struct FramePub {
+    const uint32_t *sel_counters = nullptr;
+    FrameRec *rec = nullptr;  // device address of the record, nullptr: none
+    uint32_t seq = 0;
+    bool fallback = false;    // blend the frame from all visible splats when its keys do not fit
+};
+
 template <typename KT>
 void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev, uint64_t KL, uint32_t key_bits,
-               uint32_t n_tiles, uint64_t max_chunks, int *buf, uint32_t *passes)
+               uint32_t n_tiles, uint64_t max_chunks, int *buf, uint32_t *passes, const FramePub &pub)
 {
     KT *kb[2] = {reinterpret_cast<KT *>(c->keys[0]), reinterpret_cast<KT *>(c->keys[1])};
     const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
@@ -674,7 +713,8 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
     {
         Stage st(c, V3DG_STAGE_RANGES);
         launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges, c->cbase,
-                               c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
+                               c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks, pub.sel_counters, pub.rec,
+                               pub.seq);
     }
 }
 
@@ -701,7 +741,7 @@ struct FrameInfo {
 //     then incomplete).  The caller ensures capacities first; from_fd says
 //     the camera and image were copied into c->fdev.  Capturable in a graph.
 int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, const SelView &sel, bool capacity,
-                  bool from_fd, FrameInfo *fi)
+                  bool from_fd, FrameInfo *fi, const FramePub &pub = FramePub{})
 {
     int rc;
     const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
@@ -765,7 +805,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         fi->n_visible = c->pinned[kRenVisible];
         fi->n_sel_clusters = c->pinned[8 + kSelNClusters];
         if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
-        if ((err & kErrOverflow) || K >= 0xffffffffull)
+        if ((err & (kErrOverflow | kErrKeyCap)) || K >= 0xffffffffull)
             return fail(V3DG_ERR_CAPACITY, "frame needs %llu keys; the limit is 2^32-1", (unsigned long long)K);
         if ((rc = ensure_keys(c, K))) return rc;
         if ((rc = ensure_chunks(c, K, n_tiles))) return rc;
@@ -783,9 +823,9 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     if (depth_first) {
         key_bits = tile_bits;
         if (n_tiles <= kTileKey16Max)
-            tile_keys<uint16_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes);
+            tile_keys<uint16_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes, pub);
         else
-            tile_keys<uint32_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes);
+            tile_keys<uint32_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes, pub);
     } else {
         {
             Stage st(c, V3DG_STAGE_EMIT);
@@ -804,7 +844,11 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         Stage st(c, V3DG_STAGE_BLEND);
         launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase,
                      c->items, c->cbase + c->tiles_cap, c->rcounters, KL / kChunk, max_chunks, c->scratch, c->pend,
-                     c->need, c->rewalk, c->pairs_dev);
+                     c->need, c->rewalk, c->pairs_dev, c->audit_pairs);
+        // a frame whose keys did not fit is blended from its depth-sorted slots
+        if (pub.fallback && depth_first)
+            launch_blend_all(c->stream, c->fdev, n_tiles, c->splat, c->dval[0], c->rcounters, c->pairs_dev,
+                             c->audit_pairs);
     }
     HIP_TRY(hipGetLastError());
     fi->key_bits = key_bits;
@@ -833,6 +877,50 @@ void record_frame(Ctx *c, const FrameInfo &fi, uint64_t pixels)
     c->last_buf = fi.buf;
 }
 
+// Reads the records of finished capacity-sized frames, oldest first (all of
+// them, waiting, when block is set): their counts go to the profile and the
+// frame stats, and the most keys seen decides the next capacity.
+int drain_records(v3dg_scene *s, bool block)
+{
+    while (s->rec_n > 0) {
+        const uint32_t slot = s->rec_head;
+        if (block) {
+            HIP_TRY(hipEventSynchronize(s->rec_ev[slot]));
+        } else {
+            const hipError_t q = hipEventQuery(s->rec_ev[slot]);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return fail(V3DG_ERR_HIP, "frame failed: %s", hipGetErrorString(q));
+        }
+        const volatile FrameRec &r = s->rec_h[slot];
+        if (r.seq != s->rec_want[slot]) return fail(V3DG_ERR_DEVICE, "a frame did not publish its counts");
+        const uint64_t K = (uint64_t)r.keys_lo | ((uint64_t)r.keys_hi << 32);
+        s->keys_seen = std::max(s->keys_seen, K);
+        s->acc.keys += K;
+        s->acc.visible += r.visible;
+        s->acc.slots += r.n_slots;
+        s->acc.sel_clusters += r.n_clusters;
+        s->last.n_keys = K;
+        s->last.n_slots = r.n_slots;
+        s->last_keycap = (r.err & kErrKeyCap) != 0;
+        s->rend_err |= r.err & (kErrSpin | kErrOverflow);
+        s->rec_head = (slot + 1) % Ctx::kRecRing;
+        s->rec_n -= 1;
+    }
+    return V3DG_OK;
+}
+
+// Key buffers (and chunk records) for frames of n_tiles tiles sized by
+// capacity: at least kRenderKeysPerPixel keys per pixel and twice the most
+// keys seen.  Grows only (a growth waits for the frames in flight).
+constexpr uint64_t kRenderKeysPerPixel = 16;
+int ensure_render_capacity(v3dg_scene *s, uint32_t n_tiles, uint64_t pixels)
+{
+    const uint64_t want = std::min<uint64_t>(std::max(2 * s->keys_seen, kRenderKeysPerPixel * pixels), 0xfffff000ull);
+    int rc;
+    if (want > s->cap_keys && (rc = ensure_keys(s, want, true))) return rc;
+    return ensure_chunks(s, s->cap_keys, n_tiles);
+}
+
 int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, float *image)
 {
     CamArgs cam;
@@ -843,10 +931,57 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     if (s->pool_clusters && sel->stream_frame <= s->lru.max_evicted_stamp)
         return fail(V3DG_ERR_INVALID_ARG, "the selection's clusters were paged out by a later select: select again");
     HIP_TRY(hipSetDevice(s->device));
+    const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
+    const uint64_t pixels = (uint64_t)cam.width * cam.height;
     FrameInfo fi;
     const SelView sv{sel->counters, sel->slot_row, sel->slot_inst};
-    if ((rc = enqueue_frame(s, s, cam, image, sv, false, false, &fi))) return rc;
-    record_frame(s, fi, (uint64_t)cam.width * cam.height);
+    if ((rc = drain_records(s, false))) return rc;
+    if (s->sort_mode != V3DG_SORT_DEPTH_FIRST || s->rend_tiles != n_tiles) {
+        // the first frame of an image size (or a 64-bit-key frame): sized
+        // exactly after one host wait; it sets the capacity of later frames
+        if ((rc = drain_records(s, true))) return rc;
+        if ((rc = enqueue_frame(s, s, cam, image, sv, false, false, &fi))) return rc;
+        record_frame(s, fi, pixels);
+        s->last_keycap = false;
+        s->keys_seen = std::max(s->keys_seen, fi.K);
+        // the next frame of this size grows the buffers before it runs (not
+        // now: this frame's sorted keys stay readable until then)
+        if (s->sort_mode == V3DG_SORT_DEPTH_FIRST) s->rend_tiles = n_tiles;
+        return V3DG_OK;
+    }
+    // later frames: no host wait; launches are sized by the capacity and the
+    // kernels read their counts on the device
+    if ((rc = ensure_render_capacity(s, n_tiles, pixels))) return rc;
+    if (s->rec_n == Ctx::kRecRing) {  // a ring of frames in flight: wait for the oldest
+        const uint32_t keep = s->rec_n;
+        while (s->rec_n == keep)
+            if ((rc = drain_records(s, true))) return rc;
+    }
+    if ((rc = ensure_itab(s, s->n_inst))) return rc;
+    if ((rc = ensure_slots(s, s->cap_slots))) return rc;
+    if ((rc = ensure_tiles(s, n_tiles))) return rc;
+    epoch_advance(s);
+    const uint32_t slot = (s->rec_head + s->rec_n) % Ctx::kRecRing;
+    FramePub pub;
+    pub.sel_counters = sel->counters;
+    pub.rec = s->rec_d + slot;
+    pub.seq = ++s->rec_seq;
+    pub.fallback = true;
+    s->rec_want[slot] = pub.seq;
+    if ((rc = enqueue_frame(s, s, cam, image, sv, true, false, &fi, pub))) return rc;
+    HIP_TRY(hipEventRecord(s->rec_ev[slot], s->stream));
+    s->rec_n += 1;
+    // counts that the host knows now; keys, slots and visible come with the record
+    s->acc.frames += 1;
+    s->acc.tiles += fi.n_tiles;
+    s->acc.pixels += pixels;
+    s->acc.sort_passes += fi.passes;
+    s->acc.depth_sorts += 1;
+    s->last.n_tiles = fi.n_tiles;
+    s->last.key_bits = fi.key_bits;
+    s->last.sort_mode = V3DG_SORT_DEPTH_FIRST;
+    s->last.sort_passes = fi.passes;
+    s->last_buf = fi.buf;
     return V3DG_OK;
 }
 
@@ -903,18 +1038,23 @@ int page_in(v3dg_scene *s, hipStream_t st, const uint32_t *gid, const uint32_t *
     uint32_t touched = 0;
     if (!s->lru.plan(ks.data(), ks.size(), miss, touched))
         return fail(V3DG_ERR_CAPACITY, "the cut needs more resident clusters than the pool's %u", s->pool_clusters);
+    std::vector<uint32_t> chunk;
     for (size_t i = 0; i < miss.size(); i += s->stage_cap) {
         const uint32_t m = (uint32_t)std::min<size_t>(s->stage_cap, miss.size() - i);
-        for (uint32_t j = 0; j < m; ++j) {
-            const uint32_t k = miss[i + j];
-            std::memcpy(s->stage_h + (uint64_t)j * s->page_bytes, s->h_pages.data() + (uint64_t)k * s->page_bytes,
-                        s->page_bytes);
-            s->ups_h[j] = make_uint4(k, s->lru.page_of(k), s->h_count[k], 0u);
+        // ascending clusters: a run of neighbours is one read from a page file
+        chunk.assign(miss.begin() + i, miss.begin() + i + m);
+        std::sort(chunk.begin(), chunk.end());
+        for (uint32_t j = 0; j < m; ++j) s->ups_h[j] = make_uint4(chunk[j], s->lru.page_of(chunk[j]), s->h_count[chunk[j]], 0u);
+        std::string ioerr;
+        hipError_t e = hipSuccess;
+        if (!s->pages.get(chunk.data(), m, s->stage_h, &ioerr)) {
+            for (size_t q = i; q < miss.size(); ++q) s->lru.release(miss[q]);
+            return fail(V3DG_ERR_IO, "paging in clusters failed: %s", ioerr.c_str());
         }
-        hipError_t e = hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->page_bytes, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(s->stage_d, s->stage_h, (uint64_t)m * s->stage_stride, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(s->ups_d, s->ups_h, m * sizeof(uint4), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) {
-            launch_stream_scatter(st, s->stage_d, s->ups_d, m, s->page_bytes, s->geo_bytes, s->sh_bytes,
+            launch_stream_scatter(st, s->stage_d, s->ups_d, m, s->stage_stride, s->geo_bytes, s->sh_bytes,
                                   s->n_sh, s->pos_planes, s->geo_planes, s->sh_planes, s->plane_stride, s->rowinfo);
             e = hipGetLastError();
         }
@@ -930,6 +1070,7 @@ int page_in(v3dg_scene *s, hipStream_t st, const uint32_t *gid, const uint32_t *
     s->sstats.evictions = s->lru.evictions;
     s->sstats.last_pages_in = miss.size();
     s->sstats.last_resident_used = touched + (uint32_t)miss.size();
+    s->sstats.file_reads = s->pages.reads();
     return V3DG_OK;
 }
 
@@ -960,6 +1101,7 @@ void scene_release(v3dg_scene *s)
     if (s->sel_stream) (void)hipStreamDestroy(s->sel_stream);
     if (s->stage_h) (void)hipHostFree(s->stage_h);
     if (s->ups_h) (void)hipHostFree(s->ups_h);
+    s->pages.close();
     ctx_release(s);
 }
 
@@ -1059,9 +1201,21 @@ int v3dg_load_hierarchy(const v3dg_hierarchy_desc *d, const double *instances_3x
 int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *d, const double *instances_3x4, uint32_t n_instances,
                                  void *hip_stream, uint32_t flags, uint32_t pool_clusters, v3dg_scene **out)
 {
+    return v3dg_load_hierarchy_streamed_file(d, instances_3x4, n_instances, hip_stream, flags, pool_clusters, nullptr,
+                                             0, out);
+}
+
+int v3dg_load_hierarchy_streamed_file(const v3dg_hierarchy_desc *d, const double *instances_3x4,
+                                      uint32_t n_instances, void *hip_stream, uint32_t flags, uint32_t pool_clusters,
+                                      const char *page_file, uint32_t file_flags, v3dg_scene **out)
+{
     g_err.clear();
     if (!d || !out) return fail(V3DG_ERR_INVALID_ARG, "desc and out must be non-NULL");
     if (pool_clusters >= (1u << 26)) return fail(V3DG_ERR_INVALID_ARG, "pool_clusters must be < 2^26");
+    if (page_file && (!page_file[0] || pool_clusters == 0))
+        return fail(V3DG_ERR_INVALID_ARG, "a page file needs a non-empty path and pool_clusters > 0");
+    if (file_flags & ~(V3DG_PAGE_FILE_DIRECT | V3DG_PAGE_FILE_KEEP))
+        return fail(V3DG_ERR_INVALID_ARG, "unknown page file flags 0x%x", file_flags);
     *out = nullptr;
     if (d->precision > V3DG_FP16) return fail(V3DG_ERR_INVALID_ARG, "unknown precision %u", d->precision);
     if (d->sh_degree > 3) return fail(V3DG_ERR_INVALID_ARG, "sh_degree %u > 3", d->sh_degree);
@@ -1279,9 +1433,20 @@ int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *d, const double *ins
             s->sh_bytes = (uint32_t)sh_bytes;
             s->n_sh = 3u * (uint32_t)ncoef;
             s->page_bytes = 3u * 256u + (uint32_t)kGeoPlanes * 64u * s->geo_bytes + s->n_sh * 64u * s->sh_bytes;
-            s->h_pages.assign((uint64_t)NC * s->page_bytes, 0);
+            std::string ioerr;
+            if (page_file) {
+                if (!s->pages.init_file(page_file, NC, s->page_bytes, (file_flags & V3DG_PAGE_FILE_DIRECT) != 0,
+                                        (file_flags & V3DG_PAGE_FILE_KEEP) != 0, &ioerr))
+                    return bail(fail(V3DG_ERR_IO, "page file %s: %s", page_file, ioerr.c_str()));
+            } else {
+                s->pages.init_memory(NC, s->page_bytes);
+            }
+            s->stage_stride = s->pages.stride();
+            s->sstats.tier = s->pages.tier();
+            std::vector<uint8_t> image(s->page_bytes);
             for (uint32_t k = 0; k < NC; ++k) {
-                uint8_t *img = s->h_pages.data() + (uint64_t)k * s->page_bytes;
+                uint8_t *img = image.data();
+                std::memset(img, 0, image.size());
                 const uint64_t r0 = d->first_row[k], cnt = d->count[k];
                 for (int j = 0; j < 3; ++j) std::memcpy(img + 256u * j, &hpos[j * ps + r0], cnt * 4);
                 uint8_t *g = img + 768;
@@ -1292,17 +1457,19 @@ int v3dg_load_hierarchy_streamed(const v3dg_hierarchy_desc *d, const double *ins
                 for (uint32_t j = 0; j < s->n_sh; ++j)
                     std::memcpy(h + (uint64_t)j * 64 * sh_bytes, (const uint8_t *)src_sh + (j * ps + r0) * sh_bytes,
                                 cnt * sh_bytes);
+                if (!s->pages.put(k, img, &ioerr)) return bail(fail(V3DG_ERR_IO, "%s", ioerr.c_str()));
             }
+            if (!s->pages.seal(&ioerr)) return bail(fail(V3DG_ERR_IO, "%s", ioerr.c_str()));
             const uint32_t P = s->pool_clusters;
             s->lru.init(NC, P);
             s->stage_cap = std::min<uint32_t>(P, 2048u);
             s->sstats.pool_clusters = P;
-            if (hipHostMalloc((void **)&s->stage_h, (uint64_t)s->stage_cap * s->page_bytes, hipHostMallocDefault) !=
+            if (hipHostMalloc((void **)&s->stage_h, (uint64_t)s->stage_cap * s->stage_stride, hipHostMallocDefault) !=
                     hipSuccess ||
                 hipHostMalloc((void **)&s->ups_h, s->stage_cap * sizeof(uint4), hipHostMallocDefault) != hipSuccess) {
                 return bail(fail(V3DG_ERR_OOM, "pinned staging allocation failed"));
             }
-            if ((rc = dev_alloc(&s->stage_d, (uint64_t)s->stage_cap * s->page_bytes))) return bail(rc);
+            if ((rc = dev_alloc(&s->stage_d, (uint64_t)s->stage_cap * s->stage_stride))) return bail(rc);
             if ((rc = dev_alloc(&s->ups_d, s->stage_cap))) return bail(rc);
             // non-blocking: no implicit wait for work on the null stream (the
             // scene's stream may be it); ordering is by the two events alone
@@ -1570,10 +1737,13 @@ int v3dg_get_frame_stats(v3dg_scene *s, v3dg_frame_stats *out)
     if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
     HIP_TRY(hipSetDevice(s->device));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    int rc = drain_records(s, true);
+    if (rc) return rc;
     static_assert(kRenErr < 32 && kRenFp64 < 32 && kRenConicClamp < 32, "frame stats read the first 32 counters");
     uint32_t ctr[32] = {0};
     if (s->rcounters) HIP_TRY(hipMemcpy(ctr, s->rcounters, sizeof(ctr), hipMemcpyDeviceToHost));
-    const uint32_t err = ctr[kRenErr];
+    const uint32_t err = ctr[kRenErr] | s->rend_err;
+    s->rend_err = 0;
     if (err & kErrSpin) return fail(V3DG_ERR_DEVICE, "a look-back wait expired on the device");
     if (err & kErrOverflow) return fail(V3DG_ERR_DEVICE, "tile counting and key emission disagreed");
     *out = s->last;
@@ -1589,6 +1759,8 @@ int v3dg_copy_projection(v3dg_scene *s, float *mean2, float *conic, float *rgb, 
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
     HIP_TRY(hipSetDevice(s->device));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    int rc = drain_records(s, true);
+    if (rc) return rc;
     const uint64_t n = s->last.n_slots;
     if (n_out) *n_out = n;
     if (n > cap) return fail(V3DG_ERR_CAPACITY, "%llu slots do not fit in %llu", (unsigned long long)n, (unsigned long long)cap);
@@ -1677,6 +1849,10 @@ int v3dg_copy_sorted_keys(v3dg_scene *s, uint64_t *keys, uint32_t *vals, uint64_
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
     HIP_TRY(hipSetDevice(s->device));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    int rc = drain_records(s, true);
+    if (rc) return rc;
+    if (s->last_keycap)
+        return fail(V3DG_ERR_CAPACITY, "the last frame's keys exceeded its key buffers: it was blended without them");
     const uint64_t n = s->last.n_keys;
     if (n_out) *n_out = n;
     if (n > cap) return fail(V3DG_ERR_CAPACITY, "%llu keys do not fit in %llu", (unsigned long long)n, (unsigned long long)cap);
@@ -1726,6 +1902,7 @@ int v3dg_set_profiling(v3dg_scene *s, int stage_mask)
     g_err.clear();
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
     s->profiling = (uint32_t)stage_mask & V3DG_PROFILE_ALL;
+    s->audit_pairs = (stage_mask & V3DG_PROFILE_PAIR_AUDIT) != 0;
     return V3DG_OK;
 }
 
@@ -1735,11 +1912,14 @@ int v3dg_collect_profile(v3dg_scene *s, v3dg_profile *out)
     if (!s || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument");
     HIP_TRY(hipSetDevice(s->device));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    unsigned long long pairs = 0;
-    HIP_TRY(hipMemcpy(&pairs, s->pairs_dev, sizeof(pairs), hipMemcpyDeviceToHost));
+    int rc = drain_records(s, true);
+    if (rc) return rc;
+    unsigned long long pairs[2] = {0, 0};
+    HIP_TRY(hipMemcpy(pairs, s->pairs_dev, sizeof(pairs), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemset(s->pairs_dev, 0, sizeof(pairs)));
     v3dg_profile p = s->acc;
-    p.pairs = pairs;
+    p.pairs = pairs[0];
+    p.pairs_taken = pairs[1];
     for (int i = 0; i < V3DG_N_STAGES; ++i) {
         p.ms[i] = 0.0;
         p.launches[i] = 0;

@@ -17,6 +17,8 @@
 //   sort_pass    one onesweep pass: wavefront ballot ranking into LDS, per-digit
 //                decoupled look-back across partitions, coalesced scatter
 //   tile_ranges  [start, end) of each tile in the sorted keys
+#include <algorithm>
+
 #include "v3dg_internal.h"
 
 namespace v3dg {
@@ -185,7 +187,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
             // a frame whose keys do not fit leaves holes in the key buffer: it
             // then sorts, bins and blends nothing (and is flagged)
             counters[kRenKeysEff] = (uint32_t)(tot <= key_cap ? tot : 0);
-            if (tot > key_cap) atomicOr(&counters[kRenErr], kErrOverflow);
+            if (tot > key_cap) atomicOr(&counters[kRenErr], kErrKeyCap);
         }
     }
     __syncthreads();
@@ -235,8 +237,8 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ 
         const uint32_t nt = tiles[t];
         if (nt == 0) continue;
         uint64_t off = offsets[j];
-        if (off + nt > key_cap) {
-            atomicOr(err, kErrOverflow);
+        if (off + nt > key_cap) {  // the frame's keys exceed the buffers (flagged by the scan too)
+            atomicOr(err, kErrKeyCap);
             continue;
         }
         const uint64_t end = off + nt;
@@ -369,8 +371,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     // output range of the workgroup: from its first rank to its last rank's end
     if (tid == 0) sh.lo = off;
     if (valid && (j + 1 == n || tid == kEmitThreads - 1)) sh.hi = off + nt;
-    if (off + nt > key_cap) {  // never with the capacity the host allocates
-        atomicOr(err, kErrOverflow);
+    if (off + nt > key_cap) {  // the frame's keys exceed the buffers (flagged by the scan too)
+        atomicOr(err, kErrKeyCap);
         nt = 0;
     }
     __syncthreads();
@@ -645,16 +647,14 @@ __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint3
     return ((uint64_t)epoch << 34) | (flag << 32) | v;
 }
 
+// 16-bit keys: three workgroups per CU fit in LDS, so registers are held to
+// three waves per SIMD as well
 template <typename K, int ITEMS>
-__global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__restrict__ keys_in,
-                                                                 const uint32_t *__restrict__ vals_in,
-                                                                 K *__restrict__ keys_out,
-                                                                 uint32_t *__restrict__ vals_out,
-                                                                 const uint32_t *__restrict__ n_dev, uint32_t n_host,
-                                                                 int shift, const uint32_t *__restrict__ hist,
-                                                                 uint64_t *status,
-                                                                 const uint32_t *__restrict__ epoch_dev,
-                                                                 uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 2 ? 3 : 1)))
+sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, K *__restrict__ keys_out,
+                 uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
+                 const uint32_t *__restrict__ hist, uint64_t *status, const uint32_t *__restrict__ epoch_dev,
+                 uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
 {
     constexpr int NW = kSortThreads / kWave;           // waves per block
     constexpr int PART = kSortThreads * ITEMS;         // keys of a partition
@@ -668,15 +668,26 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_ticket;
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int wid = (int)threadIdx.x / kWave;
     const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
     const uint32_t epoch = epoch_dev ? *epoch_dev + epoch_arg : epoch_arg;
+    const uint32_t nparts = (n + PART - 1) / PART;
+    // Partitions are claimed in ticket order until none is left, so the grid
+    // need not match the key count (a bound on it, or far fewer workgroups,
+    // both work).  A partition only waits on lower tickets, claimed earlier
+    // by running workgroups.
+    for (;;) {
+    // the thread index, opaque to the compiler once per partition: otherwise
+    // the per-item offsets derived from it are hoisted out of the loop and
+    // held in about 48 more registers, which costs a workgroup per CU
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & (kWave - 1);
     for (int i = tid; i < NW * kRadix; i += kSortThreads) (&s_whist[0][0])[i] = 0u;
     if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint32_t p = s_ticket;
-    const uint32_t nparts = (n + PART - 1) / PART;
-    if (p >= nparts) return;
+    if (p >= nparts) return;  // uniform
     const uint32_t part_base = p * (uint32_t)PART;
     const uint32_t wave_base = part_base + (uint32_t)wid * WAVE_KEYS;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
@@ -785,6 +796,31 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(const K *__rest
             }
         }
     }
+    __syncthreads();  // the next partition reuses the LDS arrays and the ticket word
+    }
+}
+
+// Workgroups of one pass that are resident on the device at once.  A pass
+// launches no more than that: its workgroups claim partitions until none is
+// left, and a workgroup past the resident set would only be dispatched once
+// the work is done, to find nothing (such empty workgroups still cost their
+// dispatch, at the end of the pass).
+template <typename K, int ITEMS>
+static uint32_t sort_pass_resident()
+{
+    static uint32_t per_dev[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return (uint32_t)kSortMaxGrid;
+    if (per_dev[dev] == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sort_pass_kernel<K, ITEMS>, kSortThreads, 0) !=
+                hipSuccess ||
+            cus <= 0 || per_cu <= 0)
+            return (uint32_t)kSortMaxGrid;
+        per_dev[dev] = (uint32_t)std::min<uint64_t>((uint64_t)cus * (uint64_t)per_cu, kSortMaxGrid);
+    }
+    return per_dev[dev];
 }
 
 template <typename K>
@@ -793,16 +829,18 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide)
 {
     if (n == 0) return;
-    // wide partitions (8192 keys) for large 32-bit sorts: fewer partitions to
+    // wide partitions (6144 keys) for large 32-bit sorts: fewer partitions to
     // look back over and longer digit runs to store
     if (wide && sizeof(K) <= 4) {
-        const uint32_t nparts = (uint32_t)((n + kSortPartWide - 1) / kSortPartWide);
-        hipLaunchKernelGGL((sort_pass_kernel<K, kSortItemsWide>), dim3(nparts), dim3(kSortThreads), 0, st, keys_in,
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kSortPartWide - 1) / kSortPartWide,
+                                                           sort_pass_resident<K, kSortItemsWide>());
+        hipLaunchKernelGGL((sort_pass_kernel<K, kSortItemsWide>), dim3(grid), dim3(kSortThreads), 0, st, keys_in,
                            vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
                            status, epoch_dev, epoch, ticket, err);
     } else {
-        const uint32_t nparts = (uint32_t)((n + kSortPart - 1) / kSortPart);
-        hipLaunchKernelGGL((sort_pass_kernel<K, kSortItems>), dim3(nparts), dim3(kSortThreads), 0, st, keys_in,
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kSortPart - 1) / kSortPart,
+                                                           sort_pass_resident<K, kSortItems>());
+        hipLaunchKernelGGL((sort_pass_kernel<K, kSortItems>), dim3(grid), dim3(kSortThreads), 0, st, keys_in,
                            vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
                            status, epoch_dev, epoch, ticket, err);
     }
@@ -829,9 +867,20 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
                                                           int shift, uint32_t n_tiles, uint2 *__restrict__ ranges,
                                                           uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
                                                           uint32_t *__restrict__ order, uint32_t *counters,
-                                                          uint32_t max_chunks)
+                                                          uint32_t max_chunks, const uint32_t *__restrict__ sel_counters,
+                                                          FrameRec *rec, uint32_t seq)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rec && t == 0) {  // every earlier kernel of the frame has set its counters and flags
+        rec->keys_lo = counters[kRenKeysLo];
+        rec->keys_hi = counters[kRenKeysHi];
+        rec->visible = counters[kRenVisible];
+        rec->err = counters[kRenErr];
+        rec->n_slots = sel_counters[kSelNGaussians];
+        rec->n_clusters = sel_counters[kSelNClusters];
+        __threadfence_system();
+        __hip_atomic_store(&rec->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lt = (1ull << lane) - 1ull;
     const bool in = t < n_tiles;
@@ -873,11 +922,11 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
 template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
                         uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *order, uint32_t *counters,
-                        uint64_t max_chunks)
+                        uint64_t max_chunks, const uint32_t *sel_counters, FrameRec *rec, uint32_t seq)
 {
     hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, n_dev, shift,
                        n_tiles, ranges, cbase, items, order, counters,
-                       (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull));
+                       (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull), sel_counters, rec, seq);
 }
 
 template void launch_emit32<uint16_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
@@ -899,10 +948,13 @@ template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const ui
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
 template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint2 *,
-                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
+                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t, const uint32_t *,
+                                          FrameRec *, uint32_t);
 template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *,
-                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
+                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t, const uint32_t *,
+                                          FrameRec *, uint32_t);
 template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *,
-                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t);
+                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t, const uint32_t *,
+                                          FrameRec *, uint32_t);
 
 }  // namespace v3dg

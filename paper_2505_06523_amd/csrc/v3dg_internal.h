@@ -60,6 +60,13 @@ constexpr uint32_t kEpochLimit = 1u << 30; // width of the epoch field of a sort
 constexpr uint64_t kFlagAgg = 1ull;
 constexpr uint64_t kFlagInc = 2ull;
 
+// The counts of one frame, written by the device into pinned host memory
+// once its keys are sorted, so that the host can read them after the frame
+// without a copy of its own.
+struct FrameRec {
+    uint32_t keys_lo, keys_hi, visible, err, n_slots, n_clusters, seq, pad;
+};
+
 // Device-side frame counters (u32 words) of a selection.
 enum SelCounter : int {
     kSelTicket = 0,
@@ -94,7 +101,8 @@ enum RenderCounter : int {
 
 // Error flag bits
 constexpr uint32_t kErrSpin = 1u;       // a bounded look-back wait expired
-constexpr uint32_t kErrOverflow = 2u;   // a count did not fit its field
+constexpr uint32_t kErrOverflow = 2u;   // a count did not fit its field, or counting and emission disagreed
+constexpr uint32_t kErrKeyCap = 4u;     // the frame's keys exceed its key buffers (capacity-sized launches)
 
 // ---- conservative tile coverage of a splat's support -----------------------
 // The support of a splat is {d : d^T Sigma^-1 d <= Q}, Q = 2 ln(255 o), the
@@ -229,7 +237,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanPart = kScanThreads * kScanItems;
 // exclusive scan of tiles[order[j]] (order may be NULL: identity); the total
 // goes to kRenKeysLo/Hi and to kRenKeysEff when it is at most key_cap (else
-// kRenKeysEff = 0 and kErrOverflow is raised: the frame's later steps then
+// kRenKeysEff = 0 and kErrKeyCap is raised: the frame's later steps then
 // have no keys to work on)
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
                        uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap);
@@ -255,6 +263,7 @@ constexpr int kSortItemsWide = 24;      // keys per thread of wide partitions
 constexpr int kSortPartWide = kSortThreads * kSortItemsWide;
 static_assert(kSortPartWide >= kSortPart, "look-back status is sized for partitions of kSortPart keys");
 constexpr uint64_t kSortWideFrom = 1u << 22;  // sorts of at least this many keys use wide partitions
+constexpr uint64_t kSortMaxGrid = 4096;       // workgroups of a pass (they claim partitions until none is left)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 256;
 // Digit histograms of all passes; the key count is n_dev ? *n_dev : n.
@@ -288,16 +297,27 @@ __device__ __forceinline__ uint32_t chunk_end(uint32_t c, uint32_t L)
 // work item (t, c) per chunk c >= 1 (items: counters[kRenItems]).  order is
 // a permutation of the tiles with the lists of at least kChunkFirst keys
 // first, so that the longest walks start first.
+// With rec (a record in mapped pinned host memory), the kernel also publishes
+// the frame's counts there, tagged seq: keys, visible slots and error flags
+// from counters, slots and clusters from the selection's sel_counters.
 template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
                         uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *order, uint32_t *counters,
-                        uint64_t max_chunks);
+                        uint64_t max_chunks, const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr,
+                        uint32_t seq = 0);
 // blend.hip
-// max_items / max_chunks bound the work items and chunks of the plan (grid sizes)
+// max_items / max_chunks bound the work items and chunks of the plan (grid
+// sizes).  pairs[0] counts the pairs walked; with audit, pairs[1] also counts
+// the pairs taken (alpha >= 1/255 at an active pixel), which slows the walk.
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                   const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
-                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs);
+                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, bool audit);
+// Frames whose keys exceeded the key buffers (kErrKeyCap): every tile walks
+// the n = counters[kRenVisible] visible slots in depth order (order: the
+// depth-sorted slots) and writes its pixels; other frames return at once.
+void launch_blend_all(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
+                      const uint32_t *order, const uint32_t *counters, unsigned long long *pairs, bool audit);
 // generic fill
 void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);
 

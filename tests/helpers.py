@@ -119,13 +119,13 @@ def flat_asset(pos, scale, rot, opacity, sh, sh_degree=0) -> sg.Asset:
     )
 
 
-def stacked_splats(n, seed, opacity_range, spread=0.15, depth=(1.0, 4.0)):
+def stacked_splats(n, seed, opacity_range, spread=0.15, depth=(1.0, 4.0), log_scale=-4.0):
     """n Gaussians stacked in front of the camera over a few tiles."""
     rng = np.random.default_rng(seed)
     z = rng.uniform(depth[0], depth[1], n)
     xy = rng.normal(0.0, spread, (n, 2)) * z[:, None] * 0.1
     pos = np.concatenate([xy, z[:, None]], axis=1)
-    scale = np.exp(rng.normal(-4.0, 0.4, (n, 3)))
+    scale = np.exp(rng.normal(log_scale, 0.4, (n, 3)))
     q = rng.standard_normal((n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
     q[q[:, 0] < 0] *= -1

@@ -508,3 +508,70 @@ def test_large_splats_and_32bit_tile_ids(torch):
          % (n_big, st["n_keys"], err))
     assert err <= MAX_ABS and psnr(got[None], ref[None]) >= MIN_PSNR
     sc.close()
+
+
+def test_blend_pair_counts_against_the_oracle(c1, torch):
+    """The blend kernels' own pair counts on a frame without long tile lists
+    (no later chunk is walked speculatively): the pairs they find contributing
+    (alpha >= 1/255 while the pixel still composites, the one that ends it
+    included) equal the oracle's contributing pairs up to near-threshold
+    decisions, and the pairs they evaluate (the unit of the blend roofline)
+    are at least those."""
+    a, sc = c1
+    cam = sg.single_camera_c1()
+    T = sg.identity_instances(1)
+    sel = sc.select(cam, 1.0)
+    sc.render(cam, sel)
+    sc.collect_profile()
+    sc.render(cam, sel)
+    assert sc.collect_profile()["pairs_taken"] == 0  # counted only when asked for
+    sc.set_profiling(False, audit_pairs=True)
+    sc.render(cam, sel)
+    P = sc.collect_profile()
+    sc.set_profiling(False)
+    keys, _ = sc.sorted_keys()
+    longest = int(np.bincount((keys >> np.uint64(32)).astype(np.int64)).max())
+    _, amb, st = oracle.render(a, T, cam, sel.ids())
+    _say("pairs: evaluated %d, contributing %d; oracle contributing %d (bucket walk %d); ambiguous pixels %d; "
+         "longest tile list %d" % (P["pairs"], P["pairs_taken"], st["n_hits"], st["n_pairs"], int(amb.sum()), longest))
+    assert longest <= 4096
+    assert P["pairs"] >= P["pairs_taken"] > 0
+    assert abs(P["pairs_taken"] - st["n_hits"]) <= 1e-4 * st["n_hits"] + 20 * int(amb.sum())
+
+
+def test_render_capacity_overflow_is_still_exact(torch):
+    """v3dg_render sizes the first frame of an image size exactly (one host
+    wait); later frames run on a key capacity (at least 2^20 keys, 16 keys per
+    pixel and twice the most keys seen) without host waits.  A later frame
+    that needs more keys than that is blended from all visible splats in depth
+    order: its image still matches the oracle, its sorted keys are
+    unavailable, and the next frame runs on a grown capacity with its keys
+    sorted."""
+    a = H.stacked_splats(16000, 5, (0.05, 0.5), log_scale=-1.0)
+    T = sg.identity_instances(1)
+    sc = v.Scene(a, T)
+    far = H.identity_camera(160, 120, 4.0, bg=(0.1, 0.2, 0.3))    # the stack covers a few pixels
+    near = H.identity_camera(160, 120, 600.0, bg=(0.1, 0.2, 0.3))  # every splat covers every tile
+    s_far = sc.select(far, 0.0)
+    sc.render(far, s_far)
+    k_far = sc.frame_stats()["n_keys"]
+    cap = max(2 * k_far, 16 * 160 * 120, 1 << 20)
+    s_near = sc.select(near, 0.0)
+    img = sc.render(near, s_near).clone()
+    st = sc.frame_stats()
+    _say("capacity after a %d-key frame: %d; the next frame needs %d keys" % (k_far, cap, st["n_keys"]))
+    assert st["n_keys"] > cap  # this frame overflowed the capacity
+    with pytest.raises(v.V3DGError) as ei:
+        sc.sorted_keys()
+    assert ei.value.code == v.V3DG_ERR_CAPACITY
+    ref, amb, _ = oracle.render(a, T, near, s_near.ids())
+    check_image(img.cpu().numpy(), ref, amb, "over capacity (all-splat walk)")
+    img2 = sc.render(near, s_near).clone()  # capacity grown: sorted and chunked as usual
+    keys, _ = sc.sorted_keys()
+    assert keys.size == sc.frame_stats()["n_keys"] == st["n_keys"]
+    check_image(img2.cpu().numpy(), ref, amb, "after growth")
+    # many frames in flight without host waits, then read back in order
+    outs = [sc.render(cam, sel) for cam, sel in [(far, s_far), (near, s_near)] * 12]
+    torch.cuda.synchronize()
+    assert torch.equal(outs[-1], img2) and torch.equal(outs[1], img2)
+    sc.close()

@@ -44,13 +44,19 @@ def _frames(n, seed):
 
 # cuts of these 20 frames need 1 .. 335 of the asset's 341 clusters, their
 # union all of them: pools below 341 evict, pools below 335 refuse some cuts
-@pytest.mark.parametrize("pool_frac,culling,precision", [(1.0, False, "fp32"), (0.8, False, "fp32"),
-                                                         (0.8, True, "fp32"), (0.99, False, "fp16")])
-def test_streamed_equals_resident(torch, world, pool_frac, culling, precision):
+@pytest.mark.parametrize("pool_frac,culling,precision,disk", [(1.0, False, "fp32", None), (0.8, False, "fp32", None),
+                                                              (0.8, True, "fp32", None), (0.99, False, "fp16", None),
+                                                              (0.8, False, "fp32", "buffered"),
+                                                              (0.8, True, "fp16_bf16sh", "direct")])
+def test_streamed_equals_resident(torch, world, tmp_path, pool_frac, culling, precision, disk):
     a, T = world
     res = v.Scene(a, T, precision=precision)
     pool = max(1, int(pool_frac * a.n_clusters))
-    st = v.Scene(a, T, precision=precision, pool_clusters=pool)
+    page_file = str(tmp_path / "pages.bin") if disk else None
+    ff = v.V3DG_PAGE_FILE_DIRECT if disk == "direct" else 0
+    st = v.Scene(a, T, precision=precision, pool_clusters=pool, page_file=page_file, file_flags=ff)
+    if disk:
+        assert st.stream_stats()["tier"] in ((1, 2) if disk == "direct" else (1,))
     res.set_culling(culling)
     st.set_culling(culling)
     n_checked = 0
@@ -77,8 +83,11 @@ def test_streamed_equals_resident(torch, world, pool_frac, culling, precision):
         s0.free()
         s1.free()
     stats = st.stream_stats()
-    _say("pool %d of %d clusters, culling %s, %s: %d frames equal, %d pages in, %d evictions"
-         % (pool, a.n_clusters, culling, precision, n_checked, stats["pages_in"], stats["evictions"]))
+    _say("pool %d of %d clusters, culling %s, %s, pages on %s (tier %d, %d reads): %d frames equal, %d pages in, "
+         "%d evictions" % (pool, a.n_clusters, culling, precision, disk or "host memory", stats["tier"],
+                           stats["file_reads"], n_checked, stats["pages_in"], stats["evictions"]))
+    if disk:
+        assert 0 < stats["file_reads"] <= stats["pages_in"]
     assert n_checked >= 8
     assert stats["pool_clusters"] == pool and stats["resident"] <= pool
     if pool_frac < 1.0 and not culling:
@@ -152,15 +161,21 @@ def test_a_paged_out_selection_is_refused(torch, world):
     res.close()
 
 
-def test_streamed_walk_full_size(torch):
+@pytest.mark.parametrize("disk", [False, True])
+def test_streamed_walk_full_size(torch, tmp_path, disk):
     """The benchmark asset (1M leaves, SH3) on 12 frames of the close walk at
     1920x1080, culling on, streamed through a pool of 7,430 clusters (1.25
-    times the walk's largest cut): every image equals the resident scene's bit
-    for bit, with pages evicted on the way."""
+    times the walk's largest cut), the page images in host memory or in a file
+    read directly: every image equals the resident scene's bit for bit, with
+    pages evicted on the way, and the last one matches the oracle."""
     a = sg.cached_asset(1 << 20, 3, 2)
     cams = sg.tangent_path_cameras(100)[::8]
     res = v.Scene(a)
-    st = v.Scene(a, pool_clusters=7430)
+    if disk:
+        st = v.Scene(a, pool_clusters=7430, page_file=str(tmp_path / "pages.bin"),
+                     file_flags=v.V3DG_PAGE_FILE_DIRECT)
+    else:
+        st = v.Scene(a, pool_clusters=7430)
     res.set_culling(True)
     st.set_culling(True)
     s0 = s1 = None
@@ -173,8 +188,9 @@ def test_streamed_walk_full_size(torch):
         torch.cuda.synchronize()
         assert torch.equal(img0, img1), (i, float((img0 - img1).abs().max()))
     stats = st.stream_stats()
-    _say("1M walk streamed: %d frames equal, %d pages in, %d evictions" % (len(cams), stats["pages_in"],
-                                                                         stats["evictions"]))
+    _say("1M walk streamed (pages in %s, tier %d, %d reads): %d frames equal, %d pages in, %d evictions"
+         % ("a file" if disk else "host memory", stats["tier"], stats["file_reads"], len(cams), stats["pages_in"],
+            stats["evictions"]))
     assert stats["evictions"] > 0
     # the last streamed frame (after evictions) against the oracle, sampled
     cam = cams[-1]

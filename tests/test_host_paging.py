@@ -152,3 +152,57 @@ def test_random_cuts_match_the_model(harness, seed):
             r.cmd("release %d" % k)
             ref.release(k)
     r.close()
+
+
+# --------------------------------------------------------------------------
+# page images of a streamed scene: host memory or a file on disk
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def store_harness(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("store") / "page_store_harness")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", CSRC, os.path.join(HERE, "page_store_harness.cpp"),
+                    "-o", exe], check=True)
+    return exe
+
+
+def _store(exe, path, n, page_bytes, direct):
+    p = subprocess.Popen([exe, path, str(n), str(page_bytes), str(int(direct))], stdin=subprocess.PIPE,
+                         stdout=subprocess.PIPE, text=True)
+    head = p.stdout.readline().split()
+    assert head[0] == "ready", head
+    return p, int(head[1]), int(head[2])
+
+
+def _get(p, ks):
+    p.stdin.write("get " + " ".join(map(str, ks)) + "\n")
+    p.stdin.flush()
+    head, same, pad = p.stdout.readline().split("|")
+    ok, tier, reads = map(int, head.split())
+    return ok, tier, reads, [int(x) for x in same.split()], int(pad)
+
+
+@pytest.mark.parametrize("where,direct", [("memory", False), ("file", False), ("file", True)])
+def test_page_store_round_trip(store_harness, tmp_path, where, direct):
+    """Every image comes back exactly, in the order asked, at the store's
+    stride (4 KiB-aligned slots for a file), with one read per run of
+    consecutive clusters from a file; nothing past the batch is written."""
+    path = "-" if where == "memory" else str(tmp_path / "pages.bin")
+    page_bytes = 15104  # a 64-row SH3 FP32 page image
+    p, tier, stride = _store(store_harness, path, 40, page_bytes, direct)
+    if where == "memory":
+        assert tier == 0 and stride == page_bytes
+    else:
+        assert tier in ((2, 1) if direct else (1,)) and stride == 16384
+        assert os.path.getsize(path) == 40 * 16384
+    ok, _, r0, same, pad = _get(p, [0, 1, 2, 7, 8, 20, 39])
+    assert ok and same == [1] * 7 and pad == 1
+    if where == "file":
+        assert r0 == 4  # runs 0-2, 7-8, 20, 39
+    ok, _, r1, same, pad = _get(p, list(range(10, 30)))
+    assert ok and same == [1] * 20 and pad == 1
+    if where == "file":
+        assert r1 - r0 == 1
+    p.stdin.close()
+    p.wait()
+    if where == "file":
+        assert not os.path.exists(path)  # removed with the store
