@@ -166,6 +166,7 @@ def measured_blend_traffic(args):
 def run_frames(torch, scene, frames, img, full: bool, prof: bool):
     sel = None
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in frames]
+    scene.collect_profile()  # counts and stage times of these frames only
     scene.set_profiling(prof)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
