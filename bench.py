@@ -121,17 +121,19 @@ def stage_bytes(P: dict, b_row: int) -> dict:
       sort_hist  kb B per key (the 64-bit-key mode only: the depth-first
                  binning takes its histograms from emission)
       sort_pass  2 (kb + 4) B per key and pass (key and value, read and
-                 written); kb = 2 for tile ids of up to 65,536 tiles, 4 above,
+                 written); kb = 2 for bin ids of up to 65,536 bins, 4 above,
                  8 in the 64-bit-key mode
-      ranges     per tile two binary searches, 2 ceil(log2 K) key reads, and
-                 16 B written (range 8, blend order 4, chunk base 4)
-      blend      52 B per key (slot value 4 + splat record 48) + 16 B per pixel
+      ranges     per tile two binary searches (its bin's bounds), 2 ceil(log2 K)
+                 key reads, and 16 B written (range 8, blend order 4, chunk
+                 base 4)
+      blend      52 B per key and tile of its bin (each of the bin's 4 tiles
+                 stages the slot value 4 + splat record 48) + 16 B per pixel
     """
     fr = max(P["frames"], 1)
     passes = P["sort_passes"] / fr
     depth_first = P["depth_sorts"] > 0
-    tiles_per_frame = P["tiles"] / fr
-    kb = (2 if tiles_per_frame <= 65536 else 4) if depth_first else 8
+    bins_per_frame = P["tiles"] / fr / 4  # a bin is a 2 x 2 block of tiles
+    kb = (2 if bins_per_frame <= 65536 else 4) if depth_first else 8
     keys_per_frame = P["keys"] / fr
     search = 2 * math.ceil(math.log2(max(keys_per_frame, 2))) * kb
     return {
@@ -144,7 +146,7 @@ def stage_bytes(P: dict, b_row: int) -> dict:
         "sort_hist": 0 if depth_first else P["keys"] * kb,
         "sort_pass": P["keys"] * (2 * (kb + 4)) * passes,
         "ranges": P["tiles"] * (search + 16),
-        "blend": P["keys"] * 52 + P["pixels"] * 16,
+        "blend": P["keys"] * 4 * 52 + P["pixels"] * 16,
     }
 
 

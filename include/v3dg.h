@@ -9,12 +9,13 @@
  *   2. compacts the chosen clusters' Gaussians into a slot stream,
  *   3. projects each Gaussian to a 2D conic and colour (3D Gaussian splat of
  *       Sec. 2.1, no 2D dilation as in Sec. 5.1),
- *   4. bins the splats to 16x16 tiles and puts every tile's splats in depth
- *       order: a stable radix sort of the slots by FP32 depth, then tile ids
- *       emitted in that order (16-bit up to 65,536 tiles, else 32-bit) and
- *       stably radix-sorted (the same order as 64-bit (tile, depth) keys, which
+ *   4. bins the splats to 32x32-pixel bins and puts every bin's splats in
+ *       depth order: a stable radix sort of the slots by FP32 depth, then bin
+ *       ids emitted in that order (16-bit up to 65,536 bins, else 32-bit) and
+ *       stably radix-sorted (the same order as 64-bit (bin, depth) keys, which
  *       remain selectable with v3dg_set_sort_mode),
- *   5. alpha-composites every tile front to back (Sec. 2.1).
+ *   5. alpha-composites every 16x16-pixel tile front to back (Sec. 2.1) from
+ *       its bin's list, each 8x8 quarter walking the splats that reach it.
  * All device work runs as HIP kernels on the stream given at load time.
  *
  * Conventions for every entry point:
@@ -101,10 +102,10 @@ typedef struct {
     const float *sh;            /* n_rows x (sh_degree+1)^2 x 3 */
 } v3dg_hierarchy_desc;
 
-/* How each tile's splats are put in front-to-back order (same result):
- * DEPTH_FIRST sorts the slots by FP32 depth, emits tile ids in that order
- * (16-bit on grids of up to 65,536 tiles, 32-bit beyond) and stably sorts them
- * by tile; KEYS64 emits (tile << 32 | depth bits) keys in slot order and sorts
+/* How each bin's splats are put in front-to-back order (same result):
+ * DEPTH_FIRST sorts the slots by FP32 depth, emits bin ids in that order
+ * (16-bit on grids of up to 65,536 bins, 32-bit beyond) and stably sorts them
+ * by bin; KEYS64 emits (bin << 32 | depth bits) keys in slot order and sorts
  * all their significant bits. */
 #define V3DG_SORT_DEPTH_FIRST 0
 #define V3DG_SORT_KEYS64 1
@@ -112,10 +113,10 @@ typedef struct {
 /* Counters of the last frame rendered on a scene. */
 typedef struct {
     uint64_t n_slots;    /* Gaussians in the rendered selection            */
-    uint64_t n_keys;     /* (tile, splat) pairs sorted                     */
-    uint32_t n_tiles;    /* tiles in the image                             */
+    uint64_t n_keys;     /* (bin, splat) pairs sorted                      */
+    uint32_t n_tiles;    /* 16x16-pixel tiles in the image (blended)       */
     uint32_t key_bits;   /* significant bits of the (last) sort key        */
-    uint32_t sort_passes;/* radix passes of the tile / 64-bit key sort     */
+    uint32_t sort_passes;/* radix passes of the bin / 64-bit key sort      */
     uint32_t sort_mode;  /* V3DG_SORT_*                                    */
     uint32_t n_fp64_conics;    /* splats whose 2D covariance determinant fell below
                                   1e-6 px^4 and was redone in FP64               */
@@ -123,6 +124,7 @@ typedef struct {
                                   magnitude, stored as +-1e38 (thinner than
                                   ~1e-19 px across: an axis-aligned needle still
                                   covers the pixel centres it runs through)      */
+    uint32_t n_bins;     /* 32x32-pixel bins of the image (keys name bins)  */
 } v3dg_frame_stats;
 
 /* Kernel stages timed when profiling is on (v3dg_set_profiling). */
@@ -233,8 +235,8 @@ int v3dg_select(v3dg_scene *scene, const v3dg_camera *cam, float tolerance, v3dg
  * completely.  The first frame of an image size (and every frame in the
  * 64-bit-key sort mode) synchronises once mid-frame to size the key buffers
  * exactly.  Later frames of that size run without any host wait: their
- * launches are sized by a key capacity of at least 2^20 keys, 16 keys per
- * pixel and twice the most keys any frame needed, the kernels read their counts on the
+ * launches are sized by a key capacity of at least 2^20 keys, 32 keys per
+ * pixel (up to 2^26 keys) and twice the most keys any frame needed, the kernels read their counts on the
  * device, and each frame publishes its counts to pinned host memory, read
  * when a later call finds the frame finished.  A frame that needs more keys
  * than the capacity is still rendered exactly, by every tile walking all
@@ -265,7 +267,7 @@ int v3dg_get_frame_stats(v3dg_scene *scene, v3dg_frame_stats *out);
 
 /* Per-slot results of the last frame's projection (synchronises), for
  * parity checks.  Arrays of cap entries: mean2 x2, conic x3, rgb x3; depth;
- * opacity; tiles = tiles touched (0 = culled). */
+ * opacity; tiles = bins touched (0 = culled). */
 int v3dg_copy_projection(v3dg_scene *scene, float *mean2, float *conic, float *rgb, float *opacity, float *depth,
                          uint32_t *tiles, uint64_t cap, uint64_t *n_out);
 
@@ -277,7 +279,7 @@ int v3dg_copy_projection(v3dg_scene *scene, float *mean2, float *conic, float *r
 int v3dg_copy_attributes(v3dg_scene *scene, uint64_t first, uint64_t n, float *pos, float *scale, float *rot,
                          float *opacity, float *sh);
 
-/* The last frame's sorted keys as (tile << 32 | depth bits) and values
+/* The last frame's sorted keys as (bin << 32 | depth bits) and values
  * (slot), whatever the sort mode (synchronises). */
 int v3dg_copy_sorted_keys(v3dg_scene *scene, uint64_t *keys, uint32_t *vals, uint64_t cap, uint64_t *n_out);
 
@@ -288,15 +290,15 @@ typedef struct {
     uint64_t frames;                   /* renders                                     */
     uint64_t selects, tests;           /* selections, (instance, cluster) tests       */
     uint64_t sel_clusters;             /* selected clusters of the rendered selections*/
-    uint64_t slots, visible;           /* Gaussians projected / with a tile           */
+    uint64_t slots, visible;           /* Gaussians projected / with a bin            */
     uint64_t keys, tiles, pixels;      /* sorted keys, image tiles, image pixels      */
-    uint64_t sort_passes;              /* digit passes of the tile / 64-bit key sort  */
+    uint64_t sort_passes;              /* digit passes of the bin / 64-bit key sort   */
     uint64_t depth_sorts;              /* frames that sorted slots by depth first     */
     uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending: for
                                           each splat of a quarter's list, the quarter's
                                           pixels still compositing when it is reached    */
     uint64_t pairs_taken;              /* of those, pairs with alpha >= 1/255 (composited,
-                                          or ending the pixel); later chunks of long tile
+                                          or ending the pixel); later chunks of long bin
                                           lists are walked from T = 1 and count pairs a
                                           sequential walk would not reach.  Counted only
                                           with V3DG_PROFILE_PAIR_AUDIT, else 0            */
@@ -329,7 +331,7 @@ int v3dg_set_profiling(v3dg_scene *scene, int stage_mask);
 int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
 
 /* Stable LSD radix sort of n (key, value) pairs in device memory by the low
- * key_bits bits of the keys (1..64), the primitive behind tile binning.  Synchronises;
+ * key_bits bits of the keys (1..64), the primitive behind binning.  Synchronises;
  * allocates its own temporary buffers. */
 int v3dg_sort_pairs(uint64_t *keys_dev, uint32_t *vals_dev, uint64_t n, uint32_t key_bits, void *hip_stream);
 

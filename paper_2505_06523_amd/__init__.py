@@ -65,7 +65,7 @@ class v3dg_hierarchy_desc(C.Structure):
 class v3dg_frame_stats(C.Structure):
     _fields_ = [("n_slots", C.c_uint64), ("n_keys", C.c_uint64), ("n_tiles", C.c_uint32),
                 ("key_bits", C.c_uint32), ("sort_passes", C.c_uint32), ("sort_mode", C.c_uint32),
-                ("n_fp64_conics", C.c_uint32), ("n_conics_clamped", C.c_uint32)]
+                ("n_fp64_conics", C.c_uint32), ("n_conics_clamped", C.c_uint32), ("n_bins", C.c_uint32)]
 
 
 class v3dg_stream_stats(C.Structure):
@@ -261,7 +261,7 @@ def v3dg_get_frame_stats(scene) -> dict:
     _check(lib().v3dg_get_frame_stats(scene, C.byref(st)))
     return dict(n_slots=st.n_slots, n_keys=st.n_keys, n_tiles=st.n_tiles, key_bits=st.key_bits,
                 sort_passes=st.sort_passes, sort_mode=st.sort_mode, n_fp64_conics=st.n_fp64_conics,
-                n_conics_clamped=st.n_conics_clamped)
+                n_conics_clamped=st.n_conics_clamped, n_bins=st.n_bins)
 
 
 def v3dg_copy_projection(scene, n_slots: int) -> dict:

@@ -287,12 +287,12 @@ __global__ void __launch_bounds__(256) project_kernel(const FrameDev *__restrict
         const float fy0 = fmaxf(ceilf(my - hy - 0.5f), 0.0f);
         const float fy1 = fminf(floorf(my + hy - 0.5f), (float)(cam.height - 1));
         if (!(fx0 <= fx1 && fy0 <= fy1)) continue;
-        const uint32_t tx0 = (uint32_t)fx0 / kTile, tx1 = (uint32_t)fx1 / kTile;
-        const uint32_t ty0 = (uint32_t)fy0 / kTile, ty1 = (uint32_t)fy1 / kTile;
-        uint32_t ntiles = 0;
+        const uint32_t tx0 = (uint32_t)fx0 / kBin, tx1 = (uint32_t)fx1 / kBin;
+        const uint32_t ty0 = (uint32_t)fy0 / kBin, ty1 = (uint32_t)fy1 / kBin;
+        uint32_t ntiles = 0;  // bins touched
         for (uint32_t ty = ty0; ty <= ty1; ++ty) {
             uint32_t lo, hi;
-            if (tile_row_span(br, ty, tx0, tx1, &lo, &hi)) ntiles += hi - lo + 1;
+            if (bin_row_span(br, ty, tx0, tx1, &lo, &hi)) ntiles += hi - lo + 1;
         }
         if (ntiles == 0) continue;
         out.tiles[t] = ntiles;

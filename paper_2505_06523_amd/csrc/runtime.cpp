@@ -199,7 +199,7 @@ struct Ctx {
     // frames sized by capacity publish their counts into a ring of records in
     // mapped pinned memory (FrameRec); the host reads a record once the
     // frame's event has completed
-    static constexpr uint32_t kRecRing = 16;
+    static constexpr uint32_t kRecRing = 4;  // frames in flight
     FrameRec *rec_h = nullptr, *rec_d = nullptr;
     hipEvent_t rec_ev[kRecRing] = {};
     uint32_t rec_want[kRecRing] = {};  // the tag each record must carry
@@ -262,8 +262,8 @@ struct v3dg_scene : Ctx {
     hipEvent_t ev_proj = nullptr, ev_sel = nullptr;
     // v3dg_render without host waits: the first frame of an image size is
     // sized exactly (one wait after the tile scan); later frames of that size
-    // run on key buffers of at least kRenderKeysPerPixel keys per pixel and
-    // twice the most keys seen, and their counts come back through FrameRec
+    // run on key buffers sized by capacity (ensure_render_capacity), and
+    // their counts come back through FrameRec
     uint32_t rend_tiles = 0;        // tiles of the image size the capacity is set for (0: none)
     uint64_t keys_seen = 0;         // most keys of any frame seen
     uint32_t rend_err = 0;          // error flags of capacity frames read back since the last frame stats
@@ -337,6 +337,8 @@ int make_cam(const v3dg_camera *c, CamArgs *o)
     o->height = c->height;
     o->tiles_x = (c->width + kTile - 1) / kTile;
     o->tiles_y = (c->height + kTile - 1) / kTile;
+    o->bins_x = (c->width + kBin - 1) / kBin;
+    o->bins_y = (c->height + kBin - 1) / kBin;
     return V3DG_OK;
 }
 
@@ -608,9 +610,17 @@ int ensure_status(Ctx *c, uint64_t parts)
 }
 
 // chunk buffers for frames of up to K keys over n_tiles tiles
+// Chunk records a blend plan over K keys may take: every tile of a bin walks
+// the bin's list, so a list of L > kChunkFirst keys takes at most
+// kTilesPerBin (L / kChunk + 1) records.
+uint64_t chunk_bound(uint64_t K, uint32_t n_tiles)
+{
+    return kTilesPerBin * ((K + kChunk - 1) / kChunk) + n_tiles;
+}
+
 int ensure_chunks(Ctx *c, uint64_t K, uint32_t n_tiles)
 {
-    const uint64_t need = (K + kChunk - 1) / kChunk + n_tiles;
+    const uint64_t need = chunk_bound(K, n_tiles);
     if (need <= c->cap_chunks) return V3DG_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
     dev_free(c->items);
@@ -699,7 +709,8 @@ struct FramePub {
 
 template <typename KT>
 void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev, uint64_t KL, uint32_t key_bits,
-               uint32_t n_tiles, uint64_t max_chunks, int *buf, uint32_t *passes, const FramePub &pub)
+               uint32_t tiles_x, uint32_t n_tiles, uint32_t bins_x, uint64_t max_chunks, int *buf, uint32_t *passes,
+               const FramePub &pub)
 {
     KT *kb[2] = {reinterpret_cast<KT *>(c->keys[0]), reinterpret_cast<KT *>(c->keys[1])};
     const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
@@ -712,9 +723,9 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
     if (KL > 0) run_sort<KT>(c, kb, c->vals, k_dev, KL, key_bits, 4, buf, passes, true);
     {
         Stage st(c, V3DG_STAGE_RANGES);
-        launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, n_tiles, c->ranges, c->cbase,
-                               c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks, pub.sel_counters, pub.rec,
-                               pub.seq);
+        launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, tiles_x, n_tiles, bins_x,
+                               c->ranges, c->cbase, c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks,
+                               pub.sel_counters, pub.rec, pub.seq);
     }
 }
 
@@ -726,7 +737,7 @@ struct SelView {
 // What one frame's launches were sized for.
 struct FrameInfo {
     uint64_t K = 0;            // keys (host-sized frames only)
-    uint32_t n_tiles = 0, key_bits = 0, passes = 0, N = 0, n_visible = 0, n_sel_clusters = 0;
+    uint32_t n_tiles = 0, n_bins = 0, key_bits = 0, passes = 0, N = 0, n_visible = 0, n_sel_clusters = 0;
     int buf = 0;
     bool depth_first = true;
 };
@@ -746,6 +757,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     int rc;
     const uint32_t n_tiles = cam.tiles_x * cam.tiles_y;
     fi->n_tiles = n_tiles;
+    fi->n_bins = cam.bins_x * cam.bins_y;
     if (!capacity) {
         if ((rc = ensure_itab(c, sc->n_inst))) return rc;
         if ((rc = ensure_slots(c, sc->cap_slots))) return rc;
@@ -815,35 +827,40 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         KL = c->cap_keys;
     }
     const uint32_t *k_dev = capacity ? c->rcounters + kRenKeysEff : nullptr;
-    const uint64_t max_chunks = capacity ? c->cap_chunks : KL / kChunk + n_tiles;  // chunk records the plan may use
-    const uint32_t tile_bits = std::max<uint32_t>(bits_for(n_tiles), 1);
+    // chunk records the plan may use (each tile of a bin walks the bin's list)
+    const uint64_t max_chunks = capacity ? c->cap_chunks : chunk_bound(KL, n_tiles);
+    const uint32_t n_bins = cam.bins_x * cam.bins_y;
+    const uint32_t bin_bits = std::max<uint32_t>(bits_for(n_bins), 1);
     int buf = 0;
     uint32_t passes = 0;
     uint32_t key_bits;
     if (depth_first) {
-        key_bits = tile_bits;
-        if (n_tiles <= kTileKey16Max)
-            tile_keys<uint16_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes, pub);
+        key_bits = bin_bits;
+        if (n_bins <= kBinKey16Max)
+            tile_keys<uint16_t>(c, n_dev, S, k_dev, KL, key_bits, cam.tiles_x, n_tiles, cam.bins_x, max_chunks, &buf,
+                                &passes, pub);
         else
-            tile_keys<uint32_t>(c, n_dev, S, k_dev, KL, key_bits, n_tiles, max_chunks, &buf, &passes, pub);
+            tile_keys<uint32_t>(c, n_dev, S, k_dev, KL, key_bits, cam.tiles_x, n_tiles, cam.bins_x, max_chunks, &buf,
+                                &passes, pub);
     } else {
         {
             Stage st(c, V3DG_STAGE_EMIT);
             launch_emit64(c->stream, n_dev, S, c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys, c->keys[0],
                           c->vals[0], c->rcounters + kRenErr);
         }
-        key_bits = 32 + tile_bits;
+        key_bits = 32 + bin_bits;
         if (KL > 0) run_sort<uint64_t>(c, c->keys, c->vals, k_dev, KL, key_bits, 0, &buf, &passes, false);
         {
             Stage st(c, V3DG_STAGE_RANGES);
-            launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, n_tiles, c->ranges,
-                                         c->cbase, c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
+            launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, cam.tiles_x,
+                                         n_tiles, cam.bins_x, c->ranges, c->cbase, c->items, c->cbase + c->tiles_cap,
+                                         c->rcounters, max_chunks);
         }
     }
     {
         Stage st(c, V3DG_STAGE_BLEND);
         launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase,
-                     c->items, c->cbase + c->tiles_cap, c->rcounters, KL / kChunk, max_chunks, c->scratch, c->pend,
+                     c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks, max_chunks, c->scratch, c->pend,
                      c->need, c->rewalk, c->pairs_dev, c->audit_pairs);
         // a frame whose keys did not fit is blended from its depth-sorted slots
         if (pub.fallback && depth_first)
@@ -871,6 +888,7 @@ void record_frame(Ctx *c, const FrameInfo &fi, uint64_t pixels)
     c->last.n_slots = fi.N;
     c->last.n_keys = fi.K;
     c->last.n_tiles = fi.n_tiles;
+    c->last.n_bins = fi.n_bins;
     c->last.key_bits = fi.key_bits;
     c->last.sort_mode = fi.depth_first ? V3DG_SORT_DEPTH_FIRST : V3DG_SORT_KEYS64;
     c->last.sort_passes = fi.passes;
@@ -910,12 +928,15 @@ int drain_records(v3dg_scene *s, bool block)
 }
 
 // Key buffers (and chunk records) for frames of n_tiles tiles sized by
-// capacity: at least kRenderKeysPerPixel keys per pixel and twice the most
-// keys seen.  Grows only (a growth waits for the frames in flight).
-constexpr uint64_t kRenderKeysPerPixel = 16;
+// capacity: twice the most keys seen, and at least kRenderKeysPerPixel keys
+// per pixel up to kRenderKeysFloorMax keys.  Grows only (a growth waits for
+// the frames in flight).
+constexpr uint64_t kRenderKeysPerPixel = 32;
+constexpr uint64_t kRenderKeysFloorMax = 1ull << 26;
 int ensure_render_capacity(v3dg_scene *s, uint32_t n_tiles, uint64_t pixels)
 {
-    const uint64_t want = std::min<uint64_t>(std::max(2 * s->keys_seen, kRenderKeysPerPixel * pixels), 0xfffff000ull);
+    const uint64_t floor = std::min(kRenderKeysPerPixel * pixels, kRenderKeysFloorMax);
+    const uint64_t want = std::min<uint64_t>(std::max(2 * s->keys_seen, floor), 0xfffff000ull);
     int rc;
     if (want > s->cap_keys && (rc = ensure_keys(s, want, true))) return rc;
     return ensure_chunks(s, s->cap_keys, n_tiles);
@@ -978,6 +999,7 @@ int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, 
     s->acc.sort_passes += fi.passes;
     s->acc.depth_sorts += 1;
     s->last.n_tiles = fi.n_tiles;
+    s->last.n_bins = fi.n_bins;
     s->last.key_bits = fi.key_bits;
     s->last.sort_mode = V3DG_SORT_DEPTH_FIRST;
     s->last.sort_passes = fi.passes;
@@ -1862,9 +1884,9 @@ int v3dg_copy_sorted_keys(v3dg_scene *s, uint64_t *keys, uint32_t *vals, uint64_
     if (keys) {
         if (s->last.sort_mode == V3DG_SORT_KEYS64) {
             HIP_TRY(hipMemcpy(keys, s->keys[s->last_buf], n * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        } else {  // tile ids (16 bits on grids of at most kTileKey16Max tiles); the depth bits come from the slot
+        } else {  // bin ids (16 bits on grids of at most kBinKey16Max bins); the depth bits come from the slot
             std::vector<uint32_t> tk(n), dp(s->last.n_slots);
-            if (s->last.n_tiles <= kTileKey16Max) {
+            if (s->last.n_bins <= kBinKey16Max) {
                 std::vector<uint16_t> t16(n);
                 HIP_TRY(hipMemcpy(t16.data(), s->keys[s->last_buf], n * sizeof(uint16_t), hipMemcpyDeviceToHost));
                 for (uint64_t i = 0; i < n; ++i) tk[i] = t16[i];
@@ -2076,7 +2098,7 @@ uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
     g += (K2 - keys) * 24 + ((K2 - keys + kSortPart - 1) / kSortPart) * 3 / 2 * kRadix * 8;
     const uint64_t T2 = std::max<uint64_t>(std::max<uint64_t>(n_tiles, 8160), tiles);
     g += (T2 - tiles) * 16;
-    const uint64_t ch = (K2 + kChunk - 1) / kChunk + T2;
+    const uint64_t ch = chunk_bound(K2, (uint32_t)T2);
     if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 8);
     return g;
 }

@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ 
                                                    uint32_t *err)
 {
     const uint32_t n = min(*n_dev, max_n);
-    const uint32_t tiles_x = fd->cam.tiles_x;
+    const uint32_t tiles_x = fd->cam.bins_x;  // keys name bins
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         const uint32_t t = DEPTH_FIRST ? order[j] : j;
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ 
         const uint64_t dbits = __float_as_uint(b.depth);
         for (uint32_t ty = ty0; ty <= ty1; ++ty) {
             uint32_t lo, hi;
-            if (!tile_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
+            if (!bin_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
             for (uint32_t tx = lo; tx <= hi && off < end; ++tx) {
                 const uint32_t tile = ty * tiles_x + tx;
                 if (DEPTH_FIRST)
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     __shared__ EmitShared sh;
     const uint32_t n = min(*n_dev, max_n);
     if (blockIdx.x * kEmitThreads >= n) return;  // whole workgroup past the end
-    const uint32_t tiles_x = fd->cam.tiles_x;
+    const uint32_t tiles_x = fd->cam.bins_x;  // keys name bins
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     for (int i = tid; i < 257; i += kEmitThreads) sh.d0[i] = 0u;
     for (int i = tid; i < 2 * 256; i += kEmitThreads) sh.h[i] = 0u;
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
         uint64_t o = off;
         for (uint32_t ty = ty0; ty <= ty1 && left != 0u; ++ty) {
             uint32_t lo, hi;
-            if (!tile_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
+            if (!bin_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
             const uint32_t row = ty * tiles_x;
             count_span(row + lo, row + hi, passes, sh.d0, sh.h, &sh.all);
             const uint32_t m = min(hi - lo + 1u, left);
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
             uint32_t lo = 0, len = 0;
             if (ty <= by1) {
                 uint32_t hi;
-                if (tile_row_span(bb, ty, bx0, bx1, &lo, &hi)) {
+                if (bin_row_span(bb, ty, bx0, bx1, &lo, &hi)) {
                     len = hi - lo + 1;
                     count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, sh.d0, sh.h, &sh.all);
                 }
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
     for (int i = tid; i < 2 * 256; i += kEmitThreads) s_h[i] = 0u;
     if (tid == 0) s_all = 0u;
     __syncthreads();
-    const uint32_t tiles_x = fd->cam.tiles_x;
+    const uint32_t tiles_x = fd->cam.bins_x;  // keys name bins
     for (uint32_t e = blockIdx.x; e < nb; e += gridDim.x) {
         const uint32_t j = big[e], t = order[j], nt = tiles[t];
         const uint64_t off = offsets[j];
@@ -525,7 +525,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
             uint32_t lo = 0, len = 0;
             if (ty <= ty1) {
                 uint32_t hi;
-                if (tile_row_span(b, ty, tx0, tx1, &lo, &hi)) {
+                if (bin_row_span(b, ty, tx0, tx1, &lo, &hi)) {
                     len = hi - lo + 1;
                     count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
                 }
@@ -864,7 +864,8 @@ __device__ __forceinline__ uint32_t lower_bound_tile(const K *__restrict__ keys,
 
 template <typename K>
 __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
-                                                          int shift, uint32_t n_tiles, uint2 *__restrict__ ranges,
+                                                          int shift, uint32_t tiles_x, uint32_t n_tiles, uint32_t bins_x,
+                                                          uint2 *__restrict__ ranges,
                                                           uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
                                                           uint32_t *__restrict__ order, uint32_t *counters,
                                                           uint32_t max_chunks, const uint32_t *__restrict__ sel_counters,
@@ -885,9 +886,10 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
     const uint64_t lt = (1ull << lane) - 1ull;
     const bool in = t < n_tiles;
     uint32_t L = 0;
-    if (in) {
+    if (in) {  // the keys of the tile's bin
         const uint32_t n = *n_dev;
-        const uint2 r = make_uint2(lower_bound_tile(keys, n, shift, t), lower_bound_tile(keys, n, shift, t + 1));
+        const uint32_t bin = (t / tiles_x) / 2u * bins_x + (t % tiles_x) / 2u;
+        const uint2 r = make_uint2(lower_bound_tile(keys, n, shift, bin), lower_bound_tile(keys, n, shift, bin + 1));
         ranges[t] = r;
         L = r.y - r.x;
     }
@@ -920,12 +922,13 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
 }
 
 template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
-                        uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *order, uint32_t *counters,
-                        uint64_t max_chunks, const uint32_t *sel_counters, FrameRec *rec, uint32_t seq)
+void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t tiles_x,
+                        uint32_t n_tiles, uint32_t bins_x, uint2 *ranges, uint32_t *cbase, uint2 *items,
+                        uint32_t *order, uint32_t *counters, uint64_t max_chunks, const uint32_t *sel_counters,
+                        FrameRec *rec, uint32_t seq)
 {
     hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, n_dev, shift,
-                       n_tiles, ranges, cbase, items, order, counters,
+                       tiles_x, n_tiles, bins_x, ranges, cbase, items, order, counters,
                        (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull), sel_counters, rec, seq);
 }
 
@@ -947,14 +950,14 @@ template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const ui
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
-template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint2 *,
-                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t, const uint32_t *,
-                                          FrameRec *, uint32_t);
-template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint2 *,
-                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t, const uint32_t *,
-                                          FrameRec *, uint32_t);
-template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint2 *,
-                                          uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t, const uint32_t *,
-                                          FrameRec *, uint32_t);
+template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint32_t,
+                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
+                                          const uint32_t *, FrameRec *, uint32_t);
+template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint32_t,
+                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
+                                          const uint32_t *, FrameRec *, uint32_t);
+template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint32_t,
+                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
+                                          const uint32_t *, FrameRec *, uint32_t);
 
 }  // namespace v3dg

@@ -5,7 +5,10 @@
 
 namespace v3dg {
 
-constexpr int kTile = 16;               // tile edge in pixels
+constexpr int kTile = 16;               // edge in pixels of a tile (blended by one workgroup)
+constexpr int kBin = 32;                // edge in pixels of a bin (a 2 x 2 block of tiles); keys name bins
+constexpr uint32_t kTilesPerBin = (kBin / kTile) * (kBin / kTile);
+static_assert(kBin == 2 * kTile, "a bin is a 2 x 2 block of tiles");
 constexpr int kWave = 64;               // CDNA wavefront width
 
 // Gaussian attributes are structure-of-arrays planes with a common stride
@@ -40,7 +43,7 @@ struct CamArgs {
     float near_plane, far_plane;
     float limx, limy;        // guard band of the EWA Jacobian: 1.3 * tan(half fov)
     float bg[3];
-    uint32_t width, height, tiles_x, tiles_y;
+    uint32_t width, height, tiles_x, tiles_y, bins_x, bins_y;
 };
 
 // Per-frame state of a render context in device memory.  The first kernel of
@@ -120,11 +123,16 @@ struct BinRec {            // per visible slot, 32 B
     float sc, det, Qm, depth;
 };
 
-__device__ __forceinline__ bool tile_row_span(const BinRec &b, uint32_t ty, uint32_t tx_min, uint32_t tx_max,
-                                              uint32_t *tx_lo, uint32_t *tx_hi)
+// Bins of bin row by (pixel centres kBin by + 0.5 .. + kBin - 0.5) that the
+// enlarged support (binning record b) reaches, clipped to [bx_min, bx_max]:
+// the x-extent of the ellipse over the row's pixel-centre band (plus one
+// pixel each way) is exact, so no bin is listed that the support misses.
+__device__ __forceinline__ bool bin_row_span(const BinRec &b, uint32_t by, uint32_t bx_min, uint32_t bx_max,
+                                             uint32_t *bx_lo, uint32_t *bx_hi)
 {
 #pragma clang fp contract(off)
-    const float ya = (float)(ty * 16u) + 0.5f, yb = ya + 15.0f;
+    constexpr float kEdge = (float)kBin, kInv = 1.0f / (float)kBin;  // exact: a power of two
+    const float ya = (float)(by * (uint32_t)kBin) + 0.5f, yb = ya + (kEdge - 1.0f);
     const float ymax = sqrtf(b.Qm * b.sc);
     const float lo = fmaxf(ya - 1.0f - b.my, -ymax);
     const float hi = fminf(yb + 1.0f - b.my, ymax);
@@ -138,12 +146,12 @@ __device__ __forceinline__ bool tile_row_span(const BinRec &b, uint32_t ty, uint
     const float wl = sqrtf(fmaxf(0.0f, (b.Qm - dl * dl / b.sc) * s2));
     const float xr = b.mx + k * dr + wr + 1.0f;
     const float xl = b.mx + k * dl - wl - 1.0f;
-    // tile tx holds pixel centres 16 tx + 0.5 .. 16 tx + 15.5
-    const float flo = ceilf((xl - 15.5f) * 0.0625f), fhi = floorf((xr - 0.5f) * 0.0625f);
-    const float clo = fmaxf(flo, (float)tx_min), chi = fminf(fhi, (float)tx_max);
+    // bin bx holds pixel centres kBin bx + 0.5 .. kBin bx + kBin - 0.5
+    const float flo = ceilf((xl - (kEdge - 0.5f)) * kInv), fhi = floorf((xr - 0.5f) * kInv);
+    const float clo = fmaxf(flo, (float)bx_min), chi = fminf(fhi, (float)bx_max);
     if (!(clo <= chi)) return false;
-    *tx_lo = (uint32_t)clo;
-    *tx_hi = (uint32_t)chi;
+    *bx_lo = (uint32_t)clo;
+    *bx_hi = (uint32_t)chi;
     return true;
 }
 
@@ -241,14 +249,14 @@ constexpr int kScanPart = kScanThreads * kScanItems;
 // have no keys to work on)
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
                        uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap);
-// 64-bit keys (tile << 32 | depth bits), slot order
+// 64-bit keys (bin << 32 | depth bits), slot order
 void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
                    const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
                    uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err);
-// Tile-id keys in depth order (order[j] = slot of depth rank j), with the
-// digit histograms of the tile sort (passes <= 3) accumulated into hist.
-// KT = uint16_t for grids of at most kTileKey16Max tiles, else uint32_t.
-constexpr uint32_t kTileKey16Max = 1u << 16;
+// Bin-id keys in depth order (order[j] = slot of depth rank j), with the
+// digit histograms of the bin sort (passes <= 3) accumulated into hist.
+// KT = uint16_t for grids of at most kBinKey16Max bins, else uint32_t.
+constexpr uint32_t kBinKey16Max = 1u << 16;
 // (splats of more than 2048 keys are listed in big[] (n_big: a cleared
 // counter; big: max_n entries) and emitted by one workgroup each)
 template <typename KT>
@@ -278,8 +286,8 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide);
 // Chunks of long tile lists (blending): a list of L > kChunkFirst keys is
 // cut into a first chunk of kChunkFirst keys and further chunks of kChunk.
-constexpr int kChunk = 1024;            // keys per chunk of a long tile list after the first
-constexpr int kChunkFirst = 4096;       // keys of the first chunk (walked by pass 1)
+constexpr int kChunk = 2048;            // keys per chunk of a long bin list after the first
+constexpr int kChunkFirst = 6144;       // keys of the first chunk (walked by pass 1)
 constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whole
 __device__ __forceinline__ uint32_t n_chunks(uint32_t L)
 {
@@ -290,21 +298,22 @@ __device__ __forceinline__ uint32_t chunk_end(uint32_t c, uint32_t L)
 {
     return min((uint32_t)kChunkFirst + c * (uint32_t)kChunk, L);
 }
-// Per tile t < n_tiles: ranges[t] = [first, end) of its keys in the sorted
-// keys, and the blend plan.  A tile of L > kChunkFirst keys gets n_chunks(L)
-// consecutive chunk records from cbase[t] (kNoChunk for other tiles, and for
-// long ones beyond max_chunks records, which are then blended whole) and one
-// work item (t, c) per chunk c >= 1 (items: counters[kRenItems]).  order is
-// a permutation of the tiles with the lists of at least kChunkFirst keys
-// first, so that the longest walks start first.
+// Per tile t < n_tiles (tiles_x per row): ranges[t] = [first, end) of the
+// keys of its bin (bins_x per row) in the sorted keys, and the blend plan.  A
+// tile whose bin holds L > kChunkFirst keys gets n_chunks(L) consecutive
+// chunk records from cbase[t] (kNoChunk for other tiles, and for long ones
+// beyond max_chunks records, which are then blended whole) and one work item
+// (t, c) per chunk c >= 1 (items: counters[kRenItems]).  order is a
+// permutation of the tiles with the lists of at least kChunkFirst keys first,
+// so that the longest walks start first.
 // With rec (a record in mapped pinned host memory), the kernel also publishes
 // the frame's counts there, tagged seq: keys, visible slots and error flags
 // from counters, slots and clusters from the selection's sel_counters.
 template <typename K>
-void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t n_tiles,
-                        uint2 *ranges, uint32_t *cbase, uint2 *items, uint32_t *order, uint32_t *counters,
-                        uint64_t max_chunks, const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr,
-                        uint32_t seq = 0);
+void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t tiles_x,
+                        uint32_t n_tiles, uint32_t bins_x, uint2 *ranges, uint32_t *cbase, uint2 *items,
+                        uint32_t *order, uint32_t *counters, uint64_t max_chunks,
+                        const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr, uint32_t seq = 0);
 // blend.hip
 // max_items / max_chunks bound the work items and chunks of the plan (grid
 // sizes).  pairs[0] counts the pairs walked; with audit, pairs[1] also counts

@@ -213,14 +213,15 @@ def test_sort_modes_identical(c1, torch):
 
 
 def test_tile_coverage_is_conservative(c1, torch):
-    """Every pixel where a kept splat reaches alpha >= 1/255 lies in a tile it was binned to."""
+    """Every pixel where a kept splat reaches alpha >= 1/255 lies in a 32x32
+    bin it was binned to."""
     a, sc = c1
     cam = sg.look_at((0.9, -0.7, 0.6), (0, 0, 0), 320, 200, 1.1)
     sel = sc.select(cam, 1.0)
     sc.render(cam, sel)
     keys, vals = sc.sorted_keys()
     pr = sc.projection()
-    tiles_x = (cam.width + 15) // 16
+    bins_x = (cam.width + 31) // 32
     binned = {}
     for k, t in zip((keys >> np.uint64(32)).astype(np.int64), vals.astype(np.int64)):
         binned.setdefault(t, set()).add(int(k))
@@ -236,7 +237,7 @@ def test_tile_coverage_is_conservative(c1, torch):
         power = np.minimum(0.0, -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy)
         alpha = np.minimum(0.99, o * np.exp(power))
         hit = alpha >= (1.0 / 255.0) * (1 - 1e-4)
-        need = set(((ys[hit] // 16) * tiles_x + xs[hit] // 16).tolist())
+        need = set(((ys[hit] // 32) * bins_x + xs[hit] // 32).tolist())
         assert need <= binned.get(int(t), set()), int(t)
         assert len(binned[int(t)]) == int(pr["tiles"][t])
 
@@ -283,7 +284,7 @@ def test_long_tile_lists_chunked_blending(torch, opacity, seed):
     keys, _ = sc.sorted_keys()
     per_tile = np.bincount((keys >> np.uint64(32)).astype(np.int64))
     _say("long lists: keys %d, longest tile list %d" % (st["n_keys"], per_tile.max()))
-    assert per_tile.max() > 10 * 1024  # a first chunk of 4096 keys and at least six more of 1024
+    assert per_tile.max() > 6144 + 4 * 2048  # a first chunk of 6144 keys and at least five more of 2048
     ref, amb, _ = oracle.render(a, T, cam, sel.ids())
     check_image(img, ref, amb, "stacked o=%s" % (opacity,))
     sc.set_sort_mode(v.V3DG_SORT_KEYS64)
@@ -471,15 +472,15 @@ def test_c3_image_sampled_parity(c3, torch, frame, cull):
 
 
 def test_large_splats_and_32bit_tile_ids(torch):
-    """A 4160 x 4160 image (67,600 tiles: 32-bit tile ids) of the c1-sized
-    asset seen from close by, so that near splats cover thousands of tiles and
-    go through the large-splat emission: the image and the sorted keys equal
-    the 64-bit-key mode (whose emission has no large-splat path) bit for bit,
-    and sampled pixels match the oracle."""
+    """An 8224 x 8224 image (66,049 bins of 32 x 32 pixels: 32-bit bin ids) of
+    the c1-sized asset seen from close by, so that near splats cover thousands
+    of bins and go through the large-splat emission: the image and the sorted
+    keys equal the 64-bit-key mode (whose emission has no large-splat path) bit
+    for bit, and sampled pixels match the oracle."""
     a = sg.make_asset(16384, 3, 41)
     T = sg.identity_instances(1)
     sc = v.Scene(a, T)
-    cam = sg.look_at((0.35, -0.3, 0.25), (0, 0, 0), 4160, 4160, 1.4)
+    cam = sg.look_at((0.35, -0.3, 0.25), (0, 0, 0), 8224, 8224, 1.4)
     sel = sc.select(cam, 1.0)
     sc.set_sort_mode(v.V3DG_SORT_KEYS64)
     i64 = sc.render(cam, sel).clone()
@@ -489,8 +490,8 @@ def test_large_splats_and_32bit_tile_ids(torch):
     kdf, vdf = sc.sorted_keys()
     st = sc.frame_stats()
     torch.cuda.synchronize()
-    assert st["n_tiles"] == 260 * 260 and st["key_bits"] > 16
-    # splats with more than 2048 tiles exist in this frame
+    assert st["n_bins"] == 257 * 257 and st["n_tiles"] == 514 * 514 and st["key_bits"] > 16
+    # splats with more than 2048 bins exist in this frame
     proj = sc.projection()
     tiles = np.asarray(proj["tiles"])
     n_big = int((tiles > 2048).sum())
@@ -504,7 +505,7 @@ def test_large_splats_and_32bit_tile_ids(torch):
     got = img[pix[:, 1], pix[:, 0]]
     ok = amb == 0
     err = np.abs(got - ref)[ok].max()
-    _say("4160x4160 close view: %d splats over 2048 tiles, %d keys, sampled max_abs %.3g"
+    _say("8224x8224 close view: %d splats over 2048 bins, %d keys, sampled max_abs %.3g"
          % (n_big, st["n_keys"], err))
     assert err <= MAX_ABS and psnr(got[None], ref[None]) >= MIN_PSNR
     sc.close()
@@ -520,8 +521,13 @@ def test_blend_pair_counts_against_the_oracle(c1, torch):
     a, sc = c1
     cam = sg.single_camera_c1()
     T = sg.identity_instances(1)
-    sel = sc.select(cam, 1.0)
-    sc.render(cam, sel)
+    for tau in (1.0, 16.0, 256.0, 3000.0):  # the finest cut whose bin lists fit one chunk
+        sel = sc.select(cam, tau)
+        sc.render(cam, sel)
+        keys, _ = sc.sorted_keys()
+        longest = int(np.bincount((keys >> np.uint64(32)).astype(np.int64)).max())
+        if longest <= 6144:
+            break
     sc.collect_profile()
     sc.render(cam, sel)
     assert sc.collect_profile()["pairs_taken"] == 0  # counted only when asked for
@@ -529,33 +535,32 @@ def test_blend_pair_counts_against_the_oracle(c1, torch):
     sc.render(cam, sel)
     P = sc.collect_profile()
     sc.set_profiling(False)
-    keys, _ = sc.sorted_keys()
-    longest = int(np.bincount((keys >> np.uint64(32)).astype(np.int64)).max())
     _, amb, st = oracle.render(a, T, cam, sel.ids())
-    _say("pairs: evaluated %d, contributing %d; oracle contributing %d (bucket walk %d); ambiguous pixels %d; "
-         "longest tile list %d" % (P["pairs"], P["pairs_taken"], st["n_hits"], st["n_pairs"], int(amb.sum()), longest))
-    assert longest <= 4096
+    _say("pairs at tolerance %g: evaluated %d, contributing %d; oracle contributing %d (bucket walk %d); ambiguous "
+         "pixels %d; longest bin list %d" % (tau, P["pairs"], P["pairs_taken"], st["n_hits"], st["n_pairs"],
+                                            int(amb.sum()), longest))
+    assert longest <= 6144
     assert P["pairs"] >= P["pairs_taken"] > 0
     assert abs(P["pairs_taken"] - st["n_hits"]) <= 1e-4 * st["n_hits"] + 20 * int(amb.sum())
 
 
 def test_render_capacity_overflow_is_still_exact(torch):
     """v3dg_render sizes the first frame of an image size exactly (one host
-    wait); later frames run on a key capacity (at least 2^20 keys, 16 keys per
+    wait); later frames run on a key capacity (at least 2^20 keys, 32 keys per
     pixel and twice the most keys seen) without host waits.  A later frame
     that needs more keys than that is blended from all visible splats in depth
     order: its image still matches the oracle, its sorted keys are
     unavailable, and the next frame runs on a grown capacity with its keys
     sorted."""
     a = H.stacked_splats(16000, 5, (0.05, 0.5), log_scale=-1.0)
-    T = sg.identity_instances(1)
+    T = np.tile(sg.identity_instances(1), (4, 1, 1))  # 64,000 splats: up to 62 keys per pixel
     sc = v.Scene(a, T)
     far = H.identity_camera(160, 120, 4.0, bg=(0.1, 0.2, 0.3))    # the stack covers a few pixels
-    near = H.identity_camera(160, 120, 600.0, bg=(0.1, 0.2, 0.3))  # every splat covers every tile
+    near = H.identity_camera(160, 120, 600.0, bg=(0.1, 0.2, 0.3))  # every splat covers every bin
     s_far = sc.select(far, 0.0)
     sc.render(far, s_far)
     k_far = sc.frame_stats()["n_keys"]
-    cap = max(2 * k_far, 16 * 160 * 120, 1 << 20)
+    cap = max(2 * k_far, 32 * 160 * 120, 1 << 20)
     s_near = sc.select(near, 0.0)
     img = sc.render(near, s_near).clone()
     st = sc.frame_stats()

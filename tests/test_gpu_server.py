@@ -108,10 +108,17 @@ def test_server_images_equal_standalone(scenes, torch, use_graphs):
 
 
 def test_server_retries_after_key_overflow(scenes, torch):
+    """A capacity of one key per pixel (at least 65,536) at first: requests that
+    need more are retried on grown buffers.  A fourth scene of 6,000 large
+    splats, seen from in front, covers every bin of its images (~6,000 keys
+    per bin), so its requests overflow whatever the mix."""
     rng = np.random.default_rng(5)
-    reqs = _requests(rng, 12)
-    ref = _standalone(scenes, torch, reqs)
-    srv = v.Server(scenes, n_contexts=3, max_batch=4, keys_per_pixel=1)  # too few keys at first
+    dense = v.Scene(H.stacked_splats(6000, 5, (0.05, 0.5), log_scale=-1.0), sg.identity_instances(1))
+    all_scenes = list(scenes) + [dense]
+    reqs = _requests(rng, 12) + [(3, H.identity_camera(w, h, 300.0 * w / 200.0, bg=(0.1, 0.2, 0.3)), 0.0)
+                                 for w, h in [(200, 150), (333, 250), (640, 360)]]
+    ref = _standalone(all_scenes, torch, reqs)
+    srv = v.Server(all_scenes, n_contexts=3, max_batch=4, keys_per_pixel=1)  # too few keys at first
     tickets = {}
     for i, (k, cam, tau) in enumerate(reqs):
         t, _ = srv.submit(k, cam, tau)
@@ -126,6 +133,7 @@ def test_server_retries_after_key_overflow(scenes, torch):
         assert r["status"] == 0
         assert torch.equal(r["image"], ref[i][0]), i
     srv.close()
+    dense.close()
 
 
 def test_server_budget_limits_contexts(scenes, torch):
