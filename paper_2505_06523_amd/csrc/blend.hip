@@ -5,7 +5,7 @@
 // tile's depth-sorted splats are staged through LDS in batches of 256 (one
 // gather per splat per tile); every wavefront compacts, in order, the batch
 // entries whose enlarged support reaches a pixel centre of its quarter (an
-// exact ellipse-rectangle test) and walks only those.
+// exact ellipse-rectangle test, per 8-row band) and walks only those.
 //
 // Per (pixel, splat), with d = mean - pixel centre and conic (A, B, C):
 //   power = min(0, -1/2 (A dx^2 + C dy^2) - B dx dy),  alpha = min(0.99, o e^power);
@@ -60,39 +60,18 @@ struct Pix {
     uint32_t taken;       // of those, pairs with alpha >= 1/255 (composited, or ending the pixel) (uniform)
 };
 
-// Whether the enlarged support {q <= Qm} of a splat reaches the rectangle of
-// pixel centres [xa, xb] x [ya, yb] (offsets from its mean), with q = A x^2 +
-// 2 B x y + C y^2 its quadratic form.  When the mean lies outside, the
-// minimum of q over the rectangle lies on an edge.  On the edge x = d,
-//   q(d, y) = C (y - y*)^2 + d^2 / Sxx,   y* = -B d / C,
-// since A - B^2 / C = 1 / Sxx (Sxx the 2D covariance's x entry); the same
-// holds on the edges y = d with A, C and Sxx, Syy exchanged.  Both terms are
-// non-negative, so the test has no cancellation, however thin the splat.  In
-// units of Qm: sqc = sqrt(C / Qm), isx = 1 / sqrt(Qm Sxx) (and sqa, isy), and
-// an edge reaches when (sqc (y_c - y*))^2 + (isx d)^2 <= 1 with y_c = y*
-// clamped to the edge.  A NaN counts as reaching (never a wrong skip).
-struct Reach {
-    float bc, ba, sqc, sqa, isx, isy;
-};
-
-__device__ __forceinline__ bool edge_reach(float d, float lo, float hi, float slope, float sq, float inv)
-{
-    const float t = slope * d;
-    const float u = (fminf(fmaxf(t, lo), hi) - t) * sq, w = d * inv;
-    return !(u * u + w * w > 1.0f);
-}
-
-__device__ __forceinline__ bool rect_reach(const Reach &r, float xa, float xb, float ya, float yb)
-{
-    const bool inside = xa <= 0.0f && xb >= 0.0f && ya <= 0.0f && yb >= 0.0f;
-    return inside || edge_reach(xa, ya, yb, r.bc, r.sqc, r.isx) || edge_reach(xb, ya, yb, r.bc, r.sqc, r.isx) ||
-           edge_reach(ya, xa, xb, r.ba, r.sqa, r.isy) || edge_reach(yb, xa, xb, r.ba, r.sqa, r.isy);
-}
-
 // Stage one batch entry (the splat record of key i) into LDS with its
-// quarter mask: bit q when the support reaches a pixel centre of quarter q
-// (enlarged like the binning: Qm = 1.05 Q + 0.05 with alpha >= 1/255 exactly
-// when q <= Q = 2 ln(255 o)).
+// quarter mask: bit q when the enlarged support {d : d' S^-1 d <= Qm} (S the
+// 2D covariance, Qm = 1.05 Q + 0.05 with alpha >= 1/255 exactly when
+// d' S^-1 d <= Q = 2 ln(255 o), enlarged like the binning) reaches a pixel
+// centre of quarter q.  Per 8-row band of the tile (offsets [ya, ya + 7] from
+// the mean) the support spans x in [k y - w(y), k y + w(y)] with k = Sxy /
+// Syy = -B / A and w(y) = sqrt(Qm (1 - y^2 / (Qm Syy)) / A) (A, B the conic's
+// entries: Syy / det S = A); its right end peaks at y_r = k Qm Syy /
+// sqrt(Qm Sxx) and its left end at -y_r, so the band's x-range comes from
+// those points clamped into the band.  A quarter is kept when that range
+// meets its pixel centres: exact for the rectangle of centres, with no
+// cancellation (no determinant is formed), and a NaN keeps the quarter.
 __device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid, const float4 &f0, const float4 &f1,
                                             const float4 &f2, float bx0, float by0)
 {
@@ -104,19 +83,23 @@ __device__ __forceinline__ void stage_entry(BlendShared &sh, int tid, bool valid
         sh.P1[tid] = make_float4(-0.5f * kLog2e * f1.x, -l255o, lo, 0.f);
         sh.P2[tid] = make_float4(f1.z, f1.w, f2.x, 0.f);
         // f2.z, f2.w = sqrt(Qm Sxx), sqrt(Qm Syy) from the projection
-        const float iq = 1.0f / (1.05f * (2.0f * kLn2 * l255o) + 0.05f);
-        Reach r;
-        r.bc = -f0.w / f1.x;
-        r.ba = -f0.w / f0.z;
-        r.sqc = sqrtf(f1.x * iq);
-        r.sqa = sqrtf(f0.z * iq);
-        r.isx = 1.0f / f2.z;
-        r.isy = 1.0f / f2.w;
+        const float Qm = 1.05f * (2.0f * kLn2 * l255o) + 0.05f;
+        const float k = -f0.w / f0.z, qa = Qm / f0.z, ymax = f2.w, iym = 1.0f / f2.w;
+        const float yr = k * (f2.w * f2.w / f2.z);
         const float X0 = bx0 - f0.x, Y0 = by0 - f0.y;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float xa = X0 + 8.0f * (float)(q & 1), ya = Y0 + 8.0f * (float)(q >> 1);
-            m |= (uint32_t)rect_reach(r, xa, xa + 7.0f, ya, ya + 7.0f) << q;
+        for (int band = 0; band < 2; ++band) {
+            const float ylo = fmaxf(Y0 + 8.0f * (float)band, -ymax), yhi = fminf(Y0 + 8.0f * (float)band + 7.0f, ymax);
+            const float dr = fminf(fmaxf(yr, ylo), yhi), dl = fminf(fmaxf(-yr, ylo), yhi);
+            const float ur = dr * iym, ul = dl * iym;
+            const float xr = fmaf(k, dr, sqrtf(fmaxf(0.0f, (1.0f - ur * ur) * qa)));
+            const float xl = fmaf(k, dl, -sqrtf(fmaxf(0.0f, (1.0f - ul * ul) * qa)));
+            const bool in_band = !(ylo > yhi);
+#pragma unroll
+            for (int qx = 0; qx < 2; ++qx) {
+                const float xa = X0 + 8.0f * (float)qx;
+                m |= (uint32_t)(in_band && !(xl > xa + 7.0f) && !(xr < xa)) << (2 * band + qx);
+            }
         }
     }
     sh.mask[tid] = (uint8_t)m;

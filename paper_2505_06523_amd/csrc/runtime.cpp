@@ -610,12 +610,14 @@ int ensure_status(Ctx *c, uint64_t parts)
 }
 
 // chunk buffers for frames of up to K keys over n_tiles tiles
-// Chunk records a blend plan over K keys may take: every tile of a bin walks
-// the bin's list, so a list of L > kChunkFirst keys takes at most
-// kTilesPerBin (L / kChunk + 1) records.
-uint64_t chunk_bound(uint64_t K, uint32_t n_tiles)
+// Chunk records a blend plan over K keys may take: each of the kTilesPerBin
+// tiles of a bin with L > kChunkFirst keys takes n_chunks(L) <= 2 + (L -
+// kChunkFirst) / kChunk <= L / kChunk of them (kChunkFirst >= 2 kChunk), so
+// all lists together take at most kTilesPerBin K / kChunk.
+static_assert(kChunkFirst >= 2 * kChunk, "the chunk bound needs first chunks of at least two later ones");
+uint64_t chunk_bound(uint64_t K, uint32_t /*n_tiles*/)
 {
-    return kTilesPerBin * ((K + kChunk - 1) / kChunk) + n_tiles;
+    return kTilesPerBin * ((K + kChunk - 1) / kChunk) + 1;
 }
 
 int ensure_chunks(Ctx *c, uint64_t K, uint32_t n_tiles)
