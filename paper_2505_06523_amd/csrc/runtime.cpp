@@ -609,20 +609,10 @@ int ensure_status(Ctx *c, uint64_t parts)
     return V3DG_OK;
 }
 
-// chunk buffers for frames of up to K keys over n_tiles tiles
-// Chunk records a blend plan over K keys may take: each of the kTilesPerBin
-// tiles of a bin with L > kChunkFirst keys takes n_chunks(L) <= 2 + (L -
-// kChunkFirst) / kChunk <= L / kChunk of them (kChunkFirst >= 2 kChunk), so
-// all lists together take at most kTilesPerBin K / kChunk.
-static_assert(kChunkFirst >= 2 * kChunk, "the chunk bound needs first chunks of at least two later ones");
-uint64_t chunk_bound(uint64_t K, uint32_t /*n_tiles*/)
+// chunk buffers for frames of up to K keys (chunk_bound)
+int ensure_chunks(Ctx *c, uint64_t K)
 {
-    return kTilesPerBin * ((K + kChunk - 1) / kChunk) + 1;
-}
-
-int ensure_chunks(Ctx *c, uint64_t K, uint32_t n_tiles)
-{
-    const uint64_t need = chunk_bound(K, n_tiles);
+    const uint64_t need = chunk_bound(K);
     if (need <= c->cap_chunks) return V3DG_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
     dev_free(c->items);
@@ -822,7 +812,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         if ((err & (kErrOverflow | kErrKeyCap)) || K >= 0xffffffffull)
             return fail(V3DG_ERR_CAPACITY, "frame needs %llu keys; the limit is 2^32-1", (unsigned long long)K);
         if ((rc = ensure_keys(c, K))) return rc;
-        if ((rc = ensure_chunks(c, K, n_tiles))) return rc;
+        if ((rc = ensure_chunks(c, K))) return rc;
         fi->K = K;
         KL = K;
     } else {
@@ -830,7 +820,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     }
     const uint32_t *k_dev = capacity ? c->rcounters + kRenKeysEff : nullptr;
     // chunk records the plan may use (each tile of a bin walks the bin's list)
-    const uint64_t max_chunks = capacity ? c->cap_chunks : chunk_bound(KL, n_tiles);
+    const uint64_t max_chunks = capacity ? c->cap_chunks : chunk_bound(KL);
     const uint32_t n_bins = cam.bins_x * cam.bins_y;
     const uint32_t bin_bits = std::max<uint32_t>(bits_for(n_bins), 1);
     int buf = 0;
@@ -941,7 +931,7 @@ int ensure_render_capacity(v3dg_scene *s, uint32_t n_tiles, uint64_t pixels)
     const uint64_t want = std::min<uint64_t>(std::max(2 * s->keys_seen, floor), 0xfffff000ull);
     int rc;
     if (want > s->cap_keys && (rc = ensure_keys(s, want, true))) return rc;
-    return ensure_chunks(s, s->cap_keys, n_tiles);
+    return ensure_chunks(s, s->cap_keys);
 }
 
 int render_impl(v3dg_scene *s, const v3dg_camera *c, const v3dg_selection *sel, float *image)
@@ -2100,7 +2090,7 @@ uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
     g += (K2 - keys) * 24 + ((K2 - keys + kSortPart - 1) / kSortPart) * 3 / 2 * kRadix * 8;
     const uint64_t T2 = std::max<uint64_t>(std::max<uint64_t>(n_tiles, 8160), tiles);
     g += (T2 - tiles) * 16;
-    const uint64_t ch = chunk_bound(K2, (uint32_t)T2);
+    const uint64_t ch = chunk_bound(K2);
     if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 8);
     return g;
 }
@@ -2153,7 +2143,7 @@ int srv_provision(SrvCtx *c, uint32_t n_inst, uint32_t n_tiles, uint64_t K, bool
     if ((rc = ensure_itab(c, n_inst))) return rc;
     if ((rc = ensure_tiles(c, n_tiles))) return rc;
     if ((rc = ensure_keys(c, K, true))) return rc;
-    if ((rc = ensure_chunks(c, c->cap_keys, c->tiles_cap))) return rc;
+    if ((rc = ensure_chunks(c, c->cap_keys))) return rc;
     const uint64_t after[4] = {c->itab_cap, c->tiles_cap, c->cap_keys, c->cap_chunks};
     *changed = std::memcmp(before, after, sizeof(before)) != 0 || parts_before != c->sort_status_parts;
     if (*changed) {

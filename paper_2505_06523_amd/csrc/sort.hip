@@ -899,7 +899,7 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
     uint32_t m_base = 0;
     if (lane == kWave - 1 && m_incl) m_base = atomicAdd(&counters[kRenChunks], m_incl);
     const uint32_t first = __shfl(m_base, kWave - 1, kWave) + m_incl - m;
-    const bool ok = m != 0 && (uint64_t)first + m <= max_chunks;
+    const bool ok = plan_fits(first, m, max_chunks);
     if (in) cbase[t] = ok ? first : kNoChunk;
     const uint32_t it = ok ? m - 1 : 0u;
     const uint32_t it_incl = wave_incl_scan_u32(it);

@@ -3,12 +3,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "blend_plan.h"
+
 namespace v3dg {
 
 constexpr int kTile = 16;               // edge in pixels of a tile (blended by one workgroup)
 constexpr int kBin = 32;                // edge in pixels of a bin (a 2 x 2 block of tiles); keys name bins
-constexpr uint32_t kTilesPerBin = (kBin / kTile) * (kBin / kTile);
-static_assert(kBin == 2 * kTile, "a bin is a 2 x 2 block of tiles");
+static_assert(kBin == 2 * kTile && kTilesPerBin == 4, "a bin is a 2 x 2 block of tiles");
 constexpr int kWave = 64;               // CDNA wavefront width
 
 // Gaussian attributes are structure-of-arrays planes with a common stride
@@ -284,20 +285,6 @@ template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide);
-// Chunks of long tile lists (blending): a list of L > kChunkFirst keys is
-// cut into a first chunk of kChunkFirst keys and further chunks of kChunk.
-constexpr int kChunk = 2048;            // keys per chunk of a long bin list after the first
-constexpr int kChunkFirst = 6144;       // keys of the first chunk (walked by pass 1)
-constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whole
-__device__ __forceinline__ uint32_t n_chunks(uint32_t L)
-{
-    return L <= (uint32_t)kChunkFirst ? 1u : 1u + (L - kChunkFirst + kChunk - 1) / kChunk;
-}
-__device__ __forceinline__ uint32_t chunk_begin(uint32_t c) { return c == 0 ? 0u : kChunkFirst + (c - 1) * kChunk; }
-__device__ __forceinline__ uint32_t chunk_end(uint32_t c, uint32_t L)
-{
-    return min((uint32_t)kChunkFirst + c * (uint32_t)kChunk, L);
-}
 // Per tile t < n_tiles (tiles_x per row): ranges[t] = [first, end) of the
 // keys of its bin (bins_x per row) in the sorted keys, and the blend plan.  A
 // tile whose bin holds L > kChunkFirst keys gets n_chunks(L) consecutive

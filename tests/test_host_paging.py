@@ -206,3 +206,16 @@ def test_page_store_round_trip(store_harness, tmp_path, where, direct):
     p.wait()
     if where == "file":
         assert not os.path.exists(path)  # removed with the store
+
+
+def test_blend_plan_bounds(tmp_path):
+    """The chunk-record bound the runtime sizes its buffers by
+    (paper_2505_06523_amd/csrc/blend_plan.h) holds on random plans: at that
+    size every long bin list is chunked for each of its tiles, and at any size
+    the records handed out, the work items and the re-walk entries stay inside
+    the buffer; the chunks of a list tile it exactly (C++ harness, CPU)."""
+    exe = str(tmp_path / "plan_harness")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-Wall", "-I", CSRC, os.path.join(HERE, "plan_harness.cpp"), "-o",
+                    exe], check=True)
+    out = subprocess.run([exe, "1500"], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "ok 1500", out.stdout + out.stderr
