@@ -1911,12 +1911,24 @@ int v3dg_set_culling(v3dg_scene *s, int on)
     return V3DG_OK;
 }
 
+constexpr size_t kEventPoolWarm = 512;  // two events per timed stage and frame: 256 frames of one stage
+
 int v3dg_set_profiling(v3dg_scene *s, int stage_mask)
 {
     g_err.clear();
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
     s->profiling = (uint32_t)stage_mask & V3DG_PROFILE_ALL;
     s->audit_pairs = (stage_mask & V3DG_PROFILE_PAIR_AUDIT) != 0;
+    // events for the timed stages are created here rather than inside the
+    // frames being timed (creating one costs far more than recording it)
+    if (s->profiling) {
+        HIP_TRY(hipSetDevice(s->device));
+        while (s->ev_pool.size() < kEventPoolWarm) {
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipEventCreate(&e));
+            s->ev_pool.push_back(e);
+        }
+    }
     return V3DG_OK;
 }
 
