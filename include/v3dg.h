@@ -235,8 +235,8 @@ int v3dg_select(v3dg_scene *scene, const v3dg_camera *cam, float tolerance, v3dg
  * completely.  The first frame of an image size (and every frame in the
  * 64-bit-key sort mode) synchronises once mid-frame to size the key buffers
  * exactly.  Later frames of that size run without any host wait: their
- * launches are sized by a key capacity of at least 2^20 keys, 32 keys per
- * pixel (up to 2^26 keys) and twice the most keys any frame needed, the kernels read their counts on the
+ * launches are sized by a key capacity of at least 2^20 keys, 48 keys per
+ * pixel (up to 2^27 keys) and twice the most keys any frame needed, the kernels read their counts on the
  * device, and each frame publishes its counts to pinned host memory, read
  * when a later call finds the frame finished.  A frame that needs more keys
  * than the capacity is still rendered exactly, by every tile walking all

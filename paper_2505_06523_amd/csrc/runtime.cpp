@@ -668,11 +668,13 @@ void epoch_advance(Ctx *c)
 
 // Stable sort of K (key, value) pairs held in buffer 0 by the low key_bits
 // bits; n_dev, when given, is the device-side count (K then bounds it).
+// have_hist: the digit histograms of plan dp were counted by emission;
+// otherwise the keys are sorted by 8-bit digits with their own histogram pass.
 template <typename KT>
 void run_sort(Ctx *c, KT *const kb[2], uint32_t *const vb[2], const uint32_t *n_dev, uint64_t K, uint32_t key_bits,
-              uint32_t epoch_base, int *out_buf, uint32_t *passes_out, bool have_hist)
+              uint32_t epoch_base, int *out_buf, uint32_t *passes_out, bool have_hist, const DigitPlan *dp = nullptr)
 {
-    const int passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
+    const int passes = have_hist && dp ? dp->passes : (int)((key_bits + kRadixBits - 1) / kRadixBits);
     *passes_out = (uint32_t)passes;
     int cur = 0;
     if (!have_hist) {
@@ -681,9 +683,12 @@ void run_sort(Ctx *c, KT *const kb[2], uint32_t *const vb[2], const uint32_t *n_
     }
     for (int p = 0; p < passes; ++p) {
         Stage st(c, V3DG_STAGE_SORT_PASS);
+        const int shift = have_hist && dp ? (int)dp->shift[p] : -1;
+        const int dbits = have_hist && dp ? (int)dp->bits[p] : kRadixBits;
         launch_sort_pass<KT>(c->stream, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n_dev, K, p, c->rcounters + kRenHist,
                              c->sort_status, &c->fdev->epoch, epoch_base + (uint32_t)p,
-                             c->rcounters + kRenTicketSort + p, c->rcounters + kRenErr, K >= kSortWideFrom);
+                             c->rcounters + kRenTicketSort + p, c->rcounters + kRenErr, K >= kSortWideFrom, shift,
+                             dbits);
         cur ^= 1;
     }
     *out_buf = cur;
@@ -705,14 +710,14 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
                const FramePub &pub)
 {
     KT *kb[2] = {reinterpret_cast<KT *>(c->keys[0]), reinterpret_cast<KT *>(c->keys[1])};
-    const int tpasses = (int)((key_bits + kRadixBits - 1) / kRadixBits);
+    const DigitPlan dp = even_digits(key_bits);
     {
         Stage st(c, V3DG_STAGE_EMIT);
         launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys,
-                          tpasses, kb[0], c->vals[0], c->rcounters + kRenHist, c->big, c->rcounters + kRenBig,
+                          dp, kb[0], c->vals[0], c->rcounters + kRenHist, c->big, c->rcounters + kRenBig,
                           c->rcounters + kRenErr);
     }
-    if (KL > 0) run_sort<KT>(c, kb, c->vals, k_dev, KL, key_bits, 4, buf, passes, true);
+    if (KL > 0) run_sort<KT>(c, kb, c->vals, k_dev, KL, key_bits, 4, buf, passes, true, &dp);
     {
         Stage st(c, V3DG_STAGE_RANGES);
         launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, tiles_x, n_tiles, bins_x,
@@ -923,8 +928,8 @@ int drain_records(v3dg_scene *s, bool block)
 // capacity: twice the most keys seen, and at least kRenderKeysPerPixel keys
 // per pixel up to kRenderKeysFloorMax keys.  Grows only (a growth waits for
 // the frames in flight).
-constexpr uint64_t kRenderKeysPerPixel = 32;
-constexpr uint64_t kRenderKeysFloorMax = 1ull << 26;
+constexpr uint64_t kRenderKeysPerPixel = 48;
+constexpr uint64_t kRenderKeysFloorMax = 1ull << 27;
 int ensure_render_capacity(v3dg_scene *s, uint32_t n_tiles, uint64_t pixels)
 {
     const uint64_t floor = std::min(kRenderKeysPerPixel * pixels, kRenderKeysFloorMax);

@@ -65,12 +65,14 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
     return off + incl - v;
 }
 
-// lanes of the wavefront holding the same 8-bit digit (among valid lanes)
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+// lanes of the wavefront holding the same digit of dbits <= 8 bits (among
+// valid lanes; dbits is uniform)
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, uint32_t dbits = kRadixBits)
 {
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
+        if ((uint32_t)b >= dbits) break;
         const bool bit = (d >> b) & 1u;
         const uint64_t bb = __ballot(bit);
         peers &= bit ? bb : ~bb;
@@ -290,27 +292,28 @@ constexpr int kEmitThreads = 256;
 constexpr uint32_t kSmallKeys = 48;  // measured best of 8..256 on 1080p orbits
 constexpr uint32_t kStage = 2048;
 
-__device__ __forceinline__ void count_span(uint32_t a, uint32_t b, int passes, uint32_t *s_d0, uint32_t *s_h,
+__device__ __forceinline__ void count_span(uint32_t a, uint32_t b, const DigitPlan &dp, uint32_t *s_d0, uint32_t *s_h,
                                            uint32_t *s_all)
 {
-    // tiles a..b (inclusive): every 256 consecutive ids hold each low digit once
+    // keys a..b (inclusive): every R0 consecutive ids hold each low digit once
+    const uint32_t b0 = dp.bits[0], m0 = (1u << b0) - 1u;
     const uint32_t len = b - a + 1;
-    if (len >= 256u) atomicAdd(s_all, len >> 8);
-    const uint32_t rem = len & 255u;
+    if (len > m0) atomicAdd(s_all, len >> b0);
+    const uint32_t rem = len & m0;
     if (rem) {
-        const uint32_t la = a & 255u, lb = (a + rem - 1) & 255u;
+        const uint32_t la = a & m0, lb = (a + rem - 1) & m0;
         atomicAdd(&s_d0[la], 1u);
         atomicAdd(&s_d0[lb + 1], 0xffffffffu);
-        if (la > lb) {  // wraps past digit 255
-            atomicAdd(&s_d0[256], 0xffffffffu);
+        if (la > lb) {  // wraps past the last low digit
+            atomicAdd(&s_d0[m0 + 1], 0xffffffffu);
             atomicAdd(&s_d0[0], 1u);
         }
     }
-    for (int p = 1; p < passes; ++p) {
-        const int sh = 8 * p;
+    for (int p = 1; p < dp.passes; ++p) {
+        const uint32_t sh = dp.shift[p], mp = (1u << dp.bits[p]) - 1u;
         for (uint32_t h = a >> sh; h <= (b >> sh); ++h) {
             const uint32_t lo = max(a, h << sh), hi = min(b, ((h + 1) << sh) - 1);
-            atomicAdd(&s_h[(p - 1) * 256 + (h & 255u)], hi - lo + 1);
+            atomicAdd(&s_h[(p - 1) * 256 + (h & mp)], hi - lo + 1);
         }
     }
 }
@@ -351,7 +354,7 @@ template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
     const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
-    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, int passes,
+    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, DigitPlan dp,
     KT *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *__restrict__ big,
     uint32_t *n_big, uint32_t *err)
 {
@@ -397,7 +400,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
             uint32_t lo, hi;
             if (!bin_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
             const uint32_t row = ty * tiles_x;
-            count_span(row + lo, row + hi, passes, sh.d0, sh.h, &sh.all);
+            count_span(row + lo, row + hi, dp, sh.d0, sh.h, &sh.all);
             const uint32_t m = min(hi - lo + 1u, left);
             if (staged) {
                 for (uint32_t i = 0; i < m; ++i) {
@@ -445,7 +448,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
                 uint32_t hi;
                 if (bin_row_span(bb, ty, bx0, bx1, &lo, &hi)) {
                     len = hi - lo + 1;
-                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, sh.d0, sh.h, &sh.all);
+                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, dp, sh.d0, sh.h, &sh.all);
                 }
             }
             const uint32_t incl = wave_incl_scan_u32(len);
@@ -482,12 +485,12 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
         for (int c = 0; c < 4; ++c) {
             const uint32_t v = sh.d0[c * kWave + tid];
             const uint32_t incl = wave_incl_scan_u32(v);
-            const uint32_t cntd = run + incl + sh.all;
+            const uint32_t cntd = run + incl + ((uint32_t)(c * kWave + tid) >> dp.bits[0] == 0u ? sh.all : 0u);
             if (cntd) atomicAdd(&hist[c * kWave + tid], cntd);
             run += __shfl(incl, kWave - 1, kWave);
         }
     }
-    for (int p = 1; p < passes; ++p)
+    for (int p = 1; p < dp.passes; ++p)
         for (int i = tid; i < 256; i += kEmitThreads)
             if (sh.h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], sh.h[(p - 1) * 256 + i]);
 }
@@ -500,7 +503,7 @@ template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
     const uint32_t *__restrict__ n_big, const uint32_t *__restrict__ big, const uint32_t *__restrict__ order,
     const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
-    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, int passes, KT *__restrict__ keys,
+    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, DigitPlan dp, KT *__restrict__ keys,
     uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
 {
     __shared__ uint32_t s_d0[257], s_h[2 * 256], s_all, s_tmp[4];
@@ -527,7 +530,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
                 uint32_t hi;
                 if (bin_row_span(b, ty, tx0, tx1, &lo, &hi)) {
                     len = hi - lo + 1;
-                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, passes, s_d0, s_h, &s_all);
+                    count_span(ty * tiles_x + lo, ty * tiles_x + hi, dp, s_d0, s_h, &s_all);
                 }
             }
             uint32_t total;
@@ -556,12 +559,12 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
         for (int c = 0; c < 4; ++c) {
             const uint32_t v = s_d0[c * kWave + tid];
             const uint32_t incl = wave_incl_scan_u32(v);
-            const uint32_t cntd = run + incl + s_all;
+            const uint32_t cntd = run + incl + ((uint32_t)(c * kWave + tid) >> dp.bits[0] == 0u ? s_all : 0u);
             if (cntd) atomicAdd(&hist[c * kWave + tid], cntd);
             run += __shfl(incl, kWave - 1, kWave);
         }
     }
-    for (int p = 1; p < passes; ++p)
+    for (int p = 1; p < dp.passes; ++p)
         for (int i = tid; i < 256; i += kEmitThreads)
             if (s_h[(p - 1) * 256 + i]) atomicAdd(&hist[p * 256 + i], s_h[(p - 1) * 256 + i]);
 }
@@ -569,17 +572,17 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
                    const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
-                   const FrameDev *fd, uint64_t key_cap, int passes, KT *keys, uint32_t *vals, uint32_t *hist,
+                   const FrameDev *fd, uint64_t key_cap, const DigitPlan &dp, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *big, uint32_t *n_big, uint32_t *err)
 {
     if (max_n == 0) return;
     const uint32_t blocks = (uint32_t)((max_n + kEmitThreads - 1) / kEmitThreads);
     hipLaunchKernelGGL(emit32_kernel<KT>, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order,
-                       tiles, offsets, rect, bin, fd, key_cap, passes, keys, vals, hist, big, n_big, err);
+                       tiles, offsets, rect, bin, fd, key_cap, dp, keys, vals, hist, big, n_big, err);
     // a fixed grid walks the list (any number of its slots may be large)
     const uint32_t bblocks = (uint32_t)(max_n < 2048 ? max_n : 2048);
     hipLaunchKernelGGL(emit_big_kernel<KT>, dim3(bblocks), dim3(kEmitThreads), 0, st, n_big, big, order, tiles,
-                       offsets, rect, bin, fd, passes, keys, vals, hist, err);
+                       offsets, rect, bin, fd, dp, keys, vals, hist, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,8 +656,8 @@ template <typename K, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 2 ? 3 : 1)))
 sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, K *__restrict__ keys_out,
                  uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
-                 const uint32_t *__restrict__ hist, uint64_t *status, const uint32_t *__restrict__ epoch_dev,
-                 uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
+                 uint32_t dbits, const uint32_t *__restrict__ hist, uint64_t *status,
+                 const uint32_t *__restrict__ epoch_dev, uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
 {
     constexpr int NW = kSortThreads / kWave;           // waves per block
     constexpr int PART = kSortThreads * ITEMS;         // keys of a partition
@@ -672,6 +675,7 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
     const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
     const uint32_t epoch = epoch_dev ? *epoch_dev + epoch_arg : epoch_arg;
     const uint32_t nparts = (n + PART - 1) / PART;
+    const uint32_t dmask = (1u << dbits) - 1u;  // digits d > dmask never occur: no look-back for them
     // Partitions are claimed in ticket order until none is left, so the grid
     // need not match the key count (a bound on it, or far fewer workgroups,
     // both work).  A partition only waits on lower tickets, claimed earlier
@@ -716,8 +720,8 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
         const uint32_t idx = wave_base + r * kWave + lane;
         const bool valid = idx < n;
         const K k = key[r];
-        const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid);
+        const uint32_t d = (uint32_t)(k >> shift) & dmask;
+        const uint64_t peers = match_digit(d, valid, dbits);
         const uint32_t rank_in_round = (uint32_t)__popcll(peers & lt_mask);
         const uint32_t cnt = (uint32_t)__popcll(peers);
         uint32_t old = 0;
@@ -738,7 +742,9 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
     }
     uint64_t *my = status + (uint64_t)p * kRadix + d;
     uint32_t prefix = 0;
-    if (p == 0) {
+    if ((uint32_t)d > dmask) {
+        // a digit wider than the pass's: no key holds it, no partition looks it up
+    } else if (p == 0) {
         __hip_atomic_store(my, lb_word(epoch, kFlagInc, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         __hip_atomic_store(my, lb_word(epoch, kFlagAgg, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -788,7 +794,7 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
         const uint32_t i = tid + r * kSortThreads;
         if (i < n_here) {
             const K k = s_keys[i];
-            const uint32_t dd = (uint32_t)(k >> shift) & (kRadix - 1);
+            const uint32_t dd = (uint32_t)(k >> shift) & dmask;
             const uint32_t o = s_gbase[dd] + (i - s_lstart[dd]);
             if (o < n) {  // always true when the histogram and look-back agree
                 keys_out[o] = k;
@@ -826,23 +832,26 @@ static uint32_t sort_pass_resident()
 template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
-                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide)
+                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide, int shift,
+                      int dbits)
 {
     if (n == 0) return;
+    const int sh = shift < 0 ? pass * kRadixBits : shift;
+    const uint32_t db = (uint32_t)(dbits < 1 ? 1 : dbits > kRadixBits ? kRadixBits : dbits);
     // wide partitions (6144 keys) for large 32-bit sorts: fewer partitions to
     // look back over and longer digit runs to store
     if (wide && sizeof(K) <= 4) {
         const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kSortPartWide - 1) / kSortPartWide,
                                                            sort_pass_resident<K, kSortItemsWide>());
         hipLaunchKernelGGL((sort_pass_kernel<K, kSortItemsWide>), dim3(grid), dim3(kSortThreads), 0, st, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
-                           status, epoch_dev, epoch, ticket, err);
+                           vals_in, keys_out, vals_out, n_dev, (uint32_t)n, sh, db, hist + pass * kRadix, status,
+                           epoch_dev, epoch, ticket, err);
     } else {
         const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kSortPart - 1) / kSortPart,
                                                            sort_pass_resident<K, kSortItems>());
         hipLaunchKernelGGL((sort_pass_kernel<K, kSortItems>), dim3(grid), dim3(kSortThreads), 0, st, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, (uint32_t)n, pass * kRadixBits, hist + pass * kRadix,
-                           status, epoch_dev, epoch, ticket, err);
+                           vals_in, keys_out, vals_out, n_dev, (uint32_t)n, sh, db, hist + pass * kRadix, status,
+                           epoch_dev, epoch, ticket, err);
     }
 }
 
@@ -933,23 +942,25 @@ void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, in
 }
 
 template void launch_emit32<uint16_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
-                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t, int,
-                                      uint16_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t,
+                                      const DigitPlan &, uint16_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
+                                      uint32_t *);
 template void launch_emit32<uint32_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
-                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t, int,
-                                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t,
+                                      const DigitPlan &, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
+                                      uint32_t *);
 template void launch_sort_hist<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *);
 template void launch_sort_pass<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint16_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
 template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
 template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint32_t,
                                           uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
                                           const uint32_t *, FrameRec *, uint32_t);

@@ -250,12 +250,36 @@ constexpr int kScanPart = kScanThreads * kScanItems;
 // have no keys to work on)
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
                        uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap);
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 256;
+// Digits of a radix sort: pass p orders the keys by bits [shift[p], shift[p]
+// + bits[p]) (bits[p] <= kRadixBits); digit histograms are kept kRadix apart.
+struct DigitPlan {
+    int passes = 0;
+    uint32_t shift[4] = {0u, 0u, 0u, 0u}, bits[4] = {0u, 0u, 0u, 0u};
+};
+// key_bits significant bits in the fewest passes of at most kRadixBits bits,
+// split as evenly as possible (11-bit bin ids: 6 + 5): narrower digits rank
+// with fewer ballots and look back over fewer counts.
+inline DigitPlan even_digits(uint32_t key_bits)
+{
+    DigitPlan d;
+    d.passes = (int)((key_bits + kRadixBits - 1) / kRadixBits);
+    uint32_t s = 0;
+    for (int p = 0; p < d.passes; ++p) {
+        const uint32_t left = key_bits - s, rest = (uint32_t)(d.passes - p);
+        d.bits[p] = (left + rest - 1) / rest;
+        d.shift[p] = s;
+        s += d.bits[p];
+    }
+    return d;
+}
 // 64-bit keys (bin << 32 | depth bits), slot order
 void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
                    const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
                    uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err);
 // Bin-id keys in depth order (order[j] = slot of depth rank j), with the
-// digit histograms of the bin sort (passes <= 3) accumulated into hist.
+// digit histograms of the bin sort (digits dp, passes <= 3) accumulated into hist.
 // KT = uint16_t for grids of at most kBinKey16Max bins, else uint32_t.
 constexpr uint32_t kBinKey16Max = 1u << 16;
 // (splats of more than 2048 keys are listed in big[] (n_big: a cleared
@@ -263,7 +287,7 @@ constexpr uint32_t kBinKey16Max = 1u << 16;
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
                    const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
-                   const FrameDev *fd, uint64_t key_cap, int passes, KT *keys, uint32_t *vals, uint32_t *hist,
+                   const FrameDev *fd, uint64_t key_cap, const DigitPlan &dp, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *big, uint32_t *n_big, uint32_t *err);
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;          // keys per thread
@@ -273,8 +297,6 @@ constexpr int kSortPartWide = kSortThreads * kSortItemsWide;
 static_assert(kSortPartWide >= kSortPart, "look-back status is sized for partitions of kSortPart keys");
 constexpr uint64_t kSortWideFrom = 1u << 22;  // sorts of at least this many keys use wide partitions
 constexpr uint64_t kSortMaxGrid = 4096;       // workgroups of a pass (they claim partitions until none is left)
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 256;
 // Digit histograms of all passes; the key count is n_dev ? *n_dev : n.
 template <typename K>
 void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist);
@@ -282,9 +304,12 @@ void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint
 // look-back epoch is *epoch_dev + epoch when epoch_dev is given, else epoch.
 // wide selects partitions of kSortPartWide keys (keys of at most 32 bits).
 template <typename K>
+// The pass's digit is bits [shift, shift + dbits) of the key (shift < 0:
+// the pass-th 8-bit digit); its histogram is hist + pass * kRadix.
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
-                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide);
+                      const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide,
+                      int shift = -1, int dbits = kRadixBits);
 // Per tile t < n_tiles (tiles_x per row): ranges[t] = [first, end) of the
 // keys of its bin (bins_x per row) in the sorted keys, and the blend plan.  A
 // tile whose bin holds L > kChunkFirst keys gets n_chunks(L) consecutive

@@ -546,7 +546,7 @@ def test_blend_pair_counts_against_the_oracle(c1, torch):
 
 def test_render_capacity_overflow_is_still_exact(torch):
     """v3dg_render sizes the first frame of an image size exactly (one host
-    wait); later frames run on a key capacity (at least 2^20 keys, 32 keys per
+    wait); later frames run on a key capacity (at least 2^20 keys, 48 keys per
     pixel and twice the most keys seen) without host waits.  A later frame
     that needs more keys than that is blended from all visible splats in depth
     order: its image still matches the oracle, its sorted keys are
@@ -560,7 +560,7 @@ def test_render_capacity_overflow_is_still_exact(torch):
     s_far = sc.select(far, 0.0)
     sc.render(far, s_far)
     k_far = sc.frame_stats()["n_keys"]
-    cap = max(2 * k_far, 32 * 160 * 120, 1 << 20)
+    cap = max(2 * k_far, 48 * 160 * 120, 1 << 20)
     s_near = sc.select(near, 0.0)
     img = sc.render(near, s_near).clone()
     st = sc.frame_stats()
