@@ -257,11 +257,14 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
     }
 }
 
-// pairs[0]: walked pairs; pairs[1]: taken pairs
-__device__ __forceinline__ void count_pairs(const Pix &px, int lane, unsigned long long *pairs)
+// pairs[2 s]: walked pairs; pairs[2 s + 1]: taken pairs, for s < kPairSlots.
+// Wavefronts add to slots spread by workgroup and wavefront: a single
+// counter taking every wavefront's add made the blend stage 6 % slower.
+__device__ __forceinline__ void count_pairs(const Pix &px, int wid, int lane, unsigned long long *pairs)
 {
-    if (lane == 0 && px.walked) atomicAdd(pairs, (unsigned long long)px.walked);
-    if (lane == 0 && px.taken) atomicAdd(pairs + 1, (unsigned long long)px.taken);
+    const uint32_t slot = (blockIdx.x * (kBlendThreads / kWave) + (uint32_t)wid) % kPairSlots;
+    if (lane == 0 && px.walked) atomicAdd(pairs + 2 * slot, (unsigned long long)px.walked);
+    if (lane == 0 && px.taken) atomicAdd(pairs + 2 * slot + 1, (unsigned long long)px.taken);
 }
 
 struct TileGeo {
@@ -335,7 +338,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
     } else {
         write_pixel(cam, g, px, image);
     }
-    count_pairs(px, lane, pairs);
+    count_pairs(px, wid, lane, pairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,7 +377,7 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
         if (was)
             scratch[(base + c) * kBlendThreads + g.pix] =
                 make_float4(px.cr, px.cg, px.cb, !px.active ? -px.T : px.T);
-        count_pairs(px, lane, pairs);
+        count_pairs(px, wid, lane, pairs);
         __syncthreads();  // the next item reuses the staged batch
     }
 }
@@ -469,7 +472,7 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         // a pixel that, through rounding of the folded products, does not stop in
         // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
         if (mine) write_pixel(cam, g, px, image);
-        count_pairs(px, lane, pairs);
+        count_pairs(px, wid, lane, pairs);
         __syncthreads();  // the next item reuses the staged batch
     }
 }
@@ -499,7 +502,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_all_kernel(const FrameDev
         Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u, 0u};
         blend_range<kAudit>(0, n_vis, splat, order, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
         write_pixel(cam, g, px, image);
-        count_pairs(px, lane, pairs);
+        count_pairs(px, wid, lane, pairs);
         __syncthreads();  // the next tile reuses the staged batch
     }
 }

@@ -193,7 +193,7 @@ struct Ctx {
     uint32_t profiling = 0;   // stages timed with events (bit per stage)
     bool audit_pairs = false; // blending also counts the pairs it takes
     v3dg_profile acc{};
-    unsigned long long *pairs_dev = nullptr;  // walked and taken (pixel, splat) pairs
+    unsigned long long *pairs_dev = nullptr;  // walked and taken (pixel, splat) pairs, kPairSlots of each
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
     // frames sized by capacity publish their counts into a ring of records in
@@ -473,9 +473,9 @@ int ctx_init(Ctx *c, int device, hipStream_t stream)
     c->stream = stream;
     int rc;
     if ((rc = dev_alloc(&c->fdev, 1))) return rc;
-    if ((rc = dev_alloc(&c->pairs_dev, 2))) return rc;
+    if ((rc = dev_alloc(&c->pairs_dev, 2 * kPairSlots))) return rc;
     HIP_TRY(hipMemset(c->fdev, 0, sizeof(FrameDev)));
-    HIP_TRY(hipMemset(c->pairs_dev, 0, 2 * sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(c->pairs_dev, 0, 2 * kPairSlots * sizeof(unsigned long long)));
     if (hipHostMalloc((void **)&c->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         c->pinned = nullptr;
         return fail(V3DG_ERR_OOM, "pinned allocation failed");
@@ -1945,12 +1945,15 @@ int v3dg_collect_profile(v3dg_scene *s, v3dg_profile *out)
     HIP_TRY(hipStreamSynchronize(s->stream));
     int rc = drain_records(s, true);
     if (rc) return rc;
-    unsigned long long pairs[2] = {0, 0};
+    unsigned long long pairs[2 * kPairSlots] = {0};
     HIP_TRY(hipMemcpy(pairs, s->pairs_dev, sizeof(pairs), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemset(s->pairs_dev, 0, sizeof(pairs)));
     v3dg_profile p = s->acc;
-    p.pairs = pairs[0];
-    p.pairs_taken = pairs[1];
+    p.pairs = p.pairs_taken = 0;
+    for (uint32_t k = 0; k < kPairSlots; ++k) {
+        p.pairs += pairs[2 * k];
+        p.pairs_taken += pairs[2 * k + 1];
+    }
     for (int i = 0; i < V3DG_N_STAGES; ++i) {
         p.ms[i] = 0.0;
         p.launches[i] = 0;

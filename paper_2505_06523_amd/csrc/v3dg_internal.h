@@ -327,9 +327,11 @@ void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, in
                         uint32_t *order, uint32_t *counters, uint64_t max_chunks,
                         const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr, uint32_t seq = 0);
 // blend.hip
+constexpr uint32_t kPairSlots = 256;  // spread pair counters (see count_pairs)
 // max_items / max_chunks bound the work items and chunks of the plan (grid
-// sizes).  pairs[0] counts the pairs walked; with audit, pairs[1] also counts
-// the pairs taken (alpha >= 1/255 at an active pixel), which slows the walk.
+// sizes).  pairs (2 kPairSlots counters) sums the pairs walked in its even
+// entries; with audit, its odd entries also sum the pairs taken (alpha >=
+// 1/255 at an active pixel), which slows the walk.
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                   const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
