@@ -165,11 +165,15 @@ def measured_blend_traffic(args):
     return BLEND_TRAFFIC["bytes_per_frame"]
 
 
-def run_frames(torch, scene, frames, img, full: bool, prof: bool):
+def run_frames(torch, scene, frames, img, full: bool, prof, pairs: bool = False):
+    """prof: stages timed with events (True: all); pairs: blending counts the
+    (pixel, splat) pairs it walks (a few scalar operations per pair, so the
+    timed headline pass leaves it off and a second pass over the same frames
+    counts them)."""
     sel = None
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in frames]
     scene.collect_profile()  # counts and stage times of these frames only
-    scene.set_profiling(prof)
+    scene.set_profiling(prof, pairs=pairs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i, (cam, tau) in enumerate(frames):
@@ -622,13 +626,15 @@ def main():
     # kernel); the per-stage breakdown comes from a second, identical pass
     timed_prof = False if args.no_stage_timing else ["blend"]
     log("timing %d V3DG frames" % K)
-    wall, ms, P, _ = run_frames(torch, scene, seq[:K], img, full=False, prof=timed_prof)
+    # a profiled run (rocprofv3) has one pass only, so that the profiler sees
+    # exactly the timed frames: that pass also counts the blend pairs
+    wall, ms, P, _ = run_frames(torch, scene, seq[:K], img, full=False, prof=timed_prof, pairs=args.profile_run)
     if args.no_stage_timing:
         _, _, P, _ = run_frames(torch, scene, seq[:K], img, full=False, prof=["blend"])
-    if args.profile_run:  # one pass only, so that a profiler sees exactly the timed frames
+    if args.profile_run:
         P_all = P
-    else:
-        _, _, P_all, _ = run_frames(torch, scene, seq[:K], img, full=False, prof=True)
+    else:  # the same frames again, every stage timed and the blend pairs counted
+        _, _, P_all, _ = run_frames(torch, scene, seq[:K], img, full=False, prof=True, pairs=True)
     fps = K / wall
     if args.profile_run:
         args.no_cpu = True
@@ -759,12 +765,12 @@ def main():
         P = P_all  # the timed pass carried events around blend only
     t_dom, n_dom = P["stages"][dom]
     if dom == "blend":
-        flops = P["pairs"] * BLEND_OPS_PER_PAIR
+        flops = P_all["pairs"] * BLEND_OPS_PER_PAIR  # the frames of the timed pass, counted in the second
         ach = flops / n_dom / (t_dom / n_dom * 1e-3) / 1e12
         roof = dict(kernel="blend", bound="alu", achieved=ach, peak=VALU_PEAK_TOPS, unit="T lane-ops/s",
                     frac=ach / VALU_PEAK_TOPS, traffic=measured_blend_traffic(args),
                     peak_basis="FP32 VALU issue, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane per clock",
-                    pairs_per_launch=P["pairs"] / n_dom, ops_per_pair=BLEND_OPS_PER_PAIR,
+                    pairs_per_launch=P_all["pairs"] / n_dom, ops_per_pair=BLEND_OPS_PER_PAIR,
                     avg_launch_ms=t_dom / n_dom)
     else:
         ach = sb[dom] / n_dom / (t_dom / n_dom * 1e-3) / 1e9
@@ -799,7 +805,7 @@ def main():
         "psnr_vs_full_db_min": float(np.min(psnrs)) if psnrs else None,
         "selected_gaussians_per_s": P["slots"] / wall,
         "mean_keys_per_frame": P["keys"] / max(P["frames"], 1),
-        "mean_pairs_per_frame": P["pairs"] / max(P["frames"], 1),
+        "mean_pairs_per_frame": P_all["pairs"] / max(P_all["frames"], 1),
         "stages": stages,
         "sort_hbm_gbs": (sort_b / (sort_t * 1e-3) / 1e9) if sort_t > 0 else None,
         "extended_tolerances": extended,

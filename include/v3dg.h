@@ -296,7 +296,9 @@ typedef struct {
     uint64_t depth_sorts;              /* frames that sorted slots by depth first     */
     uint64_t pairs;                    /* (pixel, splat) pairs evaluated by blending: for
                                           each splat of a quarter's list, the quarter's
-                                          pixels still compositing when it is reached    */
+                                          pixels still compositing when it is reached.
+                                          Counted only with V3DG_PROFILE_PAIRS (or
+                                          PAIR_AUDIT), else 0                            */
     uint64_t pairs_taken;              /* of those, pairs with alpha >= 1/255 (composited,
                                           or ending the pixel); later chunks of long bin
                                           lists are walked from T = 1 and count pairs a
@@ -323,10 +325,13 @@ int v3dg_set_sort_mode(v3dg_scene *scene, int mode);
  * either way.  v3dg_collect_profile synchronises, fills *out with the totals
  * since the previous collect, and clears them. */
 #define V3DG_PROFILE_ALL 0x7ff
-/* Added to stage_mask: blending also counts the pairs it takes
- * (v3dg_profile.pairs_taken, otherwise 0).  The count costs a few scalar
- * operations per pair on the walk's critical path, so it is off by default. */
+/* Added to stage_mask: blending counts the (pixel, splat) pairs it walks
+ * (v3dg_profile.pairs, otherwise 0); with PAIR_AUDIT also the pairs it takes
+ * (v3dg_profile.pairs_taken).  Counting costs a few scalar operations per
+ * pair on the walk's critical path (about 4 % of the blend stage for pairs),
+ * so both are off by default. */
 #define V3DG_PROFILE_PAIR_AUDIT 0x800
+#define V3DG_PROFILE_PAIRS 0x1000
 int v3dg_set_profiling(v3dg_scene *scene, int stage_mask);
 int v3dg_collect_profile(v3dg_scene *scene, v3dg_profile *out);
 

@@ -36,6 +36,7 @@ PRECISIONS = {"fp32": V3DG_FP32, "fp16_bf16sh": V3DG_FP16_BF16SH, "fp16": V3DG_F
 V3DG_LOAD_REPAIR_NESTING = 1
 V3DG_PROFILE_ALL = 0x7FF
 V3DG_PROFILE_PAIR_AUDIT = 0x800
+V3DG_PROFILE_PAIRS = 0x1000
 V3DG_SORT_DEPTH_FIRST = 0
 V3DG_SORT_KEYS64 = 1
 STAGES = ["setup", "select", "expand", "project", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend",
@@ -509,14 +510,17 @@ class Scene:
     def set_culling(self, on: bool = True):
         v3dg_set_culling(self.handle, on)
 
-    def set_profiling(self, on=True, audit_pairs: bool = False):
-        """True / False, or an iterable of stage names to time; audit_pairs
-        also counts the pairs blending takes (profile "pairs_taken")."""
+    def set_profiling(self, on=True, pairs: bool = False, audit_pairs: bool = False):
+        """True / False, or an iterable of stage names to time; pairs counts
+        the pairs blending walks (profile "pairs"), audit_pairs also those it
+        takes ("pairs_taken")."""
         if on is True or on is False:
             mask = V3DG_PROFILE_ALL if on else 0
         else:
             mask = sum(1 << STAGES.index(s) for s in on)
-        v3dg_set_profiling(self.handle, mask | (V3DG_PROFILE_PAIR_AUDIT if audit_pairs else 0))
+        mask |= V3DG_PROFILE_PAIRS if pairs else 0
+        mask |= V3DG_PROFILE_PAIR_AUDIT if audit_pairs else 0
+        v3dg_set_profiling(self.handle, mask)
 
     def collect_profile(self) -> dict:
         return v3dg_collect_profile(self.handle)

@@ -148,9 +148,10 @@ __device__ __forceinline__ void composite(float p, bool take, float log2o, const
 // once a pixel is known to be active; after that the splat records of the
 // next batch are gathered while the current one is walked, and the index of
 // the batch after that one is read ahead, so no walk waits on global memory.
-// kAudit also counts the pairs taken (a few scalar operations per pair, on
-// the walk's critical path: only when the profile asks for it).
-template <bool kAudit>
+// kCount 1 counts the pairs walked, 2 also the pairs taken (a few scalar
+// operations per pair on the walk's critical path, so only when the profile
+// asks for them; 0 counts nothing).
+template <int kCount>
 __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ splat,
                             const uint32_t *__restrict__ vals, float bx0, float by0, float pxc, float pyc, int wid,
                             int lane, BlendShared &sh, Pix &px)
@@ -240,9 +241,9 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
                     amid = __ballot(act1);
                     composite(p1, act1 && pass1, c1.z, col1, T, cr, cg, cb);
                 }
-                walked += (uint32_t)__popcll(am) + (two ? (uint32_t)__popcll(amid) : 0u);
+                if constexpr (kCount >= 1) walked += (uint32_t)__popcll(am) + (two ? (uint32_t)__popcll(amid) : 0u);
                 // the pass masks are the compares' own lane masks: counted on the scalar unit
-                if constexpr (kAudit)
+                if constexpr (kCount >= 2)
                     taken += (uint32_t)__popcll(am & __ballot(pass0)) + (uint32_t)__popcll(amid & __ballot(pass1));
                 am = __ballot(T > 0.0f);
             }
@@ -303,7 +304,7 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
 // Workgroup b blends tile order[b]: the tiles with the longest first chunks
 // come first, so that their walks do not start last and leave the rest of the
 // chip idle.
-template <bool kAudit>
+template <int kCount>
 __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
@@ -325,7 +326,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
     const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
     const uint32_t cb = cbase[tile];  // kNoChunk: blended whole
     const bool long_list = cb != kNoChunk && end - rg.x > (uint32_t)kChunkFirst;
-    blend_range<kAudit>(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
+    blend_range<kCount>(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
                 px);
     if (long_list) {  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cb * kBlendThreads + g.pix] =
@@ -344,7 +345,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
 // ---------------------------------------------------------------------------
 // pass 2: chunks 1.. of long tiles, in parallel, each from T = 1
 // ---------------------------------------------------------------------------
-template <bool kAudit>
+template <int kCount>
 __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) chunk_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
@@ -371,7 +372,7 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
         const float4 s0 = scratch[base * kBlendThreads + g.pix];
         Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u, 0u};
         const bool was = px.active;
-        blend_range<kAudit>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
+        blend_range<kCount>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
                     g.pyc, wid, lane, sh, px);
         // the fold reads later chunks only for pixels active after chunk 0
         if (was)
@@ -441,7 +442,7 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
 // ---------------------------------------------------------------------------
 // pass 4: walk again, with the stop rule, each chunk that holds a stop
 // ---------------------------------------------------------------------------
-template <bool kAudit>
+template <int kCount>
 __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *__restrict__ fd,
                                                                const float4 *__restrict__ splat,
                                                                const uint32_t *__restrict__ vals,
@@ -467,7 +468,7 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         const bool mine = pend[base * kBlendThreads + g.pix] == c;
         const float4 st = scratch[base * kBlendThreads + g.pix];
         Pix px{fabsf(st.w), st.x, st.y, st.z, mine, 0u, 0u};  // a pixel finished before holds -T
-        blend_range<kAudit>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
+        blend_range<kCount>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
                     g.pyc, wid, lane, sh, px);
         // a pixel that, through rounding of the folded products, does not stop in
         // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
 // staging keep only those whose support can reach it.  The image is the
 // sequential result, only slower to get.
 // ---------------------------------------------------------------------------
-template <bool kAudit>
+template <int kCount>
 __global__ void __launch_bounds__(kBlendThreads) blend_all_kernel(const FrameDev *__restrict__ fd,
                                                                   const float4 *__restrict__ splat,
                                                                   const uint32_t *__restrict__ order,
@@ -500,7 +501,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_all_kernel(const FrameDev
     for (uint32_t tile = blockIdx.x; tile < cam.tiles_x * cam.tiles_y; tile += gridDim.x) {
         const TileGeo g = tile_geo(cam, tile, wid, lane);
         Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u, 0u};
-        blend_range<kAudit>(0, n_vis, splat, order, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        blend_range<kCount>(0, n_vis, splat, order, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
         write_pixel(cam, g, px, image);
         count_pairs(px, wid, lane, pairs);
         __syncthreads();  // the next tile reuses the staged batch
@@ -510,18 +511,18 @@ __global__ void __launch_bounds__(kBlendThreads) blend_all_kernel(const FrameDev
 // launched after every frame sized by capacity: a small grid, since it
 // returns at once unless the frame's keys did not fit
 void launch_blend_all(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
-                      const uint32_t *order, const uint32_t *counters, unsigned long long *pairs, bool audit)
+                      const uint32_t *order, const uint32_t *counters, unsigned long long *pairs, int count)
 {
-    const uint32_t grid = n_tiles < 1024u ? n_tiles : 1024u;
-    if (audit)
-        hipLaunchKernelGGL(blend_all_kernel<true>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order, counters,
-                           pairs);
+    const uint32_t grid = n_tiles < 256u ? n_tiles : 256u;
+    if (count >= 2)
+        hipLaunchKernelGGL(blend_all_kernel<2>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order, counters, pairs);
+    else if (count == 1)
+        hipLaunchKernelGGL(blend_all_kernel<1>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order, counters, pairs);
     else
-        hipLaunchKernelGGL(blend_all_kernel<false>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order,
-                           counters, pairs);
+        hipLaunchKernelGGL(blend_all_kernel<0>, dim3(grid), dim3(kBlendThreads), 0, st, fd, splat, order, counters, pairs);
 }
 
-template <bool kAudit>
+template <int kCount>
 static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
                            const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                            const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
@@ -530,7 +531,7 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
     // beyond kMaxGrid items workgroups loop over further ones: a capacity-sized
     // bound on the items (frames sized without a host wait) launches no more
     constexpr uint64_t kMaxGrid = 16384;
-    hipLaunchKernelGGL(blend_kernel<kAudit>, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+    hipLaunchKernelGGL(blend_kernel<kCount>, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                        order, scratch, need, pairs);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
@@ -538,11 +539,11 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
         // rather than one per chunk of the bound (mostly empty workgroups)
         constexpr uint64_t kRewalkGrid = 2048;
         const uint32_t gc = (uint32_t)(max_chunks < kRewalkGrid ? max_chunks : kRewalkGrid);
-        hipLaunchKernelGGL(chunk_kernel<kAudit>, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+        hipLaunchKernelGGL(chunk_kernel<kCount>, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                            items, counters, scratch, need, pairs);
         hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
                            need, rewalk, counters);
-        hipLaunchKernelGGL(rewalk_kernel<kAudit>, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
+        hipLaunchKernelGGL(rewalk_kernel<kCount>, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                            scratch, pend, rewalk, counters, pairs);
     }
 }
@@ -552,15 +553,18 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                   const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
-                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, bool audit)
+                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, int count)
 {
     const uint32_t n_tiles = tiles_x * tiles_y;
-    if (audit)
-        launch_blend_t<true>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
-                             scratch, pend, need, rewalk, pairs);
+    if (count >= 2)
+        launch_blend_t<2>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
+                          scratch, pend, need, rewalk, pairs);
+    else if (count == 1)
+        launch_blend_t<1>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
+                          scratch, pend, need, rewalk, pairs);
     else
-        launch_blend_t<false>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items,
-                              max_chunks, scratch, pend, need, rewalk, pairs);
+        launch_blend_t<0>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
+                          scratch, pend, need, rewalk, pairs);
 }
 
 }  // namespace v3dg

@@ -191,7 +191,7 @@ struct Ctx {
     int last_buf = 0;
     int sort_mode = V3DG_SORT_DEPTH_FIRST;
     uint32_t profiling = 0;   // stages timed with events (bit per stage)
-    bool audit_pairs = false; // blending also counts the pairs it takes
+    int pair_count = 0;       // pairs blending counts: 0 none, 1 walked, 2 walked and taken
     v3dg_profile acc{};
     unsigned long long *pairs_dev = nullptr;  // walked and taken (pixel, splat) pairs, kPairSlots of each
     std::vector<ProfRec> prof;
@@ -858,11 +858,11 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         Stage st(c, V3DG_STAGE_BLEND);
         launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase,
                      c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks, max_chunks, c->scratch, c->pend,
-                     c->need, c->rewalk, c->pairs_dev, c->audit_pairs);
+                     c->need, c->rewalk, c->pairs_dev, c->pair_count);
         // a frame whose keys did not fit is blended from its depth-sorted slots
         if (pub.fallback && depth_first)
             launch_blend_all(c->stream, c->fdev, n_tiles, c->splat, c->dval[0], c->rcounters, c->pairs_dev,
-                             c->audit_pairs);
+                             c->pair_count);
     }
     HIP_TRY(hipGetLastError());
     fi->key_bits = key_bits;
@@ -1923,10 +1923,10 @@ int v3dg_set_profiling(v3dg_scene *s, int stage_mask)
     g_err.clear();
     if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
     s->profiling = (uint32_t)stage_mask & V3DG_PROFILE_ALL;
-    s->audit_pairs = (stage_mask & V3DG_PROFILE_PAIR_AUDIT) != 0;
+    s->pair_count = (stage_mask & V3DG_PROFILE_PAIR_AUDIT) ? 2 : (stage_mask & V3DG_PROFILE_PAIRS) ? 1 : 0;
     // events for the timed stages are created here rather than inside the
     // frames being timed (creating one costs far more than recording it)
-    if (s->profiling) {
+    if (s->profiling || s->pair_count) {
         HIP_TRY(hipSetDevice(s->device));
         while (s->ev_pool.size() < kEventPoolWarm) {
             hipEvent_t e = nullptr;

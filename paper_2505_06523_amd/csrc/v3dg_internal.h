@@ -329,18 +329,18 @@ void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, in
 // blend.hip
 constexpr uint32_t kPairSlots = 256;  // spread pair counters (see count_pairs)
 // max_items / max_chunks bound the work items and chunks of the plan (grid
-// sizes).  pairs (2 kPairSlots counters) sums the pairs walked in its even
-// entries; with audit, its odd entries also sum the pairs taken (alpha >=
-// 1/255 at an active pixel), which slows the walk.
+// sizes).  pairs (2 kPairSlots counters): with count >= 1 its even entries
+// sum the pairs walked, with count 2 its odd entries also sum the pairs taken
+// (alpha >= 1/255 at an active pixel); counting slows the walk.
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                   const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
-                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, bool audit);
+                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, int count);
 // Frames whose keys exceeded the key buffers (kErrKeyCap): every tile walks
 // the n = counters[kRenVisible] visible slots in depth order (order: the
 // depth-sorted slots) and writes its pixels; other frames return at once.
 void launch_blend_all(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
-                      const uint32_t *order, const uint32_t *counters, unsigned long long *pairs, bool audit);
+                      const uint32_t *order, const uint32_t *counters, unsigned long long *pairs, int count);
 // generic fill
 void launch_fill_u32(hipStream_t st, uint32_t *p, uint64_t n, uint32_t v);
 
