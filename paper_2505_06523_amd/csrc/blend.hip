@@ -26,6 +26,8 @@
 //   blend_kernel  walks chunk 0 of every tile (with the stop rule);
 //   chunk_kernel  walks every other chunk in parallel, each from T = 1,
 //                 giving per pixel the chunk's colour C_c and transmittance T_c;
+//                 a chunk drops the pixels that an earlier chunk of the tile
+//                 has already stopped on its own (see ChunkSkip);
 //   fold_kernel   folds the chunks in order, C += T C_c, T *= T_c.  Running
 //                 transmittance only decreases, so the stopping splat lies in
 //                 the first chunk with T T_c < 1e-4 (or that stopped on its own
@@ -59,6 +61,34 @@ struct Pix {
     uint32_t walked;      // (pixel, splat) pairs walked by the wavefront's active pixels (uniform)
     uint32_t taken;       // of those, pairs with alpha >= 1/255 (composited, or ending the pixel) (uniform)
 };
+
+// Pixels that the chunks of a long tile stopped on their own.  When chunk c'
+// walked from T = 1 stops pixel p, the sequential walk, which reaches c' with
+// T <= 1 and multiplies by the same factors, stops p at or before the same
+// splat, so the fold ends p's walk at a chunk <= c' and never reads p's
+// summary of a later chunk: a later chunk may drop p, at its start or between
+// batches.  Each chunk wavefront publishes the mask of its pixels stopped (or
+// dropped) so far in word 4 (record) + wavefront; the fold clears the words
+// of the records it has read, so every word is zero when a frame's chunks
+// start (the buffer is cleared when it is allocated).  Words are read and written as
+// device-scope atomics and no one waits on them: a mask read early only drops
+// fewer pixels.
+struct ChunkSkip {
+    uint64_t *stopm = nullptr;
+    uint64_t base = 0;  // the tile's first chunk record
+    uint32_t c = 0;     // this chunk
+};
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, o, kWave);
+        hi |= (uint32_t)__shfl_xor((int)hi, o, kWave);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
 
 // Stage one batch entry (the splat record of key i) into LDS with its
 // quarter mask: bit q when the enlarged support {d : d' S^-1 d <= Qm} (S the
@@ -150,17 +180,30 @@ __device__ __forceinline__ void composite(float p, bool take, float log2o, const
 // the batch after that one is read ahead, so no walk waits on global memory.
 // kCount 1 counts the pairs walked, 2 also the pairs taken (a few scalar
 // operations per pair on the walk's critical path, so only when the profile
-// asks for them; 0 counts nothing).
-template <int kCount>
+// asks for them; 0 counts nothing).  kSkip: a later chunk of a long tile,
+// which drops and publishes pixels as ChunkSkip describes.
+template <int kCount, bool kSkip>
 __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ splat,
                             const uint32_t *__restrict__ vals, float bx0, float by0, float pxc, float pyc, int wid,
-                            int lane, BlendShared &sh, Pix &px)
+                            int lane, BlendShared &sh, Pix &px, const ChunkSkip &sk)
 {
     const int tid = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
     float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0, f2 = f0;
     uint32_t vnext = 0;
+    const uint64_t was = __ballot(px.active);
+    uint64_t published = 0;
     for (uint32_t start = b; start < e; start += kBlendThreads) {
+        if constexpr (kSkip) {
+            if (sk.c > 1u && (was & ~published) != 0) {  // uniform
+                uint64_t dead = 0;
+                for (uint32_t j = 1u + (uint32_t)lane; j < sk.c; j += kWave)
+                    dead |= __hip_atomic_load(sk.stopm + (sk.base + j) * 4u + (uint32_t)wid, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                dead = wave_or64(dead);
+                if ((dead >> lane) & 1ull) px.active = false;
+            }
+        }
         // each wavefront notes whether it has an active pixel; the barrier also
         // ends every walk of the previous batch before its records are replaced
         const bool alive = __ballot(px.active) != 0;
@@ -255,6 +298,15 @@ __device__ void blend_range(uint32_t b, uint32_t e, const float4 *__restrict__ s
             px.cg = cg;
             px.cb = cb;
         }
+        if constexpr (kSkip) {
+            const uint64_t stopped = was & ~__ballot(px.active);
+            if (stopped != published) {  // uniform
+                if (lane == 0)
+                    __hip_atomic_store(sk.stopm + (sk.base + sk.c) * 4u + (uint32_t)wid, stopped, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                published = stopped;
+            }
+        }
     }
 }
 
@@ -326,8 +378,8 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
     const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
     const uint32_t cb = cbase[tile];  // kNoChunk: blended whole
     const bool long_list = cb != kNoChunk && end - rg.x > (uint32_t)kChunkFirst;
-    blend_range<kCount>(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh,
-                px);
+    blend_range<kCount, false>(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid,
+                               lane, sh, px, ChunkSkip{});
     if (long_list) {  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cb * kBlendThreads + g.pix] =
             make_float4(px.cr, px.cg, px.cb, px.active ? px.T : -px.T);
@@ -345,40 +397,75 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
 // ---------------------------------------------------------------------------
 // pass 2: chunks 1.. of long tiles, in parallel, each from T = 1
 // ---------------------------------------------------------------------------
+// Workgroup i takes work item i, counting first through the rounds (round r:
+// chunk r of every long tile with one), then through the items of the chunks
+// past the rounds.  Workgroups start in index order, so a later chunk starts
+// after the earlier chunks of its tile and finds more of its pixels stopped
+// by them (ChunkSkip).
 template <int kCount>
-__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) chunk_kernel(const FrameDev *__restrict__ fd,
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(7, 7))) chunk_kernel(const FrameDev *__restrict__ fd,
                                                               const float4 *__restrict__ splat,
                                                               const uint32_t *__restrict__ vals,
                                                               const uint2 *__restrict__ ranges,
                                                               const uint32_t *__restrict__ cbase,
                                                               const uint2 *__restrict__ items,
+                                                              const uint32_t *__restrict__ rounds, uint32_t rcap,
                                                               const uint32_t *__restrict__ counters,
                                                               float4 *__restrict__ scratch,
                                                               const uint32_t *__restrict__ need,
+                                                              uint64_t *__restrict__ stopm,
                                                               unsigned long long *__restrict__ pairs)
 {
+    static_assert(kChunkRounds == kWave, "one wavefront scans the round sizes");
     __shared__ BlendShared sh;
-    const uint32_t n_items = counters[kRenItems];
+    __shared__ uint32_t pre[kChunkRounds];  // inclusive prefix sums of the round sizes
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const CamArgs &cam = fd->cam;
-    // one workgroup per item (the grid covers the bound on items)
-    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const uint2 item = items[it];
-        const uint32_t tile = item.x, c = item.y;
-        const TileGeo g = tile_geo(cam, tile, wid, lane);
-        const uint2 rg = ranges[tile];
+    if (wid == 0) {
+        uint32_t v = counters[kRenRound + lane];
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t n = (uint32_t)__shfl_up((int)v, o, kWave);
+            if (lane >= o) v += n;
+        }
+        pre[lane] = v;
+    }
+    __syncthreads();
+    const uint32_t in_rounds = pre[kChunkRounds - 1], n_items = in_rounds + counters[kRenItems];
+    for (uint32_t t = blockIdx.x; t < n_items; t += gridDim.x) {
+        uint32_t tile, c;
+        if (t < in_rounds) {
+            uint32_t r = 0;  // rounds whose prefix is <= t: t lies in round r + 1
+#pragma unroll
+            for (uint32_t st = kChunkRounds / 2; st > 0; st >>= 1)
+                if (pre[r + st - 1] <= t) r += st;
+            tile = rounds[(uint64_t)r * rcap + (t - (r ? pre[r - 1] : 0u))];
+            c = r + 1u;
+        } else {
+            const uint2 item = items[t - in_rounds];
+            tile = item.x;
+            c = item.y;
+        }
         const uint64_t base = cbase[tile];
-        if (need[base] == 0u) continue;  // every pixel finished in chunk 0 (uniform)
-        const float4 s0 = scratch[base * kBlendThreads + g.pix];
-        Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u, 0u};
-        const bool was = px.active;
-        blend_range<kCount>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
-                    g.pyc, wid, lane, sh, px);
-        // the fold reads later chunks only for pixels active after chunk 0
-        if (was)
-            scratch[(base + c) * kBlendThreads + g.pix] =
-                make_float4(px.cr, px.cg, px.cb, !px.active ? -px.T : px.T);
-        count_pairs(px, wid, lane, pairs);
+        if (need[base] != 0u) {  // else every pixel finished in chunk 0 (uniform)
+            const TileGeo g = tile_geo(cam, tile, wid, lane);
+            const uint2 rg = ranges[tile];
+            const float4 s0 = scratch[base * kBlendThreads + g.pix];
+            Pix px{1.0f, 0.f, 0.f, 0.f, s0.w > 0.0f, 0u, 0u};
+            const bool was = px.active;
+            ChunkSkip sk;
+            sk.stopm = stopm;
+            sk.base = base;
+            sk.c = c;
+            blend_range<kCount, true>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0,
+                                      g.by0, g.pxc, g.pyc, wid, lane, sh, px, sk);
+            // the fold reads later chunks only for pixels active after chunk 0 (a
+            // dropped pixel's summary is never read)
+            if (was)
+                scratch[(base + c) * kBlendThreads + g.pix] =
+                    make_float4(px.cr, px.cg, px.cb, !px.active ? -px.T : px.T);
+            count_pairs(px, wid, lane, pairs);
+        }
         __syncthreads();  // the next item reuses the staged batch
     }
 }
@@ -392,8 +479,8 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
                                                              const uint2 *__restrict__ ranges,
                                                              const uint32_t *__restrict__ cbase,
                                                              float4 *__restrict__ scratch, uint32_t *__restrict__ pend,
-                                                             uint32_t *__restrict__ need, uint2 *__restrict__ rewalk,
-                                                             uint32_t *counters)
+                                                             uint32_t *__restrict__ need, uint64_t *__restrict__ stopm,
+                                                             uint2 *__restrict__ rewalk, uint32_t *counters)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const CamArgs &cam = fd->cam;
@@ -406,6 +493,10 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint64_t base = cbase[tile];
     for (uint32_t c = tid; c < m; c += kBlendThreads) need[base + c] = 0u;
+    // the chunks of this frame are done: clear their stopped-pixel words for
+    // the frames after it (every record a chunk can write was assigned to a
+    // long tile, and every long tile is folded)
+    for (uint32_t w = tid; w < 4u * m; w += kBlendThreads) stopm[4u * base + w] = 0ull;
     __syncthreads();
     const float4 s0 = scratch[base * kBlendThreads + g.pix];
     Pix px{fabsf(s0.w), s0.x, s0.y, s0.z, false, 0u, 0u};
@@ -468,8 +559,8 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         const bool mine = pend[base * kBlendThreads + g.pix] == c;
         const float4 st = scratch[base * kBlendThreads + g.pix];
         Pix px{fabsf(st.w), st.x, st.y, st.z, mine, 0u, 0u};  // a pixel finished before holds -T
-        blend_range<kCount>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0, g.pxc,
-                    g.pyc, wid, lane, sh, px);
+        blend_range<kCount, false>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0,
+                                   g.pxc, g.pyc, wid, lane, sh, px, ChunkSkip{});
         // a pixel that, through rounding of the folded products, does not stop in
         // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
         if (mine) write_pixel(cam, g, px, image);
@@ -501,7 +592,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_all_kernel(const FrameDev
     for (uint32_t tile = blockIdx.x; tile < cam.tiles_x * cam.tiles_y; tile += gridDim.x) {
         const TileGeo g = tile_geo(cam, tile, wid, lane);
         Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u, 0u};
-        blend_range<kCount>(0, n_vis, splat, order, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px);
+        blend_range<kCount, false>(0, n_vis, splat, order, g.bx0, g.by0, g.pxc, g.pyc, wid, lane, sh, px, ChunkSkip{});
         write_pixel(cam, g, px, image);
         count_pairs(px, wid, lane, pairs);
         __syncthreads();  // the next tile reuses the staged batch
@@ -525,8 +616,9 @@ void launch_blend_all(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, cons
 template <int kCount>
 static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles, const float4 *splat,
                            const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
-                           const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks,
-                           float4 *scratch, uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs)
+                           const uint32_t *rounds, uint32_t rcap, const uint32_t *order, uint32_t *counters,
+                           uint64_t max_items, uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need,
+                           uint64_t *stopm, uint2 *rewalk, unsigned long long *pairs)
 {
     // beyond kMaxGrid items workgroups loop over further ones: a capacity-sized
     // bound on the items (frames sized without a host wait) launches no more
@@ -540,9 +632,9 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
         constexpr uint64_t kRewalkGrid = 2048;
         const uint32_t gc = (uint32_t)(max_chunks < kRewalkGrid ? max_chunks : kRewalkGrid);
         hipLaunchKernelGGL(chunk_kernel<kCount>, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
-                           items, counters, scratch, need, pairs);
+                           items, rounds, rcap, counters, scratch, need, stopm, pairs);
         hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
-                           need, rewalk, counters);
+                           need, stopm, rewalk, counters);
         hipLaunchKernelGGL(rewalk_kernel<kCount>, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
                            scratch, pend, rewalk, counters, pairs);
     }
@@ -552,19 +644,20 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
 // capped and loop over the device-side counts)
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
-                  const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
-                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, int count)
+                  const uint32_t *rounds, uint32_t rcap, const uint32_t *order, uint32_t *counters, uint64_t max_items,
+                  uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint64_t *stopm, uint2 *rewalk,
+                  unsigned long long *pairs, int count)
 {
     const uint32_t n_tiles = tiles_x * tiles_y;
     if (count >= 2)
-        launch_blend_t<2>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
-                          scratch, pend, need, rewalk, pairs);
+        launch_blend_t<2>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items, max_chunks,
+                          scratch, pend, need, stopm, rewalk, pairs);
     else if (count == 1)
-        launch_blend_t<1>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
-                          scratch, pend, need, rewalk, pairs);
+        launch_blend_t<1>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items, max_chunks,
+                          scratch, pend, need, stopm, rewalk, pairs);
     else
-        launch_blend_t<0>(st, fd, n_tiles, splat, vals, ranges, cbase, items, order, counters, max_items, max_chunks,
-                          scratch, pend, need, rewalk, pairs);
+        launch_blend_t<0>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items, max_chunks,
+                          scratch, pend, need, stopm, rewalk, pairs);
 }
 
 }  // namespace v3dg

@@ -14,8 +14,8 @@
 namespace v3dg {
 
 constexpr uint32_t kTilesPerBin = 4;        // a bin is a 2 x 2 block of tiles; each tile walks the bin's list
-constexpr int kChunk = 2048;                // keys per chunk of a long bin list after the first
-constexpr int kChunkFirst = 6144;           // keys of the first chunk (walked by pass 1)
+constexpr int kChunk = 1024;                // keys per chunk of a long bin list after the first
+constexpr int kChunkFirst = 3072;           // keys of the first chunk (walked by pass 1)
 constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whole
 static_assert(kChunkFirst >= 2 * kChunk, "the chunk bound needs first chunks of at least two later ones");
 

@@ -180,10 +180,12 @@ struct Ctx {
     uint64_t *sort_status = nullptr;
     uint64_t sort_status_parts = 0;
     uint32_t *cbase = nullptr;     // per tile: first chunk of a long list; then the blend order (tiles_cap each)
-    uint2 *items = nullptr;        // (tile, chunk) work items
+    uint2 *items = nullptr;        // (tile, chunk) work items past the rounds
+    uint32_t *rounds = nullptr;    // per round of chunk work, the long tiles (tiles_cap each)
     float4 *scratch = nullptr;     // per chunk, per pixel (C, T)
     uint32_t *pend = nullptr;      // per long tile, per pixel: chunk to walk again
     uint32_t *need = nullptr;      // per chunk: walk it again
+    uint64_t *stopm = nullptr;     // per chunk, per wavefront: pixels the chunk stopped
     uint2 *rewalk = nullptr;       // (tile, chunk) to walk again
     uint64_t cap_chunks = 0;
     uint32_t *pinned = nullptr;
@@ -523,10 +525,12 @@ void ctx_release(Ctx *c)
     dev_free(c->sort_status);
     dev_free(c->pairs_dev);
     dev_free(c->cbase);
+    dev_free(c->rounds);
     dev_free(c->items);
     dev_free(c->scratch);
     dev_free(c->pend);
     dev_free(c->need);
+    dev_free(c->stopm);
     dev_free(c->rewalk);
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
@@ -593,6 +597,8 @@ int ensure_tiles(Ctx *c, uint32_t n_tiles)
     c->ranges = reinterpret_cast<uint2 *>(c->rclear + kRenCounters + 2 * c->scan_parts);
     dev_free(c->cbase);
     if ((rc = dev_alloc(&c->cbase, 2ull * c->tiles_cap))) return rc;
+    dev_free(c->rounds);
+    if ((rc = dev_alloc(&c->rounds, (uint64_t)kChunkRounds * c->tiles_cap))) return rc;
     return V3DG_OK;
 }
 
@@ -619,6 +625,7 @@ int ensure_chunks(Ctx *c, uint64_t K)
     dev_free(c->scratch);
     dev_free(c->pend);
     dev_free(c->need);
+    dev_free(c->stopm);
     dev_free(c->rewalk);
     const uint64_t cap = need + need / 2;
     int rc;
@@ -626,6 +633,9 @@ int ensure_chunks(Ctx *c, uint64_t K)
     if ((rc = dev_alloc(&c->scratch, cap * 256))) return rc;
     if ((rc = dev_alloc(&c->pend, cap * 256))) return rc;
     if ((rc = dev_alloc(&c->need, cap))) return rc;
+    if ((rc = dev_alloc(&c->stopm, cap * 4))) return rc;
+    // the blend keeps these words zero between frames (see launch_blend)
+    HIP_TRY(hipMemsetAsync(c->stopm, 0, cap * 4 * sizeof(uint64_t), c->stream));
     if ((rc = dev_alloc(&c->rewalk, cap))) return rc;
     c->cap_chunks = cap;
     return V3DG_OK;
@@ -721,8 +731,8 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
     {
         Stage st(c, V3DG_STAGE_RANGES);
         launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, tiles_x, n_tiles, bins_x,
-                               c->ranges, c->cbase, c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks,
-                               pub.sel_counters, pub.rec, pub.seq);
+                               c->ranges, c->cbase, c->items, c->rounds, c->tiles_cap, c->cbase + c->tiles_cap,
+                               c->rcounters, max_chunks, pub.sel_counters, pub.rec, pub.seq);
     }
 }
 
@@ -850,15 +860,16 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         {
             Stage st(c, V3DG_STAGE_RANGES);
             launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, cam.tiles_x,
-                                         n_tiles, cam.bins_x, c->ranges, c->cbase, c->items, c->cbase + c->tiles_cap,
-                                         c->rcounters, max_chunks);
+                                         n_tiles, cam.bins_x, c->ranges, c->cbase, c->items, c->rounds,
+                                         c->tiles_cap, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
         }
     }
     {
         Stage st(c, V3DG_STAGE_BLEND);
         launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase,
-                     c->items, c->cbase + c->tiles_cap, c->rcounters, max_chunks, max_chunks, c->scratch, c->pend,
-                     c->need, c->rewalk, c->pairs_dev, c->pair_count);
+                     c->items, c->rounds, c->tiles_cap, c->cbase + c->tiles_cap, c->rcounters, max_chunks, max_chunks,
+                     c->scratch, c->pend,
+                     c->need, c->stopm, c->rewalk, c->pairs_dev, c->pair_count);
         // a frame whose keys did not fit is blended from its depth-sorted slots
         if (pub.fallback && depth_first)
             launch_blend_all(c->stream, c->fdev, n_tiles, c->splat, c->dval[0], c->rcounters, c->pairs_dev,
@@ -2086,9 +2097,9 @@ uint64_t ctx_bytes(const SrvCtx *c)
 {
     uint64_t b = c->ws_slots * (48 + 32 + 4 + 8 + 4 + 4 + 16);
     b += (uint64_t)c->itab_cap * sizeof(InstRec) + sizeof(FrameDev) + 8;
-    b += c->rclear_words * 4 + (uint64_t)c->tiles_cap * 8;
+    b += c->rclear_words * 4 + (uint64_t)c->tiles_cap * (8 + 4 * kChunkRounds);
     b += c->cap_keys * 24 + c->sort_status_parts * kRadix * 8;
-    b += c->cap_chunks * (8 + 256 * 16 + 256 * 4 + 4 + 8);
+    b += c->cap_chunks * (8 + 256 * 16 + 256 * 4 + 4 + 32 + 8);
     b += c->sel.cap_tests * 8 + ((uint64_t)kSelCounters + 2 * c->sel.n_parts) * 4 + c->sel.cap_slots * 8;
     return b;
 }
@@ -2109,9 +2120,9 @@ uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
     const uint64_t K2 = std::max(K, keys);
     g += (K2 - keys) * 24 + ((K2 - keys + kSortPart - 1) / kSortPart) * 3 / 2 * kRadix * 8;
     const uint64_t T2 = std::max<uint64_t>(std::max<uint64_t>(n_tiles, 8160), tiles);
-    g += (T2 - tiles) * 16;
+    g += (T2 - tiles) * (16 + 4 * kChunkRounds);
     const uint64_t ch = chunk_bound(K2);
-    if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 8);
+    if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 32 + 8);
     return g;
 }
 

@@ -876,6 +876,7 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
                                                           int shift, uint32_t tiles_x, uint32_t n_tiles, uint32_t bins_x,
                                                           uint2 *__restrict__ ranges,
                                                           uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
+                                                          uint32_t *__restrict__ rounds, uint32_t rcap,
                                                           uint32_t *__restrict__ order, uint32_t *counters,
                                                           uint32_t max_chunks, const uint32_t *__restrict__ sel_counters,
                                                           FrameRec *rec, uint32_t seq)
@@ -910,12 +911,25 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
     const uint32_t first = __shfl(m_base, kWave - 1, kWave) + m_incl - m;
     const bool ok = plan_fits(first, m, max_chunks);
     if (in) cbase[t] = ok ? first : kNoChunk;
-    const uint32_t it = ok ? m - 1 : 0u;
+    // work items: chunk r of every long tile in round r (r <= kChunkRounds);
+    // the workgroup counts its tiles per round in LDS, takes one range per
+    // round with one atomic, and lists them in a second pass
+    __shared__ uint32_t rcount[kChunkRounds], rnext[kChunkRounds], rbase[kChunkRounds];
+    const uint32_t nr = ok ? min(m - 1u, (uint32_t)kChunkRounds) : 0u;
+    if (threadIdx.x < kChunkRounds) rcount[threadIdx.x] = rnext[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t r = 0; r < nr; ++r) atomicAdd(&rcount[r], 1u);
+    __syncthreads();
+    if (threadIdx.x < kChunkRounds && rcount[threadIdx.x])
+        rbase[threadIdx.x] = atomicAdd(&counters[kRenRound + threadIdx.x], rcount[threadIdx.x]);
+    __syncthreads();
+    for (uint32_t r = 0; r < nr; ++r) rounds[(uint64_t)r * rcap + rbase[r] + atomicAdd(&rnext[r], 1u)] = t;
+    const uint32_t it = ok && m - 1u > (uint32_t)kChunkRounds ? m - 1u - (uint32_t)kChunkRounds : 0u;
     const uint32_t it_incl = wave_incl_scan_u32(it);
     uint32_t it_base = 0;
     if (lane == kWave - 1 && it_incl) it_base = atomicAdd(&counters[kRenItems], it_incl);
     const uint32_t it_first = __shfl(it_base, kWave - 1, kWave) + it_incl - it;
-    for (uint32_t c = 1; c <= it; ++c) items[it_first + c - 1] = make_uint2(t, c);
+    for (uint32_t j = 0; j < it; ++j) items[it_first + j] = make_uint2(t, (uint32_t)kChunkRounds + 1u + j);
     // blend order: full first chunks at the front, the rest from the back
     const bool heavy = in && L >= (uint32_t)kChunkFirst;
     const uint64_t hb = __ballot(heavy), lb = __ballot(in && !heavy);
@@ -933,11 +947,11 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
 template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t tiles_x,
                         uint32_t n_tiles, uint32_t bins_x, uint2 *ranges, uint32_t *cbase, uint2 *items,
-                        uint32_t *order, uint32_t *counters, uint64_t max_chunks, const uint32_t *sel_counters,
-                        FrameRec *rec, uint32_t seq)
+                        uint32_t *rounds, uint32_t rcap, uint32_t *order, uint32_t *counters, uint64_t max_chunks,
+                        const uint32_t *sel_counters, FrameRec *rec, uint32_t seq)
 {
     hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, n_dev, shift,
-                       tiles_x, n_tiles, bins_x, ranges, cbase, items, order, counters,
+                       tiles_x, n_tiles, bins_x, ranges, cbase, items, rounds, rcap, order, counters,
                        (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull), sel_counters, rec, seq);
 }
 
@@ -962,13 +976,13 @@ template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const ui
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
 template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint32_t,
-                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
-                                          const uint32_t *, FrameRec *, uint32_t);
+                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
+                                          uint32_t *, uint64_t, const uint32_t *, FrameRec *, uint32_t);
 template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint32_t,
-                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
-                                          const uint32_t *, FrameRec *, uint32_t);
+                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
+                                          uint32_t *, uint64_t, const uint32_t *, FrameRec *, uint32_t);
 template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint32_t,
-                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t *, uint64_t,
-                                          const uint32_t *, FrameRec *, uint32_t);
+                                          uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
+                                          uint32_t *, uint64_t, const uint32_t *, FrameRec *, uint32_t);
 
 }  // namespace v3dg

@@ -100,8 +100,14 @@ enum RenderCounter : int {
     kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
     kRenKeysEff = 32 + 12 * 256,   // keys the frame's buffers hold: min(total, capacity)
     kRenBig = 32 + 12 * 256 + 1,   // splats left to the large-splat emission
-    kRenCounters = 32 + 12 * 256 + 32
+    kRenRound = 32 + 12 * 256 + 32,       // kChunkRounds counters: long tiles in round r + 1
+    kRenCounters = 32 + 12 * 256 + 32 + 64
 };
+// Chunks 1 .. kChunkRounds of the long lists are handed out round by round
+// (every long tile's chunk 1, then every chunk 2, ...); later chunks after
+// them, tile by tile.
+constexpr int kChunkRounds = 64;
+static_assert(kRenRound + kChunkRounds <= kRenCounters, "round counters out of range");
 
 // Error flag bits
 constexpr uint32_t kErrSpin = 1u;       // a bounded look-back wait expired
@@ -324,18 +330,21 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
 template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t tiles_x,
                         uint32_t n_tiles, uint32_t bins_x, uint2 *ranges, uint32_t *cbase, uint2 *items,
-                        uint32_t *order, uint32_t *counters, uint64_t max_chunks,
+                        uint32_t *rounds, uint32_t rcap, uint32_t *order, uint32_t *counters, uint64_t max_chunks,
                         const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr, uint32_t seq = 0);
 // blend.hip
 constexpr uint32_t kPairSlots = 256;  // spread pair counters (see count_pairs)
 // max_items / max_chunks bound the work items and chunks of the plan (grid
-// sizes).  pairs (2 kPairSlots counters): with count >= 1 its even entries
+// sizes).  rounds (kChunkRounds lists of rcap tiles) and items hold the work
+// items as the range kernel lists them; stopm holds 4 words per chunk record
+// (the later chunks' stopped pixels), zero on entry and left zero.  pairs (2 kPairSlots counters): with count >= 1 its even entries
 // sum the pairs walked, with count 2 its odd entries also sum the pairs taken
 // (alpha >= 1/255 at an active pixel); counting slows the walk.
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
-                  const uint32_t *order, uint32_t *counters, uint64_t max_items, uint64_t max_chunks, float4 *scratch,
-                  uint32_t *pend, uint32_t *need, uint2 *rewalk, unsigned long long *pairs, int count);
+                  const uint32_t *rounds, uint32_t rcap, const uint32_t *order, uint32_t *counters, uint64_t max_items,
+                  uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint64_t *stopm, uint2 *rewalk,
+                  unsigned long long *pairs, int count);
 // Frames whose keys exceeded the key buffers (kErrKeyCap): every tile walks
 // the n = counters[kRenVisible] visible slots in depth order (order: the
 // depth-sorted slots) and writes its pixels; other frames return at once.

@@ -166,3 +166,15 @@ def bundle_asset(b: dict, sh_degree: int) -> sg.Asset:
                     count=b["count"], level=b["level"], parent=b["parent"], first_child=b["first_child"],
                     n_children=b["n_children"], self_sphere=b["self_sphere"], parent_sphere=b["parent_sphere"],
                     n_leaf_clusters=int(b["n_leaf_clusters"]))
+
+
+def blend_chunk_sizes() -> tuple[int, int]:
+    """(first, later) chunk sizes in keys of the long-list blending, as the
+    library's plan header defines them."""
+    import os
+    import re
+    h = open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "paper_2505_06523_amd", "csrc",
+                          "blend_plan.h")).read()
+    first = int(re.search(r"constexpr int kChunkFirst = (\d+);", h).group(1))
+    later = int(re.search(r"constexpr int kChunk = (\d+);", h).group(1))
+    return first, later

@@ -284,7 +284,8 @@ def test_long_tile_lists_chunked_blending(torch, opacity, seed):
     keys, _ = sc.sorted_keys()
     per_tile = np.bincount((keys >> np.uint64(32)).astype(np.int64))
     _say("long lists: keys %d, longest tile list %d" % (st["n_keys"], per_tile.max()))
-    assert per_tile.max() > 6144 + 4 * 2048  # a first chunk of 6144 keys and at least five more of 2048
+    first, later = H.blend_chunk_sizes()
+    assert per_tile.max() > first + 4 * later  # a first chunk and at least five more
     ref, amb, _ = oracle.render(a, T, cam, sel.ids())
     check_image(img, ref, amb, "stacked o=%s" % (opacity,))
     sc.set_sort_mode(v.V3DG_SORT_KEYS64)
@@ -521,12 +522,13 @@ def test_blend_pair_counts_against_the_oracle(c1, torch):
     a, sc = c1
     cam = sg.single_camera_c1()
     T = sg.identity_instances(1)
-    for tau in (1.0, 16.0, 256.0, 3000.0):  # the finest cut whose bin lists fit one chunk
+    first, _ = H.blend_chunk_sizes()
+    for tau in (1.0, 16.0, 64.0, 256.0, 3000.0):  # the finest cut whose bin lists fit one chunk
         sel = sc.select(cam, tau)
         sc.render(cam, sel)
         keys, _ = sc.sorted_keys()
         longest = int(np.bincount((keys >> np.uint64(32)).astype(np.int64)).max())
-        if longest <= 6144:
+        if longest <= first:
             break
     sc.collect_profile()
     sc.render(cam, sel)
@@ -539,7 +541,7 @@ def test_blend_pair_counts_against_the_oracle(c1, torch):
     _say("pairs at tolerance %g: evaluated %d, contributing %d; oracle contributing %d (bucket walk %d); ambiguous "
          "pixels %d; longest bin list %d" % (tau, P["pairs"], P["pairs_taken"], st["n_hits"], st["n_pairs"],
                                             int(amb.sum()), longest))
-    assert longest <= 6144
+    assert longest <= first
     assert P["pairs"] >= P["pairs_taken"] > 0
     assert abs(P["pairs_taken"] - st["n_hits"]) <= 1e-4 * st["n_hits"] + 20 * int(amb.sum())
 

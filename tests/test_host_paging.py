@@ -219,3 +219,10 @@ def test_blend_plan_bounds(tmp_path):
                     exe], check=True)
     out = subprocess.run([exe, "1500"], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0 and out.stdout.strip() == "ok 1500", out.stdout + out.stderr
+
+
+def test_chunk_sizes_read_from_the_plan_header():
+    """The GPU tests size their long lists from the plan header's chunk sizes."""
+    from tests import helpers as H
+    first, later = H.blend_chunk_sizes()
+    assert later > 0 and first >= 2 * later
