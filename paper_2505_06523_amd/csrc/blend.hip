@@ -502,16 +502,25 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
     Pix px{fabsf(s0.w), s0.x, s0.y, s0.z, false, 0u, 0u};
     uint32_t pending = kNone;
     if (s0.w > 0.0f) {
-        for (uint32_t c = 1; c < m; ++c) {
-            const float4 sc = scratch[(base + c) * kBlendThreads + g.pix];
-            if (sc.w < 0.0f || px.T * sc.w < 1e-4f) {
-                pending = c;
-                break;
+        // four summaries loaded at a time (those past the stop are never used)
+        constexpr uint32_t kAhead = 4;
+        for (uint32_t c0 = 1; c0 < m && pending == kNone; c0 += kAhead) {
+            float4 sc[kAhead];
+#pragma unroll
+            for (uint32_t k = 0; k < kAhead; ++k)
+                sc[k] = c0 + k < m ? scratch[(base + c0 + k) * kBlendThreads + g.pix] : make_float4(0.f, 0.f, 0.f, 1.f);
+#pragma unroll
+            for (uint32_t k = 0; k < kAhead; ++k) {
+                if (pending != kNone || c0 + k >= m) break;
+                if (sc[k].w < 0.0f || px.T * sc[k].w < 1e-4f) {
+                    pending = c0 + k;
+                    break;
+                }
+                px.cr = fmaf(px.T, sc[k].x, px.cr);
+                px.cg = fmaf(px.T, sc[k].y, px.cg);
+                px.cb = fmaf(px.T, sc[k].z, px.cb);
+                px.T *= sc[k].w;
             }
-            px.cr = fmaf(px.T, sc.x, px.cr);
-            px.cg = fmaf(px.T, sc.y, px.cg);
-            px.cb = fmaf(px.T, sc.z, px.cb);
-            px.T *= sc.w;
         }
     }
     if (pending == kNone) {

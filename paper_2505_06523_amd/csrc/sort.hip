@@ -911,19 +911,27 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
     const uint32_t first = __shfl(m_base, kWave - 1, kWave) + m_incl - m;
     const bool ok = plan_fits(first, m, max_chunks);
     if (in) cbase[t] = ok ? first : kNoChunk;
-    // work items: chunk r of every long tile in round r (r <= kChunkRounds);
-    // the workgroup counts its tiles per round in LDS, takes one range per
-    // round with one atomic, and lists them in a second pass
-    __shared__ uint32_t rcount[kChunkRounds], rnext[kChunkRounds], rbase[kChunkRounds];
+    // work items: chunk r of every long tile in round r (r <= kChunkRounds).
+    // The workgroup orders its long tiles by their number of rounds nr,
+    // largest first (a counting sort in LDS): the tiles of round r are then
+    // its first cnt_r tiles, cnt_r = #{nr >= r}, so a tile has one position
+    // for all its rounds, and each round takes one range with one atomic.
+    static_assert(kChunkRounds == kWave, "one wavefront scans the round counts");
+    __shared__ uint32_t hcnt[kChunkRounds + 1], hstart[kChunkRounds + 1], rbase[kChunkRounds];
     const uint32_t nr = ok ? min(m - 1u, (uint32_t)kChunkRounds) : 0u;
-    if (threadIdx.x < kChunkRounds) rcount[threadIdx.x] = rnext[threadIdx.x] = 0u;
+    if (threadIdx.x <= kChunkRounds) hcnt[threadIdx.x] = 0u;
     __syncthreads();
-    for (uint32_t r = 0; r < nr; ++r) atomicAdd(&rcount[r], 1u);
+    const uint32_t rank = nr ? atomicAdd(&hcnt[nr], 1u) : 0u;
     __syncthreads();
-    if (threadIdx.x < kChunkRounds && rcount[threadIdx.x])
-        rbase[threadIdx.x] = atomicAdd(&counters[kRenRound + threadIdx.x], rcount[threadIdx.x]);
+    if (threadIdx.x < kWave) {  // lane l takes nr = kChunkRounds - l: suffix counts as a prefix scan
+        const uint32_t k = (uint32_t)kChunkRounds - (uint32_t)lane;
+        const uint32_t v = hcnt[k], cnt = wave_incl_scan_u32(v);  // cnt = #{nr >= k}
+        hstart[k] = cnt - v;
+        if (cnt) rbase[k - 1] = atomicAdd(&counters[kRenRound + k - 1], cnt);
+    }
     __syncthreads();
-    for (uint32_t r = 0; r < nr; ++r) rounds[(uint64_t)r * rcap + rbase[r] + atomicAdd(&rnext[r], 1u)] = t;
+    const uint32_t pos = nr ? hstart[nr] + rank : 0u;
+    for (uint32_t r = 0; r < nr; ++r) rounds[(uint64_t)r * rcap + rbase[r] + pos] = t;
     const uint32_t it = ok && m - 1u > (uint32_t)kChunkRounds ? m - 1u - (uint32_t)kChunkRounds : 0u;
     const uint32_t it_incl = wave_incl_scan_u32(it);
     uint32_t it_base = 0;
