@@ -8,7 +8,17 @@ seeded orbits (distance 0.5-20, elevations 15-75 deg), tolerances
 compaction + slot expansion) and rendering (projection, tile binning, radix
 sort, blending) of one (camera, tolerance).  The same frames are then rendered
 at full detail (every leaf, no selection) for the comparison the metric asks
-for.  Prints one JSON line on stdout.
+for.
+
+Two ways of issuing the frames are timed.  The headline value is the serving
+loop (v3dg_server) with SERVE_CONTEXTS render contexts: frames in flight, each
+on its own context and stream, so that one frame's sorts and scans run beside
+another's blending.  The single-stream pass issues v3dg_select +
+v3dg_render frame after frame on one stream; it gives the per-frame times
+(p50/p99), the per-stage breakdown and the blend roofline, whose kernel
+durations are then not shared with another frame.  Both run the same kernels
+on the same frames and give the same images bit for bit.  Prints one JSON
+line on stdout.
 """
 from __future__ import annotations
 
@@ -22,7 +32,12 @@ import time
 METRIC = "FPS at 1080p, V3DG-selected vs full-detail on same GPU; p50/p99 frame ms"
 WORKLOAD = ("1,048,576-leaf SH3 asset (1,398,080 rows, 21,845 clusters), 1920x1080, fov_x pi/4, FP32; "
             "the first %d frames of the sequence over 64 orbit cameras x tolerance {0,1,4,16} px^2 "
-            "(frame i: camera i mod 64, tolerance number (i + i div 64) mod 4)")
+            "(frame i: camera i mod 64, tolerance number (i + i div 64) mod 4), "
+            "issued through the serving loop with %d frames in flight")
+# render contexts (frames in flight) of the headline pass through v3dg_server,
+# and requests handed to it at once (so that a poll always finds queued work)
+SERVE_CONTEXTS = 3
+SERVE_OUTSTANDING = 4 * SERVE_CONTEXTS
 HBM_PEAK_GBS = 8000.0
 # Blending is plain FP32 VALU work (no contraction for matrix cores, no pairs
 # of identical independent ops for packed math), so its ceiling is the VALU
@@ -190,6 +205,53 @@ def run_frames(torch, scene, frames, img, full: bool, prof, pairs: bool = False)
     P = scene.collect_profile()
     ms = [a.elapsed_time(b) for a, b in ev]
     return t1 - t0, ms, P, sel
+
+
+def served_frames(torch, v, scene, frames, full: bool, warm: int):
+    """The frames through a v3dg_server over this one scene, SERVE_CONTEXTS
+    contexts, at most SERVE_OUTSTANDING requests handed over at once, each
+    into its own image.  Returns the wall time of the timed frames, their
+    latencies (submit to completion seen by poll, host clock, ms) and the
+    server's counters.  The first `warm` frames (every context's first frame
+    and graph capture) and then the frames themselves run once before the
+    clock starts."""
+    # key capacity provisioned at 48 keys per pixel, as the scene path holds
+    # it: no context grows (a synchronising reallocation and a graph
+    # recapture) inside the timed frames
+    srv = v.Server([scene], n_contexts=SERVE_CONTEXTS, max_batch=16, hbm_budget_bytes=96 << 30, use_graphs=True,
+                   keys_per_pixel=48)
+    bufs = [torch.empty((f.height, f.width, 4), dtype=torch.float32, device="cuda")
+            for f in [frames[0][0]] * SERVE_OUTSTANDING]
+
+    def issue(seq):
+        free, live, lat, k, done = list(range(len(bufs))), {}, [], 0, 0
+        while done < len(seq):
+            while k < len(seq) and free:
+                b = free.pop()
+                cam, tau = seq[k]
+                t, _ = srv.submit(0, cam, tau, bufs[b], full=full)
+                live[t] = b
+                k += 1
+            for r in srv.poll(wait=True):
+                if r["status"] != 0:
+                    raise RuntimeError("served frame failed with %d" % r["status"])
+                free.append(live.pop(r["ticket"]))
+                lat.append(r["done_ms"] - r["submit_ms"])
+                done += 1
+        return lat
+
+    issue(frames[:warm] if warm > 0 else frames[:1])
+    issue(frames)  # every context has rendered frames of the sequence's key counts
+    torch.cuda.synchronize()
+    st0 = srv.stats()
+    t0 = time.perf_counter()
+    lat = issue(frames)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return wall, lat, {k: st[k] - st0[k] for k in ("retries", "batches", "batched_requests", "graph_launches",
+                                                   "graph_captures")}
 
 
 SERVING_RUNS = [  # (label, arrival rate req/s (0: all at once), requests, graph replay)
@@ -564,6 +626,17 @@ def stream_bench(torch, v, sg, asset):
 
 def main():
     args = parse()
+    # Every render context of the serving loop issues its frames on a stream
+    # of its own.  HIP spreads a process's streams over GPU_MAX_HW_QUEUES
+    # hardware queues (4 by default), and two contexts whose streams share a
+    # queue do not overlap; the serving measurements use up to 8 contexts plus
+    # the selection stream and the scenes' streams.  Raised (never lowered)
+    # before HIP starts.
+    try:
+        hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+    except ValueError:
+        hwq = 0
+    os.environ["GPU_MAX_HW_QUEUES"] = str(max(hwq, 12))
     if args.gpus != 1:
         print("bench.py measures one GPU: the per-frame path runs on a single MI355X "
               "(frames and requests shard across GPUs by routing whole frames; not built here). "
@@ -635,16 +708,27 @@ def main():
         P_all = P
     else:  # the same frames again, every stage timed and the blend pairs counted
         _, _, P_all, _ = run_frames(torch, scene, seq[:K], img, full=False, prof=True, pairs=True)
-    fps = K / wall
+    fps_single = K / wall
+    fps, lat, srv_ctr = fps_single, [], {}
+    if not args.profile_run:
+        # the headline: the same frames with frames in flight (every context
+        # takes its first frames and graph captures in the warm-up)
+        warm_s = max(args.warmup, 2 * SERVE_CONTEXTS)
+        log("timing %d V3DG frames through the serving loop (%d contexts)" % (K, SERVE_CONTEXTS))
+        wall_s, lat, srv_ctr = served_frames(torch, v, scene, seq[:K], False, warm_s)
+        fps = K / wall_s
     if args.profile_run:
         args.no_cpu = True
         args.no_extended = True
         wall_f, ms_f = float("nan"), []
-        fps_full = float("nan")
+        fps_full = fps_full_single = float("nan")
+        lat_f = []
     else:
         log("timing %d full-detail frames" % K)
         wall_f, ms_f, P_f, _ = run_frames(torch, scene, seq[:K], img, full=True, prof=timed_prof)
-        fps_full = K / wall_f
+        fps_full_single = K / wall_f
+        wall_fs, lat_f, _ = served_frames(torch, v, scene, seq[:K], True, max(args.warmup, 2 * SERVE_CONTEXTS))
+        fps_full = K / wall_fs
 
     # quality and LOD factor against full detail on a subset of the frames
     psnrs, factors = [], []
@@ -662,7 +746,7 @@ def main():
 
     extended = {}
     if not args.no_extended:
-        extended = tau_sweep(torch, scene, cams, [64.0, 256.0, 1024.0, 4096.0], img, img2, fps_full)
+        extended = tau_sweep(torch, scene, cams, [64.0, 256.0, 1024.0, 4096.0], img, img2, fps_full_single)
 
     # the same leaves built into a bundle by the paper's Algorithm 1 on the GPU
     # (halving with 2^(1/6) scale growth instead of the generator's merges),
@@ -786,24 +870,37 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": wall / K * 1e3,
+        "ms_per_step": 1e3 / fps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (WORKLOAD % K) if not args.quick else "quick: 65,536-leaf asset", "width": 1920,
+        "config": {"workload": ((WORKLOAD % (K, SERVE_CONTEXTS)) if not args.profile_run else
+                                (WORKLOAD % (K, 1)).replace("serving loop with 1 frames in flight",
+                                                            "single stream (profiled pass)"))
+                   if not args.quick else "quick: 65,536-leaf asset", "width": 1920,
                    "height": 1080, "tolerances_px2": sorted({t for _, t in seq[:K]}),
-                   "cameras": len({id(c) for c, _ in seq[:K]}), "frames": K},
+                   "cameras": len({id(c) for c, _ in seq[:K]}), "frames": K,
+                   "frames_in_flight": SERVE_CONTEXTS if not args.profile_run else 1},
+        # per-frame time of the frames issued one at a time on one stream
         "p50_ms": pct(ms, 50),
         "p99_ms": pct(ms, 99),
         "full_detail_fps": fps_full,
         "full_detail_p50_ms": pct(ms_f, 50),
         "full_detail_p99_ms": pct(ms_f, 99),
         "speedup_vs_full": fps / fps_full,
+        "single_stream": dict(fps=fps_single, ms_per_frame=wall / K * 1e3, full_detail_fps=fps_full_single if
+                              not args.profile_run else None, speedup_vs_full=(fps_single / fps_full_single) if
+                              not args.profile_run else None),
+        "serving_loop": dict(contexts=SERVE_CONTEXTS, outstanding=SERVE_OUTSTANDING,
+                             latency_p50_ms=pct(lat, 50) if lat else None,
+                             latency_p99_ms=pct(lat, 99) if lat else None,
+                             full_detail_latency_p50_ms=pct(lat_f, 50) if lat_f else None,
+                             **srv_ctr) if lat else None,
         "allowed_factor_mean": float(np.mean(factors)) if factors else None,
         "psnr_vs_full_db_min": float(np.min(psnrs)) if psnrs else None,
-        "selected_gaussians_per_s": P["slots"] / wall,
+        "selected_gaussians_per_s": P["slots"] / K * fps,
         "mean_keys_per_frame": P["keys"] / max(P["frames"], 1),
         "mean_pairs_per_frame": P_all["pairs"] / max(P_all["frames"], 1),
         "stages": stages,

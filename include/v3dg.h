@@ -415,6 +415,14 @@ int v3dg_server_create(v3dg_scene *const *scenes, uint32_t n_scenes, const v3dg_
 int v3dg_server_submit(v3dg_server *srv, uint32_t scene, const v3dg_camera *cam, float tau, float *image_dev,
                        uint64_t *ticket);
 
+/* Queue a full-detail request: every leaf of scene `scene`, no selection
+ * (v3dg_render_full through the serving loop; the paper's comparison with
+ * vanilla 3DGS, Sec. 5).  The first such request of a scene builds the
+ * scene's list of leaves (one synchronisation of the scene's stream).  Same
+ * image contract and errors as v3dg_server_submit. */
+int v3dg_server_submit_full(v3dg_server *srv, uint32_t scene, const v3dg_camera *cam, float *image_dev,
+                            uint64_t *ticket);
+
 /* Retire finished frames (up to cap records into done[], count in *n_done),
  * then admit and launch queued requests.  wait != 0 blocks until at least one
  * frame has finished when any is in flight; it needs cap >= 1

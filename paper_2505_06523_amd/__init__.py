@@ -111,7 +111,7 @@ EXPORTS = [
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
     "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
     "v3dg_sort_pairs_noalloc", "v3dg_last_error",
-    "v3dg_server_create", "v3dg_server_submit", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
+    "v3dg_server_create", "v3dg_server_submit", "v3dg_server_submit_full", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
     "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_fit_loss", "v3dg_bundle_free", "v3dg_local_splat",
 ]
 
@@ -154,6 +154,7 @@ def lib():
         "v3dg_last_error": ([], C.c_char_p),
         "v3dg_server_create": ([P, U32, P, P], I),
         "v3dg_server_submit": ([P, U32, P, C.c_float, P, P], I),
+        "v3dg_server_submit_full": ([P, U32, P, P, P], I),
         "v3dg_server_poll": ([P, I, P, U32, P], I),
         "v3dg_server_get_stats": ([P, P], I),
         "v3dg_server_free": ([P], None),
@@ -336,6 +337,12 @@ def v3dg_server_create(scene_handles, cfg: v3dg_server_config):
 def v3dg_server_submit(srv, scene: int, cam: v3dg_camera, tau: float, image_ptr) -> int:
     t = C.c_uint64()
     _check(lib().v3dg_server_submit(srv, int(scene), C.byref(cam), float(tau), image_ptr, C.byref(t)))
+    return t.value
+
+
+def v3dg_server_submit_full(srv, scene: int, cam: v3dg_camera, image_ptr) -> int:
+    t = C.c_uint64()
+    _check(lib().v3dg_server_submit_full(srv, int(scene), C.byref(cam), image_ptr, C.byref(t)))
     return t.value
 
 
@@ -645,14 +652,18 @@ class Server:
         self.handle = v3dg_server_create([sc.handle for sc in self.scenes], cfg)
         self.outputs = {}
 
-    def submit(self, scene: int, cam, tau: float, out=None):
+    def submit(self, scene: int, cam, tau: float, out=None, full: bool = False):
+        """full: every leaf, no selection (tau is ignored)."""
         torch = _torch()
         if out is None:
             out = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device="cuda")
         if (not out.is_cuda or out.dtype != torch.float32 or not out.is_contiguous()
                 or tuple(out.shape) != (int(cam.height), int(cam.width), 4)):
             raise ValueError("image must be a contiguous float32 CUDA tensor of shape (H, W, 4)")
-        t = v3dg_server_submit(self.handle, scene, make_camera(cam), tau, C.c_void_p(out.data_ptr()))
+        if full:
+            t = v3dg_server_submit_full(self.handle, scene, make_camera(cam), C.c_void_p(out.data_ptr()))
+        else:
+            t = v3dg_server_submit(self.handle, scene, make_camera(cam), tau, C.c_void_p(out.data_ptr()))
         self.outputs[t] = out
         return t, out
 

@@ -2045,9 +2045,10 @@ struct SrvReq {
     float *image = nullptr;
     double submit_ms = 0.0, admit_ms = 0.0;
     uint32_t retries = 0;
+    bool full = false;  // every leaf, no selection (v3dg_server_submit_full)
 };
 
-using ShapeKey = std::tuple<uint32_t, uint32_t, uint32_t>;  // scene, width, height
+using ShapeKey = std::tuple<uint32_t, uint32_t, uint32_t, bool>;  // scene, width, height, full detail
 
 struct SrvCtx : Ctx {
     v3dg_selection sel;                 // selection buffers for the largest scene
@@ -2216,10 +2217,13 @@ int srv_launch(v3dg_server *s, SrvCtx *c, hipEvent_t sel_done)
 {
     v3dg_scene *sc = s->scenes[c->req.scene];
     const CamArgs &cam = c->req.cam;
-    const SelView sv{c->sel.counters, c->sel.slot_row, c->sel.slot_inst};
+    // a full-detail request renders the scene's own list of every leaf (built
+    // at submit, read-only, shared by the contexts)
+    const v3dg_selection *src = c->req.full ? sc->full : &c->sel;
+    const SelView sv{src->counters, src->slot_row, src->slot_inst};
     hipGraphExec_t exec = nullptr;
     if (s->cfg.use_graphs) {
-        const ShapeKey key{c->req.scene, cam.width, cam.height};
+        const ShapeKey key{c->req.scene, cam.width, cam.height, c->req.full};
         auto it = c->graphs.find(key);
         if (it != c->graphs.end() && it->second.second == c->generation) {
             exec = it->second.first;
@@ -2253,7 +2257,7 @@ int srv_launch(v3dg_server *s, SrvCtx *c, hipEvent_t sel_done)
         if (rc) return rc;
     }
     HIP_TRY(hipMemcpyAsync(c->pinned, c->rcounters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->pinned + 8, c->sel.counters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->pinned + 8, src->counters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipEventRecord(c->done, c->stream));
     c->busy = true;
     return V3DG_OK;
@@ -2267,14 +2271,15 @@ int srv_dispatch(v3dg_server *s, const std::vector<SrvCtx *> &batch)
     BatchSlot &b = s->ring[s->ring_next];
     s->ring_next = (s->ring_next + 1) % kBatchRing;
     if (b.used) HIP_TRY(hipEventSynchronize(b.ev));  // its descriptors may be reused now
-    uint32_t parts = 0, max_clear = 0;
+    uint32_t parts = 0, max_clear = 0, n = 0;
     for (size_t i = 0; i < batch.size(); ++i) {
         SrvCtx *c = batch[i];
+        if (c->req.full) continue;  // renders the scene's list of leaves: nothing to select
         v3dg_scene *sc = s->scenes[c->req.scene];
         SelReq q = make_selreq(sc, c->itab, c->req.K, c->req.tau, &c->sel, c->req.cam, s->cfg.cull != 0);
         q.part_begin = parts;
         parts += q.nparts;
-        b.h_req[i] = q;
+        b.h_req[n] = q;
         SelSetup su{};
         su.cam = c->req.cam;
         su.T = sc->T_dev;
@@ -2284,17 +2289,18 @@ int srv_dispatch(v3dg_server *s, const std::vector<SrvCtx *> &batch)
         su.n_inst = sc->n_inst;
         su.n_clear = (uint32_t)(kSelCounters + 2 * q.nparts);
         max_clear = std::max(max_clear, su.n_clear);
-        b.h_setup[i] = su;
+        b.h_setup[n++] = su;
     }
-    const uint32_t n = (uint32_t)batch.size();
-    HIP_TRY(hipMemcpyAsync(b.d_setup, b.h_setup, n * sizeof(SelSetup), hipMemcpyHostToDevice, s->sched));
-    HIP_TRY(hipMemcpyAsync(b.d_req, b.h_req, n * sizeof(SelReq), hipMemcpyHostToDevice, s->sched));
-    launch_select_batch(s->sched, b.d_setup, b.d_req, n, parts, s->max_inst, max_clear, b.d_ticket);
-    HIP_TRY(hipGetLastError());
+    if (n > 0) {
+        HIP_TRY(hipMemcpyAsync(b.d_setup, b.h_setup, n * sizeof(SelSetup), hipMemcpyHostToDevice, s->sched));
+        HIP_TRY(hipMemcpyAsync(b.d_req, b.h_req, n * sizeof(SelReq), hipMemcpyHostToDevice, s->sched));
+        launch_select_batch(s->sched, b.d_setup, b.d_req, n, parts, s->max_inst, max_clear, b.d_ticket);
+        HIP_TRY(hipGetLastError());
+        s->st.batches += 1;
+        s->st.batched_requests += n;
+    }
     HIP_TRY(hipEventRecord(b.ev, s->sched));
     b.used = true;
-    s->st.batches += 1;
-    s->st.batched_requests += n;
     for (SrvCtx *c : batch) {
         int rc = srv_launch(s, c, b.ev);
         if (rc) return rc;
@@ -2392,6 +2398,30 @@ int v3dg_server_submit(v3dg_server *s, uint32_t scene, const v3dg_camera *cam, f
     return V3DG_OK;
 }
 
+int v3dg_server_submit_full(v3dg_server *s, uint32_t scene, const v3dg_camera *cam, float *image_dev,
+                            uint64_t *ticket)
+{
+    g_err.clear();
+    if (!s) return fail(V3DG_ERR_INVALID_ARG, "server is NULL");
+    if (scene >= s->scenes.size()) return fail(V3DG_ERR_INVALID_ARG, "scene %u out of range", scene);
+    if (!image_dev) return fail(V3DG_ERR_INVALID_ARG, "image is NULL");
+    SrvReq r;
+    int rc = make_cam(cam, &r.cam);
+    if (rc) return rc;
+    v3dg_scene *sc = s->scenes[scene];
+    HIP_TRY(hipSetDevice(sc->device));
+    if ((rc = build_full_selection(sc))) return rc;  // once per scene, on its stream (synchronised)
+    r.ticket = s->next_ticket++;
+    r.scene = scene;
+    r.full = true;
+    r.image = image_dev;
+    r.submit_ms = now_ms(s->t0);
+    s->queue.push_back(r);
+    s->st.submitted += 1;
+    if (ticket) *ticket = r.ticket;
+    return V3DG_OK;
+}
+
 int v3dg_server_poll(v3dg_server *s, int wait, v3dg_request_done *done, uint32_t cap, uint32_t *n_done)
 {
     g_err.clear();
@@ -2412,7 +2442,7 @@ int v3dg_server_poll(v3dg_server *s, int wait, v3dg_request_done *done, uint32_t
             c->busy = false;
             const uint32_t err = c->pinned[kRenErr] | c->pinned[8 + kSelErr];
             const uint64_t K = (uint64_t)c->pinned[kRenKeysLo] | ((uint64_t)c->pinned[kRenKeysHi] << 32);
-            const ShapeKey key{c->req.scene, c->req.cam.width, c->req.cam.height};
+            const ShapeKey key{c->req.scene, c->req.cam.width, c->req.cam.height, c->req.full};
             uint64_t &seen = s->keys_seen[key];
             seen = std::max(seen, K);
             int status = V3DG_OK;
@@ -2457,7 +2487,7 @@ int v3dg_server_poll(v3dg_server *s, int wait, v3dg_request_done *done, uint32_t
         SrvReq &r = s->queue.front();
         v3dg_scene *sc = s->scenes[r.scene];
         const uint32_t n_tiles = r.cam.tiles_x * r.cam.tiles_y;
-        const ShapeKey key{r.scene, r.cam.width, r.cam.height};
+        const ShapeKey key{r.scene, r.cam.width, r.cam.height, r.full};
         const uint64_t Kneed = keys_estimate(s, key, (uint64_t)r.cam.width * r.cam.height);
         SrvCtx *c = nullptr;
         uint64_t cost = 0;

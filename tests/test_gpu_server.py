@@ -107,6 +107,45 @@ def test_server_images_equal_standalone(scenes, torch, use_graphs):
     srv.close()
 
 
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_server_full_detail_requests(scenes, torch, use_graphs):
+    """Full-detail requests (every leaf, no selection) mixed with selected
+    ones in one stream of requests: each equals v3dg_render_full (or select +
+    render) of the same camera alone, bit for bit."""
+    rng = np.random.default_rng(41 + int(use_graphs))
+    reqs = _requests(rng, 16)
+    full = [i % 2 == 0 for i in range(len(reqs))]
+    ref, slots = [], []
+    for (k, cam, tau), f in zip(reqs, full):
+        sc = scenes[k]
+        if f:
+            ref.append(sc.render_full(cam).clone())
+        else:
+            sel = sc.select(cam, tau)
+            ref.append(sc.render(cam, sel).clone())
+            sel.free()
+        slots.append(sc.frame_stats()["n_slots"])
+    torch.cuda.synchronize()
+    srv = v.Server(scenes, n_contexts=3, max_batch=8, use_graphs=use_graphs)
+    tickets = {}
+    for i, ((k, cam, tau), f) in enumerate(zip(reqs, full)):
+        t, _ = srv.submit(k, cam, tau, full=f)
+        tickets[t] = i
+    done = srv.drain()
+    st = srv.stats()
+    _say("server full-detail mix graphs=%s: %s" % (use_graphs, st))
+    assert len(done) == len(reqs)
+    for r in done:
+        i = tickets[r["ticket"]]
+        assert r["status"] == 0, r
+        assert torch.equal(r["image"], ref[i]), (i, full[i], reqs[i][0])
+        assert r["n_slots"] == slots[i], (i, full[i])
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    # only the selected requests go through the batched selection
+    assert st["batched_requests"] == len(reqs) - sum(full) + st["retries"]
+    srv.close()
+
+
 def test_server_retries_after_key_overflow(scenes, torch):
     """A capacity of one key per pixel (at least 65,536) at first: requests that
     need more are retried on grown buffers.  A fourth scene of 6,000 large
