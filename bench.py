@@ -56,7 +56,7 @@ BLEND_OPS_PER_PAIR = 24
 # Valid only for the blending source they were taken on (blend.hip and the
 # constants of v3dg_internal.h, such as the chunk sizes) and for that many
 # timed frames: the bench reports null otherwise.
-BLEND_TRAFFIC = dict(bytes_per_frame=700493909, frames=20, blend_source_sha256_16="c723477d3d9b3b72")
+BLEND_TRAFFIC = dict(bytes_per_frame=714443029, frames=20, blend_source_sha256_16="0f10ee0f4e3fc6af")
 
 
 def log(*a):
