@@ -53,10 +53,10 @@ BLEND_OPS_PER_PAIR = 24
 # HBM bytes per frame of the blend stage on the headline frames, from
 # rocprofv3 FETCH_SIZE (x2, calibrated) + WRITE_SIZE over the first
 # BLEND_TRAFFIC["frames"] frames of the sequence (profiles/hbm_counters_...).
-# Valid only for the blending source they were taken on (blend.hip and the
-# constants of v3dg_internal.h, such as the chunk sizes) and for that many
-# timed frames: the bench reports null otherwise.
-BLEND_TRAFFIC = dict(bytes_per_frame=714443029, frames=20, blend_source_sha256_16="0f10ee0f4e3fc6af")
+# Valid only for the blending source they were taken on (blend.hip, the
+# constants of v3dg_internal.h and the chunk sizes of blend_plan.h) and for
+# that many timed frames: the bench reports null otherwise.
+BLEND_TRAFFIC = dict(bytes_per_frame=714443029, frames=20, blend_source_sha256_16="dd10a660d8724629")
 
 
 def log(*a):
@@ -171,7 +171,7 @@ def measured_blend_traffic(args):
     import hashlib
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_06523_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("blend.hip", "v3dg_internal.h"):
+    for f in ("blend.hip", "v3dg_internal.h", "blend_plan.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     sha = h.hexdigest()[:16]
     if (args.quick or args.steps != BLEND_TRAFFIC["frames"] or BLEND_TRAFFIC["bytes_per_frame"] is None
