@@ -17,8 +17,12 @@ another's blending.  The single-stream pass issues v3dg_select +
 v3dg_render frame after frame on one stream; it gives the per-frame times
 (p50/p99), the per-stage breakdown and the blend roofline, whose kernel
 durations are then not shared with another frame.  Both run the same kernels
-on the same frames and give the same images bit for bit.  Prints one JSON
-line on stdout.
+on the same frames.  The serving loop cuts long bin lists into chunks of
+SERVE_CHUNK_KEYS keys (after a first chunk of three times that), the
+single-stream pass into chunks of 1,024: with other frames in flight a
+longer walk costs less than walking pairs twice, alone it holds up the frame.
+Their images then differ at most in the last bits.  Prints one JSON line on
+stdout.
 """
 from __future__ import annotations
 
@@ -38,6 +42,7 @@ WORKLOAD = ("1,048,576-leaf SH3 asset (1,398,080 rows, 21,845 clusters), 1920x10
 # and requests handed to it at once (so that a poll always finds queued work)
 SERVE_CONTEXTS = 3
 SERVE_OUTSTANDING = 4 * SERVE_CONTEXTS
+SERVE_CHUNK_KEYS = 2048  # the server's default chunk size of long bin lists
 HBM_PEAK_GBS = 8000.0
 # Blending is plain FP32 VALU work (no contraction for matrix cores, no pairs
 # of identical independent ops for packed math), so its ceiling is the VALU
@@ -125,14 +130,15 @@ def stage_bytes(P: dict, b_row: int) -> dict:
       expand     16 B per selected cluster (gid, offset, row range) + 8 B per slot
       project    40 B per slot (slot 8, position 12, opacity 4; depth, sort key,
                  sort value, tile count 16) + per visible slot the other
-                 B_row - 16 attribute bytes and 88 B of records (splat 48,
-                 binning 32, tile rectangle 8)
+                 B_row - 16 attribute bytes and 80 B of records (splat 48,
+                 binning 32)
       depth sort 4 B per slot for the histogram + 4 passes x 16 B (key and
                  value, read and written)
       scan       12 B per slot (depth order, tile count gathered, offset)
-      emit       52 B per visible slot (order, tile count, offset, rectangle,
-                 binning record) + (kb + 4) B per key written; its digit
-                 histograms are counted in place
+      emit       8 B per slot (depth order, offset; a rank's key count is
+                 the difference of consecutive offsets) + the 32-B binning
+                 record per visible slot + (kb + 4) B per key written; its
+                 digit histograms are counted in place
       sort_hist  kb B per key (the 64-bit-key mode only: the depth-first
                  binning takes its histograms from emission)
       sort_pass  2 (kb + 4) B per key and pass (key and value, read and
@@ -154,10 +160,10 @@ def stage_bytes(P: dict, b_row: int) -> dict:
     return {
         "select": P["tests"] * 32 + P["sel_clusters"] * 8,
         "expand": P["sel_clusters"] * 16 + P["slots"] * 8,
-        "project": P["slots"] * 40 + P["visible"] * ((b_row - 16) + 88),
+        "project": P["slots"] * 40 + P["visible"] * ((b_row - 16) + 80),
         "depth_sort": P["slots"] * (4 + 4 * 16) * (P["depth_sorts"] / fr),
         "scan": P["slots"] * 12,
-        "emit": P["visible"] * 52 + P["keys"] * (kb + 4),
+        "emit": P["slots"] * 8 + P["visible"] * 32 + P["keys"] * (kb + 4),
         "sort_hist": 0 if depth_first else P["keys"] * kb,
         "sort_pass": P["keys"] * (2 * (kb + 4)) * passes,
         "ranges": P["tiles"] * (search + 16),
@@ -219,7 +225,7 @@ def served_frames(torch, v, scene, frames, full: bool, warm: int):
     # it: no context grows (a synchronising reallocation and a graph
     # recapture) inside the timed frames
     srv = v.Server([scene], n_contexts=SERVE_CONTEXTS, max_batch=16, hbm_budget_bytes=96 << 30, use_graphs=True,
-                   keys_per_pixel=48)
+                   keys_per_pixel=48, chunk_keys=SERVE_CHUNK_KEYS)
     bufs = [torch.empty((f.height, f.width, 4), dtype=torch.float32, device="cuda")
             for f in [frames[0][0]] * SERVE_OUTSTANDING]
 
@@ -893,7 +899,7 @@ def main():
         "single_stream": dict(fps=fps_single, ms_per_frame=wall / K * 1e3, full_detail_fps=fps_full_single if
                               not args.profile_run else None, speedup_vs_full=(fps_single / fps_full_single) if
                               not args.profile_run else None),
-        "serving_loop": dict(contexts=SERVE_CONTEXTS, outstanding=SERVE_OUTSTANDING,
+        "serving_loop": dict(contexts=SERVE_CONTEXTS, outstanding=SERVE_OUTSTANDING, chunk_keys=SERVE_CHUNK_KEYS,
                              latency_p50_ms=pct(lat, 50) if lat else None,
                              latency_p99_ms=pct(lat, 99) if lat else None,
                              full_detail_latency_p50_ms=pct(lat_f, 50) if lat_f else None,

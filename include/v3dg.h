@@ -315,6 +315,18 @@ typedef struct {
  * and binned. */
 int v3dg_set_culling(v3dg_scene *scene, int on);
 
+/* Chunk sizes of long bin lists for later renders of this scene (default
+ * 1024).  Blending composites each bin's depth-sorted list front to back
+ * (Sec. 2.1); a list longer than 3 * keys is walked as a first chunk of
+ * 3 * keys and further chunks of `keys`, in parallel, folded in order and
+ * walked again where a pixel stops (the sequential result up to the
+ * association of FP32 products).  Smaller chunks shorten a frame's longest
+ * walk; larger ones walk fewer pairs twice, which pays when several frames
+ * share the device (the serving loop's default is 2048).  keys: 1024, 2048
+ * or 4096, else V3DG_ERR_INVALID_ARG.  Images of different chunk sizes may
+ * differ in the last bits. */
+int v3dg_set_chunk_keys(v3dg_scene *scene, uint32_t keys);
+
 /* Select the sort strategy for later renders of this scene (default
  * V3DG_SORT_DEPTH_FIRST).  Both give bit-identical images. */
 int v3dg_set_sort_mode(v3dg_scene *scene, int mode);
@@ -381,7 +393,8 @@ typedef struct {
                                    not seen yet (0: 24); later frames of a size get 1.25 x the
                                    most keys seen                                          */
     uint32_t cull;              /* 1: view culling of the cut, as v3dg_set_culling          */
-    uint32_t pad0;
+    uint32_t chunk_keys;        /* keys per later chunk of long bin lists, as
+                                   v3dg_set_chunk_keys (0: 2048)                           */
 } v3dg_server_config;
 
 typedef struct {

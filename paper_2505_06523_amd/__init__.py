@@ -87,7 +87,7 @@ class v3dg_profile(C.Structure):
 class v3dg_server_config(C.Structure):
     _fields_ = [("n_contexts", C.c_uint32), ("max_batch", C.c_uint32), ("hbm_budget_bytes", C.c_uint64),
                 ("use_graphs", C.c_uint32), ("keys_per_pixel", C.c_uint32), ("cull", C.c_uint32),
-                ("pad0", C.c_uint32)]
+                ("chunk_keys", C.c_uint32)]
 
 
 class v3dg_request_done(C.Structure):
@@ -109,7 +109,7 @@ EXPORTS = [
     "v3dg_get_stream_stats", "v3dg_set_instances", "v3dg_select", "v3dg_render", "v3dg_render_full",
     "v3dg_selection_info", "v3dg_selection_copy_ids", "v3dg_selection_copy_slots", "v3dg_selection_free",
     "v3dg_scene_free", "v3dg_get_frame_stats", "v3dg_copy_projection", "v3dg_copy_attributes", "v3dg_copy_sorted_keys",
-    "v3dg_set_sort_mode", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
+    "v3dg_set_sort_mode", "v3dg_set_chunk_keys", "v3dg_set_culling", "v3dg_set_profiling", "v3dg_collect_profile", "v3dg_sort_pairs",
     "v3dg_sort_pairs_noalloc", "v3dg_last_error",
     "v3dg_server_create", "v3dg_server_submit", "v3dg_server_submit_full", "v3dg_server_poll", "v3dg_server_get_stats", "v3dg_server_free",
     "v3dg_build_bundle", "v3dg_bundle_sizes", "v3dg_bundle_copy", "v3dg_bundle_fit_loss", "v3dg_bundle_free", "v3dg_local_splat",
@@ -146,6 +146,7 @@ def lib():
         "v3dg_copy_attributes": ([P, U64, U64, P, P, P, P, P], I),
         "v3dg_copy_sorted_keys": ([P, P, P, U64, P], I),
         "v3dg_set_sort_mode": ([P, I], I),
+        "v3dg_set_chunk_keys": ([P, U32], I),
         "v3dg_set_culling": ([P, I], I),
         "v3dg_set_profiling": ([P, I], I),
         "v3dg_collect_profile": ([P, P], I),
@@ -298,6 +299,10 @@ def v3dg_copy_sorted_keys(scene, n_keys: int):
 
 def v3dg_set_sort_mode(scene, mode: int):
     _check(lib().v3dg_set_sort_mode(scene, int(mode)))
+
+
+def v3dg_set_chunk_keys(scene, keys: int):
+    _check(lib().v3dg_set_chunk_keys(scene, int(keys)))
 
 
 def v3dg_set_culling(scene, on: bool):
@@ -514,6 +519,10 @@ class Scene:
     def set_sort_mode(self, mode: int):
         v3dg_set_sort_mode(self.handle, mode)
 
+    def set_chunk_keys(self, keys: int):
+        """Later-chunk size of long bin lists in later renders (1024, 2048 or 4096)."""
+        v3dg_set_chunk_keys(self.handle, keys)
+
     def set_culling(self, on: bool = True):
         v3dg_set_culling(self.handle, on)
 
@@ -641,12 +650,13 @@ class Server:
     completion record comes back from poll()."""
 
     def __init__(self, scenes, n_contexts: int = 8, max_batch: int = 16, hbm_budget_bytes: int = 64 << 30,
-                 use_graphs: bool = True, keys_per_pixel: int = 0, cull: bool = False):
+                 use_graphs: bool = True, keys_per_pixel: int = 0, cull: bool = False, chunk_keys: int = 0):
         cfg = v3dg_server_config()
         cfg.n_contexts, cfg.max_batch = int(n_contexts), int(max_batch)
         cfg.hbm_budget_bytes, cfg.use_graphs = int(hbm_budget_bytes), int(bool(use_graphs))
         cfg.keys_per_pixel = int(keys_per_pixel)
         cfg.cull = int(bool(cull))
+        cfg.chunk_keys = int(chunk_keys)
         self.scenes = list(scenes)  # keeps the scenes alive while the server runs
         self.handle = None
         self.handle = v3dg_server_create([sc.handle for sc in self.scenes], cfg)

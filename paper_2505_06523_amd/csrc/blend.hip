@@ -18,10 +18,10 @@
 //
 // Long lists.  A few tiles of a near view hold tens of thousands of splats and
 // would keep one workgroup busy long after the rest of the frame is done.  A
-// list longer than kChunkFirst keys is cut into a first chunk of kChunkFirst
-// keys and further chunks of kChunk (the first chunk is longer because most
-// pixels of opaque content stop within it, which leaves the later chunks
-// nothing to do).  The tile-range kernel has given every long tile its chunk
+// list longer than a first chunk is cut into the first chunk and further,
+// shorter chunks (the frame's ChunkPlan: most pixels of opaque content stop
+// within the first chunk, which leaves the later chunks nothing to do).  The
+// tile-range kernel has given every long tile its chunk
 // records and listed the work items (tile, chunk >= 1); then
 //   blend_kernel  walks chunk 0 of every tile (with the stop rule);
 //   chunk_kernel  walks every other chunk in parallel, each from T = 1,
@@ -351,7 +351,7 @@ __device__ __forceinline__ void write_pixel(const CamArgs &cam, const TileGeo &g
 }
 
 // ---------------------------------------------------------------------------
-// pass 1: every tile, up to its first kChunkFirst keys
+// pass 1: every tile, up to the end of its first chunk
 // ---------------------------------------------------------------------------
 // Workgroup b blends tile order[b]: the tiles with the longest first chunks
 // come first, so that their walks do not start last and leave the rest of the
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
                                                               const uint32_t *__restrict__ order,
                                                               float4 *__restrict__ scratch,
                                                               uint32_t *__restrict__ need,
-                                                              unsigned long long *__restrict__ pairs)
+                                                              unsigned long long *__restrict__ pairs, ChunkPlan cp)
 {
     __shared__ BlendShared sh;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -377,8 +377,8 @@ __global__ void __launch_bounds__(kBlendThreads) blend_kernel(const FrameDev *__
     Pix px{1.0f, 0.f, 0.f, 0.f, g.inside, 0u, 0u};
     const uint32_t end = rg.y > rg.x ? rg.y : rg.x;
     const uint32_t cb = cbase[tile];  // kNoChunk: blended whole
-    const bool long_list = cb != kNoChunk && end - rg.x > (uint32_t)kChunkFirst;
-    blend_range<kCount, false>(rg.x, long_list ? rg.x + kChunkFirst : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid,
+    const bool long_list = cb != kNoChunk && end - rg.x > cp.first();
+    blend_range<kCount, false>(rg.x, long_list ? rg.x + cp.first() : end, splat, vals, g.bx0, g.by0, g.pxc, g.pyc, wid,
                                lane, sh, px, ChunkSkip{});
     if (long_list) {  // state after chunk 0; a negative T marks a finished pixel
         scratch[(uint64_t)cb * kBlendThreads + g.pix] =
@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
                                                               float4 *__restrict__ scratch,
                                                               const uint32_t *__restrict__ need,
                                                               uint64_t *__restrict__ stopm,
-                                                              unsigned long long *__restrict__ pairs)
+                                                              unsigned long long *__restrict__ pairs, ChunkPlan cp)
 {
     static_assert(kChunkRounds == kWave, "one wavefront scans the round sizes");
     __shared__ BlendShared sh;
@@ -457,8 +457,8 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
             sk.stopm = stopm;
             sk.base = base;
             sk.c = c;
-            blend_range<kCount, true>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0,
-                                      g.by0, g.pxc, g.pyc, wid, lane, sh, px, sk);
+            blend_range<kCount, true>(rg.x + cp.begin(c), rg.x + cp.end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0,
+                                      g.pxc, g.pyc, wid, lane, sh, px, sk);
             // the fold reads later chunks only for pixels active after chunk 0 (a
             // dropped pixel's summary is never read)
             if (was)
@@ -480,7 +480,8 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
                                                              const uint32_t *__restrict__ cbase,
                                                              float4 *__restrict__ scratch, uint32_t *__restrict__ pend,
                                                              uint32_t *__restrict__ need, uint64_t *__restrict__ stopm,
-                                                             uint2 *__restrict__ rewalk, uint32_t *counters)
+                                                             uint2 *__restrict__ rewalk, uint32_t *counters,
+                                                             ChunkPlan cp)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const CamArgs &cam = fd->cam;
@@ -488,8 +489,8 @@ __global__ void __launch_bounds__(kBlendThreads) fold_kernel(const FrameDev *__r
     float4 *image = reinterpret_cast<float4 *>(fd->image);
     const uint2 rg = ranges[tile];
     const uint32_t L = rg.y > rg.x ? rg.y - rg.x : 0u;
-    if (L <= (uint32_t)kChunkFirst || cbase[tile] == kNoChunk) return;
-    const uint32_t m = n_chunks(L);
+    if (L <= cp.first() || cbase[tile] == kNoChunk) return;
+    const uint32_t m = cp.n_chunks(L);
     const TileGeo g = tile_geo(cam, tile, wid, lane);
     const uint64_t base = cbase[tile];
     for (uint32_t c = tid; c < m; c += kBlendThreads) need[base + c] = 0u;
@@ -552,7 +553,7 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
                                                                const uint32_t *__restrict__ pend,
                                                                const uint2 *__restrict__ rewalk,
                                                                const uint32_t *__restrict__ counters,
-                                                               unsigned long long *__restrict__ pairs)
+                                                               unsigned long long *__restrict__ pairs, ChunkPlan cp)
 {
     __shared__ BlendShared sh;
     const uint32_t n_items = counters[kRenRewalk];
@@ -568,7 +569,7 @@ __global__ void __launch_bounds__(kBlendThreads) rewalk_kernel(const FrameDev *_
         const bool mine = pend[base * kBlendThreads + g.pix] == c;
         const float4 st = scratch[base * kBlendThreads + g.pix];
         Pix px{fabsf(st.w), st.x, st.y, st.z, mine, 0u, 0u};  // a pixel finished before holds -T
-        blend_range<kCount, false>(rg.x + chunk_begin(c), rg.x + chunk_end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0,
+        blend_range<kCount, false>(rg.x + cp.begin(c), rg.x + cp.end(c, rg.y - rg.x), splat, vals, g.bx0, g.by0,
                                    g.pxc, g.pyc, wid, lane, sh, px, ChunkSkip{});
         // a pixel that, through rounding of the folded products, does not stop in
         // this chunk keeps T ~ 1e-4: the later chunks would change it by at most that
@@ -627,13 +628,13 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
                            const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                            const uint32_t *rounds, uint32_t rcap, const uint32_t *order, uint32_t *counters,
                            uint64_t max_items, uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need,
-                           uint64_t *stopm, uint2 *rewalk, unsigned long long *pairs)
+                           uint64_t *stopm, uint2 *rewalk, unsigned long long *pairs, ChunkPlan cp)
 {
     // beyond kMaxGrid items workgroups loop over further ones: a capacity-sized
     // bound on the items (frames sized without a host wait) launches no more
     constexpr uint64_t kMaxGrid = 16384;
     hipLaunchKernelGGL(blend_kernel<kCount>, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
-                       order, scratch, need, pairs);
+                       order, scratch, need, pairs, cp);
     if (max_items > 0) {
         const uint32_t gi = (uint32_t)(max_items < kMaxGrid ? max_items : kMaxGrid);
         // few chunks hold a stop to walk again: 2048 workgroups loop over them
@@ -641,11 +642,11 @@ static void launch_blend_t(hipStream_t st, const FrameDev *fd, uint32_t n_tiles,
         constexpr uint64_t kRewalkGrid = 2048;
         const uint32_t gc = (uint32_t)(max_chunks < kRewalkGrid ? max_chunks : kRewalkGrid);
         hipLaunchKernelGGL(chunk_kernel<kCount>, dim3(gi), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
-                           items, rounds, rcap, counters, scratch, need, stopm, pairs);
+                           items, rounds, rcap, counters, scratch, need, stopm, pairs, cp);
         hipLaunchKernelGGL(fold_kernel, dim3(n_tiles), dim3(kBlendThreads), 0, st, fd, ranges, cbase, scratch, pend,
-                           need, stopm, rewalk, counters);
+                           need, stopm, rewalk, counters, cp);
         hipLaunchKernelGGL(rewalk_kernel<kCount>, dim3(gc), dim3(kBlendThreads), 0, st, fd, splat, vals, ranges, cbase,
-                           scratch, pend, rewalk, counters, pairs);
+                           scratch, pend, rewalk, counters, pairs, cp);
     }
 }
 
@@ -655,18 +656,18 @@ void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                   const uint32_t *rounds, uint32_t rcap, const uint32_t *order, uint32_t *counters, uint64_t max_items,
                   uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint64_t *stopm, uint2 *rewalk,
-                  unsigned long long *pairs, int count)
+                  unsigned long long *pairs, int count, ChunkPlan cp)
 {
     const uint32_t n_tiles = tiles_x * tiles_y;
     if (count >= 2)
-        launch_blend_t<2>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items, max_chunks,
-                          scratch, pend, need, stopm, rewalk, pairs);
+        launch_blend_t<2>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items,
+                          max_chunks, scratch, pend, need, stopm, rewalk, pairs, cp);
     else if (count == 1)
-        launch_blend_t<1>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items, max_chunks,
-                          scratch, pend, need, stopm, rewalk, pairs);
+        launch_blend_t<1>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items,
+                          max_chunks, scratch, pend, need, stopm, rewalk, pairs, cp);
     else
-        launch_blend_t<0>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items, max_chunks,
-                          scratch, pend, need, stopm, rewalk, pairs);
+        launch_blend_t<0>(st, fd, n_tiles, splat, vals, ranges, cbase, items, rounds, rcap, order, counters, max_items,
+                          max_chunks, scratch, pend, need, stopm, rewalk, pairs, cp);
 }
 
 }  // namespace v3dg

@@ -14,30 +14,44 @@
 namespace v3dg {
 
 constexpr uint32_t kTilesPerBin = 4;        // a bin is a 2 x 2 block of tiles; each tile walks the bin's list
-constexpr int kChunk = 1024;                // keys per chunk of a long bin list after the first
-constexpr int kChunkFirst = 3072;           // keys of the first chunk (walked by pass 1)
 constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whole
-static_assert(kChunkFirst >= 2 * kChunk, "the chunk bound needs first chunks of at least two later ones");
 
-// A list of L > kChunkFirst keys is cut into a first chunk of kChunkFirst keys
-// and further chunks of kChunk: n_chunks(L) chunks, chunk c holding keys
-// [chunk_begin(c), chunk_end(c, L)).
-V3DG_HD inline uint32_t n_chunks(uint32_t L)
-{
-    return L <= (uint32_t)kChunkFirst ? 1u : 1u + (L - kChunkFirst + kChunk - 1) / kChunk;
-}
-V3DG_HD inline uint32_t chunk_begin(uint32_t c) { return c == 0 ? 0u : kChunkFirst + (c - 1) * kChunk; }
-V3DG_HD inline uint32_t chunk_end(uint32_t c, uint32_t L)
-{
-    const uint32_t e = (uint32_t)kChunkFirst + c * (uint32_t)kChunk;
-    return e < L ? e : L;
-}
+// Chunk sizes of a plan: later chunks of 2^shift keys and a first chunk of
+// three of them (the first chunk is longer because most pixels of opaque
+// content stop within it).  Smaller chunks shorten the longest walk of a
+// frame; larger ones walk fewer pairs speculatively and again, which pays
+// when other frames keep the chip busy meanwhile.
+constexpr uint32_t kChunkShiftMin = 10, kChunkShiftMax = 12;  // later chunks of 1,024 .. 4,096 keys
+constexpr uint32_t kChunkShiftRender = 10;  // v3dg_render: 3,072 / 1,024 keys
+constexpr uint32_t kChunkShiftServer = 11;  // the serving loop: 6,144 / 2,048 keys
+
+// A list of L > first() keys is cut into a first chunk of first() keys and
+// further chunks of later(): n_chunks(L) chunks, chunk c holding keys
+// [begin(c), end(c, L)).
+struct ChunkPlan {
+    uint32_t shift = kChunkShiftRender;
+    V3DG_HD uint32_t later() const { return 1u << shift; }
+    V3DG_HD uint32_t first() const { return 3u << shift; }
+    V3DG_HD uint32_t n_chunks(uint32_t L) const
+    {
+        return L <= first() ? 1u : 1u + ((L - first() + later() - 1u) >> shift);
+    }
+    V3DG_HD uint32_t begin(uint32_t c) const { return c == 0 ? 0u : (c + 2u) << shift; }
+    V3DG_HD uint32_t end(uint32_t c, uint32_t L) const
+    {
+        const uint32_t e = (c + 3u) << shift;
+        return e < L ? e : L;
+    }
+};
 
 // Chunk records a plan over K keys may take: each of the kTilesPerBin tiles
-// of a bin with L > kChunkFirst keys takes n_chunks(L) <= 2 + (L - kChunkFirst)
-// / kChunk <= L / kChunk records (kChunkFirst >= 2 kChunk), so all lists
-// together take at most kTilesPerBin K / kChunk.
-inline uint64_t chunk_bound(uint64_t K) { return (uint64_t)kTilesPerBin * ((K + kChunk - 1) / kChunk) + 1; }
+// of a bin with L > first keys takes n_chunks(L) <= 2 + (L - first) / later
+// = L / later - 1 records (first = 3 later), so all lists together take at
+// most kTilesPerBin K / later.
+inline uint64_t chunk_bound(uint64_t K, uint32_t shift)
+{
+    return (uint64_t)kTilesPerBin * ((K + (1ull << shift) - 1) >> shift) + 1;
+}
 
 // Whether a tile given records [first, first + m) of a buffer of max_chunks
 // records is chunked (else it is blended whole).

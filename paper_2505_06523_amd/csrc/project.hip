@@ -8,8 +8,8 @@
 // Splats with det below 1e-6 are redone in FP64 (counted per frame).
 //
 // Outputs per slot: the splat record read by blending, the FP32 depth used as
-// the sort key, and the conservative tile rectangle of the support
-// {alpha >= 1/255} (ellipse d^T Sigma^-1 d <= 2 ln(255 o) plus one pixel).
+// the sort key, the binning record of the support {alpha >= 1/255} (ellipse
+// d^T Sigma^-1 d <= 2 ln(255 o), enlarged) and the number of bins it reaches.
 #include <hip/hip_fp16.h>
 
 #include "v3dg_internal.h"
@@ -281,14 +281,8 @@ __global__ void __launch_bounds__(256) project_kernel(const FrameDev *__restrict
         br.det = det_s;
         br.Qm = 1.05f * Q + 0.05f;
         br.depth = z;
-        const float hx = sqrtf(br.Qm * a) + 1.0f, hy = sqrtf(br.Qm * c) + 1.0f;
-        const float fx0 = fmaxf(ceilf(mx - hx - 0.5f), 0.0f);
-        const float fx1 = fminf(floorf(mx + hx - 0.5f), (float)(cam.width - 1));
-        const float fy0 = fmaxf(ceilf(my - hy - 0.5f), 0.0f);
-        const float fy1 = fminf(floorf(my + hy - 0.5f), (float)(cam.height - 1));
-        if (!(fx0 <= fx1 && fy0 <= fy1)) continue;
-        const uint32_t tx0 = (uint32_t)fx0 / kBin, tx1 = (uint32_t)fx1 / kBin;
-        const uint32_t ty0 = (uint32_t)fy0 / kBin, ty1 = (uint32_t)fy1 / kBin;
+        uint32_t tx0, tx1, ty0, ty1;
+        if (!bin_box(br, cam.width, cam.height, &tx0, &tx1, &ty0, &ty1)) continue;
         uint32_t ntiles = 0;  // bins touched
         for (uint32_t ty = ty0; ty <= ty1; ++ty) {
             uint32_t lo, hi;
@@ -297,7 +291,6 @@ __global__ void __launch_bounds__(256) project_kernel(const FrameDev *__restrict
         if (ntiles == 0) continue;
         out.tiles[t] = ntiles;
         out.dkey[t] = __float_as_uint(z);
-        out.rect[t] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
         out.bin[t] = br;
         float4 *sp = out.splat + 3 * (uint64_t)t;
         sp[0] = make_float4(mx, my, ca, cb);

@@ -161,7 +161,6 @@ struct Ctx {
     float4 *splat = nullptr;
     BinRec *bin = nullptr;
     float *depth = nullptr;
-    uint2 *rect = nullptr;
     uint32_t *tiles = nullptr;
     uint32_t *offsets = nullptr;
     uint32_t *big = nullptr;  // splats emitted by the large-splat kernel
@@ -188,6 +187,7 @@ struct Ctx {
     uint64_t *stopm = nullptr;     // per chunk, per wavefront: pixels the chunk stopped
     uint2 *rewalk = nullptr;       // (tile, chunk) to walk again
     uint64_t cap_chunks = 0;
+    uint32_t chunk_shift = kChunkShiftRender;  // chunk sizes of long bin lists (ChunkPlan)
     uint32_t *pinned = nullptr;
     v3dg_frame_stats last{};
     int last_buf = 0;
@@ -502,7 +502,6 @@ void ctx_free_slots(Ctx *c)
         dev_free(c->dkey[b]);
         dev_free(c->dval[b]);
     }
-    dev_free(c->rect);
     dev_free(c->tiles);
     dev_free(c->offsets);
     dev_free(c->big);
@@ -569,7 +568,6 @@ int ensure_slots(Ctx *c, uint64_t n)
     if ((rc = dev_alloc(&c->splat, 3 * n))) return rc;
     if ((rc = dev_alloc(&c->bin, n))) return rc;
     if ((rc = dev_alloc(&c->depth, n))) return rc;
-    if ((rc = dev_alloc(&c->rect, n))) return rc;
     if ((rc = dev_alloc(&c->tiles, n))) return rc;
     if ((rc = dev_alloc(&c->offsets, n))) return rc;
     if ((rc = dev_alloc(&c->big, n))) return rc;
@@ -615,10 +613,10 @@ int ensure_status(Ctx *c, uint64_t parts)
     return V3DG_OK;
 }
 
-// chunk buffers for frames of up to K keys (chunk_bound)
+// chunk buffers for frames of up to K keys (chunk_bound of the context's plan)
 int ensure_chunks(Ctx *c, uint64_t K)
 {
-    const uint64_t need = chunk_bound(K);
+    const uint64_t need = chunk_bound(K, c->chunk_shift);
     if (need <= c->cap_chunks) return V3DG_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
     dev_free(c->items);
@@ -723,16 +721,17 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
     const DigitPlan dp = even_digits(key_bits);
     {
         Stage st(c, V3DG_STAGE_EMIT);
-        launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys,
-                          dp, kb[0], c->vals[0], c->rcounters + kRenHist, c->big, c->rcounters + kRenBig,
-                          c->rcounters + kRenErr);
+        launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rcounters + kRenKeysLo, c->bin,
+                          c->fdev, c->cap_keys, dp, kb[0], c->vals[0], c->rcounters + kRenHist, c->big,
+                          c->rcounters + kRenBig, c->rcounters + kRenErr);
     }
     if (KL > 0) run_sort<KT>(c, kb, c->vals, k_dev, KL, key_bits, 4, buf, passes, true, &dp);
     {
         Stage st(c, V3DG_STAGE_RANGES);
         launch_tile_ranges<KT>(c->stream, kb[*buf], c->rcounters + kRenKeysEff, 0, tiles_x, n_tiles, bins_x,
                                c->ranges, c->cbase, c->items, c->rounds, c->tiles_cap, c->cbase + c->tiles_cap,
-                               c->rcounters, max_chunks, pub.sel_counters, pub.rec, pub.seq);
+                               c->rcounters, max_chunks, ChunkPlan{c->chunk_shift}, pub.sel_counters, pub.rec,
+                               pub.seq);
     }
 }
 
@@ -782,7 +781,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         HIP_TRY(hipMemcpyAsync(c->rcounters + kRenSlots, n_dev, sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
         n_dev = c->rcounters + kRenSlots;
     }
-    ProjectOut po{c->splat, c->depth, c->bin, c->rect, c->tiles, c->dkey[0], c->dval[0], c->rcounters};
+    ProjectOut po{c->splat, c->depth, c->bin, c->tiles, c->dkey[0], c->dval[0], c->rcounters};
     {
         Stage st(c, V3DG_STAGE_PROJECT);
         launch_project(c->stream, c->fdev, sc->attribs(), (int)sc->precision, (int)sc->sh_degree, sel.slot_row,
@@ -835,7 +834,8 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     }
     const uint32_t *k_dev = capacity ? c->rcounters + kRenKeysEff : nullptr;
     // chunk records the plan may use (each tile of a bin walks the bin's list)
-    const uint64_t max_chunks = capacity ? c->cap_chunks : chunk_bound(KL);
+    const uint64_t max_chunks = capacity ? c->cap_chunks : chunk_bound(KL, c->chunk_shift);
+    const ChunkPlan cp{c->chunk_shift};
     const uint32_t n_bins = cam.bins_x * cam.bins_y;
     const uint32_t bin_bits = std::max<uint32_t>(bits_for(n_bins), 1);
     int buf = 0;
@@ -852,7 +852,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     } else {
         {
             Stage st(c, V3DG_STAGE_EMIT);
-            launch_emit64(c->stream, n_dev, S, c->tiles, c->offsets, c->rect, c->bin, c->fdev, c->cap_keys, c->keys[0],
+            launch_emit64(c->stream, n_dev, S, c->tiles, c->offsets, c->bin, c->fdev, c->cap_keys, c->keys[0],
                           c->vals[0], c->rcounters + kRenErr);
         }
         key_bits = 32 + bin_bits;
@@ -861,7 +861,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
             Stage st(c, V3DG_STAGE_RANGES);
             launch_tile_ranges<uint64_t>(c->stream, c->keys[buf], c->rcounters + kRenKeysEff, 32, cam.tiles_x,
                                          n_tiles, cam.bins_x, c->ranges, c->cbase, c->items, c->rounds,
-                                         c->tiles_cap, c->cbase + c->tiles_cap, c->rcounters, max_chunks);
+                                         c->tiles_cap, c->cbase + c->tiles_cap, c->rcounters, max_chunks, cp);
         }
     }
     {
@@ -869,7 +869,7 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
         launch_blend(c->stream, c->fdev, cam.tiles_x, cam.tiles_y, c->splat, c->vals[buf], c->ranges, c->cbase,
                      c->items, c->rounds, c->tiles_cap, c->cbase + c->tiles_cap, c->rcounters, max_chunks, max_chunks,
                      c->scratch, c->pend,
-                     c->need, c->stopm, c->rewalk, c->pairs_dev, c->pair_count);
+                     c->need, c->stopm, c->rewalk, c->pairs_dev, c->pair_count, cp);
         // a frame whose keys did not fit is blended from its depth-sorted slots
         if (pub.fallback && depth_first)
             launch_blend_all(c->stream, c->fdev, n_tiles, c->splat, c->dval[0], c->rcounters, c->pairs_dev,
@@ -1919,6 +1919,31 @@ int v3dg_set_sort_mode(v3dg_scene *s, int mode)
     return V3DG_OK;
 }
 
+namespace {
+// log2 of a later-chunk size: a power of two of 2^kChunkShiftMin ..
+// 2^kChunkShiftMax keys
+bool chunk_shift_of(uint32_t keys, uint32_t *shift)
+{
+    for (uint32_t k = kChunkShiftMin; k <= kChunkShiftMax; ++k)
+        if (keys == (1u << k)) {
+            *shift = k;
+            return true;
+        }
+    return false;
+}
+}  // namespace
+
+int v3dg_set_chunk_keys(v3dg_scene *s, uint32_t keys)
+{
+    g_err.clear();
+    if (!s) return fail(V3DG_ERR_INVALID_ARG, "scene is NULL");
+    uint32_t shift = 0;
+    if (!chunk_shift_of(keys, &shift))
+        return fail(V3DG_ERR_INVALID_ARG, "chunk_keys must be 1024, 2048 or 4096 (got %u)", keys);
+    s->chunk_shift = shift;
+    return V3DG_OK;
+}
+
 int v3dg_set_culling(v3dg_scene *s, int on)
 {
     g_err.clear();
@@ -2079,6 +2104,7 @@ struct v3dg_server {
     int device = 0;
     std::vector<v3dg_scene *> scenes;
     v3dg_server_config cfg{};
+    uint32_t chunk_shift = kChunkShiftServer;  // chunk sizes of the contexts' plans
     hipStream_t sched = nullptr;        // batched selection
     std::vector<SrvCtx *> ctx;
     std::deque<SrvReq> queue;
@@ -2094,9 +2120,13 @@ struct v3dg_server {
 
 namespace {
 
+// device bytes per slot: splat record 48, binning record 32, depth 4, bins
+// touched 4, key offset 4, large-splat list 4, depth-sort keys and values 16
+constexpr uint64_t kSlotBytes = 48 + 32 + 4 + 4 + 4 + 4 + 16;
+
 uint64_t ctx_bytes(const SrvCtx *c)
 {
-    uint64_t b = c->ws_slots * (48 + 32 + 4 + 8 + 4 + 4 + 16);
+    uint64_t b = c->ws_slots * kSlotBytes;
     b += (uint64_t)c->itab_cap * sizeof(InstRec) + sizeof(FrameDev) + 8;
     b += c->rclear_words * 4 + (uint64_t)c->tiles_cap * (8 + 4 * kChunkRounds);
     b += c->cap_keys * 24 + c->sort_status_parts * kRadix * 8;
@@ -2108,13 +2138,13 @@ uint64_t ctx_bytes(const SrvCtx *c)
 // bytes of a context before any image size or key count is provisioned
 uint64_t ctx_base_bytes(const SrvCtx *c)
 {
-    return c->ws_slots * (48 + 32 + 4 + 8 + 4 + 4 + 16) + (uint64_t)c->itab_cap * sizeof(InstRec) +
+    return c->ws_slots * kSlotBytes + (uint64_t)c->itab_cap * sizeof(InstRec) +
            sizeof(FrameDev) + 8 + c->sel.cap_tests * 8 + ((uint64_t)kSelCounters + 2 * c->sel.n_parts) * 4 +
            c->sel.cap_slots * 8;
 }
 
 // bytes context c (nullptr: a new one) would add to hold K keys over n_tiles tiles
-uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
+uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles, uint32_t chunk_shift)
 {
     const uint64_t keys = c ? c->cap_keys : 0, tiles = c ? c->tiles_cap : 0, chunks = c ? c->cap_chunks : 0;
     uint64_t g = 0;
@@ -2122,7 +2152,7 @@ uint64_t growth_bytes(const SrvCtx *c, uint64_t K, uint32_t n_tiles)
     g += (K2 - keys) * 24 + ((K2 - keys + kSortPart - 1) / kSortPart) * 3 / 2 * kRadix * 8;
     const uint64_t T2 = std::max<uint64_t>(std::max<uint64_t>(n_tiles, 8160), tiles);
     g += (T2 - tiles) * (16 + 4 * kChunkRounds);
-    const uint64_t ch = chunk_bound(K2);
+    const uint64_t ch = chunk_bound(K2, chunk_shift);
     if (ch > chunks) g += (ch + ch / 2 - chunks) * (8 + 256 * 16 + 256 * 4 + 4 + 32 + 8);
     return g;
 }
@@ -2189,6 +2219,7 @@ int srv_new_ctx(v3dg_server *s, SrvCtx **out)
 {
     auto *c = new (std::nothrow) SrvCtx();
     if (!c) return fail(V3DG_ERR_OOM, "host allocation failed");
+    c->chunk_shift = s->chunk_shift;
     hipStream_t st = nullptr;
     int rc = V3DG_OK;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) rc = fail(V3DG_ERR_HIP, "stream creation failed");
@@ -2319,12 +2350,16 @@ int v3dg_server_create(v3dg_scene *const *scenes, uint32_t n_scenes, const v3dg_
     if (!scenes || n_scenes == 0 || !cfg || !out) return fail(V3DG_ERR_INVALID_ARG, "NULL argument or no scenes");
     if (cfg->n_contexts < 1 || cfg->n_contexts > 64 || cfg->max_batch < 1 || cfg->max_batch > 64)
         return fail(V3DG_ERR_INVALID_ARG, "n_contexts and max_batch must be 1..64");
+    uint32_t chunk_shift = kChunkShiftServer;
+    if (cfg->chunk_keys != 0 && !chunk_shift_of(cfg->chunk_keys, &chunk_shift))
+        return fail(V3DG_ERR_INVALID_ARG, "chunk_keys must be 0, 1024, 2048 or 4096 (got %u)", cfg->chunk_keys);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     auto *s = new (std::nothrow) v3dg_server();
     if (!s) return fail(V3DG_ERR_OOM, "host allocation failed");
     s->device = dev;
     s->cfg = *cfg;
+    s->chunk_shift = chunk_shift;
     s->t0 = std::chrono::steady_clock::now();
     for (uint32_t i = 0; i < n_scenes; ++i) {
         v3dg_scene *sc = scenes[i];
@@ -2493,14 +2528,14 @@ int v3dg_server_poll(v3dg_server *s, int wait, v3dg_request_done *done, uint32_t
         uint64_t cost = 0;
         for (SrvCtx *x : s->ctx) {
             if (x->busy || std::find(batch.begin(), batch.end(), x) != batch.end()) continue;
-            const uint64_t g = growth_bytes(x, Kneed, n_tiles);
+            const uint64_t g = growth_bytes(x, Kneed, n_tiles, s->chunk_shift);
             if (!c || g < cost) {
                 c = x;
                 cost = g;
             }
         }
         const bool create = !c && s->ctx.size() < s->cfg.n_contexts;
-        if (create) cost = ctx_base_bytes(s->ctx[0]) + growth_bytes(nullptr, Kneed, n_tiles);
+        if (create) cost = ctx_base_bytes(s->ctx[0]) + growth_bytes(nullptr, Kneed, n_tiles, s->chunk_shift);
         if (!c && !create) break;  // every context is busy
         if (s->st.workspace_bytes + cost > s->cfg.hbm_budget_bytes) {
             bool busy = !batch.empty();

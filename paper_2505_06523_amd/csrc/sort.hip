@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ 
                                                    const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ tiles,
                                                    const uint32_t *__restrict__ offsets,
-                                                   const uint2 *__restrict__ rect, const BinRec *__restrict__ bin,
+                                                   const BinRec *__restrict__ bin,
                                                    const FrameDev *__restrict__ fd, uint64_t key_cap,
                                                    void *__restrict__ keys_v, uint32_t *__restrict__ vals,
                                                    uint32_t *err)
@@ -244,9 +244,9 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ 
             continue;
         }
         const uint64_t end = off + nt;
-        const uint2 rc = rect[t];
-        const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
         const BinRec b = bin[t];
+        uint32_t tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;  // an empty box lists nothing (and is flagged below)
+        bin_box(b, fd->cam.width, fd->cam.height, &tx0, &tx1, &ty0, &ty1);
         const uint64_t dbits = __float_as_uint(b.depth);
         for (uint32_t ty = ty0; ty <= ty1; ++ty) {
             uint32_t lo, hi;
@@ -266,14 +266,14 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint32_t *__restrict__ 
 }
 
 void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
-                   const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
-                   uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err)
+                   const uint32_t *offsets, const BinRec *bin, const FrameDev *fd, uint64_t key_cap, uint64_t *keys,
+                   uint32_t *vals, uint32_t *err)
 {
     if (max_n == 0) return;
     uint64_t blocks = (max_n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(emit_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, st, n_dev, (uint32_t)max_n,
-                       (const uint32_t *)nullptr, tiles, offsets, rect, bin, fd, key_cap, (void *)keys, vals, err);
+                       (const uint32_t *)nullptr, tiles, offsets, bin, fd, key_cap, (void *)keys, vals, err);
 }
 
 // Depth-first emission.  Every lane takes one depth rank; its keys (one per
@@ -283,14 +283,17 @@ void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 // larger splats are produced by the whole wavefront, one splat at a time: lane
 // r computes the span of tile row r, and lane l then writes keys l, l + 64, ...
 // of the splat, finding its row by a binary search over the row prefix sums.
-// When the workgroup's range holds at most kStage keys it is assembled in LDS
-// and written out with contiguous stores.  The digit histograms of the tile
+// The first kStage keys of the workgroup's range (up to the first splat left
+// to emit_big_kernel) are assembled in LDS and written out with contiguous
+// stores; the rest go straight to global memory.  A lane takes its key count
+// from consecutive offsets and its bin box from the binning record, so each
+// visible splat costs one 32-byte gather.  The digit histograms of the tile
 // sort are counted per row span: a span of consecutive tile ids adds one to a
 // run of low digits (a difference array over the 256 bins) and to one or two
 // higher digits.
 constexpr int kEmitThreads = 256;
 constexpr uint32_t kSmallKeys = 48;  // measured best of 8..256 on 1080p orbits
-constexpr uint32_t kStage = 2048;
+constexpr uint32_t kStage = 5120;
 
 __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, const DigitPlan &dp, uint32_t *s_d0, uint32_t *s_h,
                                            uint32_t *s_all)
@@ -318,47 +321,53 @@ __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, const DigitPl
     }
 }
 
+template <typename KT>
 struct EmitShared {
     uint32_t d0[257];
     uint32_t h[2 * 256];
     uint32_t all;
-    uint32_t staged;                   // the workgroup's keys go through LDS
+    uint32_t wlen;                     // at most this many keys go through LDS
     uint64_t lo, hi;                   // the workgroup's output range
     uint32_t pre[kEmitThreads / kWave][kWave];   // per wavefront: row prefix sums
     uint32_t base[kEmitThreads / kWave][kWave];  //   and first tile of each row
-    uint32_t key[kStage], val[kStage];
+    uint32_t slot[kEmitThreads];  // slot of each rank of the workgroup
+    KT key[kStage];               // staged keys, and the rank whose slot is
+    uint8_t rank[kStage];         //   each key's value
 };
 
-// key o of the output: into the LDS stage or straight to global memory
+// key q of the workgroup's range (output key lo + q), of the splat of rank r
+// in the workgroup (slot t): into the LDS stage when q < wlen, else straight
+// to global memory
 template <typename KT>
-__device__ __forceinline__ void put_key(EmitShared &sh, bool staged, uint64_t o, uint32_t key, uint32_t val,
-                                        KT *__restrict__ keys, uint32_t *__restrict__ vals)
+__device__ __forceinline__ void put_key(EmitShared<KT> &sh, uint32_t wlen, uint64_t lo, uint32_t q, uint32_t key,
+                                        uint32_t r, uint32_t t, KT *__restrict__ keys, uint32_t *__restrict__ vals)
 {
-    if (staged) {
-        sh.key[o - sh.lo] = key;
-        sh.val[o - sh.lo] = val;
+    if (q < wlen) {
+        sh.key[q] = (KT)key;
+        sh.rank[q] = (uint8_t)r;
     } else {
-        keys[o] = (KT)key;
-        vals[o] = val;
+        keys[lo + q] = (KT)key;
+        vals[lo + q] = t;
     }
 }
 
 // KT: uint16_t when every tile id fits in 16 bits, else uint32_t
 // Splats of more than kBigKeys keys are left to emit_big_kernel: the
 // emission kernel lists them (their rank j) in big[], counted in *n_big.  A
-// workgroup that lists one spans more than kStage keys, so it is never staged
-// and the two kernels never write the same keys.
-constexpr uint32_t kBigKeys = kStage;
+// workgroup's LDS window ends before the keys of the first splat it lists, so
+// the two kernels never write the same keys.
+constexpr uint32_t kBigKeys = 2048;
 
 template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
-    const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
-    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, uint64_t key_cap, DigitPlan dp,
+    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ total, const BinRec *__restrict__ bin,
+    const FrameDev *__restrict__ fd, uint64_t key_cap, DigitPlan dp,
     KT *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *__restrict__ big,
     uint32_t *n_big, uint32_t *err)
 {
-    __shared__ EmitShared sh;
+    __shared__ EmitShared<KT> sh;
+    static_assert(kEmitThreads <= 256, "a rank is stored in one byte");
     const uint32_t n = min(*n_dev, max_n);
     if (blockIdx.x * kEmitThreads >= n) return;  // whole workgroup past the end
     const uint32_t tiles_x = fd->cam.bins_x;  // keys name bins
@@ -369,52 +378,51 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t j = blockIdx.x * kEmitThreads + tid;
     const bool valid = j < n;
     const uint32_t t = valid ? order[j] : 0u;
-    uint32_t nt = valid ? tiles[t] : 0u;
-    const uint64_t off = valid ? offsets[j] : 0u;
+    sh.slot[tid] = t;
+    // the offsets are the exclusive scan of the ranks' key counts: rank j has
+    // the difference to the next offset (the last rank: to the total), so the
+    // count needs no gather by slot
+    const uint32_t off32 = valid ? offsets[j] : 0u;
+    const uint32_t next = valid ? (j + 1 < n ? offsets[j + 1] : total[0]) : 0u;
+    uint32_t nt = next - off32;
+    const uint64_t off = off32;
     // output range of the workgroup: from its first rank to its last rank's end
-    if (tid == 0) sh.lo = off;
+    if (tid == 0) {
+        sh.lo = off;
+        sh.wlen = kStage;
+    }
     if (valid && (j + 1 == n || tid == kEmitThreads - 1)) sh.hi = off + nt;
     if (off + nt > key_cap) {  // the frame's keys exceed the buffers (flagged by the scan too)
         atomicOr(err, kErrKeyCap);
         nt = 0;
     }
     __syncthreads();
-    if (tid == 0) sh.staged = (sh.hi <= key_cap && sh.hi - sh.lo <= kStage) ? 1u : 0u;
+    // the keys of a splat listed for emit_big_kernel are written by that
+    // kernel: the LDS window ends before the first of them
+    if (nt > kBigKeys) atomicMin(&sh.wlen, (uint32_t)(off - sh.lo));
     __syncthreads();
-    const bool staged = sh.staged != 0u;
-    uint2 rc = make_uint2(0u, 0u);
+    // keys [lo, lo + wlen) of the workgroup's range are assembled in LDS, the
+    // rest go straight to global memory (none when the range passes key_cap)
+    const uint64_t wlo = sh.lo;
+    const uint32_t wlen = sh.hi <= key_cap ? (uint32_t)min<uint64_t>(sh.hi - wlo, (uint64_t)sh.wlen) : 0u;
     BinRec b{};
+    uint32_t tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;  // an empty box lists nothing (and is flagged below)
     if (nt) {
-        rc = rect[t];
         b = bin[t];
+        bin_box(b, fd->cam.width, fd->cam.height, &tx0, &tx1, &ty0, &ty1);
     }
-    const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
     // small splats: this lane writes its own run
     if (nt && nt <= kSmallKeys) {
-        // keys left to write; a 32-bit index into the stage when the
-        // workgroup's range is assembled in LDS (uniform), else global stores
-        uint32_t left = nt;
-        uint32_t ol = staged ? (uint32_t)(off - sh.lo) : 0u;
-        uint64_t o = off;
+        uint32_t left = nt;                    // keys left to write
+        uint32_t q = (uint32_t)(off - wlo);    // position in the workgroup's range
         for (uint32_t ty = ty0; ty <= ty1 && left != 0u; ++ty) {
             uint32_t lo, hi;
             if (!bin_row_span(b, ty, tx0, tx1, &lo, &hi)) continue;
             const uint32_t row = ty * tiles_x;
             count_span(row + lo, row + hi, dp, sh.d0, sh.h, &sh.all);
             const uint32_t m = min(hi - lo + 1u, left);
-            if (staged) {
-                for (uint32_t i = 0; i < m; ++i) {
-                    sh.key[ol + i] = row + lo + i;
-                    sh.val[ol + i] = t;
-                }
-                ol += m;
-            } else {
-                for (uint32_t i = 0; i < m; ++i) {
-                    keys[o + i] = (KT)(row + lo + i);
-                    vals[o + i] = t;
-                }
-                o += m;
-            }
+            for (uint32_t i = 0; i < m; ++i) put_key(sh, wlen, wlo, q + i, row + lo + i, (uint32_t)tid, t, keys, vals);
+            q += m;
             left -= m;
         }
         if (left != 0u) atomicOr(err, kErrOverflow);  // counting and emission disagree
@@ -464,7 +472,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
                 for (uint32_t step = kWave / 2; step > 0; step >>= 1)
                     if (sh.pre[wid][r + step] <= q) r += step;
                 const uint64_t o = bo + q;
-                if (o < bend) put_key(sh, staged, o, sh.base[wid][r] + (q - sh.pre[wid][r]), bt, keys, vals);
+                if (o < bend)
+                    put_key(sh, wlen, wlo, (uint32_t)(o - wlo), sh.base[wid][r] + (q - sh.pre[wid][r]),
+                            (uint32_t)(wid * kWave + L), bt, keys, vals);
             }
             __builtin_amdgcn_wave_barrier();
             bo += total;
@@ -472,12 +482,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
         if (bo != bend && lane == 0) atomicOr(err, kErrOverflow);  // counting and emission disagree
     }
     __syncthreads();
-    if (staged) {  // contiguous copy of the assembled range
-        const uint32_t cnt = (uint32_t)(sh.hi - sh.lo);
-        for (uint32_t i = tid; i < cnt; i += kEmitThreads) {
-            keys[sh.lo + i] = (KT)sh.key[i];
-            vals[sh.lo + i] = sh.val[i];
-        }
+    for (uint32_t i = tid; i < wlen; i += kEmitThreads) {  // contiguous copy of the assembled keys
+        keys[wlo + i] = sh.key[i];
+        vals[wlo + i] = sh.slot[sh.rank[i]];
     }
     // digit histograms: prefix of the difference array gives the low-digit counts
     if (tid < kWave) {
@@ -502,8 +509,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
 template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
     const uint32_t *__restrict__ n_big, const uint32_t *__restrict__ big, const uint32_t *__restrict__ order,
-    const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const uint2 *__restrict__ rect,
-    const BinRec *__restrict__ bin, const FrameDev *__restrict__ fd, DigitPlan dp, KT *__restrict__ keys,
+    const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ offsets, const BinRec *__restrict__ bin,
+    const FrameDev *__restrict__ fd, DigitPlan dp, KT *__restrict__ keys,
     uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *err)
 {
     __shared__ uint32_t s_d0[257], s_h[2 * 256], s_all, s_tmp[4];
@@ -519,9 +526,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
     for (uint32_t e = blockIdx.x; e < nb; e += gridDim.x) {
         const uint32_t j = big[e], t = order[j], nt = tiles[t];
         const uint64_t off = offsets[j];
-        const uint2 rc = rect[t];
         const BinRec b = bin[t];
-        const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu, ty1 = rc.y >> 16;
+        uint32_t tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;  // an empty box lists nothing (and is flagged below)
+        bin_box(b, fd->cam.width, fd->cam.height, &tx0, &tx1, &ty0, &ty1);
         uint64_t o = off;
         for (uint32_t rb = ty0; rb <= ty1; rb += kEmitThreads) {
             const uint32_t ty = rb + (uint32_t)tid;
@@ -571,18 +578,18 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
 
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
-                   const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
+                   const uint32_t *tiles, const uint32_t *offsets, const uint32_t *total, const BinRec *bin,
                    const FrameDev *fd, uint64_t key_cap, const DigitPlan &dp, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *big, uint32_t *n_big, uint32_t *err)
 {
     if (max_n == 0) return;
     const uint32_t blocks = (uint32_t)((max_n + kEmitThreads - 1) / kEmitThreads);
     hipLaunchKernelGGL(emit32_kernel<KT>, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order,
-                       tiles, offsets, rect, bin, fd, key_cap, dp, keys, vals, hist, big, n_big, err);
+                       offsets, total, bin, fd, key_cap, dp, keys, vals, hist, big, n_big, err);
     // a fixed grid walks the list (any number of its slots may be large)
     const uint32_t bblocks = (uint32_t)(max_n < 2048 ? max_n : 2048);
     hipLaunchKernelGGL(emit_big_kernel<KT>, dim3(bblocks), dim3(kEmitThreads), 0, st, n_big, big, order, tiles,
-                       offsets, rect, bin, fd, dp, keys, vals, hist, err);
+                       offsets, bin, fd, dp, keys, vals, hist, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -878,7 +885,8 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
                                                           uint32_t *__restrict__ cbase, uint2 *__restrict__ items,
                                                           uint32_t *__restrict__ rounds, uint32_t rcap,
                                                           uint32_t *__restrict__ order, uint32_t *counters,
-                                                          uint32_t max_chunks, const uint32_t *__restrict__ sel_counters,
+                                                          uint32_t max_chunks, ChunkPlan cp,
+                                                          const uint32_t *__restrict__ sel_counters,
                                                           FrameRec *rec, uint32_t seq)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -904,7 +912,7 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
         L = r.y - r.x;
     }
     // chunk records and work items, one atomic per wavefront for each
-    const uint32_t m = (in && L > (uint32_t)kChunkFirst) ? n_chunks(L) : 0u;
+    const uint32_t m = (in && L > cp.first()) ? cp.n_chunks(L) : 0u;
     const uint32_t m_incl = wave_incl_scan_u32(m);
     uint32_t m_base = 0;
     if (lane == kWave - 1 && m_incl) m_base = atomicAdd(&counters[kRenChunks], m_incl);
@@ -939,7 +947,7 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const K *__restrict__ 
     const uint32_t it_first = __shfl(it_base, kWave - 1, kWave) + it_incl - it;
     for (uint32_t j = 0; j < it; ++j) items[it_first + j] = make_uint2(t, (uint32_t)kChunkRounds + 1u + j);
     // blend order: full first chunks at the front, the rest from the back
-    const bool heavy = in && L >= (uint32_t)kChunkFirst;
+    const bool heavy = in && L >= cp.first();
     const uint64_t hb = __ballot(heavy), lb = __ballot(in && !heavy);
     uint32_t fb = 0, bb = 0;
     if (lane == 0) {
@@ -956,19 +964,20 @@ template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t tiles_x,
                         uint32_t n_tiles, uint32_t bins_x, uint2 *ranges, uint32_t *cbase, uint2 *items,
                         uint32_t *rounds, uint32_t rcap, uint32_t *order, uint32_t *counters, uint64_t max_chunks,
-                        const uint32_t *sel_counters, FrameRec *rec, uint32_t seq)
+                        const ChunkPlan &cp, const uint32_t *sel_counters, FrameRec *rec, uint32_t seq)
 {
     hipLaunchKernelGGL(tile_ranges_kernel<K>, dim3((n_tiles + 255) / 256), dim3(256), 0, st, keys, n_dev, shift,
                        tiles_x, n_tiles, bins_x, ranges, cbase, items, rounds, rcap, order, counters,
-                       (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull), sel_counters, rec, seq);
+                       (uint32_t)(max_chunks < 0xffffffffull ? max_chunks : 0xffffffffull), cp, sel_counters, rec,
+                       seq);
 }
 
 template void launch_emit32<uint16_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
-                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t,
+                                      const uint32_t *, const uint32_t *, const BinRec *, const FrameDev *, uint64_t,
                                       const DigitPlan &, uint16_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
                                       uint32_t *);
 template void launch_emit32<uint32_t>(hipStream_t, const uint32_t *, uint64_t, const uint32_t *, const uint32_t *,
-                                      const uint32_t *, const uint2 *, const BinRec *, const FrameDev *, uint64_t,
+                                      const uint32_t *, const uint32_t *, const BinRec *, const FrameDev *, uint64_t,
                                       const DigitPlan &, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
                                       uint32_t *);
 template void launch_sort_hist<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint64_t, int, uint32_t *);
@@ -985,12 +994,15 @@ template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const ui
                                          const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
 template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint32_t,
                                           uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
-                                          uint32_t *, uint64_t, const uint32_t *, FrameRec *, uint32_t);
+                                          uint32_t *, uint64_t, const ChunkPlan &, const uint32_t *, FrameRec *,
+                                          uint32_t);
 template void launch_tile_ranges<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, int, uint32_t, uint32_t,
                                           uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
-                                          uint32_t *, uint64_t, const uint32_t *, FrameRec *, uint32_t);
+                                          uint32_t *, uint64_t, const ChunkPlan &, const uint32_t *, FrameRec *,
+                                          uint32_t);
 template void launch_tile_ranges<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, int, uint32_t, uint32_t,
                                           uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
-                                          uint32_t *, uint64_t, const uint32_t *, FrameRec *, uint32_t);
+                                          uint32_t *, uint64_t, const ChunkPlan &, const uint32_t *, FrameRec *,
+                                          uint32_t);
 
 }  // namespace v3dg

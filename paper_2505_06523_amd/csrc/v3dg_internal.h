@@ -162,6 +162,28 @@ __device__ __forceinline__ bool bin_row_span(const BinRec &b, uint32_t by, uint3
     return true;
 }
 
+// Bins [tx0, tx1] x [ty0, ty1] of the box around the enlarged support of
+// binning record b (half-extents sqrt(Qm Sxx) + 1 and sqrt(Qm Syy) + 1
+// pixels), clipped to the image; false when the box holds no pixel centre.
+// Projection counts a splat's keys over this box and emission lists them over
+// the same box, so both take it from here.
+__device__ __forceinline__ bool bin_box(const BinRec &b, uint32_t width, uint32_t height, uint32_t *tx0,
+                                        uint32_t *tx1, uint32_t *ty0, uint32_t *ty1)
+{
+#pragma clang fp contract(off)
+    const float hx = sqrtf(b.Qm * b.sa) + 1.0f, hy = sqrtf(b.Qm * b.sc) + 1.0f;
+    const float fx0 = fmaxf(ceilf(b.mx - hx - 0.5f), 0.0f);
+    const float fx1 = fminf(floorf(b.mx + hx - 0.5f), (float)(width - 1));
+    const float fy0 = fmaxf(ceilf(b.my - hy - 0.5f), 0.0f);
+    const float fy1 = fminf(floorf(b.my + hy - 0.5f), (float)(height - 1));
+    if (!(fx0 <= fx1 && fy0 <= fy1)) return false;
+    *tx0 = (uint32_t)fx0 / kBin;
+    *tx1 = (uint32_t)fx1 / kBin;
+    *ty0 = (uint32_t)fy0 / kBin;
+    *ty1 = (uint32_t)fy1 / kBin;
+    return true;
+}
+
 // ---- launch wrappers (implemented in the .hip files) ----------------------
 // select.hip
 // Render set-up: itab from the camera and the instances, clearing of the
@@ -234,7 +256,6 @@ struct ProjectOut {
     float4 *splat;      // 3 float4 per slot: (mx,my,A,B) (C,o,r,g) (b,depth,hx,hy)
     float *depth;       // FP32 depth of every slot
     BinRec *bin;        // binning record of visible slots
-    uint2 *rect;        // (tx0 | tx1<<16, ty0 | ty1<<16)
     uint32_t *tiles;    // tiles the support reaches (0 = culled)
     uint32_t *dkey;     // depth sort key: FP32 depth bits, 0xffffffff when culled
     uint32_t *dval;     // slot index (sort payload)
@@ -282,17 +303,19 @@ inline DigitPlan even_digits(uint32_t key_bits)
 }
 // 64-bit keys (bin << 32 | depth bits), slot order
 void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *tiles,
-                   const uint32_t *offsets, const uint2 *rect, const BinRec *bin, const FrameDev *fd,
-                   uint64_t key_cap, uint64_t *keys, uint32_t *vals, uint32_t *err);
+                   const uint32_t *offsets, const BinRec *bin, const FrameDev *fd, uint64_t key_cap, uint64_t *keys,
+                   uint32_t *vals, uint32_t *err);
 // Bin-id keys in depth order (order[j] = slot of depth rank j), with the
 // digit histograms of the bin sort (digits dp, passes <= 3) accumulated into hist.
 // KT = uint16_t for grids of at most kBinKey16Max bins, else uint32_t.
 constexpr uint32_t kBinKey16Max = 1u << 16;
 // (splats of more than 2048 keys are listed in big[] (n_big: a cleared
-// counter; big: max_n entries) and emitted by one workgroup each)
+// counter; big: max_n entries) and emitted by one workgroup each).  Rank j
+// has offsets[j + 1] - offsets[j] keys, the last rank total - offsets[j]
+// (total: the scan's key count, 64 bits as two words).
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
-                   const uint32_t *tiles, const uint32_t *offsets, const uint2 *rect, const BinRec *bin,
+                   const uint32_t *tiles, const uint32_t *offsets, const uint32_t *total, const BinRec *bin,
                    const FrameDev *fd, uint64_t key_cap, const DigitPlan &dp, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *big, uint32_t *n_big, uint32_t *err);
 constexpr int kSortThreads = 256;
@@ -318,11 +341,11 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
                       int shift = -1, int dbits = kRadixBits);
 // Per tile t < n_tiles (tiles_x per row): ranges[t] = [first, end) of the
 // keys of its bin (bins_x per row) in the sorted keys, and the blend plan.  A
-// tile whose bin holds L > kChunkFirst keys gets n_chunks(L) consecutive
+// tile whose bin holds L > cp.first() keys gets cp.n_chunks(L) consecutive
 // chunk records from cbase[t] (kNoChunk for other tiles, and for long ones
 // beyond max_chunks records, which are then blended whole) and one work item
 // (t, c) per chunk c >= 1 (items: counters[kRenItems]).  order is a
-// permutation of the tiles with the lists of at least kChunkFirst keys first,
+// permutation of the tiles with the lists of at least cp.first() keys first,
 // so that the longest walks start first.
 // With rec (a record in mapped pinned host memory), the kernel also publishes
 // the frame's counts there, tagged seq: keys, visible slots and error flags
@@ -331,7 +354,8 @@ template <typename K>
 void launch_tile_ranges(hipStream_t st, const K *keys, const uint32_t *n_dev, int shift, uint32_t tiles_x,
                         uint32_t n_tiles, uint32_t bins_x, uint2 *ranges, uint32_t *cbase, uint2 *items,
                         uint32_t *rounds, uint32_t rcap, uint32_t *order, uint32_t *counters, uint64_t max_chunks,
-                        const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr, uint32_t seq = 0);
+                        const ChunkPlan &cp, const uint32_t *sel_counters = nullptr, struct FrameRec *rec = nullptr,
+                        uint32_t seq = 0);
 // blend.hip
 constexpr uint32_t kPairSlots = 256;  // spread pair counters (see count_pairs)
 // max_items / max_chunks bound the work items and chunks of the plan (grid
@@ -339,12 +363,13 @@ constexpr uint32_t kPairSlots = 256;  // spread pair counters (see count_pairs)
 // items as the range kernel lists them; stopm holds 4 words per chunk record
 // (the later chunks' stopped pixels), zero on entry and left zero.  pairs (2 kPairSlots counters): with count >= 1 its even entries
 // sum the pairs walked, with count 2 its odd entries also sum the pairs taken
-// (alpha >= 1/255 at an active pixel); counting slows the walk.
+// (alpha >= 1/255 at an active pixel); counting slows the walk.  cp: the
+// chunk sizes the range kernel planned with.
 void launch_blend(hipStream_t st, const FrameDev *fd, uint32_t tiles_x, uint32_t tiles_y, const float4 *splat,
                   const uint32_t *vals, const uint2 *ranges, const uint32_t *cbase, const uint2 *items,
                   const uint32_t *rounds, uint32_t rcap, const uint32_t *order, uint32_t *counters, uint64_t max_items,
                   uint64_t max_chunks, float4 *scratch, uint32_t *pend, uint32_t *need, uint64_t *stopm, uint2 *rewalk,
-                  unsigned long long *pairs, int count);
+                  unsigned long long *pairs, int count, ChunkPlan cp);
 // Frames whose keys exceeded the key buffers (kErrKeyCap): every tile walks
 // the n = counters[kRenVisible] visible slots in depth order (order: the
 // depth-sorted slots) and writes its pixels; other frames return at once.

@@ -168,13 +168,14 @@ def bundle_asset(b: dict, sh_degree: int) -> sg.Asset:
                     n_leaf_clusters=int(b["n_leaf_clusters"]))
 
 
-def blend_chunk_sizes() -> tuple[int, int]:
-    """(first, later) chunk sizes in keys of the long-list blending, as the
-    library's plan header defines them."""
+def blend_chunk_sizes(server: bool = False) -> tuple[int, int]:
+    """(first, later) chunk sizes in keys of the long-list blending of scene
+    renders (server=False) or of the serving loop, as the library's plan
+    header defines them: later chunks of 2^shift keys, a first chunk of three."""
     import os
     import re
     h = open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "paper_2505_06523_amd", "csrc",
                           "blend_plan.h")).read()
-    first = int(re.search(r"constexpr int kChunkFirst = (\d+);", h).group(1))
-    later = int(re.search(r"constexpr int kChunk = (\d+);", h).group(1))
-    return first, later
+    name = "kChunkShiftServer" if server else "kChunkShiftRender"
+    shift = int(re.search(r"constexpr uint32_t %s = (\d+);" % name, h).group(1))
+    return 3 << shift, 1 << shift

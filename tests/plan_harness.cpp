@@ -1,6 +1,7 @@
 // Random blend plans against the bounds the runtime sizes its chunk buffers
-// by (blend_plan.h), on the CPU.  Bins get list lengths from a heavy-tailed
-// mix; each of a bin's four tiles asks for n_chunks(L) records, in 64-tile
+// by (blend_plan.h), on the CPU, for every chunk size a plan may take.  Bins
+// get list lengths from a heavy-tailed mix; each of a bin's four tiles asks
+// for n_chunks(L) records, in 64-tile
 // wavefronts taken in a random order, each wavefront reserving a contiguous
 // range as the range kernel's atomic does.  Checked per plan: with buffers of
 // chunk_bound(K) records every long tile is chunked; with any buffer size
@@ -28,28 +29,32 @@ int main(int argc, char **argv)
     const int plans = argc > 1 ? std::atoi(argv[1]) : 2000;
     std::mt19937_64 rng(7);
     for (int p = 0; p < plans; ++p) {
+        const ChunkPlan cp{kChunkShiftMin + (uint32_t)(p % (kChunkShiftMax - kChunkShiftMin + 1))};
+        const uint32_t kFirst = cp.first(), kLater = cp.later();
         const uint32_t n_bins = 1 + (uint32_t)(rng() % 3000);
         std::vector<uint32_t> L(n_bins);
         uint64_t K = 0;
         for (auto &x : L) {
             const uint32_t kind = (uint32_t)(rng() % 10);
             x = kind < 6 ? (uint32_t)(rng() % 2000)                                  // light
-                : kind < 9 ? (uint32_t)(kChunkFirst - 3 + rng() % (4 * kChunk + 7))  // around the cuts
+                : kind < 9 ? (uint32_t)(kFirst - 3 + rng() % (4 * kLater + 7))  // around the cuts
                            : (uint32_t)(rng() % 200000);                            // very long
             K += x;
         }
         // the chunks of a list tile it exactly
         for (uint32_t b = 0; b < n_bins; ++b) {
-            if (L[b] <= (uint32_t)kChunkFirst) continue;
-            const uint32_t m = n_chunks(L[b]);
-            if (chunk_begin(0) != 0 || chunk_end(m - 1, L[b]) != L[b]) return fail("cover", L[b], m);
+            if (L[b] <= kFirst) continue;
+            const uint32_t m = cp.n_chunks(L[b]);
+            if (cp.begin(0) != 0 || cp.end(0, L[b]) != kFirst || cp.end(m - 1, L[b]) != L[b])
+                return fail("cover", L[b], m);
             for (uint32_t c = 0; c < m; ++c) {
-                if (!(chunk_begin(c) < chunk_end(c, L[b]))) return fail("empty chunk", L[b], c);
-                if (c + 1 < m && chunk_end(c, L[b]) != chunk_begin(c + 1)) return fail("gap", L[b], c);
+                if (!(cp.begin(c) < cp.end(c, L[b]))) return fail("empty chunk", L[b], c);
+                if (c > 0 && cp.end(c, L[b]) - cp.begin(c) > kLater) return fail("chunk size", L[b], c);
+                if (c + 1 < m && cp.end(c, L[b]) != cp.begin(c + 1)) return fail("gap", L[b], c);
             }
-            if ((uint64_t)m * kChunk > (uint64_t)L[b]) return fail("records per list", L[b], m);
+            if ((uint64_t)m * kLater > (uint64_t)L[b]) return fail("records per list", L[b], m);
         }
-        const uint64_t bound = chunk_bound(K);
+        const uint64_t bound = chunk_bound(K, cp.shift);
         for (int sz = 0; sz < 3; ++sz) {
             const uint64_t max_chunks = sz == 0 ? bound : sz == 1 ? bound / 3 : rng() % (bound + 1);
             // tiles in 64-wide wavefronts, the wavefronts in a random order
@@ -62,7 +67,7 @@ int main(int argc, char **argv)
                 const uint64_t base = counter;
                 for (uint64_t t = w * 64; t < std::min(n_tiles, w * 64 + 64); ++t) {
                     const uint32_t l = L[t / kTilesPerBin];
-                    const uint32_t m = l > (uint32_t)kChunkFirst ? n_chunks(l) : 0u;
+                    const uint32_t m = l > kFirst ? cp.n_chunks(l) : 0u;
                     const uint64_t first = counter;
                     counter += m;
                     if (m) ++long_tiles;

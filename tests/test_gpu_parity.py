@@ -291,6 +291,13 @@ def test_long_tile_lists_chunked_blending(torch, opacity, seed):
     sc.set_sort_mode(v.V3DG_SORT_KEYS64)
     img2 = sc.render(cam, sel).cpu().numpy()
     assert np.array_equal(img, img2)
+    sc.set_sort_mode(v.V3DG_SORT_DEPTH_FIRST)
+    # the larger chunks of the serving loop, and the largest allowed
+    for ck in (2048, 4096):
+        sc.set_chunk_keys(ck)
+        assert per_tile.max() > 3 * ck  # a first chunk of 3 ck keys and at least one more
+        img3 = sc.render(cam, sel).cpu().numpy()
+        check_image(img3, ref, amb, "stacked o=%s, chunks of %d keys" % (opacity, ck))
     sc.close()
 
 

@@ -18,6 +18,10 @@ from tests.test_gpu_parity import MAX_ABS, MIN_PSNR, _say, check_image, psnr
 
 pytestmark = pytest.mark.gpu
 
+# the serving loop's chunk size of long bin lists: the standalone references
+# render with the same plan, so that images agree bit for bit
+SRV_CHUNK = H.blend_chunk_sizes(server=True)[1]
+
 
 @pytest.fixture(scope="module")
 def torch():
@@ -37,6 +41,8 @@ def worlds():
 @pytest.fixture(scope="module")
 def scenes(torch, worlds):
     out = [v.Scene(a, T) for a, T in worlds]
+    for sc in out:
+        sc.set_chunk_keys(SRV_CHUNK)
     yield out
     for sc in out:
         sc.close()
@@ -153,6 +159,7 @@ def test_server_retries_after_key_overflow(scenes, torch):
     per bin), so its requests overflow whatever the mix."""
     rng = np.random.default_rng(5)
     dense = v.Scene(H.stacked_splats(6000, 5, (0.05, 0.5), log_scale=-1.0), sg.identity_instances(1))
+    dense.set_chunk_keys(SRV_CHUNK)
     all_scenes = list(scenes) + [dense]
     reqs = _requests(rng, 12) + [(3, H.identity_camera(w, h, 300.0 * w / 200.0, bg=(0.1, 0.2, 0.3)), 0.0)
                                  for w, h in [(200, 150), (333, 250), (640, 360)]]
@@ -228,6 +235,40 @@ def test_server_invalid_arguments(scenes, torch):
     srv.close()
     with pytest.raises(v.V3DGError):
         v.Server(scenes, n_contexts=0)
+    for ck in (512, 3000, 8192):  # chunk sizes: 1024, 2048 or 4096 keys (0: the default)
+        with pytest.raises(v.V3DGError):
+            v.Server(scenes, n_contexts=1, chunk_keys=ck)
+        with pytest.raises(v.V3DGError):
+            scenes[0].set_chunk_keys(ck)
+
+
+@pytest.mark.parametrize("chunk_keys", [1024, 4096])
+def test_server_chunk_sizes_equal_standalone(scenes, torch, chunk_keys):
+    """Servers with other chunk sizes than the default equal standalone renders
+    of the same chunk size bit for bit, long lists included (the stacked scene,
+    ~6,000 keys per bin)."""
+    rng = np.random.default_rng(40 + chunk_keys)
+    reqs = _requests(rng, 9) + [(2, H.identity_camera(w, h, 300.0 * w / 200.0, bg=(0.1, 0.2, 0.3)), 0.0)
+                                for w, h in [(200, 150), (640, 360)]]
+    try:
+        for sc in scenes:
+            sc.set_chunk_keys(chunk_keys)
+        ref = _standalone(scenes, torch, reqs)
+        srv = v.Server(scenes, n_contexts=3, max_batch=4, use_graphs=True, chunk_keys=chunk_keys)
+        tickets = {}
+        for i, (k, cam, tau) in enumerate(reqs):
+            t, _ = srv.submit(k, cam, tau)
+            tickets[t] = i
+        done = srv.drain()
+        assert len(done) == len(reqs)
+        for r in done:
+            i = tickets[r["ticket"]]
+            assert r["status"] == 0, r
+            assert torch.equal(r["image"], ref[i][0]), (i, reqs[i][0], reqs[i][2])
+        srv.close()
+    finally:
+        for sc in scenes:
+            sc.set_chunk_keys(SRV_CHUNK)
 
 
 def test_served_images_match_the_oracle(scenes, worlds, torch):

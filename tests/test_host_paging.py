@@ -224,5 +224,7 @@ def test_blend_plan_bounds(tmp_path):
 def test_chunk_sizes_read_from_the_plan_header():
     """The GPU tests size their long lists from the plan header's chunk sizes."""
     from tests import helpers as H
-    first, later = H.blend_chunk_sizes()
-    assert later > 0 and first >= 2 * later
+    for server in (False, True):
+        first, later = H.blend_chunk_sizes(server)
+        assert 1024 <= later <= 4096 and first == 3 * later
+    assert H.blend_chunk_sizes(True)[1] >= H.blend_chunk_sizes(False)[1]
