@@ -40,9 +40,9 @@ WORKLOAD = ("1,048,576-leaf SH3 asset (1,398,080 rows, 21,845 clusters), 1920x10
             "issued through the serving loop with %d frames in flight")
 # render contexts (frames in flight) of the headline pass through v3dg_server,
 # and requests handed to it at once (so that a poll always finds queued work)
-SERVE_CONTEXTS = 3
+SERVE_CONTEXTS = 8
 SERVE_OUTSTANDING = 4 * SERVE_CONTEXTS
-SERVE_CHUNK_KEYS = 2048  # the server's default chunk size of long bin lists
+SERVE_CHUNK_KEYS = 4096  # the server's default chunk size of long bin lists
 HBM_PEAK_GBS = 8000.0
 # Blending is plain FP32 VALU work (no contraction for matrix cores, no pairs
 # of identical independent ops for packed math), so its ceiling is the VALU
@@ -88,6 +88,10 @@ def parse():
     ap.add_argument("--only", choices=["build", "stream", "composed"],
                     help="run only the offline-build, streaming or composed-scene measurement and print its JSON "
                          "(for rocprofv3)")
+    ap.add_argument("--serve-contexts", type=int, default=SERVE_CONTEXTS,
+                    help="render contexts (frames in flight) of the headline serving-loop pass")
+    ap.add_argument("--serve-chunk-keys", type=int, default=SERVE_CHUNK_KEYS, choices=[1024, 2048, 4096],
+                    help="chunk size of long bin lists in the headline serving-loop pass")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the warm-up and one pass of the timed V3DG frames (for rocprofv3: with --warmup 0 its "
                          "per-kernel averages cover exactly the launches of the roofline)")
@@ -631,7 +635,11 @@ def stream_bench(torch, v, sg, asset):
 
 
 def main():
+    global SERVE_CONTEXTS, SERVE_OUTSTANDING, SERVE_CHUNK_KEYS
     args = parse()
+    SERVE_CONTEXTS = max(1, min(args.serve_contexts, 16))
+    SERVE_OUTSTANDING = 4 * SERVE_CONTEXTS
+    SERVE_CHUNK_KEYS = args.serve_chunk_keys
     # Every render context of the serving loop issues its frames on a stream
     # of its own.  HIP spreads a process's streams over GPU_MAX_HW_QUEUES
     # hardware queues (4 by default), and two contexts whose streams share a
@@ -642,7 +650,7 @@ def main():
         hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
     except ValueError:
         hwq = 0
-    os.environ["GPU_MAX_HW_QUEUES"] = str(max(hwq, 12))
+    os.environ["GPU_MAX_HW_QUEUES"] = str(max(hwq, 12, SERVE_CONTEXTS + 4))
     if args.gpus != 1:
         print("bench.py measures one GPU: the per-frame path runs on a single MI355X "
               "(frames and requests shard across GPUs by routing whole frames; not built here). "

@@ -322,7 +322,7 @@ int v3dg_set_culling(v3dg_scene *scene, int on);
  * walked again where a pixel stops (the sequential result up to the
  * association of FP32 products).  Smaller chunks shorten a frame's longest
  * walk; larger ones walk fewer pairs twice, which pays when several frames
- * share the device (the serving loop's default is 2048).  keys: 1024, 2048
+ * share the device (the serving loop's default is 4096).  keys: 1024, 2048
  * or 4096, else V3DG_ERR_INVALID_ARG.  Images of different chunk sizes may
  * differ in the last bits. */
 int v3dg_set_chunk_keys(v3dg_scene *scene, uint32_t keys);
@@ -394,7 +394,7 @@ typedef struct {
                                    most keys seen                                          */
     uint32_t cull;              /* 1: view culling of the cut, as v3dg_set_culling          */
     uint32_t chunk_keys;        /* keys per later chunk of long bin lists, as
-                                   v3dg_set_chunk_keys (0: 2048)                           */
+                                   v3dg_set_chunk_keys (0: 4096)                           */
 } v3dg_server_config;
 
 typedef struct {

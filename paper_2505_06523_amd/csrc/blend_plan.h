@@ -23,7 +23,7 @@ constexpr uint32_t kNoChunk = 0xffffffffu;  // chunk base of a tile blended whol
 // when other frames keep the chip busy meanwhile.
 constexpr uint32_t kChunkShiftMin = 10, kChunkShiftMax = 12;  // later chunks of 1,024 .. 4,096 keys
 constexpr uint32_t kChunkShiftRender = 10;  // v3dg_render: 3,072 / 1,024 keys
-constexpr uint32_t kChunkShiftServer = 11;  // the serving loop: 6,144 / 2,048 keys
+constexpr uint32_t kChunkShiftServer = 12;  // the serving loop: 12,288 / 4,096 keys
 
 // A list of L > first() keys is cut into a first chunk of first() keys and
 // further chunks of later(): n_chunks(L) chunks, chunk c holding keys

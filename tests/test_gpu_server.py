@@ -242,7 +242,7 @@ def test_server_invalid_arguments(scenes, torch):
             scenes[0].set_chunk_keys(ck)
 
 
-@pytest.mark.parametrize("chunk_keys", [1024, 4096])
+@pytest.mark.parametrize("chunk_keys", [1024, 2048])
 def test_server_chunk_sizes_equal_standalone(scenes, torch, chunk_keys):
     """Servers with other chunk sizes than the default equal standalone renders
     of the same chunk size bit for bit, long lists included (the stacked scene,
