@@ -28,6 +28,32 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(v.EXPORTS)
 
 
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """Every structure the binding passes through the ABI has the size and the
+    field offsets of its C declaration in include/v3dg.h (compiled with gcc),
+    field for field by name."""
+    import subprocess
+    structs = [v.v3dg_camera, v.v3dg_hierarchy_desc, v.v3dg_frame_stats, v.v3dg_stream_stats, v.v3dg_profile,
+               v.v3dg_server_config, v.v3dg_request_done, v.v3dg_server_stats]
+    lines = ['#include "v3dg.h"', "#include <stddef.h>", "#include <stdio.h>", "int main(void)", "{"]
+    for S in structs:
+        n = S.__name__
+        lines.append('    printf("%s %%zu\\n", sizeof(%s));' % (n, n))
+        for f in S._fields_:
+            lines.append('    printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (n, f[0], n, f[0]))
+    lines += ["    return 0;", "}"]
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.splitlines())
+    for S in structs:
+        assert int(got[S.__name__]) == C.sizeof(S), S.__name__
+        for f in S._fields_:
+            assert int(got[S.__name__ + "." + f[0]]) == getattr(S, f[0]).offset, (S.__name__, f[0])
+
+
 def test_last_error_initially_empty():
     assert isinstance(v.last_error(), str)
 
