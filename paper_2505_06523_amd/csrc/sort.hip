@@ -293,6 +293,8 @@ void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 // higher digits.
 constexpr int kEmitThreads = 256;
 constexpr uint32_t kSmallKeys = 48;  // measured best of 8..256 on 1080p orbits
+// keys assembled in LDS per workgroup: at 3 bytes each (16-bit key, rank),
+// 5,120 keys keep the kernel at 7 waves per SIMD
 constexpr uint32_t kStage = 5120;
 
 __device__ __forceinline__ void count_span(uint32_t a, uint32_t b, const DigitPlan &dp, uint32_t *s_d0, uint32_t *s_h,
