@@ -41,7 +41,7 @@ WORKLOAD = ("1,048,576-leaf SH3 asset (1,398,080 rows, 21,845 clusters), 1920x10
 # render contexts (frames in flight) of the headline pass through v3dg_server,
 # and requests handed to it at once (so that a poll always finds queued work)
 SERVE_CONTEXTS = 8
-SERVE_OUTSTANDING = 4 * SERVE_CONTEXTS
+SERVE_OUTSTANDING = 2 * SERVE_CONTEXTS
 SERVE_CHUNK_KEYS = 4096  # the server's default chunk size of long bin lists
 HBM_PEAK_GBS = 8000.0
 # Blending is plain FP32 VALU work (no contraction for matrix cores, no pairs
@@ -638,7 +638,7 @@ def main():
     global SERVE_CONTEXTS, SERVE_OUTSTANDING, SERVE_CHUNK_KEYS
     args = parse()
     SERVE_CONTEXTS = max(1, min(args.serve_contexts, 16))
-    SERVE_OUTSTANDING = 4 * SERVE_CONTEXTS
+    SERVE_OUTSTANDING = 2 * SERVE_CONTEXTS
     SERVE_CHUNK_KEYS = args.serve_chunk_keys
     # Every render context of the serving loop issues its frames on a stream
     # of its own.  HIP spreads a process's streams over GPU_MAX_HW_QUEUES
