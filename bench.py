@@ -61,7 +61,7 @@ BLEND_OPS_PER_PAIR = 24
 # Valid only for the blending source they were taken on (blend.hip, the
 # constants of v3dg_internal.h and the chunk sizes of blend_plan.h) and for
 # that many timed frames: the bench reports null otherwise.
-BLEND_TRAFFIC = dict(bytes_per_frame=717666437, frames=20, blend_source_sha256_16="0cb8b23cbc927535")
+BLEND_TRAFFIC = dict(bytes_per_frame=718348592, frames=20, blend_source_sha256_16="ae77f12bf29de9ba")
 
 
 def log(*a):
@@ -139,10 +139,11 @@ def stage_bytes(P: dict, b_row: int) -> dict:
       depth sort 4 B per slot for the histogram + 4 passes x 16 B (key and
                  value, read and written)
       scan       12 B per slot (depth order, tile count gathered, offset)
-      emit       8 B per slot (depth order, offset; a rank's key count is
-                 the difference of consecutive offsets) + the 32-B binning
-                 record per visible slot + (kb + 4) B per key written; its
-                 digit histograms are counted in place
+      emit       40 B per visible slot (depth order and offset, a rank's key
+                 count being the difference of consecutive offsets, and the
+                 32-B binning record; culled slots sort last and are not
+                 read) + (kb + 4) B per key written; its digit histograms are
+                 counted in place
       sort_hist  kb B per key (the 64-bit-key mode only: the depth-first
                  binning takes its histograms from emission)
       sort_pass  2 (kb + 4) B per key and pass (key and value, read and
@@ -167,7 +168,7 @@ def stage_bytes(P: dict, b_row: int) -> dict:
         "project": P["slots"] * 40 + P["visible"] * ((b_row - 16) + 80),
         "depth_sort": P["slots"] * (4 + 4 * 16) * (P["depth_sorts"] / fr),
         "scan": P["slots"] * 12,
-        "emit": P["slots"] * 8 + P["visible"] * 32 + P["keys"] * (kb + 4),
+        "emit": P["visible"] * 40 + P["keys"] * (kb + 4),
         "sort_hist": 0 if depth_first else P["keys"] * kb,
         "sort_pass": P["keys"] * (2 * (kb + 4)) * passes,
         "ranges": P["tiles"] * (search + 16),

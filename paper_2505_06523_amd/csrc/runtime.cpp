@@ -721,7 +721,7 @@ void tile_keys(Ctx *c, const uint32_t *n_dev, uint64_t S, const uint32_t *k_dev,
     const DigitPlan dp = even_digits(key_bits);
     {
         Stage st(c, V3DG_STAGE_EMIT);
-        launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rcounters + kRenKeysLo, c->bin,
+        launch_emit32<KT>(c->stream, n_dev, S, c->dval[0], c->tiles, c->offsets, c->rcounters, c->bin,
                           c->fdev, c->cap_keys, dp, kb[0], c->vals[0], c->rcounters + kRenHist, c->big,
                           c->rcounters + kRenBig, c->rcounters + kRenErr);
     }

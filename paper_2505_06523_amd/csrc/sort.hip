@@ -363,14 +363,16 @@ constexpr uint32_t kBigKeys = 2048;
 template <typename KT>
 __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     const uint32_t *__restrict__ n_dev, uint32_t max_n, const uint32_t *__restrict__ order,
-    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ total, const BinRec *__restrict__ bin,
+    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ scan_ctr, const BinRec *__restrict__ bin,
     const FrameDev *__restrict__ fd, uint64_t key_cap, DigitPlan dp,
     KT *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t *__restrict__ big,
     uint32_t *n_big, uint32_t *err)
 {
     __shared__ EmitShared<KT> sh;
     static_assert(kEmitThreads <= 256, "a rank is stored in one byte");
-    const uint32_t n = min(*n_dev, max_n);
+    // culled slots (no key) sort after every visible one: only the first
+    // kRenVisible ranks emit, and the last of them ends at the frame's total
+    const uint32_t n = min(min(*n_dev, max_n), scan_ctr[kRenVisible]);
     if (blockIdx.x * kEmitThreads >= n) return;  // whole workgroup past the end
     const uint32_t tiles_x = fd->cam.bins_x;  // keys name bins
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -385,7 +387,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit32_kernel(
     // the difference to the next offset (the last rank: to the total), so the
     // count needs no gather by slot
     const uint32_t off32 = valid ? offsets[j] : 0u;
-    const uint32_t next = valid ? (j + 1 < n ? offsets[j + 1] : total[0]) : 0u;
+    const uint32_t next = valid ? (j + 1 < n ? offsets[j + 1] : scan_ctr[kRenKeysLo]) : 0u;
     uint32_t nt = next - off32;
     const uint64_t off = off32;
     // output range of the workgroup: from its first rank to its last rank's end
@@ -580,14 +582,14 @@ __global__ void __launch_bounds__(kEmitThreads) emit_big_kernel(
 
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
-                   const uint32_t *tiles, const uint32_t *offsets, const uint32_t *total, const BinRec *bin,
+                   const uint32_t *tiles, const uint32_t *offsets, const uint32_t *scan_ctr, const BinRec *bin,
                    const FrameDev *fd, uint64_t key_cap, const DigitPlan &dp, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *big, uint32_t *n_big, uint32_t *err)
 {
     if (max_n == 0) return;
     const uint32_t blocks = (uint32_t)((max_n + kEmitThreads - 1) / kEmitThreads);
     hipLaunchKernelGGL(emit32_kernel<KT>, dim3(blocks), dim3(kEmitThreads), 0, st, n_dev, (uint32_t)max_n, order,
-                       offsets, total, bin, fd, key_cap, dp, keys, vals, hist, big, n_big, err);
+                       offsets, scan_ctr, bin, fd, key_cap, dp, keys, vals, hist, big, n_big, err);
     // a fixed grid walks the list (any number of its slots may be large)
     const uint32_t bblocks = (uint32_t)(max_n < 2048 ? max_n : 2048);
     hipLaunchKernelGGL(emit_big_kernel<KT>, dim3(bblocks), dim3(kEmitThreads), 0, st, n_big, big, order, tiles,

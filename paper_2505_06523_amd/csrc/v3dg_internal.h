@@ -311,11 +311,13 @@ void launch_emit64(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const 
 constexpr uint32_t kBinKey16Max = 1u << 16;
 // (splats of more than 2048 keys are listed in big[] (n_big: a cleared
 // counter; big: max_n entries) and emitted by one workgroup each).  Rank j
-// has offsets[j + 1] - offsets[j] keys, the last rank total - offsets[j]
-// (total: the scan's key count, 64 bits as two words).
+// has offsets[j + 1] - offsets[j] keys; scan_ctr (the render counters the
+// scan filled) gives the visible ranks, scan_ctr[kRenVisible] (culled slots
+// sort last), and the key total, scan_ctr[kRenKeysLo], where the last visible
+// rank's keys end.
 template <typename KT>
 void launch_emit32(hipStream_t st, const uint32_t *n_dev, uint64_t max_n, const uint32_t *order,
-                   const uint32_t *tiles, const uint32_t *offsets, const uint32_t *total, const BinRec *bin,
+                   const uint32_t *tiles, const uint32_t *offsets, const uint32_t *scan_ctr, const BinRec *bin,
                    const FrameDev *fd, uint64_t key_cap, const DigitPlan &dp, KT *keys, uint32_t *vals, uint32_t *hist,
                    uint32_t *big, uint32_t *n_big, uint32_t *err);
 constexpr int kSortThreads = 256;
