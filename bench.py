@@ -61,7 +61,7 @@ BLEND_OPS_PER_PAIR = 24
 # Valid only for the blending source they were taken on (blend.hip, the
 # constants of v3dg_internal.h and the chunk sizes of blend_plan.h) and for
 # that many timed frames: the bench reports null otherwise.
-BLEND_TRAFFIC = dict(bytes_per_frame=718348592, frames=20, blend_source_sha256_16="ae77f12bf29de9ba")
+BLEND_TRAFFIC = dict(bytes_per_frame=718500797, frames=20, blend_source_sha256_16="104acc156a6adfa1")
 
 
 def log(*a):
@@ -138,7 +138,8 @@ def stage_bytes(P: dict, b_row: int) -> dict:
                  binning 32)
       depth sort 4 B per slot for the histogram + 4 passes x 16 B (key and
                  value, read and written)
-      scan       12 B per slot (depth order, tile count gathered, offset)
+      scan       12 B per visible slot (depth order, tile count gathered,
+                 offset; culled slots sort last and are not scanned)
       emit       40 B per visible slot (depth order and offset, a rank's key
                  count being the difference of consecutive offsets, and the
                  32-B binning record; culled slots sort last and are not
@@ -167,7 +168,7 @@ def stage_bytes(P: dict, b_row: int) -> dict:
         "expand": P["sel_clusters"] * 16 + P["slots"] * 8,
         "project": P["slots"] * 40 + P["visible"] * ((b_row - 16) + 80),
         "depth_sort": P["slots"] * (4 + 4 * 16) * (P["depth_sorts"] / fr),
-        "scan": P["slots"] * 12,
+        "scan": P["visible"] * 12,
         "emit": P["visible"] * 40 + P["keys"] * (kb + 4),
         "sort_hist": 0 if depth_first else P["keys"] * kb,
         "sort_pass": P["keys"] * (2 * (kb + 4)) * passes,

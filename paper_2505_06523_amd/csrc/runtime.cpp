@@ -808,7 +808,10 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     }
     {
         Stage st(c, V3DG_STAGE_SCAN);
-        launch_scan_tiles(c->stream, c->tiles, depth_first ? c->dval[0] : nullptr, n_dev, S, c->offsets,
+        // culled slots hold the key 0xffffffff, and no visible depth has a top
+        // byte of 0xff: the depth histogram's last bin of the top digit counts them
+        const uint32_t *n_culled = depth_first ? c->rcounters + kRenHistDepth + 3 * kRadix + (kRadix - 1) : nullptr;
+        launch_scan_tiles(c->stream, c->tiles, depth_first ? c->dval[0] : nullptr, n_dev, n_culled, S, c->offsets,
                           c->scan_status, c->rcounters, capacity ? c->cap_keys : 0xffffffffull);
     }
     uint64_t KL;  // key bound of the launches below

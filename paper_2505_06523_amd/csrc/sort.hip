@@ -86,6 +86,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, uint32_t
 __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t *__restrict__ tiles,
                                                                   const uint32_t *__restrict__ order,
                                                                   const uint32_t *__restrict__ n_dev,
+                                                                  const uint32_t *__restrict__ n_culled,
                                                                   uint32_t *__restrict__ offsets,
                                                                   uint64_t *__restrict__ status, uint32_t *counters,
                                                                   uint64_t key_cap)
@@ -94,7 +95,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
     __shared__ uint64_t s_wave[kScanThreads / kWave];
     __shared__ uint64_t s_prefix;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint32_t n = *n_dev;
+    // the last *n_culled ranks are culled slots (no keys): not scanned
+    const uint32_t n_all = *n_dev, n = n_culled ? n_all - min(n_all, *n_culled) : n_all;
     const uint32_t nparts = (n + kScanPart - 1) / kScanPart;
     if (tid == 0)
         s_ticket = __hip_atomic_fetch_add(&counters[kRenTicketScan], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -209,13 +211,14 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const uint32_t
 }
 
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
-                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap)
+                       const uint32_t *n_culled, uint64_t max_n, uint32_t *offsets, uint64_t *status,
+                       uint32_t *counters, uint64_t key_cap)
 {
     uint64_t blocks = (max_n + kScanPart - 1) / kScanPart;
     if (blocks < 1) blocks = 1;
     if (key_cap > 0xffffffffull) key_cap = 0xffffffffull;
     hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)blocks), dim3(kScanThreads), 0, st, tiles, order, n_dev,
-                       offsets, status, counters, key_cap);
+                       n_culled, offsets, status, counters, key_cap);
 }
 
 // ---------------------------------------------------------------------------

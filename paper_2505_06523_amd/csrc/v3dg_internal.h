@@ -274,9 +274,12 @@ constexpr int kScanPart = kScanThreads * kScanItems;
 // exclusive scan of tiles[order[j]] (order may be NULL: identity); the total
 // goes to kRenKeysLo/Hi and to kRenKeysEff when it is at most key_cap (else
 // kRenKeysEff = 0 and kErrKeyCap is raised: the frame's later steps then
-// have no keys to work on)
+// have no keys to work on).  n_culled (may be NULL): the number of ranks at
+// the end that hold culled slots (depth order puts them last), which are
+// not scanned; their offsets are not written.
 void launch_scan_tiles(hipStream_t st, const uint32_t *tiles, const uint32_t *order, const uint32_t *n_dev,
-                       uint64_t max_n, uint32_t *offsets, uint64_t *status, uint32_t *counters, uint64_t key_cap);
+                       const uint32_t *n_culled, uint64_t max_n, uint32_t *offsets, uint64_t *status,
+                       uint32_t *counters, uint64_t key_cap);
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 256;
 // Digits of a radix sort: pass p orders the keys by bits [shift[p], shift[p]
