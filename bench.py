@@ -61,7 +61,7 @@ BLEND_OPS_PER_PAIR = 24
 # Valid only for the blending source they were taken on (blend.hip, the
 # constants of v3dg_internal.h and the chunk sizes of blend_plan.h) and for
 # that many timed frames: the bench reports null otherwise.
-BLEND_TRAFFIC = dict(bytes_per_frame=718500797, frames=20, blend_source_sha256_16="104acc156a6adfa1")
+BLEND_TRAFFIC = dict(bytes_per_frame=717003824, frames=20, blend_source_sha256_16="269009724026a7ea")
 
 
 def log(*a):
@@ -136,8 +136,10 @@ def stage_bytes(P: dict, b_row: int) -> dict:
                  sort value, tile count 16) + per visible slot the other
                  B_row - 16 attribute bytes and 80 B of records (splat 48,
                  binning 32)
-      depth sort 4 B per slot for the histogram + 4 passes x 16 B (key and
-                 value, read and written)
+      depth sort 4 B per slot for the histogram; the first pass reads the
+                 key and value of every slot (8 B) and writes those of the
+                 visible ones (culled slots are left out), the 3 others read
+                 and write 16 B per visible slot
       scan       12 B per visible slot (depth order, tile count gathered,
                  offset; culled slots sort last and are not scanned)
       emit       40 B per visible slot (depth order and offset, a rank's key
@@ -167,7 +169,7 @@ def stage_bytes(P: dict, b_row: int) -> dict:
         "select": P["tests"] * 32 + P["sel_clusters"] * 8,
         "expand": P["sel_clusters"] * 16 + P["slots"] * 8,
         "project": P["slots"] * 40 + P["visible"] * ((b_row - 16) + 80),
-        "depth_sort": P["slots"] * (4 + 4 * 16) * (P["depth_sorts"] / fr),
+        "depth_sort": (P["slots"] * (4 + 8) + P["visible"] * (8 + 3 * 16)) * (P["depth_sorts"] / fr),
         "scan": P["visible"] * 12,
         "emit": P["visible"] * 40 + P["keys"] * (kb + 4),
         "sort_hist": 0 if depth_first else P["keys"] * kb,

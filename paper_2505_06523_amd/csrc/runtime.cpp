@@ -791,26 +791,31 @@ int enqueue_frame(Ctx *c, v3dg_scene *sc, const CamArgs &cam, float *image, cons
     const bool depth_first = capacity || c->sort_mode == V3DG_SORT_DEPTH_FIRST;
     fi->depth_first = depth_first;
     if (depth_first) {
-        // stable sort of the slots by FP32 depth bits (culled slots last)
+        // stable sort of the visible slots by FP32 depth bits: the culled ones
+        // (key 0xffffffff) are counted by the histogram and left out by the
+        // first pass, so the later passes and every step after them take the
+        // first n - culled ranks only
         {
             Stage st(c, V3DG_STAGE_DEPTH_SORT);
-            launch_sort_hist<uint32_t>(c->stream, c->dkey[0], n_dev, S, 4, c->rcounters + kRenHistDepth);
+            launch_sort_hist<uint32_t>(c->stream, c->dkey[0], n_dev, S, 4, c->rcounters + kRenHistDepth,
+                                       c->rcounters + kRenCulled);
         }
         int cur = 0;
         for (int p = 0; p < 4; ++p) {
             Stage st(c, V3DG_STAGE_DEPTH_SORT);
-            launch_sort_pass<uint32_t>(c->stream, c->dkey[cur], c->dval[cur], c->dkey[cur ^ 1], c->dval[cur ^ 1], n_dev,
-                                       S, p, c->rcounters + kRenHistDepth, c->sort_status, &c->fdev->epoch,
-                                       (uint32_t)p, c->rcounters + kRenTicketDepth + p, c->rcounters + kRenErr,
-                                       S >= kSortWideFrom);
+            launch_sort_pass<uint32_t>(c->stream, c->dkey[cur], c->dval[cur], c->dkey[cur ^ 1], c->dval[cur ^ 1],
+                                       p == 0 ? n_dev : c->rcounters + kRenDepthKept, S, p,
+                                       c->rcounters + kRenHistDepth, c->sort_status, &c->fdev->epoch, (uint32_t)p,
+                                       c->rcounters + kRenTicketDepth + p, c->rcounters + kRenErr, S >= kSortWideFrom,
+                                       -1, kRadixBits, p == 0 ? c->rcounters + kRenCulled : nullptr,
+                                       p == 0 ? c->rcounters + kRenDepthKept : nullptr);
             cur ^= 1;
         }
     }
     {
         Stage st(c, V3DG_STAGE_SCAN);
-        // culled slots hold the key 0xffffffff, and no visible depth has a top
-        // byte of 0xff: the depth histogram's last bin of the top digit counts them
-        const uint32_t *n_culled = depth_first ? c->rcounters + kRenHistDepth + 3 * kRadix + (kRadix - 1) : nullptr;
+        // the depth sort left the culled slots out (the histogram counted them)
+        const uint32_t *n_culled = depth_first ? c->rcounters + kRenCulled : nullptr;
         launch_scan_tiles(c->stream, c->tiles, depth_first ? c->dval[0] : nullptr, n_dev, n_culled, S, c->offsets,
                           c->scan_status, c->rcounters, capacity ? c->cap_keys : 0xffffffffull);
     }

@@ -610,11 +610,15 @@ constexpr int kHistItems = 4;
 template <typename K>
 __global__ void __launch_bounds__(kHistThreads) sort_hist_kernel(const K *__restrict__ keys,
                                                                  const uint32_t *__restrict__ n_dev, uint64_t n_host,
-                                                                 int passes, uint32_t *__restrict__ hist)
+                                                                 int passes, uint32_t *__restrict__ hist,
+                                                                 uint32_t *__restrict__ dropped)
 {
     __shared__ uint32_t s_h[8 * kRadix];
+    __shared__ uint32_t s_drop;
     for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x) s_h[i] = 0;
+    if (threadIdx.x == 0) s_drop = 0u;
     __syncthreads();
+    uint32_t my_drop = 0;
     const uint64_t n = n_dev ? min((uint64_t)*n_dev, n_host) : n_host;
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -632,7 +636,11 @@ __global__ void __launch_bounds__(kHistThreads) sort_hist_kernel(const K *__rest
         }
 #pragma unroll
         for (int u = 0; u < kHistItems; ++u) {
-            const bool valid = base + u * stride + lane < n;
+            bool valid = base + u * stride + lane < n;
+            if (dropped && valid && kk[u] == (K)~(K)0) {  // a dropped key: counted apart
+                valid = false;
+                ++my_drop;
+            }
             for (int p = 0; p < passes; ++p) {
                 const uint32_t d = (uint32_t)(kk[u] >> (p * kRadixBits)) & (kRadix - 1);
                 const uint64_t peers = match_digit(d, valid);
@@ -640,19 +648,22 @@ __global__ void __launch_bounds__(kHistThreads) sort_hist_kernel(const K *__rest
             }
         }
     }
+    if (dropped && my_drop) atomicAdd(&s_drop, my_drop);
     __syncthreads();
     for (int i = threadIdx.x; i < passes * kRadix; i += blockDim.x)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+    if (dropped && threadIdx.x == 0 && s_drop) atomicAdd(dropped, s_drop);
 }
 
 template <typename K>
-void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist)
+void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist,
+                      uint32_t *dropped)
 {
     if (n == 0) return;
     uint64_t blocks = (n + kHistThreads * kHistItems - 1) / (kHistThreads * kHistItems);
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(sort_hist_kernel<K>, dim3((uint32_t)blocks), dim3(kHistThreads), 0, st, keys, n_dev, n, passes,
-                       hist);
+                       hist, dropped);
 }
 
 // ---------------------------------------------------------------------------
@@ -666,12 +677,14 @@ __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint3
 
 // 16-bit keys: three workgroups per CU fit in LDS, so registers are held to
 // three waves per SIMD as well
-template <typename K, int ITEMS>
-__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 2 ? 3 : 1)))
-sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, K *__restrict__ keys_out,
-                 uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
-                 uint32_t dbits, const uint32_t *__restrict__ hist, uint64_t *status,
-                 const uint32_t *__restrict__ epoch_dev, uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
+template <typename K, int ITEMS, bool DROP>
+__device__ __forceinline__ void sort_pass_body(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+                                               K *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+                                               const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
+                                               uint32_t dbits, const uint32_t *__restrict__ hist, uint64_t *status,
+                                               const uint32_t *__restrict__ epoch_dev, uint32_t epoch_arg,
+                                               uint32_t *ticket, uint32_t *err, const uint32_t *__restrict__ dropped,
+                                               uint32_t *__restrict__ n_kept)
 {
     constexpr int NW = kSortThreads / kWave;           // waves per block
     constexpr int PART = kSortThreads * ITEMS;         // keys of a partition
@@ -686,7 +699,15 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
     __shared__ uint32_t s_ticket;
 
     const int wid = (int)threadIdx.x / kWave;
+    // DROP: this pass leaves out the keys of all ones (*dropped of them,
+    // counted apart by the histogram, which does not count their digits) and
+    // writes the count of the others to *n_kept, the key count of the passes
+    // after it.  A template parameter: the test costs the other passes
+    // registers (the 16-bit pass spilled)
     const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+    if constexpr (DROP) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *n_kept = n - min(n, *dropped);
+    }
     const uint32_t epoch = epoch_dev ? *epoch_dev + epoch_arg : epoch_arg;
     const uint32_t nparts = (n + PART - 1) / PART;
     const uint32_t dmask = (1u << dbits) - 1u;  // digits d > dmask never occur: no look-back for them
@@ -732,7 +753,7 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t idx = wave_base + r * kWave + lane;
-        const bool valid = idx < n;
+        const bool valid = idx < n && !(DROP && key[r] == (K)~(K)0);
         const K k = key[r];
         const uint32_t d = (uint32_t)(k >> shift) & dmask;
         const uint64_t peers = match_digit(d, valid, dbits);
@@ -794,7 +815,7 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const uint32_t idx = wave_base + r * kWave + lane;
-        if (idx < n) {
+        if (idx < n && !(DROP && key[r] == (K)~(K)0)) {
             const uint32_t dd = dr[r] & (kRadix - 1);
             const uint32_t pos = s_lstart[dd] + s_whist[wid][dd] + (dr[r] >> 8);
             s_keys[pos] = key[r];
@@ -802,7 +823,8 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
         }
     }
     __syncthreads();
-    const uint32_t n_here = (n - part_base) < (uint32_t)PART ? (n - part_base) : (uint32_t)PART;
+    // keys of the partition in LDS (those not dropped: tot_all)
+    const uint32_t n_here = DROP ? tot_all : ((n - part_base) < (uint32_t)PART ? (n - part_base) : (uint32_t)PART);
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t i = tid + r * kSortThreads;
@@ -818,6 +840,31 @@ sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ val
     }
     __syncthreads();  // the next partition reuses the LDS arrays and the ticket word
     }
+}
+
+// The pass kernel; sort_pass_drop_kernel is the same pass with DROP, a kernel
+// of its own so that the extra arguments cost the others nothing.
+template <typename K, int ITEMS>
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 2 ? 3 : 1)))
+sort_pass_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, K *__restrict__ keys_out,
+                 uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
+                 uint32_t dbits, const uint32_t *__restrict__ hist, uint64_t *status,
+                 const uint32_t *__restrict__ epoch_dev, uint32_t epoch_arg, uint32_t *ticket, uint32_t *err)
+{
+    sort_pass_body<K, ITEMS, false>(keys_in, vals_in, keys_out, vals_out, n_dev, n_host, shift, dbits, hist, status,
+                                    epoch_dev, epoch_arg, ticket, err, nullptr, nullptr);
+}
+
+template <typename K, int ITEMS>
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 2 ? 3 : 1)))
+sort_pass_drop_kernel(const K *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, K *__restrict__ keys_out,
+                      uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
+                      uint32_t dbits, const uint32_t *__restrict__ hist, uint64_t *status,
+                      const uint32_t *__restrict__ epoch_dev, uint32_t epoch_arg, uint32_t *ticket, uint32_t *err,
+                      const uint32_t *__restrict__ dropped, uint32_t *__restrict__ n_kept)
+{
+    sort_pass_body<K, ITEMS, true>(keys_in, vals_in, keys_out, vals_out, n_dev, n_host, shift, dbits, hist, status,
+                                   epoch_dev, epoch_arg, ticket, err, dropped, n_kept);
 }
 
 // Workgroups of one pass that are resident on the device at once.  A pass
@@ -847,7 +894,7 @@ template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide, int shift,
-                      int dbits)
+                      int dbits, const uint32_t *dropped, uint32_t *n_kept)
 {
     if (n == 0) return;
     const int sh = shift < 0 ? pass * kRadixBits : shift;
@@ -857,12 +904,28 @@ void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in,
     if (wide && sizeof(K) <= 4) {
         const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kSortPartWide - 1) / kSortPartWide,
                                                            sort_pass_resident<K, kSortItemsWide>());
+        if constexpr (sizeof(K) == 4) {
+            if (dropped) {
+                hipLaunchKernelGGL((sort_pass_drop_kernel<K, kSortItemsWide>), dim3(grid), dim3(kSortThreads), 0, st,
+                                   keys_in, vals_in, keys_out, vals_out, n_dev, (uint32_t)n, sh, db,
+                                   hist + pass * kRadix, status, epoch_dev, epoch, ticket, err, dropped, n_kept);
+                return;
+            }
+        }
         hipLaunchKernelGGL((sort_pass_kernel<K, kSortItemsWide>), dim3(grid), dim3(kSortThreads), 0, st, keys_in,
                            vals_in, keys_out, vals_out, n_dev, (uint32_t)n, sh, db, hist + pass * kRadix, status,
                            epoch_dev, epoch, ticket, err);
     } else {
         const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kSortPart - 1) / kSortPart,
                                                            sort_pass_resident<K, kSortItems>());
+        if constexpr (sizeof(K) == 4) {
+            if (dropped) {
+                hipLaunchKernelGGL((sort_pass_drop_kernel<K, kSortItems>), dim3(grid), dim3(kSortThreads), 0, st,
+                                   keys_in, vals_in, keys_out, vals_out, n_dev, (uint32_t)n, sh, db,
+                                   hist + pass * kRadix, status, epoch_dev, epoch, ticket, err, dropped, n_kept);
+                return;
+            }
+        }
         hipLaunchKernelGGL((sort_pass_kernel<K, kSortItems>), dim3(grid), dim3(kSortThreads), 0, st, keys_in,
                            vals_in, keys_out, vals_out, n_dev, (uint32_t)n, sh, db, hist + pass * kRadix, status,
                            epoch_dev, epoch, ticket, err);
@@ -987,18 +1050,24 @@ template void launch_emit32<uint32_t>(hipStream_t, const uint32_t *, uint64_t, c
                                       const uint32_t *, const uint32_t *, const BinRec *, const FrameDev *, uint64_t,
                                       const DigitPlan &, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
                                       uint32_t *);
-template void launch_sort_hist<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint64_t, int, uint32_t *);
-template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *);
-template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *);
+template void launch_sort_hist<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint64_t, int, uint32_t *,
+                                      uint32_t *);
+template void launch_sort_hist<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint64_t, int, uint32_t *,
+                                      uint32_t *);
+template void launch_sort_hist<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t, int, uint32_t *,
+                                      uint32_t *);
 template void launch_sort_pass<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, uint16_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int,
+                                         const uint32_t *, uint32_t *);
 template void launch_sort_pass<uint32_t>(hipStream_t, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int,
+                                         const uint32_t *, uint32_t *);
 template void launch_sort_pass<uint64_t>(hipStream_t, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *,
                                          const uint32_t *, uint64_t, int, const uint32_t *, uint64_t *,
-                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int);
+                                         const uint32_t *, uint32_t, uint32_t *, uint32_t *, bool, int, int,
+                                         const uint32_t *, uint32_t *);
 template void launch_tile_ranges<uint16_t>(hipStream_t, const uint16_t *, const uint32_t *, int, uint32_t, uint32_t,
                                           uint32_t, uint2 *, uint32_t *, uint2 *, uint32_t *, uint32_t, uint32_t *,
                                           uint32_t *, uint64_t, const ChunkPlan &, const uint32_t *, FrameRec *,

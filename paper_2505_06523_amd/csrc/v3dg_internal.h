@@ -96,6 +96,8 @@ enum RenderCounter : int {
     kRenBack = 21,        // tiles placed at its back
     kRenFp64 = 22,        // splats whose 2D covariance was redone in FP64 (det < 1e-6)
     kRenConicClamp = 23,  // splats with a conic entry clamped to +-kConicMax
+    kRenCulled = 24,      // slots the projection culled (depth key 0xffffffff; counted by the depth histogram)
+    kRenDepthKept = 25,   // slots the depth sort keeps: the visible ones
     kRenHist = 32,        // 8 passes x 256 bins
     kRenHistDepth = 32 + 8 * 256,  // 4 passes x 256 bins
     kRenKeysEff = 32 + 12 * 256,   // keys the frame's buffers hold: min(total, capacity)
@@ -333,7 +335,10 @@ constexpr uint64_t kSortWideFrom = 1u << 22;  // sorts of at least this many key
 constexpr uint64_t kSortMaxGrid = 4096;       // workgroups of a pass (they claim partitions until none is left)
 // Digit histograms of all passes; the key count is n_dev ? *n_dev : n.
 template <typename K>
-void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist);
+// dropped: when given, keys of all ones are not counted in the digit
+// histograms but in *dropped instead (a sort whose first pass drops them).
+void launch_sort_hist(hipStream_t st, const K *keys, const uint32_t *n_dev, uint64_t n, int passes, uint32_t *hist,
+                      uint32_t *dropped = nullptr);
 // One onesweep pass over n_dev ? *n_dev : n keys (grid sized for n); the
 // look-back epoch is *epoch_dev + epoch when epoch_dev is given, else epoch.
 // wide selects partitions of kSortPartWide keys (keys of at most 32 bits).
@@ -343,7 +348,11 @@ template <typename K>
 void launch_sort_pass(hipStream_t st, const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
                       const uint32_t *n_dev, uint64_t n, int pass, const uint32_t *hist, uint64_t *status,
                       const uint32_t *epoch_dev, uint32_t epoch, uint32_t *ticket, uint32_t *err, bool wide,
-                      int shift = -1, int dbits = kRadixBits);
+                      int shift = -1, int dbits = kRadixBits, const uint32_t *dropped = nullptr,
+                      uint32_t *n_kept = nullptr);
+// (dropped, 32-bit keys only: the pass leaves out the keys of all ones, which
+// the histogram counted in *dropped instead of their digits, writes the
+// others, and stores their count in *n_kept for the passes after it.)
 // Per tile t < n_tiles (tiles_x per row): ranges[t] = [first, end) of the
 // keys of its bin (bins_x per row) in the sorted keys, and the blend plan.  A
 // tile whose bin holds L > cp.first() keys gets cp.n_chunks(L) consecutive
