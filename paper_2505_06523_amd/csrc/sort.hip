@@ -641,6 +641,9 @@ __global__ void __launch_bounds__(kHistThreads) sort_hist_kernel(const K *__rest
                 valid = false;
                 ++my_drop;
             }
+            // a wavefront whose keys are all dropped (or past the end) counts
+            // no digit (uniform: culled slots come in runs, a cluster at a time)
+            if (__ballot(valid) == 0) continue;
             for (int p = 0; p < passes; ++p) {
                 const uint32_t d = (uint32_t)(kk[u] >> (p * kRadixBits)) & (kRadix - 1);
                 const uint64_t peers = match_digit(d, valid);
